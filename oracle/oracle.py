@@ -1,0 +1,434 @@
+"""CPU FP64 oracle for chordally decomposed ADMM on sparse SDPs.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+benchmark's CPU-baseline leg may import this module.  It shares no code with
+the GPU library: the index maps, the KKT factor, the eigensolver and the
+iteration are all re-derived here from the paper (Zheng, Fantuzzi,
+Papachristodoulou, Goulart, Wynn, "Fast ADMM for Semidefinite Programs with
+Chordal Sparsity", arXiv:1609.06068).
+
+Coordinates.  A symmetric matrix X on the aggregate pattern is held by its
+values on the lower-triangular pattern entries e = (i, j), i >= j.  The paper's
+vec(X) holds every off-diagonal value twice, so with w_e = 1 (diagonal) or 2
+(off-diagonal) every vec inner product <u, v> equals sum_e w_e u_e v_e, and the
+vec norm is the w-weighted norm.  H_k x (= vec(E_k X E_k^T), Sec. III-A) is the
+|C_k| x |C_k| submatrix; H_k^T applied to a clique matrix adds each of its
+lower-triangular values to the matching entry; D = sum_k H_k^T H_k is the
+per-entry count of cliques covering the entry (Sec. III-B.1).  A brute-force
+test checks this against the literal vec/Kronecker form on small instances.
+
+Floating point: FP64 throughout.  Own cyclic Jacobi eigensolver and own dense
+Cholesky (C, no LAPACK); numpy matrix products serve as plain library steps.
+
+Readings of the paper taken here (each is also listed in the design notes):
+  * A is the m x n^2 matrix with rows vec(A_1) .. vec(A_m) (the printed A_0 is
+    a typo: the operators use A_1..A_m);
+  * the relative residuals (the paper defers to Boyd et al. 2011, Sec. 3.3):
+      Alg. 1: eps_p = ||x_k - H_k x|| / max(||H_k x||, ||x_k||),
+              eps_d = rho ||sum_k H_k^T (x_k - x_k^prev)|| / ||sum_k H_k^T lam_k||;
+      Alg. 2: eps_p = ||z_k - v_k|| / max(||z_k||, ||v_k||),
+              eps_d = rho ||v_k - v_k^prev|| / ||lam_k||;
+    norms over all cliques stacked; a zero denominator leaves the numerator;
+  * fixed rho (default 1), zero initial guesses (also v_k = 0 in Alg. 2);
+  * Alg. 2 uses the unsubstituted multiplier update lam += rho (z - v); the
+    printed shortcut lam = rho H_k x has the wrong sign (it is -rho H_k x,
+    checked by a test).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "cdcs_oracle.c")
+
+OK, E_ARG, E_RANK, E_NUMERIC = 0, 1, 3, 7
+
+
+def build(force: bool = False) -> str:
+    """Compile the C part of the oracle with gcc (plain -O2)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = build()
+        L = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        lp = ctypes.POINTER(ctypes.c_int64)
+        L.oracle_jacobi_eigh.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int, ip]
+        L.oracle_psd_project.argtypes = [ctypes.c_int, dp, dp, dp, dp]
+        L.oracle_psd_project_batch.argtypes = [ctypes.c_int, lp, lp, dp, dp, ip]
+        L.oracle_psd_project_batch_eig.argtypes = [ctypes.c_int, lp, lp, lp, dp, dp, dp, dp]
+        L.oracle_cholesky.argtypes = [ctypes.c_int, dp, dp]
+        L.oracle_chol_solve.argtypes = [ctypes.c_int, dp, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _lp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+# --------------------------------------------------------------------------
+# Dense kernels (C): eigendecomposition, PSD projection, Cholesky
+# --------------------------------------------------------------------------
+
+def jacobi_eigh(W: np.ndarray, max_sweeps: int = 100):
+    """W = V diag(evals) V^T by cyclic-by-row Jacobi.  Returns (evals, V, sweeps)."""
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    k = W.shape[0]
+    ev = np.empty(k)
+    V = np.empty((k, k))
+    sw = ctypes.c_int(0)
+    st = lib().oracle_jacobi_eigh(k, _dp(W), _dp(ev), _dp(V), max_sweeps, ctypes.byref(sw))
+    if st != OK:
+        raise OracleError(st, "Jacobi did not converge")
+    return ev, V, sw.value
+
+
+def psd_project(W: np.ndarray) -> np.ndarray:
+    """Projection onto the PSD cone, P(W) = V max(Lambda, 0) V^T
+    (equations (E:XkUpdate), (E:zkUpdate))."""
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    k = W.shape[0]
+    P = np.empty((k, k))
+    st = lib().oracle_psd_project(k, _dp(W), _dp(P), None, None)
+    if st != OK:
+        raise OracleError(st, "Jacobi did not converge")
+    return P
+
+
+def psd_project_batch(blocks: list[np.ndarray]) -> list[np.ndarray]:
+    """Independent projections of a list of symmetric matrices (one per clique)."""
+    sizes = np.array([b.shape[0] for b in blocks], dtype=np.int64)
+    off = np.zeros(len(blocks) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes * sizes)
+    W = np.empty(off[-1])
+    for t, b in enumerate(blocks):
+        W[off[t]:off[t + 1]] = b.ravel()
+    P = np.empty_like(W)
+    status = np.zeros(len(blocks), dtype=np.int32)
+    st = lib().oracle_psd_project_batch(len(blocks), _lp(sizes), _lp(off), _dp(W), _dp(P), _ip(status))
+    if st != OK:
+        raise OracleError(st, "Jacobi did not converge")
+    return [P[off[t]:off[t + 1]].reshape(sizes[t], sizes[t]) for t in range(len(blocks))]
+
+
+def psd_project_batch_eig(blocks: list[np.ndarray]):
+    """As psd_project_batch, also returning each block's eigenvalues and
+    eigenvectors (columns of V)."""
+    sizes = np.array([b.shape[0] for b in blocks], dtype=np.int64)
+    off = np.zeros(len(blocks) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes * sizes)
+    eoff = np.zeros(len(blocks) + 1, dtype=np.int64)
+    eoff[1:] = np.cumsum(sizes)
+    W = np.empty(off[-1])
+    for t, b in enumerate(blocks):
+        W[off[t]:off[t + 1]] = b.ravel()
+    P = np.empty_like(W)
+    V = np.empty_like(W)
+    ev = np.empty(eoff[-1])
+    st = lib().oracle_psd_project_batch_eig(len(blocks), _lp(sizes), _lp(off), _lp(eoff),
+                                            _dp(W), _dp(P), _dp(ev), _dp(V))
+    if st != OK:
+        raise OracleError(st, "Jacobi did not converge")
+    Ps = [P[off[t]:off[t + 1]].reshape(sizes[t], sizes[t]) for t in range(len(blocks))]
+    evs = [ev[eoff[t]:eoff[t + 1]] for t in range(len(blocks))]
+    Vs = [V[off[t]:off[t + 1]].reshape(sizes[t], sizes[t]) for t in range(len(blocks))]
+    return Ps, evs, Vs
+
+
+def cholesky(M: np.ndarray) -> np.ndarray:
+    """M = L L^T (lower L).  Raises OracleError(E_RANK) if M is not PD."""
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    m = M.shape[0]
+    L = np.empty((m, m))
+    st = lib().oracle_cholesky(m, _dp(M), _dp(L))
+    if st != OK:
+        raise OracleError(st, "KKT Schur complement is not positive definite (A rank deficient)")
+    return L
+
+
+def chol_solve(L: np.ndarray, t: np.ndarray) -> np.ndarray:
+    """Solve L L^T y = t by forward then backward substitution."""
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    y = np.empty_like(t)
+    lib().oracle_chol_solve(L.shape[0], _dp(L), _dp(t), _dp(y))
+    return y
+
+
+# --------------------------------------------------------------------------
+# Chordal decomposition: E_k, H_k and D (Sections II-B, III-A, III-B.1)
+# --------------------------------------------------------------------------
+
+class Decomposition:
+    """Entry selectors for each clique.
+
+    idx[k] is the |C_k| x |C_k| table of entry positions of the submatrix
+    E_k X E_k^T (both triangles point to the same lower-triangular entry).
+    D[e] counts the cliques whose C_k x C_k contains e.
+    """
+
+    def __init__(self, prob):
+        n = prob.n
+        ei = np.asarray(prob.ei, dtype=np.int64)
+        ej = np.asarray(prob.ej, dtype=np.int64)
+        if np.any(ei < ej):
+            raise OracleError(2, "pattern entries must be lower triangular")
+        key = ei * n + ej
+        if np.unique(key).shape[0] != key.shape[0]:
+            raise OracleError(2, "duplicate pattern entry")
+        order = np.argsort(key)
+        skey = key[order]
+        self.nU = key.shape[0]
+        self.w = np.where(ei == ej, 1.0, 2.0)
+        self.idx = []
+        self.tril = []
+        D = np.zeros(self.nU)
+        for k in range(prob.p):
+            cl = np.asarray(prob.clique(k), dtype=np.int64)
+            if cl.shape[0] == 0 or np.any(np.diff(cl) <= 0) or cl[0] < 0 or cl[-1] >= n:
+                raise OracleError(2, f"clique {k} not sorted / out of range")
+            s = cl.shape[0]
+            I = np.maximum(cl[:, None], cl[None, :])
+            J = np.minimum(cl[:, None], cl[None, :])
+            q = (I * n + J).ravel()
+            pos = np.searchsorted(skey, q)
+            pos = np.minimum(pos, self.nU - 1)
+            if np.any(skey[pos] != q):
+                raise OracleError(2, f"clique {k} pair missing from the pattern")
+            tab = order[pos].reshape(s, s)
+            self.idx.append(tab)
+            ia, ib = np.tril_indices(s)
+            self.tril.append((ia, ib))
+            np.add.at(D, tab[ia, ib], 1.0)
+        if np.any(D == 0):
+            raise OracleError(2, "pattern entry covered by no clique")
+        self.D = D
+
+    def gather(self, x: np.ndarray, k: int) -> np.ndarray:
+        """H_k x as the clique submatrix E_k X E_k^T."""
+        return x[self.idx[k]]
+
+    def scatter(self, blocks) -> np.ndarray:
+        """sum_k H_k^T vec(B_k) in entry coordinates."""
+        out = np.zeros(self.nU)
+        for k, B in enumerate(blocks):
+            ia, ib = self.tril[k]
+            np.add.at(out, self.idx[k][ia, ib], B[ia, ib])
+        return out
+
+    def wdot(self, u, v) -> float:
+        return float(np.sum(self.w * u * v))
+
+    def wnorm(self, u) -> float:
+        return float(np.sqrt(np.sum(self.w * u * u)))
+
+
+def _stack_norm(blocks) -> float:
+    return float(np.sqrt(sum(float(np.sum(B * B)) for B in blocks)))
+
+
+def _rel(num, den):
+    return num / den if den > 0 else num
+
+
+# --------------------------------------------------------------------------
+# Affine projection: the KKT systems (E:OptCondMinYPrimal) / (E:OptCondMinYDual)
+# --------------------------------------------------------------------------
+
+class KKT:
+    """Solve [D A^T; A 0][x; y] = [r1; r2] by block elimination with a cached
+    Cholesky factor (Sec. III-B.1; the same matrix serves Alg. 2).
+
+    In entry coordinates the first block row reads D_e x_e + (A^T y)_e = r1_e
+    and the second sum_e w_e A_ie x_e = r2_i, so
+        M = A diag(w / D) A^T,  M y = A (w * r1 / D) - r2,  x = (r1 - A^T y) / D.
+    """
+
+    def __init__(self, prob, dec: Decomposition):
+        if prob.A is not None:
+            self.A = np.asarray(prob.A, dtype=np.float64)
+        else:
+            import scipy.sparse as sp
+            self.A = sp.csr_matrix((prob.A_val, prob.A_idx.astype(np.int64), prob.A_ptr),
+                                   shape=(prob.m, dec.nU))
+        self.D = dec.D
+        self.w = dec.w
+        sc = self.w / self.D
+        if isinstance(self.A, np.ndarray):
+            M = (self.A * sc[None, :]) @ self.A.T
+        else:
+            import scipy.sparse as sp
+            M = (self.A @ sp.diags(sc) @ self.A.T).toarray()
+        self.M = 0.5 * (M + M.T)
+        self.L = cholesky(self.M)
+
+    def solve(self, r1: np.ndarray, r2: np.ndarray):
+        t = self.A @ (self.w * r1 / self.D) - r2
+        y = chol_solve(self.L, t)
+        x = (r1 - self.A.T @ y) / self.D
+        return x, y
+
+
+# --------------------------------------------------------------------------
+# Algorithms 1 and 2
+# --------------------------------------------------------------------------
+
+@dataclass
+class Result:
+    form: str
+    iters: int
+    converged: bool
+    x: np.ndarray            # global x (entry coordinates)
+    y: np.ndarray            # KKT multiplier y of the last affine step
+    blocks: list             # x_k (Alg. 1) or z_k (Alg. 2), full clique matrices
+    lam: list                # lambda_k
+    v: list | None           # v_k (Alg. 2)
+    eps_p: list = field(default_factory=list)
+    eps_d: list = field(default_factory=list)
+    X_sdp: np.ndarray | None = None   # primal SDP variable on the entries
+    y_sdp: np.ndarray | None = None   # dual SDP multiplier
+    Z_sdp: np.ndarray | None = None   # dual slack on the entries
+    obj_primal: float = 0.0
+    obj_dual: float = 0.0
+
+
+class Oracle:
+    def __init__(self, prob):
+        self.prob = prob
+        self.dec = Decomposition(prob)
+        self.kkt = KKT(prob, self.dec)
+        self.sizes = [int(s) for s in prob.clique_sizes()]
+
+    def zero_blocks(self):
+        return [np.zeros((s, s)) for s in self.sizes]
+
+    # ---- Algorithm 1: decomposed primal form ------------------------------
+    def admm_primal(self, rho=1.0, max_iter=200, tol=0.0, xk=None, lam=None, callback=None) -> Result:
+        dec, kkt, prob = self.dec, self.kkt, self.prob
+        c, b = prob.c, prob.b
+        xk = self.zero_blocks() if xk is None else [B.copy() for B in xk]
+        lam = self.zero_blocks() if lam is None else [B.copy() for B in lam]
+        res = Result("primal", 0, False, None, None, xk, lam, None)
+        for it in range(1, max_iter + 1):
+            # X-block: (E:OptCondMinYPrimal)
+            r1 = dec.scatter([xk[k] + lam[k] / rho for k in range(prob.p)]) - c / rho
+            x, y = kkt.solve(r1, b)
+            # Y-block: (E:XkUpdate), one PSD projection per clique
+            Hx = [dec.gather(x, k) for k in range(prob.p)]
+            W = [Hx[k] - lam[k] / rho for k in range(prob.p)]
+            xk_new = psd_project_batch(W)
+            # Z-block: (E:LambdakUpdate)
+            lam = [lam[k] + rho * (xk_new[k] - Hx[k]) for k in range(prob.p)]
+            # relative residuals
+            rp = _stack_norm([xk_new[k] - Hx[k] for k in range(prob.p)])
+            eps_p = _rel(rp, max(_stack_norm(Hx), _stack_norm(xk_new)))
+            s = rho * dec.scatter([xk_new[k] - xk[k] for k in range(prob.p)])
+            eps_d = _rel(dec.wnorm(s), dec.wnorm(dec.scatter(lam)))
+            xk = xk_new
+            res.eps_p.append(eps_p)
+            res.eps_d.append(eps_d)
+            res.iters = it
+            if callback is not None:
+                callback(it, x, y, xk, lam)
+            if max(eps_p, eps_d) <= tol:
+                res.converged = True
+                break
+        res.x, res.y, res.blocks, res.lam = x, y, xk, lam
+        res.X_sdp = x
+        res.y_sdp = -rho * y
+        res.Z_sdp = dec.scatter(lam)
+        res.obj_primal = dec.wdot(c, x)
+        res.obj_dual = float(np.dot(b, res.y_sdp))
+        return res
+
+    # ---- Algorithm 2: decomposed dual form --------------------------------
+    def admm_dual(self, rho=1.0, max_iter=200, tol=0.0, z=None, v=None, lam=None, callback=None) -> Result:
+        dec, kkt, prob = self.dec, self.kkt, self.prob
+        c, b = prob.c, prob.b
+        z = self.zero_blocks() if z is None else [B.copy() for B in z]
+        v = self.zero_blocks() if v is None else [B.copy() for B in v]
+        lam = self.zero_blocks() if lam is None else [B.copy() for B in lam]
+        res = Result("dual", 0, False, None, None, z, lam, v)
+        for it in range(1, max_iter + 1):
+            # Y-block first: (E:zkUpdate)
+            z = psd_project_batch([v[k] - lam[k] / rho for k in range(prob.p)])
+            # X-block: (E:OptCondMinYDual), then (E:vkEqn)
+            r1 = c - dec.scatter([z[k] + lam[k] / rho for k in range(prob.p)])
+            x, y = kkt.solve(r1, -b / rho)
+            v_new = [z[k] + lam[k] / rho + dec.gather(x, k) for k in range(prob.p)]
+            # Z-block: (E:MultUpdateDualSDP)
+            lam = [lam[k] + rho * (z[k] - v_new[k]) for k in range(prob.p)]
+            rp = _stack_norm([z[k] - v_new[k] for k in range(prob.p)])
+            eps_p = _rel(rp, max(_stack_norm(z), _stack_norm(v_new)))
+            eps_d = _rel(rho * _stack_norm([v_new[k] - v[k] for k in range(prob.p)]), _stack_norm(lam))
+            v = v_new
+            res.eps_p.append(eps_p)
+            res.eps_d.append(eps_d)
+            res.iters = it
+            if callback is not None:
+                callback(it, x, y, z, lam)
+            if max(eps_p, eps_d) <= tol:
+                res.converged = True
+                break
+        res.x, res.y, res.blocks, res.lam, res.v = x, y, z, lam, v
+        res.y_sdp = y
+        res.Z_sdp = dec.scatter(z)
+        res.X_sdp = -rho * x
+        res.obj_dual = float(np.dot(b, y))
+        res.obj_primal = dec.wdot(c, res.X_sdp)
+        return res
+
+    def solve(self, form="primal", **kw) -> Result:
+        return self.admm_primal(**kw) if form == "primal" else self.admm_dual(**kw)
+
+    # ---- optimality measures of the original SDP (Sec. I) -----------------
+    def sdp_kkt_residuals(self, res: Result):
+        """Relative primal infeasibility, dual infeasibility and duality gap of
+        (X_sdp, y_sdp, Z_sdp) for the SDP pair (E:PrimalSDP)/(E:DualSDP), plus
+        the smallest clique eigenvalue of X and of the Z_k blocks."""
+        dec, prob = self.dec, self.prob
+        A = self.kkt.A
+        X, y, Z = res.X_sdp, res.y_sdp, res.Z_sdp
+        AX = A @ (dec.w * X)
+        pinf = np.linalg.norm(AX - prob.b) / (1.0 + np.linalg.norm(prob.b))
+        dres = A.T @ y + Z - prob.c
+        dinf = dec.wnorm(dres) / (1.0 + dec.wnorm(prob.c))
+        pobj = dec.wdot(prob.c, X)
+        dobj = float(np.dot(prob.b, y))
+        gap = abs(pobj - dobj) / (1.0 + abs(pobj) + abs(dobj))
+        xmin = min(float(np.linalg.eigvalsh(dec.gather(X, k)).min()) for k in range(prob.p))
+        zblocks = res.lam if res.form == "primal" else res.blocks
+        zmin = min(float(np.linalg.eigvalsh(B).min()) for B in zblocks)
+        return dict(pinf=pinf, dinf=dinf, gap=gap, pobj=pobj, dobj=dobj, xmin=xmin, zmin=zmin)

@@ -1,0 +1,369 @@
+"""Seeded synthetic SDP instances with chordal aggregate sparsity.
+
+This module only *draws inputs*: a sparsity pattern with its maximal cliques,
+constraint matrices A_1..A_m, a right-hand side b and a cost C, in the standard
+primal/dual forms of Section I of the paper (operators A(X) = [<A_i, X>] and
+A*(y) = sum_i A_i y_i).  It contains none of the ADMM arithmetic; both the CPU
+oracle and the GPU library consume the same arrays.
+
+Storage convention (shared input format, not an algorithm):
+  * the pattern is a list of distinct lower-triangular entries (ei[e], ej[e])
+    with ei >= ej, diagonal included; "entry e" means that list position;
+  * every symmetric n x n matrix on the pattern is stored by its value on each
+    entry (a matrix value, not a weighted one);
+  * A is an m x nU array (dense on the pattern) or a CSR over entries;
+  * cliques are a CSR (clique_ptr, clique_vert) with vertices sorted in the
+    natural order (Section II-B: E_k lists the vertices of C_k in increasing
+    order).
+
+Instances are made strictly feasible by construction: b = A(X0) with X0 a
+Gram matrix, and C = A*(y0) + Z0 with Z0 a sum of clique-supported PSD blocks
+(Agler's form, Section II-C).  All draws use numpy PCG64 with the given seed.
+A is rounded to FP32-representable values so that a FP32 copy of A is exact.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Problem:
+    n: int
+    ei: np.ndarray          # int32 [nU]   row index of entry e (ei >= ej)
+    ej: np.ndarray          # int32 [nU]   column index of entry e
+    clique_ptr: np.ndarray  # int64 [p+1]
+    clique_vert: np.ndarray  # int32 [sum s_k], sorted within each clique
+    b: np.ndarray           # float64 [m]
+    c: np.ndarray           # float64 [nU]  values of C on the entries
+    A: np.ndarray | None = None      # float64 [m, nU] dense-on-pattern A
+    A_ptr: np.ndarray | None = None  # int64 [m+1]   CSR alternative
+    A_idx: np.ndarray | None = None  # int32 [nnzA]  entry indices
+    A_val: np.ndarray | None = None  # float64 [nnzA]
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nU(self) -> int:
+        return int(self.ei.shape[0])
+
+    @property
+    def m(self) -> int:
+        return int(self.b.shape[0])
+
+    @property
+    def p(self) -> int:
+        return int(self.clique_ptr.shape[0] - 1)
+
+    def clique(self, k: int) -> np.ndarray:
+        return self.clique_vert[self.clique_ptr[k]:self.clique_ptr[k + 1]]
+
+    def clique_sizes(self) -> np.ndarray:
+        return np.diff(self.clique_ptr).astype(np.int64)
+
+    def A_dense(self) -> np.ndarray:
+        """A as an m x nU array (materialises a CSR A)."""
+        if self.A is not None:
+            return self.A
+        out = np.zeros((self.m, self.nU))
+        for i in range(self.m):
+            lo, hi = self.A_ptr[i], self.A_ptr[i + 1]
+            np.add.at(out[i], self.A_idx[lo:hi], self.A_val[lo:hi])
+        return out
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _f32(a: np.ndarray) -> np.ndarray:
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _entry_lookup(n: int, ei: np.ndarray, ej: np.ndarray):
+    """Sorted keys for (i, j) -> entry position lookups (input bookkeeping)."""
+    key = ei.astype(np.int64) * n + ej.astype(np.int64)
+    order = np.argsort(key, kind="stable")
+    return key[order], order
+
+
+def _find_entries(n, lookup, ii, jj):
+    skey, order = lookup
+    hi = np.maximum(ii, jj).astype(np.int64)
+    lo = np.minimum(ii, jj).astype(np.int64)
+    q = hi * n + lo
+    pos = np.searchsorted(skey, q)
+    if np.any(pos >= skey.shape[0]) or np.any(skey[np.minimum(pos, skey.shape[0] - 1)] != q):
+        raise ValueError("pair not in pattern")
+    return order[pos]
+
+
+def _pattern_from_cliques(n: int, cliques: list[np.ndarray]):
+    """Lower-triangular entries of the union of C_k x C_k, clique-major.
+
+    Entries first met in clique k are listed with clique k, in the clique's
+    packed lower-triangular (row-major) order; this keeps each clique's private
+    entries contiguous.
+    """
+    seen = {}
+    ei, ej = [], []
+    for cl in cliques:
+        s = cl.shape[0]
+        for a in range(s):
+            va = int(cl[a])
+            for bb in range(a + 1):
+                vb = int(cl[bb])
+                key = (va, vb)
+                if key not in seen:
+                    seen[key] = len(ei)
+                    ei.append(va)
+                    ej.append(vb)
+    return np.asarray(ei, dtype=np.int32), np.asarray(ej, dtype=np.int32)
+
+
+def _block_arrow_pattern(l: int, d: int, h: int):
+    """Block-arrow pattern (Section V-A, Fig. 2): l diagonal blocks of size d
+    plus an arrow head of size h.  Cliques C_i = B_i U H.  Entries are listed
+    clique by clique (rows of the clique-local lower triangle that touch B_i),
+    then the head x head entries once at the end."""
+    n = l * d + h
+    head = np.arange(l * d, n, dtype=np.int32)
+    cliques = [np.concatenate([np.arange(i * d, (i + 1) * d, dtype=np.int32), head]) for i in range(l)]
+    s = d + h
+    # clique-local packed lower-tri rows a, columns b <= a with b < d
+    loc_a, loc_b = [], []
+    for a in range(s):
+        for bb in range(min(a, d - 1) + 1):
+            loc_a.append(a)
+            loc_b.append(bb)
+    loc_a = np.asarray(loc_a)
+    loc_b = np.asarray(loc_b)
+    ei = np.concatenate([cl[loc_a] for cl in cliques] + [head[np.tril_indices(h)[0]]]) if h > 0 else \
+        np.concatenate([cl[loc_a] for cl in cliques])
+    ej = np.concatenate([cl[loc_b] for cl in cliques] + [head[np.tril_indices(h)[1]]]) if h > 0 else \
+        np.concatenate([cl[loc_b] for cl in cliques])
+    return n, cliques, ei.astype(np.int32), ej.astype(np.int32)
+
+
+def _finish(n, cliques, ei, ej, A_rows, rng, m, gram_rank=None, meta=None, A_sparse=None):
+    """Draw X0, y0, Z0 and set b = A(X0), C = A*(y0) + Z0."""
+    nU = ei.shape[0]
+    w = np.where(ei == ej, 1.0, 2.0)
+    lookup = _entry_lookup(n, ei, ej)
+    # X0 = G G^T / r on the pattern entries (G is n x r)
+    r = n if gram_rank is None else gram_rank
+    G = rng.standard_normal((n, r))
+    x0 = np.empty(nU)
+    step = max(1, (1 << 24) // max(r, 1))
+    for lo in range(0, nU, step):
+        hi = min(nU, lo + step)
+        x0[lo:hi] = np.einsum("ij,ij->i", G[ei[lo:hi]], G[ej[lo:hi]]) / r
+    if gram_rank is not None:
+        x0[ei == ej] += 1.0  # X0 = G G^T / r + I keeps a low-rank Gram PD
+    del G
+    y0 = rng.standard_normal(m)
+    # Z0 = sum_k E_k^T (R_k R_k^T / s_k) E_k  (Agler form, Theorem 2)
+    z0 = np.zeros(nU)
+    for cl in cliques:
+        s = cl.shape[0]
+        R = rng.standard_normal((s, s))
+        Zk = R @ R.T / s
+        ia, ib = np.tril_indices(s)
+        idx = _find_entries(n, lookup, cl[ia], cl[ib])
+        np.add.at(z0, idx, Zk[ia, ib])
+    if A_sparse is None:
+        A = A_rows
+        b = A @ (w * x0)             # <A_i, X0> = sum_e w_e A_ie X0_e
+        c = A.T @ y0 + z0            # (A*(y0))_e = sum_i A_ie y0_i
+    else:
+        ptr, idx, val = A_sparse
+        b = np.zeros(m)
+        c = z0.copy()
+        for i in range(m):
+            lo, hi = ptr[i], ptr[i + 1]
+            b[i] = np.dot(val[lo:hi], w[idx[lo:hi]] * x0[idx[lo:hi]])
+            np.add.at(c, idx[lo:hi], val[lo:hi] * y0[i])
+        A = None
+    clique_ptr = np.zeros(len(cliques) + 1, dtype=np.int64)
+    clique_ptr[1:] = np.cumsum([cl.shape[0] for cl in cliques])
+    clique_vert = np.concatenate(cliques).astype(np.int32)
+    prob = Problem(n=n, ei=ei, ej=ej, clique_ptr=clique_ptr, clique_vert=clique_vert,
+                   b=b, c=c, A=A, meta=dict(meta or {}))
+    if A_sparse is not None:
+        prob.A_ptr, prob.A_idx, prob.A_val = A_sparse
+    prob.meta.update({"x0": x0, "y0": y0, "z0": z0})
+    return prob
+
+
+def _symmetrised_normal(rng, m, ei, ej):
+    """A_i = (R + R^T)/2 restricted to the pattern, R ~ N(0, 1) entrywise."""
+    nU = ei.shape[0]
+    out = np.empty((m, nU))
+    diag = ei == ej
+    chunk = max(1, (1 << 24) // max(nU, 1))
+    for lo in range(0, m, chunk):
+        hi = min(m, lo + chunk)
+        r1 = rng.standard_normal((hi - lo, nU))
+        r2 = rng.standard_normal((hi - lo, nU))
+        out[lo:hi] = np.where(diag[None, :], r1, 0.5 * (r1 + r2))
+    return _f32(out)
+
+
+def block_arrow(l: int, d: int, h: int, m: int, seed: int) -> Problem:
+    """Random block-arrow SDP (stand-in for the block-arrow benchmark of
+    Section V-A): each A_i is a symmetrised N(0,1) matrix on the whole
+    pattern, b = A(X0) with X0 = G G^T / n, C = A*(y0) + Z0."""
+    rng = _rng(seed)
+    n, cliques, ei, ej = _block_arrow_pattern(l, d, h)
+    A = _symmetrised_normal(rng, m, ei, ej)
+    return _finish(n, cliques, ei, ej, A, rng, m,
+                   meta={"kind": "block_arrow", "l": l, "d": d, "h": h, "seed": seed})
+
+
+def config_seed(config: int, instance: int = 0) -> int:
+    return 1000 * config + instance
+
+
+# The five workloads of the benchmark suite, by name.
+C1 = dict(l=10, d=10, h=5, m=50)        # plain FP64 parity anchor, n = 105
+C2 = dict(l=200, d=20, h=10, m=2000)    # headline: n = 4010, 200 cliques of 30
+C5 = dict(l=100, d=16, h=8, m=800)      # differentiation workload
+
+
+def c1(instance: int = 0) -> Problem:
+    return block_arrow(seed=config_seed(1, instance), **C1)
+
+
+def c2(instance: int = 0) -> Problem:
+    return block_arrow(seed=config_seed(2, instance), **C2)
+
+
+def c5(instance: int = 0) -> Problem:
+    return block_arrow(seed=config_seed(5, instance), **C5)
+
+
+def random_symmetric(k: int, seed: int, scale: float = 1.0) -> np.ndarray:
+    """Symmetric k x k test matrix with N(0,1) entries (for projection tests)."""
+    rng = _rng(seed)
+    R = rng.standard_normal((k, k)) * scale
+    return (R + R.T) / 2
+
+
+def clique_batch(sizes, seed: int):
+    """Packed batch of random symmetric clique matrices (float64, full k x k
+    row-major per clique), plus offsets."""
+    rng = _rng(seed)
+    sizes = np.asarray(sizes, dtype=np.int64)
+    off = np.zeros(sizes.shape[0] + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes * sizes)
+    W = np.empty(off[-1])
+    for t, k in enumerate(sizes):
+        R = rng.standard_normal((k, k))
+        W[off[t]:off[t + 1]] = ((R + R.T) / 2).ravel()
+    return sizes, off, W
+
+
+def trace_problem(n_blocks: int, d: int, h: int, seed: int) -> Problem:
+    """min <C, X> s.t. tr X = 1, X PSD, on a block-arrow pattern.
+    The optimum is lambda_min(C) (Rayleigh), a closed form for tests."""
+    rng = _rng(seed)
+    n, cliques, ei, ej = _block_arrow_pattern(n_blocks, d, h)
+    nU = ei.shape[0]
+    A = np.where(ei == ej, 1.0, 0.0)[None, :]
+    b = np.array([1.0])
+    R = rng.standard_normal((n, n))
+    Cfull = (R + R.T) / 2
+    c = Cfull[ei, ej].copy()
+    clique_ptr = np.zeros(len(cliques) + 1, dtype=np.int64)
+    clique_ptr[1:] = np.cumsum([cl.shape[0] for cl in cliques])
+    return Problem(n=n, ei=ei, ej=ej, clique_ptr=clique_ptr,
+                   clique_vert=np.concatenate(cliques).astype(np.int32),
+                   b=b, c=c, A=A, meta={"kind": "trace", "seed": seed})
+
+
+def lambda_max_problem(k: int, seed: int) -> Problem:
+    """Dual form max <b, y> s.t. A*(y) + Z = C, Z PSD, with m = 1, A_1 = -I,
+    b = -1, C = -M for a random symmetric M on the full k x k pattern (one
+    clique).  Then y = -t and the constraint reads t I - M PSD, so the optimal
+    <b, y> = -min t = -lambda_max(M)."""
+    rng = _rng(seed)
+    R = rng.standard_normal((k, k))
+    Mfull = (R + R.T) / 2
+    ei, ej = np.tril_indices(k)
+    ei = ei.astype(np.int32)
+    ej = ej.astype(np.int32)
+    A = np.where(ei == ej, -1.0, 0.0)[None, :]
+    cl = np.arange(k, dtype=np.int32)
+    return Problem(n=k, ei=ei, ej=ej, clique_ptr=np.array([0, k], dtype=np.int64),
+                   clique_vert=cl, b=np.array([-1.0]), c=-Mfull[ei, ej].copy(), A=A,
+                   meta={"kind": "lambda_max", "M": Mfull})
+
+
+def with_cliques(prob: Problem, cliques: list[np.ndarray]) -> Problem:
+    """The same SDP data posed over a different clique cover of a pattern that
+    contains the original one (entries absent from the original pattern get
+    zero data).  Used to compare the decomposed and undecomposed problems."""
+    n = prob.n
+    ei, ej = _pattern_from_cliques(n, cliques)
+    lookup = _entry_lookup(n, ei, ej)
+    pos = _find_entries(n, lookup, prob.ei, prob.ej)
+    nU = ei.shape[0]
+    c = np.zeros(nU)
+    c[pos] = prob.c
+    A = np.zeros((prob.m, nU))
+    A[:, pos] = prob.A_dense()
+    clique_ptr = np.zeros(len(cliques) + 1, dtype=np.int64)
+    clique_ptr[1:] = np.cumsum([cl.shape[0] for cl in cliques])
+    return Problem(n=n, ei=ei, ej=ej, clique_ptr=clique_ptr,
+                   clique_vert=np.concatenate(cliques).astype(np.int32),
+                   b=prob.b.copy(), c=c, A=A, meta=dict(prob.meta, recliqued=True))
+
+
+def block_trace_problem(l: int, d: int, seed: int) -> Problem:
+    """Block-diagonal pattern (block-arrow with h = 0) with one trace
+    constraint per block: min <C, X> s.t. tr X_b = 1 for each block, X PSD.
+    The problem decouples; the optimum is sum_b lambda_min(C_b)."""
+    rng = _rng(seed)
+    n, cliques, ei, ej = _block_arrow_pattern(l, d, 0)
+    nU = ei.shape[0]
+    A = np.zeros((l, nU))
+    blk = ei // d
+    A[blk, np.arange(nU)] = np.where(ei == ej, 1.0, 0.0)
+    R = rng.standard_normal((n, n))
+    Cfull = (R + R.T) / 2
+    clique_ptr = np.zeros(len(cliques) + 1, dtype=np.int64)
+    clique_ptr[1:] = np.cumsum([cl.shape[0] for cl in cliques])
+    return Problem(n=n, ei=ei, ej=ej, clique_ptr=clique_ptr,
+                   clique_vert=np.concatenate(cliques).astype(np.int32),
+                   b=np.ones(l), c=Cfull[ei, ej].copy(), A=A,
+                   meta={"kind": "block_trace", "C": Cfull, "l": l, "d": d})
+
+
+def small_chordal(n: int, p: int, smax: int, m: int, seed: int) -> Problem:
+    """Small random chordal instance built from a clique tree: clique k > 0
+    takes a separator from a random earlier clique and adds new vertices.
+    Dense symmetrised N(0,1) constraints on the pattern; vertex labels are
+    randomly permuted.  n is the resulting vertex count (argument is a cap)."""
+    rng = _rng(seed)
+    cliques = []
+    nv = 0
+    for k in range(p):
+        s = int(rng.integers(2, smax + 1))
+        if k == 0:
+            cl = list(range(nv, nv + s))
+            nv += s
+        else:
+            par = cliques[int(rng.integers(0, k))]
+            o = int(rng.integers(1, min(len(par), s - 1) + 1))
+            sep = list(rng.choice(par, size=o, replace=False))
+            new = list(range(nv, nv + s - o))
+            nv += s - o
+            cl = sep + new
+        cliques.append(sorted(int(v) for v in cl))
+        if nv >= n:
+            break
+    perm = rng.permutation(nv)
+    cliques = [np.sort(perm[np.asarray(cl)]).astype(np.int32) for cl in cliques]
+    ei, ej = _pattern_from_cliques(nv, cliques)
+    A = _symmetrised_normal(rng, m, ei, ej)
+    return _finish(nv, cliques, ei, ej, A, rng, m, meta={"kind": "small_chordal", "seed": seed})
