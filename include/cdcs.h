@@ -1,0 +1,230 @@
+/*
+ * cdcs.h -- C-ABI of the MI355X (gfx950) library for chordally decomposed ADMM
+ * on sparse semidefinite programs.
+ *
+ * Method: Zheng, Fantuzzi, Papachristodoulou, Goulart, Wynn, "Fast ADMM for
+ * Semidefinite Programs with Chordal Sparsity" (arXiv:1609.06068).
+ *   - problem forms: Sec. I, (E:PrimalSDP) and (E:DualSDP);
+ *   - decomposition: Sec. II-B/II-C (E_k, Grone's and Agler's theorems),
+ *     Sec. III-A (H_k = E_k (x) E_k, (E:PrimalVectorForm)), Sec. IV-A
+ *     ((E:DualDecomposedSDPVector));
+ *   - iteration: Algorithm 1 (primal form) and Algorithm 2 (dual form).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pattern entries.  The aggregate sparsity pattern is passed as a list of
+ * nnz distinct lower-triangular entries e = (i[e], j[e]), i >= j, diagonal
+ * included.  Every "global" vector of length nnz (x, C, columns of A) is indexed
+ * by that list position and holds matrix values (an off-diagonal entry stands
+ * for both (i, j) and (j, i)).  Inner products and norms of global vectors
+ * weight off-diagonal entries by 2, so they equal the paper's vec() products.
+ *
+ * Cliques.  p cliques as a CSR (ptr[p+1], vert[]), vertices strictly
+ * increasing inside a clique (the natural order of Sec. II-B).  The pattern
+ * must equal the union of C_k x C_k (lower triangles).  Clique sizes are
+ * limited to 1..CDCS_MAX_CLIQUE.
+ *
+ * Packed clique blocks.  Per-clique matrices (x_k, z_k, v_k, lambda_k, W_k,
+ * P(W_k)) are stored as packed lower triangles, row-major: element (a, b),
+ * a >= b, of clique k sits at off[k] + a(a+1)/2 + b, where off[] is the
+ * prefix sum of s_k(s_k+1)/2 (cdcs_clique_offsets).  a, b index the clique's
+ * sorted vertex list.  These blocks are FP32; global vectors are FP64.
+ *
+ * Memory.  Pointers documented "host" are read during the call only and may
+ * be freed on return.  Pointers documented "device" are caller-owned device
+ * memory (e.g. torch tensors); the library never frees them.  The handle owns
+ * its internal device data.  A handle is not thread-safe; calls on one handle
+ * must be serialised by the caller.
+ *
+ * Streams.  Work is enqueued on the caller's stream (0 = legacy default
+ * stream).  Entry points return after enqueueing, except cdcs_setup and
+ * cdcs_admm_solve, which synchronise on that stream.
+ *
+ * Errors.  Every entry point returns a cdcs_status and never aborts; the
+ * message of the last failure on the calling thread is cdcs_last_error().
+ */
+#ifndef CDCS_H
+#define CDCS_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CDCS_MAX_CLIQUE 96
+
+typedef enum {
+    CDCS_OK = 0,
+    CDCS_E_ARG = 1,            /* bad argument, size or pointer */
+    CDCS_E_PATTERN = 2,        /* cliques/pattern/data inconsistent */
+    CDCS_E_RANK = 3,           /* A D^-1 A^T not positive definite: A rank deficient */
+    CDCS_E_DEVICE = 4,         /* HIP runtime failure */
+    CDCS_E_NOMEM = 5,          /* device allocation failed */
+    CDCS_E_NOT_CONVERGED = 6,  /* iteration cap reached; results are written */
+    CDCS_E_NUMERIC = 7         /* an eigensolve hit its sweep cap, or NaN/Inf */
+} cdcs_status;
+
+typedef enum { CDCS_PRIMAL = 0, /* Algorithm 1 */ CDCS_DUAL = 1 /* Algorithm 2 */ } cdcs_form;
+
+typedef struct cdcs_handle cdcs_handle;
+
+/* Aggregate sparsity pattern G(V, E) (Sec. III-A), lower triangle. */
+typedef struct {
+    int32_t n;            /* matrix order */
+    int64_t nnz;          /* number of entries */
+    const int32_t *i;     /* host [nnz], row index, 0 <= j[e] <= i[e] < n */
+    const int32_t *j;     /* host [nnz] */
+} cdcs_pattern;
+
+/* Maximal cliques C_1..C_p of the (chordal) pattern (Sec. II-A). */
+typedef struct {
+    int32_t p;
+    const int64_t *ptr;   /* host [p+1], ptr[0] = 0 */
+    const int32_t *vert;  /* host [ptr[p]] */
+} cdcs_cliques;
+
+/* Constraint matrices A_1..A_m of the operator A(X) = [<A_i, X>] (Sec. I),
+ * each given by its values on pattern entries.  dense = 1: val is m x nnz
+ * row-major (ptr, idx ignored).  dense = 0: CSR rows (ptr[m+1], idx[] pattern
+ * entry of each value, val[]); duplicates are summed.  Values are stored on
+ * the device in FP32 (off-diagonal ones doubled, exactly); the KKT factor is
+ * built from those stored values. */
+typedef struct {
+    int32_t m;
+    int32_t dense;
+    const int64_t *ptr;   /* host [m+1] (dense = 0) */
+    const int32_t *idx;   /* host [ptr[m]] (dense = 0) */
+    const double *val;    /* host */
+} cdcs_constraints;
+
+typedef struct {
+    double rho;           /* ADMM penalty, > 0 (the paper leaves it free) */
+    double tol;           /* stop when max(eps_p, eps_d) <= tol; 0 runs max_iter */
+    int32_t max_iter;     /* iteration cap (>= 1) */
+    int32_t form;         /* cdcs_form */
+    int32_t check_every;  /* iterations per captured HIP graph (0: no graph, eager launches) */
+} cdcs_options;
+
+typedef struct {
+    int32_t iters;        /* completed iterations */
+    int32_t status;       /* cdcs_status of the solve */
+    int32_t converged;    /* 1 if max(eps_p, eps_d) <= tol */
+    int32_t jacobi_cap_hits; /* eigensolves that stopped at the sweep cap */
+    double eps_p, eps_d;  /* relative residuals of the last iteration */
+    double obj_primal;    /* <C, X> of the primal iterate */
+    double obj_dual;      /* <b, y> of the dual iterate */
+    double loop_s;        /* wall time of the iteration loop */
+} cdcs_info;
+
+/* Caller-owned ADMM state (device memory).  Zero-filled state is the
+ * paper-neutral initial guess; a previous solve's state is a warm start.
+ *   x   [nnz]    FP64  global x (Alg. 1: the primal X on the pattern;
+ *                      Alg. 2: the multiplier, X_sdp = -rho x)
+ *   y   [m]      FP64  KKT multiplier y (Alg. 1: y_sdp = -rho y; Alg. 2: y_sdp = y)
+ *   blk [nslots] FP32  x_k (Alg. 1) or z_k (Alg. 2), packed
+ *   lam [nslots] FP32  lambda_k, packed
+ *   v   [nslots] FP32  v_k (Alg. 2 only; NULL allowed for Alg. 1) */
+typedef struct {
+    double *x;
+    double *y;
+    float *blk;
+    float *lam;
+    float *v;
+} cdcs_state;
+
+typedef struct {
+    int32_t n, m, p, smax;
+    int64_t nnz, nslots;
+} cdcs_sizes;
+
+/*
+ * Setup (Algorithms 1/2, "Setup: Chordal decomposition, KKT factorization").
+ * Validates the pattern and cliques, builds the entry selectors H_k and the
+ * overlap counts D = sum_k H_k^T H_k (Sec. III-B.1), uploads the data, forms
+ * M = A diag(w/D) A^T on the device in FP64 and factors it (Cholesky), caching
+ * the inverse triangular factor for the affine projection.
+ *   b [m] host FP64, c [nnz] host FP64 (values of C on the entries).
+ *   opts may be NULL (rho = 1).  The cached factor does not depend on rho.
+ * Errors: CDCS_E_ARG, CDCS_E_PATTERN (unsorted/duplicate clique vertex, clique
+ * pair missing from the pattern, entry in no clique, index out of range),
+ * CDCS_E_RANK (A not of full row rank), CDCS_E_NOMEM, CDCS_E_DEVICE.
+ * On error *out is NULL.
+ */
+cdcs_status cdcs_setup(const cdcs_pattern *pattern, const cdcs_constraints *A,
+                       const double *b, const double *c, const cdcs_cliques *cliques,
+                       const cdcs_options *opts, hipStream_t stream, cdcs_handle **out);
+
+cdcs_status cdcs_get_sizes(const cdcs_handle *h, cdcs_sizes *out);
+
+/* Packed-slot offsets off[0..p] (host array of p+1 int64 written). */
+cdcs_status cdcs_clique_offsets(const cdcs_handle *h, int64_t *off_host);
+
+/*
+ * Batched projection onto the product of PSD cones, P_k[W_k] of (E:XkUpdate)
+ * and (E:zkUpdate): P(W) = Q max(Lambda, 0) Q^T for each of nb independent
+ * symmetric blocks, FP32 (round-robin parallel Jacobi, one workgroup per
+ * block).  Handle-free.
+ *   sizes [nb] device int32, each in 1..CDCS_MAX_CLIQUE
+ *   off   [nb+1] device int64, packed offsets (prefix sums of s(s+1)/2)
+ *   W, P  [off[nb]] device FP32 packed lower triangles (may not alias)
+ *   evals [sum s] device FP32 or NULL: eigenvalues, block t at eoff[t]
+ *   evecs [sum s^2] device FP32 or NULL: eigenvectors as columns of a
+ *         row-major s x s matrix, block t at voff[t]
+ *   eoff, voff device int64 [nb+1] (required when evals/evecs are given)
+ *   smax  host: the largest size in sizes[] (selects the kernel variant)
+ * A block whose size lies outside 1..smax is skipped (its P is not written);
+ * nb <= 0 is a no-op.  Errors: CDCS_E_ARG (smax outside 1..CDCS_MAX_CLIQUE,
+ * NULL W/P/sizes/off), CDCS_E_DEVICE.
+ */
+cdcs_status cdcs_psd_project_batched(int32_t nb, int32_t smax, const int32_t *sizes,
+                                     const int64_t *off, const float *W, float *P,
+                                     float *evals, const int64_t *eoff,
+                                     float *evecs, const int64_t *voff, hipStream_t stream);
+
+/*
+ * Affine projection: solve the KKT system of (E:OptCondMinYPrimal)
+ * [D A^T; A 0][x; y] = [r1; r2] by block elimination with the cached factor
+ * (the same matrix serves (E:OptCondMinYDual), Sec. IV-B.1):
+ *   y = M^-1 (A (w r1 / D) - r2),   x = (r1 - A^T y) / D.
+ *   r1, x [nnz] device FP64; r2, y [m] device FP64.  x may alias r1.
+ */
+cdcs_status cdcs_affine_project(const cdcs_handle *h, const double *r1, const double *r2,
+                                double *x, double *y, hipStream_t stream);
+
+/*
+ * ADMM iterations of Algorithm 1 (opts->form = CDCS_PRIMAL) or Algorithm 2
+ * (CDCS_DUAL) on the caller's state, until max(eps_p, eps_d) <= tol or
+ * max_iter iterations.  Residuals (Boyd et al. 2011, Sec. 3.3, relative form):
+ *   Alg. 1: eps_p = ||x_k - H_k x|| / max(||H_k x||, ||x_k||),
+ *           eps_d = rho ||sum_k H_k^T (x_k - x_k_prev)|| / ||sum_k H_k^T lambda_k||;
+ *   Alg. 2: eps_p = ||z_k - v_k|| / max(||z_k||, ||v_k||),
+ *           eps_d = rho ||v_k - v_k_prev|| / ||lambda_k||.
+ * With check_every > 0, check_every iterations are captured in one HIP graph
+ * and replayed; every kernel of an iteration after convergence returns at
+ * once.  Synchronises on stream.  Returns CDCS_OK when converged (or when
+ * tol = 0 and max_iter iterations ran), CDCS_E_NOT_CONVERGED at the cap,
+ * CDCS_E_NUMERIC if an eigensolve hit its sweep cap.  info may be NULL.
+ */
+cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st, const cdcs_options *opts,
+                            cdcs_info *info, hipStream_t stream);
+
+/* One iteration (eager launches) continuing from the state; equivalent to
+ * cdcs_admm_solve with max_iter = 1, tol = 0, check_every = 0. */
+cdcs_status cdcs_admm_step(cdcs_handle *h, const cdcs_state *st, int32_t form, double rho,
+                           hipStream_t stream);
+
+/* Residual history of the last solve: n_host pairs (eps_p, eps_d), host. */
+cdcs_status cdcs_residual_history(const cdcs_handle *h, double *hist_host, int32_t n_host);
+
+cdcs_status cdcs_destroy(cdcs_handle *h);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *cdcs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CDCS_H */

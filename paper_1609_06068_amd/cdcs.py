@@ -1,0 +1,317 @@
+"""Python binding of libcdcs.so (the gfx950 library declared in include/cdcs.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch supplies device memory and the stream.  Importing this
+module does not load the library; the first call does, and it fails loudly
+(CdcsLibraryMissing) when libcdcs.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcdcs.so")
+
+OK, E_ARG, E_PATTERN, E_RANK, E_DEVICE, E_NOMEM, E_NOT_CONVERGED, E_NUMERIC = range(8)
+PRIMAL, DUAL = 0, 1
+MAX_CLIQUE = 96
+STATUS_NAMES = {0: "CDCS_OK", 1: "CDCS_E_ARG", 2: "CDCS_E_PATTERN", 3: "CDCS_E_RANK", 4: "CDCS_E_DEVICE",
+                5: "CDCS_E_NOMEM", 6: "CDCS_E_NOT_CONVERGED", 7: "CDCS_E_NUMERIC"}
+
+# Every symbol include/cdcs.h declares.
+EXPORTS = ["cdcs_setup", "cdcs_get_sizes", "cdcs_clique_offsets", "cdcs_psd_project_batched",
+           "cdcs_affine_project", "cdcs_admm_solve", "cdcs_admm_step", "cdcs_residual_history",
+           "cdcs_destroy", "cdcs_last_error"]
+
+
+class CdcsLibraryMissing(ImportError):
+    pass
+
+
+class CdcsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Pattern(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("i", ctypes.c_void_p), ("j", ctypes.c_void_p)]
+
+
+class _Cliques(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("ptr", ctypes.c_void_p), ("vert", ctypes.c_void_p)]
+
+
+class _Constraints(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("dense", ctypes.c_int32), ("ptr", ctypes.c_void_p),
+                ("idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("form", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("jacobi_cap_hits", ctypes.c_int32), ("eps_p", ctypes.c_double), ("eps_d", ctypes.c_double),
+                ("obj_primal", ctypes.c_double), ("obj_dual", ctypes.c_double), ("loop_s", ctypes.c_double)]
+
+
+class _State(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("blk", ctypes.c_void_p),
+                ("lam", ctypes.c_void_p), ("v", ctypes.c_void_p)]
+
+
+class _Sizes(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("p", ctypes.c_int32), ("smax", ctypes.c_int32),
+                ("nnz", ctypes.c_int64), ("nslots", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libcdcs.so and declare the C signatures (no device work)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise CdcsLibraryMissing(f"{path} is not built (run __graft_entry__.build())")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    L.cdcs_setup.argtypes = [P(_Pattern), P(_Constraints), vp, vp, P(_Cliques), vp, vp, P(vp)]
+    L.cdcs_get_sizes.argtypes = [vp, P(_Sizes)]
+    L.cdcs_clique_offsets.argtypes = [vp, vp]
+    L.cdcs_psd_project_batched.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.cdcs_affine_project.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.cdcs_admm_solve.argtypes = [vp, P(_State), P(_Options), P(_Info), vp]
+    L.cdcs_admm_step.argtypes = [vp, P(_State), i32, dbl, vp]
+    L.cdcs_residual_history.argtypes = [vp, vp, i32]
+    L.cdcs_destroy.argtypes = [vp]
+    L.cdcs_last_error.argtypes = []
+    L.cdcs_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "cdcs_last_error":
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(st: int, what: str):
+    if st != OK:
+        msg = load_library().cdcs_last_error().decode(errors="replace")
+        raise CdcsError(st, f"{what}: {msg}")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the cdcs library needs a HIP device (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _stream(torch, stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _np_ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+@dataclass
+class SolveInfo:
+    iters: int
+    status: int
+    converged: bool
+    jacobi_cap_hits: int
+    eps_p: float
+    eps_d: float
+    obj_primal: float
+    obj_dual: float
+    loop_s: float
+
+
+class Solver:
+    """One SDP set up on the device (cdcs_setup) and its ADMM entry points."""
+
+    def __init__(self, prob):
+        L = load_library()
+        torch = _torch()
+        self._torch = torch
+        ei = np.ascontiguousarray(prob.ei, dtype=np.int32)
+        ej = np.ascontiguousarray(prob.ej, dtype=np.int32)
+        cptr = np.ascontiguousarray(prob.clique_ptr, dtype=np.int64)
+        cvert = np.ascontiguousarray(prob.clique_vert, dtype=np.int32)
+        b = np.ascontiguousarray(prob.b, dtype=np.float64)
+        c = np.ascontiguousarray(prob.c, dtype=np.float64)
+        pat = _Pattern(int(prob.n), int(ei.shape[0]), _np_ptr(ei), _np_ptr(ej))
+        cl = _Cliques(int(cptr.shape[0] - 1), _np_ptr(cptr), _np_ptr(cvert))
+        if prob.A is not None:
+            aval = np.ascontiguousarray(prob.A, dtype=np.float64)
+            cons = _Constraints(int(b.shape[0]), 1, None, None, _np_ptr(aval))
+            keep = (aval,)
+        else:
+            aptr = np.ascontiguousarray(prob.A_ptr, dtype=np.int64)
+            aidx = np.ascontiguousarray(prob.A_idx, dtype=np.int32)
+            aval = np.ascontiguousarray(prob.A_val, dtype=np.float64)
+            cons = _Constraints(int(b.shape[0]), 0, _np_ptr(aptr), _np_ptr(aidx), _np_ptr(aval))
+            keep = (aptr, aidx, aval)
+        h = ctypes.c_void_p()
+        st = L.cdcs_setup(ctypes.byref(pat), ctypes.byref(cons), _np_ptr(b), _np_ptr(c), ctypes.byref(cl),
+                          None, _stream(torch), ctypes.byref(h))
+        del keep
+        _check(st, "cdcs_setup")
+        self._h = h
+        sz = _Sizes()
+        _check(L.cdcs_get_sizes(h, ctypes.byref(sz)), "cdcs_get_sizes")
+        self.n, self.m, self.p, self.smax = sz.n, sz.m, sz.p, sz.smax
+        self.nnz, self.nslots = sz.nnz, sz.nslots
+        off = np.empty(self.p + 1, dtype=np.int64)
+        _check(L.cdcs_clique_offsets(h, _np_ptr(off)), "cdcs_clique_offsets")
+        self.offsets = off
+        self.sizes = np.diff(np.asarray(prob.clique_ptr, dtype=np.int64))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().cdcs_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def new_state(self, form: str = "primal") -> dict:
+        torch = self._torch
+        dev = torch.device("cuda")
+        st = {
+            "x": torch.zeros(self.nnz, dtype=torch.float64, device=dev),
+            "y": torch.zeros(self.m, dtype=torch.float64, device=dev),
+            "blk": torch.zeros(self.nslots, dtype=torch.float32, device=dev),
+            "lam": torch.zeros(self.nslots, dtype=torch.float32, device=dev),
+            "v": torch.zeros(self.nslots, dtype=torch.float32, device=dev) if form == "dual" else None,
+        }
+        return st
+
+    @staticmethod
+    def _cstate(st: dict) -> _State:
+        return _State(_ptr(st["x"]), _ptr(st["y"]), _ptr(st["blk"]), _ptr(st["lam"]), _ptr(st.get("v")))
+
+    def solve(self, state: dict, form: str = "primal", rho: float = 1.0, tol: float = 1e-4,
+              max_iter: int = 500, check_every: int = 50, stream=None, raise_on_cap: bool = False) -> SolveInfo:
+        L = load_library()
+        f = PRIMAL if form == "primal" else DUAL
+        opts = _Options(float(rho), float(tol), int(max_iter), f, int(check_every))
+        info = _Info()
+        cs = self._cstate(state)
+        st = L.cdcs_admm_solve(self._h, ctypes.byref(cs), ctypes.byref(opts), ctypes.byref(info),
+                               _stream(self._torch, stream))
+        if st not in (OK, E_NOT_CONVERGED) or (raise_on_cap and st == E_NOT_CONVERGED):
+            _check(st, "cdcs_admm_solve")
+        return SolveInfo(info.iters, info.status, bool(info.converged), info.jacobi_cap_hits, info.eps_p,
+                         info.eps_d, info.obj_primal, info.obj_dual, info.loop_s)
+
+    def step(self, state: dict, form: str = "primal", rho: float = 1.0, stream=None):
+        L = load_library()
+        cs = self._cstate(state)
+        _check(L.cdcs_admm_step(self._h, ctypes.byref(cs), PRIMAL if form == "primal" else DUAL, float(rho),
+                                _stream(self._torch, stream)), "cdcs_admm_step")
+
+    def history(self, n: int) -> np.ndarray:
+        out = np.zeros((n, 2))
+        _check(load_library().cdcs_residual_history(self._h, _np_ptr(out), int(n)), "cdcs_residual_history")
+        return out
+
+    def affine_project(self, r1, r2, stream=None):
+        torch = self._torch
+        x = torch.empty(self.nnz, dtype=torch.float64, device=r1.device)
+        y = torch.empty(self.m, dtype=torch.float64, device=r1.device)
+        r1 = r1.contiguous()
+        r2 = r2.contiguous()
+        _check(load_library().cdcs_affine_project(self._h, _ptr(r1), _ptr(r2), _ptr(x), _ptr(y),
+                                                   _stream(torch, stream)), "cdcs_affine_project")
+        return x, y
+
+
+def packed_offsets(sizes) -> np.ndarray:
+    sizes = np.asarray(sizes, dtype=np.int64)
+    off = np.zeros(sizes.shape[0] + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes * (sizes + 1) // 2)
+    return off
+
+
+def psd_project_batched(W, sizes, offsets=None, smax=None, eig: bool = False, stream=None):
+    """P(W_k) for a packed batch of symmetric blocks (device tensors).
+
+    W: float32 cuda tensor of packed lower triangles; sizes: int32 cuda tensor
+    (or host array); offsets: int64 cuda tensor of nb+1 packed offsets.
+    Returns P (and eigenvalues / eigenvector matrices when eig=True)."""
+    torch = _torch()
+    sizes_h = np.asarray(sizes.cpu() if hasattr(sizes, "cpu") else sizes, dtype=np.int64)
+    nb = int(sizes_h.shape[0])
+    if smax is None:
+        smax = int(sizes_h.max()) if nb else 1
+    if nb and (sizes_h.min() < 1 or sizes_h.max() > MAX_CLIQUE):
+        raise CdcsError(E_ARG, "block sizes must lie in 1..96")
+    dev = W.device
+    sizes_d = torch.as_tensor(sizes_h.astype(np.int32), device=dev)
+    if offsets is None:
+        offsets = torch.as_tensor(packed_offsets(sizes_h), device=dev)
+    W = W.contiguous()
+    P = torch.empty_like(W)
+    evals = evecs = eoff = voff = None
+    if eig:
+        eo = np.zeros(nb + 1, dtype=np.int64)
+        eo[1:] = np.cumsum(sizes_h)
+        vo = np.zeros(nb + 1, dtype=np.int64)
+        vo[1:] = np.cumsum(sizes_h * sizes_h)
+        eoff = torch.as_tensor(eo, device=dev)
+        voff = torch.as_tensor(vo, device=dev)
+        evals = torch.empty(int(eo[-1]), dtype=torch.float32, device=dev)
+        evecs = torch.empty(int(vo[-1]), dtype=torch.float32, device=dev)
+    st = load_library().cdcs_psd_project_batched(nb, int(smax), _ptr(sizes_d), _ptr(offsets), _ptr(W), _ptr(P),
+                                                 _ptr(evals), _ptr(eoff), _ptr(evecs), _ptr(voff),
+                                                 _stream(torch, stream))
+    _check(st, "cdcs_psd_project_batched")
+    if eig:
+        return P, evals, evecs, eoff, voff
+    return P
+
+
+def pack_blocks(blocks) -> np.ndarray:
+    """Full symmetric blocks -> packed lower triangles (row-major), layout only."""
+    out = []
+    for B in blocks:
+        ia, ib = np.tril_indices(B.shape[0])
+        out.append(np.asarray(B)[ia, ib])
+    return np.concatenate(out) if out else np.zeros(0)
+
+
+def unpack_blocks(packed, sizes, offsets=None):
+    """Packed lower triangles -> list of full symmetric numpy blocks, layout only."""
+    packed = np.asarray(packed)
+    sizes = np.asarray(sizes, dtype=np.int64)
+    if offsets is None:
+        offsets = packed_offsets(sizes)
+    blocks = []
+    for t, s in enumerate(sizes):
+        s = int(s)
+        B = np.zeros((s, s), dtype=packed.dtype)
+        ia, ib = np.tril_indices(s)
+        vals = packed[offsets[t]:offsets[t] + s * (s + 1) // 2]
+        B[ia, ib] = vals
+        B[ib, ia] = vals
+        blocks.append(B)
+    return blocks

@@ -1,0 +1,551 @@
+// C-ABI entry points: setup (validation, chordal-decomposition maps, upload,
+// KKT factorisation), the batched projection, the affine projection and the
+// ADMM driver with HIP-graph capture of whole iterations.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "cdcs_internal.h"
+
+using namespace cdcs;
+
+namespace {
+
+thread_local std::string g_err;
+
+cdcs_status fail(cdcs_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIP_OK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(e_ == hipErrorOutOfMemory ? CDCS_E_NOMEM : CDCS_E_DEVICE,          \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                \
+    } while (0)
+
+int64_t round_up(int64_t v, int64_t q) { return (v + q - 1) / q * q; }
+
+// Threads per workgroup of the projection kernel for a size bucket.
+int proj_threads(int smax) { return smax <= 32 ? 128 : 256; }
+
+struct GraphKey {
+    int form;
+    int K;
+    double rho;
+    const void *x, *y, *blk, *lam, *v;
+    bool operator<(const GraphKey &o) const {
+        return std::tie(form, K, rho, x, y, blk, lam, v) < std::tie(o.form, o.K, o.rho, o.x, o.y, o.blk, o.lam, o.v);
+    }
+};
+
+struct Bucket {
+    int smax;
+    int count;
+    int32_t *ids;  // device
+};
+
+}  // namespace
+
+struct cdcs_handle {
+    int device = 0;
+    Dev d;
+    std::vector<void *> allocs;
+    std::vector<int64_t> off_host;
+    std::vector<Bucket> buckets;
+    hipStream_t cap_stream = nullptr;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    std::vector<hipGraph_t> graph_defs;
+    int last_iters = 0;
+
+    template <typename T>
+    cdcs_status alloc(T **p, int64_t count) {
+        *p = nullptr;
+        if (count <= 0) count = 1;
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, (size_t)count * sizeof(T));
+        if (e != hipSuccess) return fail(CDCS_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        allocs.push_back(q);
+        *p = static_cast<T *>(q);
+        return CDCS_OK;
+    }
+
+    ~cdcs_handle() {
+        for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        for (auto g : graph_defs) (void)hipGraphDestroy(g);
+        for (void *p : allocs) (void)hipFree(p);
+        if (d.ctl_host) (void)hipHostFree(d.ctl_host);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
+};
+
+namespace {
+
+#define CK(expr)                          \
+    do {                                  \
+        cdcs_status s_ = (expr);          \
+        if (s_ != CDCS_OK) return s_;     \
+    } while (0)
+
+template <typename T>
+cdcs_status upload(cdcs_handle *h, T **dst, const std::vector<T> &src, hipStream_t s) {
+    CK(h->alloc(dst, (int64_t)src.size()));
+    (void)s;
+    // Synchronous copy: the host vectors die when setup returns, also on error paths.
+    if (!src.empty()) HIP_OK(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return CDCS_OK;
+}
+
+cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraints *A, const double *b,
+                  const double *c, const cdcs_cliques *cl, hipStream_t s) {
+    Dev &d = h->d;
+    if (!pat || !A || !b || !c || !cl) return fail(CDCS_E_ARG, "NULL argument");
+    if (pat->n < 1 || pat->nnz < 1 || !pat->i || !pat->j) return fail(CDCS_E_ARG, "empty or NULL pattern");
+    if (A->m < 1 || !A->val) return fail(CDCS_E_ARG, "no constraints");
+    if (cl->p < 1 || !cl->ptr || !cl->vert) return fail(CDCS_E_ARG, "no cliques");
+    const int32_t n = pat->n;
+    const int64_t nU = pat->nnz;
+    const int32_t m = A->m;
+    const int32_t p = cl->p;
+    if (nU >= (int64_t)1 << 31) return fail(CDCS_E_ARG, "pattern too large");
+    if (m > 8192) return fail(CDCS_E_ARG, "m > 8192 is not supported by the dense factor");
+
+    // Pattern: lower triangular, in range, distinct.
+    std::vector<std::pair<int64_t, int32_t>> keys((size_t)nU);
+    for (int64_t e = 0; e < nU; ++e) {
+        const int32_t i = pat->i[e], j = pat->j[e];
+        if (j < 0 || i < j || i >= n) return fail(CDCS_E_PATTERN, "pattern entry " + std::to_string(e) + " not lower triangular / out of range");
+        keys[(size_t)e] = {(int64_t)i * n + j, (int32_t)e};
+    }
+    std::sort(keys.begin(), keys.end());
+    for (size_t q = 1; q < keys.size(); ++q)
+        if (keys[q].first == keys[q - 1].first) return fail(CDCS_E_PATTERN, "duplicate pattern entry");
+    auto find = [&](int32_t i, int32_t j) -> int32_t {
+        const int64_t key = (int64_t)std::max(i, j) * n + std::min(i, j);
+        auto it = std::lower_bound(keys.begin(), keys.end(), std::make_pair(key, (int32_t)-1));
+        if (it == keys.end() || it->first != key) return -1;
+        return it->second;
+    };
+
+    // Cliques: E_k with vertices in increasing order (Sec. II-B); gather map H_k.
+    if (cl->ptr[0] != 0) return fail(CDCS_E_PATTERN, "clique ptr[0] != 0");
+    d.n = n;
+    d.m = m;
+    d.p = p;
+    d.nU = nU;
+    d.smax = 0;
+    h->off_host.assign((size_t)p + 1, 0);
+    std::vector<int32_t> size((size_t)p);
+    for (int32_t k = 0; k < p; ++k) {
+        const int64_t a0 = cl->ptr[k], a1 = cl->ptr[k + 1];
+        const int64_t sk = a1 - a0;
+        if (sk < 1 || sk > CDCS_MAX_CLIQUE)
+            return fail(sk < 1 ? CDCS_E_PATTERN : CDCS_E_ARG, "clique " + std::to_string(k) + " size " + std::to_string(sk) + " outside 1.." + std::to_string(CDCS_MAX_CLIQUE));
+        for (int64_t q = a0; q < a1; ++q) {
+            const int32_t v = cl->vert[q];
+            if (v < 0 || v >= n) return fail(CDCS_E_PATTERN, "clique vertex out of range");
+            if (q > a0 && v <= cl->vert[q - 1]) return fail(CDCS_E_PATTERN, "clique " + std::to_string(k) + " not strictly increasing");
+        }
+        size[(size_t)k] = (int32_t)sk;
+        d.smax = std::max<int32_t>(d.smax, (int32_t)sk);
+        h->off_host[(size_t)k + 1] = h->off_host[(size_t)k] + sk * (sk + 1) / 2;
+    }
+    const int64_t nslots = h->off_host[(size_t)p];
+    if (nslots >= (int64_t)1 << 31) return fail(CDCS_E_ARG, "too many clique slots");
+    d.nslots = nslots;
+    std::vector<int32_t> gather((size_t)nslots);
+    std::vector<int32_t> cnt((size_t)nU, 0);
+    for (int32_t k = 0; k < p; ++k) {
+        const int32_t *cv = cl->vert + cl->ptr[k];
+        const int sk = size[(size_t)k];
+        int64_t g = h->off_host[(size_t)k];
+        for (int a = 0; a < sk; ++a)
+            for (int bb = 0; bb <= a; ++bb, ++g) {
+                const int32_t e = find(cv[a], cv[bb]);
+                if (e < 0) return fail(CDCS_E_PATTERN, "clique " + std::to_string(k) + " pair missing from the pattern");
+                gather[(size_t)g] = e;
+                ++cnt[(size_t)e];
+            }
+    }
+    // D = sum_k H_k^T H_k: overlap count of each entry; inverse map as CSR.
+    std::vector<int32_t> inv_ptr((size_t)nU + 1, 0);
+    for (int64_t e = 0; e < nU; ++e) {
+        if (cnt[(size_t)e] == 0) return fail(CDCS_E_PATTERN, "pattern entry " + std::to_string(e) + " lies in no clique");
+        inv_ptr[(size_t)e + 1] = inv_ptr[(size_t)e] + cnt[(size_t)e];
+    }
+    std::vector<int32_t> inv_slot((size_t)nslots), fillp(inv_ptr.begin(), inv_ptr.end() - 1);
+    for (int64_t g = 0; g < nslots; ++g) inv_slot[(size_t)fillp[(size_t)gather[(size_t)g]]++] = (int32_t)g;
+
+    d.ldU = round_up(nU, 64);
+    d.ldM = round_up(m, 4);
+    std::vector<double> invD((size_t)d.ldU, 0.0), s2((size_t)d.ldU, 0.0), wt((size_t)d.ldU, 0.0), cvec((size_t)nU);
+    for (int64_t e = 0; e < nU; ++e) {
+        const double w = (pat->i[e] == pat->j[e]) ? 1.0 : 2.0;
+        const double D = (double)cnt[(size_t)e];
+        wt[(size_t)e] = w;
+        invD[(size_t)e] = 1.0 / D;
+        s2[(size_t)e] = 1.0 / (w * D);
+        cvec[(size_t)e] = c[e];
+    }
+
+    // Constraint matrix, Aw = w A in FP32, both row-major and transposed.
+    const int64_t dense_elems = (int64_t)m * d.ldU;
+    if (dense_elems > ((int64_t)1 << 33)) return fail(CDCS_E_ARG, "dense A too large (sparse A path not built)");
+    std::vector<float> Aw((size_t)dense_elems, 0.0f);
+    if (A->dense) {
+        for (int32_t i = 0; i < m; ++i)
+            for (int64_t e = 0; e < nU; ++e)
+                Aw[(size_t)(i * d.ldU + e)] = (float)(wt[(size_t)e] * A->val[(size_t)i * nU + e]);
+    } else {
+        if (!A->ptr || !A->idx) return fail(CDCS_E_ARG, "CSR A without ptr/idx");
+        std::vector<double> row((size_t)nU);
+        for (int32_t i = 0; i < m; ++i) {
+            std::fill(row.begin(), row.end(), 0.0);
+            for (int64_t q = A->ptr[i]; q < A->ptr[i + 1]; ++q) {
+                const int32_t e = A->idx[q];
+                if (e < 0 || e >= nU) return fail(CDCS_E_PATTERN, "A entry index out of range");
+                row[(size_t)e] += A->val[q];
+            }
+            for (int64_t e = 0; e < nU; ++e) Aw[(size_t)(i * d.ldU + e)] = (float)(wt[(size_t)e] * row[(size_t)e]);
+        }
+    }
+    std::vector<float> AwT((size_t)(nU * d.ldM), 0.0f);
+    for (int32_t i = 0; i < m; ++i)
+        for (int64_t e = 0; e < nU; ++e) AwT[(size_t)(e * d.ldM + i)] = Aw[(size_t)(i * d.ldU + e)];
+
+    // Cliques by decreasing size, split into LDS size buckets.
+    std::vector<int32_t> order((size_t)p);
+    for (int32_t k = 0; k < p; ++k) order[(size_t)k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t bq) { return size[(size_t)a] > size[(size_t)bq]; });
+    const int bmax[3] = {32, 64, 96};
+    std::vector<std::vector<int32_t>> bl(3);
+    for (int32_t k : order) {
+        const int sk = size[(size_t)k];
+        bl[sk <= 32 ? 0 : (sk <= 64 ? 1 : 2)].push_back(k);
+    }
+
+    // Upload.
+    CK(upload(h, &d.clq_size, size, s));
+    CK(upload(h, &d.clq_off, h->off_host, s));
+    CK(upload(h, &d.gather, gather, s));
+    CK(upload(h, &d.inv_ptr, inv_ptr, s));
+    CK(upload(h, &d.inv_slot, inv_slot, s));
+    CK(upload(h, &d.invD, invD, s));
+    CK(upload(h, &d.s2, s2, s));
+    CK(upload(h, &d.wt, wt, s));
+    CK(upload(h, &d.c, cvec, s));
+    CK(upload(h, &d.b, std::vector<double>(b, b + m), s));
+    CK(upload(h, &d.Aw, Aw, s));
+    CK(upload(h, &d.AwT, AwT, s));
+    CK(upload(h, &d.order, order, s));
+    for (int q = 0; q < 3; ++q) {
+        if (bl[(size_t)q].empty()) continue;
+        Bucket bk{bmax[q], (int)bl[(size_t)q].size(), nullptr};
+        CK(upload(h, &bk.ids, bl[(size_t)q], s));
+        h->buckets.push_back(bk);
+    }
+    // Work buffers (zeroed: padding of u and the first generation of sx matter).
+    CK(h->alloc(&d.u, d.ldU));
+    HIP_OK(hipMemsetAsync(d.u, 0, (size_t)d.ldU * sizeof(double), s));
+    CK(h->alloc(&d.t, d.ldM));
+    CK(h->alloc(&d.y1, d.ldM));
+    CK(h->alloc(&d.sx, 2 * nU));
+    HIP_OK(hipMemsetAsync(d.sx, 0, (size_t)(2 * nU) * sizeof(double), s));
+    CK(h->alloc(&d.cpart, 4 * (int64_t)p));
+    HIP_OK(hipMemsetAsync(d.cpart, 0, (size_t)(4 * p) * sizeof(double), s));
+    CK(h->alloc(&d.spart, 2 * (int64_t)scatter_blocks(d)));
+    CK(h->alloc(&d.vpart, 5 * (int64_t)vupdate_blocks(d)));
+    CK(h->alloc(&d.obj, 2));
+    CK(h->alloc(&d.info, 4));
+    HIP_OK(hipMemsetAsync(d.info, 0, 4 * sizeof(int32_t), s));
+    CK(h->alloc(&d.ctl, 1));
+    HIP_OK(hipHostMalloc((void **)&d.ctl_host, sizeof(Ctl), hipHostMallocDefault));
+    d.hist_cap = 0;
+
+    // KKT factor: M = Aw diag(s2) Aw^T, Cholesky, inverse factors.
+    double *M = nullptr, *diag0 = nullptr;
+    HIP_OK(hipMalloc(&M, (size_t)m * m * sizeof(double)));
+    hipError_t e1 = hipMalloc(&diag0, (size_t)m * sizeof(double));
+    if (e1 != hipSuccess) {
+        (void)hipFree(M);
+        return fail(CDCS_E_NOMEM, "hipMalloc diag");
+    }
+    CK(h->alloc(&d.Linv, (int64_t)m * m));
+    CK(h->alloc(&d.LinvT, (int64_t)m * m));
+    launch_syrk(d.Aw, d.ldU, d.s2, m, M, s);
+    launch_potrf(M, m, diag0, d.info, s);
+    launch_trtri(M, m, d.LinvT, d.Linv, s);
+    int32_t info_h[4] = {0, 0, 0, 0};
+    hipError_t e2 = hipMemcpyAsync(info_h, d.info, sizeof(info_h), hipMemcpyDeviceToHost, s);
+    hipError_t e3 = hipStreamSynchronize(s);
+    (void)hipFree(M);
+    (void)hipFree(diag0);
+    if (e2 != hipSuccess || e3 != hipSuccess)
+        return fail(CDCS_E_DEVICE, std::string("setup kernels: ") + hipGetErrorString(e2 != hipSuccess ? e2 : e3));
+    if (info_h[0] != 0)
+        return fail(CDCS_E_RANK, "A D^-1 A^T is not positive definite (pivot " + std::to_string(info_h[1]) + "): A is rank deficient");
+    HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    return CDCS_OK;
+}
+
+void launch_projection(cdcs_handle *h, int mode, const cdcs_state *st, double rho, hipStream_t s) {
+    Dev &d = h->d;
+    for (const Bucket &bk : h->buckets) {
+        ProjArgs a{};
+        a.mode = mode;
+        a.nblk = bk.count;
+        a.ids = bk.ids;
+        a.size = d.clq_size;
+        a.off = d.clq_off;
+        a.gather = d.gather;
+        a.x = st->x;
+        a.blk = st->blk;
+        a.lam = st->lam;
+        a.v = st->v;
+        a.rho = rho;
+        a.cpart = d.cpart;
+        a.ctl = d.ctl;
+        launch_project(a, bk.smax, proj_threads(bk.smax), s);
+    }
+}
+
+void enqueue_iteration(cdcs_handle *h, const cdcs_state *st, int form, double rho, hipStream_t s) {
+    Dev &d = h->d;
+    if (form == CDCS_PRIMAL) {
+        launch_scatter_primal(d, st->blk, st->lam, rho, s);
+        launch_check_primal(d, rho, s);
+        launch_affine(d, d.b, 1.0, st->x, st->y, d.ctl, s);
+        launch_projection(h, PROJ_PRIMAL, st, rho, s);
+    } else {
+        launch_projection(h, PROJ_DUAL, st, rho, s);
+        launch_scatter_dual(d, st->blk, st->lam, rho, s);
+        launch_affine(d, d.b, -1.0 / rho, st->x, st->y, d.ctl, s);
+        launch_vupdate(d, st->x, st->blk, st->lam, st->v, rho, s);
+        launch_check_dual(d, rho, s);
+    }
+}
+
+cdcs_status get_graph(cdcs_handle *h, const cdcs_state *st, int form, int K, double rho, hipGraphExec_t *out) {
+    GraphKey key{form, K, rho, st->x, st->y, st->blk, st->lam, st->v};
+    auto it = h->graphs.find(key);
+    if (it != h->graphs.end()) {
+        *out = it->second;
+        return CDCS_OK;
+    }
+    HIP_OK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < K; ++i) enqueue_iteration(h, st, form, rho, h->cap_stream);
+    hipGraph_t g = nullptr;
+    HIP_OK(hipStreamEndCapture(h->cap_stream, &g));
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(CDCS_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    h->graph_defs.push_back(g);
+    h->graphs[key] = ex;
+    *out = ex;
+    return CDCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cdcs_last_error(void) { return g_err.c_str(); }
+
+cdcs_status cdcs_setup(const cdcs_pattern *pattern, const cdcs_constraints *A, const double *b, const double *c,
+                       const cdcs_cliques *cliques, const cdcs_options *opts, hipStream_t stream,
+                       cdcs_handle **out) {
+    (void)opts;
+    if (!out) return fail(CDCS_E_ARG, "out is NULL");
+    *out = nullptr;
+    g_err.clear();
+    cdcs_handle *h = new (std::nothrow) cdcs_handle();
+    if (!h) return fail(CDCS_E_NOMEM, "host allocation");
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(CDCS_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    cdcs_status st = build(h, pattern, A, b, c, cliques, stream);
+    if (st != CDCS_OK) {
+        (void)hipStreamSynchronize(stream);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return CDCS_OK;
+}
+
+cdcs_status cdcs_get_sizes(const cdcs_handle *h, cdcs_sizes *out) {
+    if (!h || !out) return fail(CDCS_E_ARG, "NULL argument");
+    out->n = h->d.n;
+    out->m = h->d.m;
+    out->p = h->d.p;
+    out->smax = h->d.smax;
+    out->nnz = h->d.nU;
+    out->nslots = h->d.nslots;
+    return CDCS_OK;
+}
+
+cdcs_status cdcs_clique_offsets(const cdcs_handle *h, int64_t *off_host) {
+    if (!h || !off_host) return fail(CDCS_E_ARG, "NULL argument");
+    std::memcpy(off_host, h->off_host.data(), h->off_host.size() * sizeof(int64_t));
+    return CDCS_OK;
+}
+
+cdcs_status cdcs_psd_project_batched(int32_t nb, int32_t smax, const int32_t *sizes, const int64_t *off,
+                                     const float *W, float *P, float *evals, const int64_t *eoff, float *evecs,
+                                     const int64_t *voff, hipStream_t stream) {
+    if (nb <= 0) return CDCS_OK;
+    if (smax < 1 || smax > CDCS_MAX_CLIQUE) return fail(CDCS_E_ARG, "smax outside 1..CDCS_MAX_CLIQUE");
+    if (!sizes || !off || !W || !P) return fail(CDCS_E_ARG, "NULL device pointer");
+    if ((evals && !eoff) || (evecs && !voff)) return fail(CDCS_E_ARG, "evals/evecs need eoff/voff");
+    ProjArgs a{};
+    a.mode = PROJ_STANDALONE;
+    a.nblk = nb;
+    a.size = sizes;
+    a.off = off;
+    a.Win = W;
+    a.Pout = P;
+    a.evals = evals;
+    a.eoff = eoff;
+    a.evecs = evecs;
+    a.voff = voff;
+    const int bucket = smax <= 32 ? 32 : (smax <= 64 ? 64 : 96);
+    launch_project(a, bucket, proj_threads(bucket), stream);
+    HIP_OK(hipGetLastError());
+    return CDCS_OK;
+}
+
+cdcs_status cdcs_affine_project(const cdcs_handle *h, const double *r1, const double *r2, double *x, double *y,
+                                hipStream_t stream) {
+    if (!h || !r1 || !r2 || !x || !y) return fail(CDCS_E_ARG, "NULL argument");
+    const Dev &d = h->d;
+    launch_scale_u(d, r1, stream);
+    launch_affine(d, r2, 1.0, x, y, nullptr, stream);
+    HIP_OK(hipGetLastError());
+    return CDCS_OK;
+}
+
+cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st, const cdcs_options *opts, cdcs_info *info,
+                            hipStream_t stream) {
+    if (!h || !st || !opts) return fail(CDCS_E_ARG, "NULL argument");
+    if (!st->x || !st->y || !st->blk || !st->lam) return fail(CDCS_E_ARG, "state has NULL buffers");
+    const int form = opts->form;
+    if (form != CDCS_PRIMAL && form != CDCS_DUAL) return fail(CDCS_E_ARG, "bad form");
+    if (form == CDCS_DUAL && !st->v) return fail(CDCS_E_ARG, "dual form needs state.v");
+    if (!(opts->rho > 0.0) || !(opts->tol >= 0.0) || opts->max_iter < 1)
+        return fail(CDCS_E_ARG, "need rho > 0, tol >= 0, max_iter >= 1");
+    Dev &d = h->d;
+    const double rho = opts->rho;
+    if (d.hist_cap < opts->max_iter) {
+        if (d.hist) {
+            HIP_OK(hipStreamSynchronize(stream));
+            (void)hipFree(d.hist);
+            h->allocs.erase(std::remove(h->allocs.begin(), h->allocs.end(), (void *)d.hist), h->allocs.end());
+            d.hist = nullptr;
+        }
+        CK(h->alloc(&d.hist, 2 * (int64_t)opts->max_iter));
+        d.hist_cap = opts->max_iter;
+        // captured graphs hold the old history pointer
+        for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+        h->graphs.clear();
+    }
+    launch_reset_ctl(d, opts->max_iter, opts->tol, stream);
+    HIP_OK(hipGetLastError());
+    auto t0 = std::chrono::steady_clock::now();
+    const int K = opts->check_every;
+    if (K > 0) {
+        hipGraphExec_t ex = nullptr;
+        CK(get_graph(h, st, form, K, rho, &ex));
+        for (int done = 0; done < opts->max_iter; done += K) {
+            HIP_OK(hipGraphLaunch(ex, stream));
+            HIP_OK(hipMemcpyAsync(d.ctl_host, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+            HIP_OK(hipStreamSynchronize(stream));
+            if (d.ctl_host->stop) break;
+        }
+    } else {
+        for (int it = 0; it < opts->max_iter; ++it) {
+            enqueue_iteration(h, st, form, rho, stream);
+            HIP_OK(hipGetLastError());
+            if ((it + 1) % 16 == 0) {
+                HIP_OK(hipMemcpyAsync(d.ctl_host, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+                HIP_OK(hipStreamSynchronize(stream));
+                if (d.ctl_host->stop) break;
+            }
+        }
+    }
+    if (form == CDCS_PRIMAL) {
+        // residuals of the last iteration need the next right-hand side's scatter
+        launch_scatter_primal(d, st->blk, st->lam, rho, stream);
+        launch_check_primal(d, rho, stream);
+    }
+    launch_objectives(d, st->x, st->y, stream);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(d.ctl_host, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    double obj[2] = {0.0, 0.0};
+    HIP_OK(hipMemcpyAsync(obj, d.obj, sizeof(obj), hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    auto t1 = std::chrono::steady_clock::now();
+    const Ctl c = *d.ctl_host;
+    h->last_iters = c.iter;
+    cdcs_status status = CDCS_OK;
+    if (c.jacobi_cap > 0) status = CDCS_E_NUMERIC;
+    else if (c.stop != 1 && opts->tol > 0.0) status = CDCS_E_NOT_CONVERGED;
+    if (info) {
+        info->iters = c.iter;
+        info->status = status;
+        info->converged = (c.stop == 1);
+        info->jacobi_cap_hits = c.jacobi_cap;
+        info->eps_p = c.eps_p;
+        info->eps_d = c.eps_d;
+        if (form == CDCS_PRIMAL) {
+            info->obj_primal = obj[0];
+            info->obj_dual = -rho * obj[1];
+        } else {
+            info->obj_primal = -rho * obj[0];
+            info->obj_dual = obj[1];
+        }
+        info->loop_s = std::chrono::duration<double>(t1 - t0).count();
+    }
+    if (status != CDCS_OK)
+        g_err = status == CDCS_E_NUMERIC ? "an eigensolve hit its sweep cap" : "iteration cap reached";
+    return status;
+}
+
+cdcs_status cdcs_admm_step(cdcs_handle *h, const cdcs_state *st, int32_t form, double rho, hipStream_t stream) {
+    cdcs_options o{};
+    o.rho = rho;
+    o.tol = 0.0;
+    o.max_iter = 1;
+    o.form = form;
+    o.check_every = 0;
+    return cdcs_admm_solve(h, st, &o, nullptr, stream);
+}
+
+cdcs_status cdcs_residual_history(const cdcs_handle *h, double *hist_host, int32_t n_host) {
+    if (!h || (!hist_host && n_host > 0)) return fail(CDCS_E_ARG, "NULL argument");
+    const int n = std::min<int>(n_host, std::min(h->last_iters, h->d.hist_cap));
+    if (n <= 0) return CDCS_OK;
+    HIP_OK(hipMemcpy(hist_host, h->d.hist, (size_t)n * 2 * sizeof(double), hipMemcpyDeviceToHost));
+    return CDCS_OK;
+}
+
+cdcs_status cdcs_destroy(cdcs_handle *h) {
+    if (!h) return CDCS_OK;
+    (void)hipDeviceSynchronize();
+    delete h;
+    return CDCS_OK;
+}
+
+}  // extern "C"

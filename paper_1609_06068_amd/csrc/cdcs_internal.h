@@ -1,0 +1,119 @@
+// Internal declarations of the gfx950 library: the handle, the device-side
+// control block and the kernel launchers shared between translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cdcs.h"
+
+namespace cdcs {
+
+// Device control block of an ADMM solve.  Kernels of an iteration read
+// `stop` first and return at once when it is set, so a captured graph of
+// several iterations becomes a no-op after convergence.
+struct Ctl {
+    int32_t iter;       // completed iterations
+    int32_t stop;       // 0 running, 1 converged, 2 iteration cap
+    int32_t max_iter;
+    int32_t jacobi_cap; // eigensolves that hit the sweep cap
+    double tol;
+    double eps_p, eps_d;
+};
+
+// Arguments of the batched projection kernel.
+enum ProjMode : int32_t {
+    PROJ_STANDALONE = 0,  // W given packed, P written packed
+    PROJ_PRIMAL = 1,      // Alg. 1: W = H_k x - lam/rho; x_k = P(W); lam += rho (x_k - H_k x)
+    PROJ_DUAL = 2,        // Alg. 2: W = v - lam/rho; z_k = P(W)
+};
+
+struct ProjArgs {
+    int32_t mode;
+    int32_t nblk;              // blocks in this launch
+    const int32_t *ids;        // [nblk] block ids (NULL: identity)
+    const int32_t *size;       // [*] block sizes
+    const int64_t *off;        // [*] packed offsets
+    // standalone
+    const float *Win;
+    float *Pout;
+    float *evals;
+    const int64_t *eoff;
+    float *evecs;
+    const int64_t *voff;
+    // ADMM
+    const int32_t *gather;     // [nslots] pattern entry of each packed slot
+    const double *x;           // [nnz]
+    float *blk;                // [nslots]
+    float *lam;                // [nslots]
+    const float *v;            // [nslots]
+    double rho;
+    double *cpart;             // [p][4] per-block partial sums
+    Ctl *ctl;                  // may be NULL (standalone)
+};
+
+void launch_project(const ProjArgs &a, int smax, int nthreads, hipStream_t s);
+
+// Affine-step, scatter, residual and setup kernels (kernels_affine.hip).
+struct Dev {
+    // problem
+    int32_t n = 0, m = 0, p = 0, smax = 0;
+    int64_t nU = 0, nslots = 0;
+    int64_t ldU = 0;               // row stride of Aw (nU rounded up to 64)
+    int64_t ldM = 0;               // row stride of AwT (m rounded up to 4)
+    int32_t *clq_size = nullptr;   // [p]
+    int64_t *clq_off = nullptr;    // [p+1]
+    int32_t *gather = nullptr;     // [nslots]
+    int32_t *inv_ptr = nullptr;    // [nU+1]
+    int32_t *inv_slot = nullptr;   // [nslots]
+    double *invD = nullptr;        // [nU]  1 / D_e
+    double *s2 = nullptr;          // [nU]  1 / (w_e D_e)
+    double *wt = nullptr;          // [nU]  w_e (1 diagonal, 2 off-diagonal)
+    double *c = nullptr;           // [nU]
+    double *b = nullptr;           // [m]
+    float *Aw = nullptr;           // [m * ldU] row-major, w_e * A_ie, zero padded
+    float *AwT = nullptr;          // [nU * ldM] row-major transpose of Aw, zero padded
+    double *Linv = nullptr;        // [m * m] row-major, L^-1 (lower)
+    double *LinvT = nullptr;       // [m * m] row-major, L^-T (upper)
+    int32_t *order = nullptr;      // [p] cliques by decreasing size
+    // work
+    double *u = nullptr;           // [ldU] r1 / D, zero padded
+    double *t = nullptr;           // [m]
+    double *y1 = nullptr;          // [m]
+    double *sx = nullptr;          // [2 * nU] sum_k H_k^T x_k, two generations
+    double *cpart = nullptr;       // [p * 4]
+    double *spart = nullptr;       // [nsblk * 2]
+    double *vpart = nullptr;       // [nvblk * 5]
+    double *hist = nullptr;        // [hist_cap * 2]
+    double *obj = nullptr;         // [2]
+    int32_t hist_cap = 0;
+    int32_t *info = nullptr;       // [4] setup status words
+    Ctl *ctl = nullptr;
+    Ctl *ctl_host = nullptr;       // pinned mirror
+};
+
+// scatter / residual / affine kernels
+int scatter_blocks(const Dev &d);
+int vupdate_blocks(const Dev &d);
+void launch_reset_ctl(const Dev &d, int max_iter, double tol, hipStream_t s);
+void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s);
+void launch_check_primal(const Dev &d, double rho, hipStream_t s);
+void launch_scatter_dual(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s);
+void launch_vupdate(const Dev &d, const double *x, const float *blk, float *lam, float *v, double rho,
+                    hipStream_t s);
+void launch_check_dual(const Dev &d, double rho, hipStream_t s);
+void launch_scale_u(const Dev &d, const double *r1, hipStream_t s);
+void launch_affine(const Dev &d, const double *r2, double r2scale, double *x, double *y, const Ctl *ctl,
+                   hipStream_t s);
+void launch_objectives(const Dev &d, const double *x, const double *y, hipStream_t s);
+
+// setup kernels (kernels_setup.hip)
+void launch_syrk(const float *Aw, int64_t ld, const double *s2, int m, double *M, hipStream_t s);
+void launch_potrf(double *M, int m, double *diag0, int32_t *info, hipStream_t s);
+void launch_trtri(const double *L, int m, double *LinvT, double *Linv, hipStream_t s);
+
+}  // namespace cdcs

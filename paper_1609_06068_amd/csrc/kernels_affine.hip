@@ -1,0 +1,414 @@
+// Scatter-add with overlap counts, affine projection, multiplier epilogue of
+// Algorithm 2 and the residual / stopping reductions.
+//
+// Paper anchors: the right-hand sides of (E:OptCondMinYPrimal) and
+// (E:OptCondMinYDual) (sums of H_k^T over cliques), block elimination with the
+// cached factor (Sec. III-B.1), (E:vkEqn) and (E:MultUpdateDualSDP), and the
+// stopping rule of Algorithms 1 and 2.
+//
+// Determinism: the scatter is owner-computes over the inverse map (each pattern
+// entry sums its own clique slots in a fixed order) and every reduction is a
+// fixed-shape tree, so repeated runs give identical bits.
+#include "cdcs_internal.h"
+
+namespace cdcs {
+namespace {
+
+constexpr int kNT = 256;
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block sum (kNT threads), result valid in every thread.
+__device__ __forceinline__ double block_sum_d(double v, double *red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    v = wave_sum_d(v);
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < kNT / 64; ++i) r += red[i];
+    return r;
+}
+
+__global__ __launch_bounds__(kNT) void k_reset_ctl(Ctl *ctl, int max_iter, double tol) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctl->iter = 0;
+        ctl->stop = 0;
+        ctl->max_iter = max_iter;
+        ctl->jacobi_cap = 0;
+        ctl->tol = tol;
+        ctl->eps_p = 0.0;
+        ctl->eps_d = 0.0;
+    }
+}
+
+// Alg. 1 right-hand side r1 = sum_k H_k^T (x_k + lam_k / rho) - c / rho, u = r1 / D,
+// plus the dual-residual terms: S^n = sum_k H_k^T x_k is kept in two generations
+// (indexed by the parity of the completed-iteration count, so a repeated launch
+// for the same n rewrites the same values), and sum_k H_k^T lam_k.
+__global__ __launch_bounds__(kNT) void k_scatter_primal(const int32_t *__restrict__ inv_ptr,
+                                                        const int32_t *__restrict__ inv_slot,
+                                                        const float *__restrict__ blk,
+                                                        const float *__restrict__ lam,
+                                                        const double *__restrict__ c,
+                                                        const double *__restrict__ invD,
+                                                        const double *__restrict__ wt, double *__restrict__ u,
+                                                        double *__restrict__ sx, double *__restrict__ spart,
+                                                        int64_t nU, double rho, const Ctl *ctl) {
+    __shared__ double red[kNT / 64];
+    if (ctl->stop) return;
+    const int n = ctl->iter;
+    const int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    double ds2 = 0.0, sl2 = 0.0;
+    if (e < nU) {
+        double s_x = 0.0, s_l = 0.0;
+        const int32_t q1 = inv_ptr[e + 1];
+        for (int32_t q = inv_ptr[e]; q < q1; ++q) {
+            const int32_t sl = inv_slot[q];
+            s_x += (double)blk[sl];
+            s_l += (double)lam[sl];
+        }
+        const double r1 = s_x + s_l / rho - c[e] / rho;
+        u[e] = r1 * invD[e];
+        double *cur = sx + (int64_t)(n & 1) * nU;
+        const double *prev = sx + (int64_t)((n + 1) & 1) * nU;
+        const double d = s_x - prev[e];
+        cur[e] = s_x;
+        const double w = wt[e];
+        ds2 = w * d * d;
+        sl2 = w * s_l * s_l;
+    }
+    ds2 = block_sum_d(ds2, red);
+    sl2 = block_sum_d(sl2, red);
+    if (threadIdx.x == 0) {
+        spart[2 * (int64_t)blockIdx.x + 0] = ds2;
+        spart[2 * (int64_t)blockIdx.x + 1] = sl2;
+    }
+}
+
+// Alg. 1 residual check of iteration n = ctl->iter (if any), then start the next one.
+__global__ __launch_bounds__(kNT) void k_check_primal(const double *__restrict__ cpart, int p,
+                                                      const double *__restrict__ spart, int nsblk, double rho,
+                                                      double *__restrict__ hist, int hist_cap, Ctl *ctl) {
+    __shared__ double red[kNT / 64];
+    if (ctl->stop) return;
+    const int n = ctl->iter;
+    const int tid = threadIdx.x;
+    if (n >= 1) {
+        double r2 = 0.0, h2 = 0.0, x2 = 0.0, d2 = 0.0, l2 = 0.0;
+        for (int k = tid; k < p; k += kNT) {
+            r2 += cpart[4 * (int64_t)k + 0];
+            h2 += cpart[4 * (int64_t)k + 1];
+            x2 += cpart[4 * (int64_t)k + 2];
+        }
+        for (int b = tid; b < nsblk; b += kNT) {
+            d2 += spart[2 * (int64_t)b + 0];
+            l2 += spart[2 * (int64_t)b + 1];
+        }
+        r2 = block_sum_d(r2, red);
+        h2 = block_sum_d(h2, red);
+        x2 = block_sum_d(x2, red);
+        d2 = block_sum_d(d2, red);
+        l2 = block_sum_d(l2, red);
+        if (tid == 0) {
+            const double den_p = fmax(sqrt(h2), sqrt(x2));
+            const double num_p = sqrt(r2);
+            const double eps_p = den_p > 0.0 ? num_p / den_p : num_p;
+            const double num_d = rho * sqrt(d2);
+            const double den_d = sqrt(l2);
+            const double eps_d = den_d > 0.0 ? num_d / den_d : num_d;
+            ctl->eps_p = eps_p;
+            ctl->eps_d = eps_d;
+            if (n - 1 < hist_cap) {
+                hist[2 * (int64_t)(n - 1) + 0] = eps_p;
+                hist[2 * (int64_t)(n - 1) + 1] = eps_d;
+            }
+            if (fmax(eps_p, eps_d) <= ctl->tol) {
+                ctl->stop = 1;
+                return;
+            }
+        }
+    }
+    if (tid == 0) {
+        if (ctl->stop == 0) {
+            if (n >= ctl->max_iter) ctl->stop = 2;
+            else ctl->iter = n + 1;
+        }
+    }
+}
+
+// Alg. 2 right-hand side r1 = c - sum_k H_k^T (z_k + lam_k / rho), u = r1 / D.
+__global__ __launch_bounds__(kNT) void k_scatter_dual(const int32_t *__restrict__ inv_ptr,
+                                                      const int32_t *__restrict__ inv_slot,
+                                                      const float *__restrict__ blk,
+                                                      const float *__restrict__ lam,
+                                                      const double *__restrict__ c,
+                                                      const double *__restrict__ invD, double *__restrict__ u,
+                                                      int64_t nU, double rho, const Ctl *ctl) {
+    if (ctl->stop) return;
+    const int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (e >= nU) return;
+    double s = 0.0;
+    const int32_t q1 = inv_ptr[e + 1];
+    for (int32_t q = inv_ptr[e]; q < q1; ++q) {
+        const int32_t sl = inv_slot[q];
+        s += (double)blk[sl] + (double)lam[sl] / rho;
+    }
+    u[e] = (c[e] - s) * invD[e];
+}
+
+// Alg. 2 epilogue: v_k = z_k + lam_k / rho + H_k x (E:vkEqn),
+// lam_k += rho (z_k - v_k) (E:MultUpdateDualSDP), and residual partial sums.
+__global__ __launch_bounds__(kNT) void k_vupdate(const int32_t *__restrict__ gather,
+                                                 const double *__restrict__ x, const double *__restrict__ wt,
+                                                 const float *__restrict__ blk, float *__restrict__ lam,
+                                                 float *__restrict__ v, double *__restrict__ vpart,
+                                                 int64_t nslots, double rho, const Ctl *ctl) {
+    __shared__ double red[kNT / 64];
+    if (ctl->stop) return;
+    const int64_t s = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0, q4 = 0.0;
+    if (s < nslots) {
+        const int32_t e = gather[s];
+        const double hx = x[e];
+        const double z = blk[s], l = lam[s], vo = v[s];
+        const double vn = z + l / rho + hx;
+        const double ln = l + rho * (z - vn);
+        v[s] = (float)vn;
+        lam[s] = (float)ln;
+        const double w = wt[e];
+        q0 = w * (z - vn) * (z - vn);
+        q1 = w * z * z;
+        q2 = w * vn * vn;
+        q3 = w * (vn - vo) * (vn - vo);
+        q4 = w * ln * ln;
+    }
+    q0 = block_sum_d(q0, red);
+    q1 = block_sum_d(q1, red);
+    q2 = block_sum_d(q2, red);
+    q3 = block_sum_d(q3, red);
+    q4 = block_sum_d(q4, red);
+    if (threadIdx.x == 0) {
+        double *o = vpart + 5 * (int64_t)blockIdx.x;
+        o[0] = q0;
+        o[1] = q1;
+        o[2] = q2;
+        o[3] = q3;
+        o[4] = q4;
+    }
+}
+
+// Alg. 2 residual check of the iteration just completed.
+__global__ __launch_bounds__(kNT) void k_check_dual(const double *__restrict__ vpart, int nvblk, double rho,
+                                                    double *__restrict__ hist, int hist_cap, Ctl *ctl) {
+    __shared__ double red[kNT / 64];
+    if (ctl->stop) return;
+    const int tid = threadIdx.x;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0;
+    for (int b = tid; b < nvblk; b += kNT) {
+        const double *o = vpart + 5 * (int64_t)b;
+        a0 += o[0];
+        a1 += o[1];
+        a2 += o[2];
+        a3 += o[3];
+        a4 += o[4];
+    }
+    a0 = block_sum_d(a0, red);
+    a1 = block_sum_d(a1, red);
+    a2 = block_sum_d(a2, red);
+    a3 = block_sum_d(a3, red);
+    a4 = block_sum_d(a4, red);
+    if (tid == 0) {
+        const int n = ctl->iter + 1;
+        const double den_p = fmax(sqrt(a1), sqrt(a2));
+        const double eps_p = den_p > 0.0 ? sqrt(a0) / den_p : sqrt(a0);
+        const double den_d = sqrt(a4);
+        const double eps_d = den_d > 0.0 ? rho * sqrt(a3) / den_d : rho * sqrt(a3);
+        ctl->eps_p = eps_p;
+        ctl->eps_d = eps_d;
+        ctl->iter = n;
+        if (n - 1 < hist_cap) {
+            hist[2 * (int64_t)(n - 1) + 0] = eps_p;
+            hist[2 * (int64_t)(n - 1) + 1] = eps_d;
+        }
+        if (fmax(eps_p, eps_d) <= ctl->tol) ctl->stop = 1;
+        else if (n >= ctl->max_iter) ctl->stop = 2;
+    }
+}
+
+__global__ __launch_bounds__(kNT) void k_scale_u(const double *__restrict__ r1, const double *__restrict__ invD,
+                                                 double *__restrict__ u, int64_t nU) {
+    const int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (e < nU) u[e] = r1[e] * invD[e];
+}
+
+// t = A (w u) - r2scale * r2: RG rows of the FP32 matrix Aw (= w A, row-major,
+// leading dimension ld, zero padded to ld) per workgroup, FP64 accumulation.
+template <int RG>
+__global__ __launch_bounds__(kNT) void k_gemv_Au(const float *__restrict__ Aw, int64_t ld,
+                                                 const double *__restrict__ u, const double *__restrict__ r2,
+                                                 double r2scale, double *__restrict__ t, int m, const Ctl *ctl) {
+    __shared__ double red[kNT / 64];
+    if (ctl != nullptr && ctl->stop) return;
+    const int row0 = blockIdx.x * RG;
+    double acc[RG];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) acc[r] = 0.0;
+    const float *base[RG];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) base[r] = Aw + (int64_t)min(row0 + r, m - 1) * ld;
+#pragma unroll 2
+    for (int64_t c = (int64_t)threadIdx.x * 4; c < ld; c += (int64_t)kNT * 4) {
+        const double2 u01 = *reinterpret_cast<const double2 *>(u + c);
+        const double2 u23 = *reinterpret_cast<const double2 *>(u + c + 2);
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+            const float4 av = *reinterpret_cast<const float4 *>(base[r] + c);
+            acc[r] += (double)av.x * u01.x + (double)av.y * u01.y + (double)av.z * u23.x + (double)av.w * u23.y;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+        const double s = block_sum_d(acc[r], red);
+        if (threadIdx.x == 0 && row0 + r < m) t[row0 + r] = s - r2scale * r2[row0 + r];
+    }
+}
+
+// Triangular product out = T vin over the row range [lo, hi) of each row:
+// lower (T = L^-1): [0, i]; upper (T = L^-T): [i, m).  One wave per row.
+__global__ __launch_bounds__(kNT) void k_trmv(const double *__restrict__ T, int m, int upper,
+                                              const double *__restrict__ vin, double *__restrict__ vout,
+                                              const Ctl *ctl) {
+    if (ctl != nullptr && ctl->stop) return;
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * (kNT / 64) + (threadIdx.x >> 6);
+    if (row >= m) return;
+    const int lo = upper ? row : 0, hi = upper ? m : row + 1;
+    const double *tr = T + (int64_t)row * m;
+    double acc = 0.0;
+    for (int j = lo + lane; j < hi; j += 64) acc += tr[j] * vin[j];
+    acc = wave_sum_d(acc);
+    if (lane == 0) vout[row] = acc;
+}
+
+// x = u - s2 * (Aw^T y): one wave per row of AwT (= (w A)^T, row-major, leading
+// dimension ldm, zero padded), y staged in LDS in chunks.
+__global__ __launch_bounds__(kNT) void k_gemv_ATy(const float *__restrict__ AwT, int64_t ldm,
+                                                  const double *__restrict__ y, const double *__restrict__ u,
+                                                  const double *__restrict__ s2, double *__restrict__ x,
+                                                  int64_t nU, int m, const Ctl *ctl) {
+    constexpr int CH = 2048;
+    __shared__ double ys[CH];
+    if (ctl != nullptr && ctl->stop) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t rows_per_block = (nU + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = min(nU, r0 + rows_per_block);
+    for (int64_t rb = r0; rb < r1; rb += kNT / 64) {
+        const int64_t row = rb + w;
+        double acc = 0.0;
+        for (int c0 = 0; c0 < m; c0 += CH) {
+            const int cn = min(CH, m - c0);
+            __syncthreads();
+            for (int i = threadIdx.x; i < CH; i += kNT) ys[i] = (i < cn) ? y[c0 + i] : 0.0;
+            __syncthreads();
+            if (row < r1) {
+                const float *ar = AwT + row * ldm + c0;
+                for (int i = lane * 4; i < cn; i += 256) {
+                    const float4 av = *reinterpret_cast<const float4 *>(ar + i);
+                    acc += (double)av.x * ys[i] + (double)av.y * ys[i + 1] + (double)av.z * ys[i + 2] +
+                           (double)av.w * ys[i + 3];
+                }
+            }
+        }
+        acc = wave_sum_d(acc);
+        if (lane == 0 && row < r1) x[row] = u[row] - s2[row] * acc;
+    }
+}
+
+__global__ __launch_bounds__(kNT) void k_objectives(const double *__restrict__ c, const double *__restrict__ wt,
+                                                    const double *__restrict__ x, int64_t nU,
+                                                    const double *__restrict__ b, const double *__restrict__ y,
+                                                    int m, double *__restrict__ out) {
+    __shared__ double red[kNT / 64];
+    double s1 = 0.0, s2 = 0.0;
+    for (int64_t e = threadIdx.x; e < nU; e += kNT) s1 += wt[e] * c[e] * x[e];
+    for (int i = threadIdx.x; i < m; i += kNT) s2 += b[i] * y[i];
+    s1 = block_sum_d(s1, red);
+    s2 = block_sum_d(s2, red);
+    if (threadIdx.x == 0) {
+        out[0] = s1;
+        out[1] = s2;
+    }
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kNT - 1) / kNT); }
+
+}  // namespace
+
+int scatter_blocks(const Dev &d) { return (int)blocks_for(d.nU); }
+int vupdate_blocks(const Dev &d) { return (int)blocks_for(d.nslots); }
+
+void launch_reset_ctl(const Dev &d, int max_iter, double tol, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(kNT), 0, s, d.ctl, max_iter, tol);
+}
+
+void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s) {
+    hipLaunchKernelGGL(k_scatter_primal, dim3(blocks_for(d.nU)), dim3(kNT), 0, s, d.inv_ptr, d.inv_slot, blk, lam,
+                       d.c, d.invD, d.wt, d.u, d.sx, d.spart, d.nU, rho, (const Ctl *)d.ctl);
+}
+
+void launch_check_primal(const Dev &d, double rho, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_primal, dim3(1), dim3(kNT), 0, s, (const double *)d.cpart, d.p,
+                       (const double *)d.spart, scatter_blocks(d), rho, d.hist, d.hist_cap, d.ctl);
+}
+
+void launch_scatter_dual(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s) {
+    hipLaunchKernelGGL(k_scatter_dual, dim3(blocks_for(d.nU)), dim3(kNT), 0, s, d.inv_ptr, d.inv_slot, blk, lam,
+                       d.c, d.invD, d.u, d.nU, rho, (const Ctl *)d.ctl);
+}
+
+void launch_vupdate(const Dev &d, const double *x, const float *blk, float *lam, float *v, double rho,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_vupdate, dim3(blocks_for(d.nslots)), dim3(kNT), 0, s, d.gather, x, d.wt, blk, lam, v,
+                       d.vpart, d.nslots, rho, (const Ctl *)d.ctl);
+}
+
+void launch_check_dual(const Dev &d, double rho, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_dual, dim3(1), dim3(kNT), 0, s, (const double *)d.vpart, vupdate_blocks(d), rho,
+                       d.hist, d.hist_cap, d.ctl);
+}
+
+void launch_scale_u(const Dev &d, const double *r1, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_u, dim3(blocks_for(d.nU)), dim3(kNT), 0, s, r1, (const double *)d.invD, d.u, d.nU);
+}
+
+// Affine projection from u = r1 / D: t = A (w u) - r2scale r2, y = L^-T L^-1 t,
+// x = u - (A^T y) / D.
+void launch_affine(const Dev &d, const double *r2, double r2scale, double *x, double *y, const Ctl *ctl,
+                   hipStream_t s) {
+    constexpr int RG = 4;
+    hipLaunchKernelGGL((k_gemv_Au<RG>), dim3((d.m + RG - 1) / RG), dim3(kNT), 0, s, (const float *)d.Aw, d.ldU,
+                       (const double *)d.u, r2, r2scale, d.t, d.m, ctl);
+    const unsigned tb = (unsigned)((d.m + kNT / 64 - 1) / (kNT / 64));
+    hipLaunchKernelGGL(k_trmv, dim3(tb), dim3(kNT), 0, s, (const double *)d.Linv, d.m, 0, (const double *)d.t, d.y1,
+                       ctl);
+    hipLaunchKernelGGL(k_trmv, dim3(tb), dim3(kNT), 0, s, (const double *)d.LinvT, d.m, 1, (const double *)d.y1, y,
+                       ctl);
+    const int64_t want = (d.nU + 15) / 16;  // ~16 rows (4 per wave) per workgroup
+    const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 65535));
+    hipLaunchKernelGGL(k_gemv_ATy, dim3(gb), dim3(kNT), 0, s, (const float *)d.AwT, d.ldM, (const double *)y,
+                       (const double *)d.u, (const double *)d.s2, x, d.nU, d.m, ctl);
+}
+
+void launch_objectives(const Dev &d, const double *x, const double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_objectives, dim3(1), dim3(kNT), 0, s, (const double *)d.c, (const double *)d.wt, x, d.nU,
+                       (const double *)d.b, y, d.m, d.obj);
+}
+
+}  // namespace cdcs

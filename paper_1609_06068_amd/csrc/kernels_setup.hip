@@ -1,0 +1,256 @@
+// Setup of the affine projection ("Setup: ... KKT factorization" of
+// Algorithms 1 and 2; Sec. III-B.1: the KKT matrix is constant, so its
+// factorisation is computed once and cached).
+//
+//   M = A diag(w / D) A^T = Aw diag(s2) Aw^T     (Aw = w A, s2 = 1 / (w D)), FP64
+//   M = L L^T                                    (blocked right-looking Cholesky)
+//   L^-1 and L^-T                                (column-wise substitution)
+//
+// The solve y = M^-1 t of each iteration is then two triangular matrix-vector
+// products with the cached inverse factor, which spreads over the whole GPU
+// instead of a length-m chain of dependent substitution steps.
+#include "cdcs_internal.h"
+
+namespace cdcs {
+namespace {
+
+constexpr int TS = 64;   // output tile of the SYRK kernels
+constexpr int KC = 32;   // reduction chunk
+constexpr int NB = 64;   // Cholesky panel width
+
+__device__ __forceinline__ int tri_row_i(int64_t s) {
+    int64_t a = (int64_t)((sqrt(8.0 * (double)s + 1.0) - 1.0) * 0.5);
+    while ((a + 1) * (a + 2) / 2 <= s) ++a;
+    while (a * (a + 1) / 2 > s) --a;
+    return (int)a;
+}
+
+// M[i][j] (i >= j tiles) = sum_e Aw[i][e] * Aw[j][e] * s2[e].
+__global__ __launch_bounds__(256) void k_syrk(const float *__restrict__ Aw, int64_t ld,
+                                              const double *__restrict__ s2, int m, double *__restrict__ M) {
+    __shared__ double As[TS][KC + 1];
+    __shared__ double Bs[TS][KC + 1];
+    const int tb = blockIdx.x;
+    const int I = tri_row_i(tb), J = tb - I * (I + 1) / 2;
+    const int i0 = I * TS, j0 = J * TS;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int64_t e0 = 0; e0 < ld; e0 += KC) {
+        for (int idx = threadIdx.x; idx < TS * KC; idx += 256) {
+            const int r = idx / KC, q = idx - r * KC;
+            const int64_t e = e0 + q;
+            const double sc = s2[e];
+            const int ri = i0 + r, rj = j0 + r;
+            As[r][q] = (ri < m) ? (double)Aw[(int64_t)ri * ld + e] * sc : 0.0;
+            Bs[r][q] = (rj < m) ? (double)Aw[(int64_t)rj * ld + e] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int q = 0; q < KC; ++q) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = As[ty * 4 + a][q];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bv[b] = Bs[tx * 4 + b][q];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = i0 + ty * 4 + a, j = j0 + tx * 4 + b;
+            if (i < m && j < m) M[(int64_t)i * m + j] = acc[a][b];
+        }
+}
+
+__global__ void k_copy_diag(const double *__restrict__ M, int m, double *__restrict__ d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) d[i] = M[(int64_t)i * m + i];
+}
+
+// Unblocked Cholesky of the diagonal block [kb, kb+nb)^2 (lower) in LDS.
+// A pivot <= 2^-40 times the original diagonal flags rank deficiency
+// (info[0] = 1, info[1] = row) and is replaced by 1 to keep the rest finite.
+__global__ __launch_bounds__(256) void k_potrf_diag(double *__restrict__ M, int m, int kb, int nb,
+                                                    const double *__restrict__ diag0, int32_t *info) {
+    __shared__ double L[NB][NB + 1];
+    for (int idx = threadIdx.x; idx < nb * nb; idx += 256) {
+        const int i = idx / nb, j = idx - i * nb;
+        L[i][j] = (j <= i) ? M[(int64_t)(kb + i) * m + kb + j] : 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        if (threadIdx.x == 0) {
+            double piv = L[j][j];
+            if (!(piv > ldexp(diag0[kb + j], -40))) {
+                if (info[0] == 0) {
+                    info[0] = 1;
+                    info[1] = kb + j;
+                }
+                piv = 1.0;
+            }
+            L[j][j] = sqrt(piv);
+        }
+        __syncthreads();
+        const double ljj = L[j][j];
+        for (int i = j + 1 + threadIdx.x; i < nb; i += 256) L[i][j] /= ljj;
+        __syncthreads();
+        // trailing update of the block: L[i][l] -= L[i][j] L[l][j], j < l <= i
+        const int rem = nb - j - 1;
+        for (int idx = threadIdx.x; idx < rem * rem; idx += 256) {
+            const int i = j + 1 + idx / rem, l = j + 1 + idx % rem;
+            if (l <= i) L[i][l] -= L[i][j] * L[l][j];
+        }
+        __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < nb * nb; idx += 256) {
+        const int i = idx / nb, j = idx - i * nb;
+        if (j <= i) M[(int64_t)(kb + i) * m + kb + j] = L[i][j];
+    }
+}
+
+// Panel below the diagonal block: rows r >= kb+nb solve X L11^T = A21.
+// One thread per row; the row lives in LDS.
+__global__ __launch_bounds__(64) void k_trsm_panel(double *__restrict__ M, int m, int kb, int nb) {
+    __shared__ double L[NB][NB + 1];
+    __shared__ double X[64][NB + 1];
+    for (int idx = threadIdx.x; idx < nb * nb; idx += 64) {
+        const int i = idx / nb, j = idx - i * nb;
+        L[i][j] = M[(int64_t)(kb + i) * m + kb + j];
+    }
+    const int r0 = kb + nb + blockIdx.x * 64;
+    for (int idx = threadIdx.x; idx < 64 * nb; idx += 64) {
+        const int rr = idx / nb, j = idx - rr * nb;
+        X[rr][j] = (r0 + rr < m) ? M[(int64_t)(r0 + rr) * m + kb + j] : 0.0;
+    }
+    __syncthreads();
+    const int rr = threadIdx.x;
+    if (r0 + rr < m) {
+        for (int j = 0; j < nb; ++j) {
+            double s = X[rr][j];
+            for (int l = 0; l < j; ++l) s -= X[rr][l] * L[j][l];
+            X[rr][j] = s / L[j][j];
+        }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 64 * nb; idx += 64) {
+        const int q = idx / nb, j = idx - q * nb;
+        if (r0 + q < m) M[(int64_t)(r0 + q) * m + kb + j] = X[q][j];
+    }
+}
+
+// Trailing update M22 -= L21 L21^T on lower tiles of the trailing matrix.
+__global__ __launch_bounds__(256) void k_syrk_update(double *__restrict__ M, int m, int kb, int nb) {
+    __shared__ double As[TS][NB + 1];
+    __shared__ double Bs[TS][NB + 1];
+    const int t0 = kb + nb;
+    const int tb = blockIdx.x;
+    const int I = tri_row_i(tb), J = tb - I * (I + 1) / 2;
+    const int i0 = t0 + I * TS, j0 = t0 + J * TS;
+    for (int idx = threadIdx.x; idx < TS * nb; idx += 256) {
+        const int r = idx / nb, q = idx - r * nb;
+        As[r][q] = (i0 + r < m) ? M[(int64_t)(i0 + r) * m + kb + q] : 0.0;
+        Bs[r][q] = (j0 + r < m) ? M[(int64_t)(j0 + r) * m + kb + q] : 0.0;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int q = 0; q < nb; ++q) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) av[a] = As[ty * 4 + a][q];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bv[b] = Bs[tx * 4 + b][q];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = i0 + ty * 4 + a, j = j0 + tx * 4 + b;
+            if (i < m && j <= i) M[(int64_t)i * m + j] -= acc[a][b];
+        }
+}
+
+// Row j of L^-T (= column j of L^-1): solve L z = e_j, z_i = 0 for i < j.
+// One wave per j; z kept in LDS (dynamic, m doubles).
+__global__ __launch_bounds__(64) void k_trtri_cols(const double *__restrict__ L, int m,
+                                                   double *__restrict__ LinvT) {
+    extern __shared__ double z[];
+    const int j = blockIdx.x;
+    const int lane = threadIdx.x;
+    double *out = LinvT + (int64_t)j * m;
+    for (int i = lane; i < j; i += 64) out[i] = 0.0;
+    for (int i = j; i < m; ++i) {
+        const double *li = L + (int64_t)i * m;
+        double acc = 0.0;
+        for (int l = j + lane; l < i; l += 64) acc += li[l] * z[l];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        const double zi = ((i == j ? 1.0 : 0.0) - acc) / li[i];
+        if (lane == 0) {
+            z[i] = zi;
+            out[i] = zi;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_transpose(const double *__restrict__ in, int m, double *__restrict__ out) {
+    __shared__ double tile[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+        const int i = by + r, j = bx + threadIdx.x;
+        tile[r][threadIdx.x] = (i < m && j < m) ? in[(int64_t)i * m + j] : 0.0;
+    }
+    __syncthreads();
+    for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+        const int i = bx + r, j = by + threadIdx.x;
+        if (i < m && j < m) out[(int64_t)i * m + j] = tile[threadIdx.x][r];
+    }
+}
+
+}  // namespace
+
+void launch_syrk(const float *Aw, int64_t ld, const double *s2, int m, double *M, hipStream_t s) {
+    const int T = (m + TS - 1) / TS;
+    hipLaunchKernelGGL(k_syrk, dim3(T * (T + 1) / 2), dim3(256), 0, s, Aw, ld, s2, m, M);
+}
+
+void launch_potrf(double *M, int m, double *diag0, int32_t *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_diag, dim3((m + 255) / 256), dim3(256), 0, s, (const double *)M, m, diag0);
+    for (int kb = 0; kb < m; kb += NB) {
+        const int nb = std::min(NB, m - kb);
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, M, m, kb, nb, (const double *)diag0, info);
+        const int rem = m - kb - nb;
+        if (rem > 0) {
+            hipLaunchKernelGGL(k_trsm_panel, dim3((rem + 63) / 64), dim3(64), 0, s, M, m, kb, nb);
+            const int T = (rem + TS - 1) / TS;
+            hipLaunchKernelGGL(k_syrk_update, dim3(T * (T + 1) / 2), dim3(256), 0, s, M, m, kb, nb);
+        }
+    }
+}
+
+void launch_trtri(const double *L, int m, double *LinvT, double *Linv, hipStream_t s) {
+    hipLaunchKernelGGL(k_trtri_cols, dim3(m), dim3(64), (size_t)m * sizeof(double), s, L, m, LinvT);
+    hipLaunchKernelGGL(k_transpose, dim3((m + 31) / 32, (m + 31) / 32), dim3(32, 8), 0, s, (const double *)LinvT, m,
+                       Linv);
+}
+
+}  // namespace cdcs

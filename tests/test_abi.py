@@ -1,0 +1,55 @@
+"""Host-side checks of the C-ABI library (CPU only, no device calls)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1609_06068_amd import cdcs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "cdcs.h")).read()
+    return sorted(set(re.findall(r"^(?:cdcs_status|const char \*)\s*(cdcs_\w+)\(", src, flags=re.M)))
+
+
+def test_header_declarations_match_binding_list():
+    assert _declared_symbols() == sorted(cdcs.EXPORTS)
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    if not os.path.exists(cdcs.LIB_PATH):
+        pytest.skip("libcdcs.so not built")
+    lib = ctypes.CDLL(cdcs.LIB_PATH)
+    for name in _declared_symbols():
+        assert hasattr(lib, name), name
+    L = cdcs.load_library()
+    assert L.cdcs_last_error() is not None
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    with pytest.raises(cdcs.CdcsLibraryMissing):
+        cdcs._lib_backup = cdcs._lib
+        try:
+            cdcs._lib = None
+            cdcs.load_library(str(tmp_path / "nope.so"))
+        finally:
+            cdcs._lib = cdcs._lib_backup
+
+
+def test_packing_roundtrip():
+    rng = np.random.default_rng(0)
+    blocks = []
+    for s in [1, 3, 5]:
+        R = rng.standard_normal((s, s))
+        blocks.append(R + R.T)
+    packed = cdcs.pack_blocks(blocks)
+    assert packed.shape[0] == 1 + 6 + 15
+    back = cdcs.unpack_blocks(packed, [1, 3, 5])
+    for a, b in zip(blocks, back):
+        assert np.array_equal(a, b)
+    # slot (a, b) of a block sits at a(a+1)/2 + b
+    assert packed[1 + (2 * 3 // 2 + 1)] == blocks[1][2, 1]
