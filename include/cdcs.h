@@ -116,6 +116,7 @@ typedef struct {
     double obj_primal;    /* <C, X> of the primal iterate */
     double obj_dual;      /* <b, y> of the dual iterate */
     double loop_s;        /* wall time of the iteration loop */
+    int64_t jacobi_sweeps; /* Jacobi sweeps summed over all eigensolves of the solve */
 } cdcs_info;
 
 /* Caller-owned ADMM state (device memory).  Zero-filled state is the
@@ -214,6 +215,25 @@ cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st, const cdcs_opt
  * cdcs_admm_solve with max_iter = 1, tol = 0, check_every = 0. */
 cdcs_status cdcs_admm_step(cdcs_handle *h, const cdcs_state *st, int32_t form, double rho,
                            hipStream_t stream);
+
+/* Kernels of one iteration, for cdcs_profile_kernel. */
+typedef enum {
+    CDCS_K_PROJECT = 0,   /* fused gather + Jacobi projection + epilogue, all size buckets */
+    CDCS_K_GEMV_AU = 1,   /* t = A (w r1 / D) - r2       (affine step, first half) */
+    CDCS_K_TRMV = 2,      /* y = L^-T (L^-1 t)           (two triangular products) */
+    CDCS_K_GEMV_ATY = 3,  /* x = (r1 - A^T y) / D        (affine step, second half) */
+    CDCS_K_SCATTER = 4    /* r1 = sum_k H_k^T (...)      (right-hand side scatter) */
+} cdcs_kernel;
+
+/*
+ * Instrumentation: enqueue `reps` back-to-back launches of one kernel of an
+ * iteration of the given form, with the arguments it has inside
+ * cdcs_admm_solve on this state (the state is updated as by those launches).
+ * Lets a caller bracket one kernel with events on `stream` to time it.
+ * Errors: CDCS_E_ARG (unknown kernel, reps < 1, NULL state buffers).
+ */
+cdcs_status cdcs_profile_kernel(cdcs_handle *h, const cdcs_state *st, int32_t form, double rho,
+                                int32_t kernel, int32_t reps, hipStream_t stream);
 
 /* Residual history of the last solve: n_host pairs (eps_p, eps_d), host. */
 cdcs_status cdcs_residual_history(const cdcs_handle *h, double *hist_host, int32_t n_host);

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcdcs.so")
 
 OK, E_ARG, E_PATTERN, E_RANK, E_DEVICE, E_NOMEM, E_NOT_CONVERGED, E_NUMERIC = range(8)
+K_PROJECT, K_GEMV_AU, K_TRMV, K_GEMV_ATY, K_SCATTER = range(5)
 PRIMAL, DUAL = 0, 1
 MAX_CLIQUE = 96
 STATUS_NAMES = {0: "CDCS_OK", 1: "CDCS_E_ARG", 2: "CDCS_E_PATTERN", 3: "CDCS_E_RANK", 4: "CDCS_E_DEVICE",
@@ -24,7 +25,8 @@ STATUS_NAMES = {0: "CDCS_OK", 1: "CDCS_E_ARG", 2: "CDCS_E_PATTERN", 3: "CDCS_E_R
 
 # Every symbol include/cdcs.h declares.
 EXPORTS = ["cdcs_setup", "cdcs_get_sizes", "cdcs_clique_offsets", "cdcs_psd_project_batched",
-           "cdcs_affine_project", "cdcs_admm_solve", "cdcs_admm_step", "cdcs_residual_history",
+           "cdcs_affine_project", "cdcs_admm_solve", "cdcs_admm_step", "cdcs_profile_kernel",
+           "cdcs_residual_history",
            "cdcs_destroy", "cdcs_last_error"]
 
 
@@ -59,7 +61,8 @@ class _Options(ctypes.Structure):
 class _Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("jacobi_cap_hits", ctypes.c_int32), ("eps_p", ctypes.c_double), ("eps_d", ctypes.c_double),
-                ("obj_primal", ctypes.c_double), ("obj_dual", ctypes.c_double), ("loop_s", ctypes.c_double)]
+                ("obj_primal", ctypes.c_double), ("obj_dual", ctypes.c_double), ("loop_s", ctypes.c_double),
+                ("jacobi_sweeps", ctypes.c_int64)]
 
 
 class _State(ctypes.Structure):
@@ -92,6 +95,7 @@ def load_library(path: str = LIB_PATH):
     L.cdcs_affine_project.argtypes = [vp, vp, vp, vp, vp, vp]
     L.cdcs_admm_solve.argtypes = [vp, P(_State), P(_Options), P(_Info), vp]
     L.cdcs_admm_step.argtypes = [vp, P(_State), i32, dbl, vp]
+    L.cdcs_profile_kernel.argtypes = [vp, P(_State), i32, dbl, i32, i32, vp]
     L.cdcs_residual_history.argtypes = [vp, vp, i32]
     L.cdcs_destroy.argtypes = [vp]
     L.cdcs_last_error.argtypes = []
@@ -140,6 +144,7 @@ class SolveInfo:
     obj_primal: float
     obj_dual: float
     loop_s: float
+    jacobi_sweeps: int
 
 
 class Solver:
@@ -221,13 +226,21 @@ class Solver:
         if st not in (OK, E_NOT_CONVERGED) or (raise_on_cap and st == E_NOT_CONVERGED):
             _check(st, "cdcs_admm_solve")
         return SolveInfo(info.iters, info.status, bool(info.converged), info.jacobi_cap_hits, info.eps_p,
-                         info.eps_d, info.obj_primal, info.obj_dual, info.loop_s)
+                         info.eps_d, info.obj_primal, info.obj_dual, info.loop_s, info.jacobi_sweeps)
 
     def step(self, state: dict, form: str = "primal", rho: float = 1.0, stream=None):
         L = load_library()
         cs = self._cstate(state)
         _check(L.cdcs_admm_step(self._h, ctypes.byref(cs), PRIMAL if form == "primal" else DUAL, float(rho),
                                 _stream(self._torch, stream)), "cdcs_admm_step")
+
+    def profile_kernel(self, state: dict, kernel: int, reps: int = 1, form: str = "primal", rho: float = 1.0,
+                       stream=None):
+        """Enqueue `reps` launches of one kernel of an iteration (for event timing)."""
+        cs = self._cstate(state)
+        _check(load_library().cdcs_profile_kernel(self._h, ctypes.byref(cs), PRIMAL if form == "primal" else DUAL,
+                                                   float(rho), int(kernel), int(reps), _stream(self._torch, stream)),
+               "cdcs_profile_kernel")
 
     def history(self, n: int) -> np.ndarray:
         out = np.zeros((n, 2))
@@ -259,16 +272,23 @@ def psd_project_batched(W, sizes, offsets=None, smax=None, eig: bool = False, st
     (or host array); offsets: int64 cuda tensor of nb+1 packed offsets.
     Returns P (and eigenvalues / eigenvector matrices when eig=True)."""
     torch = _torch()
-    sizes_h = np.asarray(sizes.cpu() if hasattr(sizes, "cpu") else sizes, dtype=np.int64)
-    nb = int(sizes_h.shape[0])
-    if smax is None:
-        smax = int(sizes_h.max()) if nb else 1
-    if nb and (sizes_h.min() < 1 or sizes_h.max() > MAX_CLIQUE):
-        raise CdcsError(E_ARG, "block sizes must lie in 1..96")
     dev = W.device
-    sizes_d = torch.as_tensor(sizes_h.astype(np.int32), device=dev)
-    if offsets is None:
-        offsets = torch.as_tensor(packed_offsets(sizes_h), device=dev)
+    if isinstance(sizes, torch.Tensor) and sizes.is_cuda and not eig:
+        # device-resident sizes/offsets: no host round trip (smax and offsets required)
+        if smax is None or offsets is None:
+            raise CdcsError(E_ARG, "device sizes need smax and device offsets")
+        sizes_d = sizes
+        nb = int(sizes.shape[0])
+    else:
+        sizes_h = np.asarray(sizes.cpu() if hasattr(sizes, "cpu") else sizes, dtype=np.int64)
+        nb = int(sizes_h.shape[0])
+        if smax is None:
+            smax = int(sizes_h.max()) if nb else 1
+        if nb and (sizes_h.min() < 1 or sizes_h.max() > MAX_CLIQUE):
+            raise CdcsError(E_ARG, "block sizes must lie in 1..96")
+        sizes_d = torch.as_tensor(sizes_h.astype(np.int32), device=dev)
+        if offsets is None:
+            offsets = torch.as_tensor(packed_offsets(sizes_h), device=dev)
     W = W.contiguous()
     P = torch.empty_like(W)
     evals = evecs = eoff = voff = None
@@ -287,6 +307,24 @@ def psd_project_batched(W, sizes, offsets=None, smax=None, eig: bool = False, st
     _check(st, "cdcs_psd_project_batched")
     if eig:
         return P, evals, evecs, eoff, voff
+    return P
+
+
+def psd_project_plain(W, sizes_d, offsets_d, smax: int, P=None, stream=None):
+    """The clique-per-launch form: the same projection kernel launched once per
+    block with a one-workgroup grid (no graph).  Baseline for the batched form."""
+    torch = _torch()
+    L = load_library()
+    P = torch.empty_like(W) if P is None else P
+    s = _stream(torch, stream)
+    nb = int(sizes_d.shape[0])
+    sp, op, wp, pp = sizes_d.data_ptr(), offsets_d.data_ptr(), W.data_ptr(), P.data_ptr()
+    fn = L.cdcs_psd_project_batched
+    for t in range(nb):
+        st = fn(1, int(smax), ctypes.c_void_p(sp + 4 * t), ctypes.c_void_p(op + 8 * t), ctypes.c_void_p(wp),
+                ctypes.c_void_p(pp), None, None, None, None, s)
+        if st != OK:
+            _check(st, "cdcs_psd_project_batched")
     return P
 
 

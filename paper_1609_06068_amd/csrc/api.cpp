@@ -35,7 +35,7 @@ cdcs_status fail(cdcs_status st, const std::string &msg) {
 int64_t round_up(int64_t v, int64_t q) { return (v + q - 1) / q * q; }
 
 // Threads per workgroup of the projection kernel for a size bucket.
-int proj_threads(int smax) { return smax <= 32 ? 128 : 256; }
+int proj_threads(int smax) { (void)smax; return 256; }
 
 struct GraphKey {
     int form;
@@ -181,6 +181,10 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
         if (cnt[(size_t)e] == 0) return fail(CDCS_E_PATTERN, "pattern entry " + std::to_string(e) + " lies in no clique");
         inv_ptr[(size_t)e + 1] = inv_ptr[(size_t)e] + cnt[(size_t)e];
     }
+    std::vector<int32_t> heavy;
+    for (int64_t e = 0; e < nU; ++e)
+        if (cnt[(size_t)e] > heavy_threshold()) heavy.push_back((int32_t)e);
+    d.nheavy = (int32_t)heavy.size();
     std::vector<int32_t> inv_slot((size_t)nslots), fillp(inv_ptr.begin(), inv_ptr.end() - 1);
     for (int64_t g = 0; g < nslots; ++g) inv_slot[(size_t)fillp[(size_t)gather[(size_t)g]]++] = (int32_t)g;
 
@@ -225,11 +229,13 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
     std::vector<int32_t> order((size_t)p);
     for (int32_t k = 0; k < p; ++k) order[(size_t)k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t bq) { return size[(size_t)a] > size[(size_t)bq]; });
-    const int bmax[3] = {32, 64, 96};
-    std::vector<std::vector<int32_t>> bl(3);
+    constexpr int NBK = 5;
+    const int bmax[NBK] = {16, 32, 48, 64, 96};
+    std::vector<std::vector<int32_t>> bl(NBK);
     for (int32_t k : order) {
-        const int sk = size[(size_t)k];
-        bl[sk <= 32 ? 0 : (sk <= 64 ? 1 : 2)].push_back(k);
+        const int S = proj_bucket(size[(size_t)k]);
+        for (int q = 0; q < NBK; ++q)
+            if (bmax[q] == S) bl[(size_t)q].push_back(k);
     }
 
     // Upload.
@@ -238,6 +244,7 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
     CK(upload(h, &d.gather, gather, s));
     CK(upload(h, &d.inv_ptr, inv_ptr, s));
     CK(upload(h, &d.inv_slot, inv_slot, s));
+    CK(upload(h, &d.heavy, heavy, s));
     CK(upload(h, &d.invD, invD, s));
     CK(upload(h, &d.s2, s2, s));
     CK(upload(h, &d.wt, wt, s));
@@ -246,7 +253,12 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
     CK(upload(h, &d.Aw, Aw, s));
     CK(upload(h, &d.AwT, AwT, s));
     CK(upload(h, &d.order, order, s));
-    for (int q = 0; q < 3; ++q) {
+    std::vector<int64_t> vwoff((size_t)p + 1, 0);
+    for (int32_t k = 0; k < p; ++k) vwoff[(size_t)k + 1] = vwoff[(size_t)k] + (int64_t)size[(size_t)k] * size[(size_t)k];
+    CK(upload(h, &d.vwoff, vwoff, s));
+    CK(h->alloc(&d.vwarm, vwoff[(size_t)p]));
+    launch_identity_blocks(d.clq_size, d.vwoff, p, d.vwarm, s);
+    for (int q = 0; q < NBK; ++q) {
         if (bl[(size_t)q].empty()) continue;
         Bucket bk{bmax[q], (int)bl[(size_t)q].size(), nullptr};
         CK(upload(h, &bk.ids, bl[(size_t)q], s));
@@ -256,6 +268,7 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
     CK(h->alloc(&d.u, d.ldU));
     HIP_OK(hipMemsetAsync(d.u, 0, (size_t)d.ldU * sizeof(double), s));
     CK(h->alloc(&d.t, d.ldM));
+    CK(h->alloc(&d.tpart, 8 * d.ldM));
     CK(h->alloc(&d.y1, d.ldM));
     CK(h->alloc(&d.sx, 2 * nU));
     HIP_OK(hipMemsetAsync(d.sx, 0, (size_t)(2 * nU) * sizeof(double), s));
@@ -311,6 +324,8 @@ void launch_projection(cdcs_handle *h, int mode, const cdcs_state *st, double rh
         a.lam = st->lam;
         a.v = st->v;
         a.rho = rho;
+        a.vwarm = d.vwarm;
+        a.vwoff = d.vwoff;
         a.cpart = d.cpart;
         a.ctl = d.ctl;
         launch_project(a, bk.smax, proj_threads(bk.smax), s);
@@ -421,7 +436,7 @@ cdcs_status cdcs_psd_project_batched(int32_t nb, int32_t smax, const int32_t *si
     a.eoff = eoff;
     a.evecs = evecs;
     a.voff = voff;
-    const int bucket = smax <= 32 ? 32 : (smax <= 64 ? 64 : 96);
+    const int bucket = proj_bucket(smax);
     launch_project(a, bucket, proj_threads(bucket), stream);
     HIP_OK(hipGetLastError());
     return CDCS_OK;
@@ -462,6 +477,9 @@ cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st, const cdcs_opt
         h->graphs.clear();
     }
     launch_reset_ctl(d, opts->max_iter, opts->tol, stream);
+    // the eigenvector warm start restarts at each solve: a solve is a function
+    // of (problem, state, options) only
+    launch_identity_blocks(d.clq_size, d.vwoff, d.p, d.vwarm, stream);
     HIP_OK(hipGetLastError());
     auto t0 = std::chrono::steady_clock::now();
     const int K = opts->check_every;
@@ -517,6 +535,7 @@ cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st, const cdcs_opt
             info->obj_dual = obj[1];
         }
         info->loop_s = std::chrono::duration<double>(t1 - t0).count();
+        info->jacobi_sweeps = c.sweeps;
     }
     if (status != CDCS_OK)
         g_err = status == CDCS_E_NUMERIC ? "an eigensolve hit its sweep cap" : "iteration cap reached";
@@ -531,6 +550,40 @@ cdcs_status cdcs_admm_step(cdcs_handle *h, const cdcs_state *st, int32_t form, d
     o.form = form;
     o.check_every = 0;
     return cdcs_admm_solve(h, st, &o, nullptr, stream);
+}
+
+cdcs_status cdcs_profile_kernel(cdcs_handle *h, const cdcs_state *st, int32_t form, double rho, int32_t kernel,
+                                int32_t reps, hipStream_t stream) {
+    if (!h || !st || !st->x || !st->y || !st->blk || !st->lam) return fail(CDCS_E_ARG, "NULL argument");
+    if (form != CDCS_PRIMAL && form != CDCS_DUAL) return fail(CDCS_E_ARG, "bad form");
+    if (form == CDCS_DUAL && !st->v) return fail(CDCS_E_ARG, "dual form needs state.v");
+    if (reps < 1 || !(rho > 0.0)) return fail(CDCS_E_ARG, "need reps >= 1, rho > 0");
+    Dev &d = h->d;
+    launch_reset_ctl(d, 1 << 30, 0.0, stream);
+    for (int r = 0; r < reps; ++r) {
+        switch (kernel) {
+        case CDCS_K_PROJECT:
+            launch_projection(h, form == CDCS_PRIMAL ? PROJ_PRIMAL : PROJ_DUAL, st, rho, stream);
+            break;
+        case CDCS_K_GEMV_AU:
+            launch_affine_part(d, 0, d.b, form == CDCS_PRIMAL ? 1.0 : -1.0 / rho, st->x, st->y, d.ctl, stream);
+            break;
+        case CDCS_K_TRMV:
+            launch_affine_part(d, 1, d.b, 1.0, st->x, st->y, d.ctl, stream);
+            break;
+        case CDCS_K_GEMV_ATY:
+            launch_affine_part(d, 2, d.b, 1.0, st->x, st->y, d.ctl, stream);
+            break;
+        case CDCS_K_SCATTER:
+            if (form == CDCS_PRIMAL) launch_scatter_primal(d, st->blk, st->lam, rho, stream);
+            else launch_scatter_dual(d, st->blk, st->lam, rho, stream);
+            break;
+        default:
+            return fail(CDCS_E_ARG, "unknown kernel id");
+        }
+    }
+    HIP_OK(hipGetLastError());
+    return CDCS_OK;
 }
 
 cdcs_status cdcs_residual_history(const cdcs_handle *h, double *hist_host, int32_t n_host) {

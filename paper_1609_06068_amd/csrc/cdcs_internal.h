@@ -21,6 +21,8 @@ struct Ctl {
     int32_t stop;       // 0 running, 1 converged, 2 iteration cap
     int32_t max_iter;
     int32_t jacobi_cap; // eigensolves that hit the sweep cap
+    int32_t sweeps;     // Jacobi sweeps summed over all eigensolves
+    int32_t pad_;
     double tol;
     double eps_p, eps_d;
 };
@@ -52,11 +54,17 @@ struct ProjArgs {
     float *lam;                // [nslots]
     const float *v;            // [nslots]
     double rho;
+    float *vwarm;              // eigenvector warm start (ADMM modes), NULL: cold
+    const int64_t *vwoff;      // [*] offsets of the k x k blocks in vwarm
     double *cpart;             // [p][4] per-block partial sums
     Ctl *ctl;                  // may be NULL (standalone)
 };
 
+// Size bucket (padded clique size) of the projection kernel for cliques <= smax.
+int proj_bucket(int smax);
 void launch_project(const ProjArgs &a, int smax, int nthreads, hipStream_t s);
+// Set every k x k block of V (at voff[k]) to the identity.
+void launch_identity_blocks(const int32_t *size, const int64_t *voff, int p, float *V, hipStream_t s);
 
 // Affine-step, scatter, residual and setup kernels (kernels_affine.hip).
 struct Dev {
@@ -70,6 +78,8 @@ struct Dev {
     int32_t *gather = nullptr;     // [nslots]
     int32_t *inv_ptr = nullptr;    // [nU+1]
     int32_t *inv_slot = nullptr;   // [nslots]
+    int32_t *heavy = nullptr;      // [nheavy] entries with long inverse lists
+    int32_t nheavy = 0;
     double *invD = nullptr;        // [nU]  1 / D_e
     double *s2 = nullptr;          // [nU]  1 / (w_e D_e)
     double *wt = nullptr;          // [nU]  w_e (1 diagonal, 2 off-diagonal)
@@ -80,9 +90,12 @@ struct Dev {
     double *Linv = nullptr;        // [m * m] row-major, L^-1 (lower)
     double *LinvT = nullptr;       // [m * m] row-major, L^-T (upper)
     int32_t *order = nullptr;      // [p] cliques by decreasing size
+    int64_t *vwoff = nullptr;      // [p+1] offsets of k x k blocks (prefix sums of s_k^2)
+    float *vwarm = nullptr;        // [sum s_k^2] eigenvectors of the last projection
     // work
     double *u = nullptr;           // [ldU] r1 / D, zero padded
     double *t = nullptr;           // [m]
+    double *tpart = nullptr;       // [8 * m] split-K partials of A u
     double *y1 = nullptr;          // [m]
     double *sx = nullptr;          // [2 * nU] sum_k H_k^T x_k, two generations
     double *cpart = nullptr;       // [p * 4]
@@ -98,6 +111,7 @@ struct Dev {
 
 // scatter / residual / affine kernels
 int scatter_blocks(const Dev &d);
+int heavy_threshold();
 int vupdate_blocks(const Dev &d);
 void launch_reset_ctl(const Dev &d, int max_iter, double tol, hipStream_t s);
 void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s);
@@ -109,6 +123,9 @@ void launch_check_dual(const Dev &d, double rho, hipStream_t s);
 void launch_scale_u(const Dev &d, const double *r1, hipStream_t s);
 void launch_affine(const Dev &d, const double *r2, double r2scale, double *x, double *y, const Ctl *ctl,
                    hipStream_t s);
+// One part of the affine step: 0 gemv_Au, 1 both triangular products, 2 gemv_ATy.
+void launch_affine_part(const Dev &d, int part, const double *r2, double r2scale, double *x, double *y,
+                        const Ctl *ctl, hipStream_t s);
 void launch_objectives(const Dev &d, const double *x, const double *y, hipStream_t s);
 
 // setup kernels (kernels_setup.hip)

@@ -15,6 +15,8 @@ namespace cdcs {
 namespace {
 
 constexpr int kNT = 256;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kGemvSlices = 8;  // column slices of the split-K A u product
 
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
@@ -41,11 +43,18 @@ __global__ __launch_bounds__(kNT) void k_reset_ctl(Ctl *ctl, int max_iter, doubl
         ctl->stop = 0;
         ctl->max_iter = max_iter;
         ctl->jacobi_cap = 0;
+        ctl->sweeps = 0;
         ctl->tol = tol;
         ctl->eps_p = 0.0;
         ctl->eps_d = 0.0;
     }
 }
+
+// Entries whose inverse list (clique slots covering the entry) is longer than
+// this are summed by a whole wave in extra workgroups of the same launch; the
+// others by one thread each.  Both orders are fixed, so results are bitwise
+// reproducible.
+constexpr int kHeavy = 32;
 
 // Alg. 1 right-hand side r1 = sum_k H_k^T (x_k + lam_k / rho) - c / rho, u = r1 / D,
 // plus the dual-residual terms: S^n = sum_k H_k^T x_k is kept in two generations
@@ -53,7 +62,8 @@ __global__ __launch_bounds__(kNT) void k_reset_ctl(Ctl *ctl, int max_iter, doubl
 // for the same n rewrites the same values), and sum_k H_k^T lam_k.
 __global__ __launch_bounds__(kNT) void k_scatter_primal(const int32_t *__restrict__ inv_ptr,
                                                         const int32_t *__restrict__ inv_slot,
-                                                        const float *__restrict__ blk,
+                                                        const int32_t *__restrict__ heavy, int nheavy,
+                                                        int nlight_blocks, const float *__restrict__ blk,
                                                         const float *__restrict__ lam,
                                                         const double *__restrict__ c,
                                                         const double *__restrict__ invD,
@@ -63,16 +73,40 @@ __global__ __launch_bounds__(kNT) void k_scatter_primal(const int32_t *__restric
     __shared__ double red[kNT / 64];
     if (ctl->stop) return;
     const int n = ctl->iter;
-    const int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    double ds2 = 0.0, sl2 = 0.0;
-    if (e < nU) {
-        double s_x = 0.0, s_l = 0.0;
-        const int32_t q1 = inv_ptr[e + 1];
-        for (int32_t q = inv_ptr[e]; q < q1; ++q) {
-            const int32_t sl = inv_slot[q];
-            s_x += (double)blk[sl];
-            s_l += (double)lam[sl];
+    const int lane = threadIdx.x & 63;
+    int64_t e = -1;
+    double s_x = 0.0, s_l = 0.0;
+    bool owner = false;
+    if ((int)blockIdx.x < nlight_blocks) {
+        e = (int64_t)blockIdx.x * kNT + threadIdx.x;
+        if (e < nU) {
+            const int32_t q0 = inv_ptr[e], q1 = inv_ptr[e + 1];
+            if (q1 - q0 <= kHeavy) {
+                owner = true;
+                for (int32_t q = q0; q < q1; ++q) {
+                    const int32_t sl = inv_slot[q];
+                    s_x += (double)blk[sl];
+                    s_l += (double)lam[sl];
+                }
+            }
         }
+    } else {
+        const int hw = ((int)blockIdx.x - nlight_blocks) * (kNT / 64) + (threadIdx.x >> 6);
+        if (hw < nheavy) {
+            e = heavy[hw];
+            const int32_t q0 = inv_ptr[e], q1 = inv_ptr[e + 1];
+            for (int32_t q = q0 + lane; q < q1; q += 64) {
+                const int32_t sl = inv_slot[q];
+                s_x += (double)blk[sl];
+                s_l += (double)lam[sl];
+            }
+            s_x = wave_sum_d(s_x);
+            s_l = wave_sum_d(s_l);
+            owner = (lane == 0);
+        }
+    }
+    double ds2 = 0.0, sl2 = 0.0;
+    if (owner) {
         const double r1 = s_x + s_l / rho - c[e] / rho;
         u[e] = r1 * invD[e];
         double *cur = sx + (int64_t)(n & 1) * nU;
@@ -145,21 +179,38 @@ __global__ __launch_bounds__(kNT) void k_check_primal(const double *__restrict__
 // Alg. 2 right-hand side r1 = c - sum_k H_k^T (z_k + lam_k / rho), u = r1 / D.
 __global__ __launch_bounds__(kNT) void k_scatter_dual(const int32_t *__restrict__ inv_ptr,
                                                       const int32_t *__restrict__ inv_slot,
-                                                      const float *__restrict__ blk,
+                                                      const int32_t *__restrict__ heavy, int nheavy,
+                                                      int nlight_blocks, const float *__restrict__ blk,
                                                       const float *__restrict__ lam,
                                                       const double *__restrict__ c,
                                                       const double *__restrict__ invD, double *__restrict__ u,
                                                       int64_t nU, double rho, const Ctl *ctl) {
     if (ctl->stop) return;
-    const int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (e >= nU) return;
-    double s = 0.0;
-    const int32_t q1 = inv_ptr[e + 1];
-    for (int32_t q = inv_ptr[e]; q < q1; ++q) {
-        const int32_t sl = inv_slot[q];
-        s += (double)blk[sl] + (double)lam[sl] / rho;
+    const int lane = threadIdx.x & 63;
+    if ((int)blockIdx.x < nlight_blocks) {
+        const int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x;
+        if (e >= nU) return;
+        const int32_t q0 = inv_ptr[e], q1 = inv_ptr[e + 1];
+        if (q1 - q0 > kHeavy) return;
+        double s = 0.0;
+        for (int32_t q = q0; q < q1; ++q) {
+            const int32_t sl = inv_slot[q];
+            s += (double)blk[sl] + (double)lam[sl] / rho;
+        }
+        u[e] = (c[e] - s) * invD[e];
+    } else {
+        const int hw = ((int)blockIdx.x - nlight_blocks) * (kNT / 64) + (threadIdx.x >> 6);
+        if (hw >= nheavy) return;
+        const int32_t e = heavy[hw];
+        const int32_t q0 = inv_ptr[e], q1 = inv_ptr[e + 1];
+        double s = 0.0;
+        for (int32_t q = q0 + lane; q < q1; q += 64) {
+            const int32_t sl = inv_slot[q];
+            s += (double)blk[sl] + (double)lam[sl] / rho;
+        }
+        s = wave_sum_d(s);
+        if (lane == 0) u[e] = (c[e] - s) * invD[e];
     }
-    u[e] = (c[e] - s) * invD[e];
 }
 
 // Alg. 2 epilogue: v_k = z_k + lam_k / rho + H_k x (E:vkEqn),
@@ -247,15 +298,19 @@ __global__ __launch_bounds__(kNT) void k_scale_u(const double *__restrict__ r1, 
     if (e < nU) u[e] = r1[e] * invD[e];
 }
 
-// t = A (w u) - r2scale * r2: RG rows of the FP32 matrix Aw (= w A, row-major,
-// leading dimension ld, zero padded to ld) per workgroup, FP64 accumulation.
+// Split-K partial products of t = A (w u): tpart[slice][row] is the dot
+// product of row `row` of the FP32 matrix Aw (= w A, row-major, leading
+// dimension ld, zero padded) with u over the columns of one slice.  RG rows per
+// workgroup, so each u slice is read once per RG rows; FP64 accumulation.
 template <int RG>
 __global__ __launch_bounds__(kNT) void k_gemv_Au(const float *__restrict__ Aw, int64_t ld,
-                                                 const double *__restrict__ u, const double *__restrict__ r2,
-                                                 double r2scale, double *__restrict__ t, int m, const Ctl *ctl) {
+                                                 const double *__restrict__ u, double *__restrict__ tpart, int m,
+                                                 int64_t slice_cols, const Ctl *ctl) {
     __shared__ double red[kNT / 64];
     if (ctl != nullptr && ctl->stop) return;
     const int row0 = blockIdx.x * RG;
+    const int64_t c0 = (int64_t)blockIdx.y * slice_cols;
+    const int64_t c1 = min(ld, c0 + slice_cols);
     double acc[RG];
 #pragma unroll
     for (int r = 0; r < RG; ++r) acc[r] = 0.0;
@@ -263,20 +318,34 @@ __global__ __launch_bounds__(kNT) void k_gemv_Au(const float *__restrict__ Aw, i
 #pragma unroll
     for (int r = 0; r < RG; ++r) base[r] = Aw + (int64_t)min(row0 + r, m - 1) * ld;
 #pragma unroll 2
-    for (int64_t c = (int64_t)threadIdx.x * 4; c < ld; c += (int64_t)kNT * 4) {
+    for (int64_t c = c0 + (int64_t)threadIdx.x * 4; c < c1; c += (int64_t)kNT * 4) {
         const double2 u01 = *reinterpret_cast<const double2 *>(u + c);
         const double2 u23 = *reinterpret_cast<const double2 *>(u + c + 2);
+        f32x4 av[RG];
 #pragma unroll
-        for (int r = 0; r < RG; ++r) {
-            const float4 av = *reinterpret_cast<const float4 *>(base[r] + c);
-            acc[r] += (double)av.x * u01.x + (double)av.y * u01.y + (double)av.z * u23.x + (double)av.w * u23.y;
-        }
+        for (int r = 0; r < RG; ++r) av[r] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(base[r] + c));
+#pragma unroll
+        for (int r = 0; r < RG; ++r)
+            acc[r] += (double)av[r].x * u01.x + (double)av[r].y * u01.y + (double)av[r].z * u23.x +
+                      (double)av[r].w * u23.y;
     }
 #pragma unroll
     for (int r = 0; r < RG; ++r) {
-        const double s = block_sum_d(acc[r], red);
-        if (threadIdx.x == 0 && row0 + r < m) t[row0 + r] = s - r2scale * r2[row0 + r];
+        const double sum = block_sum_d(acc[r], red);
+        if (threadIdx.x == 0 && row0 + r < m) tpart[(int64_t)blockIdx.y * m + row0 + r] = sum;
     }
+}
+
+// t = sum of the slice partials - r2scale * r2 (fixed slice order).
+__global__ __launch_bounds__(kNT) void k_reduce_t(const double *__restrict__ tpart, int nslice,
+                                                  const double *__restrict__ r2, double r2scale,
+                                                  double *__restrict__ t, int m, const Ctl *ctl) {
+    if (ctl != nullptr && ctl->stop) return;
+    const int i = blockIdx.x * kNT + threadIdx.x;
+    if (i >= m) return;
+    double sum = 0.0;
+    for (int q = 0; q < nslice; ++q) sum += tpart[(int64_t)q * m + i];
+    t[i] = sum - r2scale * r2[i];
 }
 
 // Triangular product out = T vin over the row range [lo, hi) of each row:
@@ -296,8 +365,10 @@ __global__ __launch_bounds__(kNT) void k_trmv(const double *__restrict__ T, int 
     if (lane == 0) vout[row] = acc;
 }
 
-// x = u - s2 * (Aw^T y): one wave per row of AwT (= (w A)^T, row-major, leading
-// dimension ldm, zero padded), y staged in LDS in chunks.
+// x = u - s2 * (Aw^T y): four rows of AwT (= (w A)^T, row-major, leading
+// dimension ldm, zero padded) per wave, 16 per workgroup; y staged in LDS.
+constexpr int kAtyRows = 16;
+
 __global__ __launch_bounds__(kNT) void k_gemv_ATy(const float *__restrict__ AwT, int64_t ldm,
                                                   const double *__restrict__ y, const double *__restrict__ u,
                                                   const double *__restrict__ s2, double *__restrict__ x,
@@ -306,28 +377,32 @@ __global__ __launch_bounds__(kNT) void k_gemv_ATy(const float *__restrict__ AwT,
     __shared__ double ys[CH];
     if (ctl != nullptr && ctl->stop) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t rows_per_block = (nU + gridDim.x - 1) / gridDim.x;
-    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
-    const int64_t r1 = min(nU, r0 + rows_per_block);
-    for (int64_t rb = r0; rb < r1; rb += kNT / 64) {
-        const int64_t row = rb + w;
-        double acc = 0.0;
-        for (int c0 = 0; c0 < m; c0 += CH) {
-            const int cn = min(CH, m - c0);
-            __syncthreads();
-            for (int i = threadIdx.x; i < CH; i += kNT) ys[i] = (i < cn) ? y[c0 + i] : 0.0;
-            __syncthreads();
-            if (row < r1) {
-                const float *ar = AwT + row * ldm + c0;
-                for (int i = lane * 4; i < cn; i += 256) {
-                    const float4 av = *reinterpret_cast<const float4 *>(ar + i);
-                    acc += (double)av.x * ys[i] + (double)av.y * ys[i + 1] + (double)av.z * ys[i + 2] +
-                           (double)av.w * ys[i + 3];
-                }
-            }
+    const int64_t rb = (int64_t)blockIdx.x * kAtyRows + 4 * w;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const float *ar[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ar[q] = AwT + min(rb + q, nU - 1) * ldm;
+    for (int c0 = 0; c0 < m; c0 += CH) {
+        const int cn = min(CH, m - c0);
+        __syncthreads();
+        for (int i = threadIdx.x; i < CH; i += kNT) ys[i] = (i < cn) ? y[c0 + i] : 0.0;
+        __syncthreads();
+        for (int i = lane * 4; i < cn; i += 256) {
+            const double y0 = ys[i], y1 = ys[i + 1], y2 = ys[i + 2], y3 = ys[i + 3];
+            f32x4 av[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                av[q] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(ar[q] + c0 + i));
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                acc[q] += (double)av[q].x * y0 + (double)av[q].y * y1 + (double)av[q].z * y2 + (double)av[q].w * y3;
         }
-        acc = wave_sum_d(acc);
-        if (lane == 0 && row < r1) x[row] = u[row] - s2[row] * acc;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double sum = wave_sum_d(acc[q]);
+        const int64_t row = rb + q;
+        if (lane == 0 && row < nU) x[row] = u[row] - s2[row] * sum;
     }
 }
 
@@ -351,7 +426,9 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kNT - 1) / kNT); 
 
 }  // namespace
 
-int scatter_blocks(const Dev &d) { return (int)blocks_for(d.nU); }
+int scatter_light_blocks(const Dev &d) { return (int)blocks_for(d.nU); }
+int scatter_blocks(const Dev &d) { return scatter_light_blocks(d) + (d.nheavy + kNT / 64 - 1) / (kNT / 64); }
+int heavy_threshold() { return kHeavy; }
 int vupdate_blocks(const Dev &d) { return (int)blocks_for(d.nslots); }
 
 void launch_reset_ctl(const Dev &d, int max_iter, double tol, hipStream_t s) {
@@ -359,8 +436,9 @@ void launch_reset_ctl(const Dev &d, int max_iter, double tol, hipStream_t s) {
 }
 
 void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s) {
-    hipLaunchKernelGGL(k_scatter_primal, dim3(blocks_for(d.nU)), dim3(kNT), 0, s, d.inv_ptr, d.inv_slot, blk, lam,
-                       d.c, d.invD, d.wt, d.u, d.sx, d.spart, d.nU, rho, (const Ctl *)d.ctl);
+    hipLaunchKernelGGL(k_scatter_primal, dim3(scatter_blocks(d)), dim3(kNT), 0, s, d.inv_ptr, d.inv_slot,
+                       (const int32_t *)d.heavy, d.nheavy, scatter_light_blocks(d), blk, lam, d.c, d.invD, d.wt, d.u,
+                       d.sx, d.spart, d.nU, rho, (const Ctl *)d.ctl);
 }
 
 void launch_check_primal(const Dev &d, double rho, hipStream_t s) {
@@ -369,8 +447,9 @@ void launch_check_primal(const Dev &d, double rho, hipStream_t s) {
 }
 
 void launch_scatter_dual(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s) {
-    hipLaunchKernelGGL(k_scatter_dual, dim3(blocks_for(d.nU)), dim3(kNT), 0, s, d.inv_ptr, d.inv_slot, blk, lam,
-                       d.c, d.invD, d.u, d.nU, rho, (const Ctl *)d.ctl);
+    hipLaunchKernelGGL(k_scatter_dual, dim3(scatter_blocks(d)), dim3(kNT), 0, s, d.inv_ptr, d.inv_slot,
+                       (const int32_t *)d.heavy, d.nheavy, scatter_light_blocks(d), blk, lam, d.c, d.invD, d.u, d.nU,
+                       rho, (const Ctl *)d.ctl);
 }
 
 void launch_vupdate(const Dev &d, const double *x, const float *blk, float *lam, float *v, double rho,
@@ -390,20 +469,40 @@ void launch_scale_u(const Dev &d, const double *r1, hipStream_t s) {
 
 // Affine projection from u = r1 / D: t = A (w u) - r2scale r2, y = L^-T L^-1 t,
 // x = u - (A^T y) / D.
+int gemv_slices(const Dev &d) {
+    const int64_t ncb = (d.ldU + 1023) / 1024;
+    return (int)std::min<int64_t>(kGemvSlices, ncb);
+}
+
+void launch_affine_part(const Dev &d, int part, const double *r2, double r2scale, double *x, double *y,
+                        const Ctl *ctl, hipStream_t s) {
+    if (part == 0) {
+        constexpr int RG = 8;
+        const int ns = gemv_slices(d);
+        const int64_t ncb = (d.ldU + 1023) / 1024;
+        const int64_t slice_cols = (ncb + ns - 1) / ns * 1024;
+        hipLaunchKernelGGL((k_gemv_Au<RG>), dim3((d.m + RG - 1) / RG, ns), dim3(kNT), 0, s, (const float *)d.Aw,
+                           d.ldU, (const double *)d.u, d.tpart, d.m, slice_cols, ctl);
+        hipLaunchKernelGGL(k_reduce_t, dim3((d.m + kNT - 1) / kNT), dim3(kNT), 0, s, (const double *)d.tpart, ns,
+                           r2, r2scale, d.t, d.m, ctl);
+    } else if (part == 1) {
+        const unsigned tb = (unsigned)((d.m + kNT / 64 - 1) / (kNT / 64));
+        hipLaunchKernelGGL(k_trmv, dim3(tb), dim3(kNT), 0, s, (const double *)d.Linv, d.m, 0, (const double *)d.t,
+                           d.y1, ctl);
+        hipLaunchKernelGGL(k_trmv, dim3(tb), dim3(kNT), 0, s, (const double *)d.LinvT, d.m, 1, (const double *)d.y1,
+                           y, ctl);
+    } else {
+        const unsigned gb = (unsigned)((d.nU + kAtyRows - 1) / kAtyRows);
+        hipLaunchKernelGGL(k_gemv_ATy, dim3(gb), dim3(kNT), 0, s, (const float *)d.AwT, d.ldM, (const double *)y,
+                           (const double *)d.u, (const double *)d.s2, x, d.nU, d.m, ctl);
+    }
+}
+
 void launch_affine(const Dev &d, const double *r2, double r2scale, double *x, double *y, const Ctl *ctl,
                    hipStream_t s) {
-    constexpr int RG = 4;
-    hipLaunchKernelGGL((k_gemv_Au<RG>), dim3((d.m + RG - 1) / RG), dim3(kNT), 0, s, (const float *)d.Aw, d.ldU,
-                       (const double *)d.u, r2, r2scale, d.t, d.m, ctl);
-    const unsigned tb = (unsigned)((d.m + kNT / 64 - 1) / (kNT / 64));
-    hipLaunchKernelGGL(k_trmv, dim3(tb), dim3(kNT), 0, s, (const double *)d.Linv, d.m, 0, (const double *)d.t, d.y1,
-                       ctl);
-    hipLaunchKernelGGL(k_trmv, dim3(tb), dim3(kNT), 0, s, (const double *)d.LinvT, d.m, 1, (const double *)d.y1, y,
-                       ctl);
-    const int64_t want = (d.nU + 15) / 16;  // ~16 rows (4 per wave) per workgroup
-    const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 65535));
-    hipLaunchKernelGGL(k_gemv_ATy, dim3(gb), dim3(kNT), 0, s, (const float *)d.AwT, d.ldM, (const double *)y,
-                       (const double *)d.u, (const double *)d.s2, x, d.nU, d.m, ctl);
+    launch_affine_part(d, 0, r2, r2scale, x, y, ctl, s);
+    launch_affine_part(d, 1, r2, r2scale, x, y, ctl, s);
+    launch_affine_part(d, 2, r2, r2scale, x, y, ctl, s);
 }
 
 void launch_objectives(const Dev &d, const double *x, const double *y, hipStream_t s) {

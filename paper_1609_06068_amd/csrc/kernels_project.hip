@@ -3,15 +3,26 @@
 // global vector and, for Algorithm 1, the multiplier update (E:LambdakUpdate)
 // and the per-clique residual partial sums.
 //
-// One workgroup per clique.  The clique matrix W (FP32) is staged in LDS and
-// diagonalised by two-sided Jacobi with the round-robin (circle) ordering:
-// in each of the kk-1 steps of a sweep the kk/2 disjoint pairs are rotated
-// together, so the step is one LDS pass with one barrier between computing
-// the rotations and applying them.  The sweep stops when
-//   off(A)^2 <= (2^-23)^2 ||W||_F^2.
-// FP32 accumulation of the eigenvector matrix loses orthogonality like
+// One workgroup per clique.  Every clique of a size bucket is padded to the
+// bucket size S with zero rows and columns (a zero pair never rotates), so all
+// loops have compile-time trip counts.  The clique matrix (FP32) lives in LDS
+// and is diagonalised by two-sided Jacobi with the round-robin (circle)
+// ordering: the S/2 disjoint pairs of a step are rotated together.  A step is
+// two phases separated by barriers: one wave computes the S/2 rotations, then
+// every thread applies them to its fixed share of lower 2x2 blocks of A
+// (writing the transposes alongside) and of row pairs of V.  Pair indices are
+// recomputed arithmetically each step; no index tables are read.  Sweeps stop
+// when off(A)^2 <= (2^-23)^2 ||W||_F^2.
+//
+// Warm start (ADMM modes): W changes little between iterations, so the kernel
+// keeps each clique's eigenvector matrix V_prev and runs Jacobi on
+// V_prev^T W V_prev, accumulating into V_prev.  Any orthogonal start gives the
+// same eigendecomposition of W; a good one needs far fewer sweeps.
+//
+// FP32 accumulation of the eigenvectors loses orthogonality like
 // sqrt(#rotations) eps, so one Newton-Schulz step V <- V - V (V^T V - I) / 2
-// re-orthonormalises it before the rebuild P = V max(Lambda, 0) V^T.
+// re-orthonormalises them before P = V max(Lambda, 0) V^T (register-tiled
+// products on a G x G thread grid).
 #include "cdcs_internal.h"
 
 namespace cdcs {
@@ -69,16 +80,62 @@ __device__ __forceinline__ int tri_row(int s) {
     return a;
 }
 
+// Circle ordering on S indices: position 0 holds index 0, position j >= 1
+// holds 1 + (j - 1 + r) mod (S - 1); pair t joins positions t and S-1-t.
+template <int S>
+__device__ __forceinline__ void pair_at(int t, int r, int &P, int &Q) {
+    constexpr int M = S - 1;
+    int x = t - 1 + r;  // in [-1, 2M)
+    x = (x >= M) ? x - M : x;
+    int y = M - 1 - t + r;  // in [0, 2M)
+    y = (y >= M) ? y - M : y;
+    const int a = (t == 0) ? 0 : 1 + x;
+    const int b = 1 + y;
+    P = min(a, b);
+    Q = max(a, b);
+}
+
+// C[i][j] (+)= sum_q X[q or i][..] ... : register-tiled S x S products.
+// mode 0: C = X^T Y   (C[i][j] = sum_q X[q][i] Y[q][j])
+// mode 1: C = X Y     (C[i][j] = sum_q X[i][q] Y[q][j])
+template <int S, int G, int MODE>
+__device__ __forceinline__ void tile_product(const float *X, const float *Y, float (&acc)[S / G][S / G], int ti,
+                                             int tj) {
+    constexpr int LD = S + 1, T = S / G;
+#pragma unroll
+    for (int u = 0; u < T; ++u)
+#pragma unroll
+        for (int v = 0; v < T; ++v) acc[u][v] = 0.0f;
+    for (int q = 0; q < S; ++q) {
+        float xa[T], yb[T];
+#pragma unroll
+        for (int u = 0; u < T; ++u) xa[u] = MODE == 0 ? X[q * LD + ti * T + u] : X[(ti * T + u) * LD + q];
+#pragma unroll
+        for (int v = 0; v < T; ++v) yb[v] = Y[q * LD + tj * T + v];
+#pragma unroll
+        for (int u = 0; u < T; ++u)
+#pragma unroll
+            for (int v = 0; v < T; ++v) acc[u][v] += xa[u] * yb[v];
+    }
+}
+
 template <int S, int NT>
 __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
-    constexpr int LD = S + 1;  // odd row stride: column walks hit distinct banks
+    static_assert(S % 16 == 0 && S <= 96, "bucket size");
+    static_assert(NT == 64 || NT == 256, "thread grid is 8x8 or 16x16");
+    constexpr int H = S / 2;                 // pairs per step
+    constexpr int LD = S + 1;                // odd row stride
+    constexpr int NSTEP = S - 1;             // steps per sweep
+    constexpr int NBLK = H * (H + 1) / 2;    // lower 2x2 blocks (I >= J)
+    constexpr int NA = (NBLK + NT - 1) / NT; // A blocks per thread
+    constexpr int NV = (S * H + NT - 1) / NT;  // V row pairs per thread
+    constexpr int G = (NT == 64) ? 8 : 16;   // thread grid of the tiled products
+    constexpr int T = S / G;                 // tile edge
     __shared__ float sA[S * LD];
     __shared__ float sV[S * LD];
     __shared__ float sX[S * LD];
-    __shared__ float sLam[S];
-    __shared__ float sLp[S];
-    __shared__ int sP[S / 2], sQ[S / 2];
-    __shared__ float sC[S / 2], sS[S / 2], sT[S / 2];
+    __shared__ float sC[H], sS[H], sT[H];
+    __shared__ float sLam[S], sLp[S];
     __shared__ float redf[NT / 64];
     __shared__ double redd[NT / 64];
 
@@ -88,20 +145,23 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
     const int id = a.ids ? a.ids[bi] : bi;
     const int k = a.size[id];
     if (k < 1 || k > S) return;
-    const int kk = k + (k & 1);  // padded to even with a zero row/column
-    const int np = kk >> 1;
     const int64_t off = a.off[id];
     const int nslot = k * (k + 1) / 2;
     const int tid = threadIdx.x;
+    const bool warm = (a.mode != PROJ_STANDALONE) && (a.vwarm != nullptr);
+    float *vw = warm ? a.vwarm + a.vwoff[id] : nullptr;
+    const int ti = tid / G, tj = tid % G;
 
-    for (int idx = tid; idx < kk * kk; idx += NT) {
-        const int i = idx / kk, j = idx - i * kk;
+    for (int idx = tid; idx < S * S; idx += NT) {
+        const int i = idx / S, j = idx % S;
         sA[i * LD + j] = 0.0f;
-        sV[i * LD + j] = (i == j) ? 1.0f : 0.0f;
+        float v = (i == j) ? 1.0f : 0.0f;
+        if (warm && i < k && j < k) v = vw[i * k + j];
+        sV[i * LD + j] = v;
     }
     __syncthreads();
 
-    // Gather W (packed lower triangle) into the full LDS matrix.
+    // Gather W (packed lower triangle of the k x k block).
     float amax = 0.0f;
     for (int s = tid; s < nslot; s += NT) {
         const int i = tri_row(s), j = s - i * (i + 1) / 2;
@@ -118,7 +178,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
         sA[j * LD + i] = w;
         amax = fmaxf(amax, fabsf(w));
     }
-    // Scale by a power of two (exact) so that max |w| is in [1, 2): squares
+    // Scale by a power of two (exact) so that max |w| lies in [1, 2): squares
     // neither overflow nor underflow for any finite FP32 input.
     amax = block_max<NT>(amax, redf);
     const int ex = (amax > 0.0f && isfinite(amax)) ? ilogbf(amax) : 0;
@@ -134,14 +194,57 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
     const float fro2 = block_sum<NT>(fro, redf);
     const float thr = kEps * kEps * fro2;
 
-    for (int sweep = 0;; ++sweep) {
-        float o = 0.0f;
-        for (int idx = tid; idx < kk * kk; idx += NT) {
-            const int i = idx / kk, j = idx - i * kk;
-            if (i != j) {
-                const float v = sA[i * LD + j];
-                o += v * v;
+    if (warm) {
+        // A <- V^T W V, symmetrised (V = V_prev, orthonormal to FP32 accuracy)
+        float acc[T][T];
+        tile_product<S, G, 1>(sA, sV, acc, ti, tj);  // W V
+#pragma unroll
+        for (int u = 0; u < T; ++u)
+#pragma unroll
+            for (int v = 0; v < T; ++v) sX[(ti * T + u) * LD + tj * T + v] = acc[u][v];
+        __syncthreads();
+        tile_product<S, G, 0>(sV, sX, acc, ti, tj);  // V^T (W V)
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < T; ++u)
+#pragma unroll
+            for (int v = 0; v < T; ++v) sA[(ti * T + u) * LD + tj * T + v] = acc[u][v];
+        __syncthreads();
+        for (int idx = tid; idx < S * S; idx += NT) {
+            const int i = idx / S, j = idx % S;
+            if (i > j) {
+                const float m = 0.5f * (sA[i * LD + j] + sA[j * LD + i]);
+                sA[i * LD + j] = m;
+                sA[j * LD + i] = m;
             }
+        }
+        __syncthreads();
+    }
+
+    // Fixed work assignment for the rotation steps.
+    int aI[NA], aJ[NA], vRow[NV], vJ[NV];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+        const int idx = tid + q * NT;
+        const int I = tri_row(min(idx, NBLK - 1));
+        aI[q] = (idx < NBLK) ? I : -1;
+        aJ[q] = min(idx, NBLK - 1) - I * (I + 1) / 2;
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const int idx = tid + q * NT;
+        vRow[q] = (idx < S * H) ? idx / H : -1;
+        vJ[q] = idx % H;
+    }
+
+    int sweep = 0;
+    for (;; ++sweep) {
+        float o = 0.0f;
+#pragma unroll 4
+        for (int idx = tid; idx < S * S; idx += NT) {
+            const int i = idx / S, j = idx % S;
+            const float v = sA[i * LD + j];
+            o += (i != j) ? v * v : 0.0f;
         }
         const float off2 = block_sum<NT>(o, redf);
         if (off2 <= thr) break;
@@ -149,39 +252,34 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
             if (tid == 0 && a.ctl != nullptr) atomicAdd(&a.ctl->jacobi_cap, 1);
             break;
         }
-        for (int r = 0; r < kk - 1; ++r) {
-            // Circle ordering: position 0 holds index 0, position j >= 1 holds
-            // 1 + (j - 1 + r) mod (kk - 1); pair t joins positions t, kk-1-t.
-            if (tid < np) {
-                int P = (tid == 0) ? 0 : 1 + (tid - 1 + r) % (kk - 1);
-                int Q = 1 + (kk - 2 - tid + r) % (kk - 1);
-                if (P > Q) {
-                    const int tmp = P;
-                    P = Q;
-                    Q = tmp;
-                }
+        for (int r = 0; r < NSTEP; ++r) {
+            if (tid < H) {
+                int P, Q;
+                pair_at<S>(tid, r, P, Q);
                 const float apq = sA[P * LD + Q];
                 float c = 1.0f, s = 0.0f, ta = 0.0f;
-                if (apq != 0.0f) {
+                if (fabsf(apq) > 1e-30f) {  // entries are scaled to max |a| ~ 1
                     const float app = sA[P * LD + P], aqq = sA[Q * LD + Q];
-                    const float tau = (aqq - app) / (2.0f * apq);
-                    const float t = copysignf(1.0f, tau) / (fabsf(tau) + sqrtf(1.0f + tau * tau));
-                    c = 1.0f / sqrtf(1.0f + t * t);
+                    const float tau = 0.5f * (aqq - app) * __builtin_amdgcn_rcpf(apq);
+                    const float t = copysignf(__builtin_amdgcn_rcpf(fabsf(tau) + __builtin_sqrtf(1.0f + tau * tau)),
+                                              tau);
+                    c = __builtin_amdgcn_rsqf(1.0f + t * t);
                     s = t * c;
                     ta = t * apq;
                 }
-                sP[tid] = P;
-                sQ[tid] = Q;
                 sC[tid] = c;
                 sS[tid] = s;
                 sT[tid] = ta;
             }
             __syncthreads();
-            // A <- J^T A J by 2x2 blocks (rows of pair I, columns of pair J);
-            // every element belongs to exactly one block, so this is in place.
-            for (int it = tid; it < np * np; it += NT) {
-                const int I = it / np, J = it - I * np;
-                const int p1 = sP[I], q1 = sQ[I];
+            // A <- J^T A J on this thread's lower 2x2 blocks (rows of pair I,
+            // columns of pair J); the transposed block is written alongside.
+#pragma unroll
+            for (int q = 0; q < NA; ++q) {
+                const int I = aI[q], J = aJ[q];
+                if (I < 0) continue;
+                int p1, q1;
+                pair_at<S>(I, r, p1, q1);
                 if (I == J) {
                     const float ta = sT[I];
                     sA[p1 * LD + p1] -= ta;
@@ -189,22 +287,32 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
                     sA[p1 * LD + q1] = 0.0f;
                     sA[q1 * LD + p1] = 0.0f;
                 } else {
-                    const int p2 = sP[J], q2 = sQ[J];
+                    int p2, q2;
+                    pair_at<S>(J, r, p2, q2);
                     const float c1 = sC[I], s1 = sS[I], c2 = sC[J], s2 = sS[J];
                     const float a00 = sA[p1 * LD + p2], a01 = sA[p1 * LD + q2];
                     const float a10 = sA[q1 * LD + p2], a11 = sA[q1 * LD + q2];
                     const float b00 = c1 * a00 - s1 * a10, b01 = c1 * a01 - s1 * a11;
                     const float b10 = s1 * a00 + c1 * a10, b11 = s1 * a01 + c1 * a11;
-                    sA[p1 * LD + p2] = c2 * b00 - s2 * b01;
-                    sA[p1 * LD + q2] = s2 * b00 + c2 * b01;
-                    sA[q1 * LD + p2] = c2 * b10 - s2 * b11;
-                    sA[q1 * LD + q2] = s2 * b10 + c2 * b11;
+                    const float n00 = c2 * b00 - s2 * b01, n01 = s2 * b00 + c2 * b01;
+                    const float n10 = c2 * b10 - s2 * b11, n11 = s2 * b10 + c2 * b11;
+                    sA[p1 * LD + p2] = n00;
+                    sA[p1 * LD + q2] = n01;
+                    sA[q1 * LD + p2] = n10;
+                    sA[q1 * LD + q2] = n11;
+                    sA[p2 * LD + p1] = n00;
+                    sA[q2 * LD + p1] = n01;
+                    sA[p2 * LD + q1] = n10;
+                    sA[q2 * LD + q1] = n11;
                 }
             }
             // V <- V J
-            for (int it = tid; it < kk * np; it += NT) {
-                const int row = it / np, J = it - row * np;
-                const int p2 = sP[J], q2 = sQ[J];
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                const int row = vRow[q], J = vJ[q];
+                if (row < 0) continue;
+                int p2, q2;
+                pair_at<S>(J, r, p2, q2);
                 const float c2 = sC[J], s2 = sS[J];
                 const float vp = sV[row * LD + p2], vq = sV[row * LD + q2];
                 sV[row * LD + p2] = c2 * vp - s2 * vq;
@@ -213,50 +321,88 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
             __syncthreads();
         }
     }
+    if (tid == 0 && a.ctl != nullptr) atomicAdd(&a.ctl->sweeps, sweep);
 
-    if (tid < kk) {
+    if (tid < S) {
         const float l = sA[tid * LD + tid] * unscale;
         sLam[tid] = l;
         sLp[tid] = fmaxf(l, 0.0f);
     }
-    // E = V^T V - I
-    for (int idx = tid; idx < kk * kk; idx += NT) {
-        const int i = idx / kk, j = idx - i * kk;
-        float acc = 0.0f;
-        for (int r = 0; r < kk; ++r) acc += sV[r * LD + i] * sV[r * LD + j];
-        sX[i * LD + j] = acc - (i == j ? 1.0f : 0.0f);
+    {
+        // E = V^T V - I  -> sX
+        float acc[T][T];
+        tile_product<S, G, 0>(sV, sV, acc, ti, tj);
+#pragma unroll
+        for (int u = 0; u < T; ++u)
+#pragma unroll
+            for (int v = 0; v < T; ++v)
+                sX[(ti * T + u) * LD + tj * T + v] = acc[u][v] - ((ti * T + u) == (tj * T + v) ? 1.0f : 0.0f);
     }
     __syncthreads();
-    // Vn = V - V E / 2, stored over A (only its diagonal was still needed)
-    for (int idx = tid; idx < kk * kk; idx += NT) {
-        const int r = idx / kk, j = idx - r * kk;
-        float acc = 0.0f;
-        for (int i = 0; i < kk; ++i) acc += sV[r * LD + i] * sX[i * LD + j];
-        sA[r * LD + j] = sV[r * LD + j] - 0.5f * acc;
+    {
+        // Vn = V - V E / 2  -> sA
+        float acc[T][T];
+        tile_product<S, G, 1>(sV, sX, acc, ti, tj);
+#pragma unroll
+        for (int u = 0; u < T; ++u)
+#pragma unroll
+            for (int v = 0; v < T; ++v) {
+                const int i = ti * T + u, j = tj * T + v;
+                sA[i * LD + j] = sV[i * LD + j] - 0.5f * acc[u][v];
+            }
+    }
+    __syncthreads();
+    {
+        // P = Vn diag(max(Lambda, 0)) Vn^T  -> sX
+        float acc[T][T];
+#pragma unroll
+        for (int u = 0; u < T; ++u)
+#pragma unroll
+            for (int v = 0; v < T; ++v) acc[u][v] = 0.0f;
+        for (int q = 0; q < S; ++q) {
+            const float lq = sLp[q];
+            float ba[T], bb[T];
+#pragma unroll
+            for (int u = 0; u < T; ++u) ba[u] = sA[(ti * T + u) * LD + q] * lq;
+#pragma unroll
+            for (int v = 0; v < T; ++v) bb[v] = sA[(tj * T + v) * LD + q];
+#pragma unroll
+            for (int u = 0; u < T; ++u)
+#pragma unroll
+                for (int v = 0; v < T; ++v) acc[u][v] += ba[u] * bb[v];
+        }
+#pragma unroll
+        for (int u = 0; u < T; ++u)
+#pragma unroll
+            for (int v = 0; v < T; ++v) sX[(ti * T + u) * LD + tj * T + v] = acc[u][v];
     }
     __syncthreads();
 
-    // Rebuild P = Vn max(Lambda, 0) Vn^T on the packed lower triangle.
+    if (warm)
+        for (int idx = tid; idx < k * k; idx += NT) {
+            const int i = idx / k, j = idx - i * k;
+            vw[idx] = sA[i * LD + j];
+        }
+
     double p0 = 0.0, p1 = 0.0, p2 = 0.0;
     for (int s = tid; s < nslot; s += NT) {
         const int i = tri_row(s), j = s - i * (i + 1) / 2;
-        float acc = 0.0f;
-        for (int t = 0; t < k; ++t) acc += sA[i * LD + t] * sLp[t] * sA[j * LD + t];
+        const float pv32 = sX[i * LD + j];
         const int64_t g = off + s;
         if (a.mode == PROJ_STANDALONE) {
-            a.Pout[g] = acc;
+            a.Pout[g] = pv32;
         } else if (a.mode == PROJ_PRIMAL) {
             const double hx = a.x[a.gather[g]];
-            const double pv = (double)acc;
+            const double pv = (double)pv32;
             a.lam[g] = (float)((double)a.lam[g] + a.rho * (pv - hx));
-            a.blk[g] = acc;
+            a.blk[g] = pv32;
             const double wgt = (i == j) ? 1.0 : 2.0;
             const double d = pv - hx;
             p0 += wgt * d * d;
             p1 += wgt * hx * hx;
             p2 += wgt * pv * pv;
         } else {
-            a.blk[g] = acc;
+            a.blk[g] = pv32;
         }
     }
     if (a.mode == PROJ_PRIMAL) {
@@ -270,6 +416,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
         }
     }
     if (a.mode == PROJ_STANDALONE) {
+        // eigenpairs of the k x k block: Lambda and the re-orthonormalised V
         if (a.evals != nullptr)
             for (int t = tid; t < k; t += NT) a.evals[a.eoff[id] + t] = sLam[t];
         if (a.evecs != nullptr)
@@ -285,21 +432,39 @@ void launch_t(const ProjArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_project<S, NT>), dim3(a.nblk), dim3(NT), 0, s, a);
 }
 
+__global__ void k_identity_blocks(const int32_t *__restrict__ size, const int64_t *__restrict__ voff, int p,
+                                  float *__restrict__ V) {
+    const int id = blockIdx.x;
+    if (id >= p) return;
+    const int k = size[id];
+    for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) V[voff[id] + idx] = (idx / k == idx % k) ? 1.0f : 0.0f;
+}
+
 }  // namespace
+
+int proj_bucket(int smax) {
+    if (smax <= 16) return 16;
+    if (smax <= 32) return 32;
+    if (smax <= 48) return 48;
+    if (smax <= 64) return 64;
+    return 96;
+}
 
 void launch_project(const ProjArgs &a, int smax, int nthreads, hipStream_t s) {
     if (a.nblk <= 0) return;
-    if (smax <= 32) {
-        if (nthreads <= 64) launch_t<32, 64>(a, s);
-        else if (nthreads <= 128) launch_t<32, 128>(a, s);
-        else launch_t<32, 256>(a, s);
-    } else if (smax <= 64) {
-        if (nthreads <= 128) launch_t<64, 128>(a, s);
-        else launch_t<64, 256>(a, s);
-    } else {
-        if (nthreads <= 256) launch_t<96, 256>(a, s);
-        else launch_t<96, 512>(a, s);
+    const int S = proj_bucket(smax);
+    const bool wide = nthreads > 64 || S > 48;
+    switch (S) {
+    case 16: wide ? launch_t<16, 256>(a, s) : launch_t<16, 64>(a, s); break;
+    case 32: wide ? launch_t<32, 256>(a, s) : launch_t<32, 64>(a, s); break;
+    case 48: wide ? launch_t<48, 256>(a, s) : launch_t<48, 64>(a, s); break;
+    case 64: launch_t<64, 256>(a, s); break;
+    default: launch_t<96, 256>(a, s); break;
     }
+}
+
+void launch_identity_blocks(const int32_t *size, const int64_t *voff, int p, float *V, hipStream_t s) {
+    if (p > 0) hipLaunchKernelGGL(k_identity_blocks, dim3(p), dim3(256), 0, s, size, voff, p, V);
 }
 
 }  // namespace cdcs
