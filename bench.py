@@ -81,7 +81,13 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=50, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a 1 GiB elementwise kernel (counter calibration for rocprofv3 --pmc)")
+    ap.add_argument("--print-hash", action="store_true", help="print the kernel source hash and exit")
     args = ap.parse_args()
+    if args.print_hash:
+        print(kernel_source_hash())
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -97,6 +103,13 @@ def main():
     torch.cuda.set_device(0)
     form = args.form
     rho = 1.0
+    if args.copy_probe:
+        xp = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        yp = torch.empty_like(xp)
+        for _ in range(3):
+            torch.mul(xp, 2.0, out=yp)
+        torch.cuda.synchronize()
+        del xp, yp
     _log("generating workload")
     prob = synth.c2()
     t0 = time.perf_counter()
@@ -128,13 +141,20 @@ def main():
     _log(f"timed: {K} iterations in {elapsed:.4f}s -> {ips:.1f} it/s, {sweeps_per_solve:.2f} sweeps/eigensolve")
 
     # Per-kernel average durations with HIP events (same arguments as in the loop).
+    # (The solve's graphs replay after each warmup; profile_kernel graphs read the same state.)
     R = args.kernel_reps
     names = {cdcs.K_GEMV_AU: "gemv_Au", cdcs.K_GEMV_ATY: "gemv_ATy", cdcs.K_TRMV: "trmv",
              cdcs.K_PROJECT: "project", cdcs.K_SCATTER: "scatter"}
     kern_ms = {}
     for kid, name in names.items():
+        # R launches captured in one graph (the solve's launch mode), replayed between events
         sol.profile_kernel(stt, kid, reps=2, form=form, rho=rho)  # warm
-        kern_ms[name] = time_events(torch, lambda: sol.profile_kernel(stt, kid, reps=R, form=form, rho=rho)) / R
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            sol.profile_kernel(stt, kid, reps=R, form=form, rho=rho)
+        g.replay()
+        kern_ms[name] = time_events(torch, g.replay, reps_outer=3) / R
+        del g
     abytes = algorithmic_bytes(sol, prob)
     kern = {n: {"us": kern_ms[n] * 1e3, "GB_s": abytes[n] / (kern_ms[n] * 1e-3) / 1e9} for n in names.values()}
     _log("kernels: " + ", ".join(f"{n} {v['us']:.1f}us {v['GB_s']:.0f}GB/s" for n, v in kern.items()))

@@ -219,7 +219,8 @@ cdcs_status cdcs_admm_step(cdcs_handle *h, const cdcs_state *st, int32_t form, d
 /* Kernels of one iteration, for cdcs_profile_kernel. */
 typedef enum {
     CDCS_K_PROJECT = 0,   /* fused gather + Jacobi projection + epilogue, all size buckets */
-    CDCS_K_GEMV_AU = 1,   /* t = A (w r1 / D) - r2       (affine step, first half) */
+    CDCS_K_GEMV_AU = 1,   /* partials of A (w r1 / D)    (affine step, first half; without the
+                             small reduction to t = A (w r1 / D) - r2 that follows it) */
     CDCS_K_TRMV = 2,      /* y = L^-T (L^-1 t)           (two triangular products) */
     CDCS_K_GEMV_ATY = 3,  /* x = (r1 - A^T y) / D        (affine step, second half) */
     CDCS_K_SCATTER = 4    /* r1 = sum_k H_k^T (...)      (right-hand side scatter) */

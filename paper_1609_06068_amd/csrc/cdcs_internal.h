@@ -123,7 +123,8 @@ void launch_check_dual(const Dev &d, double rho, hipStream_t s);
 void launch_scale_u(const Dev &d, const double *r1, hipStream_t s);
 void launch_affine(const Dev &d, const double *r2, double r2scale, double *x, double *y, const Ctl *ctl,
                    hipStream_t s);
-// One part of the affine step: 0 gemv_Au, 1 both triangular products, 2 gemv_ATy.
+// One part of the affine step: 0 split-K A u partials, 3 their reduction to t,
+// 1 both triangular products, 2 gemv_ATy.
 void launch_affine_part(const Dev &d, int part, const double *r2, double r2scale, double *x, double *y,
                         const Ctl *ctl, hipStream_t s);
 void launch_objectives(const Dev &d, const double *x, const double *y, hipStream_t s);

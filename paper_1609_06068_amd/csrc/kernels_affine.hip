@@ -359,9 +359,16 @@ __global__ __launch_bounds__(kNT) void k_trmv(const double *__restrict__ T, int 
     if (row >= m) return;
     const int lo = upper ? row : 0, hi = upper ? m : row + 1;
     const double *tr = T + (int64_t)row * m;
-    double acc = 0.0;
-    for (int j = lo + lane; j < hi; j += 64) acc += tr[j] * vin[j];
-    acc = wave_sum_d(acc);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int j = lo + lane;
+    for (; j + 192 < hi; j += 256) {
+        a0 += tr[j] * vin[j];
+        a1 += tr[j + 64] * vin[j + 64];
+        a2 += tr[j + 128] * vin[j + 128];
+        a3 += tr[j + 192] * vin[j + 192];
+    }
+    for (; j < hi; j += 64) a0 += tr[j] * vin[j];
+    const double acc = wave_sum_d((a0 + a1) + (a2 + a3));
     if (lane == 0) vout[row] = acc;
 }
 
@@ -483,8 +490,9 @@ void launch_affine_part(const Dev &d, int part, const double *r2, double r2scale
         const int64_t slice_cols = (ncb + ns - 1) / ns * 1024;
         hipLaunchKernelGGL((k_gemv_Au<RG>), dim3((d.m + RG - 1) / RG, ns), dim3(kNT), 0, s, (const float *)d.Aw,
                            d.ldU, (const double *)d.u, d.tpart, d.m, slice_cols, ctl);
-        hipLaunchKernelGGL(k_reduce_t, dim3((d.m + kNT - 1) / kNT), dim3(kNT), 0, s, (const double *)d.tpart, ns,
-                           r2, r2scale, d.t, d.m, ctl);
+    } else if (part == 3) {
+        hipLaunchKernelGGL(k_reduce_t, dim3((d.m + kNT - 1) / kNT), dim3(kNT), 0, s, (const double *)d.tpart,
+                           gemv_slices(d), r2, r2scale, d.t, d.m, ctl);
     } else if (part == 1) {
         const unsigned tb = (unsigned)((d.m + kNT / 64 - 1) / (kNT / 64));
         hipLaunchKernelGGL(k_trmv, dim3(tb), dim3(kNT), 0, s, (const double *)d.Linv, d.m, 0, (const double *)d.t,
@@ -501,6 +509,7 @@ void launch_affine_part(const Dev &d, int part, const double *r2, double r2scale
 void launch_affine(const Dev &d, const double *r2, double r2scale, double *x, double *y, const Ctl *ctl,
                    hipStream_t s) {
     launch_affine_part(d, 0, r2, r2scale, x, y, ctl, s);
+    launch_affine_part(d, 3, r2, r2scale, x, y, ctl, s);
     launch_affine_part(d, 1, r2, r2scale, x, y, ctl, s);
     launch_affine_part(d, 2, r2, r2scale, x, y, ctl, s);
 }
