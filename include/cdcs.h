@@ -185,6 +185,33 @@ cdcs_status cdcs_psd_project_batched(int32_t nb, int32_t smax, const int32_t *si
                                      float *evecs, const int64_t *voff, hipStream_t stream);
 
 /*
+ * Adjoint of the batched projection, for differentiating through
+ * (E:XkUpdate) / (E:zkUpdate): given the eigenpairs written by
+ * cdcs_psd_project_batched (evals, evecs with the same eoff/voff) and the
+ * cotangent gP of P (packed), writes the cotangent gW of W (packed):
+ *   Wbar = V (Gamma o (V^T G V)) V^T   (Daleckii-Krein form),
+ * Gamma_ij = (max(l_i,0) - max(l_j,0)) / (l_i - l_j), 1 if both l > 0, 0 if
+ * both l <= 0 (the derivative of max(., 0) at 0 is taken as 0).  An
+ * off-diagonal packed value stands for both triangles: G holds half of it on
+ * each side and gW adds both triangles of Wbar.  gW may not alias gP.
+ * Errors: CDCS_E_ARG, CDCS_E_DEVICE.
+ */
+cdcs_status cdcs_psd_project_vjp(int32_t nb, int32_t smax, const int32_t *sizes, const int64_t *off,
+                                 const float *evals, const int64_t *eoff, const float *evecs,
+                                 const int64_t *voff, const float *gP, float *gW, hipStream_t stream);
+
+/*
+ * Entry selectors of Sec. III-A in FP64, for building differentiable
+ * iterations: cdcs_gather writes H_k x for every clique into packed slots
+ * (x [nnz] -> packed [nslots]); cdcs_scatter writes sum_k H_k^T applied to
+ * packed clique blocks (packed [nslots] -> out [nnz]; each packed slot adds to
+ * its entry once, so the two are transposes of each other).  Device buffers;
+ * no aliasing.  Errors: CDCS_E_ARG.
+ */
+cdcs_status cdcs_gather(const cdcs_handle *h, const double *x, double *packed, hipStream_t stream);
+cdcs_status cdcs_scatter(const cdcs_handle *h, const double *packed, double *out, hipStream_t stream);
+
+/*
  * Affine projection: solve the KKT system of (E:OptCondMinYPrimal)
  * [D A^T; A 0][x; y] = [r1; r2] by block elimination with the cached factor
  * (the same matrix serves (E:OptCondMinYDual), Sec. IV-B.1):

@@ -432,3 +432,128 @@ class Oracle:
         zblocks = res.lam if res.form == "primal" else res.blocks
         zmin = min(float(np.linalg.eigvalsh(B).min()) for B in zblocks)
         return dict(pinf=pinf, dinf=dinf, gap=gap, pobj=pobj, dobj=dobj, xmin=xmin, zmin=zmin)
+
+
+# --------------------------------------------------------------------------
+# Differentiating unrolled Algorithm 1 (reverse mode, FP64)
+# --------------------------------------------------------------------------
+
+def dk_gamma(lam: np.ndarray) -> np.ndarray:
+    """First divided differences of f(t) = max(t, 0) at the eigenvalues
+    (Daleckii-Krein): Gamma_ij = (f(l_i) - f(l_j)) / (l_i - l_j), with
+    f'(l) = 1 for l > 0 and 0 for l <= 0 on ties (the derivative at 0 is taken
+    as 0)."""
+    li = lam[:, None]
+    lj = lam[None, :]
+    pi = np.maximum(li, 0.0)
+    pj = np.maximum(lj, 0.0)
+    both_pos = (li > 0) & (lj > 0)
+    both_non = (li <= 0) & (lj <= 0)
+    den = li - lj
+    with np.errstate(divide="ignore", invalid="ignore"):
+        mixed = (pi - pj) / den
+    return np.where(both_pos, 1.0, np.where(both_non, 0.0, mixed))
+
+
+def psd_project_vjp(lam: np.ndarray, V: np.ndarray, G: np.ndarray) -> np.ndarray:
+    """Adjoint of the Frechet derivative of P(W) = V max(L, 0) V^T at W (self-
+    adjoint in the Frobenius product): V (Gamma o (V^T G V)) V^T, G symmetric."""
+    B = V.T @ G @ V
+    return V @ (dk_gamma(lam) * B) @ V.T
+
+
+class Unrolled:
+    """K iterations of Algorithm 1 from zero state, x_K as a function of
+    (c, b), with its reverse-mode derivative.
+
+    The forward keeps the state (x_k, lambda_k) before each iteration (the
+    per-iteration checkpoint); the backward recomputes one iteration at a time.
+    Coordinates are plain (unweighted) on the entry vectors and on full clique
+    blocks; a loss L(x_K) supplies dL/dx_K in the same coordinates.
+    """
+
+    def __init__(self, orc: Oracle, K: int, rho: float = 1.0):
+        self.o, self.K, self.rho = orc, K, rho
+
+    def _iteration(self, xk, lam, c, b):
+        o, rho, p = self.o, self.rho, self.o.prob.p
+        r1 = o.dec.scatter([xk[k] + lam[k] / rho for k in range(p)]) - c / rho
+        x, y = o.kkt.solve(r1, b)
+        h = [o.dec.gather(x, k) for k in range(p)]
+        W = [h[k] - lam[k] / rho for k in range(p)]
+        P, evs, Vs = psd_project_batch_eig(W)
+        lam_new = [lam[k] + rho * (P[k] - h[k]) for k in range(p)]
+        return x, P, lam_new, (evs, Vs)
+
+    def forward(self, c, b):
+        p = self.o.prob.p
+        xk = self.o.zero_blocks()
+        lam = self.o.zero_blocks()
+        self.ckpt = []
+        self.min_abs_eig = np.inf
+        x = None
+        for _ in range(self.K):
+            self.ckpt.append((xk, lam))
+            x, xk, lam, (evs, Vs) = self._iteration(xk, lam, c, b)
+            for k in range(p):
+                nrm = np.linalg.norm(np.concatenate([xk[k].ravel(), lam[k].ravel()])) + 1e-300
+                self.min_abs_eig = min(self.min_abs_eig, float(np.abs(evs[k]).min()) / nrm)
+        self.c, self.b = c, b
+        return x
+
+    def _affine_adjoint(self, xbar):
+        """(d x / d r1)^T xbar and (d x / d b)^T xbar via the same KKT solve:
+        x = F(r1, b) gives r1bar = w F(xbar / w, 0) and bbar = y of that solve."""
+        w = self.o.dec.w
+        xo, yo = self.o.kkt.solve(xbar / w, np.zeros(self.o.prob.m))
+        return w * xo, yo
+
+    def backward(self, xbar_K):
+        o, rho, p = self.o, self.rho, self.o.prob.p
+        dec = o.dec
+        cbar = np.zeros(dec.nU)
+        bbar = np.zeros(o.prob.m)
+        xkbar = [np.zeros_like(B) for B in self.ckpt[0][0]]
+        lambar = [np.zeros_like(B) for B in self.ckpt[0][0]]
+        for n in range(self.K - 1, -1, -1):
+            xk_prev, lam_prev = self.ckpt[n]
+            x, P, _, (evs, Vs) = self._iteration(xk_prev, lam_prev, self.c, self.b)
+            # lambda_new = lambda + rho (P - h)
+            Pbar = [xkbar[k] + rho * lambar[k] for k in range(p)]
+            hbar = [-rho * lambar[k] for k in range(p)]
+            lam_prev_bar = [lambar[k].copy() for k in range(p)]
+            # P = proj(W), W = h - lambda / rho
+            for k in range(p):
+                G = 0.5 * (Pbar[k] + Pbar[k].T)
+                Wbar = psd_project_vjp(evs[k], Vs[k], G)
+                hbar[k] = hbar[k] + Wbar
+                lam_prev_bar[k] = lam_prev_bar[k] - Wbar / rho
+            # h = H_k x  (gather); its adjoint adds both triangles of each block
+            xbar = np.zeros(dec.nU)
+            for k in range(p):
+                np.add.at(xbar, dec.idx[k].ravel(), hbar[k].ravel())
+            if n == self.K - 1:
+                xbar = xbar + xbar_K
+            # x = F(r1, b)
+            r1bar, bb = self._affine_adjoint(xbar)
+            bbar += bb
+            cbar += -r1bar / rho
+            # r1 = sum_k H_k^T (x_k + lambda_k / rho) - c / rho (lower triangles)
+            q = [np.zeros_like(B) for B in xk_prev]
+            for k in range(p):
+                ia, ib = dec.tril[k]
+                q[k][ia, ib] = r1bar[dec.idx[k][ia, ib]]
+            xkbar = q
+            lambar = [lam_prev_bar[k] + q[k] / rho for k in range(p)]
+        return cbar, bbar
+
+
+def loss_linear(prob, dec, x):
+    """<C, X> on the pattern (vec inner product) and its gradient in x."""
+    return float(np.sum(dec.w * prob.c * x)), dec.w * prob.c
+
+
+def loss_target(dec, x, xt):
+    """||X - X_target||_F^2 on the pattern and its gradient in x."""
+    d = x - xt
+    return float(np.sum(dec.w * d * d)), 2.0 * dec.w * d

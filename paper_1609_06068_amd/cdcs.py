@@ -25,9 +25,8 @@ STATUS_NAMES = {0: "CDCS_OK", 1: "CDCS_E_ARG", 2: "CDCS_E_PATTERN", 3: "CDCS_E_R
 
 # Every symbol include/cdcs.h declares.
 EXPORTS = ["cdcs_setup", "cdcs_get_sizes", "cdcs_clique_offsets", "cdcs_psd_project_batched",
-           "cdcs_affine_project", "cdcs_admm_solve", "cdcs_admm_step", "cdcs_profile_kernel",
-           "cdcs_residual_history",
-           "cdcs_destroy", "cdcs_last_error"]
+           "cdcs_psd_project_vjp", "cdcs_gather", "cdcs_scatter", "cdcs_affine_project", "cdcs_admm_solve",
+           "cdcs_admm_step", "cdcs_profile_kernel", "cdcs_residual_history", "cdcs_destroy", "cdcs_last_error"]
 
 
 class CdcsLibraryMissing(ImportError):
@@ -92,6 +91,9 @@ def load_library(path: str = LIB_PATH):
     L.cdcs_get_sizes.argtypes = [vp, P(_Sizes)]
     L.cdcs_clique_offsets.argtypes = [vp, vp]
     L.cdcs_psd_project_batched.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.cdcs_psd_project_vjp.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.cdcs_gather.argtypes = [vp, vp, vp, vp]
+    L.cdcs_scatter.argtypes = [vp, vp, vp, vp]
     L.cdcs_affine_project.argtypes = [vp, vp, vp, vp, vp, vp]
     L.cdcs_admm_solve.argtypes = [vp, P(_State), P(_Options), P(_Info), vp]
     L.cdcs_admm_step.argtypes = [vp, P(_State), i32, dbl, vp]
@@ -247,6 +249,23 @@ class Solver:
         _check(load_library().cdcs_residual_history(self._h, _np_ptr(out), int(n)), "cdcs_residual_history")
         return out
 
+    def gather(self, x, stream=None):
+        """H_k x for every clique, packed (FP64)."""
+        torch = self._torch
+        x = x.contiguous()
+        out = torch.empty(self.nslots, dtype=torch.float64, device=x.device)
+        _check(load_library().cdcs_gather(self._h, _ptr(x), _ptr(out), _stream(torch, stream)), "cdcs_gather")
+        return out
+
+    def scatter(self, packed, stream=None):
+        """sum_k H_k^T of packed clique blocks (FP64), on the pattern entries."""
+        torch = self._torch
+        packed = packed.contiguous()
+        out = torch.empty(self.nnz, dtype=torch.float64, device=packed.device)
+        _check(load_library().cdcs_scatter(self._h, _ptr(packed), _ptr(out), _stream(torch, stream)),
+               "cdcs_scatter")
+        return out
+
     def affine_project(self, r1, r2, stream=None):
         torch = self._torch
         x = torch.empty(self.nnz, dtype=torch.float64, device=r1.device)
@@ -308,6 +327,18 @@ def psd_project_batched(W, sizes, offsets=None, smax=None, eig: bool = False, st
     if eig:
         return P, evals, evecs, eoff, voff
     return P
+
+
+def psd_project_vjp(gP, evals, evecs, eoff, voff, sizes_d, offsets_d, smax: int, stream=None):
+    """Cotangent of W from the cotangent of P (Daleckii-Krein), packed FP32."""
+    torch = _torch()
+    gP = gP.contiguous()
+    gW = torch.empty_like(gP)
+    st = load_library().cdcs_psd_project_vjp(int(sizes_d.shape[0]), int(smax), _ptr(sizes_d), _ptr(offsets_d),
+                                             _ptr(evals), _ptr(eoff), _ptr(evecs), _ptr(voff), _ptr(gP),
+                                             _ptr(gW), _stream(torch, stream))
+    _check(st, "cdcs_psd_project_vjp")
+    return gW
 
 
 def psd_project_plain(W, sizes_d, offsets_d, smax: int, P=None, stream=None):

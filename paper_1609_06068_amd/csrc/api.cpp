@@ -442,6 +442,42 @@ cdcs_status cdcs_psd_project_batched(int32_t nb, int32_t smax, const int32_t *si
     return CDCS_OK;
 }
 
+cdcs_status cdcs_psd_project_vjp(int32_t nb, int32_t smax, const int32_t *sizes, const int64_t *off,
+                                 const float *evals, const int64_t *eoff, const float *evecs, const int64_t *voff,
+                                 const float *gP, float *gW, hipStream_t stream) {
+    if (nb <= 0) return CDCS_OK;
+    if (smax < 1 || smax > CDCS_MAX_CLIQUE) return fail(CDCS_E_ARG, "smax outside 1..CDCS_MAX_CLIQUE");
+    if (!sizes || !off || !evals || !eoff || !evecs || !voff || !gP || !gW)
+        return fail(CDCS_E_ARG, "NULL device pointer");
+    VjpArgs a{};
+    a.nblk = nb;
+    a.size = sizes;
+    a.off = off;
+    a.evals = evals;
+    a.eoff = eoff;
+    a.evecs = evecs;
+    a.voff = voff;
+    a.gP = gP;
+    a.gW = gW;
+    launch_project_vjp(a, smax, stream);
+    HIP_OK(hipGetLastError());
+    return CDCS_OK;
+}
+
+cdcs_status cdcs_gather(const cdcs_handle *h, const double *x, double *packed, hipStream_t stream) {
+    if (!h || !x || !packed) return fail(CDCS_E_ARG, "NULL argument");
+    launch_gather_f64(h->d, x, packed, stream);
+    HIP_OK(hipGetLastError());
+    return CDCS_OK;
+}
+
+cdcs_status cdcs_scatter(const cdcs_handle *h, const double *packed, double *out, hipStream_t stream) {
+    if (!h || !packed || !out) return fail(CDCS_E_ARG, "NULL argument");
+    launch_scatter_f64(h->d, packed, out, stream);
+    HIP_OK(hipGetLastError());
+    return CDCS_OK;
+}
+
 cdcs_status cdcs_affine_project(const cdcs_handle *h, const double *r1, const double *r2, double *x, double *y,
                                 hipStream_t stream) {
     if (!h || !r1 || !r2 || !x || !y) return fail(CDCS_E_ARG, "NULL argument");

@@ -63,6 +63,20 @@ struct ProjArgs {
 // Size bucket (padded clique size) of the projection kernel for cliques <= smax.
 int proj_bucket(int smax);
 void launch_project(const ProjArgs &a, int smax, int nthreads, hipStream_t s);
+
+// Arguments of the projection adjoint (Daleckii-Krein) kernel.
+struct VjpArgs {
+    int32_t nblk;
+    const int32_t *size;
+    const int64_t *off;        // packed offsets
+    const float *evals;
+    const int64_t *eoff;
+    const float *evecs;        // k x k row-major, eigenvectors in columns
+    const int64_t *voff;
+    const float *gP;           // packed cotangent of P
+    float *gW;                 // packed cotangent of W
+};
+void launch_project_vjp(const VjpArgs &a, int smax, hipStream_t s);
 // Set every k x k block of V (at voff[k]) to the identity.
 void launch_identity_blocks(const int32_t *size, const int64_t *voff, int p, float *V, hipStream_t s);
 
@@ -127,6 +141,9 @@ void launch_affine(const Dev &d, const double *r2, double r2scale, double *x, do
 // 1 both triangular products, 2 gemv_ATy.
 void launch_affine_part(const Dev &d, int part, const double *r2, double r2scale, double *x, double *y,
                         const Ctl *ctl, hipStream_t s);
+// FP64 gather (entries -> packed slots) and scatter-add (packed -> entries).
+void launch_gather_f64(const Dev &d, const double *x, double *packed, hipStream_t s);
+void launch_scatter_f64(const Dev &d, const double *packed, double *out, hipStream_t s);
 void launch_objectives(const Dev &d, const double *x, const double *y, hipStream_t s);
 
 // setup kernels (kernels_setup.hip)

@@ -292,6 +292,41 @@ __global__ __launch_bounds__(kNT) void k_check_dual(const double *__restrict__ v
     }
 }
 
+// Gather H_k x for every clique into packed slots (FP64).
+__global__ __launch_bounds__(kNT) void k_gather_f64(const int32_t *__restrict__ gather,
+                                                    const double *__restrict__ x, double *__restrict__ out,
+                                                    int64_t nslots) {
+    const int64_t s = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (s < nslots) out[s] = x[gather[s]];
+}
+
+// sum_k H_k^T over packed slots (FP64), owner-computes like the ADMM scatter.
+__global__ __launch_bounds__(kNT) void k_scatter_f64(const int32_t *__restrict__ inv_ptr,
+                                                     const int32_t *__restrict__ inv_slot,
+                                                     const int32_t *__restrict__ heavy, int nheavy,
+                                                     int nlight_blocks, const double *__restrict__ packed,
+                                                     double *__restrict__ out, int64_t nU) {
+    const int lane = threadIdx.x & 63;
+    if ((int)blockIdx.x < nlight_blocks) {
+        const int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x;
+        if (e >= nU) return;
+        const int32_t q0 = inv_ptr[e], q1 = inv_ptr[e + 1];
+        if (q1 - q0 > kHeavy) return;
+        double acc = 0.0;
+        for (int32_t q = q0; q < q1; ++q) acc += packed[inv_slot[q]];
+        out[e] = acc;
+    } else {
+        const int hw = ((int)blockIdx.x - nlight_blocks) * (kNT / 64) + (threadIdx.x >> 6);
+        if (hw >= nheavy) return;
+        const int32_t e = heavy[hw];
+        const int32_t q0 = inv_ptr[e], q1 = inv_ptr[e + 1];
+        double acc = 0.0;
+        for (int32_t q = q0 + lane; q < q1; q += 64) acc += packed[inv_slot[q]];
+        acc = wave_sum_d(acc);
+        if (lane == 0) out[e] = acc;
+    }
+}
+
 __global__ __launch_bounds__(kNT) void k_scale_u(const double *__restrict__ r1, const double *__restrict__ invD,
                                                  double *__restrict__ u, int64_t nU) {
     const int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x;
@@ -512,6 +547,17 @@ void launch_affine(const Dev &d, const double *r2, double r2scale, double *x, do
     launch_affine_part(d, 3, r2, r2scale, x, y, ctl, s);
     launch_affine_part(d, 1, r2, r2scale, x, y, ctl, s);
     launch_affine_part(d, 2, r2, r2scale, x, y, ctl, s);
+}
+
+void launch_gather_f64(const Dev &d, const double *x, double *packed, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_f64, dim3(blocks_for(d.nslots)), dim3(kNT), 0, s, (const int32_t *)d.gather, x, packed,
+                       d.nslots);
+}
+
+void launch_scatter_f64(const Dev &d, const double *packed, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_scatter_f64, dim3(scatter_blocks(d)), dim3(kNT), 0, s, (const int32_t *)d.inv_ptr,
+                       (const int32_t *)d.inv_slot, (const int32_t *)d.heavy, d.nheavy, scatter_light_blocks(d),
+                       packed, out, d.nU);
 }
 
 void launch_objectives(const Dev &d, const double *x, const double *y, hipStream_t s) {

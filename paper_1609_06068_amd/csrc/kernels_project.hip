@@ -95,9 +95,10 @@ __device__ __forceinline__ void pair_at(int t, int r, int &P, int &Q) {
     Q = max(a, b);
 }
 
-// C[i][j] (+)= sum_q X[q or i][..] ... : register-tiled S x S products.
+// Register-tiled S x S products on a G x G thread grid (tile T = S / G):
 // mode 0: C = X^T Y   (C[i][j] = sum_q X[q][i] Y[q][j])
 // mode 1: C = X Y     (C[i][j] = sum_q X[i][q] Y[q][j])
+// mode 2: C = X Y^T   (C[i][j] = sum_q X[i][q] Y[j][q])
 template <int S, int G, int MODE>
 __device__ __forceinline__ void tile_product(const float *X, const float *Y, float (&acc)[S / G][S / G], int ti,
                                              int tj) {
@@ -111,7 +112,7 @@ __device__ __forceinline__ void tile_product(const float *X, const float *Y, flo
 #pragma unroll
         for (int u = 0; u < T; ++u) xa[u] = MODE == 0 ? X[q * LD + ti * T + u] : X[(ti * T + u) * LD + q];
 #pragma unroll
-        for (int v = 0; v < T; ++v) yb[v] = Y[q * LD + tj * T + v];
+        for (int v = 0; v < T; ++v) yb[v] = MODE == 2 ? Y[(tj * T + v) * LD + q] : Y[q * LD + tj * T + v];
 #pragma unroll
         for (int u = 0; u < T; ++u)
 #pragma unroll
@@ -427,6 +428,98 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
     }
 }
 
+// Adjoint of the projection (Daleckii-Krein): for W = V diag(lambda) V^T and a
+// cotangent G of P(W) (symmetric), Wbar = V (Gamma o (V^T G V)) V^T with
+// Gamma_ij the first divided difference of max(., 0) at (lambda_i, lambda_j)
+// (1 if both positive, 0 if both <= 0, else (l_i+ - l_j+) / (l_i - l_j)).
+// Packed coordinates: an off-diagonal packed cotangent stands for both
+// triangles, so G gets half of it on each side and Wbar's two triangles add up.
+template <int S, int NT>
+__global__ __launch_bounds__(NT) void k_project_vjp(VjpArgs a) {
+    static_assert(S % 16 == 0 && S <= 96, "bucket size");
+    constexpr int LD = S + 1;
+    constexpr int G = (NT == 64) ? 8 : 16;
+    constexpr int T = S / G;
+    __shared__ float sA[S * LD];
+    __shared__ float sV[S * LD];
+    __shared__ float sX[S * LD];
+    __shared__ float sLam[S];
+    const int bi = blockIdx.x;
+    if (bi >= a.nblk) return;
+    const int k = a.size[bi];
+    if (k < 1 || k > S) return;
+    const int64_t off = a.off[bi], eo = a.eoff[bi], vo = a.voff[bi];
+    const int nslot = k * (k + 1) / 2;
+    const int tid = threadIdx.x;
+    const int ti = tid / G, tj = tid % G;
+    for (int idx = tid; idx < S * S; idx += NT) {
+        const int i = idx / S, j = idx % S;
+        sA[i * LD + j] = 0.0f;
+        sV[i * LD + j] = (i < k && j < k) ? a.evecs[vo + i * k + j] : (i == j ? 1.0f : 0.0f);
+    }
+    if (tid < S) sLam[tid] = tid < k ? a.evals[eo + tid] : 0.0f;
+    __syncthreads();
+    for (int s = tid; s < nslot; s += NT) {
+        const int i = tri_row(s), j = s - i * (i + 1) / 2;
+        const float g = a.gP[off + s];
+        if (i == j) {
+            sA[i * LD + i] = g;
+        } else {
+            sA[i * LD + j] = 0.5f * g;
+            sA[j * LD + i] = 0.5f * g;
+        }
+    }
+    __syncthreads();
+    float acc[T][T];
+    tile_product<S, G, 1>(sA, sV, acc, ti, tj);  // G V
+#pragma unroll
+    for (int u = 0; u < T; ++u)
+#pragma unroll
+        for (int v = 0; v < T; ++v) sX[(ti * T + u) * LD + tj * T + v] = acc[u][v];
+    __syncthreads();
+    tile_product<S, G, 0>(sV, sX, acc, ti, tj);  // V^T G V
+#pragma unroll
+    for (int u = 0; u < T; ++u)
+#pragma unroll
+        for (int v = 0; v < T; ++v) {
+            const int i = ti * T + u, j = tj * T + v;
+            const float li = sLam[i], lj = sLam[j];
+            float gam;
+            if (li > 0.0f && lj > 0.0f) gam = 1.0f;
+            else if (li <= 0.0f && lj <= 0.0f) gam = 0.0f;
+            else gam = (fmaxf(li, 0.0f) - fmaxf(lj, 0.0f)) / (li - lj);
+            acc[u][v] *= gam;
+        }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < T; ++u)
+#pragma unroll
+        for (int v = 0; v < T; ++v) sA[(ti * T + u) * LD + tj * T + v] = acc[u][v];
+    __syncthreads();
+    tile_product<S, G, 1>(sV, sA, acc, ti, tj);  // V (Gamma o B)
+#pragma unroll
+    for (int u = 0; u < T; ++u)
+#pragma unroll
+        for (int v = 0; v < T; ++v) sX[(ti * T + u) * LD + tj * T + v] = acc[u][v];
+    __syncthreads();
+    tile_product<S, G, 2>(sX, sV, acc, ti, tj);  // (V (Gamma o B)) V^T
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < T; ++u)
+#pragma unroll
+        for (int v = 0; v < T; ++v) sA[(ti * T + u) * LD + tj * T + v] = acc[u][v];
+    __syncthreads();
+    for (int s = tid; s < nslot; s += NT) {
+        const int i = tri_row(s), j = s - i * (i + 1) / 2;
+        a.gW[off + s] = (i == j) ? sA[i * LD + i] : sA[i * LD + j] + sA[j * LD + i];
+    }
+}
+
+template <int S, int NT>
+void launch_vjp_t(const VjpArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_project_vjp<S, NT>), dim3(a.nblk), dim3(NT), 0, s, a);
+}
+
 template <int S, int NT>
 void launch_t(const ProjArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_project<S, NT>), dim3(a.nblk), dim3(NT), 0, s, a);
@@ -460,6 +553,17 @@ void launch_project(const ProjArgs &a, int smax, int nthreads, hipStream_t s) {
     case 48: wide ? launch_t<48, 256>(a, s) : launch_t<48, 64>(a, s); break;
     case 64: launch_t<64, 256>(a, s); break;
     default: launch_t<96, 256>(a, s); break;
+    }
+}
+
+void launch_project_vjp(const VjpArgs &a, int smax, hipStream_t s) {
+    if (a.nblk <= 0) return;
+    switch (proj_bucket(smax)) {
+    case 16: launch_vjp_t<16, 256>(a, s); break;
+    case 32: launch_vjp_t<32, 256>(a, s); break;
+    case 48: launch_vjp_t<48, 256>(a, s); break;
+    case 64: launch_vjp_t<64, 256>(a, s); break;
+    default: launch_vjp_t<96, 256>(a, s); break;
     }
 }
 

@@ -367,3 +367,10 @@ def small_chordal(n: int, p: int, smax: int, m: int, seed: int) -> Problem:
     ei, ej = _pattern_from_cliques(nv, cliques)
     A = _symmetrised_normal(rng, m, ei, ej)
     return _finish(nv, cliques, ei, ej, A, rng, m, meta={"kind": "small_chordal", "seed": seed})
+
+
+def unit_directions(dim: int, count: int, seed: int) -> np.ndarray:
+    """count random unit vectors in R^dim (rows), for directional derivatives."""
+    rng = _rng(seed)
+    D = rng.standard_normal((count, dim))
+    return D / np.linalg.norm(D, axis=1, keepdims=True)
