@@ -157,6 +157,44 @@ cdcs_status cdcs_setup(const cdcs_pattern *pattern, const cdcs_constraints *A,
                        const double *b, const double *c, const cdcs_cliques *cliques,
                        const cdcs_options *opts, hipStream_t stream, cdcs_handle **out);
 
+/* One SDP of a batch (all pointers host, as for cdcs_setup). */
+typedef struct {
+    const cdcs_pattern *pattern;
+    const cdcs_constraints *A;
+    const double *b;
+    const double *c;
+    const cdcs_cliques *cliques;
+} cdcs_problem;
+
+/*
+ * Many independent SDPs in one handle (the batching form of the hot path;
+ * the paper only notes that the per-clique projections are independent and
+ * parallel, Sec. III-B.2).  Instance q's entries, cliques, packed slots and
+ * constraint rows follow instance q-1's, so state buffers are the
+ * concatenations of the per-instance buffers (sizes from cdcs_get_sizes,
+ * packed offsets from cdcs_clique_offsets; instance boundaries are the
+ * prefix sums of the per-instance nnz, slots and m).  One projection launch
+ * covers every instance's cliques; the affine step uses one cached factor per
+ * instance (block-diagonal A).  cdcs_admm_solve (Algorithm 1 only) stops each
+ * instance on its own residuals: once max(eps_p, eps_d) <= tol, that
+ * instance's state is frozen and its time to tolerance is recorded
+ * (cdcs_batch_info).  Each instance needs m <= 256.  Errors as cdcs_setup
+ * (the message names the failing problem).
+ */
+cdcs_status cdcs_setup_batch(int32_t nprob, const cdcs_problem *probs, const cdcs_options *opts,
+                             hipStream_t stream, cdcs_handle **out);
+
+typedef struct {
+    int32_t iters;        /* iterations when the instance stopped */
+    int32_t status;       /* CDCS_OK (converged) or CDCS_E_NOT_CONVERGED */
+    double eps_p, eps_d;  /* residuals at the last check of the instance */
+    double obj_primal, obj_dual;
+    double time_to_tol_s; /* device wall time from solve start to the instance's stop */
+} cdcs_instance_info;
+
+/* Per-instance results of the last solve on a batch handle (host [nprob]). */
+cdcs_status cdcs_batch_info(const cdcs_handle *h, int32_t nprob, cdcs_instance_info *out_host);
+
 cdcs_status cdcs_get_sizes(const cdcs_handle *h, cdcs_sizes *out);
 
 /* Packed-slot offsets off[0..p] (host array of p+1 int64 written). */

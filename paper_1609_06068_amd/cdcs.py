@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "CDCS_OK", 1: "CDCS_E_ARG", 2: "CDCS_E_PATTERN", 3: "CDCS_E_R
                 5: "CDCS_E_NOMEM", 6: "CDCS_E_NOT_CONVERGED", 7: "CDCS_E_NUMERIC"}
 
 # Every symbol include/cdcs.h declares.
-EXPORTS = ["cdcs_setup", "cdcs_get_sizes", "cdcs_clique_offsets", "cdcs_psd_project_batched",
+EXPORTS = ["cdcs_setup", "cdcs_setup_batch", "cdcs_batch_info", "cdcs_get_sizes", "cdcs_clique_offsets", "cdcs_psd_project_batched",
            "cdcs_psd_project_vjp", "cdcs_gather", "cdcs_scatter", "cdcs_affine_project", "cdcs_admm_solve",
            "cdcs_admm_step", "cdcs_profile_kernel", "cdcs_residual_history", "cdcs_destroy", "cdcs_last_error"]
 
@@ -69,6 +69,17 @@ class _State(ctypes.Structure):
                 ("lam", ctypes.c_void_p), ("v", ctypes.c_void_p)]
 
 
+class _Problem(ctypes.Structure):
+    _fields_ = [("pattern", ctypes.POINTER(_Pattern)), ("A", ctypes.POINTER(_Constraints)),
+                ("b", ctypes.c_void_p), ("c", ctypes.c_void_p), ("cliques", ctypes.POINTER(_Cliques))]
+
+
+class _InstanceInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("eps_p", ctypes.c_double),
+                ("eps_d", ctypes.c_double), ("obj_primal", ctypes.c_double), ("obj_dual", ctypes.c_double),
+                ("time_to_tol_s", ctypes.c_double)]
+
+
 class _Sizes(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("p", ctypes.c_int32), ("smax", ctypes.c_int32),
                 ("nnz", ctypes.c_int64), ("nslots", ctypes.c_int64)]
@@ -88,6 +99,8 @@ def load_library(path: str = LIB_PATH):
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     P = ctypes.POINTER
     L.cdcs_setup.argtypes = [P(_Pattern), P(_Constraints), vp, vp, P(_Cliques), vp, vp, P(vp)]
+    L.cdcs_setup_batch.argtypes = [i32, P(_Problem), vp, vp, P(vp)]
+    L.cdcs_batch_info.argtypes = [vp, i32, P(_InstanceInfo)]
     L.cdcs_get_sizes.argtypes = [vp, P(_Sizes)]
     L.cdcs_clique_offsets.argtypes = [vp, vp]
     L.cdcs_psd_project_batched.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -149,36 +162,45 @@ class SolveInfo:
     jacobi_sweeps: int
 
 
+def _marshal(prob):
+    """C structs describing one problem (host arrays kept alive in the tuple)."""
+    ei = np.ascontiguousarray(prob.ei, dtype=np.int32)
+    ej = np.ascontiguousarray(prob.ej, dtype=np.int32)
+    cptr = np.ascontiguousarray(prob.clique_ptr, dtype=np.int64)
+    cvert = np.ascontiguousarray(prob.clique_vert, dtype=np.int32)
+    b = np.ascontiguousarray(prob.b, dtype=np.float64)
+    c = np.ascontiguousarray(prob.c, dtype=np.float64)
+    pat = _Pattern(int(prob.n), int(ei.shape[0]), _np_ptr(ei), _np_ptr(ej))
+    cl = _Cliques(int(cptr.shape[0] - 1), _np_ptr(cptr), _np_ptr(cvert))
+    if prob.A is not None:
+        aval = np.ascontiguousarray(prob.A, dtype=np.float64)
+        cons = _Constraints(int(b.shape[0]), 1, None, None, _np_ptr(aval))
+        keep = (aval,)
+    else:
+        aptr = np.ascontiguousarray(prob.A_ptr, dtype=np.int64)
+        aidx = np.ascontiguousarray(prob.A_idx, dtype=np.int32)
+        aval = np.ascontiguousarray(prob.A_val, dtype=np.float64)
+        cons = _Constraints(int(b.shape[0]), 0, _np_ptr(aptr), _np_ptr(aidx), _np_ptr(aval))
+        keep = (aptr, aidx, aval)
+    return pat, cons, b, c, cl, (ei, ej, cptr, cvert, b, c) + keep
+
+
 class Solver:
     """One SDP set up on the device (cdcs_setup) and its ADMM entry points."""
 
-    def __init__(self, prob):
+    def __init__(self, prob, _handle=None):
         L = load_library()
         torch = _torch()
         self._torch = torch
-        ei = np.ascontiguousarray(prob.ei, dtype=np.int32)
-        ej = np.ascontiguousarray(prob.ej, dtype=np.int32)
-        cptr = np.ascontiguousarray(prob.clique_ptr, dtype=np.int64)
-        cvert = np.ascontiguousarray(prob.clique_vert, dtype=np.int32)
-        b = np.ascontiguousarray(prob.b, dtype=np.float64)
-        c = np.ascontiguousarray(prob.c, dtype=np.float64)
-        pat = _Pattern(int(prob.n), int(ei.shape[0]), _np_ptr(ei), _np_ptr(ej))
-        cl = _Cliques(int(cptr.shape[0] - 1), _np_ptr(cptr), _np_ptr(cvert))
-        if prob.A is not None:
-            aval = np.ascontiguousarray(prob.A, dtype=np.float64)
-            cons = _Constraints(int(b.shape[0]), 1, None, None, _np_ptr(aval))
-            keep = (aval,)
+        if _handle is None:
+            pat, cons, b, c, cl, keep = _marshal(prob)
+            h = ctypes.c_void_p()
+            st = L.cdcs_setup(ctypes.byref(pat), ctypes.byref(cons), _np_ptr(b), _np_ptr(c), ctypes.byref(cl),
+                              None, _stream(torch), ctypes.byref(h))
+            del keep
+            _check(st, "cdcs_setup")
         else:
-            aptr = np.ascontiguousarray(prob.A_ptr, dtype=np.int64)
-            aidx = np.ascontiguousarray(prob.A_idx, dtype=np.int32)
-            aval = np.ascontiguousarray(prob.A_val, dtype=np.float64)
-            cons = _Constraints(int(b.shape[0]), 0, _np_ptr(aptr), _np_ptr(aidx), _np_ptr(aval))
-            keep = (aptr, aidx, aval)
-        h = ctypes.c_void_p()
-        st = L.cdcs_setup(ctypes.byref(pat), ctypes.byref(cons), _np_ptr(b), _np_ptr(c), ctypes.byref(cl),
-                          None, _stream(torch), ctypes.byref(h))
-        del keep
-        _check(st, "cdcs_setup")
+            h = _handle
         self._h = h
         sz = _Sizes()
         _check(L.cdcs_get_sizes(h, ctypes.byref(sz)), "cdcs_get_sizes")
@@ -187,7 +209,9 @@ class Solver:
         off = np.empty(self.p + 1, dtype=np.int64)
         _check(L.cdcs_clique_offsets(h, _np_ptr(off)), "cdcs_clique_offsets")
         self.offsets = off
-        self.sizes = np.diff(np.asarray(prob.clique_ptr, dtype=np.int64))
+        self.sizes = np.diff(off)
+        # packed offsets are prefix sums of s(s+1)/2: recover s
+        self.sizes = ((np.sqrt(8 * self.sizes + 1) - 1) // 2).astype(np.int64)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -275,6 +299,46 @@ class Solver:
         _check(load_library().cdcs_affine_project(self._h, _ptr(r1), _ptr(r2), _ptr(x), _ptr(y),
                                                    _stream(torch, stream)), "cdcs_affine_project")
         return x, y
+
+
+@dataclass
+class InstanceInfo:
+    iters: int
+    status: int
+    eps_p: float
+    eps_d: float
+    obj_primal: float
+    obj_dual: float
+    time_to_tol_s: float
+
+
+class BatchSolver(Solver):
+    """Many independent SDPs in one handle (cdcs_setup_batch): one projection
+    launch over every instance's cliques, one factor per instance, per-instance
+    stopping.  State buffers are the concatenations of the per-instance ones."""
+
+    def __init__(self, probs):
+        L = load_library()
+        torch = _torch()
+        marsh = [_marshal(p) for p in probs]
+        arr = (_Problem * len(probs))()
+        for q, (pat, cons, b, c, cl, keep) in enumerate(marsh):
+            arr[q] = _Problem(ctypes.pointer(pat), ctypes.pointer(cons), _np_ptr(b), _np_ptr(c), ctypes.pointer(cl))
+        h = ctypes.c_void_p()
+        st = L.cdcs_setup_batch(len(probs), arr, None, _stream(torch), ctypes.byref(h))
+        del marsh, arr
+        _check(st, "cdcs_setup_batch")
+        super().__init__(None, _handle=h)
+        self.nprob = len(probs)
+        self.entry_off = np.concatenate([[0], np.cumsum([p.nU for p in probs])]).astype(np.int64)
+        self.row_off = np.concatenate([[0], np.cumsum([p.m for p in probs])]).astype(np.int64)
+        self.clique_off = np.concatenate([[0], np.cumsum([p.p for p in probs])]).astype(np.int64)
+
+    def instance_info(self) -> list:
+        out = (_InstanceInfo * self.nprob)()
+        _check(load_library().cdcs_batch_info(self._h, self.nprob, out), "cdcs_batch_info")
+        return [InstanceInfo(o.iters, o.status, o.eps_p, o.eps_d, o.obj_primal, o.obj_dual, o.time_to_tol_s)
+                for o in out]
 
 
 def packed_offsets(sizes) -> np.ndarray:

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -64,7 +65,9 @@ struct cdcs_handle {
     hipStream_t cap_stream = nullptr;
     std::map<GraphKey, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_defs;
+    std::unique_ptr<Batch> batch_host;
     int last_iters = 0;
+    double last_rho = 1.0;
 
     template <typename T>
     cdcs_status alloc(T **p, int64_t count) {
@@ -104,9 +107,20 @@ cdcs_status upload(cdcs_handle *h, T **dst, const std::vector<T> &src, hipStream
     return CDCS_OK;
 }
 
-cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraints *A, const double *b,
-                  const double *c, const cdcs_cliques *cl, hipStream_t s) {
-    Dev &d = h->d;
+// One SDP validated and decomposed on the host, in its own (local) indices.
+struct HostProblem {
+    int32_t n = 0, m = 0, p = 0, smax = 0;
+    int64_t nU = 0, nslots = 0, ld = 0;
+    std::vector<int32_t> size;       // [p] clique sizes
+    std::vector<int64_t> off;        // [p+1] packed slot offsets
+    std::vector<int32_t> gather;     // [nslots] entry of each packed slot (H_k)
+    std::vector<int32_t> cnt;        // [nU] D_e = number of cliques covering e
+    std::vector<double> wt, invD, s2, c, b;
+    std::vector<float> Aw;           // [m * ld] w-scaled A, row-major, zero padded
+};
+
+cdcs_status host_problem(const cdcs_pattern *pat, const cdcs_constraints *A, const double *b, const double *c,
+                         const cdcs_cliques *cl, int64_t align, HostProblem &P) {
     if (!pat || !A || !b || !c || !cl) return fail(CDCS_E_ARG, "NULL argument");
     if (pat->n < 1 || pat->nnz < 1 || !pat->i || !pat->j) return fail(CDCS_E_ARG, "empty or NULL pattern");
     if (A->m < 1 || !A->val) return fail(CDCS_E_ARG, "no constraints");
@@ -116,13 +130,13 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
     const int32_t m = A->m;
     const int32_t p = cl->p;
     if (nU >= (int64_t)1 << 31) return fail(CDCS_E_ARG, "pattern too large");
-    if (m > 8192) return fail(CDCS_E_ARG, "m > 8192 is not supported by the dense factor");
 
     // Pattern: lower triangular, in range, distinct.
     std::vector<std::pair<int64_t, int32_t>> keys((size_t)nU);
     for (int64_t e = 0; e < nU; ++e) {
         const int32_t i = pat->i[e], j = pat->j[e];
-        if (j < 0 || i < j || i >= n) return fail(CDCS_E_PATTERN, "pattern entry " + std::to_string(e) + " not lower triangular / out of range");
+        if (j < 0 || i < j || i >= n)
+            return fail(CDCS_E_PATTERN, "pattern entry " + std::to_string(e) + " not lower triangular / out of range");
         keys[(size_t)e] = {(int64_t)i * n + j, (int32_t)e};
     }
     std::sort(keys.begin(), keys.end());
@@ -137,77 +151,70 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
 
     // Cliques: E_k with vertices in increasing order (Sec. II-B); gather map H_k.
     if (cl->ptr[0] != 0) return fail(CDCS_E_PATTERN, "clique ptr[0] != 0");
-    d.n = n;
-    d.m = m;
-    d.p = p;
-    d.nU = nU;
-    d.smax = 0;
-    h->off_host.assign((size_t)p + 1, 0);
-    std::vector<int32_t> size((size_t)p);
+    P.n = n;
+    P.m = m;
+    P.p = p;
+    P.nU = nU;
+    P.smax = 0;
+    P.off.assign((size_t)p + 1, 0);
+    P.size.resize((size_t)p);
     for (int32_t k = 0; k < p; ++k) {
         const int64_t a0 = cl->ptr[k], a1 = cl->ptr[k + 1];
         const int64_t sk = a1 - a0;
         if (sk < 1 || sk > CDCS_MAX_CLIQUE)
-            return fail(sk < 1 ? CDCS_E_PATTERN : CDCS_E_ARG, "clique " + std::to_string(k) + " size " + std::to_string(sk) + " outside 1.." + std::to_string(CDCS_MAX_CLIQUE));
+            return fail(sk < 1 ? CDCS_E_PATTERN : CDCS_E_ARG,
+                        "clique " + std::to_string(k) + " size " + std::to_string(sk) + " outside 1.." +
+                            std::to_string(CDCS_MAX_CLIQUE));
         for (int64_t q = a0; q < a1; ++q) {
             const int32_t v = cl->vert[q];
             if (v < 0 || v >= n) return fail(CDCS_E_PATTERN, "clique vertex out of range");
-            if (q > a0 && v <= cl->vert[q - 1]) return fail(CDCS_E_PATTERN, "clique " + std::to_string(k) + " not strictly increasing");
+            if (q > a0 && v <= cl->vert[q - 1])
+                return fail(CDCS_E_PATTERN, "clique " + std::to_string(k) + " not strictly increasing");
         }
-        size[(size_t)k] = (int32_t)sk;
-        d.smax = std::max<int32_t>(d.smax, (int32_t)sk);
-        h->off_host[(size_t)k + 1] = h->off_host[(size_t)k] + sk * (sk + 1) / 2;
+        P.size[(size_t)k] = (int32_t)sk;
+        P.smax = std::max<int32_t>(P.smax, (int32_t)sk);
+        P.off[(size_t)k + 1] = P.off[(size_t)k] + sk * (sk + 1) / 2;
     }
-    const int64_t nslots = h->off_host[(size_t)p];
-    if (nslots >= (int64_t)1 << 31) return fail(CDCS_E_ARG, "too many clique slots");
-    d.nslots = nslots;
-    std::vector<int32_t> gather((size_t)nslots);
-    std::vector<int32_t> cnt((size_t)nU, 0);
+    P.nslots = P.off[(size_t)p];
+    if (P.nslots >= (int64_t)1 << 31) return fail(CDCS_E_ARG, "too many clique slots");
+    P.gather.resize((size_t)P.nslots);
+    P.cnt.assign((size_t)nU, 0);
     for (int32_t k = 0; k < p; ++k) {
         const int32_t *cv = cl->vert + cl->ptr[k];
-        const int sk = size[(size_t)k];
-        int64_t g = h->off_host[(size_t)k];
+        const int sk = P.size[(size_t)k];
+        int64_t g = P.off[(size_t)k];
         for (int a = 0; a < sk; ++a)
             for (int bb = 0; bb <= a; ++bb, ++g) {
                 const int32_t e = find(cv[a], cv[bb]);
                 if (e < 0) return fail(CDCS_E_PATTERN, "clique " + std::to_string(k) + " pair missing from the pattern");
-                gather[(size_t)g] = e;
-                ++cnt[(size_t)e];
+                P.gather[(size_t)g] = e;
+                ++P.cnt[(size_t)e];
             }
     }
-    // D = sum_k H_k^T H_k: overlap count of each entry; inverse map as CSR.
-    std::vector<int32_t> inv_ptr((size_t)nU + 1, 0);
+    // D = sum_k H_k^T H_k: overlap count of each entry (Sec. III-B.1).
+    P.wt.resize((size_t)nU);
+    P.invD.resize((size_t)nU);
+    P.s2.resize((size_t)nU);
+    P.c.assign(c, c + nU);
+    P.b.assign(b, b + m);
     for (int64_t e = 0; e < nU; ++e) {
-        if (cnt[(size_t)e] == 0) return fail(CDCS_E_PATTERN, "pattern entry " + std::to_string(e) + " lies in no clique");
-        inv_ptr[(size_t)e + 1] = inv_ptr[(size_t)e] + cnt[(size_t)e];
-    }
-    std::vector<int32_t> heavy;
-    for (int64_t e = 0; e < nU; ++e)
-        if (cnt[(size_t)e] > heavy_threshold()) heavy.push_back((int32_t)e);
-    d.nheavy = (int32_t)heavy.size();
-    std::vector<int32_t> inv_slot((size_t)nslots), fillp(inv_ptr.begin(), inv_ptr.end() - 1);
-    for (int64_t g = 0; g < nslots; ++g) inv_slot[(size_t)fillp[(size_t)gather[(size_t)g]]++] = (int32_t)g;
-
-    d.ldU = round_up(nU, 64);
-    d.ldM = round_up(m, 4);
-    std::vector<double> invD((size_t)d.ldU, 0.0), s2((size_t)d.ldU, 0.0), wt((size_t)d.ldU, 0.0), cvec((size_t)nU);
-    for (int64_t e = 0; e < nU; ++e) {
+        if (P.cnt[(size_t)e] == 0)
+            return fail(CDCS_E_PATTERN, "pattern entry " + std::to_string(e) + " lies in no clique");
         const double w = (pat->i[e] == pat->j[e]) ? 1.0 : 2.0;
-        const double D = (double)cnt[(size_t)e];
-        wt[(size_t)e] = w;
-        invD[(size_t)e] = 1.0 / D;
-        s2[(size_t)e] = 1.0 / (w * D);
-        cvec[(size_t)e] = c[e];
+        const double D = (double)P.cnt[(size_t)e];
+        P.wt[(size_t)e] = w;
+        P.invD[(size_t)e] = 1.0 / D;
+        P.s2[(size_t)e] = 1.0 / (w * D);
     }
-
-    // Constraint matrix, Aw = w A in FP32, both row-major and transposed.
-    const int64_t dense_elems = (int64_t)m * d.ldU;
+    // Constraint matrix, w A in FP32 (exact for FP32-representable A).
+    P.ld = round_up(nU, align);
+    const int64_t dense_elems = (int64_t)m * P.ld;
     if (dense_elems > ((int64_t)1 << 33)) return fail(CDCS_E_ARG, "dense A too large (sparse A path not built)");
-    std::vector<float> Aw((size_t)dense_elems, 0.0f);
+    P.Aw.assign((size_t)dense_elems, 0.0f);
     if (A->dense) {
         for (int32_t i = 0; i < m; ++i)
             for (int64_t e = 0; e < nU; ++e)
-                Aw[(size_t)(i * d.ldU + e)] = (float)(wt[(size_t)e] * A->val[(size_t)i * nU + e]);
+                P.Aw[(size_t)(i * P.ld + e)] = (float)(P.wt[(size_t)e] * A->val[(size_t)i * nU + e]);
     } else {
         if (!A->ptr || !A->idx) return fail(CDCS_E_ARG, "CSR A without ptr/idx");
         std::vector<double> row((size_t)nU);
@@ -218,17 +225,43 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
                 if (e < 0 || e >= nU) return fail(CDCS_E_PATTERN, "A entry index out of range");
                 row[(size_t)e] += A->val[q];
             }
-            for (int64_t e = 0; e < nU; ++e) Aw[(size_t)(i * d.ldU + e)] = (float)(wt[(size_t)e] * row[(size_t)e]);
+            for (int64_t e = 0; e < nU; ++e) P.Aw[(size_t)(i * P.ld + e)] = (float)(P.wt[(size_t)e] * row[(size_t)e]);
         }
     }
-    std::vector<float> AwT((size_t)(nU * d.ldM), 0.0f);
-    for (int32_t i = 0; i < m; ++i)
-        for (int64_t e = 0; e < nU; ++e) AwT[(size_t)(e * d.ldM + i)] = Aw[(size_t)(i * d.ldU + e)];
+    return CDCS_OK;
+}
 
+// Inverse of the gather map as CSR (entry -> its slots, in slot order), and
+// the entries whose lists are long enough to be summed by a whole wave.
+void inverse_map(const std::vector<int32_t> &gather, const std::vector<int32_t> &cnt, int heavy_above,
+                 std::vector<int32_t> &inv_ptr, std::vector<int32_t> &inv_slot, std::vector<int32_t> &heavy) {
+    const int64_t nU = (int64_t)cnt.size();
+    inv_ptr.assign((size_t)nU + 1, 0);
+    for (int64_t e = 0; e < nU; ++e) inv_ptr[(size_t)e + 1] = inv_ptr[(size_t)e] + cnt[(size_t)e];
+    heavy.clear();
+    for (int64_t e = 0; e < nU; ++e)
+        if (cnt[(size_t)e] > heavy_above) heavy.push_back((int32_t)e);
+    inv_slot.resize(gather.size());
+    std::vector<int32_t> fillp(inv_ptr.begin(), inv_ptr.end() - 1);
+    for (size_t g = 0; g < gather.size(); ++g) inv_slot[(size_t)fillp[(size_t)gather[g]]++] = (int32_t)g;
+}
+
+// Common device state: maps, per-entry scalars, buckets, work buffers.
+cdcs_status upload_common(cdcs_handle *h, const std::vector<int32_t> &size, const std::vector<int32_t> &gather,
+                          const std::vector<int32_t> &cnt, const std::vector<double> &wt,
+                          const std::vector<double> &invD, const std::vector<double> &s2,
+                          const std::vector<double> &c, const std::vector<double> &b, int heavy_above,
+                          hipStream_t s) {
+    Dev &d = h->d;
+    const int32_t p = d.p;
+    std::vector<int32_t> inv_ptr, inv_slot, heavy;
+    inverse_map(gather, cnt, heavy_above, inv_ptr, inv_slot, heavy);
+    d.nheavy = (int32_t)heavy.size();
     // Cliques by decreasing size, split into LDS size buckets.
     std::vector<int32_t> order((size_t)p);
     for (int32_t k = 0; k < p; ++k) order[(size_t)k] = k;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t bq) { return size[(size_t)a] > size[(size_t)bq]; });
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t bq) { return size[(size_t)a] > size[(size_t)bq]; });
     constexpr int NBK = 5;
     const int bmax[NBK] = {16, 32, 48, 64, 96};
     std::vector<std::vector<int32_t>> bl(NBK);
@@ -237,8 +270,6 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
         for (int q = 0; q < NBK; ++q)
             if (bmax[q] == S) bl[(size_t)q].push_back(k);
     }
-
-    // Upload.
     CK(upload(h, &d.clq_size, size, s));
     CK(upload(h, &d.clq_off, h->off_host, s));
     CK(upload(h, &d.gather, gather, s));
@@ -248,13 +279,12 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
     CK(upload(h, &d.invD, invD, s));
     CK(upload(h, &d.s2, s2, s));
     CK(upload(h, &d.wt, wt, s));
-    CK(upload(h, &d.c, cvec, s));
-    CK(upload(h, &d.b, std::vector<double>(b, b + m), s));
-    CK(upload(h, &d.Aw, Aw, s));
-    CK(upload(h, &d.AwT, AwT, s));
+    CK(upload(h, &d.c, c, s));
+    CK(upload(h, &d.b, b, s));
     CK(upload(h, &d.order, order, s));
     std::vector<int64_t> vwoff((size_t)p + 1, 0);
-    for (int32_t k = 0; k < p; ++k) vwoff[(size_t)k + 1] = vwoff[(size_t)k] + (int64_t)size[(size_t)k] * size[(size_t)k];
+    for (int32_t k = 0; k < p; ++k)
+        vwoff[(size_t)k + 1] = vwoff[(size_t)k] + (int64_t)size[(size_t)k] * size[(size_t)k];
     CK(upload(h, &d.vwoff, vwoff, s));
     CK(h->alloc(&d.vwarm, vwoff[(size_t)p]));
     launch_identity_blocks(d.clq_size, d.vwoff, p, d.vwarm, s);
@@ -264,17 +294,13 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
         CK(upload(h, &bk.ids, bl[(size_t)q], s));
         h->buckets.push_back(bk);
     }
-    // Work buffers (zeroed: padding of u and the first generation of sx matter).
-    CK(h->alloc(&d.u, d.ldU));
-    HIP_OK(hipMemsetAsync(d.u, 0, (size_t)d.ldU * sizeof(double), s));
     CK(h->alloc(&d.t, d.ldM));
     CK(h->alloc(&d.tpart, 8 * d.ldM));
     CK(h->alloc(&d.y1, d.ldM));
-    CK(h->alloc(&d.sx, 2 * nU));
-    HIP_OK(hipMemsetAsync(d.sx, 0, (size_t)(2 * nU) * sizeof(double), s));
+    CK(h->alloc(&d.sx, 2 * d.nU));
+    HIP_OK(hipMemsetAsync(d.sx, 0, (size_t)(2 * d.nU) * sizeof(double), s));
     CK(h->alloc(&d.cpart, 4 * (int64_t)p));
     HIP_OK(hipMemsetAsync(d.cpart, 0, (size_t)(4 * p) * sizeof(double), s));
-    CK(h->alloc(&d.spart, 2 * (int64_t)scatter_blocks(d)));
     CK(h->alloc(&d.vpart, 5 * (int64_t)vupdate_blocks(d)));
     CK(h->alloc(&d.obj, 2));
     CK(h->alloc(&d.info, 4));
@@ -282,6 +308,40 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
     CK(h->alloc(&d.ctl, 1));
     HIP_OK(hipHostMalloc((void **)&d.ctl_host, sizeof(Ctl), hipHostMallocDefault));
     d.hist_cap = 0;
+    return CDCS_OK;
+}
+
+cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraints *A, const double *b,
+                  const double *c, const cdcs_cliques *cl, hipStream_t s) {
+    Dev &d = h->d;
+    HostProblem P;
+    CK(host_problem(pat, A, b, c, cl, 64, P));
+    if (P.m > 8192) return fail(CDCS_E_ARG, "m > 8192 is not supported by the dense factor");
+    d.n = P.n;
+    d.m = P.m;
+    d.p = P.p;
+    d.nU = P.nU;
+    d.smax = P.smax;
+    d.nslots = P.nslots;
+    d.ldU = P.ld;
+    d.ldM = round_up(P.m, 4);
+    h->off_host = P.off;
+    // u is padded to ldU (the A u kernel reads whole 4-wide groups)
+    std::vector<double> pad_invD(P.invD), pad_s2(P.s2), pad_wt(P.wt);
+    pad_invD.resize((size_t)d.ldU, 0.0);
+    pad_s2.resize((size_t)d.ldU, 0.0);
+    pad_wt.resize((size_t)d.ldU, 0.0);
+    CK(upload_common(h, P.size, P.gather, P.cnt, pad_wt, pad_invD, pad_s2, P.c, P.b, heavy_threshold(), s));
+    CK(h->alloc(&d.spart, 2 * (int64_t)scatter_blocks(d)));
+    CK(h->alloc(&d.u, d.ldU));
+    HIP_OK(hipMemsetAsync(d.u, 0, (size_t)d.ldU * sizeof(double), s));
+    // A (w-scaled, FP32) row-major and transposed.
+    const int64_t nU = P.nU, m = P.m;
+    std::vector<float> AwT((size_t)(nU * d.ldM), 0.0f);
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t e = 0; e < nU; ++e) AwT[(size_t)(e * d.ldM + i)] = P.Aw[(size_t)(i * d.ldU + e)];
+    CK(upload(h, &d.Aw, P.Aw, s));
+    CK(upload(h, &d.AwT, AwT, s));
 
     // KKT factor: M = Aw diag(s2) Aw^T, Cholesky, inverse factors.
     double *M = nullptr, *diag0 = nullptr;
@@ -291,11 +351,11 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
         (void)hipFree(M);
         return fail(CDCS_E_NOMEM, "hipMalloc diag");
     }
-    CK(h->alloc(&d.Linv, (int64_t)m * m));
-    CK(h->alloc(&d.LinvT, (int64_t)m * m));
-    launch_syrk(d.Aw, d.ldU, d.s2, m, M, s);
-    launch_potrf(M, m, diag0, d.info, s);
-    launch_trtri(M, m, d.LinvT, d.Linv, s);
+    CK(h->alloc(&d.Linv, m * m));
+    CK(h->alloc(&d.LinvT, m * m));
+    launch_syrk(d.Aw, d.ldU, d.s2, (int)m, M, s);
+    launch_potrf(M, (int)m, diag0, d.info, s);
+    launch_trtri(M, (int)m, d.LinvT, d.Linv, s);
     int32_t info_h[4] = {0, 0, 0, 0};
     hipError_t e2 = hipMemcpyAsync(info_h, d.info, sizeof(info_h), hipMemcpyDeviceToHost, s);
     hipError_t e3 = hipStreamSynchronize(s);
@@ -304,7 +364,137 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
     if (e2 != hipSuccess || e3 != hipSuccess)
         return fail(CDCS_E_DEVICE, std::string("setup kernels: ") + hipGetErrorString(e2 != hipSuccess ? e2 : e3));
     if (info_h[0] != 0)
-        return fail(CDCS_E_RANK, "A D^-1 A^T is not positive definite (pivot " + std::to_string(info_h[1]) + "): A is rank deficient");
+        return fail(CDCS_E_RANK,
+                    "A D^-1 A^T is not positive definite (pivot " + std::to_string(info_h[1]) + "): A is rank deficient");
+    HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    return CDCS_OK;
+}
+
+// Many SDPs: concatenate every instance's entries, cliques, slots and rows.
+cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs, hipStream_t s) {
+    Dev &d = h->d;
+    if (nprob < 1 || !probs) return fail(CDCS_E_ARG, "no problems");
+    h->batch_host.reset(new Batch());
+    d.batch = h->batch_host.get();
+    Batch &B = *d.batch;
+    B.nprob = nprob;
+    std::vector<int64_t> U_off(1, 0), A_off, F_off;
+    std::vector<int32_t> m_off(1, 0), k_off(1, 0), A_ld, einst, rinst, kinst;
+    std::vector<int32_t> size, gather, cnt;
+    std::vector<double> wt, invD, s2, c, b;
+    std::vector<float> Aw;
+    std::vector<int32_t> sblk, sblk_off(1, 0), syrk_jobs, trtri_jobs;
+    h->off_host.assign(1, 0);
+    int64_t Atot = 0, Ftot = 0;
+    d.smax = 0;
+    d.n = 0;
+    for (int32_t q = 0; q < nprob; ++q) {
+        HostProblem P;
+        const cdcs_problem &pr = probs[q];
+        cdcs_status st = host_problem(pr.pattern, pr.A, pr.b, pr.c, pr.cliques, 4, P);
+        if (st != CDCS_OK) return fail(st, "problem " + std::to_string(q) + ": " + g_err);
+        if (P.m > 256) return fail(CDCS_E_ARG, "problem " + std::to_string(q) + ": batched factors need m <= 256");
+        const int64_t u0 = U_off.back();
+        const int64_t slot0 = h->off_host.back();
+        for (int32_t k = 0; k < P.p; ++k) {
+            size.push_back(P.size[(size_t)k]);
+            h->off_host.push_back(slot0 + P.off[(size_t)k + 1]);
+            kinst.push_back(q);
+        }
+        for (int32_t g : P.gather) gather.push_back((int32_t)(u0 + g));
+        cnt.insert(cnt.end(), P.cnt.begin(), P.cnt.end());
+        wt.insert(wt.end(), P.wt.begin(), P.wt.end());
+        invD.insert(invD.end(), P.invD.begin(), P.invD.end());
+        s2.insert(s2.end(), P.s2.begin(), P.s2.end());
+        c.insert(c.end(), P.c.begin(), P.c.end());
+        b.insert(b.end(), P.b.begin(), P.b.end());
+        for (int64_t e = 0; e < P.nU; ++e) einst.push_back(q);
+        for (int32_t i = 0; i < P.m; ++i) rinst.push_back(q);
+        A_off.push_back(Atot);
+        A_ld.push_back((int32_t)P.ld);
+        Aw.insert(Aw.end(), P.Aw.begin(), P.Aw.end());
+        Atot += (int64_t)P.Aw.size();
+        F_off.push_back(Ftot);
+        Ftot += (int64_t)P.m * P.m;
+        // scatter blocks of <= 256 entries inside the instance
+        for (int64_t e0 = 0; e0 < P.nU; e0 += 256) {
+            sblk.push_back(q);
+            sblk.push_back((int32_t)(u0 + e0));
+            sblk.push_back((int32_t)(u0 + std::min<int64_t>(P.nU, e0 + 256)));
+            sblk.push_back(0);
+        }
+        sblk_off.push_back((int32_t)(sblk.size() / 4));
+        const int T = (P.m + 31) / 32;
+        for (int I = 0; I < T; ++I)
+            for (int J = 0; J <= I; ++J) {
+                syrk_jobs.push_back(q);
+                syrk_jobs.push_back(I);
+                syrk_jobs.push_back(J);
+                syrk_jobs.push_back(0);
+            }
+        for (int32_t j = 0; j < P.m; ++j) {
+            trtri_jobs.push_back(q);
+            trtri_jobs.push_back(j);
+        }
+        U_off.push_back(u0 + P.nU);
+        m_off.push_back(m_off.back() + P.m);
+        k_off.push_back(k_off.back() + P.p);
+        d.smax = std::max(d.smax, P.smax);
+        d.n += P.n;
+    }
+    d.nU = U_off.back();
+    d.m = m_off.back();
+    d.p = k_off.back();
+    d.nslots = h->off_host.back();
+    if (d.nU >= (int64_t)1 << 31 || d.nslots >= (int64_t)1 << 31) return fail(CDCS_E_ARG, "batch too large");
+    d.ldU = d.nU;
+    d.ldM = round_up(d.m, 4);
+    CK(upload_common(h, size, gather, cnt, wt, invD, s2, c, b, 1 << 30, s));
+    CK(h->alloc(&d.u, d.nU));
+    CK(upload(h, &d.Aw, Aw, s));
+    CK(upload(h, &B.U_off, U_off, s));
+    CK(upload(h, &B.m_off, m_off, s));
+    CK(upload(h, &B.k_off, k_off, s));
+    CK(upload(h, &B.A_off, A_off, s));
+    CK(upload(h, &B.A_ld, A_ld, s));
+    CK(upload(h, &B.F_off, F_off, s));
+    CK(upload(h, &B.einst, einst, s));
+    CK(upload(h, &B.rinst, rinst, s));
+    CK(upload(h, &B.kinst, kinst, s));
+    CK(upload(h, &B.sblk, sblk, s));
+    CK(upload(h, &B.sblk_off, sblk_off, s));
+    CK(upload(h, &B.syrk_jobs, syrk_jobs, s));
+    CK(upload(h, &B.trtri_jobs, trtri_jobs, s));
+    B.nsblk = (int32_t)(sblk.size() / 4);
+    B.nsyrk = (int32_t)(syrk_jobs.size() / 4);
+    CK(h->alloc(&d.spart, 2 * (int64_t)B.nsblk));
+    CK(h->alloc(&B.istop, nprob));
+    HIP_OK(hipMemsetAsync(B.istop, 0, (size_t)nprob * sizeof(int32_t), s));
+    CK(h->alloc(&B.iiters, nprob));
+    CK(h->alloc(&B.itime, nprob));
+    CK(h->alloc(&B.t0, 1));
+    CK(h->alloc(&B.ieps, 2 * (int64_t)nprob));
+    HIP_OK(hipMemsetAsync(B.ieps, 0, (size_t)(2 * nprob) * sizeof(double), s));
+    CK(h->alloc(&B.iobj, 2 * (int64_t)nprob));
+    CK(h->alloc(&B.nrunning, 1));
+    CK(h->alloc(&B.finfo, nprob));
+    HIP_OK(hipMemsetAsync(B.finfo, 0, (size_t)nprob * sizeof(int32_t), s));
+    // per-instance KKT factors
+    double *M = nullptr;
+    HIP_OK(hipMalloc(&M, (size_t)std::max<int64_t>(Ftot, 1) * sizeof(double)));
+    CK(h->alloc(&d.Linv, Ftot));
+    CK(h->alloc(&d.LinvT, Ftot));
+    launch_bsetup(d, M, s);
+    std::vector<int32_t> finfo((size_t)nprob, 0);
+    hipError_t e2 = hipMemcpyAsync(finfo.data(), B.finfo, (size_t)nprob * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    hipError_t e3 = hipStreamSynchronize(s);
+    (void)hipFree(M);
+    if (e2 != hipSuccess || e3 != hipSuccess)
+        return fail(CDCS_E_DEVICE, std::string("batch setup kernels: ") + hipGetErrorString(e2 != hipSuccess ? e2 : e3));
+    for (int32_t q = 0; q < nprob; ++q)
+        if (finfo[(size_t)q] != 0)
+            return fail(CDCS_E_RANK, "problem " + std::to_string(q) + ": A D^-1 A^T is not positive definite (pivot " +
+                                         std::to_string(finfo[(size_t)q] - 1) + ")");
     HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     return CDCS_OK;
 }
@@ -324,6 +514,8 @@ void launch_projection(cdcs_handle *h, int mode, const cdcs_state *st, double rh
         a.lam = st->lam;
         a.v = st->v;
         a.rho = rho;
+        a.kinst = d.batch ? d.batch->kinst : nullptr;
+        a.istop = d.batch ? d.batch->istop : nullptr;
         a.vwarm = d.vwarm;
         a.vwoff = d.vwoff;
         a.cpart = d.cpart;
@@ -334,6 +526,13 @@ void launch_projection(cdcs_handle *h, int mode, const cdcs_state *st, double rh
 
 void enqueue_iteration(cdcs_handle *h, const cdcs_state *st, int form, double rho, hipStream_t s) {
     Dev &d = h->d;
+    if (d.batch) {  // Algorithm 1, per-instance stopping
+        launch_bscatter_primal(d, st->blk, st->lam, rho, s);
+        launch_bcheck_primal(d, rho, s);
+        launch_baffine(d, d.b, 1.0, st->x, st->y, d.ctl, d.batch->istop, s);
+        launch_projection(h, PROJ_PRIMAL, st, rho, s);
+        return;
+    }
     if (form == CDCS_PRIMAL) {
         launch_scatter_primal(d, st->blk, st->lam, rho, s);
         launch_check_primal(d, rho, s);
@@ -398,6 +597,60 @@ cdcs_status cdcs_setup(const cdcs_pattern *pattern, const cdcs_constraints *A, c
         return st;
     }
     *out = h;
+    return CDCS_OK;
+}
+
+cdcs_status cdcs_setup_batch(int32_t nprob, const cdcs_problem *probs, const cdcs_options *opts, hipStream_t stream,
+                             cdcs_handle **out) {
+    (void)opts;
+    if (!out) return fail(CDCS_E_ARG, "out is NULL");
+    *out = nullptr;
+    g_err.clear();
+    cdcs_handle *h = new (std::nothrow) cdcs_handle();
+    if (!h) return fail(CDCS_E_NOMEM, "host allocation");
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(CDCS_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    cdcs_status st = build_batch(h, nprob, probs, stream);
+    if (st != CDCS_OK) {
+        (void)hipStreamSynchronize(stream);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return CDCS_OK;
+}
+
+cdcs_status cdcs_batch_info(const cdcs_handle *h, int32_t nprob, cdcs_instance_info *out_host) {
+    if (!h || !out_host) return fail(CDCS_E_ARG, "NULL argument");
+    const Batch *B = h->d.batch;
+    if (!B) return fail(CDCS_E_ARG, "not a batch handle");
+    if (nprob != B->nprob) return fail(CDCS_E_ARG, "nprob does not match the handle");
+    std::vector<int32_t> stp((size_t)nprob), its((size_t)nprob);
+    std::vector<uint64_t> tim((size_t)nprob);
+    std::vector<double> eps((size_t)(2 * nprob)), obj((size_t)(2 * nprob));
+    uint64_t t0 = 0;
+    HIP_OK(hipMemcpy(stp.data(), B->istop, stp.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(its.data(), B->iiters, its.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(tim.data(), B->itime, tim.size() * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(eps.data(), B->ieps, eps.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(obj.data(), B->iobj, obj.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(&t0, B->t0, sizeof(uint64_t), hipMemcpyDeviceToHost));
+    int rate_khz = 0;
+    HIP_OK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, h->device));
+    const double rho = h->last_rho;
+    for (int32_t q = 0; q < nprob; ++q) {
+        cdcs_instance_info &o = out_host[q];
+        o.iters = stp[(size_t)q] ? its[(size_t)q] : h->last_iters;
+        o.status = stp[(size_t)q] == 1 ? CDCS_OK : CDCS_E_NOT_CONVERGED;
+        o.eps_p = eps[(size_t)(2 * q)];
+        o.eps_d = eps[(size_t)(2 * q + 1)];
+        o.obj_primal = obj[(size_t)(2 * q)];
+        o.obj_dual = -rho * obj[(size_t)(2 * q + 1)];
+        o.time_to_tol_s = (stp[(size_t)q] && rate_khz > 0) ? (double)(tim[(size_t)q] - t0) / (1e3 * rate_khz) : -1.0;
+    }
     return CDCS_OK;
 }
 
@@ -483,7 +736,8 @@ cdcs_status cdcs_affine_project(const cdcs_handle *h, const double *r1, const do
     if (!h || !r1 || !r2 || !x || !y) return fail(CDCS_E_ARG, "NULL argument");
     const Dev &d = h->d;
     launch_scale_u(d, r1, stream);
-    launch_affine(d, r2, 1.0, x, y, nullptr, stream);
+    if (d.batch) launch_baffine(d, r2, 1.0, x, y, nullptr, nullptr, stream);
+    else launch_affine(d, r2, 1.0, x, y, nullptr, stream);
     HIP_OK(hipGetLastError());
     return CDCS_OK;
 }
@@ -499,6 +753,8 @@ cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st, const cdcs_opt
         return fail(CDCS_E_ARG, "need rho > 0, tol >= 0, max_iter >= 1");
     Dev &d = h->d;
     const double rho = opts->rho;
+    if (d.batch && form != CDCS_PRIMAL) return fail(CDCS_E_ARG, "batch handles run Algorithm 1 only");
+    h->last_rho = rho;
     if (d.hist_cap < opts->max_iter) {
         if (d.hist) {
             HIP_OK(hipStreamSynchronize(stream));
@@ -513,6 +769,7 @@ cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st, const cdcs_opt
         h->graphs.clear();
     }
     launch_reset_ctl(d, opts->max_iter, opts->tol, stream);
+    if (d.batch) launch_breset(d, stream);
     // the eigenvector warm start restarts at each solve: a solve is a function
     // of (problem, state, options) only
     launch_identity_blocks(d.clq_size, d.vwoff, d.p, d.vwarm, stream);
@@ -539,7 +796,11 @@ cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st, const cdcs_opt
             }
         }
     }
-    if (form == CDCS_PRIMAL) {
+    if (d.batch) {
+        launch_bscatter_primal(d, st->blk, st->lam, rho, stream);
+        launch_bcheck_primal(d, rho, stream);
+        launch_bobjectives(d, st->x, st->y, d.batch->iobj, stream);
+    } else if (form == CDCS_PRIMAL) {
         // residuals of the last iteration need the next right-hand side's scatter
         launch_scatter_primal(d, st->blk, st->lam, rho, stream);
         launch_check_primal(d, rho, stream);
@@ -554,12 +815,18 @@ cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st, const cdcs_opt
     const Ctl c = *d.ctl_host;
     h->last_iters = c.iter;
     cdcs_status status = CDCS_OK;
+    int converged = (c.stop == 1);
+    if (d.batch) {
+        std::vector<int32_t> stp((size_t)d.batch->nprob);
+        HIP_OK(hipMemcpy(stp.data(), d.batch->istop, stp.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        converged = std::all_of(stp.begin(), stp.end(), [](int32_t v) { return v == 1; });
+    }
     if (c.jacobi_cap > 0) status = CDCS_E_NUMERIC;
-    else if (c.stop != 1 && opts->tol > 0.0) status = CDCS_E_NOT_CONVERGED;
+    else if (!converged && opts->tol > 0.0) status = CDCS_E_NOT_CONVERGED;
     if (info) {
         info->iters = c.iter;
         info->status = status;
-        info->converged = (c.stop == 1);
+        info->converged = converged;
         info->jacobi_cap_hits = c.jacobi_cap;
         info->eps_p = c.eps_p;
         info->eps_d = c.eps_d;
@@ -596,6 +863,17 @@ cdcs_status cdcs_profile_kernel(cdcs_handle *h, const cdcs_state *st, int32_t fo
     if (reps < 1 || !(rho > 0.0)) return fail(CDCS_E_ARG, "need reps >= 1, rho > 0");
     Dev &d = h->d;
     launch_reset_ctl(d, 1 << 30, 0.0, stream);
+    if (d.batch) {
+        launch_breset(d, stream);
+        for (int r = 0; r < reps; ++r) {
+            if (kernel == CDCS_K_PROJECT) launch_projection(h, PROJ_PRIMAL, st, rho, stream);
+            else if (kernel == CDCS_K_SCATTER) launch_bscatter_primal(d, st->blk, st->lam, rho, stream);
+            else if (kernel == CDCS_K_GEMV_AU) launch_baffine(d, d.b, 1.0, st->x, st->y, d.ctl, nullptr, stream);
+            else return fail(CDCS_E_ARG, "batch handles profile CDCS_K_PROJECT, CDCS_K_SCATTER, CDCS_K_GEMV_AU");
+        }
+        HIP_OK(hipGetLastError());
+        return CDCS_OK;
+    }
     for (int r = 0; r < reps; ++r) {
         switch (kernel) {
         case CDCS_K_PROJECT:

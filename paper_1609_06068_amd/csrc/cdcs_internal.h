@@ -54,6 +54,8 @@ struct ProjArgs {
     float *lam;                // [nslots]
     const float *v;            // [nslots]
     double rho;
+    const int32_t *kinst;      // [*] instance of each block (many-SDP handles), or NULL
+    const int32_t *istop;      // [nprob] per-instance stop flags, or NULL
     float *vwarm;              // eigenvector warm start (ADMM modes), NULL: cold
     const int64_t *vwoff;      // [*] offsets of the k x k blocks in vwarm
     double *cpart;             // [p][4] per-block partial sums
@@ -79,6 +81,34 @@ struct VjpArgs {
 void launch_project_vjp(const VjpArgs &a, int smax, hipStream_t s);
 // Set every k x k block of V (at voff[k]) to the identity.
 void launch_identity_blocks(const int32_t *size, const int64_t *voff, int p, float *V, hipStream_t s);
+
+// Many independent SDPs in one handle: index ranges and per-instance state.
+struct Batch {
+    int32_t nprob = 0;
+    int64_t *U_off = nullptr;      // [nprob+1] entry ranges
+    int32_t *m_off = nullptr;      // [nprob+1] constraint-row ranges
+    int32_t *k_off = nullptr;      // [nprob+1] clique ranges
+    int64_t *A_off = nullptr;      // [nprob] offset of A_q (w-scaled FP32, m_q x A_ld[q])
+    int32_t *A_ld = nullptr;       // [nprob]
+    int64_t *F_off = nullptr;      // [nprob] offset of the m_q x m_q FP64 factors
+    int32_t *einst = nullptr;      // [nU] instance of each entry
+    int32_t *rinst = nullptr;      // [m] instance of each row
+    int32_t *kinst = nullptr;      // [p] instance of each clique
+    int32_t *sblk = nullptr;       // [nsblk * 4] scatter blocks (q, e0, e1, 0)
+    int32_t *sblk_off = nullptr;   // [nprob+1] scatter-block ranges
+    int32_t nsblk = 0;
+    int32_t *syrk_jobs = nullptr;  // [nsyrk * 4] (q, I, J, 0) tiles of M_q
+    int32_t nsyrk = 0;
+    int32_t *trtri_jobs = nullptr; // [m * 2] (q, j)
+    int32_t *istop = nullptr;      // [nprob] 0 running, 1 converged, 2 iteration cap
+    int32_t *iiters = nullptr;     // [nprob] iterations at stop
+    uint64_t *itime = nullptr;     // [nprob] device wall clock at stop
+    uint64_t *t0 = nullptr;        // [1] device wall clock at solve start
+    double *ieps = nullptr;        // [nprob * 2] last eps_p, eps_d
+    double *iobj = nullptr;        // [nprob * 2] <c, x>_w and <b, y>
+    int32_t *nrunning = nullptr;   // [1] instances still running
+    int32_t *finfo = nullptr;      // [nprob] factorisation status
+};
 
 // Affine-step, scatter, residual and setup kernels (kernels_affine.hip).
 struct Dev {
@@ -121,7 +151,17 @@ struct Dev {
     int32_t *info = nullptr;       // [4] setup status words
     Ctl *ctl = nullptr;
     Ctl *ctl_host = nullptr;       // pinned mirror
+    Batch *batch = nullptr;        // many-SDP handles only
 };
+
+// many-SDP kernels (kernels_batch.hip)
+void launch_breset(const Dev &d, hipStream_t s);
+void launch_bscatter_primal(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s);
+void launch_bcheck_primal(const Dev &d, double rho, hipStream_t s);
+void launch_baffine(const Dev &d, const double *r2, double r2scale, double *x, double *y, const Ctl *ctl,
+                    const int32_t *istop, hipStream_t s);
+void launch_bsetup(const Dev &d, double *M, hipStream_t s);
+void launch_bobjectives(const Dev &d, const double *x, const double *y, double *out, hipStream_t s);
 
 // scatter / residual / affine kernels
 int scatter_blocks(const Dev &d);

@@ -144,6 +144,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
     const int bi = blockIdx.x;
     if (bi >= a.nblk) return;
     const int id = a.ids ? a.ids[bi] : bi;
+    if (a.istop != nullptr && a.istop[a.kinst[id]]) return;  // instance already stopped
     const int k = a.size[id];
     if (k < 1 || k > S) return;
     const int64_t off = a.off[id];

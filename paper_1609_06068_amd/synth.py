@@ -374,3 +374,24 @@ def unit_directions(dim: int, count: int, seed: int) -> np.ndarray:
     rng = _rng(seed)
     D = rng.standard_normal((count, dim))
     return D / np.linalg.norm(D, axis=1, keepdims=True)
+
+
+def c4_params(count: int = 512, seed: int = 4000):
+    """Per-instance (l, d, h, m) of the many-SDP workload: l in 5..40,
+    d in 8..32, h in 2..12 drawn uniformly, m = 5 l."""
+    rng = _rng(seed)
+    out = []
+    for _ in range(count):
+        l = int(rng.integers(5, 41))
+        d = int(rng.integers(8, 33))
+        h = int(rng.integers(2, 13))
+        out.append((l, d, h, 5 * l))
+    return out
+
+
+def c4(count: int = 512, first: int = 0):
+    """The many-SDP workload: `count` independent block-arrow SDPs (instances
+    first..first+count-1 of the seeded sequence), seed 1000*4 + instance."""
+    params = c4_params(first + count)
+    return [block_arrow(l, d, h, m, seed=config_seed(4, first + i))
+            for i, (l, d, h, m) in enumerate(params[first:first + count])]
