@@ -88,9 +88,12 @@ typedef struct {
 /* Constraint matrices A_1..A_m of the operator A(X) = [<A_i, X>] (Sec. I),
  * each given by its values on pattern entries.  dense = 1: val is m x nnz
  * row-major (ptr, idx ignored).  dense = 0: CSR rows (ptr[m+1], idx[] pattern
- * entry of each value, val[]); duplicates are summed.  Values are stored on
- * the device in FP32 (off-diagonal ones doubled, exactly); the KKT factor is
- * built from those stored values. */
+ * entry of each value, val[]); duplicates are summed.  A dense matrix, or a
+ * CSR one with more than a fifth of its m x nnz entries present, is stored on
+ * the device in FP32 (off-diagonal values doubled, exactly) as a dense array
+ * and its transpose; a sparser CSR matrix is kept sparse in FP64 (rows for
+ * A u, the nonzero columns for A^T y).  The KKT factor is built from the
+ * stored values.  Batch handles (cdcs_setup_batch) always store A densely. */
 typedef struct {
     int32_t m;
     int32_t dense;
@@ -135,9 +138,13 @@ typedef struct {
     float *v;
 } cdcs_state;
 
+/* Sizes of a handle.  sparse_a = 1 if A is kept sparse (nnz_a coefficients),
+ * 0 if it is stored densely (nnz_a = m * nnz). */
 typedef struct {
     int32_t n, m, p, smax;
     int64_t nnz, nslots;
+    int32_t sparse_a, pad_;
+    int64_t nnz_a;
 } cdcs_sizes;
 
 /*

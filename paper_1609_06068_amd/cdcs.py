@@ -82,7 +82,8 @@ class _InstanceInfo(ctypes.Structure):
 
 class _Sizes(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("p", ctypes.c_int32), ("smax", ctypes.c_int32),
-                ("nnz", ctypes.c_int64), ("nslots", ctypes.c_int64)]
+                ("nnz", ctypes.c_int64), ("nslots", ctypes.c_int64), ("sparse_a", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("nnz_a", ctypes.c_int64)]
 
 
 _lib = None
@@ -206,6 +207,7 @@ class Solver:
         _check(L.cdcs_get_sizes(h, ctypes.byref(sz)), "cdcs_get_sizes")
         self.n, self.m, self.p, self.smax = sz.n, sz.m, sz.p, sz.smax
         self.nnz, self.nslots = sz.nnz, sz.nslots
+        self.sparse_a, self.nnz_a = bool(sz.sparse_a), sz.nnz_a
         off = np.empty(self.p + 1, dtype=np.int64)
         _check(L.cdcs_clique_offsets(h, _np_ptr(off)), "cdcs_clique_offsets")
         self.offsets = off

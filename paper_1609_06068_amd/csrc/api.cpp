@@ -116,11 +116,18 @@ struct HostProblem {
     std::vector<int32_t> gather;     // [nslots] entry of each packed slot (H_k)
     std::vector<int32_t> cnt;        // [nU] D_e = number of cliques covering e
     std::vector<double> wt, invD, s2, c, b;
-    std::vector<float> Aw;           // [m * ld] w-scaled A, row-major, zero padded
+    std::vector<float> Aw;           // [m * ld] w-scaled A, row-major, zero padded (dense path)
+    bool sparse = false;             // CSR path: rows sorted by entry, duplicates summed
+    std::vector<int32_t> sp_ptr, sp_col;
+    std::vector<double> sp_val;      // w_e * A_ie
 };
 
+// A CSR input is kept sparse when a dense FP32 copy would be read at more
+// than five times the bytes of the coefficients.
+bool keep_sparse(int64_t nnz, int64_t m, int64_t nU) { return nnz * 5 < m * nU; }
+
 cdcs_status host_problem(const cdcs_pattern *pat, const cdcs_constraints *A, const double *b, const double *c,
-                         const cdcs_cliques *cl, int64_t align, HostProblem &P) {
+                         const cdcs_cliques *cl, int64_t align, bool allow_sparse, HostProblem &P) {
     if (!pat || !A || !b || !c || !cl) return fail(CDCS_E_ARG, "NULL argument");
     if (pat->n < 1 || pat->nnz < 1 || !pat->i || !pat->j) return fail(CDCS_E_ARG, "empty or NULL pattern");
     if (A->m < 1 || !A->val) return fail(CDCS_E_ARG, "no constraints");
@@ -206,8 +213,41 @@ cdcs_status host_problem(const cdcs_pattern *pat, const cdcs_constraints *A, con
         P.invD[(size_t)e] = 1.0 / D;
         P.s2[(size_t)e] = 1.0 / (w * D);
     }
-    // Constraint matrix, w A in FP32 (exact for FP32-representable A).
     P.ld = round_up(nU, align);
+    if (!A->dense) {
+        if (!A->ptr || !A->idx) return fail(CDCS_E_ARG, "CSR A without ptr/idx");
+        if (A->ptr[0] != 0) return fail(CDCS_E_ARG, "CSR A ptr[0] != 0");
+        for (int32_t i = 0; i < m; ++i)
+            if (A->ptr[i + 1] < A->ptr[i]) return fail(CDCS_E_ARG, "CSR A ptr not monotone");
+        for (int64_t q = 0; q < A->ptr[m]; ++q)
+            if (A->idx[q] < 0 || A->idx[q] >= nU) return fail(CDCS_E_PATTERN, "A entry index out of range");
+    }
+    if (!A->dense && allow_sparse && keep_sparse(A->ptr[m], m, nU)) {
+        // Sparse path: w A in FP64, each row sorted by entry with duplicates summed.
+        if (A->ptr[m] >= (int64_t)1 << 31) return fail(CDCS_E_ARG, "too many A coefficients");
+        P.sparse = true;
+        P.sp_ptr.assign((size_t)m + 1, 0);
+        std::vector<std::pair<int32_t, double>> row;
+        for (int32_t i = 0; i < m; ++i) {
+            row.clear();
+            for (int64_t q = A->ptr[i]; q < A->ptr[i + 1]; ++q) row.push_back({A->idx[q], A->val[q]});
+            std::sort(row.begin(), row.end(),
+                      [](const std::pair<int32_t, double> &x, const std::pair<int32_t, double> &y) {
+                          return x.first < y.first;
+                      });
+            for (size_t q = 0; q < row.size(); ++q) {
+                if (q > 0 && row[q].first == row[q - 1].first) {
+                    P.sp_val.back() += P.wt[(size_t)row[q].first] * row[q].second;
+                    continue;
+                }
+                P.sp_col.push_back(row[q].first);
+                P.sp_val.push_back(P.wt[(size_t)row[q].first] * row[q].second);
+            }
+            P.sp_ptr[(size_t)i + 1] = (int32_t)P.sp_col.size();
+        }
+        return CDCS_OK;
+    }
+    // Constraint matrix, w A in FP32 (exact for FP32-representable A).
     const int64_t dense_elems = (int64_t)m * P.ld;
     if (dense_elems > ((int64_t)1 << 33)) return fail(CDCS_E_ARG, "dense A too large (sparse A path not built)");
     P.Aw.assign((size_t)dense_elems, 0.0f);
@@ -216,15 +256,10 @@ cdcs_status host_problem(const cdcs_pattern *pat, const cdcs_constraints *A, con
             for (int64_t e = 0; e < nU; ++e)
                 P.Aw[(size_t)(i * P.ld + e)] = (float)(P.wt[(size_t)e] * A->val[(size_t)i * nU + e]);
     } else {
-        if (!A->ptr || !A->idx) return fail(CDCS_E_ARG, "CSR A without ptr/idx");
         std::vector<double> row((size_t)nU);
         for (int32_t i = 0; i < m; ++i) {
             std::fill(row.begin(), row.end(), 0.0);
-            for (int64_t q = A->ptr[i]; q < A->ptr[i + 1]; ++q) {
-                const int32_t e = A->idx[q];
-                if (e < 0 || e >= nU) return fail(CDCS_E_PATTERN, "A entry index out of range");
-                row[(size_t)e] += A->val[q];
-            }
+            for (int64_t q = A->ptr[i]; q < A->ptr[i + 1]; ++q) row[(size_t)A->idx[q]] += A->val[q];
             for (int64_t e = 0; e < nU; ++e) P.Aw[(size_t)(i * P.ld + e)] = (float)(P.wt[(size_t)e] * row[(size_t)e]);
         }
     }
@@ -315,7 +350,7 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
                   const double *c, const cdcs_cliques *cl, hipStream_t s) {
     Dev &d = h->d;
     HostProblem P;
-    CK(host_problem(pat, A, b, c, cl, 64, P));
+    CK(host_problem(pat, A, b, c, cl, 64, true, P));
     if (P.m > 8192) return fail(CDCS_E_ARG, "m > 8192 is not supported by the dense factor");
     d.n = P.n;
     d.m = P.m;
@@ -335,13 +370,48 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
     CK(h->alloc(&d.spart, 2 * (int64_t)scatter_blocks(d)));
     CK(h->alloc(&d.u, d.ldU));
     HIP_OK(hipMemsetAsync(d.u, 0, (size_t)d.ldU * sizeof(double), s));
-    // A (w-scaled, FP32) row-major and transposed.
     const int64_t nU = P.nU, m = P.m;
-    std::vector<float> AwT((size_t)(nU * d.ldM), 0.0f);
-    for (int64_t i = 0; i < m; ++i)
-        for (int64_t e = 0; e < nU; ++e) AwT[(size_t)(e * d.ldM + i)] = P.Aw[(size_t)(i * d.ldU + e)];
-    CK(upload(h, &d.Aw, P.Aw, s));
-    CK(upload(h, &d.AwT, AwT, s));
+    std::vector<int32_t> tid;  // touched-entry index of each coefficient (sparse setup only)
+    if (P.sparse) {
+        // Coefficients by touched entry (the columns of A that are not zero).
+        d.sparse = 1;
+        d.nnzA = (int64_t)P.sp_col.size();
+        std::vector<int32_t> ccount((size_t)nU, 0), tc_of((size_t)nU, -1), tc_e, tc_ptr(1, 0), tc_row;
+        std::vector<double> tc_val;
+        for (int32_t e : P.sp_col) ++ccount[(size_t)e];
+        for (int64_t e = 0; e < nU; ++e)
+            if (ccount[(size_t)e] > 0) {
+                tc_of[(size_t)e] = (int32_t)tc_e.size();
+                tc_e.push_back((int32_t)e);
+                tc_ptr.push_back(tc_ptr.back() + ccount[(size_t)e]);
+            }
+        d.ntc = (int32_t)tc_e.size();
+        tc_row.resize((size_t)d.nnzA);
+        tc_val.resize((size_t)d.nnzA);
+        tid.resize((size_t)d.nnzA);
+        std::vector<int32_t> fillp(tc_ptr.begin(), tc_ptr.end() - 1);
+        for (int32_t i = 0; i < (int32_t)m; ++i)
+            for (int32_t q = P.sp_ptr[(size_t)i]; q < P.sp_ptr[(size_t)i + 1]; ++q) {
+                const int32_t t = tc_of[(size_t)P.sp_col[(size_t)q]];
+                tid[(size_t)q] = t;
+                tc_row[(size_t)fillp[(size_t)t]] = i;
+                tc_val[(size_t)fillp[(size_t)t]++] = P.sp_val[(size_t)q];
+            }
+        CK(upload(h, &d.sp_ptr, P.sp_ptr, s));
+        CK(upload(h, &d.sp_col, P.sp_col, s));
+        CK(upload(h, &d.sp_val, P.sp_val, s));
+        CK(upload(h, &d.tc_e, tc_e, s));
+        CK(upload(h, &d.tc_ptr, tc_ptr, s));
+        CK(upload(h, &d.tc_row, tc_row, s));
+        CK(upload(h, &d.tc_val, tc_val, s));
+    } else {
+        // A (w-scaled, FP32) row-major and transposed.
+        std::vector<float> AwT((size_t)(nU * d.ldM), 0.0f);
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t e = 0; e < nU; ++e) AwT[(size_t)(e * d.ldM + i)] = P.Aw[(size_t)(i * d.ldU + e)];
+        CK(upload(h, &d.Aw, P.Aw, s));
+        CK(upload(h, &d.AwT, AwT, s));
+    }
 
     // KKT factor: M = Aw diag(s2) Aw^T, Cholesky, inverse factors.
     double *M = nullptr, *diag0 = nullptr;
@@ -353,7 +423,13 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
     }
     CK(h->alloc(&d.Linv, m * m));
     CK(h->alloc(&d.LinvT, m * m));
-    launch_syrk(d.Aw, d.ldU, d.s2, (int)m, M, s);
+    int32_t *tid_d = nullptr;
+    if (d.sparse) {
+        CK(upload(h, &tid_d, tid, s));
+        launch_sp_syrk(d, tid_d, M, s);
+    } else {
+        launch_syrk(d.Aw, d.ldU, d.s2, (int)m, M, s);
+    }
     launch_potrf(M, (int)m, diag0, d.info, s);
     launch_trtri(M, (int)m, d.LinvT, d.Linv, s);
     int32_t info_h[4] = {0, 0, 0, 0};
@@ -391,7 +467,7 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
     for (int32_t q = 0; q < nprob; ++q) {
         HostProblem P;
         const cdcs_problem &pr = probs[q];
-        cdcs_status st = host_problem(pr.pattern, pr.A, pr.b, pr.c, pr.cliques, 4, P);
+        cdcs_status st = host_problem(pr.pattern, pr.A, pr.b, pr.c, pr.cliques, 4, false, P);
         if (st != CDCS_OK) return fail(st, "problem " + std::to_string(q) + ": " + g_err);
         if (P.m > 256) return fail(CDCS_E_ARG, "problem " + std::to_string(q) + ": batched factors need m <= 256");
         const int64_t u0 = U_off.back();
@@ -534,13 +610,13 @@ void enqueue_iteration(cdcs_handle *h, const cdcs_state *st, int form, double rh
         return;
     }
     if (form == CDCS_PRIMAL) {
-        launch_scatter_primal(d, st->blk, st->lam, rho, s);
+        launch_scatter_primal(d, st->blk, st->lam, rho, st->x, s);
         launch_check_primal(d, rho, s);
         launch_affine(d, d.b, 1.0, st->x, st->y, d.ctl, s);
         launch_projection(h, PROJ_PRIMAL, st, rho, s);
     } else {
         launch_projection(h, PROJ_DUAL, st, rho, s);
-        launch_scatter_dual(d, st->blk, st->lam, rho, s);
+        launch_scatter_dual(d, st->blk, st->lam, rho, st->x, s);
         launch_affine(d, d.b, -1.0 / rho, st->x, st->y, d.ctl, s);
         launch_vupdate(d, st->x, st->blk, st->lam, st->v, rho, s);
         launch_check_dual(d, rho, s);
@@ -662,6 +738,9 @@ cdcs_status cdcs_get_sizes(const cdcs_handle *h, cdcs_sizes *out) {
     out->smax = h->d.smax;
     out->nnz = h->d.nU;
     out->nslots = h->d.nslots;
+    out->sparse_a = h->d.sparse;
+    out->pad_ = 0;
+    out->nnz_a = h->d.sparse ? h->d.nnzA : (int64_t)h->d.m * h->d.nU;
     return CDCS_OK;
 }
 
@@ -735,7 +814,7 @@ cdcs_status cdcs_affine_project(const cdcs_handle *h, const double *r1, const do
                                 hipStream_t stream) {
     if (!h || !r1 || !r2 || !x || !y) return fail(CDCS_E_ARG, "NULL argument");
     const Dev &d = h->d;
-    launch_scale_u(d, r1, stream);
+    launch_scale_u(d, r1, x, stream);
     if (d.batch) launch_baffine(d, r2, 1.0, x, y, nullptr, nullptr, stream);
     else launch_affine(d, r2, 1.0, x, y, nullptr, stream);
     HIP_OK(hipGetLastError());
@@ -802,7 +881,8 @@ cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st, const cdcs_opt
         launch_bobjectives(d, st->x, st->y, d.batch->iobj, stream);
     } else if (form == CDCS_PRIMAL) {
         // residuals of the last iteration need the next right-hand side's scatter
-        launch_scatter_primal(d, st->blk, st->lam, rho, stream);
+        // (x keeps the last iterate: no copy of u into it)
+        launch_scatter_primal(d, st->blk, st->lam, rho, nullptr, stream);
         launch_check_primal(d, rho, stream);
     }
     launch_objectives(d, st->x, st->y, stream);
@@ -889,8 +969,8 @@ cdcs_status cdcs_profile_kernel(cdcs_handle *h, const cdcs_state *st, int32_t fo
             launch_affine_part(d, 2, d.b, 1.0, st->x, st->y, d.ctl, stream);
             break;
         case CDCS_K_SCATTER:
-            if (form == CDCS_PRIMAL) launch_scatter_primal(d, st->blk, st->lam, rho, stream);
-            else launch_scatter_dual(d, st->blk, st->lam, rho, stream);
+            if (form == CDCS_PRIMAL) launch_scatter_primal(d, st->blk, st->lam, rho, st->x, stream);
+            else launch_scatter_dual(d, st->blk, st->lam, rho, st->x, stream);
             break;
         default:
             return fail(CDCS_E_ARG, "unknown kernel id");

@@ -131,6 +131,17 @@ struct Dev {
     double *b = nullptr;           // [m]
     float *Aw = nullptr;           // [m * ldU] row-major, w_e * A_ie, zero padded
     float *AwT = nullptr;          // [nU * ldM] row-major transpose of Aw, zero padded
+    // sparse A (CSR input of low density): rows for A u, touched columns for A^T y
+    int32_t sparse = 0;
+    int64_t nnzA = 0;
+    int32_t ntc = 0;               // pattern entries with at least one constraint coefficient
+    int32_t *sp_ptr = nullptr;     // [m+1]   row pointers
+    int32_t *sp_col = nullptr;     // [nnzA]  entry of each coefficient (sorted within a row)
+    double *sp_val = nullptr;      // [nnzA]  w_e * A_ie
+    int32_t *tc_e = nullptr;       // [ntc]   touched entries, increasing
+    int32_t *tc_ptr = nullptr;     // [ntc+1]
+    int32_t *tc_row = nullptr;     // [nnzA]  row of each coefficient, by touched entry
+    double *tc_val = nullptr;      // [nnzA]  w_e * A_ie, by touched entry
     double *Linv = nullptr;        // [m * m] row-major, L^-1 (lower)
     double *LinvT = nullptr;       // [m * m] row-major, L^-T (upper)
     int32_t *order = nullptr;      // [p] cliques by decreasing size
@@ -168,13 +179,16 @@ int scatter_blocks(const Dev &d);
 int heavy_threshold();
 int vupdate_blocks(const Dev &d);
 void launch_reset_ctl(const Dev &d, int max_iter, double tol, hipStream_t s);
-void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s);
+// xcopy: sparse-A handles also write x = u (entries without coefficients keep it)
+void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, double rho, double *xcopy,
+                           hipStream_t s);
 void launch_check_primal(const Dev &d, double rho, hipStream_t s);
-void launch_scatter_dual(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s);
+void launch_scatter_dual(const Dev &d, const float *blk, const float *lam, double rho, double *xcopy,
+                        hipStream_t s);
 void launch_vupdate(const Dev &d, const double *x, const float *blk, float *lam, float *v, double rho,
                     hipStream_t s);
 void launch_check_dual(const Dev &d, double rho, hipStream_t s);
-void launch_scale_u(const Dev &d, const double *r1, hipStream_t s);
+void launch_scale_u(const Dev &d, const double *r1, double *xcopy, hipStream_t s);
 void launch_affine(const Dev &d, const double *r2, double r2scale, double *x, double *y, const Ctl *ctl,
                    hipStream_t s);
 // One part of the affine step: 0 split-K A u partials, 3 their reduction to t,
@@ -188,6 +202,8 @@ void launch_objectives(const Dev &d, const double *x, const double *y, hipStream
 
 // setup kernels (kernels_setup.hip)
 void launch_syrk(const float *Aw, int64_t ld, const double *s2, int m, double *M, hipStream_t s);
+// M (zeroed, m x m) = sum over coefficients of a sparse A; tid[q] = touched-entry index of sp_col[q]
+void launch_sp_syrk(const Dev &d, const int32_t *tid, double *M, hipStream_t s);
 void launch_potrf(double *M, int m, double *diag0, int32_t *info, hipStream_t s);
 void launch_trtri(const double *L, int m, double *LinvT, double *Linv, hipStream_t s);
 

@@ -68,6 +68,7 @@ __global__ __launch_bounds__(kNT) void k_scatter_primal(const int32_t *__restric
                                                         const double *__restrict__ c,
                                                         const double *__restrict__ invD,
                                                         const double *__restrict__ wt, double *__restrict__ u,
+                                                        double *__restrict__ xcopy,
                                                         double *__restrict__ sx, double *__restrict__ spart,
                                                         int64_t nU, double rho, const Ctl *ctl) {
     __shared__ double red[kNT / 64];
@@ -109,6 +110,7 @@ __global__ __launch_bounds__(kNT) void k_scatter_primal(const int32_t *__restric
     if (owner) {
         const double r1 = s_x + s_l / rho - c[e] / rho;
         u[e] = r1 * invD[e];
+        if (xcopy) xcopy[e] = r1 * invD[e];
         double *cur = sx + (int64_t)(n & 1) * nU;
         const double *prev = sx + (int64_t)((n + 1) & 1) * nU;
         const double d = s_x - prev[e];
@@ -184,7 +186,8 @@ __global__ __launch_bounds__(kNT) void k_scatter_dual(const int32_t *__restrict_
                                                       const float *__restrict__ lam,
                                                       const double *__restrict__ c,
                                                       const double *__restrict__ invD, double *__restrict__ u,
-                                                      int64_t nU, double rho, const Ctl *ctl) {
+                                                      double *__restrict__ xcopy, int64_t nU, double rho,
+                                                      const Ctl *ctl) {
     if (ctl->stop) return;
     const int lane = threadIdx.x & 63;
     if ((int)blockIdx.x < nlight_blocks) {
@@ -198,6 +201,7 @@ __global__ __launch_bounds__(kNT) void k_scatter_dual(const int32_t *__restrict_
             s += (double)blk[sl] + (double)lam[sl] / rho;
         }
         u[e] = (c[e] - s) * invD[e];
+        if (xcopy) xcopy[e] = (c[e] - s) * invD[e];
     } else {
         const int hw = ((int)blockIdx.x - nlight_blocks) * (kNT / 64) + (threadIdx.x >> 6);
         if (hw >= nheavy) return;
@@ -209,7 +213,10 @@ __global__ __launch_bounds__(kNT) void k_scatter_dual(const int32_t *__restrict_
             s += (double)blk[sl] + (double)lam[sl] / rho;
         }
         s = wave_sum_d(s);
-        if (lane == 0) u[e] = (c[e] - s) * invD[e];
+        if (lane == 0) {
+            u[e] = (c[e] - s) * invD[e];
+            if (xcopy) xcopy[e] = (c[e] - s) * invD[e];
+        }
     }
 }
 
@@ -328,9 +335,45 @@ __global__ __launch_bounds__(kNT) void k_scatter_f64(const int32_t *__restrict__
 }
 
 __global__ __launch_bounds__(kNT) void k_scale_u(const double *__restrict__ r1, const double *__restrict__ invD,
-                                                 double *__restrict__ u, int64_t nU) {
+                                                 double *__restrict__ u, double *__restrict__ xcopy, int64_t nU) {
     const int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (e < nU) u[e] = r1[e] * invD[e];
+    if (e >= nU) return;
+    u[e] = r1[e] * invD[e];
+    if (xcopy) xcopy[e] = r1[e] * invD[e];
+}
+
+// Sparse A: t_i = sum over the coefficients of row i of Aw_ie u_e - r2scale r2_i.
+// One wave per row, lanes over the coefficients.
+__global__ __launch_bounds__(kNT) void k_spmv_Au(const int32_t *__restrict__ sp_ptr,
+                                                 const int32_t *__restrict__ sp_col,
+                                                 const double *__restrict__ sp_val, const double *__restrict__ u,
+                                                 const double *__restrict__ r2, double r2scale,
+                                                 double *__restrict__ t, int m, const Ctl *ctl) {
+    if (ctl != nullptr && ctl->stop) return;
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * (kNT / 64) + (threadIdx.x >> 6);
+    if (row >= m) return;
+    double acc = 0.0;
+    for (int32_t q = sp_ptr[row] + lane; q < sp_ptr[row + 1]; q += 64) acc += sp_val[q] * u[sp_col[q]];
+    acc = wave_sum_d(acc);
+    if (lane == 0) t[row] = acc - r2scale * r2[row];
+}
+
+// Sparse A: x_e = u_e - s2_e (Aw^T y)_e on the entries that carry coefficients
+// (x = u elsewhere was written with u).  One thread per touched entry.
+__global__ __launch_bounds__(kNT) void k_sp_xcorr(const int32_t *__restrict__ tc_e,
+                                                  const int32_t *__restrict__ tc_ptr,
+                                                  const int32_t *__restrict__ tc_row,
+                                                  const double *__restrict__ tc_val, const double *__restrict__ y,
+                                                  const double *__restrict__ u, const double *__restrict__ s2,
+                                                  double *__restrict__ x, int ntc, const Ctl *ctl) {
+    if (ctl != nullptr && ctl->stop) return;
+    const int t = blockIdx.x * kNT + threadIdx.x;
+    if (t >= ntc) return;
+    double acc = 0.0;
+    for (int32_t r = tc_ptr[t]; r < tc_ptr[t + 1]; ++r) acc += tc_val[r] * y[tc_row[r]];
+    const int32_t e = tc_e[t];
+    x[e] = u[e] - s2[e] * acc;
 }
 
 // Split-K partial products of t = A (w u): tpart[slice][row] is the dot
@@ -477,10 +520,11 @@ void launch_reset_ctl(const Dev &d, int max_iter, double tol, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(kNT), 0, s, d.ctl, max_iter, tol);
 }
 
-void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s) {
+void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, double rho, double *xcopy,
+                           hipStream_t s) {
     hipLaunchKernelGGL(k_scatter_primal, dim3(scatter_blocks(d)), dim3(kNT), 0, s, d.inv_ptr, d.inv_slot,
                        (const int32_t *)d.heavy, d.nheavy, scatter_light_blocks(d), blk, lam, d.c, d.invD, d.wt, d.u,
-                       d.sx, d.spart, d.nU, rho, (const Ctl *)d.ctl);
+                       d.sparse ? xcopy : nullptr, d.sx, d.spart, d.nU, rho, (const Ctl *)d.ctl);
 }
 
 void launch_check_primal(const Dev &d, double rho, hipStream_t s) {
@@ -488,10 +532,11 @@ void launch_check_primal(const Dev &d, double rho, hipStream_t s) {
                        (const double *)d.spart, scatter_blocks(d), rho, d.hist, d.hist_cap, d.ctl);
 }
 
-void launch_scatter_dual(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s) {
+void launch_scatter_dual(const Dev &d, const float *blk, const float *lam, double rho, double *xcopy,
+                        hipStream_t s) {
     hipLaunchKernelGGL(k_scatter_dual, dim3(scatter_blocks(d)), dim3(kNT), 0, s, d.inv_ptr, d.inv_slot,
-                       (const int32_t *)d.heavy, d.nheavy, scatter_light_blocks(d), blk, lam, d.c, d.invD, d.u, d.nU,
-                       rho, (const Ctl *)d.ctl);
+                       (const int32_t *)d.heavy, d.nheavy, scatter_light_blocks(d), blk, lam, d.c, d.invD, d.u,
+                       d.sparse ? xcopy : nullptr, d.nU, rho, (const Ctl *)d.ctl);
 }
 
 void launch_vupdate(const Dev &d, const double *x, const float *blk, float *lam, float *v, double rho,
@@ -505,8 +550,9 @@ void launch_check_dual(const Dev &d, double rho, hipStream_t s) {
                        d.hist, d.hist_cap, d.ctl);
 }
 
-void launch_scale_u(const Dev &d, const double *r1, hipStream_t s) {
-    hipLaunchKernelGGL(k_scale_u, dim3(blocks_for(d.nU)), dim3(kNT), 0, s, r1, (const double *)d.invD, d.u, d.nU);
+void launch_scale_u(const Dev &d, const double *r1, double *xcopy, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_u, dim3(blocks_for(d.nU)), dim3(kNT), 0, s, r1, (const double *)d.invD, d.u,
+                       d.sparse ? xcopy : nullptr, d.nU);
 }
 
 // Affine projection from u = r1 / D: t = A (w u) - r2scale r2, y = L^-T L^-1 t,
@@ -518,7 +564,18 @@ int gemv_slices(const Dev &d) {
 
 void launch_affine_part(const Dev &d, int part, const double *r2, double r2scale, double *x, double *y,
                         const Ctl *ctl, hipStream_t s) {
-    if (part == 0) {
+    if (d.sparse && part == 0) {
+        hipLaunchKernelGGL(k_spmv_Au, dim3((d.m + kNT / 64 - 1) / (kNT / 64)), dim3(kNT), 0, s,
+                           (const int32_t *)d.sp_ptr, (const int32_t *)d.sp_col, (const double *)d.sp_val,
+                           (const double *)d.u, r2, r2scale, d.t, d.m, ctl);
+    } else if (d.sparse && part == 3) {
+        // A u already carries - r2scale r2
+    } else if (d.sparse && part == 2) {
+        if (d.ntc > 0)
+            hipLaunchKernelGGL(k_sp_xcorr, dim3(blocks_for(d.ntc)), dim3(kNT), 0, s, (const int32_t *)d.tc_e,
+                               (const int32_t *)d.tc_ptr, (const int32_t *)d.tc_row, (const double *)d.tc_val,
+                               (const double *)y, (const double *)d.u, (const double *)d.s2, x, d.ntc, ctl);
+    } else if (part == 0) {
         constexpr int RG = 8;
         const int ns = gemv_slices(d);
         const int64_t ncb = (d.ldU + 1023) / 1024;

@@ -4,7 +4,7 @@
 //
 //   M = A diag(w / D) A^T = Aw diag(s2) Aw^T     (Aw = w A, s2 = 1 / (w D)), FP64
 //   M = L L^T                                    (blocked right-looking Cholesky)
-//   L^-1 and L^-T                                (column-wise substitution)
+//   L^-1 and L^-T                                (blocked, 64-row block rows)
 //
 // The solve y = M^-1 t of each iteration is then two triangular matrix-vector
 // products with the cached inverse factor, which spreads over the whole GPU
@@ -188,27 +188,99 @@ __global__ __launch_bounds__(256) void k_syrk_update(double *__restrict__ M, int
         }
 }
 
-// Row j of L^-T (= column j of L^-1): solve L z = e_j, z_i = 0 for i < j.
-// One wave per j; z kept in LDS (dynamic, m doubles).
-__global__ __launch_bounds__(64) void k_trtri_cols(const double *__restrict__ L, int m,
-                                                   double *__restrict__ LinvT) {
-    extern __shared__ double z[];
-    const int j = blockIdx.x;
-    const int lane = threadIdx.x;
-    double *out = LinvT + (int64_t)j * m;
-    for (int i = lane; i < j; i += 64) out[i] = 0.0;
-    for (int i = j; i < m; ++i) {
-        const double *li = L + (int64_t)i * m;
-        double acc = 0.0;
-        for (int l = j + lane; l < i; l += 64) acc += li[l] * z[l];
+// Blocked triangular inverse X = L^-1, block row I at a time (64-row blocks):
+//   X_IC = L_II^-1 (delta_IC I - sum_{C <= K < I} L_IK X_KC),  C <= I.
+// One workgroup per column block C of the current block row; the sum is a
+// 64 x 64 tile product over the already finished block rows, the L_II^-1
+// application a forward substitution of 64 columns in parallel.
+__global__ __launch_bounds__(256) void k_trtri_blockrow(const double *__restrict__ L, int m, int I,
+                                                        double *__restrict__ X) {
+    constexpr int B = 64, KC = 16;
+    __shared__ double Ls[B][B + 1];  // L_II, later the right-hand sides
+    __shared__ double As[B][KC + 1];
+    __shared__ double Bs[KC][B + 1];
+    const int C = blockIdx.x;
+    const int r0 = I * B, c0 = C * B;
+    const int nr = min(B, m - r0), nc = min(B, m - c0);
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double acc[4][4];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-        const double zi = ((i == j ? 1.0 : 0.0) - acc) / li[i];
-        if (lane == 0) {
-            z[i] = zi;
-            out[i] = zi;
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    // S = sum over K in [C, I) of L_IK X_KC (columns k0 = C*B .. r0-1)
+    for (int k0 = c0; k0 < r0; k0 += KC) {
+        for (int idx = threadIdx.x; idx < B * KC; idx += 256) {
+            const int r = idx / KC, q = idx % KC;
+            As[r][q] = (r < nr) ? L[(int64_t)(r0 + r) * m + k0 + q] : 0.0;
+        }
+        for (int idx = threadIdx.x; idx < KC * B; idx += 256) {
+            const int q = idx / B, c = idx % B;
+            Bs[q][c] = (c < nc) ? X[(int64_t)(k0 + q) * m + c0 + c] : 0.0;
         }
         __syncthreads();
+#pragma unroll
+        for (int q = 0; q < KC; ++q) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = As[ty * 4 + a][q];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bv[b] = Bs[q][tx * 4 + b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+        }
+        __syncthreads();
+    }
+    // right-hand sides T = delta - S in Bs-sized scratch: reuse Ls after loading L_II below
+    __shared__ double T[B][B + 1];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int r = ty * 4 + a, c = tx * 4 + b;
+            T[r][c] = ((I == C && r == c) ? 1.0 : 0.0) - acc[a][b];
+        }
+    for (int idx = threadIdx.x; idx < B * B; idx += 256) {
+        const int r = idx / B, c = idx % B;
+        Ls[r][c] = (r < nr && c <= r) ? L[(int64_t)(r0 + r) * m + r0 + c] : (r == c ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    // forward substitution L_II Xcol = Tcol, one column per thread (64 columns)
+    if (threadIdx.x < B) {
+        const int c = threadIdx.x;
+        for (int r = 0; r < nr; ++r) {
+            double v = T[r][c];
+            for (int q = 0; q < r; ++q) v -= Ls[r][q] * T[q][c];
+            T[r][c] = v / Ls[r][r];
+        }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < B * B; idx += 256) {
+        const int r = idx / B, c = idx % B;
+        if (r < nr && c < nc) X[(int64_t)(r0 + r) * m + c0 + c] = (I == C && c > r) ? 0.0 : T[r][c];
+    }
+}
+
+// Sparse A: row i of M = sum over the coefficients (i, e) of row i and the
+// coefficients (i', e) of the same entry e of Aw_ie Aw_i'e s2_e.  One thread
+// owns row i (fixed summation order, no atomics).
+__global__ __launch_bounds__(256) void k_sp_syrk(const int32_t *__restrict__ sp_ptr,
+                                                 const int32_t *__restrict__ sp_col,
+                                                 const double *__restrict__ sp_val,
+                                                 const int32_t *__restrict__ tid,
+                                                 const int32_t *__restrict__ tc_ptr,
+                                                 const int32_t *__restrict__ tc_row,
+                                                 const double *__restrict__ tc_val,
+                                                 const double *__restrict__ s2, int m, double *__restrict__ M) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    double *row = M + (int64_t)i * m;
+    for (int32_t q = sp_ptr[i]; q < sp_ptr[i + 1]; ++q) {
+        const double a = sp_val[q] * s2[sp_col[q]];
+        const int32_t t = tid[q];
+        for (int32_t r = tc_ptr[t]; r < tc_ptr[t + 1]; ++r) row[tc_row[r]] += a * tc_val[r];
     }
 }
 
@@ -247,10 +319,21 @@ void launch_potrf(double *M, int m, double *diag0, int32_t *info, hipStream_t s)
     }
 }
 
+void launch_sp_syrk(const Dev &d, const int32_t *tid, double *M, hipStream_t s) {
+    (void)hipMemsetAsync(M, 0, (size_t)d.m * d.m * sizeof(double), s);
+    hipLaunchKernelGGL(k_sp_syrk, dim3((d.m + 255) / 256), dim3(256), 0, s, (const int32_t *)d.sp_ptr,
+                       (const int32_t *)d.sp_col, (const double *)d.sp_val, tid, (const int32_t *)d.tc_ptr,
+                       (const int32_t *)d.tc_row, (const double *)d.tc_val, (const double *)d.s2, d.m, M);
+}
+
 void launch_trtri(const double *L, int m, double *LinvT, double *Linv, hipStream_t s) {
-    hipLaunchKernelGGL(k_trtri_cols, dim3(m), dim3(64), (size_t)m * sizeof(double), s, L, m, LinvT);
-    hipLaunchKernelGGL(k_transpose, dim3((m + 31) / 32, (m + 31) / 32), dim3(32, 8), 0, s, (const double *)LinvT, m,
-                       Linv);
+    // Linv must be zero above the diagonal blocks: written block row by block row
+    (void)hipMemsetAsync(Linv, 0, (size_t)m * m * sizeof(double), s);
+    const int nb = (m + 63) / 64;
+    for (int I = 0; I < nb; ++I)
+        hipLaunchKernelGGL(k_trtri_blockrow, dim3(I + 1), dim3(256), 0, s, L, m, I, Linv);
+    hipLaunchKernelGGL(k_transpose, dim3((m + 31) / 32, (m + 31) / 32), dim3(32, 8), 0, s, (const double *)Linv, m,
+                       LinvT);
 }
 
 }  // namespace cdcs

@@ -228,6 +228,10 @@ def config_seed(config: int, instance: int = 0) -> int:
 C1 = dict(l=10, d=10, h=5, m=50)        # plain FP64 parity anchor, n = 105
 C2 = dict(l=200, d=20, h=10, m=2000)    # headline: n = 4010, 200 cliques of 30
 C5 = dict(l=100, d=16, h=8, m=800)      # differentiation workload
+# uneven batching: 3000 cliques of 4..96 vertices, separators of 1..8, sparse A
+C3 = dict(p=3000, smin=4, smax=96, omax=8, m=8000, nnz_row=20)
+# the same generator at a size the oracle solves in seconds
+C3_SMALL = dict(p=40, smin=4, smax=96, omax=8, m=150, nnz_row=20)
 
 
 def c1(instance: int = 0) -> Problem:
@@ -236,6 +240,14 @@ def c1(instance: int = 0) -> Problem:
 
 def c2(instance: int = 0) -> Problem:
     return block_arrow(seed=config_seed(2, instance), **C2)
+
+
+def c3(instance: int = 0) -> Problem:
+    return peo_chordal(seed=config_seed(3, instance), **C3)
+
+
+def c3_small(instance: int = 0) -> Problem:
+    return peo_chordal(seed=config_seed(3, 100 + instance), **C3_SMALL)
 
 
 def c5(instance: int = 0) -> Problem:
@@ -367,6 +379,66 @@ def small_chordal(n: int, p: int, smax: int, m: int, seed: int) -> Problem:
     ei, ej = _pattern_from_cliques(nv, cliques)
     A = _symmetrised_normal(rng, m, ei, ej)
     return _finish(nv, cliques, ei, ej, A, rng, m, meta={"kind": "small_chordal", "seed": seed})
+
+
+def _peo_cliques(p: int, smin: int, smax: int, omax: int, rng):
+    """Clique tree grown in perfect-elimination order: clique 0 has s_0 fresh
+    vertices; clique k > 0 draws s_k, a uniform parent j < k and a separator of
+    min(U{1..omax}, s_k - 1, s_j - 1) vertices of C_j, then adds s_k - |sep|
+    fresh vertices.  Every clique has a fresh vertex and no separator covers a
+    whole clique, so the cliques are the maximal cliques of the chordal union
+    (running-intersection property of a clique tree, Section II-B)."""
+    sizes = rng.integers(smin, smax + 1, size=p)
+    cliques, fresh_from, nv = [], [], 0
+    for k in range(p):
+        s = int(sizes[k])
+        if k == 0:
+            sep = np.empty(0, dtype=np.int64)
+        else:
+            par = cliques[int(rng.integers(0, k))]
+            o = min(int(rng.integers(1, omax + 1)), s - 1, par.shape[0] - 1)
+            sep = rng.choice(par, size=o, replace=False)
+        new = np.arange(nv, nv + s - sep.shape[0], dtype=np.int64)
+        nv += new.shape[0]
+        cliques.append(np.concatenate([sep, new]))
+        fresh_from.append(sep.shape[0])
+    return cliques, fresh_from, nv
+
+
+def peo_chordal(p: int, smin: int, smax: int, omax: int, m: int, nnz_row: int, seed: int,
+                gram_rank: int = 64) -> Problem:
+    """Random chordal SDP with uneven cliques (stand-in for the SDPLIB-like
+    uneven-clique workloads of Section V-B).  Pattern: union of C_k x C_k over
+    the clique tree of _peo_cliques, vertex labels randomly permuted.  Each A_i
+    has nnz_row distinct pattern entries chosen uniformly with N(0,1) values
+    (an off-diagonal entry stands for both mirrored positions), stored as CSR.
+    b = A(X0) with X0 = G G^T / r + I (G is n x r), C = A*(y0) + Z0."""
+    rng = _rng(seed)
+    cliques, fresh_from, nv = _peo_cliques(p, smin, smax, omax, rng)
+    perm = rng.permutation(nv).astype(np.int64)
+    # Entries of clique k not met before are the pairs with a fresh vertex.
+    ei_l, ej_l, sorted_cl = [], [], []
+    for cl, f in zip(cliques, fresh_from):
+        lab = perm[cl]
+        s = lab.shape[0]
+        ia, ib = np.tril_indices(s)
+        keep = ia >= f  # local index a is fresh (fresh vertices come last)
+        va, vb = lab[ia[keep]], lab[ib[keep]]
+        ei_l.append(np.maximum(va, vb))
+        ej_l.append(np.minimum(va, vb))
+        sorted_cl.append(np.sort(lab).astype(np.int32))
+    ei = np.concatenate(ei_l).astype(np.int32)
+    ej = np.concatenate(ej_l).astype(np.int32)
+    nU = ei.shape[0]
+    ptr = np.arange(m + 1, dtype=np.int64) * nnz_row
+    idx = np.empty(m * nnz_row, dtype=np.int32)
+    for i in range(m):
+        idx[i * nnz_row:(i + 1) * nnz_row] = np.sort(rng.choice(nU, size=nnz_row, replace=False))
+    val = _f32(rng.standard_normal(m * nnz_row))
+    return _finish(nv, sorted_cl, ei, ej, None, rng, m, gram_rank=gram_rank,
+                   meta={"kind": "peo_chordal", "p": p, "smin": smin, "smax": smax, "omax": omax,
+                         "nnz_row": nnz_row, "seed": seed},
+                   A_sparse=(ptr, idx, val))
 
 
 def unit_directions(dim: int, count: int, seed: int) -> np.ndarray:
