@@ -308,6 +308,40 @@ typedef enum {
 cdcs_status cdcs_profile_kernel(cdcs_handle *h, const cdcs_state *st, int32_t form, double rho,
                                 int32_t kernel, int32_t reps, hipStream_t stream);
 
+/*
+ * Launch plan of the batched projection inside the ADMM loop ("thousands of
+ * cliques of uneven sizes" in one step, Sec. III-B.2): cliques are padded to
+ * size buckets S in {16, 32, 48, 64, 80, 96}.  Either one persistent launch
+ * draws every clique, largest first, from a device work queue
+ * (persistent = 1, `threads` per workgroup, `grid` workgroups), or each
+ * bucket gets its own launch with its own workgroup size (persistent = 0).
+ * Setup picks the faster form by timing both on the handle's cliques
+ * (queue_us, buckets_us: microseconds per projection of all cliques on
+ * generated nearly diagonal blocks).
+ */
+typedef struct {
+    int32_t persistent;
+    int32_t threads;
+    int32_t grid;
+    int32_t nbuckets;
+    int32_t bucket_size[8];
+    int32_t bucket_threads[8];
+    int32_t bucket_count[8];
+    float queue_us;
+    float buckets_us;
+} cdcs_tuning;
+
+cdcs_status cdcs_get_tuning(const cdcs_handle *h, cdcs_tuning *out);
+
+/*
+ * Override the tuned plan: persistent = 1 with threads 256 or 512, or
+ * persistent = 0 with threads 64, 256 or 512 for every bucket that has that
+ * size built (others keep 256), or 0 to keep the tuned per-bucket sizes.
+ * Synchronizes the device and drops captured graphs.  Errors: CDCS_E_ARG,
+ * CDCS_E_DEVICE.
+ */
+cdcs_status cdcs_set_projection_plan(cdcs_handle *h, int32_t persistent, int32_t threads);
+
 /* Residual history of the last solve: n_host pairs (eps_p, eps_d), host. */
 cdcs_status cdcs_residual_history(const cdcs_handle *h, double *hist_host, int32_t n_host);
 

@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "CDCS_OK", 1: "CDCS_E_ARG", 2: "CDCS_E_PATTERN", 3: "CDCS_E_R
 # Every symbol include/cdcs.h declares.
 EXPORTS = ["cdcs_setup", "cdcs_setup_batch", "cdcs_batch_info", "cdcs_get_sizes", "cdcs_clique_offsets", "cdcs_psd_project_batched",
            "cdcs_psd_project_vjp", "cdcs_gather", "cdcs_scatter", "cdcs_affine_project", "cdcs_admm_solve",
-           "cdcs_admm_step", "cdcs_profile_kernel", "cdcs_residual_history", "cdcs_destroy", "cdcs_last_error"]
+           "cdcs_admm_step", "cdcs_profile_kernel", "cdcs_get_tuning", "cdcs_set_projection_plan",
+           "cdcs_residual_history", "cdcs_destroy", "cdcs_last_error"]
 
 
 class CdcsLibraryMissing(ImportError):
@@ -80,6 +81,13 @@ class _InstanceInfo(ctypes.Structure):
                 ("time_to_tol_s", ctypes.c_double)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("persistent", ctypes.c_int32), ("threads", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("nbuckets", ctypes.c_int32), ("bucket_size", ctypes.c_int32 * 8),
+                ("bucket_threads", ctypes.c_int32 * 8), ("bucket_count", ctypes.c_int32 * 8),
+                ("queue_us", ctypes.c_float), ("buckets_us", ctypes.c_float)]
+
+
 class _Sizes(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("p", ctypes.c_int32), ("smax", ctypes.c_int32),
                 ("nnz", ctypes.c_int64), ("nslots", ctypes.c_int64), ("sparse_a", ctypes.c_int32),
@@ -103,6 +111,8 @@ def load_library(path: str = LIB_PATH):
     L.cdcs_setup_batch.argtypes = [i32, P(_Problem), vp, vp, P(vp)]
     L.cdcs_batch_info.argtypes = [vp, i32, P(_InstanceInfo)]
     L.cdcs_get_sizes.argtypes = [vp, P(_Sizes)]
+    L.cdcs_get_tuning.argtypes = [vp, P(_Tuning)]
+    L.cdcs_set_projection_plan.argtypes = [vp, i32, i32]
     L.cdcs_clique_offsets.argtypes = [vp, vp]
     L.cdcs_psd_project_batched.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.cdcs_psd_project_vjp.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -269,6 +279,21 @@ class Solver:
         _check(load_library().cdcs_profile_kernel(self._h, ctypes.byref(cs), PRIMAL if form == "primal" else DUAL,
                                                    float(rho), int(kernel), int(reps), _stream(self._torch, stream)),
                "cdcs_profile_kernel")
+
+    def tuning(self) -> dict:
+        """The projection launch plan chosen at setup (cdcs_get_tuning)."""
+        t = _Tuning()
+        _check(load_library().cdcs_get_tuning(self._h, ctypes.byref(t)), "cdcs_get_tuning")
+        nb = t.nbuckets
+        return {"persistent": bool(t.persistent), "threads": t.threads, "grid": t.grid,
+                "buckets": [{"size": t.bucket_size[q], "threads": t.bucket_threads[q], "count": t.bucket_count[q]}
+                            for q in range(nb)],
+                "queue_us": t.queue_us, "buckets_us": t.buckets_us}
+
+    def set_projection_plan(self, persistent: bool, threads: int = 0):
+        """Override the tuned plan (cdcs_set_projection_plan)."""
+        _check(load_library().cdcs_set_projection_plan(self._h, int(bool(persistent)), int(threads)),
+               "cdcs_set_projection_plan")
 
     def history(self, n: int) -> np.ndarray:
         out = np.zeros((n, 2))

@@ -35,8 +35,6 @@ cdcs_status fail(cdcs_status st, const std::string &msg) {
 
 int64_t round_up(int64_t v, int64_t q) { return (v + q - 1) / q * q; }
 
-// Threads per workgroup of the projection kernel for a size bucket.
-int proj_threads(int smax) { (void)smax; return 256; }
 
 struct GraphKey {
     int form;
@@ -52,6 +50,17 @@ struct Bucket {
     int smax;
     int count;
     int32_t *ids;  // device
+    int nt = 256;  // workgroup size (autotuned)
+};
+
+// How the projection of every clique is launched: one persistent queue launch
+// over all cliques, or one launch per size bucket.  Chosen at setup by timing
+// the candidates on this handle's cliques.
+struct ProjPlan {
+    bool queue = false;
+    int nt = 256;      // queue workgroup size
+    int grid = 0;      // queue workgroups
+    float queue_us = -1.0f, buckets_us = -1.0f;
 };
 
 }  // namespace
@@ -62,6 +71,8 @@ struct cdcs_handle {
     std::vector<void *> allocs;
     std::vector<int64_t> off_host;
     std::vector<Bucket> buckets;
+    ProjPlan plan;
+    unsigned long long *ticket = nullptr;  // device counter of the queue launch
     hipStream_t cap_stream = nullptr;
     std::map<GraphKey, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_defs;
@@ -97,6 +108,8 @@ namespace {
         cdcs_status s_ = (expr);          \
         if (s_ != CDCS_OK) return s_;     \
     } while (0)
+
+cdcs_status tune_projection(cdcs_handle *h, hipStream_t s);
 
 template <typename T>
 cdcs_status upload(cdcs_handle *h, T **dst, const std::vector<T> &src, hipStream_t s) {
@@ -297,8 +310,8 @@ cdcs_status upload_common(cdcs_handle *h, const std::vector<int32_t> &size, cons
     for (int32_t k = 0; k < p; ++k) order[(size_t)k] = k;
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t bq) { return size[(size_t)a] > size[(size_t)bq]; });
-    constexpr int NBK = 5;
-    const int bmax[NBK] = {16, 32, 48, 64, 96};
+    constexpr int NBK = 6;
+    const int bmax[NBK] = {16, 32, 48, 64, 80, 96};
     std::vector<std::vector<int32_t>> bl(NBK);
     for (int32_t k : order) {
         const int S = proj_bucket(size[(size_t)k]);
@@ -341,6 +354,8 @@ cdcs_status upload_common(cdcs_handle *h, const std::vector<int32_t> &size, cons
     CK(h->alloc(&d.info, 4));
     HIP_OK(hipMemsetAsync(d.info, 0, 4 * sizeof(int32_t), s));
     CK(h->alloc(&d.ctl, 1));
+    CK(h->alloc(&h->ticket, 1));
+    HIP_OK(hipMemsetAsync(h->ticket, 0, sizeof(unsigned long long), s));
     HIP_OK(hipHostMalloc((void **)&d.ctl_host, sizeof(Ctl), hipHostMallocDefault));
     d.hist_cap = 0;
     return CDCS_OK;
@@ -442,6 +457,7 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
     if (info_h[0] != 0)
         return fail(CDCS_E_RANK,
                     "A D^-1 A^T is not positive definite (pivot " + std::to_string(info_h[1]) + "): A is rank deficient");
+    CK(tune_projection(h, s));
     HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     return CDCS_OK;
 }
@@ -571,33 +587,154 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
         if (finfo[(size_t)q] != 0)
             return fail(CDCS_E_RANK, "problem " + std::to_string(q) + ": A D^-1 A^T is not positive definite (pivot " +
                                          std::to_string(finfo[(size_t)q] - 1) + ")");
+    CK(tune_projection(h, s));
     HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     return CDCS_OK;
 }
 
-void launch_projection(cdcs_handle *h, int mode, const cdcs_state *st, double rho, hipStream_t s) {
-    Dev &d = h->d;
-    for (const Bucket &bk : h->buckets) {
-        ProjArgs a{};
-        a.mode = mode;
-        a.nblk = bk.count;
-        a.ids = bk.ids;
-        a.size = d.clq_size;
-        a.off = d.clq_off;
-        a.gather = d.gather;
+ProjArgs proj_args(const cdcs_handle *h, int mode, const cdcs_state *st, double rho) {
+    const Dev &d = h->d;
+    ProjArgs a{};
+    a.mode = mode;
+    a.size = d.clq_size;
+    a.off = d.clq_off;
+    a.gather = d.gather;
+    if (st) {
         a.x = st->x;
         a.blk = st->blk;
         a.lam = st->lam;
         a.v = st->v;
-        a.rho = rho;
-        a.kinst = d.batch ? d.batch->kinst : nullptr;
-        a.istop = d.batch ? d.batch->istop : nullptr;
-        a.vwarm = d.vwarm;
-        a.vwoff = d.vwoff;
-        a.cpart = d.cpart;
-        a.ctl = d.ctl;
-        launch_project(a, bk.smax, proj_threads(bk.smax), s);
     }
+    a.rho = rho;
+    a.kinst = d.batch ? d.batch->kinst : nullptr;
+    a.istop = d.batch ? d.batch->istop : nullptr;
+    a.vwarm = d.vwarm;
+    a.vwoff = d.vwoff;
+    a.warm_store = 1;
+    a.cpart = d.cpart;
+    a.ctl = d.ctl;
+    return a;
+}
+
+// The projection of every clique with the handle's plan.
+void launch_plan(cdcs_handle *h, ProjArgs a, hipStream_t s) {
+    const Dev &d = h->d;
+    if (h->plan.queue) {
+        a.nblk = d.p;
+        a.ids = d.order;
+        launch_project_queue(a, d.smax, h->plan.nt, h->plan.grid, h->ticket, s);
+        return;
+    }
+    for (const Bucket &bk : h->buckets) {
+        a.nblk = bk.count;
+        a.ids = bk.ids;
+        launch_project(a, bk.smax, bk.nt, s);
+    }
+}
+
+void launch_projection(cdcs_handle *h, int mode, const cdcs_state *st, double rho, hipStream_t s) {
+    launch_plan(h, proj_args(h, mode, st, rho), s);
+}
+
+int device_cus(cdcs_handle *h) {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || ncu < 1)
+        ncu = 256;
+    return ncu;
+}
+
+int queue_grid(cdcs_handle *h, int nt) {
+    const int occ = project_queue_occupancy(h->d.smax, nt);
+    return occ < 1 ? 0 : std::min(h->d.p, occ * device_cus(h));
+}
+
+// Autotuner: time every candidate launch form of the projection on this
+// handle's cliques (generated nearly diagonal blocks, warm-start products on,
+// outputs to scratch) and keep the fastest: per size bucket the best
+// workgroup size, against the persistent queue launch at 256 or 512 threads.
+cdcs_status tune_projection(cdcs_handle *h, hipStream_t s) {
+    Dev &d = h->d;
+    float *W = nullptr, *P = nullptr, *Vt = nullptr;
+    int64_t vtot = 0;
+    HIP_OK(hipMemcpy(&vtot, d.vwoff + d.p, sizeof(int64_t), hipMemcpyDeviceToHost));
+    HIP_OK(hipMalloc(&W, (size_t)std::max<int64_t>(d.nslots, 1) * sizeof(float)));
+    hipError_t e = hipMalloc(&P, (size_t)std::max<int64_t>(d.nslots, 1) * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&Vt, (size_t)std::max<int64_t>(vtot, 1) * sizeof(float));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    auto cleanup = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipFree(W);
+        (void)hipFree(P);
+        (void)hipFree(Vt);
+    };
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(CDCS_E_NOMEM, "autotuner scratch");
+    }
+    launch_tune_blocks(d.clq_size, d.clq_off, d.p, W, s);
+    launch_identity_blocks(d.clq_size, d.vwoff, d.p, Vt, s);
+    ProjArgs a = proj_args(h, PROJ_STANDALONE, nullptr, 1.0);
+    a.Win = W;
+    a.Pout = P;
+    a.vwarm = Vt;
+    a.warm_store = 0;
+    a.kinst = nullptr;
+    a.istop = nullptr;
+    a.ctl = nullptr;
+    constexpr int REPS = 3;
+    auto time_us = [&](auto &&launch) -> float {
+        launch();  // warm
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < REPS; ++r) launch();
+        (void)hipEventRecord(e1, s);
+        float ms = -1.0f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return 1e30f;
+        return ms * 1e3f / REPS;
+    };
+    // per-bucket launches
+    float bsum = 0.0f;
+    for (Bucket &bk : h->buckets) {
+        float best = 1e30f;
+        for (int nt : {64, 256, 512}) {
+            if (!proj_threads_ok(proj_bucket(bk.smax), nt)) continue;
+            ProjArgs b = a;
+            b.nblk = bk.count;
+            b.ids = bk.ids;
+            const float us = time_us([&]() { launch_project(b, bk.smax, nt, s); });
+            if (us < best) {
+                best = us;
+                bk.nt = nt;
+            }
+        }
+        bsum += best;
+    }
+    h->plan.buckets_us = bsum;
+    // persistent queue launch
+    float qbest = 1e30f;
+    for (int nt : {256, 512}) {
+        const int grid = queue_grid(h, nt);
+        if (grid < 1) continue;
+        HIP_OK(hipMemsetAsync(h->ticket, 0, sizeof(unsigned long long), s));
+        ProjArgs b = a;
+        b.nblk = d.p;
+        b.ids = d.order;
+        const float us = time_us([&]() { launch_project_queue(b, d.smax, nt, grid, h->ticket, s); });
+        if (us < qbest) {
+            qbest = us;
+            h->plan.nt = nt;
+            h->plan.grid = grid;
+        }
+    }
+    h->plan.queue_us = qbest < 1e29f ? qbest : -1.0f;
+    h->plan.queue = qbest < bsum;
+    HIP_OK(hipMemsetAsync(h->ticket, 0, sizeof(unsigned long long), s));
+    e = hipStreamSynchronize(s);
+    cleanup();
+    if (e != hipSuccess) return fail(CDCS_E_DEVICE, std::string("autotuner: ") + hipGetErrorString(e));
+    return CDCS_OK;
 }
 
 void enqueue_iteration(cdcs_handle *h, const cdcs_state *st, int form, double rho, hipStream_t s) {
@@ -768,8 +905,7 @@ cdcs_status cdcs_psd_project_batched(int32_t nb, int32_t smax, const int32_t *si
     a.eoff = eoff;
     a.evecs = evecs;
     a.voff = voff;
-    const int bucket = proj_bucket(smax);
-    launch_project(a, bucket, proj_threads(bucket), stream);
+    launch_project(a, proj_bucket(smax), 256, stream);
     HIP_OK(hipGetLastError());
     return CDCS_OK;
 }
@@ -977,6 +1113,49 @@ cdcs_status cdcs_profile_kernel(cdcs_handle *h, const cdcs_state *st, int32_t fo
         }
     }
     HIP_OK(hipGetLastError());
+    return CDCS_OK;
+}
+
+cdcs_status cdcs_get_tuning(const cdcs_handle *h, cdcs_tuning *out) {
+    if (!h || !out) return fail(CDCS_E_ARG, "NULL argument");
+    std::memset(out, 0, sizeof(*out));
+    out->persistent = h->plan.queue ? 1 : 0;
+    out->threads = h->plan.nt;
+    out->grid = h->plan.grid;
+    out->nbuckets = (int32_t)std::min<size_t>(h->buckets.size(), 8);
+    for (int q = 0; q < out->nbuckets; ++q) {
+        out->bucket_size[q] = h->buckets[(size_t)q].smax;
+        out->bucket_threads[q] = h->buckets[(size_t)q].nt;
+        out->bucket_count[q] = h->buckets[(size_t)q].count;
+    }
+    out->queue_us = h->plan.queue_us;
+    out->buckets_us = h->plan.buckets_us;
+    return CDCS_OK;
+}
+
+cdcs_status cdcs_set_projection_plan(cdcs_handle *h, int32_t persistent, int32_t threads) {
+    if (!h) return fail(CDCS_E_ARG, "NULL handle");
+    if (persistent != 0 && persistent != 1) return fail(CDCS_E_ARG, "persistent must be 0 or 1");
+    if (persistent) {
+        if (threads != 256 && threads != 512) return fail(CDCS_E_ARG, "queue launches use 256 or 512 threads");
+        const int grid = queue_grid(h, threads);
+        if (grid < 1) return fail(CDCS_E_DEVICE, "queue kernel does not fit on a CU");
+        HIP_OK(hipDeviceSynchronize());
+        HIP_OK(hipMemset(h->ticket, 0, sizeof(unsigned long long)));
+        h->plan.queue = true;
+        h->plan.nt = threads;
+        h->plan.grid = grid;
+    } else {
+        if (threads != 0 && threads != 64 && threads != 256 && threads != 512)
+            return fail(CDCS_E_ARG, "threads must be 0, 64, 256 or 512");
+        h->plan.queue = false;
+        if (threads != 0)
+            for (Bucket &bk : h->buckets) bk.nt = proj_threads_ok(proj_bucket(bk.smax), threads) ? threads : 256;
+    }
+    // captured graphs hold the old launches
+    HIP_OK(hipDeviceSynchronize());
+    for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
     return CDCS_OK;
 }
 

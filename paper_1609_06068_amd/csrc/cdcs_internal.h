@@ -56,15 +56,26 @@ struct ProjArgs {
     double rho;
     const int32_t *kinst;      // [*] instance of each block (many-SDP handles), or NULL
     const int32_t *istop;      // [nprob] per-instance stop flags, or NULL
-    float *vwarm;              // eigenvector warm start (ADMM modes), NULL: cold
+    float *vwarm;              // eigenvector warm start, NULL: cold
     const int64_t *vwoff;      // [*] offsets of the k x k blocks in vwarm
+    int32_t warm_store;        // write the new eigenvectors back to vwarm
     double *cpart;             // [p][4] per-block partial sums
     Ctl *ctl;                  // may be NULL (standalone)
 };
 
-// Size bucket (padded clique size) of the projection kernel for cliques <= smax.
+// Size bucket (padded clique size) of the projection kernel for cliques <= smax:
+// 16, 32, 48, 64, 80 or 96.
 int proj_bucket(int smax);
+// Workgroup sizes built for a bucket: 64 (S <= 48), 256, 512 (S >= 48).
+bool proj_threads_ok(int S, int nthreads);
+// One launch over a.nblk cliques of one bucket (workgroup b: clique a.ids[b]).
 void launch_project(const ProjArgs &a, int smax, int nthreads, hipStream_t s);
+// Persistent launch over a.nblk cliques of every bucket up to smax, drawn in
+// a.ids order from the ticket counter (nthreads 256 or 512).
+void launch_project_queue(const ProjArgs &a, int smax, int nthreads, int grid, unsigned long long *ticket,
+                          hipStream_t s);
+// Resident workgroups per CU of the persistent launch.
+int project_queue_occupancy(int smax, int nthreads);
 
 // Arguments of the projection adjoint (Daleckii-Krein) kernel.
 struct VjpArgs {
@@ -79,6 +90,8 @@ struct VjpArgs {
     float *gW;                 // packed cotangent of W
 };
 void launch_project_vjp(const VjpArgs &a, int smax, hipStream_t s);
+// Autotuning input: nearly diagonal symmetric packed blocks (see the kernel).
+void launch_tune_blocks(const int32_t *size, const int64_t *off, int p, float *W, hipStream_t s);
 // Set every k x k block of V (at voff[k]) to the identity.
 void launch_identity_blocks(const int32_t *size, const int64_t *voff, int p, float *V, hipStream_t s);
 

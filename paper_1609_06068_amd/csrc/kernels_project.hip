@@ -95,64 +95,81 @@ __device__ __forceinline__ void pair_at(int t, int r, int &P, int &Q) {
     Q = max(a, b);
 }
 
-// Register-tiled S x S products on a G x G thread grid (tile T = S / G):
+// Register-tiled S x S products on a GR x GC thread grid (GR = 16 rows of
+// threads, GC = NT / 16 columns): thread (ti, tj) owns rows ti*TR .. +TR and
+// columns tj*TC .. +TC of the result (TR = S / 16, TC = ceil(S / GC); columns
+// past S are computed from clamped loads and never stored).
+template <int S, int NT>
+struct Tiles {
+    static constexpr int GR = 16, GC = NT / 16;
+    static constexpr int TR = S / GR, TC = (S + GC - 1) / GC;
+};
+
 // mode 0: C = X^T Y   (C[i][j] = sum_q X[q][i] Y[q][j])
 // mode 1: C = X Y     (C[i][j] = sum_q X[i][q] Y[q][j])
 // mode 2: C = X Y^T   (C[i][j] = sum_q X[i][q] Y[j][q])
-template <int S, int G, int MODE>
-__device__ __forceinline__ void tile_product(const float *X, const float *Y, float (&acc)[S / G][S / G], int ti,
-                                             int tj) {
-    constexpr int LD = S + 1, T = S / G;
+template <int S, int NT, int MODE>
+__device__ __forceinline__ void tile_product(const float *X, const float *Y,
+                                             float (&acc)[Tiles<S, NT>::TR][Tiles<S, NT>::TC], int ti, int tj) {
+    constexpr int LD = S + 1, TR = Tiles<S, NT>::TR, TC = Tiles<S, NT>::TC;
 #pragma unroll
-    for (int u = 0; u < T; ++u)
+    for (int u = 0; u < TR; ++u)
 #pragma unroll
-        for (int v = 0; v < T; ++v) acc[u][v] = 0.0f;
+        for (int v = 0; v < TC; ++v) acc[u][v] = 0.0f;
+#pragma unroll 4
     for (int q = 0; q < S; ++q) {
-        float xa[T], yb[T];
+        float xa[TR], yb[TC];
 #pragma unroll
-        for (int u = 0; u < T; ++u) xa[u] = MODE == 0 ? X[q * LD + ti * T + u] : X[(ti * T + u) * LD + q];
+        for (int u = 0; u < TR; ++u) xa[u] = MODE == 0 ? X[q * LD + ti * TR + u] : X[(ti * TR + u) * LD + q];
 #pragma unroll
-        for (int v = 0; v < T; ++v) yb[v] = MODE == 2 ? Y[(tj * T + v) * LD + q] : Y[q * LD + tj * T + v];
+        for (int v = 0; v < TC; ++v) {
+            const int j = min(tj * TC + v, S - 1);
+            yb[v] = MODE == 2 ? Y[j * LD + q] : Y[q * LD + j];
+        }
 #pragma unroll
-        for (int u = 0; u < T; ++u)
+        for (int u = 0; u < TR; ++u)
 #pragma unroll
-            for (int v = 0; v < T; ++v) acc[u][v] += xa[u] * yb[v];
+            for (int v = 0; v < TC; ++v) acc[u][v] += xa[u] * yb[v];
     }
 }
 
-template <int S, int NT>
-__global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
-    static_assert(S % 16 == 0 && S <= 96, "bucket size");
-    static_assert(NT == 64 || NT == 256, "thread grid is 8x8 or 16x16");
-    constexpr int H = S / 2;                 // pairs per step
-    constexpr int LD = S + 1;                // odd row stride
-    constexpr int NSTEP = S - 1;             // steps per sweep
-    constexpr int NBLK = H * (H + 1) / 2;    // lower 2x2 blocks (I >= J)
-    constexpr int NA = (NBLK + NT - 1) / NT; // A blocks per thread
-    constexpr int NV = (S * H + NT - 1) / NT;  // V row pairs per thread
-    constexpr int G = (NT == 64) ? 8 : 16;   // thread grid of the tiled products
-    constexpr int T = S / G;                 // tile edge
-    __shared__ float sA[S * LD];
-    __shared__ float sV[S * LD];
-    __shared__ float sX[S * LD];
-    __shared__ float sC[H], sS[H], sT[H];
-    __shared__ float sLam[S], sLp[S];
-    __shared__ float redf[NT / 64];
-    __shared__ double redd[NT / 64];
+// Small per-workgroup LDS of the projection (sized for the largest bucket).
+struct ProjSmall {
+    float c[48], s[48], t[48];   // rotations of one step
+    float lam[96], lp[96];       // eigenvalues, clamped eigenvalues
+    float redf[8];
+    double redd[8];
+    int zero;                    // 0; read as volatile (see project_one)
+};
 
-    if (a.ctl != nullptr && a.ctl->stop) return;
-    const int bi = blockIdx.x;
-    if (bi >= a.nblk) return;
-    const int id = a.ids ? a.ids[bi] : bi;
+// Projection of clique `id` by one workgroup of NT threads, cliques padded to
+// S.  sA and sV are S x (S+1) FP32 LDS arrays.
+template <int S, int NT>
+__device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__restrict__ sA,
+                                            float *__restrict__ sV, ProjSmall &sm) {
+    static_assert(S % 16 == 0 && S <= 96, "bucket size");
+    static_assert(NT == 64 || NT == 256 || NT == 512, "workgroup size");
+    using TL = Tiles<S, NT>;
+    constexpr int TR = TL::TR, TC = TL::TC, GC = TL::GC;
+    constexpr int H = S / 2;                   // pairs per step
+    constexpr int LD = S + 1;                  // odd row stride
+    constexpr int NSTEP = S - 1;               // steps per sweep
+    constexpr int NBLK = H * (H + 1) / 2;      // lower 2x2 blocks (I >= J)
+    constexpr int NA = (NBLK + NT - 1) / NT;   // A blocks per thread
+    constexpr int NV = (S * H + NT - 1) / NT;  // V row pairs per thread
+
     if (a.istop != nullptr && a.istop[a.kinst[id]]) return;  // instance already stopped
     const int k = a.size[id];
     if (k < 1 || k > S) return;
     const int64_t off = a.off[id];
     const int nslot = k * (k + 1) / 2;
-    const int tid = threadIdx.x;
-    const bool warm = (a.mode != PROJ_STANDALONE) && (a.vwarm != nullptr);
+    // The thread index goes through a volatile LDS zero so that the compiler
+    // cannot hoist the per-thread work tables out of a queue launch's clique
+    // loop (which would keep them live across all cliques and buckets).
+    const int tid = threadIdx.x + *(volatile int *)&sm.zero;
+    const bool warm = a.vwarm != nullptr;
     float *vw = warm ? a.vwarm + a.vwoff[id] : nullptr;
-    const int ti = tid / G, tj = tid % G;
+    const int ti = tid / GC, tj = tid % GC;
 
     for (int idx = tid; idx < S * S; idx += NT) {
         const int i = idx / S, j = idx % S;
@@ -182,7 +199,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
     }
     // Scale by a power of two (exact) so that max |w| lies in [1, 2): squares
     // neither overflow nor underflow for any finite FP32 input.
-    amax = block_max<NT>(amax, redf);
+    amax = block_max<NT>(amax, sm.redf);
     const int ex = (amax > 0.0f && isfinite(amax)) ? ilogbf(amax) : 0;
     const float scale = ldexpf(1.0f, -ex), unscale = ldexpf(1.0f, ex);
     float fro = 0.0f;
@@ -193,24 +210,28 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
         sA[j * LD + i] = w;
         fro += (i == j ? 1.0f : 2.0f) * w * w;
     }
-    const float fro2 = block_sum<NT>(fro, redf);
+    const float fro2 = block_sum<NT>(fro, sm.redf);
     const float thr = kEps * kEps * fro2;
 
+    float acc[TR][TC];
     if (warm) {
-        // A <- V^T W V, symmetrised (V = V_prev, orthonormal to FP32 accuracy)
-        float acc[T][T];
-        tile_product<S, G, 1>(sA, sV, acc, ti, tj);  // W V
-#pragma unroll
-        for (int u = 0; u < T; ++u)
-#pragma unroll
-            for (int v = 0; v < T; ++v) sX[(ti * T + u) * LD + tj * T + v] = acc[u][v];
-        __syncthreads();
-        tile_product<S, G, 0>(sV, sX, acc, ti, tj);  // V^T (W V)
+        // A <- V^T W V, symmetrised (V = V_prev, orthonormal to FP32 accuracy).
+        // Each product finishes reading before its result overwrites sA.
+        tile_product<S, NT, 1>(sA, sV, acc, ti, tj);  // W V
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < T; ++u)
+        for (int u = 0; u < TR; ++u)
 #pragma unroll
-            for (int v = 0; v < T; ++v) sA[(ti * T + u) * LD + tj * T + v] = acc[u][v];
+            for (int v = 0; v < TC; ++v)
+                if (tj * TC + v < S) sA[(ti * TR + u) * LD + tj * TC + v] = acc[u][v];
+        __syncthreads();
+        tile_product<S, NT, 0>(sV, sA, acc, ti, tj);  // V^T (W V)
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < TR; ++u)
+#pragma unroll
+            for (int v = 0; v < TC; ++v)
+                if (tj * TC + v < S) sA[(ti * TR + u) * LD + tj * TC + v] = acc[u][v];
         __syncthreads();
         for (int idx = tid; idx < S * S; idx += NT) {
             const int i = idx / S, j = idx % S;
@@ -248,12 +269,13 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
             const float v = sA[i * LD + j];
             o += (i != j) ? v * v : 0.0f;
         }
-        const float off2 = block_sum<NT>(o, redf);
+        const float off2 = block_sum<NT>(o, sm.redf);
         if (off2 <= thr) break;
         if (sweep >= kMaxSweeps) {
             if (tid == 0 && a.ctl != nullptr) atomicAdd(&a.ctl->jacobi_cap, 1);
             break;
         }
+#pragma unroll 1
         for (int r = 0; r < NSTEP; ++r) {
             if (tid < H) {
                 int P, Q;
@@ -269,9 +291,9 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
                     s = t * c;
                     ta = t * apq;
                 }
-                sC[tid] = c;
-                sS[tid] = s;
-                sT[tid] = ta;
+                sm.c[tid] = c;
+                sm.s[tid] = s;
+                sm.t[tid] = ta;
             }
             __syncthreads();
             // A <- J^T A J on this thread's lower 2x2 blocks (rows of pair I,
@@ -283,7 +305,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
                 int p1, q1;
                 pair_at<S>(I, r, p1, q1);
                 if (I == J) {
-                    const float ta = sT[I];
+                    const float ta = sm.t[I];
                     sA[p1 * LD + p1] -= ta;
                     sA[q1 * LD + q1] += ta;
                     sA[p1 * LD + q1] = 0.0f;
@@ -291,7 +313,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
                 } else {
                     int p2, q2;
                     pair_at<S>(J, r, p2, q2);
-                    const float c1 = sC[I], s1 = sS[I], c2 = sC[J], s2 = sS[J];
+                    const float c1 = sm.c[I], s1 = sm.s[I], c2 = sm.c[J], s2 = sm.s[J];
                     const float a00 = sA[p1 * LD + p2], a01 = sA[p1 * LD + q2];
                     const float a10 = sA[q1 * LD + p2], a11 = sA[q1 * LD + q2];
                     const float b00 = c1 * a00 - s1 * a10, b01 = c1 * a01 - s1 * a11;
@@ -315,7 +337,7 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
                 if (row < 0) continue;
                 int p2, q2;
                 pair_at<S>(J, r, p2, q2);
-                const float c2 = sC[J], s2 = sS[J];
+                const float c2 = sm.c[J], s2 = sm.s[J];
                 const float vp = sV[row * LD + p2], vq = sV[row * LD + q2];
                 sV[row * LD + p2] = c2 * vp - s2 * vq;
                 sV[row * LD + q2] = s2 * vp + c2 * vq;
@@ -327,69 +349,68 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
 
     if (tid < S) {
         const float l = sA[tid * LD + tid] * unscale;
-        sLam[tid] = l;
-        sLp[tid] = fmaxf(l, 0.0f);
+        sm.lam[tid] = l;
+        sm.lp[tid] = fmaxf(l, 0.0f);
     }
-    {
-        // E = V^T V - I  -> sX
-        float acc[T][T];
-        tile_product<S, G, 0>(sV, sV, acc, ti, tj);
-#pragma unroll
-        for (int u = 0; u < T; ++u)
-#pragma unroll
-            for (int v = 0; v < T; ++v)
-                sX[(ti * T + u) * LD + tj * T + v] = acc[u][v] - ((ti * T + u) == (tj * T + v) ? 1.0f : 0.0f);
-    }
+    // E = V^T V - I  -> sA (A's eigenvalues are in sm.lam)
+    tile_product<S, NT, 0>(sV, sV, acc, ti, tj);
     __syncthreads();
-    {
-        // Vn = V - V E / 2  -> sA
-        float acc[T][T];
-        tile_product<S, G, 1>(sV, sX, acc, ti, tj);
 #pragma unroll
-        for (int u = 0; u < T; ++u)
+    for (int u = 0; u < TR; ++u)
 #pragma unroll
-            for (int v = 0; v < T; ++v) {
-                const int i = ti * T + u, j = tj * T + v;
-                sA[i * LD + j] = sV[i * LD + j] - 0.5f * acc[u][v];
-            }
-    }
+        for (int v = 0; v < TC; ++v) {
+            const int i = ti * TR + u, j = tj * TC + v;
+            if (j < S) sA[i * LD + j] = acc[u][v] - (i == j ? 1.0f : 0.0f);
+        }
     __syncthreads();
+    // Vn = V - V E / 2  -> sV (every thread has read V before any writes)
+    tile_product<S, NT, 1>(sV, sA, acc, ti, tj);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < TR; ++u)
+#pragma unroll
+        for (int v = 0; v < TC; ++v) {
+            const int i = ti * TR + u, j = tj * TC + v;
+            if (j < S) sV[i * LD + j] -= 0.5f * acc[u][v];
+        }
+    __syncthreads();
+    // P = Vn diag(max(Lambda, 0)) Vn^T  -> sA
     {
-        // P = Vn diag(max(Lambda, 0)) Vn^T  -> sX
-        float acc[T][T];
 #pragma unroll
-        for (int u = 0; u < T; ++u)
+        for (int u = 0; u < TR; ++u)
 #pragma unroll
-            for (int v = 0; v < T; ++v) acc[u][v] = 0.0f;
+            for (int v = 0; v < TC; ++v) acc[u][v] = 0.0f;
+#pragma unroll 4
         for (int q = 0; q < S; ++q) {
-            const float lq = sLp[q];
-            float ba[T], bb[T];
+            const float lq = sm.lp[q];
+            float ba[TR], bb[TC];
 #pragma unroll
-            for (int u = 0; u < T; ++u) ba[u] = sA[(ti * T + u) * LD + q] * lq;
+            for (int u = 0; u < TR; ++u) ba[u] = sV[(ti * TR + u) * LD + q] * lq;
 #pragma unroll
-            for (int v = 0; v < T; ++v) bb[v] = sA[(tj * T + v) * LD + q];
+            for (int v = 0; v < TC; ++v) bb[v] = sV[min(tj * TC + v, S - 1) * LD + q];
 #pragma unroll
-            for (int u = 0; u < T; ++u)
+            for (int u = 0; u < TR; ++u)
 #pragma unroll
-                for (int v = 0; v < T; ++v) acc[u][v] += ba[u] * bb[v];
+                for (int v = 0; v < TC; ++v) acc[u][v] += ba[u] * bb[v];
         }
 #pragma unroll
-        for (int u = 0; u < T; ++u)
+        for (int u = 0; u < TR; ++u)
 #pragma unroll
-            for (int v = 0; v < T; ++v) sX[(ti * T + u) * LD + tj * T + v] = acc[u][v];
+            for (int v = 0; v < TC; ++v)
+                if (tj * TC + v < S) sA[(ti * TR + u) * LD + tj * TC + v] = acc[u][v];
     }
     __syncthreads();
 
-    if (warm)
+    if (warm && a.warm_store)
         for (int idx = tid; idx < k * k; idx += NT) {
             const int i = idx / k, j = idx - i * k;
-            vw[idx] = sA[i * LD + j];
+            vw[idx] = sV[i * LD + j];
         }
 
     double p0 = 0.0, p1 = 0.0, p2 = 0.0;
     for (int s = tid; s < nslot; s += NT) {
         const int i = tri_row(s), j = s - i * (i + 1) / 2;
-        const float pv32 = sX[i * LD + j];
+        const float pv32 = sA[i * LD + j];
         const int64_t g = off + s;
         if (a.mode == PROJ_STANDALONE) {
             a.Pout[g] = pv32;
@@ -408,9 +429,9 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
         }
     }
     if (a.mode == PROJ_PRIMAL) {
-        p0 = block_sum<NT>(p0, redd);
-        p1 = block_sum<NT>(p1, redd);
-        p2 = block_sum<NT>(p2, redd);
+        p0 = block_sum<NT>(p0, sm.redd);
+        p1 = block_sum<NT>(p1, sm.redd);
+        p2 = block_sum<NT>(p2, sm.redd);
         if (tid == 0) {
             a.cpart[4 * (int64_t)id + 0] = p0;
             a.cpart[4 * (int64_t)id + 1] = p1;
@@ -420,13 +441,81 @@ __global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
     if (a.mode == PROJ_STANDALONE) {
         // eigenpairs of the k x k block: Lambda and the re-orthonormalised V
         if (a.evals != nullptr)
-            for (int t = tid; t < k; t += NT) a.evals[a.eoff[id] + t] = sLam[t];
+            for (int t = tid; t < k; t += NT) a.evals[a.eoff[id] + t] = sm.lam[t];
         if (a.evecs != nullptr)
             for (int idx = tid; idx < k * k; idx += NT) {
                 const int i = idx / k, j = idx - i * k;
-                a.evecs[a.voff[id] + idx] = sA[i * LD + j];
+                a.evecs[a.voff[id] + idx] = sV[i * LD + j];
             }
     }
+    __syncthreads();  // LDS is reused by the next clique of a queue launch
+}
+
+// One launch per size bucket: workgroup b projects clique ids[b] (or b).
+template <int S, int NT>
+__global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
+    __shared__ float sbuf[2 * S * (S + 1)];
+    __shared__ ProjSmall sm;
+    if (a.ctl != nullptr && a.ctl->stop) return;
+    const int bi = blockIdx.x;
+    if (bi >= a.nblk) return;
+    if (threadIdx.x == 0) sm.zero = 0;
+    __syncthreads();
+    project_one<S, NT>(a, a.ids ? a.ids[bi] : bi, sbuf, sbuf + S * (S + 1), sm);
+}
+
+__device__ __forceinline__ int bucket_of(int k) {
+    return k <= 16 ? 16 : k <= 32 ? 32 : k <= 48 ? 48 : k <= 64 ? 64 : k <= 80 ? 80 : 96;
+}
+
+// Draw the next queue ticket for the workgroup (two barriers).
+__device__ __forceinline__ int draw_item(unsigned long long *ticket, unsigned long long period, int *s_item) {
+    if (threadIdx.x == 0) *s_item = (int)(atomicAdd(ticket, 1ull) % period);
+    __syncthreads();
+    const int item = *s_item;
+    __syncthreads();
+    return item;
+}
+
+// Drain the queue while it hands out cliques of bucket S.  Tickets of one
+// workgroup only increase and ids are in decreasing size, so a workgroup
+// passes through the buckets in order; each bucket's loop-invariant state
+// (work tables of the rotation steps) is live only inside its own loop.
+template <int S, int NT>
+__device__ __forceinline__ int drain_bucket(const ProjArgs &a, int item, float *sbuf, ProjSmall &sm,
+                                            unsigned long long *ticket, unsigned long long period, int *s_item) {
+    while (item < a.nblk) {
+        const int id = a.ids[item];
+        if (bucket_of(a.size[id]) != S) break;
+        project_one<S, NT>(a, id, sbuf, sbuf + S * (S + 1), sm);
+        item = draw_item(ticket, period, s_item);
+    }
+    return item;
+}
+
+// One persistent launch over every clique (all size buckets up to SB): each
+// workgroup repeatedly draws a ticket from a 64-bit counter and projects
+// clique ids[ticket mod period] (ids in decreasing size: largest first), until
+// its ticket falls past nblk.  A launch of G workgroups draws exactly
+// nblk + G = period tickets (every workgroup ends on one failing draw), so
+// launch L owns tickets [L period, (L+1) period) and the counter never needs a
+// reset between stream-ordered launches of the same configuration.
+template <int SB, int NT>
+__global__ __launch_bounds__(NT) void k_project_queue(ProjArgs a, unsigned long long *ticket,
+                                                      unsigned long long period) {
+    __shared__ float sbuf[2 * SB * (SB + 1)];
+    __shared__ ProjSmall sm;
+    __shared__ int s_item;
+    if (a.ctl != nullptr && a.ctl->stop) return;
+    if (threadIdx.x == 0) sm.zero = 0;  // published by draw_item's barriers
+    int item = draw_item(ticket, period, &s_item);
+    if constexpr (SB >= 96) item = drain_bucket<96, NT>(a, item, sbuf, sm, ticket, period, &s_item);
+    if constexpr (SB >= 80) item = drain_bucket<80, NT>(a, item, sbuf, sm, ticket, period, &s_item);
+    if constexpr (SB >= 64) item = drain_bucket<64, NT>(a, item, sbuf, sm, ticket, period, &s_item);
+    if constexpr (SB >= 48) item = drain_bucket<48, NT>(a, item, sbuf, sm, ticket, period, &s_item);
+    if constexpr (SB >= 32) item = drain_bucket<32, NT>(a, item, sbuf, sm, ticket, period, &s_item);
+    item = drain_bucket<16, NT>(a, item, sbuf, sm, ticket, period, &s_item);
+    // every clique's bucket is <= SB, so the queue is exhausted here
 }
 
 // Adjoint of the projection (Daleckii-Krein): for W = V diag(lambda) V^T and a
@@ -439,8 +528,8 @@ template <int S, int NT>
 __global__ __launch_bounds__(NT) void k_project_vjp(VjpArgs a) {
     static_assert(S % 16 == 0 && S <= 96, "bucket size");
     constexpr int LD = S + 1;
-    constexpr int G = (NT == 64) ? 8 : 16;
-    constexpr int T = S / G;
+    constexpr int GC = Tiles<S, NT>::GC, T = Tiles<S, NT>::TR;
+    static_assert(Tiles<S, NT>::TR == Tiles<S, NT>::TC, "square tiles");
     __shared__ float sA[S * LD];
     __shared__ float sV[S * LD];
     __shared__ float sX[S * LD];
@@ -452,7 +541,7 @@ __global__ __launch_bounds__(NT) void k_project_vjp(VjpArgs a) {
     const int64_t off = a.off[bi], eo = a.eoff[bi], vo = a.voff[bi];
     const int nslot = k * (k + 1) / 2;
     const int tid = threadIdx.x;
-    const int ti = tid / G, tj = tid % G;
+    const int ti = tid / GC, tj = tid % GC;
     for (int idx = tid; idx < S * S; idx += NT) {
         const int i = idx / S, j = idx % S;
         sA[i * LD + j] = 0.0f;
@@ -472,13 +561,13 @@ __global__ __launch_bounds__(NT) void k_project_vjp(VjpArgs a) {
     }
     __syncthreads();
     float acc[T][T];
-    tile_product<S, G, 1>(sA, sV, acc, ti, tj);  // G V
+    tile_product<S, NT, 1>(sA, sV, acc, ti, tj);  // G V
 #pragma unroll
     for (int u = 0; u < T; ++u)
 #pragma unroll
         for (int v = 0; v < T; ++v) sX[(ti * T + u) * LD + tj * T + v] = acc[u][v];
     __syncthreads();
-    tile_product<S, G, 0>(sV, sX, acc, ti, tj);  // V^T G V
+    tile_product<S, NT, 0>(sV, sX, acc, ti, tj);  // V^T G V
 #pragma unroll
     for (int u = 0; u < T; ++u)
 #pragma unroll
@@ -497,13 +586,13 @@ __global__ __launch_bounds__(NT) void k_project_vjp(VjpArgs a) {
 #pragma unroll
         for (int v = 0; v < T; ++v) sA[(ti * T + u) * LD + tj * T + v] = acc[u][v];
     __syncthreads();
-    tile_product<S, G, 1>(sV, sA, acc, ti, tj);  // V (Gamma o B)
+    tile_product<S, NT, 1>(sV, sA, acc, ti, tj);  // V (Gamma o B)
 #pragma unroll
     for (int u = 0; u < T; ++u)
 #pragma unroll
         for (int v = 0; v < T; ++v) sX[(ti * T + u) * LD + tj * T + v] = acc[u][v];
     __syncthreads();
-    tile_product<S, G, 2>(sX, sV, acc, ti, tj);  // (V (Gamma o B)) V^T
+    tile_product<S, NT, 2>(sX, sV, acc, ti, tj);  // (V (Gamma o B)) V^T
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < T; ++u)
@@ -526,6 +615,40 @@ void launch_t(const ProjArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_project<S, NT>), dim3(a.nblk), dim3(NT), 0, s, a);
 }
 
+template <int SB, int NT>
+void launch_queue_t(const ProjArgs &a, int grid, unsigned long long *ticket, hipStream_t s) {
+    hipLaunchKernelGGL((k_project_queue<SB, NT>), dim3(grid), dim3(NT), 0, s, a, ticket,
+                       (unsigned long long)(a.nblk + grid));
+}
+
+template <int SB, int NT>
+int queue_occ_t() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_project_queue<SB, NT>, NT, 0) != hipSuccess) return 0;
+    return nb;
+}
+
+// Autotuning input: for each clique a symmetric k x k block with distinct
+// diagonal values in (-1, 1) and off-diagonal values of size 1e-3 from an
+// integer hash, i.e. the nearly diagonal matrices a warm-started eigensolve
+// sees inside the ADMM loop.
+__global__ void k_tune_blocks(const int32_t *__restrict__ size, const int64_t *__restrict__ off, int p,
+                              float *__restrict__ W) {
+    const int id = blockIdx.x;
+    if (id >= p) return;
+    const int k = size[id];
+    const int nslot = k * (k + 1) / 2;
+    for (int s = threadIdx.x; s < nslot; s += blockDim.x) {
+        const int i = tri_row(s), j = s - i * (i + 1) / 2;
+        uint32_t h = (uint32_t)id * 0x9E3779B1u ^ (uint32_t)s * 0x85EBCA77u;
+        h ^= h >> 15;
+        h *= 0x2C1B3C6Du;
+        h ^= h >> 12;
+        const float u = (float)(h & 0xFFFFFF) * (2.0f / 16777216.0f) - 1.0f;
+        W[off[id] + s] = (i == j) ? (float)(2 * i - k + 1) / (float)k : 1e-3f * u;
+    }
+}
+
 __global__ void k_identity_blocks(const int32_t *__restrict__ size, const int64_t *__restrict__ voff, int p,
                                   float *__restrict__ V) {
     const int id = blockIdx.x;
@@ -541,19 +664,54 @@ int proj_bucket(int smax) {
     if (smax <= 32) return 32;
     if (smax <= 48) return 48;
     if (smax <= 64) return 64;
+    if (smax <= 80) return 80;
     return 96;
+}
+
+bool proj_threads_ok(int S, int nthreads) {
+    if (nthreads == 256) return true;
+    if (nthreads == 64) return S <= 48;
+    if (nthreads == 512) return S >= 48;
+    return false;
 }
 
 void launch_project(const ProjArgs &a, int smax, int nthreads, hipStream_t s) {
     if (a.nblk <= 0) return;
     const int S = proj_bucket(smax);
-    const bool wide = nthreads > 64 || S > 48;
+    const int nt = proj_threads_ok(S, nthreads) ? nthreads : 256;
     switch (S) {
-    case 16: wide ? launch_t<16, 256>(a, s) : launch_t<16, 64>(a, s); break;
-    case 32: wide ? launch_t<32, 256>(a, s) : launch_t<32, 64>(a, s); break;
-    case 48: wide ? launch_t<48, 256>(a, s) : launch_t<48, 64>(a, s); break;
-    case 64: launch_t<64, 256>(a, s); break;
-    default: launch_t<96, 256>(a, s); break;
+    case 16: nt == 64 ? launch_t<16, 64>(a, s) : launch_t<16, 256>(a, s); break;
+    case 32: nt == 64 ? launch_t<32, 64>(a, s) : launch_t<32, 256>(a, s); break;
+    case 48: nt == 64 ? launch_t<48, 64>(a, s) : nt == 512 ? launch_t<48, 512>(a, s) : launch_t<48, 256>(a, s); break;
+    case 64: nt == 512 ? launch_t<64, 512>(a, s) : launch_t<64, 256>(a, s); break;
+    case 80: nt == 512 ? launch_t<80, 512>(a, s) : launch_t<80, 256>(a, s); break;
+    default: nt == 512 ? launch_t<96, 512>(a, s) : launch_t<96, 256>(a, s); break;
+    }
+}
+
+int project_queue_occupancy(int smax, int nthreads) {
+    const bool w = nthreads == 512;
+    switch (proj_bucket(smax)) {
+    case 16: return w ? queue_occ_t<16, 512>() : queue_occ_t<16, 256>();
+    case 32: return w ? queue_occ_t<32, 512>() : queue_occ_t<32, 256>();
+    case 48: return w ? queue_occ_t<48, 512>() : queue_occ_t<48, 256>();
+    case 64: return w ? queue_occ_t<64, 512>() : queue_occ_t<64, 256>();
+    case 80: return w ? queue_occ_t<80, 512>() : queue_occ_t<80, 256>();
+    default: return w ? queue_occ_t<96, 512>() : queue_occ_t<96, 256>();
+    }
+}
+
+void launch_project_queue(const ProjArgs &a, int smax, int nthreads, int grid, unsigned long long *ticket,
+                          hipStream_t s) {
+    if (a.nblk <= 0 || grid <= 0) return;
+    const bool w = nthreads == 512;
+    switch (proj_bucket(smax)) {
+    case 16: w ? launch_queue_t<16, 512>(a, grid, ticket, s) : launch_queue_t<16, 256>(a, grid, ticket, s); break;
+    case 32: w ? launch_queue_t<32, 512>(a, grid, ticket, s) : launch_queue_t<32, 256>(a, grid, ticket, s); break;
+    case 48: w ? launch_queue_t<48, 512>(a, grid, ticket, s) : launch_queue_t<48, 256>(a, grid, ticket, s); break;
+    case 64: w ? launch_queue_t<64, 512>(a, grid, ticket, s) : launch_queue_t<64, 256>(a, grid, ticket, s); break;
+    case 80: w ? launch_queue_t<80, 512>(a, grid, ticket, s) : launch_queue_t<80, 256>(a, grid, ticket, s); break;
+    default: w ? launch_queue_t<96, 512>(a, grid, ticket, s) : launch_queue_t<96, 256>(a, grid, ticket, s); break;
     }
 }
 
@@ -564,8 +722,13 @@ void launch_project_vjp(const VjpArgs &a, int smax, hipStream_t s) {
     case 32: launch_vjp_t<32, 256>(a, s); break;
     case 48: launch_vjp_t<48, 256>(a, s); break;
     case 64: launch_vjp_t<64, 256>(a, s); break;
+    case 80: launch_vjp_t<80, 256>(a, s); break;
     default: launch_vjp_t<96, 256>(a, s); break;
     }
+}
+
+void launch_tune_blocks(const int32_t *size, const int64_t *off, int p, float *W, hipStream_t s) {
+    if (p > 0) hipLaunchKernelGGL(k_tune_blocks, dim3(p), dim3(256), 0, s, size, off, p, W);
 }
 
 void launch_identity_blocks(const int32_t *size, const int64_t *voff, int p, float *V, hipStream_t s) {

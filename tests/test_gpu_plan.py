@@ -1,0 +1,122 @@
+"""Launch plans of the batched projection (needs a GPU): the persistent queue
+launch over all cliques and the per-bucket launches, at every workgroup size,
+against the oracle on the uneven-clique instance, and the queue's ticket
+counter across eager, graph and instrumentation launches."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1609_06068_amd import cdcs, synth
+
+pytestmark = pytest.mark.gpu
+
+PLANS = [(True, 256), (True, 512), (False, 64), (False, 256), (False, 512)]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available()
+    cdcs.load_library()
+    return _t
+
+
+@pytest.fixture(scope="module")
+def small():
+    prob = synth.c3_small()
+    return prob, O.Oracle(prob).solve("primal", rho=1.0, max_iter=30)
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300)
+
+
+def _lam(sol, st):
+    return np.concatenate([B.ravel() for B in cdcs.unpack_blocks(st["lam"].cpu().numpy().astype(np.float64),
+                                                                 sol.sizes, sol.offsets)])
+
+
+@pytest.mark.parametrize("plan", PLANS, ids=[f"{'queue' if q else 'buckets'}{t}" for q, t in PLANS])
+def test_every_plan_matches_the_oracle(torch, small, plan):
+    prob, ref = small
+    sol = cdcs.Solver(prob)
+    sol.set_projection_plan(*plan)
+    tun = sol.tuning()
+    assert tun["persistent"] == plan[0]
+    st = sol.new_state("primal")
+    info = sol.solve(st, form="primal", tol=0.0, max_iter=30, check_every=10)
+    assert info.iters == 30 and info.jacobi_cap_hits == 0
+    assert _rel(st["x"].cpu().numpy(), ref.x) <= 1e-4
+    assert _rel(_lam(sol, st), np.concatenate([B.ravel() for B in ref.lam])) <= 1e-4
+    sol.close()
+
+
+def test_queue_tickets_stay_aligned_across_launch_kinds(torch, small):
+    """The queue launch relies on every launch drawing exactly p + grid
+    tickets.  Interleave eager iterations, graph replays and instrumentation
+    launches; a fresh solve afterwards must equal a fresh solve before."""
+    prob, _ = small
+    sol = cdcs.Solver(prob)
+    sol.set_projection_plan(True, 256)
+    a = sol.new_state("primal")
+    sol.solve(a, form="primal", tol=0.0, max_iter=12, check_every=4)
+    junk = sol.new_state("primal")
+    sol.solve(junk, form="primal", tol=0.0, max_iter=5, check_every=0)
+    sol.profile_kernel(junk, cdcs.K_PROJECT, reps=7)
+    sol.solve(junk, form="primal", tol=0.0, max_iter=9, check_every=3)
+    b = sol.new_state("primal")
+    sol.solve(b, form="primal", tol=0.0, max_iter=12, check_every=4)
+    for k in ("x", "blk", "lam"):
+        assert torch.equal(a[k], b[k]), k
+    sol.close()
+
+
+def test_queue_and_bucket_launches_agree(torch, small):
+    prob, _ = small
+    out = []
+    for plan in [(True, 256), (False, 256)]:
+        sol = cdcs.Solver(prob)
+        sol.set_projection_plan(*plan)
+        st = sol.new_state("primal")
+        sol.solve(st, form="primal", tol=0.0, max_iter=20, check_every=10)
+        out.append(st["x"].cpu().numpy())
+        sol.close()
+    assert _rel(out[0], out[1]) <= 1e-6
+
+
+def test_tuning_report_and_plan_errors(torch, small):
+    prob, _ = small
+    sol = cdcs.Solver(prob)
+    t = sol.tuning()
+    assert t["queue_us"] > 0 and t["buckets_us"] > 0
+    assert t["persistent"] == (t["queue_us"] < t["buckets_us"])
+    assert sum(b["count"] for b in t["buckets"]) == prob.p
+    assert [b["size"] for b in t["buckets"]] == sorted(b["size"] for b in t["buckets"])
+    assert all(b["size"] in (16, 32, 48, 64, 80, 96) for b in t["buckets"])
+    if t["persistent"]:
+        assert t["threads"] in (256, 512) and 0 < t["grid"] <= prob.p
+    with pytest.raises(cdcs.CdcsError) as e:
+        sol.set_projection_plan(True, 64)
+    assert e.value.status == cdcs.E_ARG
+    with pytest.raises(cdcs.CdcsError):
+        sol.set_projection_plan(False, 100)
+    sol.close()
+
+
+def test_batch_handle_queue_plan(torch):
+    """The queue launch over the cliques of many instances, with per-instance
+    stopping flags."""
+    shapes = [(10, 10, 5, 50), (5, 8, 2, 25), (7, 12, 6, 35), (3, 4, 3, 9)]
+    probs = [synth.block_arrow(l, d, h, m, seed=900 + i) for i, (l, d, h, m) in enumerate(shapes)]
+    res = {}
+    for plan in [(True, 256), (False, 256)]:
+        sol = cdcs.BatchSolver(probs)
+        sol.set_projection_plan(*plan)
+        st = sol.new_state("primal")
+        info = sol.solve(st, form="primal", tol=1e-4, max_iter=2000, check_every=25)
+        assert info.converged
+        res[plan] = [i.iters for i in sol.instance_info()], st["x"].cpu().numpy()
+        sol.close()
+    (it_q, x_q), (it_b, x_b) = res[(True, 256)], res[(False, 256)]
+    assert it_q == it_b
+    assert _rel(x_q, x_b) <= 1e-6
