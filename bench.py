@@ -197,9 +197,12 @@ def run_single(args, torch, workload):
 
     # Accuracy: cold start, stop at max(eps_p, eps_d) <= 1e-4.
     st = sol.new_state(form)
-    acc = sol.solve(st, form=form, rho=rho, tol=1e-4, max_iter=spec["acc_cap"], check_every=GRAPH_CHUNK)
+    acc = sol.solve(st, form=form, rho=rho, tol=1e-4, max_iter=1 if args.profile else spec["acc_cap"],
+                    check_every=GRAPH_CHUNK)
     torch.cuda.synchronize()
     _log(f"to 1e-4: {acc.iters} iterations, converged={acc.converged}, {acc.loop_s:.4f}s")
+    tuning = sol.tuning()
+    _log(f"projection plan: {tuning}")
 
     # Timed region: warmup, then exactly K iterations (no early exit).
     K, W = args.steps, args.warmup
@@ -220,7 +223,7 @@ def run_single(args, torch, workload):
     abytes = algorithmic_bytes(sol, prob)
     kern = {n: {"us": kern_ms[n] * 1e3, "GB_s": abytes[n] / (kern_ms[n] * 1e-3) / 1e9} for n in kern_ms}
     _log("kernels: " + ", ".join(f"{n} {v['us']:.1f}us {v['GB_s']:.0f}GB/s" for n, v in kern.items()))
-    batched = batched_vs_plain(torch, sol, st, rho)
+    batched = None if args.profile else batched_vs_plain(torch, sol, st, rho)
     tfile = os.path.join(ROOT, "profiles", spec["traffic"])
     roofline = roofline_for(kern_ms, abytes, sol.sizes, tfile)
     result = base_result(ips, "ADMM iterations/s", K, W, 1e3 * elapsed / K,
@@ -234,13 +237,14 @@ def run_single(args, torch, workload):
                      "time_to_tol_s": acc.loop_s, "eps_p": acc.eps_p, "eps_d": acc.eps_d,
                      "obj_primal": acc.obj_primal, "obj_dual": acc.obj_dual},
         "batched_vs_plain": batched,
+        "projection_plan": tuning,
         "kernels": kern,
         "roofline": roofline,
     })
     if workload == "c3":
         result["projection_model_tflops"] = projection_model_flops(sol.sizes) / (kern_ms["project"] * 1e-3) / 1e12
 
-    if not args.no_cpu:
+    if not (args.no_cpu or args.profile):
         from threadpoolctl import threadpool_limits
 
         from oracle import oracle as orc
@@ -418,6 +422,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB elementwise kernel (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--print-hash", action="store_true", help="print the kernel source hash and exit")
+    ap.add_argument("--profile", action="store_true",
+                    help="profiler runs: skip the accuracy solve, the plain-form comparison and the oracle")
     args = ap.parse_args()
     if args.print_hash:
         print(kernel_source_hash())

@@ -80,19 +80,25 @@ __device__ __forceinline__ int tri_row(int s) {
     return a;
 }
 
-// Circle ordering on S indices: position 0 holds index 0, position j >= 1
-// holds 1 + (j - 1 + r) mod (S - 1); pair t joins positions t and S-1-t.
-template <int S>
-__device__ __forceinline__ void pair_at(int t, int r, int &P, int &Q) {
-    constexpr int M = S - 1;
+// Round-robin (circle) ordering on K (even) indices, steps r = 0 .. K-2:
+// position 0 holds index 0, position j >= 1 holds 1 + (j - 1 + r) mod (K-1);
+// pair t joins positions t ("top", index a) and K-1-t ("bottom", index b).
+__device__ __forceinline__ void pair_dyn(int t, int r, int K, int &a, int &b) {
+    const int M = K - 1;
     int x = t - 1 + r;  // in [-1, 2M)
     x = (x >= M) ? x - M : x;
     int y = M - 1 - t + r;  // in [0, 2M)
     y = (y >= M) ? y - M : y;
-    const int a = (t == 0) ? 0 : 1 + x;
-    const int b = 1 + y;
-    P = min(a, b);
-    Q = max(a, b);
+    a = (t == 0) ? 0 : 1 + x;
+    b = 1 + y;
+}
+
+// Full-wave lane shifts: lane i receives lane i+1 (shl) or lane i-1 (shr).
+__device__ __forceinline__ float wave_shl1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float wave_shr1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
 }
 
 // Register-tiled S x S products on a GR x GC thread grid (GR = 16 rows of
@@ -108,19 +114,27 @@ struct Tiles {
 // mode 0: C = X^T Y   (C[i][j] = sum_q X[q][i] Y[q][j])
 // mode 1: C = X Y     (C[i][j] = sum_q X[i][q] Y[q][j])
 // mode 2: C = X Y^T   (C[i][j] = sum_q X[i][q] Y[j][q])
+// Sums run over q < n (n <= S; the rest of X and Y is zero padding).  With
+// lp, the X operand of mode 2 is scaled by lp[q] (C = X diag(lp) Y^T).
 template <int S, int NT, int MODE>
 __device__ __forceinline__ void tile_product(const float *X, const float *Y,
-                                             float (&acc)[Tiles<S, NT>::TR][Tiles<S, NT>::TC], int ti, int tj) {
+                                             float (&acc)[Tiles<S, NT>::TR][Tiles<S, NT>::TC], int ti, int tj,
+                                             int n = S, const float *lp = nullptr) {
     constexpr int LD = S + 1, TR = Tiles<S, NT>::TR, TC = Tiles<S, NT>::TC;
 #pragma unroll
     for (int u = 0; u < TR; ++u)
 #pragma unroll
         for (int v = 0; v < TC; ++v) acc[u][v] = 0.0f;
 #pragma unroll 4
-    for (int q = 0; q < S; ++q) {
+    for (int q = 0; q < n; ++q) {
         float xa[TR], yb[TC];
 #pragma unroll
         for (int u = 0; u < TR; ++u) xa[u] = MODE == 0 ? X[q * LD + ti * TR + u] : X[(ti * TR + u) * LD + q];
+        if (lp != nullptr) {
+            const float l = lp[q];
+#pragma unroll
+            for (int u = 0; u < TR; ++u) xa[u] *= l;
+        }
 #pragma unroll
         for (int v = 0; v < TC; ++v) {
             const int j = min(tj * TC + v, S - 1);
@@ -133,9 +147,103 @@ __device__ __forceinline__ void tile_product(const float *X, const float *Y,
     }
 }
 
+// S x S products on FP32 matrix cores (v_mfma_f32_16x16x4_f32), buckets S >=
+// 32.  The 16 x 16 output tiles are split over the waves as a WR x WC grid of
+// tile blocks, so each wave loads one A operand per tile row and one B operand
+// per tile column of its block for every 4-deep slice of the sum.
+// Operand layout of the instruction (lane l): A[l % 16][l / 16] (16 x 4),
+// B[l / 16][l % 16] (4 x 16); result element r: D[(l / 16) * 4 + r][l % 16].
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int S, int NT>
+struct MfmaTiles {
+    static constexpr int T = S / 16;
+    static constexpr int NW = NT / 64;
+    static constexpr int WR = NW == 1 ? 1 : 2;
+    static constexpr int WC = NW / WR;
+    static constexpr int TRW = (T + WR - 1) / WR, TCW = (T + WC - 1) / WC;
+};
+
+// C = X^T Y (mode 0), X Y (mode 1) or X diag(lp) Y^T (mode 2) over q < n.
+template <int S, int NT, int MODE>
+__device__ __forceinline__ void mfma_product(const float *X, const float *Y, const float *lp, int n, int lane,
+                                             int wv,
+                                             f32x4 (&acc)[MfmaTiles<S, NT>::TRW][MfmaTiles<S, NT>::TCW]) {
+    using MT = MfmaTiles<S, NT>;
+    constexpr int LD = S + 1, TRW = MT::TRW, TCW = MT::TCW;
+    const int wr = wv / MT::WC, wc = wv % MT::WC;
+    const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int u = 0; u < TRW; ++u)
+#pragma unroll
+        for (int v = 0; v < TCW; ++v) acc[u][v] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int n4 = (n + 3) & ~3;  // <= S; terms past n are zero
+#pragma unroll 2
+    for (int q0 = 0; q0 < n4; q0 += 4) {
+        const int q = q0 + lk;
+        float av[TRW], bv[TCW];
+#pragma unroll
+        for (int u = 0; u < TRW; ++u) {
+            const int i = min((wr * TRW + u) * 16 + lr, S - 1);  // tiles past S: clamped, never stored
+            av[u] = MODE == 0 ? X[q * LD + i] : X[i * LD + q];
+            if (MODE == 2) av[u] *= lp[q];
+        }
+#pragma unroll
+        for (int v = 0; v < TCW; ++v) {
+            const int j = min((wc * TCW + v) * 16 + lr, S - 1);
+            bv[v] = MODE == 2 ? Y[j * LD + q] : Y[q * LD + j];
+        }
+#pragma unroll
+        for (int u = 0; u < TRW; ++u)
+#pragma unroll
+            for (int v = 0; v < TCW; ++v) acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[v], acc[u][v], 0, 0, 0);
+    }
+}
+
+// Compute an S x S product (matrix cores for S >= 32, register tiles on the
+// vector ALUs below), wait until every thread has read its operands, then
+// hand each result element to st(row, col, value): the result may overwrite
+// an operand.  The caller synchronises before reading what st wrote.
+template <int S, int NT, int MODE, typename Store>
+__device__ __forceinline__ void product_store(const float *X, const float *Y, const float *lp, int n, int tid,
+                                              Store st) {
+    if constexpr (S >= 32) {
+        using MT = MfmaTiles<S, NT>;
+        const int lane = tid & 63, wv = tid >> 6;
+        f32x4 acc[MT::TRW][MT::TCW];
+        mfma_product<S, NT, MODE>(X, Y, lp, n, lane, wv, acc);
+        __syncthreads();
+        const int wr = wv / MT::WC, wc = wv % MT::WC;
+#pragma unroll
+        for (int u = 0; u < MT::TRW; ++u)
+#pragma unroll
+            for (int v = 0; v < MT::TCW; ++v) {
+                const int col = (wc * MT::TCW + v) * 16 + (lane & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = (wr * MT::TRW + u) * 16 + (lane >> 4) * 4 + r;
+                    if (row < S && col < S) st(row, col, acc[u][v][r]);
+                }
+            }
+    } else {
+        using TL = Tiles<S, NT>;
+        const int ti = tid / TL::GC, tj = tid % TL::GC;
+        float acc[TL::TR][TL::TC];
+        tile_product<S, NT, MODE>(X, Y, acc, ti, tj, n, MODE == 2 ? lp : nullptr);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < TL::TR; ++u)
+#pragma unroll
+            for (int v = 0; v < TL::TC; ++v)
+                if (tj * TL::TC + v < S) st(ti * TL::TR + u, tj * TL::TC + v, acc[u][v]);
+    }
+}
+
 // Small per-workgroup LDS of the projection (sized for the largest bucket).
 struct ProjSmall {
-    float c[48], s[48], t[48];   // rotations of one step
+    float2 cs[48];               // rotations of one step: (c, s) of pair t
+    int pq[48];                  // its indices P | Q << 16 (P < Q)
+    float t[48];                 // t * a_PQ of pair t
     float lam[96], lp[96];       // eigenvalues, clamped eigenvalues
     float redf[8];
     double redd[8];
@@ -149,14 +257,11 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
                                             float *__restrict__ sV, ProjSmall &sm) {
     static_assert(S % 16 == 0 && S <= 96, "bucket size");
     static_assert(NT == 64 || NT == 256 || NT == 512, "workgroup size");
-    using TL = Tiles<S, NT>;
-    constexpr int TR = TL::TR, TC = TL::TC, GC = TL::GC;
-    constexpr int H = S / 2;                   // pairs per step
-    constexpr int LD = S + 1;                  // odd row stride
-    constexpr int NSTEP = S - 1;               // steps per sweep
-    constexpr int NBLK = H * (H + 1) / 2;      // lower 2x2 blocks (I >= J)
-    constexpr int NA = (NBLK + NT - 1) / NT;   // A blocks per thread
-    constexpr int NV = (S * H + NT - 1) / NT;  // V row pairs per thread
+    constexpr int LD = S + 1;                    // odd row stride
+    constexpr int HMAX = S / 2;                  // pairs per step, at most
+    constexpr int NA = (HMAX * (HMAX + 1) / 2 + NT - 1) / NT;  // 2x2 blocks of A per thread, at most
+    constexpr int NW = NT / 64;                  // waves
+    constexpr int RPW = (S + NW - 1) / NW;       // rows of V per wave, at most
 
     if (a.istop != nullptr && a.istop[a.kinst[id]]) return;  // instance already stopped
     const int k = a.size[id];
@@ -169,7 +274,6 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
     const int tid = threadIdx.x + *(volatile int *)&sm.zero;
     const bool warm = a.vwarm != nullptr;
     float *vw = warm ? a.vwarm + a.vwoff[id] : nullptr;
-    const int ti = tid / GC, tj = tid % GC;
 
     for (int idx = tid; idx < S * S; idx += NT) {
         const int i = idx / S, j = idx % S;
@@ -213,25 +317,13 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
     const float fro2 = block_sum<NT>(fro, sm.redf);
     const float thr = kEps * kEps * fro2;
 
-    float acc[TR][TC];
+    const int Kw = k + (k & 1);  // products run over the active size
+    auto to_sA = [&](int i, int j, float v) { sA[i * LD + j] = v; };
     if (warm) {
         // A <- V^T W V, symmetrised (V = V_prev, orthonormal to FP32 accuracy).
-        // Each product finishes reading before its result overwrites sA.
-        tile_product<S, NT, 1>(sA, sV, acc, ti, tj);  // W V
+        product_store<S, NT, 1>(sA, sV, nullptr, Kw, tid, to_sA);  // W V
         __syncthreads();
-#pragma unroll
-        for (int u = 0; u < TR; ++u)
-#pragma unroll
-            for (int v = 0; v < TC; ++v)
-                if (tj * TC + v < S) sA[(ti * TR + u) * LD + tj * TC + v] = acc[u][v];
-        __syncthreads();
-        tile_product<S, NT, 0>(sV, sA, acc, ti, tj);  // V^T (W V)
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < TR; ++u)
-#pragma unroll
-            for (int v = 0; v < TC; ++v)
-                if (tj * TC + v < S) sA[(ti * TR + u) * LD + tj * TC + v] = acc[u][v];
+        product_store<S, NT, 0>(sV, sA, nullptr, Kw, tid, to_sA);  // V^T (W V)
         __syncthreads();
         for (int idx = tid; idx < S * S; idx += NT) {
             const int i = idx / S, j = idx % S;
@@ -244,20 +336,35 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
         __syncthreads();
     }
 
-    // Fixed work assignment for the rotation steps.
-    int aI[NA], aJ[NA], vRow[NV], vJ[NV];
+    // Jacobi on the K = k rounded up to even leading indices (one zero
+    // padding row and column for odd k; the rest of the bucket is not
+    // touched): K-1 steps of K/2 disjoint rotations per sweep.
+    const int K = k + (k & 1);
+    const int HK = K >> 1;
+    const int nblk = HK * (HK + 1) / 2;
+    // Lower 2x2 blocks (rows of pair I, columns of pair J, I >= J) of this thread.
+    int aI[NA], aJ[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
         const int idx = tid + q * NT;
-        const int I = tri_row(min(idx, NBLK - 1));
-        aI[q] = (idx < NBLK) ? I : -1;
-        aJ[q] = min(idx, NBLK - 1) - I * (I + 1) / 2;
+        const int I = tri_row(min(idx, nblk - 1));
+        aI[q] = (idx < nblk) ? I : -1;
+        aJ[q] = min(idx, nblk - 1) - I * (I + 1) / 2;
     }
+    // V in registers: lane t of a wave holds, for its rows (wave w: rows
+    // w, w + NW, ...), the columns of pair t's top and bottom positions.  A
+    // step rotates them and then moves every column one position along the
+    // circle (a one-lane shift), so columns never go through LDS; after a
+    // whole sweep positions and indices coincide again.
+    const int lane = tid & 63, wv = tid >> 6;
+    const bool vlane = lane < HK;
+    float vt[RPW], vb[RPW];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        const int idx = tid + q * NT;
-        vRow[q] = (idx < S * H) ? idx / H : -1;
-        vJ[q] = idx % H;
+    for (int j = 0; j < RPW; ++j) {
+        const int row = wv + j * NW;
+        const bool ok = vlane && row < K;
+        vt[j] = ok ? sV[row * LD + lane] : 0.0f;
+        vb[j] = ok ? sV[row * LD + K - 1 - lane] : 0.0f;
     }
 
     int sweep = 0;
@@ -276,10 +383,11 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
             break;
         }
 #pragma unroll 1
-        for (int r = 0; r < NSTEP; ++r) {
-            if (tid < H) {
-                int P, Q;
-                pair_at<S>(tid, r, P, Q);
+        for (int r = 0; r < K - 1; ++r) {
+            if (tid < HK) {
+                int ta_, tb_;
+                pair_dyn(tid, r, K, ta_, tb_);
+                const int P = min(ta_, tb_), Q = max(ta_, tb_);
                 const float apq = sA[P * LD + Q];
                 float c = 1.0f, s = 0.0f, ta = 0.0f;
                 if (fabsf(apq) > 1e-30f) {  // entries are scaled to max |a| ~ 1
@@ -291,19 +399,19 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
                     s = t * c;
                     ta = t * apq;
                 }
-                sm.c[tid] = c;
-                sm.s[tid] = s;
+                sm.cs[tid] = make_float2(c, s);
+                sm.pq[tid] = P | (Q << 16);
                 sm.t[tid] = ta;
             }
             __syncthreads();
-            // A <- J^T A J on this thread's lower 2x2 blocks (rows of pair I,
-            // columns of pair J); the transposed block is written alongside.
+            // A <- J^T A J on this thread's lower 2x2 blocks; the transposed
+            // block is written alongside.
 #pragma unroll
             for (int q = 0; q < NA; ++q) {
                 const int I = aI[q], J = aJ[q];
                 if (I < 0) continue;
-                int p1, q1;
-                pair_at<S>(I, r, p1, q1);
+                const int pq1 = sm.pq[I];
+                const int p1 = pq1 & 0xFFFF, q1 = pq1 >> 16;
                 if (I == J) {
                     const float ta = sm.t[I];
                     sA[p1 * LD + p1] -= ta;
@@ -311,9 +419,10 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
                     sA[p1 * LD + q1] = 0.0f;
                     sA[q1 * LD + p1] = 0.0f;
                 } else {
-                    int p2, q2;
-                    pair_at<S>(J, r, p2, q2);
-                    const float c1 = sm.c[I], s1 = sm.s[I], c2 = sm.c[J], s2 = sm.s[J];
+                    const int pq2 = sm.pq[J];
+                    const int p2 = pq2 & 0xFFFF, q2 = pq2 >> 16;
+                    const float2 cs1 = sm.cs[I], cs2 = sm.cs[J];
+                    const float c1 = cs1.x, s1 = cs1.y, c2 = cs2.x, s2 = cs2.y;
                     const float a00 = sA[p1 * LD + p2], a01 = sA[p1 * LD + q2];
                     const float a10 = sA[q1 * LD + p2], a11 = sA[q1 * LD + q2];
                     const float b00 = c1 * a00 - s1 * a10, b01 = c1 * a01 - s1 * a11;
@@ -330,21 +439,36 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
                     sA[q2 * LD + q1] = n11;
                 }
             }
-            // V <- V J
+            // V <- V J in registers: (V_P, V_Q) <- (c V_P - s V_Q, s V_P + c V_Q);
+            // the top column is P unless the pair is reversed (top index > bottom).
+            {
+                int ta_, tb_;
+                pair_dyn(lane, r, K, ta_, tb_);
+                const float2 cs = sm.cs[vlane ? lane : 0];
+                const float c = cs.x, sg = (ta_ > tb_) ? -cs.y : cs.y;
 #pragma unroll
-            for (int q = 0; q < NV; ++q) {
-                const int row = vRow[q], J = vJ[q];
-                if (row < 0) continue;
-                int p2, q2;
-                pair_at<S>(J, r, p2, q2);
-                const float c2 = sm.c[J], s2 = sm.s[J];
-                const float vp = sV[row * LD + p2], vq = sV[row * LD + q2];
-                sV[row * LD + p2] = c2 * vp - s2 * vq;
-                sV[row * LD + q2] = s2 * vp + c2 * vq;
+                for (int j = 0; j < RPW; ++j) {
+                    const float nt = c * vt[j] - sg * vb[j];
+                    const float nb = sg * vt[j] + c * vb[j];
+                    const float up = wave_shl1(nt);  // top of lane + 1
+                    const float dn = wave_shr1(nb);  // bottom of lane - 1
+                    vt[j] = (lane == 0) ? nt : (lane == HK - 1) ? nb : up;
+                    vb[j] = (lane == 0) ? (HK == 1 ? nb : up) : dn;
+                }
             }
             __syncthreads();
         }
     }
+    // registers -> sV (positions equal indices after whole sweeps)
+#pragma unroll
+    for (int j = 0; j < RPW; ++j) {
+        const int row = wv + j * NW;
+        if (vlane && row < K) {
+            sV[row * LD + lane] = vt[j];
+            sV[row * LD + K - 1 - lane] = vb[j];
+        }
+    }
+    __syncthreads();
     if (tid == 0 && a.ctl != nullptr) atomicAdd(&a.ctl->sweeps, sweep);
 
     if (tid < S) {
@@ -353,52 +477,14 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
         sm.lp[tid] = fmaxf(l, 0.0f);
     }
     // E = V^T V - I  -> sA (A's eigenvalues are in sm.lam)
-    tile_product<S, NT, 0>(sV, sV, acc, ti, tj);
+    product_store<S, NT, 0>(sV, sV, nullptr, K, tid,
+                            [&](int i, int j, float v) { sA[i * LD + j] = v - (i == j ? 1.0f : 0.0f); });
     __syncthreads();
-#pragma unroll
-    for (int u = 0; u < TR; ++u)
-#pragma unroll
-        for (int v = 0; v < TC; ++v) {
-            const int i = ti * TR + u, j = tj * TC + v;
-            if (j < S) sA[i * LD + j] = acc[u][v] - (i == j ? 1.0f : 0.0f);
-        }
-    __syncthreads();
-    // Vn = V - V E / 2  -> sV (every thread has read V before any writes)
-    tile_product<S, NT, 1>(sV, sA, acc, ti, tj);
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < TR; ++u)
-#pragma unroll
-        for (int v = 0; v < TC; ++v) {
-            const int i = ti * TR + u, j = tj * TC + v;
-            if (j < S) sV[i * LD + j] -= 0.5f * acc[u][v];
-        }
+    // Vn = V - V E / 2  -> sV
+    product_store<S, NT, 1>(sV, sA, nullptr, K, tid, [&](int i, int j, float v) { sV[i * LD + j] -= 0.5f * v; });
     __syncthreads();
     // P = Vn diag(max(Lambda, 0)) Vn^T  -> sA
-    {
-#pragma unroll
-        for (int u = 0; u < TR; ++u)
-#pragma unroll
-            for (int v = 0; v < TC; ++v) acc[u][v] = 0.0f;
-#pragma unroll 4
-        for (int q = 0; q < S; ++q) {
-            const float lq = sm.lp[q];
-            float ba[TR], bb[TC];
-#pragma unroll
-            for (int u = 0; u < TR; ++u) ba[u] = sV[(ti * TR + u) * LD + q] * lq;
-#pragma unroll
-            for (int v = 0; v < TC; ++v) bb[v] = sV[min(tj * TC + v, S - 1) * LD + q];
-#pragma unroll
-            for (int u = 0; u < TR; ++u)
-#pragma unroll
-                for (int v = 0; v < TC; ++v) acc[u][v] += ba[u] * bb[v];
-        }
-#pragma unroll
-        for (int u = 0; u < TR; ++u)
-#pragma unroll
-            for (int v = 0; v < TC; ++v)
-                if (tj * TC + v < S) sA[(ti * TR + u) * LD + tj * TC + v] = acc[u][v];
-    }
+    product_store<S, NT, 2>(sV, sV, sm.lp, K, tid, to_sA);
     __syncthreads();
 
     if (warm && a.warm_store)
@@ -451,9 +537,20 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
     __syncthreads();  // LDS is reused by the next clique of a queue launch
 }
 
+// Waves per SIMD that the LDS of one workgroup (2 S x (S+1) FP32 buffers
+// and the small arrays) allows on a CU of 160 KB, capped at 4: the register
+// budget the compiler is asked to meet (512 / waves registers per lane).
+constexpr int proj_waves_per_eu(int S, int NT) {
+    const int lds = 2 * S * (S + 1) * 4 + 2048;
+    const int wg = 163840 / lds;
+    const int w = wg * (NT / 64) / 4;
+    return w < 1 ? 1 : (w > 4 ? 4 : w);
+}
+
 // One launch per size bucket: workgroup b projects clique ids[b] (or b).
 template <int S, int NT>
-__global__ __launch_bounds__(NT) void k_project(ProjArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(proj_waves_per_eu(S, NT))))
+void k_project(ProjArgs a) {
     __shared__ float sbuf[2 * S * (S + 1)];
     __shared__ ProjSmall sm;
     if (a.ctl != nullptr && a.ctl->stop) return;
@@ -501,7 +598,8 @@ __device__ __forceinline__ int drain_bucket(const ProjArgs &a, int item, float *
 // launch L owns tickets [L period, (L+1) period) and the counter never needs a
 // reset between stream-ordered launches of the same configuration.
 template <int SB, int NT>
-__global__ __launch_bounds__(NT) void k_project_queue(ProjArgs a, unsigned long long *ticket,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(proj_waves_per_eu(SB, NT))))
+void k_project_queue(ProjArgs a, unsigned long long *ticket,
                                                       unsigned long long period) {
     __shared__ float sbuf[2 * SB * (SB + 1)];
     __shared__ ProjSmall sm;
@@ -670,7 +768,7 @@ int proj_bucket(int smax) {
 
 bool proj_threads_ok(int S, int nthreads) {
     if (nthreads == 256) return true;
-    if (nthreads == 64) return S <= 48;
+    if (nthreads == 64) return S <= 16;
     if (nthreads == 512) return S >= 48;
     return false;
 }
@@ -681,8 +779,8 @@ void launch_project(const ProjArgs &a, int smax, int nthreads, hipStream_t s) {
     const int nt = proj_threads_ok(S, nthreads) ? nthreads : 256;
     switch (S) {
     case 16: nt == 64 ? launch_t<16, 64>(a, s) : launch_t<16, 256>(a, s); break;
-    case 32: nt == 64 ? launch_t<32, 64>(a, s) : launch_t<32, 256>(a, s); break;
-    case 48: nt == 64 ? launch_t<48, 64>(a, s) : nt == 512 ? launch_t<48, 512>(a, s) : launch_t<48, 256>(a, s); break;
+    case 32: launch_t<32, 256>(a, s); break;
+    case 48: nt == 512 ? launch_t<48, 512>(a, s) : launch_t<48, 256>(a, s); break;
     case 64: nt == 512 ? launch_t<64, 512>(a, s) : launch_t<64, 256>(a, s); break;
     case 80: nt == 512 ? launch_t<80, 512>(a, s) : launch_t<80, 256>(a, s); break;
     default: nt == 512 ? launch_t<96, 512>(a, s) : launch_t<96, 256>(a, s); break;
