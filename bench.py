@@ -76,7 +76,8 @@ def algorithmic_bytes(sol, prob):
     import numpy as np
     m, nU, ns, p = sol.m, sol.nnz, sol.nslots, sol.p
     out = {
-        "trmv": 2 * (m * (m + 1) // 2) * 8 + 4 * m * 8,      # L^-1 and L^-T triangles, vectors
+        # L^-1 and L^-T (dense triangles, or CSR: 4 B column + 8 B value + 8 B gathered element), vectors
+        "trmv": (2 * sol.nnz_factor * (4 + 8 + 8) if sol.sparse_factor else 2 * (m * (m + 1) // 2) * 8) + 4 * m * 8,
         "project": nU * 8 + ns * (4 + 4 + 4) + p * 24,        # x, lam in/out, x_k out, partials
         "scatter": ns * 8 + nU * (8 * 3 + 8 * 2),             # x_k, lam; c, 1/D, w; S_prev in, u and S out
     }

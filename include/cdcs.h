@@ -139,12 +139,15 @@ typedef struct {
 } cdcs_state;
 
 /* Sizes of a handle.  sparse_a = 1 if A is kept sparse (nnz_a coefficients),
- * 0 if it is stored densely (nnz_a = m * nnz). */
+ * 0 if it is stored densely (nnz_a = m * nnz).  sparse_factor = 1 if the
+ * inverse Cholesky factor is kept as CSR (nnz_factor nonzeros in L^-1), 0 if
+ * dense (nnz_factor = m (m + 1) / 2). */
 typedef struct {
     int32_t n, m, p, smax;
     int64_t nnz, nslots;
-    int32_t sparse_a, pad_;
+    int32_t sparse_a, sparse_factor;
     int64_t nnz_a;
+    int64_t nnz_factor;
 } cdcs_sizes;
 
 /*
@@ -152,7 +155,9 @@ typedef struct {
  * Validates the pattern and cliques, builds the entry selectors H_k and the
  * overlap counts D = sum_k H_k^T H_k (Sec. III-B.1), uploads the data, forms
  * M = A diag(w/D) A^T on the device in FP64 and factors it (Cholesky), caching
- * the inverse triangular factor for the affine projection.
+ * the inverse triangular factor for the affine projection (as CSR when L^-1
+ * has under an eighth of a triangle's entries, else dense), and times the
+ * launch forms of the batched projection (cdcs_get_tuning).
  *   b [m] host FP64, c [nnz] host FP64 (values of C on the entries).
  *   opts may be NULL (rho = 1).  The cached factor does not depend on rho.
  * Errors: CDCS_E_ARG, CDCS_E_PATTERN (unsorted/duplicate clique vertex, clique

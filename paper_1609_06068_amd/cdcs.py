@@ -91,7 +91,7 @@ class _Tuning(ctypes.Structure):
 class _Sizes(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("p", ctypes.c_int32), ("smax", ctypes.c_int32),
                 ("nnz", ctypes.c_int64), ("nslots", ctypes.c_int64), ("sparse_a", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("nnz_a", ctypes.c_int64)]
+                ("sparse_factor", ctypes.c_int32), ("nnz_a", ctypes.c_int64), ("nnz_factor", ctypes.c_int64)]
 
 
 _lib = None
@@ -218,6 +218,7 @@ class Solver:
         self.n, self.m, self.p, self.smax = sz.n, sz.m, sz.p, sz.smax
         self.nnz, self.nslots = sz.nnz, sz.nslots
         self.sparse_a, self.nnz_a = bool(sz.sparse_a), sz.nnz_a
+        self.sparse_factor, self.nnz_factor = bool(sz.sparse_factor), sz.nnz_factor
         off = np.empty(self.p + 1, dtype=np.int64)
         _check(L.cdcs_clique_offsets(h, _np_ptr(off)), "cdcs_clique_offsets")
         self.offsets = off

@@ -111,6 +111,8 @@ namespace {
 
 cdcs_status tune_projection(cdcs_handle *h, hipStream_t s);
 
+cdcs_status compress_factors(cdcs_handle *h, hipStream_t s);
+
 template <typename T>
 cdcs_status upload(cdcs_handle *h, T **dst, const std::vector<T> &src, hipStream_t s) {
     CK(h->alloc(dst, (int64_t)src.size()));
@@ -361,6 +363,61 @@ cdcs_status upload_common(cdcs_handle *h, const std::vector<int32_t> &size, cons
     return CDCS_OK;
 }
 
+// Keep the inverse factors as CSR when L^-1 holds under an eighth of the
+// entries of a triangle (nearly diagonal M, e.g. sparse constraints that
+// rarely share an entry): the two triangular products then read their
+// nonzeros only.  The dense copies are released.
+cdcs_status compress_factors(cdcs_handle *h, hipStream_t s) {
+    Dev &d = h->d;
+    const int m = d.m;
+    std::vector<int32_t> cnt((size_t)m);
+    int32_t *cnt_d = nullptr;
+    HIP_OK(hipMalloc(&cnt_d, (size_t)m * sizeof(int32_t)));
+    launch_tri_count(d.Linv, m, 0, cnt_d, s);
+    hipError_t e = hipMemcpyAsync(cnt.data(), cnt_d, (size_t)m * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(cnt_d);
+        return fail(CDCS_E_DEVICE, std::string("factor nonzero count: ") + hipGetErrorString(e));
+    }
+    int64_t nnz = 0;
+    for (int32_t c : cnt) nnz += c;
+    const int64_t tri = (int64_t)m * (m + 1) / 2;
+    if (nnz * 8 >= tri || nnz >= ((int64_t)1 << 31)) {
+        (void)hipFree(cnt_d);
+        return CDCS_OK;
+    }
+    // CSR of L^-1; L^-T's rows are L^-1's columns, counted from the dense transpose
+    std::vector<int32_t> ptr((size_t)m + 1, 0), tcnt((size_t)m), tptr((size_t)m + 1, 0);
+    for (int i = 0; i < m; ++i) ptr[(size_t)i + 1] = ptr[(size_t)i] + cnt[(size_t)i];
+    launch_tri_count(d.LinvT, m, 1, cnt_d, s);
+    e = hipMemcpyAsync(tcnt.data(), cnt_d, (size_t)m * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(cnt_d);
+    if (e != hipSuccess) return fail(CDCS_E_DEVICE, std::string("factor nonzero count: ") + hipGetErrorString(e));
+    for (int i = 0; i < m; ++i) tptr[(size_t)i + 1] = tptr[(size_t)i] + tcnt[(size_t)i];
+    if (tptr[(size_t)m] != nnz) return fail(CDCS_E_NUMERIC, "inverse factor and its transpose differ in nonzeros");
+    CK(upload(h, &d.li_ptr, ptr, s));
+    CK(upload(h, &d.lt_ptr, tptr, s));
+    CK(h->alloc(&d.li_col, nnz));
+    CK(h->alloc(&d.li_val, nnz));
+    CK(h->alloc(&d.lt_col, nnz));
+    CK(h->alloc(&d.lt_val, nnz));
+    launch_tri_compress(d.Linv, m, 0, d.li_ptr, d.li_col, d.li_val, s);
+    launch_tri_compress(d.LinvT, m, 1, d.lt_ptr, d.lt_col, d.lt_val, s);
+    HIP_OK(hipStreamSynchronize(s));
+    // drop the dense copies
+    for (double *p : {d.Linv, d.LinvT}) {
+        h->allocs.erase(std::remove(h->allocs.begin(), h->allocs.end(), (void *)p), h->allocs.end());
+        (void)hipFree(p);
+    }
+    d.Linv = nullptr;
+    d.LinvT = nullptr;
+    d.sparse_linv = 1;
+    d.nnz_linv = nnz;
+    return CDCS_OK;
+}
+
 cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraints *A, const double *b,
                   const double *c, const cdcs_cliques *cl, hipStream_t s) {
     Dev &d = h->d;
@@ -457,6 +514,7 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
     if (info_h[0] != 0)
         return fail(CDCS_E_RANK,
                     "A D^-1 A^T is not positive definite (pivot " + std::to_string(info_h[1]) + "): A is rank deficient");
+    CK(compress_factors(h, s));
     CK(tune_projection(h, s));
     HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     return CDCS_OK;
@@ -876,8 +934,9 @@ cdcs_status cdcs_get_sizes(const cdcs_handle *h, cdcs_sizes *out) {
     out->nnz = h->d.nU;
     out->nslots = h->d.nslots;
     out->sparse_a = h->d.sparse;
-    out->pad_ = 0;
+    out->sparse_factor = h->d.sparse_linv;
     out->nnz_a = h->d.sparse ? h->d.nnzA : (int64_t)h->d.m * h->d.nU;
+    out->nnz_factor = h->d.sparse_linv ? h->d.nnz_linv : (int64_t)h->d.m * (h->d.m + 1) / 2;
     return CDCS_OK;
 }
 

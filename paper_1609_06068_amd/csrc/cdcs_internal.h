@@ -155,6 +155,14 @@ struct Dev {
     int32_t *tc_ptr = nullptr;     // [ntc+1]
     int32_t *tc_row = nullptr;     // [nnzA]  row of each coefficient, by touched entry
     double *tc_val = nullptr;      // [nnzA]  w_e * A_ie, by touched entry
+    // sparse inverse factors (used when L^-1 has few nonzeros): CSR rows of
+    // L^-1 (lower) and of L^-T (upper), FP64
+    int32_t sparse_linv = 0;
+    int64_t nnz_linv = 0;
+    int32_t *li_ptr = nullptr, *li_col = nullptr;
+    double *li_val = nullptr;
+    int32_t *lt_ptr = nullptr, *lt_col = nullptr;
+    double *lt_val = nullptr;
     double *Linv = nullptr;        // [m * m] row-major, L^-1 (lower)
     double *LinvT = nullptr;       // [m * m] row-major, L^-T (upper)
     int32_t *order = nullptr;      // [p] cliques by decreasing size
@@ -219,5 +227,10 @@ void launch_syrk(const float *Aw, int64_t ld, const double *s2, int m, double *M
 void launch_sp_syrk(const Dev &d, const int32_t *tid, double *M, hipStream_t s);
 void launch_potrf(double *M, int m, double *diag0, int32_t *info, hipStream_t s);
 void launch_trtri(const double *L, int m, double *LinvT, double *Linv, hipStream_t s);
+// Nonzeros of each row of a dense m x m triangle (lower: columns <= row,
+// upper: columns >= row) -> cnt[m]; then the CSR copy given ptr[m+1].
+void launch_tri_count(const double *T, int m, int upper, int32_t *cnt, hipStream_t s);
+void launch_tri_compress(const double *T, int m, int upper, const int32_t *ptr, int32_t *col, double *val,
+                         hipStream_t s);
 
 }  // namespace cdcs

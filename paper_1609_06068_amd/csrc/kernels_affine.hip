@@ -450,6 +450,21 @@ __global__ __launch_bounds__(kNT) void k_trmv(const double *__restrict__ T, int 
     if (lane == 0) vout[row] = acc;
 }
 
+// Sparse triangular product out = T vin with T in CSR (sparse inverse
+// factors): one wave per row, fixed summation order.
+__global__ __launch_bounds__(kNT) void k_csr_mv(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                                const double *__restrict__ val, const double *__restrict__ vin,
+                                                double *__restrict__ vout, int m, const Ctl *ctl) {
+    if (ctl != nullptr && ctl->stop) return;
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * (kNT / 64) + (threadIdx.x >> 6);
+    if (row >= m) return;
+    double acc = 0.0;
+    for (int32_t q = ptr[row] + lane; q < ptr[row + 1]; q += 64) acc += val[q] * vin[col[q]];
+    acc = wave_sum_d(acc);
+    if (lane == 0) vout[row] = acc;
+}
+
 // x = u - s2 * (Aw^T y): four rows of AwT (= (w A)^T, row-major, leading
 // dimension ldm, zero padded) per wave, 16 per workgroup; y staged in LDS.
 constexpr int kAtyRows = 16;
@@ -585,6 +600,12 @@ void launch_affine_part(const Dev &d, int part, const double *r2, double r2scale
     } else if (part == 3) {
         hipLaunchKernelGGL(k_reduce_t, dim3((d.m + kNT - 1) / kNT), dim3(kNT), 0, s, (const double *)d.tpart,
                            gemv_slices(d), r2, r2scale, d.t, d.m, ctl);
+    } else if (part == 1 && d.sparse_linv) {
+        const unsigned tb = (unsigned)((d.m + kNT / 64 - 1) / (kNT / 64));
+        hipLaunchKernelGGL(k_csr_mv, dim3(tb), dim3(kNT), 0, s, (const int32_t *)d.li_ptr, (const int32_t *)d.li_col,
+                           (const double *)d.li_val, (const double *)d.t, d.y1, d.m, ctl);
+        hipLaunchKernelGGL(k_csr_mv, dim3(tb), dim3(kNT), 0, s, (const int32_t *)d.lt_ptr, (const int32_t *)d.lt_col,
+                           (const double *)d.lt_val, (const double *)d.y1, y, d.m, ctl);
     } else if (part == 1) {
         const unsigned tb = (unsigned)((d.m + kNT / 64 - 1) / (kNT / 64));
         hipLaunchKernelGGL(k_trmv, dim3(tb), dim3(kNT), 0, s, (const double *)d.Linv, d.m, 0, (const double *)d.t,

@@ -284,6 +284,43 @@ __global__ __launch_bounds__(256) void k_sp_syrk(const int32_t *__restrict__ sp_
     }
 }
 
+// Nonzeros of row i of a triangle, one wave per row.
+__global__ __launch_bounds__(256) void k_tri_count(const double *__restrict__ T, int m, int upper,
+                                                   int32_t *__restrict__ cnt) {
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= m) return;
+    const int lo = upper ? row : 0, hi = upper ? m : row + 1;
+    int c = 0;
+    for (int j = lo + lane; j < hi; j += 64) c += (T[(int64_t)row * m + j] != 0.0);
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if (lane == 0) cnt[row] = c;
+}
+
+// CSR copy of the triangle's nonzeros, columns increasing; one wave per row,
+// 64 columns at a time compacted with a ballot.
+__global__ __launch_bounds__(256) void k_tri_compress(const double *__restrict__ T, int m, int upper,
+                                                      const int32_t *__restrict__ ptr, int32_t *__restrict__ col,
+                                                      double *__restrict__ val) {
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= m) return;
+    const int lo = upper ? row : 0, hi = upper ? m : row + 1;
+    int pos = ptr[row];
+    for (int j0 = lo; j0 < hi; j0 += 64) {
+        const int j = j0 + lane;
+        const double v = (j < hi) ? T[(int64_t)row * m + j] : 0.0;
+        const bool nz = v != 0.0;
+        const unsigned long long mask = __ballot(nz);
+        const int before = __popcll(mask & ((1ull << lane) - 1ull));
+        if (nz) {
+            col[pos + before] = j;
+            val[pos + before] = v;
+        }
+        pos += __popcll(mask);
+    }
+}
+
 __global__ void k_transpose(const double *__restrict__ in, int m, double *__restrict__ out) {
     __shared__ double tile[32][33];
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
@@ -317,6 +354,15 @@ void launch_potrf(double *M, int m, double *diag0, int32_t *info, hipStream_t s)
             hipLaunchKernelGGL(k_syrk_update, dim3(T * (T + 1) / 2), dim3(256), 0, s, M, m, kb, nb);
         }
     }
+}
+
+void launch_tri_count(const double *T, int m, int upper, int32_t *cnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_tri_count, dim3((m + 3) / 4), dim3(256), 0, s, T, m, upper, cnt);
+}
+
+void launch_tri_compress(const double *T, int m, int upper, const int32_t *ptr, int32_t *col, double *val,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_tri_compress, dim3((m + 3) / 4), dim3(256), 0, s, T, m, upper, ptr, col, val);
 }
 
 void launch_sp_syrk(const Dev &d, const int32_t *tid, double *M, hipStream_t s) {

@@ -216,6 +216,7 @@ def c2(torch):
 def test_c2_affine_projection_parity(torch, c2):
     orc = O.Oracle(c2)
     sol = cdcs.Solver(c2)
+    assert not sol.sparse_a and not sol.sparse_factor  # dense constraints: dense factor
     rng = np.random.default_rng(2)
     r1 = rng.standard_normal(c2.nU)
     r2 = rng.standard_normal(c2.m)
