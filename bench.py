@@ -294,17 +294,21 @@ def run_many(args, torch):
     setup_s = time.perf_counter() - t0
     _log(f"setup {setup_s:.2f}s  nnz={sol.nnz} m={sol.m} p={sol.p}")
     # cold solves to 1e-4, every instance stopping on its own
+    cap = 1 if args.profile else 3000
     st = sol.new_state("primal")
-    sol.solve(st, form="primal", rho=rho, tol=1e-4, max_iter=3000, check_every=GRAPH_CHUNK)  # warm graphs
+    sol.solve(st, form="primal", rho=rho, tol=1e-4, max_iter=cap, check_every=GRAPH_CHUNK)  # warm graphs
     st = sol.new_state("primal")
-    acc = sol.solve(st, form="primal", rho=rho, tol=1e-4, max_iter=3000, check_every=GRAPH_CHUNK)
+    acc = sol.solve(st, form="primal", rho=rho, tol=1e-4, max_iter=cap, check_every=GRAPH_CHUNK)
     torch.cuda.synchronize()
     inst = sol.instance_info()
     t2t = np.array([i.time_to_tol_s for i in inst])
     its = np.array([i.iters for i in inst])
     conv = np.array([i.status == cdcs.OK for i in inst])
-    _log(f"batch solve: {acc.iters} iterations, {conv.sum()}/{len(inst)} converged, {acc.loop_s:.3f}s; "
-         f"time to tol p50 {np.percentile(t2t[conv], 50) * 1e3:.2f}ms p99 {np.percentile(t2t[conv], 99) * 1e3:.2f}ms")
+    _log(f"batch solve: {acc.iters} iterations, {conv.sum()}/{len(inst)} converged, {acc.loop_s:.3f}s")
+    if conv.any():
+        _log(f"time to tol p50 {np.percentile(t2t[conv], 50) * 1e3:.2f}ms p99 {np.percentile(t2t[conv], 99) * 1e3:.2f}ms")
+    tuning = sol.tuning()
+    _log(f"projection plan: {tuning}")
     # Timed region: exactly K whole-batch iterations (no early exit).
     K, W = args.steps, args.warmup
     stt = sol.new_state("primal")
@@ -330,9 +334,23 @@ def run_many(args, torch):
                      "time_to_tol_p50_ms": float(np.percentile(t2t[conv], 50) * 1e3) if conv.any() else None,
                      "time_to_tol_p99_ms": float(np.percentile(t2t[conv], 99) * 1e3) if conv.any() else None,
                      "batch_solve_s": acc.loop_s},
-        "batched_vs_plain": batched_vs_plain(torch, sol, st, rho),
+        "batched_vs_plain": None if args.profile else batched_vs_plain(torch, sol, st, rho),
+        "projection_plan": tuning,
     })
-    if not args.no_cpu:
+    # per-kernel averages: projection, scatter, whole affine step
+    R = args.kernel_reps
+    kern = {}
+    for kid, name in ((cdcs.K_PROJECT, "project"), (cdcs.K_SCATTER, "scatter"), (cdcs.K_GEMV_AU, "affine")):
+        sol.profile_kernel(stt, kid, reps=2)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            sol.profile_kernel(stt, kid, reps=R)
+        g.replay()
+        kern[name] = {"us": time_events(torch, g.replay, reps_outer=3) / R * 1e3}
+        del g
+    result["kernels"] = kern
+    _log("kernels: " + ", ".join(f"{n} {v['us']:.1f}us" for n, v in kern.items()))
+    if not (args.no_cpu or args.profile):
         from threadpoolctl import threadpool_limits
 
         from oracle import oracle as orc

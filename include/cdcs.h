@@ -321,8 +321,8 @@ cdcs_status cdcs_profile_kernel(cdcs_handle *h, const cdcs_state *st, int32_t fo
  * (persistent = 1, `threads` per workgroup, `grid` workgroups), or each
  * bucket gets its own launch with its own workgroup size (persistent = 0).
  * Setup picks the faster form by timing both on the handle's cliques
- * (queue_us, buckets_us: microseconds per projection of all cliques on
- * generated nearly diagonal blocks).
+ * (queue_us, buckets_us = sum of bucket_us: microseconds per projection of
+ * all cliques on generated nearly diagonal blocks).
  */
 typedef struct {
     int32_t persistent;
@@ -332,6 +332,7 @@ typedef struct {
     int32_t bucket_size[8];
     int32_t bucket_threads[8];
     int32_t bucket_count[8];
+    float bucket_us[8];      /* best per-bucket launch time */
     float queue_us;
     float buckets_us;
 } cdcs_tuning;

@@ -85,7 +85,7 @@ class _Tuning(ctypes.Structure):
     _fields_ = [("persistent", ctypes.c_int32), ("threads", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("nbuckets", ctypes.c_int32), ("bucket_size", ctypes.c_int32 * 8),
                 ("bucket_threads", ctypes.c_int32 * 8), ("bucket_count", ctypes.c_int32 * 8),
-                ("queue_us", ctypes.c_float), ("buckets_us", ctypes.c_float)]
+                ("bucket_us", ctypes.c_float * 8), ("queue_us", ctypes.c_float), ("buckets_us", ctypes.c_float)]
 
 
 class _Sizes(ctypes.Structure):
@@ -287,8 +287,8 @@ class Solver:
         _check(load_library().cdcs_get_tuning(self._h, ctypes.byref(t)), "cdcs_get_tuning")
         nb = t.nbuckets
         return {"persistent": bool(t.persistent), "threads": t.threads, "grid": t.grid,
-                "buckets": [{"size": t.bucket_size[q], "threads": t.bucket_threads[q], "count": t.bucket_count[q]}
-                            for q in range(nb)],
+                "buckets": [{"size": t.bucket_size[q], "threads": t.bucket_threads[q], "count": t.bucket_count[q],
+                             "us": t.bucket_us[q]} for q in range(nb)],
                 "queue_us": t.queue_us, "buckets_us": t.buckets_us}
 
     def set_projection_plan(self, persistent: bool, threads: int = 0):

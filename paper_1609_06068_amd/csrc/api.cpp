@@ -51,6 +51,7 @@ struct Bucket {
     int count;
     int32_t *ids;  // device
     int nt = 256;  // workgroup size (autotuned)
+    float us = -1.0f;  // tuned launch time
 };
 
 // How the projection of every clique is launched: one persistent queue launch
@@ -353,6 +354,7 @@ cdcs_status upload_common(cdcs_handle *h, const std::vector<int32_t> &size, cons
     HIP_OK(hipMemsetAsync(d.cpart, 0, (size_t)(4 * p) * sizeof(double), s));
     CK(h->alloc(&d.vpart, 5 * (int64_t)vupdate_blocks(d)));
     CK(h->alloc(&d.obj, 2));
+    CK(h->alloc(&d.opart, objective_partials()));
     CK(h->alloc(&d.info, 4));
     HIP_OK(hipMemsetAsync(d.info, 0, 4 * sizeof(int32_t), s));
     CK(h->alloc(&d.ctl, 1));
@@ -533,7 +535,7 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
     std::vector<int32_t> size, gather, cnt;
     std::vector<double> wt, invD, s2, c, b;
     std::vector<float> Aw;
-    std::vector<int32_t> sblk, sblk_off(1, 0), syrk_jobs, trtri_jobs;
+    std::vector<int32_t> sblk, sblk_off(1, 0), syrk_jobs, trtri_jobs, rjobs, ejobs;
     h->off_host.assign(1, 0);
     int64_t Atot = 0, Ftot = 0;
     d.smax = 0;
@@ -586,6 +588,16 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
             trtri_jobs.push_back(q);
             trtri_jobs.push_back(j);
         }
+        for (int32_t r = 0; r < P.m; r += 4) {
+            rjobs.push_back(q);
+            rjobs.push_back(m_off.back() + r);
+            rjobs.push_back(std::min<int32_t>(4, P.m - r));
+            rjobs.push_back(0);
+        }
+        for (int64_t e0 = 0; e0 < P.nU; e0 += 1024) {
+            ejobs.push_back(q);
+            ejobs.push_back((int32_t)e0);
+        }
         U_off.push_back(u0 + P.nU);
         m_off.push_back(m_off.back() + P.m);
         k_off.push_back(k_off.back() + P.p);
@@ -615,6 +627,36 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
     CK(upload(h, &B.sblk_off, sblk_off, s));
     CK(upload(h, &B.syrk_jobs, syrk_jobs, s));
     CK(upload(h, &B.trtri_jobs, trtri_jobs, s));
+    // largest jobs first (rows of the longest instances, blocks of the instances
+    // with the most constraints), so no long job starts last
+    {
+        std::vector<int32_t> order((size_t)(rjobs.size() / 4));
+        for (size_t t = 0; t < order.size(); ++t) order[t] = (int32_t)t;
+        auto rwork = [&](int32_t t) {
+            const int32_t q = rjobs[(size_t)t * 4];
+            return (U_off[(size_t)q + 1] - U_off[(size_t)q]) * rjobs[(size_t)t * 4 + 2];
+        };
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return rwork(a) > rwork(b); });
+        std::vector<int32_t> sorted;
+        sorted.reserve(rjobs.size());
+        for (int32_t t : order) sorted.insert(sorted.end(), rjobs.begin() + (size_t)t * 4, rjobs.begin() + (size_t)t * 4 + 4);
+        rjobs.swap(sorted);
+        std::vector<int32_t> eorder((size_t)(ejobs.size() / 2));
+        for (size_t t = 0; t < eorder.size(); ++t) eorder[t] = (int32_t)t;
+        auto ework = [&](int32_t t) {
+            const int32_t q = ejobs[(size_t)t * 2];
+            return m_off[(size_t)q + 1] - m_off[(size_t)q];
+        };
+        std::stable_sort(eorder.begin(), eorder.end(), [&](int32_t a, int32_t b) { return ework(a) > ework(b); });
+        std::vector<int32_t> esorted;
+        esorted.reserve(ejobs.size());
+        for (int32_t t : eorder) esorted.insert(esorted.end(), ejobs.begin() + (size_t)t * 2, ejobs.begin() + (size_t)t * 2 + 2);
+        ejobs.swap(esorted);
+    }
+    CK(upload(h, &B.rjobs, rjobs, s));
+    CK(upload(h, &B.ejobs, ejobs, s));
+    B.nrjobs = (int32_t)(rjobs.size() / 4);
+    B.nejobs = (int32_t)(ejobs.size() / 2);
     B.nsblk = (int32_t)(sblk.size() / 4);
     B.nsyrk = (int32_t)(syrk_jobs.size() / 4);
     CK(h->alloc(&d.spart, 2 * (int64_t)B.nsblk));
@@ -767,6 +809,7 @@ cdcs_status tune_projection(cdcs_handle *h, hipStream_t s) {
                 bk.nt = nt;
             }
         }
+        bk.us = best;
         bsum += best;
     }
     h->plan.buckets_us = bsum;
@@ -1186,6 +1229,7 @@ cdcs_status cdcs_get_tuning(const cdcs_handle *h, cdcs_tuning *out) {
         out->bucket_size[q] = h->buckets[(size_t)q].smax;
         out->bucket_threads[q] = h->buckets[(size_t)q].nt;
         out->bucket_count[q] = h->buckets[(size_t)q].count;
+        out->bucket_us[q] = h->buckets[(size_t)q].us;
     }
     out->queue_us = h->plan.queue_us;
     out->buckets_us = h->plan.buckets_us;

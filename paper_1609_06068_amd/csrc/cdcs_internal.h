@@ -113,6 +113,10 @@ struct Batch {
     int32_t *syrk_jobs = nullptr;  // [nsyrk * 4] (q, I, J, 0) tiles of M_q
     int32_t nsyrk = 0;
     int32_t *trtri_jobs = nullptr; // [m * 2] (q, j)
+    int32_t *rjobs = nullptr;      // [nrjobs * 4] (q, first row, rows <= 4, 0) of the A u product
+    int32_t nrjobs = 0;
+    int32_t *ejobs = nullptr;      // [nejobs * 2] (q, first entry in q) of 1024-entry A^T y blocks
+    int32_t nejobs = 0;
     int32_t *istop = nullptr;      // [nprob] 0 running, 1 converged, 2 iteration cap
     int32_t *iiters = nullptr;     // [nprob] iterations at stop
     uint64_t *itime = nullptr;     // [nprob] device wall clock at stop
@@ -179,6 +183,7 @@ struct Dev {
     double *vpart = nullptr;       // [nvblk * 5]
     double *hist = nullptr;        // [hist_cap * 2]
     double *obj = nullptr;         // [2]
+    double *opart = nullptr;       // [objective_partials()] partial sums of the objectives
     int32_t hist_cap = 0;
     int32_t *info = nullptr;       // [4] setup status words
     Ctl *ctl = nullptr;
@@ -220,6 +225,7 @@ void launch_affine_part(const Dev &d, int part, const double *r2, double r2scale
 void launch_gather_f64(const Dev &d, const double *x, double *packed, hipStream_t s);
 void launch_scatter_f64(const Dev &d, const double *packed, double *out, hipStream_t s);
 void launch_objectives(const Dev &d, const double *x, const double *y, hipStream_t s);
+int objective_partials();
 
 // setup kernels (kernels_setup.hip)
 void launch_syrk(const float *Aw, int64_t ld, const double *s2, int m, double *M, hipStream_t s);

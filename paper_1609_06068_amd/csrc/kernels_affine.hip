@@ -506,14 +506,35 @@ __global__ __launch_bounds__(kNT) void k_gemv_ATy(const float *__restrict__ AwT,
     }
 }
 
+// Objective terms <c, x>_w and <b, y>: fixed-shape two-pass reduction
+// (kObjBlocks grid-stride partials, then one workgroup in block order).
+constexpr int kObjBlocks = 512;
+
 __global__ __launch_bounds__(kNT) void k_objectives(const double *__restrict__ c, const double *__restrict__ wt,
                                                     const double *__restrict__ x, int64_t nU,
                                                     const double *__restrict__ b, const double *__restrict__ y,
-                                                    int m, double *__restrict__ out) {
+                                                    int m, double *__restrict__ part) {
     __shared__ double red[kNT / 64];
     double s1 = 0.0, s2 = 0.0;
-    for (int64_t e = threadIdx.x; e < nU; e += kNT) s1 += wt[e] * c[e] * x[e];
-    for (int i = threadIdx.x; i < m; i += kNT) s2 += b[i] * y[i];
+    for (int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x; e < nU; e += (int64_t)kObjBlocks * kNT)
+        s1 += wt[e] * c[e] * x[e];
+    for (int i = blockIdx.x * kNT + threadIdx.x; i < m; i += kObjBlocks * kNT) s2 += b[i] * y[i];
+    s1 = block_sum_d(s1, red);
+    s2 = block_sum_d(s2, red);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x + 0] = s1;
+        part[2 * blockIdx.x + 1] = s2;
+    }
+}
+
+__global__ __launch_bounds__(kNT) void k_objectives_finish(const double *__restrict__ part,
+                                                           double *__restrict__ out) {
+    __shared__ double red[kNT / 64];
+    double s1 = 0.0, s2 = 0.0;
+    for (int q = threadIdx.x; q < kObjBlocks; q += kNT) {
+        s1 += part[2 * q];
+        s2 += part[2 * q + 1];
+    }
     s1 = block_sum_d(s1, red);
     s2 = block_sum_d(s2, red);
     if (threadIdx.x == 0) {
@@ -638,9 +659,12 @@ void launch_scatter_f64(const Dev &d, const double *packed, double *out, hipStre
                        packed, out, d.nU);
 }
 
+int objective_partials() { return 2 * kObjBlocks; }
+
 void launch_objectives(const Dev &d, const double *x, const double *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_objectives, dim3(1), dim3(kNT), 0, s, (const double *)d.c, (const double *)d.wt, x, d.nU,
-                       (const double *)d.b, y, d.m, d.obj);
+    hipLaunchKernelGGL(k_objectives, dim3(kObjBlocks), dim3(kNT), 0, s, (const double *)d.c, (const double *)d.wt, x,
+                       d.nU, (const double *)d.b, y, d.m, d.opart);
+    hipLaunchKernelGGL(k_objectives_finish, dim3(1), dim3(kNT), 0, s, (const double *)d.opart, d.obj);
 }
 
 }  // namespace cdcs

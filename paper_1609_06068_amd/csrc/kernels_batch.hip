@@ -149,41 +149,52 @@ __global__ void k_bcheck_finish(const int32_t *nrunning, Ctl *ctl) {
 }
 
 // t_r = A_q(r) . (w u)_q - r2scale r2_r, one wave per global constraint row.
+// t = A_q (w u_q) - r2scale r2 for up to 4 consecutive rows of one instance
+// per wave (job (q, first row, rows)): each u element loaded once serves all
+// the wave's rows.  Lanes stride the row in float4 groups; FP64 accumulation.
+constexpr int kRowsPerWave = 4;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(kNT) void k_bgemv_Au(const float *__restrict__ A, const int64_t *__restrict__ A_off,
-                                                  const int32_t *__restrict__ A_ld,
-                                                  const int32_t *__restrict__ rinst, const int32_t *__restrict__ m_off,
+                                                  const int32_t *__restrict__ A_ld, const int4 *__restrict__ rjobs,
+                                                  int njobs, const int32_t *__restrict__ m_off,
                                                   const int64_t *__restrict__ U_off,
                                                   const int32_t *__restrict__ istop, const double *__restrict__ u,
                                                   const double *__restrict__ r2, double r2scale,
-                                                  double *__restrict__ t, int mtot, const Ctl *ctl) {
+                                                  double *__restrict__ t, const Ctl *ctl) {
     if (ctl != nullptr && ctl->stop) return;
     const int lane = threadIdx.x & 63;
-    const int r = blockIdx.x * (kNT / 64) + (threadIdx.x >> 6);
-    if (r >= mtot) return;
-    const int q = rinst[r];
+    const int jb = blockIdx.x * (kNT / 64) + (threadIdx.x >> 6);
+    if (jb >= njobs) return;
+    const int4 job = rjobs[jb];  // (q, first row (global), rows, 0)
+    const int q = job.x, r0 = job.y, nr = job.z;
     if (istop != nullptr && istop[q]) return;
     const int64_t u0 = U_off[q];
     const int nU = (int)(U_off[q + 1] - u0);
-    const float *row = A + A_off[q] + (int64_t)(r - m_off[q]) * A_ld[q];
+    const int ld = A_ld[q];
+    const float *base = A + A_off[q] + (int64_t)(r0 - m_off[q]) * ld;
     const double *uq = u + u0;
-    double acc0 = 0.0, acc1 = 0.0;
-    int j = lane * 4;
-    for (; j + 260 <= nU; j += 512) {
-        const float4 a = *reinterpret_cast<const float4 *>(row + j);
-        const float4 b = *reinterpret_cast<const float4 *>(row + j + 256);
-        acc0 += (double)a.x * uq[j] + (double)a.y * uq[j + 1] + (double)a.z * uq[j + 2] + (double)a.w * uq[j + 3];
-        acc1 += (double)b.x * uq[j + 256] + (double)b.y * uq[j + 257] + (double)b.z * uq[j + 258] +
-                (double)b.w * uq[j + 259];
-    }
-    for (; j < nU; j += 256) {
-        const float4 a = *reinterpret_cast<const float4 *>(row + j);
-        const float av[4] = {a.x, a.y, a.z, a.w};
+    double acc[kRowsPerWave];
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-            if (j + v < nU) acc0 += (double)av[v] * uq[j + v];
+    for (int v = 0; v < kRowsPerWave; ++v) acc[v] = 0.0;
+    for (int j = lane * 4; j < nU; j += 256) {
+        double uj[4];  // (u_q may start at an odd entry: scalar loads)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) uj[v] = (j + v < nU) ? uq[j + v] : 0.0;
+#pragma unroll
+        for (int v = 0; v < kRowsPerWave; ++v) {
+            if (v < nr) {
+                // A is streamed once per product: non-temporal loads keep u in the caches
+                const f32x4 a = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(base + (int64_t)v * ld + j));
+                acc[v] += (double)a.x * uj[0] + (double)a.y * uj[1] + (double)a.z * uj[2] + (double)a.w * uj[3];
+            }
+        }
     }
-    const double s = wave_sum_d(acc0 + acc1);
-    if (lane == 0) t[r] = s - r2scale * r2[r];
+#pragma unroll
+    for (int v = 0; v < kRowsPerWave; ++v) {
+        const double sv = wave_sum_d(acc[v]);
+        if (lane == 0 && v < nr) t[r0 + v] = sv - r2scale * r2[r0 + v];
+    }
 }
 
 // One triangular product per instance: out_q = T_q in_q, T_q lower (upper = 0)
@@ -209,34 +220,45 @@ __global__ __launch_bounds__(kNT) void k_btrmv(const double *__restrict__ T, con
     if (lane == 0) vout[r] = acc;
 }
 
-// x_e = u_e - s2_e (A_q^T y_q)_e: one thread per entry, the column walk over
-// the instance's m_q rows is coalesced across neighbouring entries.
+// x_e = u_e - s2_e (A_q^T y_q)_e: a workgroup takes 1024 consecutive entries
+// of one instance (job (q, first entry within the instance)), each thread 4
+// of them with float4 loads down the instance's m_q rows (coalesced across
+// the workgroup's threads).
 __global__ __launch_bounds__(kNT) void k_bgemv_ATy(const float *__restrict__ A, const int64_t *__restrict__ A_off,
-                                                   const int32_t *__restrict__ A_ld,
-                                                   const int32_t *__restrict__ einst,
+                                                   const int32_t *__restrict__ A_ld, const int2 *__restrict__ ejobs,
                                                    const int32_t *__restrict__ m_off,
                                                    const int64_t *__restrict__ U_off,
                                                    const int32_t *__restrict__ istop, const double *__restrict__ y,
                                                    const double *__restrict__ u, const double *__restrict__ s2,
-                                                   double *__restrict__ x, int64_t nU, const Ctl *ctl) {
+                                                   double *__restrict__ x, const Ctl *ctl) {
     if (ctl != nullptr && ctl->stop) return;
-    const int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    if (e >= nU) return;
-    const int q = einst[e];
+    const int2 job = ejobs[blockIdx.x];
+    const int q = job.x;
     if (istop != nullptr && istop[q]) return;
-    const int64_t j = e - U_off[q];
+    const int64_t u0 = U_off[q];
+    const int nU = (int)(U_off[q + 1] - u0);
+    const int j = job.y + 4 * (int)threadIdx.x;
+    if (j >= nU) return;
     const int ld = A_ld[q];
     const int m0 = m_off[q], mq = m_off[q + 1] - m0;
     const float *col = A + A_off[q] + j;
     const double *yq = y + m0;
-    double a0 = 0.0, a1 = 0.0;
-    int i = 0;
-    for (; i + 1 < mq; i += 2) {
-        a0 += (double)col[(int64_t)i * ld] * yq[i];
-        a1 += (double)col[(int64_t)(i + 1) * ld] * yq[i + 1];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 4
+    for (int i = 0; i < mq; ++i) {
+        const f32x4 a = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(col + (int64_t)i * ld));
+        const double yi = yq[i];
+        a0 += (double)a.x * yi;
+        a1 += (double)a.y * yi;
+        a2 += (double)a.z * yi;
+        a3 += (double)a.w * yi;
     }
-    if (i < mq) a0 += (double)col[(int64_t)i * ld] * yq[i];
-    x[e] = u[e] - s2[e] * (a0 + a1);
+    const double av[4] = {a0, a1, a2, a3};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t e = u0 + j + v;
+        if (j + v < nU) x[e] = u[e] - s2[e] * av[v];
+    }
 }
 
 // ---- setup: per-instance M_q = A_q diag(s2_q) A_q^T, Cholesky, inverse ----
@@ -401,20 +423,20 @@ void launch_bcheck_primal(const Dev &d, double rho, hipStream_t s) {
 void launch_baffine(const Dev &d, const double *r2, double r2scale, double *x, double *y, const Ctl *ctl,
                     const int32_t *istop, hipStream_t s) {
     const Batch &B = *d.batch;
-    hipLaunchKernelGGL(k_bgemv_Au, dim3(waves_blocks(d.m)), dim3(kNT), 0, s, (const float *)d.Aw,
-                       (const int64_t *)B.A_off, (const int32_t *)B.A_ld, (const int32_t *)B.rinst,
+    hipLaunchKernelGGL(k_bgemv_Au, dim3(waves_blocks(B.nrjobs)), dim3(kNT), 0, s, (const float *)d.Aw,
+                       (const int64_t *)B.A_off, (const int32_t *)B.A_ld, (const int4 *)B.rjobs, B.nrjobs,
                        (const int32_t *)B.m_off, (const int64_t *)B.U_off, istop, (const double *)d.u, r2, r2scale,
-                       d.t, d.m, ctl);
+                       d.t, ctl);
     hipLaunchKernelGGL(k_btrmv, dim3(waves_blocks(d.m)), dim3(kNT), 0, s, (const double *)d.Linv,
                        (const int64_t *)B.F_off, (const int32_t *)B.rinst, (const int32_t *)B.m_off, istop, 0,
                        (const double *)d.t, d.y1, d.m, ctl);
     hipLaunchKernelGGL(k_btrmv, dim3(waves_blocks(d.m)), dim3(kNT), 0, s, (const double *)d.LinvT,
                        (const int64_t *)B.F_off, (const int32_t *)B.rinst, (const int32_t *)B.m_off, istop, 1,
                        (const double *)d.y1, y, d.m, ctl);
-    hipLaunchKernelGGL(k_bgemv_ATy, dim3((unsigned)((d.nU + kNT - 1) / kNT)), dim3(kNT), 0, s, (const float *)d.Aw,
-                       (const int64_t *)B.A_off, (const int32_t *)B.A_ld, (const int32_t *)B.einst,
+    hipLaunchKernelGGL(k_bgemv_ATy, dim3((unsigned)B.nejobs), dim3(kNT), 0, s, (const float *)d.Aw,
+                       (const int64_t *)B.A_off, (const int32_t *)B.A_ld, (const int2 *)B.ejobs,
                        (const int32_t *)B.m_off, (const int64_t *)B.U_off, istop, (const double *)y,
-                       (const double *)d.u, (const double *)d.s2, x, d.nU, ctl);
+                       (const double *)d.u, (const double *)d.s2, x, ctl);
 }
 
 void launch_bsetup(const Dev &d, double *M, hipStream_t s) {

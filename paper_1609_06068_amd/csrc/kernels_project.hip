@@ -93,12 +93,13 @@ __device__ __forceinline__ void pair_dyn(int t, int r, int K, int &a, int &b) {
     b = 1 + y;
 }
 
-// Full-wave lane shifts: lane i receives lane i+1 (shl) or lane i-1 (shr).
+// Full-wave lane shifts: lane i receives lane i+1 (shl) or lane i-1 (shr);
+// lane 0 of the right shift has no source and keeps `old` (bound control off).
 __device__ __forceinline__ float wave_shl1(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
 }
-__device__ __forceinline__ float wave_shr1(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+__device__ __forceinline__ float wave_shr1(float v, float old) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x138, 0xF, 0xF, false));
 }
 
 // Register-tiled S x S products on a GR x GC thread grid (GR = 16 rows of
@@ -242,7 +243,7 @@ __device__ __forceinline__ void product_store(const float *X, const float *Y, co
 // Small per-workgroup LDS of the projection (sized for the largest bucket).
 struct ProjSmall {
     float2 cs[48];               // rotations of one step: (c, s) of pair t
-    int pq[48];                  // its indices P | Q << 16 (P < Q)
+    int4 pq[48];                 // its indices P < Q as byte offsets (P LD, Q LD, P, Q) * 4
     float t[48];                 // t * a_PQ of pair t
     float lam[96], lp[96];       // eigenvalues, clamped eigenvalues
     float redf[8];
@@ -400,60 +401,74 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
                     ta = t * apq;
                 }
                 sm.cs[tid] = make_float2(c, s);
-                sm.pq[tid] = P | (Q << 16);
+                sm.pq[tid] = make_int4(P * LD * 4, Q * LD * 4, P * 4, Q * 4);
                 sm.t[tid] = ta;
             }
             __syncthreads();
             // A <- J^T A J on this thread's lower 2x2 blocks; the transposed
             // block is written alongside.
+            char *const A8 = reinterpret_cast<char *>(sA);
+#define AE(off) (*reinterpret_cast<float *>(A8 + (off)))
 #pragma unroll
             for (int q = 0; q < NA; ++q) {
                 const int I = aI[q], J = aJ[q];
                 if (I < 0) continue;
-                const int pq1 = sm.pq[I];
-                const int p1 = pq1 & 0xFFFF, q1 = pq1 >> 16;
+                const int4 o1 = sm.pq[I];  // P1 LD, Q1 LD, P1, Q1 (bytes)
                 if (I == J) {
                     const float ta = sm.t[I];
-                    sA[p1 * LD + p1] -= ta;
-                    sA[q1 * LD + q1] += ta;
-                    sA[p1 * LD + q1] = 0.0f;
-                    sA[q1 * LD + p1] = 0.0f;
+                    AE(o1.x + o1.z) -= ta;
+                    AE(o1.y + o1.w) += ta;
+                    AE(o1.x + o1.w) = 0.0f;
+                    AE(o1.y + o1.z) = 0.0f;
                 } else {
-                    const int pq2 = sm.pq[J];
-                    const int p2 = pq2 & 0xFFFF, q2 = pq2 >> 16;
+                    const int4 o2 = sm.pq[J];
                     const float2 cs1 = sm.cs[I], cs2 = sm.cs[J];
                     const float c1 = cs1.x, s1 = cs1.y, c2 = cs2.x, s2 = cs2.y;
-                    const float a00 = sA[p1 * LD + p2], a01 = sA[p1 * LD + q2];
-                    const float a10 = sA[q1 * LD + p2], a11 = sA[q1 * LD + q2];
+                    const float a00 = AE(o1.x + o2.z), a01 = AE(o1.x + o2.w);
+                    const float a10 = AE(o1.y + o2.z), a11 = AE(o1.y + o2.w);
                     const float b00 = c1 * a00 - s1 * a10, b01 = c1 * a01 - s1 * a11;
                     const float b10 = s1 * a00 + c1 * a10, b11 = s1 * a01 + c1 * a11;
                     const float n00 = c2 * b00 - s2 * b01, n01 = s2 * b00 + c2 * b01;
                     const float n10 = c2 * b10 - s2 * b11, n11 = s2 * b10 + c2 * b11;
-                    sA[p1 * LD + p2] = n00;
-                    sA[p1 * LD + q2] = n01;
-                    sA[q1 * LD + p2] = n10;
-                    sA[q1 * LD + q2] = n11;
-                    sA[p2 * LD + p1] = n00;
-                    sA[q2 * LD + p1] = n01;
-                    sA[p2 * LD + q1] = n10;
-                    sA[q2 * LD + q1] = n11;
+                    AE(o1.x + o2.z) = n00;
+                    AE(o1.x + o2.w) = n01;
+                    AE(o1.y + o2.z) = n10;
+                    AE(o1.y + o2.w) = n11;
+                    AE(o2.x + o1.z) = n00;
+                    AE(o2.y + o1.z) = n01;
+                    AE(o2.x + o1.w) = n10;
+                    AE(o2.y + o1.w) = n11;
                 }
             }
+#undef AE
             // V <- V J in registers: (V_P, V_Q) <- (c V_P - s V_Q, s V_P + c V_Q);
             // the top column is P unless the pair is reversed (top index > bottom).
-            {
+            // Rows past K (zero in these columns) are skipped per wave.
+            if (HK > 1) {
                 int ta_, tb_;
                 pair_dyn(lane, r, K, ta_, tb_);
                 const float2 cs = sm.cs[vlane ? lane : 0];
                 const float c = cs.x, sg = (ta_ > tb_) ? -cs.y : cs.y;
+                const bool first = lane == 0, last = lane == HK - 1;
 #pragma unroll
                 for (int j = 0; j < RPW; ++j) {
-                    const float nt = c * vt[j] - sg * vb[j];
-                    const float nb = sg * vt[j] + c * vb[j];
-                    const float up = wave_shl1(nt);  // top of lane + 1
-                    const float dn = wave_shr1(nb);  // bottom of lane - 1
-                    vt[j] = (lane == 0) ? nt : (lane == HK - 1) ? nb : up;
-                    vb[j] = (lane == 0) ? (HK == 1 ? nb : up) : dn;
+                    if (wv + j * NW < K) {
+                        const float nt = c * vt[j] - sg * vb[j];
+                        const float nb = sg * vt[j] + c * vb[j];
+                        const float up = wave_shl1(nt);  // top of lane + 1
+                        vt[j] = first ? nt : (last ? nb : up);
+                        vb[j] = wave_shr1(nb, up);  // bottom of lane - 1; lane 0: top of lane 1
+                    }
+                }
+            } else {
+                // one pair (K = 2): a rotation, no movement
+                const float2 cs = sm.cs[0];
+#pragma unroll
+                for (int j = 0; j < RPW; ++j) {
+                    const float nt = cs.x * vt[j] - cs.y * vb[j];
+                    const float nb = cs.y * vt[j] + cs.x * vb[j];
+                    vt[j] = nt;
+                    vb[j] = nb;
                 }
             }
             __syncthreads();

@@ -9,6 +9,12 @@ scaled FETCH and WRITE bytes per launch and the source hash of the kernels
 (bench.py reports `traffic` only while the hash matches).
 
 usage: python -m paper_1609_06068_amd.pmc_summary FETCH_CSV WRITE_CSV HASH OUT_JSON
+       python -m paper_1609_06068_amd.pmc_summary trace KERNEL_TRACE_CSV [MIN_US]
+
+The `trace` form prints, per kernel of a `rocprofv3 --kernel-trace` CSV, the
+launch count and the median / mean duration of the launches longer than
+MIN_US (default 5 us): launches of captured graphs after the device stop flag
+is set return at once and would otherwise dominate the statistics.
 """
 from __future__ import annotations
 
@@ -20,8 +26,9 @@ from collections import defaultdict
 
 PROBE_BYTES = 1 << 30
 PROBE_PATTERN = re.compile(r"MulFunctor")
-KERNELS = {"gemv_Au": r"k_gemv_Au<", "gemv_ATy": r"k_gemv_ATy", "project": r"k_project<",
-           "scatter": r"k_scatter_primal", "trmv": r"k_trmv", "reduce_t": r"k_reduce_t"}
+KERNELS = {"gemv_Au": r"k_gemv_Au<", "gemv_ATy": r"k_gemv_ATy", "project": r"k_project(<|_queue<)",
+           "scatter": r"k_scatter_primal", "trmv": r"k_trmv", "reduce_t": r"k_reduce_t",
+           "spmv_Au": r"k_spmv_Au", "sp_xcorr": r"k_sp_xcorr", "csr_mv": r"k_csr_mv"}
 
 
 def _read(path, counter):
@@ -64,7 +71,32 @@ def summarise(fetch_csv, write_csv, source_hash):
     return out
 
 
+def trace_summary(trace_csv, min_us=5.0):
+    """Per-kernel launch statistics of a kernel-trace CSV (text table)."""
+    dur = defaultdict(list)
+    with open(trace_csv) as fh:
+        for row in csv.DictReader(fh):
+            name = (row.get("Kernel_Name") or "").replace("cdcs::(anonymous namespace)::", "")
+            name = name.replace("void ", "").split("(")[0]
+            dur[name].append((int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e3)
+    rows = []
+    for name, v in dur.items():
+        real = sorted(x for x in v if x > min_us)
+        if not real:
+            continue
+        rows.append((sum(real), name, len(v), len(real), real[len(real) // 2], sum(real) / len(real)))
+    rows.sort(reverse=True)
+    out = [f"{'kernel':44s} {'launches':>8s} {'>' + str(min_us) + 'us':>8s} {'median_us':>10s} {'mean_us':>10s} "
+           f"{'total_ms':>9s}"]
+    for tot, name, n, nr, med, mean in rows:
+        out.append(f"{name[:44]:44s} {n:8d} {nr:8d} {med:10.1f} {mean:10.1f} {tot / 1e3:9.2f}")
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
+    if sys.argv[1] == "trace":
+        print(trace_summary(sys.argv[2], float(sys.argv[3]) if len(sys.argv) > 3 else 5.0))
+        sys.exit(0)
     fetch_csv, write_csv, h, out_json = sys.argv[1:5]
     res = summarise(fetch_csv, write_csv, h)
     with open(out_json, "w") as fh:
