@@ -178,7 +178,7 @@ SINGLE = {
                acc_cap=500, cpu_iters=50, traffic="traffic_c2.json"),
     "c3": dict(desc="clique-tree SDP, 3000 cliques of 4..96 (separators 1..8), m=8000 sparse A "
                     "(20 coefficients per constraint)",
-               acc_cap=3000, cpu_iters=2, traffic="traffic_c3.json"),
+               acc_cap=6000, cpu_iters=2, traffic="traffic_c3.json"),
 }
 
 
@@ -348,8 +348,29 @@ def run_many(args, torch):
         g.replay()
         kern[name] = {"us": time_events(torch, g.replay, reps_outer=3) / R * 1e3}
         del g
+    # algorithmic bytes of the affine step: A_q read twice (FP32, rows of ld_q),
+    # the triangular factors (FP64 triangles) and the vectors u, x, t, y
+    a_bytes = 0
+    f_bytes = 0
+    for pr in probs:
+        ld = (pr.nU + 3) // 4 * 4
+        a_bytes += 2 * pr.m * ld * 4
+        f_bytes += 2 * (pr.m * (pr.m + 1) // 2) * 8
+    aff_bytes = a_bytes + f_bytes + sol.nnz * 8 * 4 + sol.m * 8 * 4
+    kern["affine"]["GB_s"] = aff_bytes / (kern["affine"]["us"] * 1e-6) / 1e9
     result["kernels"] = kern
     _log("kernels: " + ", ".join(f"{n} {v['us']:.1f}us" for n, v in kern.items()))
+    if kern["affine"]["us"] >= kern["project"]["us"]:
+        gbs = kern["affine"]["GB_s"]
+        result["roofline"] = {"bound": "hbm", "kernel": "affine (4 kernels)", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                              "algorithmic_bytes": aff_bytes, "avg_us": kern["affine"]["us"]}
+    else:
+        fl = projection_model_flops(sol.sizes)
+        ach = fl / (kern["project"]["us"] * 1e-6) / 1e12
+        result["roofline"] = {"bound": "alu", "kernel": "project", "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS,
+                              "unit": "TFLOP/s", "frac": ach / FP32_VALU_PEAK_TFLOPS, "traffic": None,
+                              "algorithmic_flops": fl, "avg_us": kern["project"]["us"]}
     if not (args.no_cpu or args.profile):
         from threadpoolctl import threadpool_limits
 
