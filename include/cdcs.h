@@ -225,6 +225,11 @@ cdcs_status cdcs_clique_offsets(const cdcs_handle *h, int64_t *off_host);
  *         row-major s x s matrix, block t at voff[t]
  *   eoff, voff device int64 [nb+1] (required when evals/evecs are given)
  *   smax  host: the largest size in sizes[] (selects the kernel variant)
+ * Accuracy: the sweeps stop once the off-diagonal part left in the rotated
+ * block is at most 2^-20 ||W||_F; since the projection onto the PSD cone is
+ * 1-Lipschitz in the Frobenius norm, P is then within 2^-20 ||W||_F (plus FP32
+ * rounding) of P(W).  When evals or evecs are requested the sweeps run to
+ * 2^-23 ||W||_F, so the eigenpairs themselves are converged.
  * A block whose size lies outside 1..smax is skipped (its P is not written);
  * nb <= 0 is a no-op.  Errors: CDCS_E_ARG (smax outside 1..CDCS_MAX_CLIQUE,
  * NULL W/P/sizes/off), CDCS_E_DEVICE.
