@@ -66,7 +66,7 @@ struct ProjArgs {
 // Size bucket (padded clique size) of the projection kernel for cliques <= smax:
 // 16, 32, 48, 64, 80 or 96.
 int proj_bucket(int smax);
-// Workgroup sizes built for a bucket: 64 (S = 16), 256, 512 (S >= 48).
+// Workgroup sizes built for a bucket: 64 (S <= 32), 256, 512 (S >= 48).
 bool proj_threads_ok(int S, int nthreads);
 // One launch over a.nblk cliques of one bucket (workgroup b: clique a.ids[b]).
 void launch_project(const ProjArgs &a, int smax, int nthreads, hipStream_t s);

@@ -565,7 +565,8 @@ constexpr int proj_waves_per_eu(int S, int NT) {
     const int lds = 2 * S * (S + 1) * 4 + 2048;
     const int wg = 163840 / lds;
     const int w = wg * (NT / 64) / 4;
-    return w < 1 ? 1 : (w > 4 ? 4 : w);
+    const int cap = NT == 64 ? 2 : 4;  // one-wave workgroups hold all of V in registers
+    return w < 1 ? 1 : (w > cap ? cap : w);
 }
 
 // One launch per size bucket: workgroup b projects clique ids[b] (or b).
@@ -789,7 +790,7 @@ int proj_bucket(int smax) {
 
 bool proj_threads_ok(int S, int nthreads) {
     if (nthreads == 256) return true;
-    if (nthreads == 64) return S <= 16;
+    if (nthreads == 64) return S <= 32;
     if (nthreads == 512) return S >= 48;
     return false;
 }
@@ -800,7 +801,7 @@ void launch_project(const ProjArgs &a, int smax, int nthreads, hipStream_t s) {
     const int nt = proj_threads_ok(S, nthreads) ? nthreads : 256;
     switch (S) {
     case 16: nt == 64 ? launch_t<16, 64>(a, s) : launch_t<16, 256>(a, s); break;
-    case 32: launch_t<32, 256>(a, s); break;
+    case 32: nt == 64 ? launch_t<32, 64>(a, s) : launch_t<32, 256>(a, s); break;
     case 48: nt == 512 ? launch_t<48, 512>(a, s) : launch_t<48, 256>(a, s); break;
     case 64: nt == 512 ? launch_t<64, 512>(a, s) : launch_t<64, 256>(a, s); break;
     case 80: nt == 512 ? launch_t<80, 512>(a, s) : launch_t<80, 256>(a, s); break;
