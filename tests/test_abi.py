@@ -53,3 +53,40 @@ def test_packing_roundtrip():
         assert np.array_equal(a, b)
     # slot (a, b) of a block sits at a(a+1)/2 + b
     assert packed[1 + (2 * 3 // 2 + 1)] == blocks[1][2, 1]
+
+
+# C structs of include/cdcs.h and their ctypes mirrors in the binding.
+_STRUCTS = {
+    "cdcs_pattern": cdcs._Pattern, "cdcs_cliques": cdcs._Cliques, "cdcs_constraints": cdcs._Constraints,
+    "cdcs_options": cdcs._Options, "cdcs_info": cdcs._Info, "cdcs_state": cdcs._State,
+    "cdcs_problem": cdcs._Problem, "cdcs_instance_info": cdcs._InstanceInfo, "cdcs_tuning": cdcs._Tuning,
+    "cdcs_sizes": cdcs._Sizes,
+}
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Compile a host program against include/cdcs.h with g++ and compare every
+    struct's size and field offsets with the ctypes definitions."""
+    import shutil
+    import subprocess
+    if shutil.which("g++") is None or not os.path.isdir("/opt/rocm/include"):
+        pytest.skip("g++ or the ROCm headers are not available")
+    lines = ['#include <cstdio>', '#include <cstddef>', '#include "cdcs.h"', "int main() {"]
+    for cname, py in _STRUCTS.items():
+        lines.append(f'  std::printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  std::printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.cpp"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["g++", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                           "-I", "/opt/rocm/include", str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, py in _STRUCTS.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
