@@ -149,11 +149,12 @@ __global__ void k_bcheck_finish(const int32_t *nrunning, Ctl *ctl) {
 }
 
 // t_r = A_q(r) . (w u)_q - r2scale r2_r, one wave per global constraint row.
-// t = A_q (w u_q) - r2scale r2 for up to 4 consecutive rows of one instance
+// t = A_q (w u_q) - r2scale r2 for up to 8 consecutive rows of one instance
 // per wave (job (q, first row, rows)): each u element loaded once serves all
 // the wave's rows.  Lanes stride the row in float4 groups; FP64 accumulation.
-constexpr int kRowsPerWave = 4;
+constexpr int kRowsPerWave = 8;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kMaxBatchRows = 256;  // constraints per instance (checked at setup)
 
 __global__ __launch_bounds__(kNT) void k_bgemv_Au(const float *__restrict__ A, const int64_t *__restrict__ A_off,
                                                   const int32_t *__restrict__ A_ld, const int4 *__restrict__ rjobs,
@@ -231,23 +232,28 @@ __global__ __launch_bounds__(kNT) void k_bgemv_ATy(const float *__restrict__ A, 
                                                    const int32_t *__restrict__ istop, const double *__restrict__ y,
                                                    const double *__restrict__ u, const double *__restrict__ s2,
                                                    double *__restrict__ x, const Ctl *ctl) {
+    __shared__ double ys[kMaxBatchRows];
     if (ctl != nullptr && ctl->stop) return;
     const int2 job = ejobs[blockIdx.x];
     const int q = job.x;
     if (istop != nullptr && istop[q]) return;
     const int64_t u0 = U_off[q];
     const int nU = (int)(U_off[q + 1] - u0);
+    {
+        const int m0 = m_off[q], mq = m_off[q + 1] - m0;
+        for (int i = threadIdx.x; i < mq; i += kNT) ys[i] = y[m0 + i];
+        __syncthreads();
+    }
     const int j = job.y + 4 * (int)threadIdx.x;
     if (j >= nU) return;
     const int ld = A_ld[q];
     const int m0 = m_off[q], mq = m_off[q + 1] - m0;
     const float *col = A + A_off[q] + j;
-    const double *yq = y + m0;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-#pragma unroll 4
+#pragma unroll 8
     for (int i = 0; i < mq; ++i) {
         const f32x4 a = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(col + (int64_t)i * ld));
-        const double yi = yq[i];
+        const double yi = ys[i];
         a0 += (double)a.x * yi;
         a1 += (double)a.y * yi;
         a2 += (double)a.z * yi;
