@@ -61,9 +61,10 @@ def summarise(fetch_csv, write_csv, source_hash):
         wv = [v for n, vs in w.items() if re.search(pat, n) for v in vs]
         if not fv or not wv:
             continue
-        # median over launches (early-exit launches of captured graphs read ~0)
-        fv.sort()
-        wv.sort()
+        # median over the launches that did work (launches of captured graphs
+        # after the stop flag return at once and read ~0)
+        fv = sorted(v for v in fv if v > 0.01 * max(fv))
+        wv = sorted(v for v in wv if v > 0.01 * max(wv)) or [0.0]
         fb = fv[len(fv) // 2] * sf
         wb = wv[len(wv) // 2] * sw
         out["kernels"][key] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
