@@ -37,10 +37,10 @@ __device__ __forceinline__ double block_sum_d(double v, double *red) {
     return r;
 }
 
-// The residual checks reduce tens of thousands of partial sums in one
-// workgroup: 1024 threads, fixed order (bitwise reproducible).
-constexpr int kCheckNT = 1024;
-
+// The residual checks reduce the partial sums of the scatter and projection
+// launches in one workgroup of CNT threads (1024 when there are tens of
+// thousands of partials, 256 otherwise), fixed order (bitwise reproducible).
+template <int CNT>
 __device__ __forceinline__ double check_sum_d(double v, double *red) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     v = wave_sum_d(v);
@@ -49,7 +49,7 @@ __device__ __forceinline__ double check_sum_d(double v, double *red) {
     __syncthreads();
     double r = 0.0;
 #pragma unroll
-    for (int i = 0; i < kCheckNT / 64; ++i) r += red[i];
+    for (int i = 0; i < CNT / 64; ++i) r += red[i];
     return r;
 }
 
@@ -144,31 +144,32 @@ __global__ __launch_bounds__(kNT) void k_scatter_primal(const int32_t *__restric
 }
 
 // Alg. 1 residual check of iteration n = ctl->iter (if any), then start the next one.
-__global__ __launch_bounds__(kCheckNT) void k_check_primal(const double *__restrict__ cpart, int p,
-                                                           const double *__restrict__ spart, int nsblk, double rho,
-                                                           double *__restrict__ hist, int hist_cap, Ctl *ctl) {
-    __shared__ double red[kCheckNT / 64];
+template <int CNT>
+__global__ __launch_bounds__(CNT) void k_check_primal(const double *__restrict__ cpart, int p,
+                                                      const double *__restrict__ spart, int nsblk, double rho,
+                                                      double *__restrict__ hist, int hist_cap, Ctl *ctl) {
+    __shared__ double red[CNT / 64];
     if (ctl->stop) return;
     const int n = ctl->iter;
     const int tid = threadIdx.x;
     if (n >= 1) {
         double r2 = 0.0, h2 = 0.0, x2 = 0.0, d2 = 0.0, l2 = 0.0;
-        for (int k = tid; k < p; k += kCheckNT) {
+        for (int k = tid; k < p; k += CNT) {
             const double4 c4 = *reinterpret_cast<const double4 *>(cpart + 4 * (int64_t)k);
             r2 += c4.x;
             h2 += c4.y;
             x2 += c4.z;
         }
-        for (int b = tid; b < nsblk; b += kCheckNT) {
+        for (int b = tid; b < nsblk; b += CNT) {
             const double2 s2v = *reinterpret_cast<const double2 *>(spart + 2 * (int64_t)b);
             d2 += s2v.x;
             l2 += s2v.y;
         }
-        r2 = check_sum_d(r2, red);
-        h2 = check_sum_d(h2, red);
-        x2 = check_sum_d(x2, red);
-        d2 = check_sum_d(d2, red);
-        l2 = check_sum_d(l2, red);
+        r2 = check_sum_d<CNT>(r2, red);
+        h2 = check_sum_d<CNT>(h2, red);
+        x2 = check_sum_d<CNT>(x2, red);
+        d2 = check_sum_d<CNT>(d2, red);
+        l2 = check_sum_d<CNT>(l2, red);
         if (tid == 0) {
             const double den_p = fmax(sqrt(h2), sqrt(x2));
             const double num_p = sqrt(r2);
@@ -280,13 +281,14 @@ __global__ __launch_bounds__(kNT) void k_vupdate(const int32_t *__restrict__ gat
 }
 
 // Alg. 2 residual check of the iteration just completed.
-__global__ __launch_bounds__(kCheckNT) void k_check_dual(const double *__restrict__ vpart, int nvblk, double rho,
-                                                         double *__restrict__ hist, int hist_cap, Ctl *ctl) {
-    __shared__ double red[kCheckNT / 64];
+template <int CNT>
+__global__ __launch_bounds__(CNT) void k_check_dual(const double *__restrict__ vpart, int nvblk, double rho,
+                                                    double *__restrict__ hist, int hist_cap, Ctl *ctl) {
+    __shared__ double red[CNT / 64];
     if (ctl->stop) return;
     const int tid = threadIdx.x;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0;
-    for (int b = tid; b < nvblk; b += kCheckNT) {
+    for (int b = tid; b < nvblk; b += CNT) {
         const double *o = vpart + 5 * (int64_t)b;
         a0 += o[0];
         a1 += o[1];
@@ -294,11 +296,11 @@ __global__ __launch_bounds__(kCheckNT) void k_check_dual(const double *__restric
         a3 += o[3];
         a4 += o[4];
     }
-    a0 = check_sum_d(a0, red);
-    a1 = check_sum_d(a1, red);
-    a2 = check_sum_d(a2, red);
-    a3 = check_sum_d(a3, red);
-    a4 = check_sum_d(a4, red);
+    a0 = check_sum_d<CNT>(a0, red);
+    a1 = check_sum_d<CNT>(a1, red);
+    a2 = check_sum_d<CNT>(a2, red);
+    a3 = check_sum_d<CNT>(a3, red);
+    a4 = check_sum_d<CNT>(a4, red);
     if (tid == 0) {
         const int n = ctl->iter + 1;
         const double den_p = fmax(sqrt(a1), sqrt(a2));
@@ -582,8 +584,12 @@ void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, dou
 }
 
 void launch_check_primal(const Dev &d, double rho, hipStream_t s) {
-    hipLaunchKernelGGL(k_check_primal, dim3(1), dim3(kCheckNT), 0, s, (const double *)d.cpart, d.p,
-                       (const double *)d.spart, scatter_blocks(d), rho, d.hist, d.hist_cap, d.ctl);
+    if (d.p + scatter_blocks(d) > 8192)
+        hipLaunchKernelGGL(k_check_primal<1024>, dim3(1), dim3(1024), 0, s, (const double *)d.cpart, d.p,
+                           (const double *)d.spart, scatter_blocks(d), rho, d.hist, d.hist_cap, d.ctl);
+    else
+        hipLaunchKernelGGL(k_check_primal<kNT>, dim3(1), dim3(kNT), 0, s, (const double *)d.cpart, d.p,
+                           (const double *)d.spart, scatter_blocks(d), rho, d.hist, d.hist_cap, d.ctl);
 }
 
 void launch_scatter_dual(const Dev &d, const float *blk, const float *lam, double rho, double *xcopy,
@@ -600,8 +606,12 @@ void launch_vupdate(const Dev &d, const double *x, const float *blk, float *lam,
 }
 
 void launch_check_dual(const Dev &d, double rho, hipStream_t s) {
-    hipLaunchKernelGGL(k_check_dual, dim3(1), dim3(kCheckNT), 0, s, (const double *)d.vpart, vupdate_blocks(d), rho,
-                       d.hist, d.hist_cap, d.ctl);
+    if (vupdate_blocks(d) > 8192)
+        hipLaunchKernelGGL(k_check_dual<1024>, dim3(1), dim3(1024), 0, s, (const double *)d.vpart, vupdate_blocks(d),
+                           rho, d.hist, d.hist_cap, d.ctl);
+    else
+        hipLaunchKernelGGL(k_check_dual<kNT>, dim3(1), dim3(kNT), 0, s, (const double *)d.vpart, vupdate_blocks(d),
+                           rho, d.hist, d.hist_cap, d.ctl);
 }
 
 void launch_scale_u(const Dev &d, const double *r1, double *xcopy, hipStream_t s) {
