@@ -7,12 +7,14 @@
 // bucket size S with zero rows and columns (a zero pair never rotates), so all
 // loops have compile-time trip counts.  The clique matrix (FP32) lives in LDS
 // and is diagonalised by two-sided Jacobi with the round-robin (circle)
-// ordering: the S/2 disjoint pairs of a step are rotated together.  A step is
-// two phases separated by barriers: one wave computes the S/2 rotations, then
-// every thread applies them to its fixed share of lower 2x2 blocks of A
-// (writing the transposes alongside) and of row pairs of V.  Pair indices are
-// recomputed arithmetically each step; no index tables are read.  Sweeps stop
-// when off(A) <= tau ||W||_F: the projection onto the PSD cone is
+// ordering: the disjoint pairs of a step are rotated together.  During the
+// sweeps A is stored by position, as lower 2x2 pair blocks in four element
+// planes, so a thread reads its blocks with unit-stride LDS accesses and
+// writes the rotated elements straight to where the ring move takes them
+// (two buffers, swapped every step); V stays in registers.  A step is two
+// phases separated by barriers: one wave computes the rotations, then every
+// thread applies them to its fixed blocks of A and to its rows of V.  Sweeps
+// stop when off(A) <= tau ||W||_F: the projection onto the PSD cone is
 // 1-Lipschitz in the Frobenius norm, so rebuilding from the diagonal of a
 // matrix whose off-diagonal part E remains moves P by at most ||E||_F.  Inside
 // the ADMM loop tau = 2^-20 (error <= 1e-6 ||W||_F); when eigenpairs are
@@ -25,8 +27,8 @@
 //
 // FP32 accumulation of the eigenvectors loses orthogonality like
 // sqrt(#rotations) eps, so one Newton-Schulz step V <- V - V (V^T V - I) / 2
-// re-orthonormalises them before P = V max(Lambda, 0) V^T (register-tiled
-// products on a G x G thread grid).
+// re-orthonormalises them before P = V max(Lambda, 0) V^T (products on the
+// matrix cores for S >= 32, register tiles on the vector ALUs below).
 #include "cdcs_internal.h"
 
 namespace cdcs {
@@ -48,6 +50,19 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// A value that is the same in every lane of the wave, moved to a scalar
+// register so that branches and loop bounds on it are scalar.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Sum over the workgroup, result in every thread.  Contains two barriers.
 template <int NT, typename T>
 __device__ __forceinline__ T block_sum(T v, T *red) {
@@ -59,7 +74,7 @@ __device__ __forceinline__ T block_sum(T v, T *red) {
     T r = 0;
 #pragma unroll
     for (int i = 0; i < NT / 64; ++i) r += red[i];
-    return r;
+    return uniform(r);
 }
 
 // Max over the workgroup, result in every thread.  Contains two barriers.
@@ -74,7 +89,7 @@ __device__ __forceinline__ float block_max(float v, float *red) {
     float r = red[0];
 #pragma unroll
     for (int i = 1; i < NT / 64; ++i) r = fmaxf(r, red[i]);
-    return r;
+    return uniform(r);
 }
 
 // Row a of the packed lower-triangular slot s = a(a+1)/2 + b.
@@ -85,17 +100,41 @@ __device__ __forceinline__ int tri_row(int s) {
     return a;
 }
 
-// Round-robin (circle) ordering on K (even) indices, steps r = 0 .. K-2:
-// position 0 holds index 0, position j >= 1 holds 1 + (j - 1 + r) mod (K-1);
-// pair t joins positions t ("top", index a) and K-1-t ("bottom", index b).
-__device__ __forceinline__ void pair_dyn(int t, int r, int K, int &a, int &b) {
-    const int M = K - 1;
-    int x = t - 1 + r;  // in [-1, 2M)
-    x = (x >= M) ? x - M : x;
-    int y = M - 1 - t + r;  // in [0, 2M)
-    y = (y >= M) ? y - M : y;
-    a = (t == 0) ? 0 : 1 + x;
-    b = 1 + y;
+// Round-robin (circle) ordering by position: pair t of a step joins slots
+// (t, top) and (t, bottom) of HK pairs.  After a step, slot (t, h) moves to
+// (t2, h2): (0, top) stays, (1, top) -> (0, bottom), (t, top) -> (t-1, top)
+// for t >= 2, (t, bottom) -> (t+1, bottom) for t < HK-1 and (HK-1, bottom)
+// -> (HK-1, top).  With one pair nothing moves.
+__device__ __forceinline__ void ring_next(int t, int h, int HK, int &t2, int &h2) {
+    if (HK == 1) {
+        t2 = t;
+        h2 = h;
+    } else if (h == 0) {
+        t2 = t <= 1 ? 0 : t - 1;
+        h2 = t == 1 ? 1 : 0;
+    } else {
+        t2 = t < HK - 1 ? t + 1 : HK - 1;
+        h2 = t < HK - 1 ? 1 : 0;
+    }
+}
+
+// Element offset (plane * nbs + block) of entry (slot (t1, g1), slot (t2, g2))
+// of a symmetric matrix stored as lower 2x2 pair blocks in four planes
+// (element e = 2 g_row + g_col of block I (I+1)/2 + J, I >= J).  Entries of an
+// upper block are stored transposed; the off-diagonal entry of a diagonal
+// block lives in element 2 only.
+__device__ __forceinline__ int pair_slot(int t1, int g1, int t2, int g2, int nbs) {
+    int I = t1, J = t2, e;
+    if (t1 > t2) {
+        e = 2 * g1 + g2;
+    } else if (t1 < t2) {
+        I = t2;
+        J = t1;
+        e = 2 * g2 + g1;
+    } else {
+        e = g1 == g2 ? 3 * g1 : 2;
+    }
+    return e * nbs + I * (I + 1) / 2 + J;
 }
 
 // Full-wave lane shifts: lane i receives lane i+1 (shl) or lane i-1 (shr);
@@ -184,7 +223,6 @@ __device__ __forceinline__ void mfma_product(const float *X, const float *Y, con
 #pragma unroll
         for (int v = 0; v < TCW; ++v) acc[u][v] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     const int n4 = (n + 3) & ~3;  // <= S; terms past n are zero
-#pragma unroll 2
     for (int q0 = 0; q0 < n4; q0 += 4) {
         const int q = q0 + lk;
         float av[TRW], bv[TCW];
@@ -215,7 +253,7 @@ __device__ __forceinline__ void product_store(const float *X, const float *Y, co
                                               Store st) {
     if constexpr (S >= 32) {
         using MT = MfmaTiles<S, NT>;
-        const int lane = tid & 63, wv = tid >> 6;
+        const int lane = tid & 63, wv = uniform(tid >> 6);
         f32x4 acc[MT::TRW][MT::TCW];
         mfma_product<S, NT, MODE>(X, Y, lp, n, lane, wv, acc);
         __syncthreads();
@@ -247,9 +285,7 @@ __device__ __forceinline__ void product_store(const float *X, const float *Y, co
 
 // Small per-workgroup LDS of the projection (sized for the largest bucket).
 struct ProjSmall {
-    float2 cs[48];               // rotations of one step: (c, s) of pair t
-    int4 pq[48];                 // its indices P < Q as byte offsets (P LD, Q LD, P, Q) * 4
-    float t[48];                 // t * a_PQ of pair t
+    float4 cst[48];              // rotations of one step: (c, s, t a_PQ, 0) of pair t
     float lam[96], lp[96];       // eigenvalues, clamped eigenvalues
     float redf[8];
     double redd[8];
@@ -270,7 +306,7 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
     constexpr int RPW = (S + NW - 1) / NW;       // rows of V per wave, at most
 
     if (a.istop != nullptr && a.istop[a.kinst[id]]) return;  // instance already stopped
-    const int k = a.size[id];
+    const int k = uniform(a.size[id]);
     if (k < 1 || k > S) return;
     const int64_t off = a.off[id];
     const int nslot = k * (k + 1) / 2;
@@ -345,25 +381,48 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
 
     // Jacobi on the K = k rounded up to even leading indices (one zero
     // padding row and column for odd k; the rest of the bucket is not
-    // touched): K-1 steps of K/2 disjoint rotations per sweep.
+    // touched): K-1 steps of K/2 disjoint rotations per sweep in the
+    // round-robin (circle) order.  Pair t of a step joins position (t, top)
+    // and (t, bottom); (0, top) stays, every other position moves one place
+    // along the ring (t, top) -> (t-1, top) -> ... -> (1, top) -> (0, bottom)
+    // -> (1, bottom) -> ... -> (HK-1, bottom) -> (HK-1, top) after a step, so
+    // after K-1 steps every index is back where it started.  A is kept by
+    // position: its lower 2x2 pair blocks (I >= J) in four element planes,
+    // ping-ponged between two buffers.  A thread rotates its blocks and stores
+    // each element straight into the slot its row and column move to; those
+    // addresses are set once per eigensolve.  V is kept by position in
+    // registers and moved the same way.
     const int K = k + (k & 1);
     const int HK = K >> 1;
     const int nblk = HK * (HK + 1) / 2;
-    // Lower 2x2 blocks (rows of pair I, columns of pair J, I >= J) of this thread.
-    int aI[NA], aJ[NA];
+    constexpr int NBS = HMAX * (HMAX + 1) / 2;  // plane stride in blocks
+    constexpr int PL = NBS * 4;                   // plane stride in bytes
+    static_assert(4 * NBS <= S * LD, "a pair-block buffer fits in an S x (S+1) array");
+    // Blocks of this thread: pair indices and the destination byte offsets
+    // of the four elements (element e = 2 h_row + h_col, h: 0 top, 1 bottom;
+    // a diagonal block keeps only e = 0, 2, 3).
+    // Element 1 of a diagonal block is not kept (it equals element 2), so its
+    // read address points at element 2.
+    int bI[NA], bJ[NA], dst[NA][4], a01[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
-        const int idx = tid + q * NT;
-        const int I = tri_row(min(idx, nblk - 1));
-        aI[q] = (idx < nblk) ? I : -1;
-        aJ[q] = min(idx, nblk - 1) - I * (I + 1) / 2;
+        const int b = tid + q * NT;
+        const int bc = min(b, nblk - 1);
+        const int I = tri_row(bc), J = bc - I * (I + 1) / 2;
+        bI[q] = (b < nblk) ? I : -1;
+        bJ[q] = J;
+        a01[q] = (I == J ? 2 * PL : PL) + b * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            int t1, g1, t2, g2;
+            ring_next(I, e >> 1, HK, t1, g1);
+            ring_next(J, e & 1, HK, t2, g2);
+            dst[q][e] = pair_slot(t1, g1, t2, g2, NBS) * 4;
+        }
     }
     // V in registers: lane t of a wave holds, for its rows (wave w: rows
-    // w, w + NW, ...), the columns of pair t's top and bottom positions.  A
-    // step rotates them and then moves every column one position along the
-    // circle (a one-lane shift), so columns never go through LDS; after a
-    // whole sweep positions and indices coincide again.
-    const int lane = tid & 63, wv = tid >> 6;
+    // w, w + NW, ...), the columns at positions (t, top) and (t, bottom).
+    const int lane = tid & 63, wv = uniform(tid >> 6);
     const bool vlane = lane < HK;
     float vt[RPW], vb[RPW];
 #pragma unroll
@@ -373,15 +432,110 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
         vt[j] = ok ? sV[row * LD + lane] : 0.0f;
         vb[j] = ok ? sV[row * LD + K - 1 - lane] : 0.0f;
     }
+    __syncthreads();  // sV is free: it becomes pair-block buffer 0
+    char *const B0 = reinterpret_cast<char *>(sV);
+    char *const B1 = reinterpret_cast<char *>(sA);
+#define LF(ptr, off) (*reinterpret_cast<const float *>((ptr) + (off)))
+#define SF(ptr, off) (*reinterpret_cast<float *>((ptr) + (off)))
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+        if (bI[q] < 0) continue;
+        const int I = bI[q], J = bJ[q], b4 = (tid + q * NT) * 4;
+        const int r0 = I, r1 = K - 1 - I, c0 = J, c1 = K - 1 - J;  // indices at the start of a sweep
+        SF(B0, b4) = sA[r0 * LD + c0];
+        SF(B0, PL + b4) = sA[r0 * LD + c1];
+        SF(B0, 2 * PL + b4) = sA[r1 * LD + c0];
+        SF(B0, 3 * PL + b4) = sA[r1 * LD + c1];
+    }
+    __syncthreads();
 
+    // One rotation step from buffer `cur` into buffer `nxt`.
+    auto step = [&](const char *__restrict__ cur, char *__restrict__ nxt) {
+        if (tid < HK) {
+            const int bd = tid * (tid + 3) * 2;  // block (t, t), bytes
+            const float app = LF(cur, bd), apq = LF(cur, 2 * PL + bd), aqq = LF(cur, 3 * PL + bd);
+            float c = 1.0f, s = 0.0f, ta = 0.0f;
+            if (fabsf(apq) > 1e-30f) {  // entries are scaled to max |a| ~ 1
+                const float tau = 0.5f * (aqq - app) * __builtin_amdgcn_rcpf(apq);
+                const float t = copysignf(__builtin_amdgcn_rcpf(fabsf(tau) + __builtin_sqrtf(1.0f + tau * tau)),
+                                          tau);
+                c = __builtin_amdgcn_rsqf(1.0f + t * t);
+                s = t * c;
+                ta = t * apq;
+            }
+            sm.cst[tid] = make_float4(c, s, ta, 0.0f);
+        }
+        __syncthreads();
+        // A <- J^T A J on this thread's blocks, stored at the moved positions.
+        // A diagonal block takes the Jacobi values (exact zero off the
+        // diagonal) in place of the generic product, without branching.
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            const int I = bI[q], J = bJ[q];
+            if (I < 0) continue;
+            const int b4 = (tid + q * NT) * 4;
+            const bool dg = I == J;
+            const float a00 = LF(cur, b4), a01v = LF(cur, a01[q]);
+            const float a10 = LF(cur, 2 * PL + b4), a11 = LF(cur, 3 * PL + b4);
+            const float4 cs1 = sm.cst[I];
+            const float2 cs2 = *reinterpret_cast<const float2 *>(&sm.cst[J]);
+            const float c1 = cs1.x, s1 = cs1.y, c2 = cs2.x, s2 = cs2.y;
+            const float b00 = c1 * a00 - s1 * a10, b01 = c1 * a01v - s1 * a11;
+            const float b10 = s1 * a00 + c1 * a10, b11 = s1 * a01v + c1 * a11;
+            const float n00 = c2 * b00 - s2 * b01, n01 = s2 * b00 + c2 * b01;
+            const float n10 = c2 * b10 - s2 * b11, n11 = s2 * b10 + c2 * b11;
+            SF(nxt, dst[q][0]) = dg ? a00 - cs1.z : n00;
+            SF(nxt, dst[q][1]) = dg ? 0.0f : n01;
+            SF(nxt, dst[q][2]) = dg ? 0.0f : n10;
+            SF(nxt, dst[q][3]) = dg ? a11 + cs1.z : n11;
+        }
+        // V <- V J in registers: (V_top, V_bottom) <- (c V_top - s V_bottom,
+        // s V_top + c V_bottom), then the ring move (one-lane shifts).  Rows
+        // past K are zero in lanes < HK and stay zero; lanes >= HK never feed
+        // a lane < HK (the last pair takes its own bottom, not lane HK).
+        if (HK > 1) {
+            const float4 cs = sm.cst[vlane ? lane : 0];
+            const float c = cs.x, sg = cs.y;
+            const bool first = lane == 0, last = lane == HK - 1;
+#pragma unroll
+            for (int j = 0; j < RPW; ++j) {
+                const float nt = c * vt[j] - sg * vb[j];
+                const float nb = sg * vt[j] + c * vb[j];
+                const float up = wave_shl1(nt);  // top of lane + 1
+                vt[j] = first ? nt : (last ? nb : up);
+                vb[j] = wave_shr1(nb, up);  // bottom of lane - 1; lane 0: top of lane 1
+            }
+        } else {
+            // one pair (K = 2): a rotation, no movement
+            const float4 cs = sm.cst[0];
+#pragma unroll
+            for (int j = 0; j < RPW; ++j) {
+                const float nt = cs.x * vt[j] - cs.y * vb[j];
+                const float nb = cs.y * vt[j] + cs.x * vb[j];
+                vt[j] = nt;
+                vb[j] = nb;
+            }
+        }
+        __syncthreads();
+    };
+
+    // A sweep is K-1 (odd) steps: pairs of steps B0 -> B1 -> B0, a last
+    // step B0 -> B1 and a copy back, so a sweep starts and ends in B0.
     int sweep = 0;
     for (;; ++sweep) {
+        // off(A)^2 = 2 x (squares of the lower off-diagonal entries)
         float o = 0.0f;
-#pragma unroll 4
-        for (int idx = tid; idx < S * S; idx += NT) {
-            const int i = idx / S, j = idx % S;
-            const float v = sA[i * LD + j];
-            o += (i != j) ? v * v : 0.0f;
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            if (bI[q] < 0) continue;
+            const int b4 = (tid + q * NT) * 4;
+            const float a10 = LF(B0, 2 * PL + b4);
+            if (bI[q] == bJ[q]) {
+                o += 2.0f * a10 * a10;
+            } else {
+                const float a00 = LF(B0, b4), a01 = LF(B0, PL + b4), a11 = LF(B0, 3 * PL + b4);
+                o += 2.0f * (a00 * a00 + a01 * a01 + a10 * a10 + a11 * a11);
+            }
         }
         const float off2 = block_sum<NT>(o, sm.redf);
         if (off2 <= thr) break;
@@ -390,97 +544,42 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
             break;
         }
 #pragma unroll 1
-        for (int r = 0; r < K - 1; ++r) {
-            if (tid < HK) {
-                int ta_, tb_;
-                pair_dyn(tid, r, K, ta_, tb_);
-                const int P = min(ta_, tb_), Q = max(ta_, tb_);
-                const float apq = sA[P * LD + Q];
-                float c = 1.0f, s = 0.0f, ta = 0.0f;
-                if (fabsf(apq) > 1e-30f) {  // entries are scaled to max |a| ~ 1
-                    const float app = sA[P * LD + P], aqq = sA[Q * LD + Q];
-                    const float tau = 0.5f * (aqq - app) * __builtin_amdgcn_rcpf(apq);
-                    const float t = copysignf(__builtin_amdgcn_rcpf(fabsf(tau) + __builtin_sqrtf(1.0f + tau * tau)),
-                                              tau);
-                    c = __builtin_amdgcn_rsqf(1.0f + t * t);
-                    s = t * c;
-                    ta = t * apq;
-                }
-                sm.cs[tid] = make_float2(c, s);
-                sm.pq[tid] = make_int4(P * LD * 4, Q * LD * 4, P * 4, Q * 4);
-                sm.t[tid] = ta;
-            }
-            __syncthreads();
-            // A <- J^T A J on this thread's lower 2x2 blocks; the transposed
-            // block is written alongside.
-            char *const A8 = reinterpret_cast<char *>(sA);
-#define AE(off) (*reinterpret_cast<float *>(A8 + (off)))
-#pragma unroll
-            for (int q = 0; q < NA; ++q) {
-                const int I = aI[q], J = aJ[q];
-                if (I < 0) continue;
-                const int4 o1 = sm.pq[I];  // P1 LD, Q1 LD, P1, Q1 (bytes)
-                if (I == J) {
-                    const float ta = sm.t[I];
-                    AE(o1.x + o1.z) -= ta;
-                    AE(o1.y + o1.w) += ta;
-                    AE(o1.x + o1.w) = 0.0f;
-                    AE(o1.y + o1.z) = 0.0f;
-                } else {
-                    const int4 o2 = sm.pq[J];
-                    const float2 cs1 = sm.cs[I], cs2 = sm.cs[J];
-                    const float c1 = cs1.x, s1 = cs1.y, c2 = cs2.x, s2 = cs2.y;
-                    const float a00 = AE(o1.x + o2.z), a01 = AE(o1.x + o2.w);
-                    const float a10 = AE(o1.y + o2.z), a11 = AE(o1.y + o2.w);
-                    const float b00 = c1 * a00 - s1 * a10, b01 = c1 * a01 - s1 * a11;
-                    const float b10 = s1 * a00 + c1 * a10, b11 = s1 * a01 + c1 * a11;
-                    const float n00 = c2 * b00 - s2 * b01, n01 = s2 * b00 + c2 * b01;
-                    const float n10 = c2 * b10 - s2 * b11, n11 = s2 * b10 + c2 * b11;
-                    AE(o1.x + o2.z) = n00;
-                    AE(o1.x + o2.w) = n01;
-                    AE(o1.y + o2.z) = n10;
-                    AE(o1.y + o2.w) = n11;
-                    AE(o2.x + o1.z) = n00;
-                    AE(o2.y + o1.z) = n01;
-                    AE(o2.x + o1.w) = n10;
-                    AE(o2.y + o1.w) = n11;
-                }
-            }
-#undef AE
-            // V <- V J in registers: (V_P, V_Q) <- (c V_P - s V_Q, s V_P + c V_Q);
-            // the top column is P unless the pair is reversed (top index > bottom).
-            // Rows past K (zero in these columns) are skipped per wave.
-            if (HK > 1) {
-                int ta_, tb_;
-                pair_dyn(lane, r, K, ta_, tb_);
-                const float2 cs = sm.cs[vlane ? lane : 0];
-                const float c = cs.x, sg = (ta_ > tb_) ? -cs.y : cs.y;
-                const bool first = lane == 0, last = lane == HK - 1;
-#pragma unroll
-                for (int j = 0; j < RPW; ++j) {
-                    if (wv + j * NW < K) {
-                        const float nt = c * vt[j] - sg * vb[j];
-                        const float nb = sg * vt[j] + c * vb[j];
-                        const float up = wave_shl1(nt);  // top of lane + 1
-                        vt[j] = first ? nt : (last ? nb : up);
-                        vb[j] = wave_shr1(nb, up);  // bottom of lane - 1; lane 0: top of lane 1
-                    }
-                }
-            } else {
-                // one pair (K = 2): a rotation, no movement
-                const float2 cs = sm.cs[0];
-#pragma unroll
-                for (int j = 0; j < RPW; ++j) {
-                    const float nt = cs.x * vt[j] - cs.y * vb[j];
-                    const float nb = cs.y * vt[j] + cs.x * vb[j];
-                    vt[j] = nt;
-                    vb[j] = nb;
-                }
-            }
-            __syncthreads();
+        for (int r = 0; r < K - 2; r += 2) {
+            step(B0, B1);
+            step(B1, B0);
         }
+        step(B0, B1);
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            if (bI[q] < 0) continue;
+            const int b4 = (tid + q * NT) * 4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) SF(B0, e * PL + b4) = LF(B1, e * PL + b4);
+        }
+        __syncthreads();
     }
-    // registers -> sV (positions equal indices after whole sweeps)
+    if (tid == 0 && a.ctl != nullptr) atomicAdd(&a.ctl->sweeps, sweep);
+
+    // Eigenvalues from the diagonal blocks (positions equal indices after
+    // whole sweeps); indices past K are padding.
+    if (tid < S) {
+        float l = 0.0f;
+        if (tid < K) {
+            const int t = tid < HK ? tid : K - 1 - tid;
+            l = LF(B0, (tid < HK ? 0 : 3 * PL) + t * (t + 3) * 2) * unscale;
+        }
+        sm.lam[tid] = l;
+        sm.lp[tid] = fmaxf(l, 0.0f);
+    }
+#undef LF
+#undef SF
+    __syncthreads();  // buffers are read; sV takes V back
+    // registers -> sV; outside the leading K x K block the identity, so that
+    // the products below see exact zeros there
+    for (int idx = tid; idx < S * S; idx += NT) {
+        const int i = idx / S, j = idx % S;
+        if (i >= K || j >= K) sV[i * LD + j] = (i == j) ? 1.0f : 0.0f;
+    }
 #pragma unroll
     for (int j = 0; j < RPW; ++j) {
         const int row = wv + j * NW;
@@ -490,13 +589,6 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
         }
     }
     __syncthreads();
-    if (tid == 0 && a.ctl != nullptr) atomicAdd(&a.ctl->sweeps, sweep);
-
-    if (tid < S) {
-        const float l = sA[tid * LD + tid] * unscale;
-        sm.lam[tid] = l;
-        sm.lp[tid] = fmaxf(l, 0.0f);
-    }
     // E = V^T V - I  -> sA (A's eigenvalues are in sm.lam)
     product_store<S, NT, 0>(sV, sV, nullptr, K, tid,
                             [&](int i, int j, float v) { sA[i * LD + j] = v - (i == j ? 1.0f : 0.0f); });
