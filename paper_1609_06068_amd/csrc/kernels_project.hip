@@ -29,6 +29,8 @@
 // sqrt(#rotations) eps, so one Newton-Schulz step V <- V - V (V^T V - I) / 2
 // re-orthonormalises them before P = V max(Lambda, 0) V^T (products on the
 // matrix cores for S >= 32, register tiles on the vector ALUs below).
+#include <type_traits>
+
 #include "cdcs_internal.h"
 
 namespace cdcs {
@@ -100,21 +102,31 @@ __device__ __forceinline__ int tri_row(int s) {
     return a;
 }
 
-// Round-robin (circle) ordering by position: pair t of a step joins slots
-// (t, top) and (t, bottom) of HK pairs.  After a step, slot (t, h) moves to
-// (t2, h2): (0, top) stays, (1, top) -> (0, bottom), (t, top) -> (t-1, top)
-// for t >= 2, (t, bottom) -> (t+1, bottom) for t < HK-1 and (HK-1, bottom)
-// -> (HK-1, top).  With one pair nothing moves.
-__device__ __forceinline__ void ring_next(int t, int h, int HK, int &t2, int &h2) {
-    if (HK == 1) {
-        t2 = t;
-        h2 = h;
-    } else if (h == 0) {
-        t2 = t <= 1 ? 0 : t - 1;
-        h2 = t == 1 ? 1 : 0;
+// Odd-even ordering with swaps on K (even) positions.  Even steps pair
+// positions (2i, 2i+1), i < K/2 (tiling 0); odd steps pair (2i-1, 2i), 1 <= i
+// < K/2, and put positions 0 and K-1 in the end pairs (ghost, 0) and
+// (K-1, ghost) with a ghost position that holds zeros (tiling 1, K/2 + 1
+// pairs).  After every rotation the two positions of each pair exchange
+// their contents, so over K steps every two positions meet once and the
+// order is reversed.  Slot (t, h) is member h of pair t of a tiling; its
+// position, -1 for a ghost:
+__device__ __forceinline__ int slot_pos(int tiling, int t, int h, int HK) {
+    if (tiling == 0) return 2 * t + h;
+    if (t == 0) return h == 0 ? -1 : 0;
+    if (t == HK) return h == 0 ? 2 * HK - 1 : -1;
+    return 2 * t - 1 + h;
+}
+// ... and the slot of position p (not a ghost) in a tiling.
+__device__ __forceinline__ void pos_slot(int tiling, int p, int HK, int &t, int &h) {
+    if (tiling == 0) {
+        t = p >> 1;
+        h = p & 1;
+    } else if (p == 2 * HK - 1) {
+        t = HK;
+        h = 0;
     } else {
-        t2 = t < HK - 1 ? t + 1 : HK - 1;
-        h2 = t < HK - 1 ? 1 : 0;
+        t = (p + 1) >> 1;
+        h = (p + 1) & 1;
     }
 }
 
@@ -138,12 +150,12 @@ __device__ __forceinline__ int pair_slot(int t1, int g1, int t2, int g2, int nbs
 }
 
 // Full-wave lane shifts: lane i receives lane i+1 (shl) or lane i-1 (shr);
-// lane 0 of the right shift has no source and keeps `old` (bound control off).
+// lane 63 of the left shift and lane 0 of the right shift read zero.
 __device__ __forceinline__ float wave_shl1(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
 }
-__device__ __forceinline__ float wave_shr1(float v, float old) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x138, 0xF, 0xF, false));
+__device__ __forceinline__ float wave_shr0(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
 }
 
 // Register-tiled S x S products on a GR x GC thread grid (GR = 16 rows of
@@ -285,7 +297,7 @@ __device__ __forceinline__ void product_store(const float *X, const float *Y, co
 
 // Small per-workgroup LDS of the projection (sized for the largest bucket).
 struct ProjSmall {
-    float4 cst[48];              // rotations of one step: (c, s, t a_PQ, 0) of pair t
+    float4 cst[64];              // rotations of one step: (c, s, t a_PQ, 0) of pair t
     float lam[96], lp[96];       // eigenvalues, clamped eigenvalues
     float redf[8];
     double redd[8];
@@ -301,7 +313,8 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
     static_assert(NT == 64 || NT == 256 || NT == 512, "workgroup size");
     constexpr int LD = S + 1;                    // odd row stride
     constexpr int HMAX = S / 2;                  // pairs per step, at most
-    constexpr int NA = (HMAX * (HMAX + 1) / 2 + NT - 1) / NT;  // 2x2 blocks of A per thread, at most
+    constexpr int NBS = (HMAX + 1) * (HMAX + 2) / 2;           // 2x2 blocks of a tiling, at most
+    constexpr int NA = (NBS + NT - 1) / NT;                    // blocks per thread, at most
     constexpr int NW = NT / 64;                  // waves
     constexpr int RPW = (S + NW - 1) / NW;       // rows of V per wave, at most
 
@@ -381,47 +394,49 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
 
     // Jacobi on the K = k rounded up to even leading indices (one zero
     // padding row and column for odd k; the rest of the bucket is not
-    // touched): K-1 steps of K/2 disjoint rotations per sweep in the
-    // round-robin (circle) order.  Pair t of a step joins position (t, top)
-    // and (t, bottom); (0, top) stays, every other position moves one place
-    // along the ring (t, top) -> (t-1, top) -> ... -> (1, top) -> (0, bottom)
-    // -> (1, bottom) -> ... -> (HK-1, bottom) -> (HK-1, top) after a step, so
-    // after K-1 steps every index is back where it started.  A is kept by
-    // position: its lower 2x2 pair blocks (I >= J) in four element planes,
-    // ping-ponged between two buffers.  A thread rotates its blocks and stores
-    // each element straight into the slot its row and column move to; those
-    // addresses are set once per eigensolve.  V is kept by position in
-    // registers and moved the same way.
+    // touched), in the odd-even ordering: a sweep is K steps, even steps on
+    // tiling 0 and odd steps on tiling 1.  The end pairs of tiling 1 hold a
+    // ghost position and rotate by (c, s) = (0, -1) and (0, 1): with the swap
+    // that leaves the real position as it is and the ghost at zero.  A is
+    // kept by position as the lower 2x2 pair blocks of the current tiling in
+    // four element planes; a step reads one buffer and writes each rotated
+    // element straight to its slot of the other tiling in the other buffer
+    // (ghost entries go to a dummy slot).  Those addresses are set once per
+    // eigensolve.  V is kept by position in registers (lane i: positions 2i
+    // and 2i+1).  After an odd number of sweeps position p holds index K-1-p.
     const int K = k + (k & 1);
     const int HK = K >> 1;
-    const int nblk = HK * (HK + 1) / 2;
-    constexpr int NBS = HMAX * (HMAX + 1) / 2;  // plane stride in blocks
-    constexpr int PL = NBS * 4;                   // plane stride in bytes
-    static_assert(4 * NBS <= S * LD, "a pair-block buffer fits in an S x (S+1) array");
-    // Blocks of this thread: pair indices and the destination byte offsets
-    // of the four elements (element e = 2 h_row + h_col, h: 0 top, 1 bottom;
-    // a diagonal block keeps only e = 0, 2, 3).
-    // Element 1 of a diagonal block is not kept (it equals element 2), so its
-    // read address points at element 2.
-    int bI[NA], bJ[NA], dst[NA][4], a01[NA];
+    const int nblk0 = HK * (HK + 1) / 2, nblk1 = (HK + 1) * (HK + 2) / 2;
+    constexpr int PL = NBS * 4;          // plane stride in bytes
+    constexpr int DUMMY = 4 * NBS * 4;   // write-only slot for ghost entries
+    static_assert(4 * NBS + 1 <= S * LD, "a pair-block buffer fits in an S x (S+1) array");
+    // Blocks of this thread (the same lower-triangle numbering in both
+    // tilings): pair indices, the read address of element 1 (a diagonal
+    // block keeps only elements 0, 2, 3, and 1 equals 2) and, per tiling, the
+    // byte offsets in the other tiling where the four rotated and swapped
+    // elements go (element e = 2 h_row + h_col).
+    int bI[NA], bJ[NA], a01[NA], dst[2][NA][4];
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
         const int b = tid + q * NT;
-        const int bc = min(b, nblk - 1);
+        const int bc = min(b, nblk1 - 1);
         const int I = tri_row(bc), J = bc - I * (I + 1) / 2;
-        bI[q] = (b < nblk) ? I : -1;
+        bI[q] = (b < nblk1) ? I : -1;
         bJ[q] = J;
         a01[q] = (I == J ? 2 * PL : PL) + b * 4;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            int t1, g1, t2, g2;
-            ring_next(I, e >> 1, HK, t1, g1);
-            ring_next(J, e & 1, HK, t2, g2);
-            dst[q][e] = pair_slot(t1, g1, t2, g2, NBS) * 4;
-        }
+        for (int T = 0; T < 2; ++T)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int p1 = slot_pos(T, I, 1 - (e >> 1), HK), p2 = slot_pos(T, J, 1 - (e & 1), HK);
+                int t1, g1, t2, g2;
+                pos_slot(1 - T, max(p1, 0), HK, t1, g1);
+                pos_slot(1 - T, max(p2, 0), HK, t2, g2);
+                dst[T][q][e] = (p1 < 0 || p2 < 0) ? DUMMY : pair_slot(t1, g1, t2, g2, NBS) * 4;
+            }
     }
-    // V in registers: lane t of a wave holds, for its rows (wave w: rows
-    // w, w + NW, ...), the columns at positions (t, top) and (t, bottom).
+    // V in registers: lane i of a wave holds, for its rows (wave w: rows
+    // w, w + NW, ...), the columns at positions 2i ("top") and 2i+1.
     const int lane = tid & 63, wv = uniform(tid >> 6);
     const bool vlane = lane < HK;
     float vt[RPW], vb[RPW];
@@ -429,8 +444,8 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
     for (int j = 0; j < RPW; ++j) {
         const int row = wv + j * NW;
         const bool ok = vlane && row < K;
-        vt[j] = ok ? sV[row * LD + lane] : 0.0f;
-        vb[j] = ok ? sV[row * LD + K - 1 - lane] : 0.0f;
+        vt[j] = ok ? sV[row * LD + 2 * lane] : 0.0f;
+        vb[j] = ok ? sV[row * LD + 2 * lane + 1] : 0.0f;
     }
     __syncthreads();  // sV is free: it becomes pair-block buffer 0
     char *const B0 = reinterpret_cast<char *>(sV);
@@ -439,42 +454,53 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
 #define SF(ptr, off) (*reinterpret_cast<float *>((ptr) + (off)))
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
-        if (bI[q] < 0) continue;
-        const int I = bI[q], J = bJ[q], b4 = (tid + q * NT) * 4;
-        const int r0 = I, r1 = K - 1 - I, c0 = J, c1 = K - 1 - J;  // indices at the start of a sweep
-        SF(B0, b4) = sA[r0 * LD + c0];
-        SF(B0, PL + b4) = sA[r0 * LD + c1];
-        SF(B0, 2 * PL + b4) = sA[r1 * LD + c0];
-        SF(B0, 3 * PL + b4) = sA[r1 * LD + c1];
+        const int b = tid + q * NT;
+        if (b >= nblk0) continue;
+        const int r = 2 * bI[q], c = 2 * bJ[q], b4 = b * 4;  // positions are indices at the start
+        SF(B0, b4) = sA[r * LD + c];
+        SF(B0, PL + b4) = sA[r * LD + c + 1];
+        SF(B0, 2 * PL + b4) = sA[(r + 1) * LD + c];
+        SF(B0, 3 * PL + b4) = sA[(r + 1) * LD + c + 1];
     }
     __syncthreads();
+    for (int idx = tid; idx < 4 * NBS; idx += NT) SF(B1, idx * 4) = 0.0f;  // ghost slots of tiling 1 stay zero
+    __syncthreads();
 
-    // One rotation step from buffer `cur` into buffer `nxt`.
-    auto step = [&](const char *__restrict__ cur, char *__restrict__ nxt) {
-        if (tid < HK) {
-            const int bd = tid * (tid + 3) * 2;  // block (t, t), bytes
-            const float app = LF(cur, bd), apq = LF(cur, 2 * PL + bd), aqq = LF(cur, 3 * PL + bd);
+    // One rotation step on tiling T, from buffer `cur` into buffer `nxt`.
+    auto step = [&](auto tiling, const char *__restrict__ cur, char *__restrict__ nxt) {
+        constexpr int T = decltype(tiling)::value;
+        const int npair = HK + T;
+        if (tid < npair) {
             float c = 1.0f, s = 0.0f, ta = 0.0f;
-            if (fabsf(apq) > 1e-30f) {  // entries are scaled to max |a| ~ 1
-                const float tau = 0.5f * (aqq - app) * __builtin_amdgcn_rcpf(apq);
-                const float t = copysignf(__builtin_amdgcn_rcpf(fabsf(tau) + __builtin_sqrtf(1.0f + tau * tau)),
-                                          tau);
-                c = __builtin_amdgcn_rsqf(1.0f + t * t);
-                s = t * c;
-                ta = t * apq;
+            if (T == 1 && (tid == 0 || tid == HK)) {
+                c = 0.0f;
+                s = tid == 0 ? -1.0f : 1.0f;
+            } else {
+                const int bd = tid * (tid + 3) * 2;  // block (t, t), bytes
+                const float app = LF(cur, bd), apq = LF(cur, 2 * PL + bd), aqq = LF(cur, 3 * PL + bd);
+                if (fabsf(apq) > 1e-30f) {  // entries are scaled to max |a| ~ 1
+                    const float tau = 0.5f * (aqq - app) * __builtin_amdgcn_rcpf(apq);
+                    const float t =
+                        copysignf(__builtin_amdgcn_rcpf(fabsf(tau) + __builtin_sqrtf(1.0f + tau * tau)), tau);
+                    c = __builtin_amdgcn_rsqf(1.0f + t * t);
+                    s = t * c;
+                    ta = t * apq;
+                }
             }
             sm.cst[tid] = make_float4(c, s, ta, 0.0f);
         }
         __syncthreads();
-        // A <- J^T A J on this thread's blocks, stored at the moved positions.
-        // A diagonal block takes the Jacobi values (exact zero off the
-        // diagonal) in place of the generic product, without branching.
+        // A <- J^T A J on this thread's blocks, swapped and stored in the other
+        // tiling.  A diagonal block of a real pair takes the Jacobi values
+        // (exact zero off the diagonal) by select; the ghost pairs' blocks
+        // use the product, which is exact for their (0, +-1) rotations.
+        const int nblk = T == 0 ? nblk0 : nblk1;
 #pragma unroll
         for (int q = 0; q < NA; ++q) {
             const int I = bI[q], J = bJ[q];
-            if (I < 0) continue;
+            if (tid + q * NT >= nblk) continue;
             const int b4 = (tid + q * NT) * 4;
-            const bool dg = I == J;
+            const bool dg = I == J && (T == 0 || (I != 0 && I != HK));
             const float a00 = LF(cur, b4), a01v = LF(cur, a01[q]);
             const float a10 = LF(cur, 2 * PL + b4), a11 = LF(cur, 3 * PL + b4);
             const float4 cs1 = sm.cst[I];
@@ -484,57 +510,48 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
             const float b10 = s1 * a00 + c1 * a10, b11 = s1 * a01v + c1 * a11;
             const float n00 = c2 * b00 - s2 * b01, n01 = s2 * b00 + c2 * b01;
             const float n10 = c2 * b10 - s2 * b11, n11 = s2 * b10 + c2 * b11;
-            SF(nxt, dst[q][0]) = dg ? a00 - cs1.z : n00;
-            SF(nxt, dst[q][1]) = dg ? 0.0f : n01;
-            SF(nxt, dst[q][2]) = dg ? 0.0f : n10;
-            SF(nxt, dst[q][3]) = dg ? a11 + cs1.z : n11;
+            SF(nxt, dst[T][q][0]) = dg ? a00 - cs1.z : n00;
+            SF(nxt, dst[T][q][1]) = dg ? 0.0f : n01;
+            SF(nxt, dst[T][q][2]) = dg ? 0.0f : n10;
+            SF(nxt, dst[T][q][3]) = dg ? a11 + cs1.z : n11;
         }
-        // V <- V J in registers: (V_top, V_bottom) <- (c V_top - s V_bottom,
-        // s V_top + c V_bottom), then the ring move (one-lane shifts).  Rows
-        // past K are zero in lanes < HK and stay zero; lanes >= HK never feed
-        // a lane < HK (the last pair takes its own bottom, not lane HK).
-        if (HK > 1) {
-            const float4 cs = sm.cst[vlane ? lane : 0];
-            const float c = cs.x, sg = cs.y;
-            const bool first = lane == 0, last = lane == HK - 1;
+        // V <- V J, swapped.  Even steps: a lane's own two columns.  Odd
+        // steps: lane i pairs position 2i-1 (bottom of lane i-1) with its top;
+        // the new position 2i-1 goes back to lane i-1.  Lanes past the pairs
+        // rotate by the identity and keep zeros.
+        const bool pl = lane < npair;
+        const float4 csl = sm.cst[pl ? lane : 0];
+        const float c = pl ? csl.x : 1.0f, sg = pl ? csl.y : 0.0f;
 #pragma unroll
-            for (int j = 0; j < RPW; ++j) {
-                const float nt = c * vt[j] - sg * vb[j];
-                const float nb = sg * vt[j] + c * vb[j];
-                const float up = wave_shl1(nt);  // top of lane + 1
-                vt[j] = first ? nt : (last ? nb : up);
-                vb[j] = wave_shr1(nb, up);  // bottom of lane - 1; lane 0: top of lane 1
-            }
-        } else {
-            // one pair (K = 2): a rotation, no movement
-            const float4 cs = sm.cst[0];
-#pragma unroll
-            for (int j = 0; j < RPW; ++j) {
-                const float nt = cs.x * vt[j] - cs.y * vb[j];
-                const float nb = cs.y * vt[j] + cs.x * vb[j];
-                vt[j] = nt;
-                vb[j] = nb;
+        for (int j = 0; j < RPW; ++j) {
+            if (T == 0) {
+                const float t0 = vt[j];
+                vt[j] = sg * t0 + c * vb[j];
+                vb[j] = c * t0 - sg * vb[j];
+            } else {
+                const float x = wave_shr0(vb[j]);  // bottom of lane - 1 (lane 0: ghost)
+                const float z = sg * x + c * vt[j];
+                vt[j] = c * x - sg * vt[j];
+                vb[j] = wave_shl1(z);
             }
         }
         __syncthreads();
     };
 
-    // A sweep is K-1 (odd) steps: pairs of steps B0 -> B1 -> B0, a last
-    // step B0 -> B1 and a copy back, so a sweep starts and ends in B0.
     int sweep = 0;
     for (;; ++sweep) {
-        // off(A)^2 = 2 x (squares of the lower off-diagonal entries)
+        // off(A)^2 = 2 x (squares of the lower off-diagonal entries), tiling 0
         float o = 0.0f;
 #pragma unroll
         for (int q = 0; q < NA; ++q) {
-            if (bI[q] < 0) continue;
+            if (tid + q * NT >= nblk0) continue;
             const int b4 = (tid + q * NT) * 4;
             const float a10 = LF(B0, 2 * PL + b4);
             if (bI[q] == bJ[q]) {
                 o += 2.0f * a10 * a10;
             } else {
-                const float a00 = LF(B0, b4), a01 = LF(B0, PL + b4), a11 = LF(B0, 3 * PL + b4);
-                o += 2.0f * (a00 * a00 + a01 * a01 + a10 * a10 + a11 * a11);
+                const float a00 = LF(B0, b4), a01v = LF(B0, PL + b4), a11 = LF(B0, 3 * PL + b4);
+                o += 2.0f * (a00 * a00 + a01v * a01v + a10 * a10 + a11 * a11);
             }
         }
         const float off2 = block_sum<NT>(o, sm.redf);
@@ -544,29 +561,22 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
             break;
         }
 #pragma unroll 1
-        for (int r = 0; r < K - 2; r += 2) {
-            step(B0, B1);
-            step(B1, B0);
+        for (int r = 0; r < K; r += 2) {
+            step(std::integral_constant<int, 0>{}, B0, B1);
+            step(std::integral_constant<int, 1>{}, B1, B0);
         }
-        step(B0, B1);
-#pragma unroll
-        for (int q = 0; q < NA; ++q) {
-            if (bI[q] < 0) continue;
-            const int b4 = (tid + q * NT) * 4;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) SF(B0, e * PL + b4) = LF(B1, e * PL + b4);
-        }
-        __syncthreads();
     }
     if (tid == 0 && a.ctl != nullptr) atomicAdd(&a.ctl->sweeps, sweep);
+    const bool rev = sweep & 1;  // position p holds index K-1-p
 
-    // Eigenvalues from the diagonal blocks (positions equal indices after
-    // whole sweeps); indices past K are padding.
+    // Eigenvalues from the diagonal blocks of tiling 0; indices past K are
+    // padding.
     if (tid < S) {
         float l = 0.0f;
         if (tid < K) {
-            const int t = tid < HK ? tid : K - 1 - tid;
-            l = LF(B0, (tid < HK ? 0 : 3 * PL) + t * (t + 3) * 2) * unscale;
+            const int p = rev ? K - 1 - tid : tid;
+            const int t = p >> 1;
+            l = LF(B0, ((p & 1) ? 3 * PL : 0) + t * (t + 3) * 2) * unscale;
         }
         sm.lam[tid] = l;
         sm.lp[tid] = fmaxf(l, 0.0f);
@@ -584,11 +594,13 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
     for (int j = 0; j < RPW; ++j) {
         const int row = wv + j * NW;
         if (vlane && row < K) {
-            sV[row * LD + lane] = vt[j];
-            sV[row * LD + K - 1 - lane] = vb[j];
+            const int c0 = rev ? K - 1 - 2 * lane : 2 * lane, c1 = rev ? K - 2 - 2 * lane : 2 * lane + 1;
+            sV[row * LD + c0] = vt[j];
+            sV[row * LD + c1] = vb[j];
         }
     }
     __syncthreads();
+
     // E = V^T V - I  -> sA (A's eigenvalues are in sm.lam)
     product_store<S, NT, 0>(sV, sV, nullptr, K, tid,
                             [&](int i, int j, float v) { sA[i * LD + j] = v - (i == j ? 1.0f : 0.0f); });

@@ -120,3 +120,28 @@ def test_batch_handle_queue_plan(torch):
     (it_q, x_q), (it_b, x_b) = res[(True, 256)], res[(False, 256)]
     assert it_q == it_b
     assert _rel(x_q, x_b) <= 1e-6
+
+
+def test_queue_with_many_cliques_per_workgroup(torch):
+    """More cliques than queue workgroups, so every workgroup projects several
+    cliques of different buckets in turn inside one launch (LDS and the
+    warm-start state pass from clique to clique).  The queue launch must
+    agree with the per-bucket launches through warm-started ADMM iterations,
+    and the eigensolver must stay at its warm-start sweep count."""
+    prob = synth.peo_chordal(p=1500, smin=4, smax=96, omax=8, m=2000, nnz_row=20, seed=4242)
+    out = {}
+    for plan in [(True, 512), (False, 512)]:
+        sol = cdcs.Solver(prob)
+        sol.set_projection_plan(*plan)
+        t = sol.tuning()
+        if plan[0]:
+            assert t["grid"] < prob.p  # several cliques per workgroup
+        st = sol.new_state("primal")
+        info = sol.solve(st, form="primal", tol=0.0, max_iter=60, check_every=20)
+        assert info.jacobi_cap_hits == 0
+        out[plan] = (st["x"].cpu().numpy(), _lam(sol, st), info.jacobi_sweeps / (info.iters * prob.p))
+        sol.close()
+    (xq, lq, swq), (xb, lb, swb) = out[(True, 512)], out[(False, 512)]
+    assert _rel(xq, xb) <= 1e-5
+    assert _rel(lq, lb) <= 1e-5
+    assert swq <= 1.25 * swb + 0.05
