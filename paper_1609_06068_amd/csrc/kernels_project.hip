@@ -234,8 +234,10 @@ __device__ __forceinline__ void mfma_product(const float *X, const float *Y, con
     for (int u = 0; u < TRW; ++u)
 #pragma unroll
         for (int v = 0; v < TCW; ++v) acc[u][v] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    const int n4 = (n + 3) & ~3;  // <= S; terms past n are zero
-    for (int q0 = 0; q0 < n4; q0 += 4) {
+    // Two 4-deep slices per iteration (n rounded up to 8 <= S; terms past n
+    // are zero), so the second slice's loads overlap the first's products.
+    const int n8 = (n + 7) & ~7;
+    auto slice = [&](int q0) {
         const int q = q0 + lk;
         float av[TRW], bv[TCW];
 #pragma unroll
@@ -253,6 +255,10 @@ __device__ __forceinline__ void mfma_product(const float *X, const float *Y, con
         for (int u = 0; u < TRW; ++u)
 #pragma unroll
             for (int v = 0; v < TCW; ++v) acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[v], acc[u][v], 0, 0, 0);
+    };
+    for (int q0 = 0; q0 < n8; q0 += 8) {
+        slice(q0);
+        slice(q0 + 4);
     }
 }
 
@@ -297,7 +303,7 @@ __device__ __forceinline__ void product_store(const float *X, const float *Y, co
 
 // Small per-workgroup LDS of the projection (sized for the largest bucket).
 struct ProjSmall {
-    float4 cst[64];              // rotations of one step: (c, s, t a_PQ, 0) of pair t
+    float4 cst[64];              // rotations of one step: (c, s, -, -) of pair t
     float lam[96], lp[96];       // eigenvalues, clamped eigenvalues
     float redf[8];
     double redd[8];
@@ -339,22 +345,35 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
     }
     __syncthreads();
 
-    // Gather W (packed lower triangle of the k x k block).
+    // Gather W (packed lower triangle of the k x k block).  Each thread
+    // loads GU slots before storing any, so their memory latencies overlap
+    // (indices past the block are clamped for the loads and not stored).
+    constexpr int GU = 4;
     float amax = 0.0f;
-    for (int s = tid; s < nslot; s += NT) {
-        const int i = tri_row(s), j = s - i * (i + 1) / 2;
-        float w;
-        if (a.mode == PROJ_STANDALONE) {
-            w = a.Win[off + s];
-        } else if (a.mode == PROJ_PRIMAL) {
-            const double hx = a.x[a.gather[off + s]];
-            w = (float)(hx - (double)a.lam[off + s] / a.rho);
-        } else {
-            w = (float)((double)a.v[off + s] - (double)a.lam[off + s] / a.rho);
+    for (int s0 = tid; s0 < nslot; s0 += GU * NT) {
+        float w[GU];
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const int64_t g = off + min(s0 + u * NT, nslot - 1);
+            if (a.mode == PROJ_STANDALONE) {
+                w[u] = a.Win[g];
+            } else if (a.mode == PROJ_PRIMAL) {
+                const double hx = a.x[a.gather[g]];
+                w[u] = (float)(hx - (double)a.lam[g] / a.rho);
+            } else {
+                w[u] = (float)((double)a.v[g] - (double)a.lam[g] / a.rho);
+            }
         }
-        sA[i * LD + j] = w;
-        sA[j * LD + i] = w;
-        amax = fmaxf(amax, fabsf(w));
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const int s = s0 + u * NT;
+            if (s < nslot) {
+                const int i = tri_row(s), j = s - i * (i + 1) / 2;
+                sA[i * LD + j] = w[u];
+                sA[j * LD + i] = w[u];
+                amax = fmaxf(amax, fabsf(w[u]));
+            }
+        }
     }
     // Scale by a power of two (exact) so that max |w| lies in [1, 2): squares
     // neither overflow nor underflow for any finite FP32 input.
@@ -410,12 +429,22 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
     constexpr int PL = NBS * 4;          // plane stride in bytes
     constexpr int DUMMY = 4 * NBS * 4;   // write-only slot for ghost entries
     static_assert(4 * NBS + 1 <= S * LD, "a pair-block buffer fits in an S x (S+1) array");
+    // Byte offset in tiling 1-T of element e (= 2 h_row + h_col) of block
+    // (I, J) of tiling T after the rotation and the swap.
+    auto move_to = [&](int T, int I, int J, int e) {
+        const int p1 = slot_pos(T, I, 1 - (e >> 1), HK), p2 = slot_pos(T, J, 1 - (e & 1), HK);
+        int t1, g1, t2, g2;
+        pos_slot(1 - T, max(p1, 0), HK, t1, g1);
+        pos_slot(1 - T, max(p2, 0), HK, t2, g2);
+        return (p1 < 0 || p2 < 0) ? DUMMY : pair_slot(t1, g1, t2, g2, NBS) * 4;
+    };
     // Blocks of this thread (the same lower-triangle numbering in both
-    // tilings): pair indices, the read address of element 1 (a diagonal
-    // block keeps only elements 0, 2, 3, and 1 equals 2) and, per tiling, the
-    // byte offsets in the other tiling where the four rotated and swapped
-    // elements go (element e = 2 h_row + h_col).
-    int bI[NA], bJ[NA], a01[NA], dst[2][NA][4];
+    // tilings): pair indices and, per tiling, where the four rotated
+    // elements go.  The diagonal block of a real pair is written by the
+    // thread that computes that pair's rotation (thread t: pair t), with the
+    // targets in dgo; element 1 of a diagonal block is not kept (it equals
+    // element 2; in tiling 1 the ghost pairs' element 1 stays zero).
+    int bI[NA], bJ[NA], dst[2][NA][4], dgo[2][3];
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
         const int b = tid + q * NT;
@@ -423,17 +452,19 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
         const int I = tri_row(bc), J = bc - I * (I + 1) / 2;
         bI[q] = (b < nblk1) ? I : -1;
         bJ[q] = J;
-        a01[q] = (I == J ? 2 * PL : PL) + b * 4;
 #pragma unroll
         for (int T = 0; T < 2; ++T)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int p1 = slot_pos(T, I, 1 - (e >> 1), HK), p2 = slot_pos(T, J, 1 - (e & 1), HK);
-                int t1, g1, t2, g2;
-                pos_slot(1 - T, max(p1, 0), HK, t1, g1);
-                pos_slot(1 - T, max(p2, 0), HK, t2, g2);
-                dst[T][q][e] = (p1 < 0 || p2 < 0) ? DUMMY : pair_slot(t1, g1, t2, g2, NBS) * 4;
-            }
+            for (int e = 0; e < 4; ++e) dst[T][q][e] = move_to(T, I, J, e);
+    }
+    {
+        const int t = min(tid, HK);
+#pragma unroll
+        for (int T = 0; T < 2; ++T) {
+            dgo[T][0] = move_to(T, t, t, 0);
+            dgo[T][1] = move_to(T, t, t, 2);
+            dgo[T][2] = move_to(T, t, t, 3);
+        }
     }
     // V in registers: lane i of a wave holds, for its rows (wave w: rows
     // w, w + NW, ...), the columns at positions 2i ("top") and 2i+1.
@@ -471,13 +502,16 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
         constexpr int T = decltype(tiling)::value;
         const int npair = HK + T;
         if (tid < npair) {
-            float c = 1.0f, s = 0.0f, ta = 0.0f;
+            float c = 1.0f, s = 0.0f;
             if (T == 1 && (tid == 0 || tid == HK)) {
                 c = 0.0f;
                 s = tid == 0 ? -1.0f : 1.0f;
             } else {
+                // Jacobi rotation of pair t; the new diagonal block (exact zero
+                // off the diagonal) goes straight to the other tiling.
                 const int bd = tid * (tid + 3) * 2;  // block (t, t), bytes
                 const float app = LF(cur, bd), apq = LF(cur, 2 * PL + bd), aqq = LF(cur, 3 * PL + bd);
+                float ta = 0.0f;
                 if (fabsf(apq) > 1e-30f) {  // entries are scaled to max |a| ~ 1
                     const float tau = 0.5f * (aqq - app) * __builtin_amdgcn_rcpf(apq);
                     const float t =
@@ -486,34 +520,33 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
                     s = t * c;
                     ta = t * apq;
                 }
+                SF(nxt, dgo[T][0]) = app - ta;
+                SF(nxt, dgo[T][1]) = 0.0f;
+                SF(nxt, dgo[T][2]) = aqq + ta;
             }
-            sm.cst[tid] = make_float4(c, s, ta, 0.0f);
+            sm.cst[tid] = make_float4(c, s, 0.0f, 0.0f);
         }
         __syncthreads();
-        // A <- J^T A J on this thread's blocks, swapped and stored in the other
-        // tiling.  A diagonal block of a real pair takes the Jacobi values
-        // (exact zero off the diagonal) by select; the ghost pairs' blocks
-        // use the product, which is exact for their (0, +-1) rotations.
+        // A <- J^T A J on this thread's off-diagonal blocks (and the ghost
+        // pairs' diagonal blocks, exact for their (0, +-1) rotations), swapped
+        // and stored in the other tiling.
         const int nblk = T == 0 ? nblk0 : nblk1;
 #pragma unroll
         for (int q = 0; q < NA; ++q) {
             const int I = bI[q], J = bJ[q];
-            if (tid + q * NT >= nblk) continue;
+            if (tid + q * NT >= nblk || (I == J && (T == 0 || (I != 0 && I != HK)))) continue;
             const int b4 = (tid + q * NT) * 4;
-            const bool dg = I == J && (T == 0 || (I != 0 && I != HK));
-            const float a00 = LF(cur, b4), a01v = LF(cur, a01[q]);
+            const float a00 = LF(cur, b4), a01 = LF(cur, PL + b4);
             const float a10 = LF(cur, 2 * PL + b4), a11 = LF(cur, 3 * PL + b4);
-            const float4 cs1 = sm.cst[I];
+            const float2 cs1 = *reinterpret_cast<const float2 *>(&sm.cst[I]);
             const float2 cs2 = *reinterpret_cast<const float2 *>(&sm.cst[J]);
             const float c1 = cs1.x, s1 = cs1.y, c2 = cs2.x, s2 = cs2.y;
-            const float b00 = c1 * a00 - s1 * a10, b01 = c1 * a01v - s1 * a11;
-            const float b10 = s1 * a00 + c1 * a10, b11 = s1 * a01v + c1 * a11;
-            const float n00 = c2 * b00 - s2 * b01, n01 = s2 * b00 + c2 * b01;
-            const float n10 = c2 * b10 - s2 * b11, n11 = s2 * b10 + c2 * b11;
-            SF(nxt, dst[T][q][0]) = dg ? a00 - cs1.z : n00;
-            SF(nxt, dst[T][q][1]) = dg ? 0.0f : n01;
-            SF(nxt, dst[T][q][2]) = dg ? 0.0f : n10;
-            SF(nxt, dst[T][q][3]) = dg ? a11 + cs1.z : n11;
+            const float b00 = c1 * a00 - s1 * a10, b01 = c1 * a01 - s1 * a11;
+            const float b10 = s1 * a00 + c1 * a10, b11 = s1 * a01 + c1 * a11;
+            SF(nxt, dst[T][q][0]) = c2 * b00 - s2 * b01;
+            SF(nxt, dst[T][q][1]) = s2 * b00 + c2 * b01;
+            SF(nxt, dst[T][q][2]) = c2 * b10 - s2 * b11;
+            SF(nxt, dst[T][q][3]) = s2 * b10 + c2 * b11;
         }
         // V <- V J, swapped.  Even steps: a lane's own two columns.  Odd
         // steps: lane i pairs position 2i-1 (bottom of lane i-1) with its top;
@@ -619,24 +652,38 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
         }
 
     double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-    for (int s = tid; s < nslot; s += NT) {
-        const int i = tri_row(s), j = s - i * (i + 1) / 2;
-        const float pv32 = sA[i * LD + j];
-        const int64_t g = off + s;
-        if (a.mode == PROJ_STANDALONE) {
-            a.Pout[g] = pv32;
-        } else if (a.mode == PROJ_PRIMAL) {
-            const double hx = a.x[a.gather[g]];
-            const double pv = (double)pv32;
-            a.lam[g] = (float)((double)a.lam[g] + a.rho * (pv - hx));
-            a.blk[g] = pv32;
-            const double wgt = (i == j) ? 1.0 : 2.0;
-            const double d = pv - hx;
-            p0 += wgt * d * d;
-            p1 += wgt * hx * hx;
-            p2 += wgt * pv * pv;
-        } else {
-            a.blk[g] = pv32;
+    for (int s0 = tid; s0 < nslot; s0 += GU * NT) {
+        double hx[GU];
+        float lm[GU];
+        if (a.mode == PROJ_PRIMAL) {
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int64_t g = off + min(s0 + u * NT, nslot - 1);
+                hx[u] = a.x[a.gather[g]];
+                lm[u] = a.lam[g];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const int s = s0 + u * NT;
+            if (s >= nslot) continue;
+            const int i = tri_row(s), j = s - i * (i + 1) / 2;
+            const float pv32 = sA[i * LD + j];
+            const int64_t g = off + s;
+            if (a.mode == PROJ_STANDALONE) {
+                a.Pout[g] = pv32;
+            } else if (a.mode == PROJ_PRIMAL) {
+                const double pv = (double)pv32;
+                a.lam[g] = (float)((double)lm[u] + a.rho * (pv - hx[u]));
+                a.blk[g] = pv32;
+                const double wgt = (i == j) ? 1.0 : 2.0;
+                const double d = pv - hx[u];
+                p0 += wgt * d * d;
+                p1 += wgt * hx[u] * hx[u];
+                p2 += wgt * pv * pv;
+            } else {
+                a.blk[g] = pv32;
+            }
         }
     }
     if (a.mode == PROJ_PRIMAL) {
