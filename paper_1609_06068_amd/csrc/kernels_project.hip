@@ -205,56 +205,66 @@ __device__ __forceinline__ void tile_product(const float *X, const float *Y,
 }
 
 // S x S products on FP32 matrix cores (v_mfma_f32_16x16x4_f32), buckets S >=
-// 32.  The 16 x 16 output tiles are split over the waves as a WR x WC grid of
-// tile blocks, so each wave loads one A operand per tile row and one B operand
-// per tile column of its block for every 4-deep slice of the sum.
+// 32.  The 16 x 16 output tiles (all T x T, or the T (T+1) / 2 on and below
+// the diagonal when only the lower triangle of a symmetric result is needed)
+// are dealt to the waves round-robin; a wave keeps the accumulators of its
+// tiles and loads one A and one B operand per tile for every 4-deep slice.
 // Operand layout of the instruction (lane l): A[l % 16][l / 16] (16 x 4),
 // B[l / 16][l % 16] (4 x 16); result element r: D[(l / 16) * 4 + r][l % 16].
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-template <int S, int NT>
+template <int S, int NT, bool LOWER>
 struct MfmaTiles {
     static constexpr int T = S / 16;
     static constexpr int NW = NT / 64;
-    static constexpr int WR = NW == 1 ? 1 : 2;
-    static constexpr int WC = NW / WR;
-    static constexpr int TRW = (T + WR - 1) / WR, TCW = (T + WC - 1) / WC;
+    static constexpr int NTILE = LOWER ? T * (T + 1) / 2 : T * T;
+    static constexpr int PER = (NTILE + NW - 1) / NW;  // tiles per wave, at most
 };
 
-// C = X^T Y (mode 0), X Y (mode 1) or X diag(lp) Y^T (mode 2) over q < n.
-template <int S, int NT, int MODE>
+// Tile t of the list -> tile row and column (uniform across the wave).
+template <int T, bool LOWER>
+__device__ __forceinline__ void tile_rc(int t, int &ti, int &tj) {
+    if (LOWER) {
+        ti = 0;
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        tj = t - ti * (ti + 1) / 2;
+    } else {
+        ti = t / T;
+        tj = t - ti * T;
+    }
+}
+
+// C = X^T Y (mode 0), X Y (mode 1) or X diag(lp) Y^T (mode 2) over q < n, on
+// this wave's tiles.
+template <int S, int NT, int MODE, bool LOWER>
 __device__ __forceinline__ void mfma_product(const float *X, const float *Y, const float *lp, int n, int lane,
-                                             int wv,
-                                             f32x4 (&acc)[MfmaTiles<S, NT>::TRW][MfmaTiles<S, NT>::TCW]) {
-    using MT = MfmaTiles<S, NT>;
-    constexpr int LD = S + 1, TRW = MT::TRW, TCW = MT::TCW;
-    const int wr = wv / MT::WC, wc = wv % MT::WC;
+                                             int wv, f32x4 (&acc)[MfmaTiles<S, NT, LOWER>::PER]) {
+    using MT = MfmaTiles<S, NT, LOWER>;
+    constexpr int LD = S + 1, PER = MT::PER;
     const int lr = lane & 15, lk = lane >> 4;
+    int ra[PER], cb[PER];  // this lane's A row and B column, per tile
 #pragma unroll
-    for (int u = 0; u < TRW; ++u)
-#pragma unroll
-        for (int v = 0; v < TCW; ++v) acc[u][v] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int r = 0; r < PER; ++r) {
+        int ti, tj;
+        tile_rc<MT::T, LOWER>(min(wv + r * MT::NW, MT::NTILE - 1), ti, tj);
+        ra[r] = ti * 16 + lr;
+        cb[r] = tj * 16 + lr;
+        acc[r] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
     // Two 4-deep slices per iteration (n rounded up to 8 <= S; terms past n
     // are zero), so the second slice's loads overlap the first's products.
     const int n8 = (n + 7) & ~7;
     auto slice = [&](int q0) {
         const int q = q0 + lk;
-        float av[TRW], bv[TCW];
+        const float l = MODE == 2 ? lp[q] : 1.0f;
 #pragma unroll
-        for (int u = 0; u < TRW; ++u) {
-            const int i = min((wr * TRW + u) * 16 + lr, S - 1);  // tiles past S: clamped, never stored
-            av[u] = MODE == 0 ? X[q * LD + i] : X[i * LD + q];
-            if (MODE == 2) av[u] *= lp[q];
+        for (int r = 0; r < PER; ++r) {
+            if (wv + r * MT::NW >= MT::NTILE) continue;  // uniform
+            float av = MODE == 0 ? X[q * LD + ra[r]] : X[ra[r] * LD + q];
+            if (MODE == 2) av *= l;
+            const float bv = MODE == 2 ? Y[cb[r] * LD + q] : Y[q * LD + cb[r]];
+            acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[r], 0, 0, 0);
         }
-#pragma unroll
-        for (int v = 0; v < TCW; ++v) {
-            const int j = min((wc * TCW + v) * 16 + lr, S - 1);
-            bv[v] = MODE == 2 ? Y[j * LD + q] : Y[q * LD + j];
-        }
-#pragma unroll
-        for (int u = 0; u < TRW; ++u)
-#pragma unroll
-            for (int v = 0; v < TCW; ++v) acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[v], acc[u][v], 0, 0, 0);
     };
     for (int q0 = 0; q0 < n8; q0 += 8) {
         slice(q0);
@@ -265,28 +275,33 @@ __device__ __forceinline__ void mfma_product(const float *X, const float *Y, con
 // Compute an S x S product (matrix cores for S >= 32, register tiles on the
 // vector ALUs below), wait until every thread has read its operands, then
 // hand each result element to st(row, col, value): the result may overwrite
-// an operand.  The caller synchronises before reading what st wrote.
-template <int S, int NT, int MODE, typename Store>
+// an operand.  The caller synchronises before reading what st wrote.  LOWER:
+// only elements on and below the diagonal of a symmetric result are needed
+// (the matrix-core path then computes only the tiles on and below the
+// diagonal and may skip the others; MIRROR also hands over their transposes).
+template <int S, int NT, int MODE, bool LOWER = false, bool MIRROR = false, typename Store>
 __device__ __forceinline__ void product_store(const float *X, const float *Y, const float *lp, int n, int tid,
                                               Store st) {
     if constexpr (S >= 32) {
-        using MT = MfmaTiles<S, NT>;
+        using MT = MfmaTiles<S, NT, LOWER>;
         const int lane = tid & 63, wv = uniform(tid >> 6);
-        f32x4 acc[MT::TRW][MT::TCW];
-        mfma_product<S, NT, MODE>(X, Y, lp, n, lane, wv, acc);
+        f32x4 acc[MT::PER];
+        mfma_product<S, NT, MODE, LOWER>(X, Y, lp, n, lane, wv, acc);
         __syncthreads();
-        const int wr = wv / MT::WC, wc = wv % MT::WC;
 #pragma unroll
-        for (int u = 0; u < MT::TRW; ++u)
+        for (int r = 0; r < MT::PER; ++r) {
+            const int t = wv + r * MT::NW;
+            if (t >= MT::NTILE) continue;
+            int ti, tj;
+            tile_rc<MT::T, LOWER>(t, ti, tj);
+            const int col = tj * 16 + (lane & 15);
 #pragma unroll
-            for (int v = 0; v < MT::TCW; ++v) {
-                const int col = (wc * MT::TCW + v) * 16 + (lane & 15);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = (wr * MT::TRW + u) * 16 + (lane >> 4) * 4 + r;
-                    if (row < S && col < S) st(row, col, acc[u][v][r]);
-                }
+            for (int rr = 0; rr < 4; ++rr) {
+                const int row = ti * 16 + (lane >> 4) * 4 + rr;
+                st(row, col, acc[r][rr]);
+                if (MIRROR && ti != tj) st(col, row, acc[r][rr]);
             }
+        }
     } else {
         using TL = Tiles<S, NT>;
         const int ti = tid / TL::GC, tj = tid % TL::GC;
@@ -336,12 +351,23 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
     const bool warm = a.vwarm != nullptr;
     float *vw = warm ? a.vwarm + a.vwoff[id] : nullptr;
 
-    for (int idx = tid; idx < S * S; idx += NT) {
-        const int i = idx / S, j = idx % S;
-        sA[i * LD + j] = 0.0f;
-        float v = (i == j) ? 1.0f : 0.0f;
-        if (warm && i < k && j < k) v = vw[i * k + j];
-        sV[i * LD + j] = v;
+    // A <- 0; V <- V_prev (warm start) or I, padded with the identity.  All
+    // of a thread's V_prev loads are issued before its first store.
+    constexpr int NI = (S * S + NT - 1) / NT;
+    float vv[NI];
+#pragma unroll
+    for (int r = 0; r < NI; ++r) {
+        const int idx = tid + r * NT, i = idx / S, j = idx % S;
+        vv[r] = (i == j) ? 1.0f : 0.0f;
+        if (warm && idx < S * S && i < k && j < k) vv[r] = vw[i * k + j];
+    }
+#pragma unroll
+    for (int r = 0; r < NI; ++r) {
+        const int idx = tid + r * NT, i = idx / S, j = idx % S;
+        if (idx < S * S) {
+            sA[i * LD + j] = 0.0f;
+            sV[i * LD + j] = vv[r];
+        }
     }
     __syncthreads();
 
@@ -395,19 +421,11 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
     const int Kw = k + (k & 1);  // products run over the active size
     auto to_sA = [&](int i, int j, float v) { sA[i * LD + j] = v; };
     if (warm) {
-        // A <- V^T W V, symmetrised (V = V_prev, orthonormal to FP32 accuracy).
-        product_store<S, NT, 1>(sA, sV, nullptr, Kw, tid, to_sA);  // W V
+        // A <- V^T W V (V = V_prev, orthonormal to FP32 accuracy); the
+        // eigensolver reads only its lower triangle.
+        product_store<S, NT, 1>(sA, sV, nullptr, Kw, tid, to_sA);        // W V
         __syncthreads();
-        product_store<S, NT, 0>(sV, sA, nullptr, Kw, tid, to_sA);  // V^T (W V)
-        __syncthreads();
-        for (int idx = tid; idx < S * S; idx += NT) {
-            const int i = idx / S, j = idx % S;
-            if (i > j) {
-                const float m = 0.5f * (sA[i * LD + j] + sA[j * LD + i]);
-                sA[i * LD + j] = m;
-                sA[j * LD + i] = m;
-            }
-        }
+        product_store<S, NT, 0, true>(sV, sA, nullptr, Kw, tid, to_sA);  // V^T (W V)
         __syncthreads();
     }
 
@@ -635,14 +653,14 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
     __syncthreads();
 
     // E = V^T V - I  -> sA (A's eigenvalues are in sm.lam)
-    product_store<S, NT, 0>(sV, sV, nullptr, K, tid,
-                            [&](int i, int j, float v) { sA[i * LD + j] = v - (i == j ? 1.0f : 0.0f); });
+    product_store<S, NT, 0, true, true>(sV, sV, nullptr, K, tid,
+                                        [&](int i, int j, float v) { sA[i * LD + j] = v - (i == j ? 1.0f : 0.0f); });
     __syncthreads();
     // Vn = V - V E / 2  -> sV
     product_store<S, NT, 1>(sV, sA, nullptr, K, tid, [&](int i, int j, float v) { sV[i * LD + j] -= 0.5f * v; });
     __syncthreads();
-    // P = Vn diag(max(Lambda, 0)) Vn^T  -> sA
-    product_store<S, NT, 2>(sV, sV, sm.lp, K, tid, to_sA);
+    // P = Vn diag(max(Lambda, 0)) Vn^T  -> sA (lower triangle; only it is read)
+    product_store<S, NT, 2, true>(sV, sV, sm.lp, K, tid, to_sA);
     __syncthreads();
 
     if (warm && a.warm_store)
