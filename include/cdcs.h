@@ -18,6 +18,10 @@
  * by that list position and holds matrix values (an off-diagonal entry stands
  * for both (i, j) and (j, i)).  Inner products and norms of global vectors
  * weight off-diagonal entries by 2, so they equal the paper's vec() products.
+ * (Inside a handle the entries are renumbered by first appearance in the
+ * packed clique blocks, so that the gather and scatter between global vectors
+ * and blocks stream through memory; every entry point converts its global
+ * vectors from and to the pattern order given here.)
  *
  * Cliques.  p cliques as a CSR (ptr[p+1], vert[]), vertices strictly
  * increasing inside a clique (the natural order of Sec. II-B).  The pattern
@@ -34,7 +38,9 @@
  * be freed on return.  Pointers documented "device" are caller-owned device
  * memory (e.g. torch tensors); the library never frees them.  The handle owns
  * its internal device data.  A handle is not thread-safe; calls on one handle
- * must be serialised by the caller.
+ * must be serialised by the caller, and the device work they enqueue must not
+ * overlap (one stream, or streams ordered by events): the handle's work
+ * buffers, the iterate among them, are shared by its calls.
  *
  * Streams.  Work is enqueued on the caller's stream (0 = legacy default
  * stream).  Entry points return after enqueueing, except cdcs_setup and
@@ -311,8 +317,12 @@ typedef enum {
 /*
  * Instrumentation: enqueue `reps` back-to-back launches of one kernel of an
  * iteration of the given form, with the arguments it has inside
- * cdcs_admm_solve on this state (the state is updated as by those launches).
- * Lets a caller bracket one kernel with events on `stream` to time it.
+ * cdcs_admm_solve on this state (y, blk, lam, v are updated as by those
+ * launches).  The x these launches read and write is the handle's own copy of
+ * the iterate, which equals st->x after a cdcs_admm_solve or cdcs_admm_step
+ * on this state; st->x itself is neither read nor written, so nothing but the
+ * named kernel runs.  Lets a caller bracket one kernel with events on
+ * `stream` to time it.
  * Errors: CDCS_E_ARG (unknown kernel, reps < 1, NULL state buffers).
  */
 cdcs_status cdcs_profile_kernel(cdcs_handle *h, const cdcs_state *st, int32_t form, double rho,

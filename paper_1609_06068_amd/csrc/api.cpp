@@ -129,7 +129,8 @@ struct HostProblem {
     int64_t nU = 0, nslots = 0, ld = 0;
     std::vector<int32_t> size;       // [p] clique sizes
     std::vector<int64_t> off;        // [p+1] packed slot offsets
-    std::vector<int32_t> gather;     // [nslots] entry of each packed slot (H_k)
+    std::vector<int32_t> gather;     // [nslots] internal entry of each packed slot (H_k)
+    std::vector<int32_t> perm;       // [nU] pattern position of each internal entry
     std::vector<int32_t> cnt;        // [nU] D_e = number of cliques covering e
     std::vector<double> wt, invD, s2, c, b;
     std::vector<float> Aw;           // [m * ld] w-scaled A, row-major, zero padded (dense path)
@@ -214,20 +215,44 @@ cdcs_status host_problem(const cdcs_pattern *pat, const cdcs_constraints *A, con
                 ++P.cnt[(size_t)e];
             }
     }
+    for (int64_t e = 0; e < nU; ++e)
+        if (P.cnt[(size_t)e] == 0) return fail(CDCS_E_PATTERN, "pattern entry " + std::to_string(e) + " lies in no clique");
+    // Internal entry order: first appearance in the packed slots, clique by
+    // clique.  An entry's value then sits where its (first) clique's slots
+    // sit, so the gather of x into the blocks and the scatter back read
+    // consecutive addresses; only entries shared by several cliques are read
+    // out of order.  Entry-space vectors cross the interface in pattern order.
+    std::vector<int32_t> inv((size_t)nU, -1);
+    P.perm.resize((size_t)nU);
+    {
+        int32_t nxt = 0;
+        for (int64_t g = 0; g < P.nslots; ++g) {
+            int32_t &ie = inv[(size_t)P.gather[(size_t)g]];
+            if (ie < 0) {
+                ie = nxt;
+                P.perm[(size_t)nxt++] = P.gather[(size_t)g];
+            }
+            P.gather[(size_t)g] = ie;
+        }
+    }
     // D = sum_k H_k^T H_k: overlap count of each entry (Sec. III-B.1).
+    std::vector<int32_t> cnt_pat;
+    cnt_pat.swap(P.cnt);
+    P.cnt.resize((size_t)nU);
     P.wt.resize((size_t)nU);
     P.invD.resize((size_t)nU);
     P.s2.resize((size_t)nU);
-    P.c.assign(c, c + nU);
+    P.c.resize((size_t)nU);
     P.b.assign(b, b + m);
     for (int64_t e = 0; e < nU; ++e) {
-        if (P.cnt[(size_t)e] == 0)
-            return fail(CDCS_E_PATTERN, "pattern entry " + std::to_string(e) + " lies in no clique");
+        const size_t ie = (size_t)inv[(size_t)e];
         const double w = (pat->i[e] == pat->j[e]) ? 1.0 : 2.0;
-        const double D = (double)P.cnt[(size_t)e];
-        P.wt[(size_t)e] = w;
-        P.invD[(size_t)e] = 1.0 / D;
-        P.s2[(size_t)e] = 1.0 / (w * D);
+        const double D = (double)cnt_pat[(size_t)e];
+        P.cnt[ie] = cnt_pat[(size_t)e];
+        P.wt[ie] = w;
+        P.invD[ie] = 1.0 / D;
+        P.s2[ie] = 1.0 / (w * D);
+        P.c[ie] = c[e];
     }
     P.ld = round_up(nU, align);
     if (!A->dense) {
@@ -246,7 +271,7 @@ cdcs_status host_problem(const cdcs_pattern *pat, const cdcs_constraints *A, con
         std::vector<std::pair<int32_t, double>> row;
         for (int32_t i = 0; i < m; ++i) {
             row.clear();
-            for (int64_t q = A->ptr[i]; q < A->ptr[i + 1]; ++q) row.push_back({A->idx[q], A->val[q]});
+            for (int64_t q = A->ptr[i]; q < A->ptr[i + 1]; ++q) row.push_back({inv[(size_t)A->idx[q]], A->val[q]});
             std::sort(row.begin(), row.end(),
                       [](const std::pair<int32_t, double> &x, const std::pair<int32_t, double> &y) {
                           return x.first < y.first;
@@ -269,13 +294,15 @@ cdcs_status host_problem(const cdcs_pattern *pat, const cdcs_constraints *A, con
     P.Aw.assign((size_t)dense_elems, 0.0f);
     if (A->dense) {
         for (int32_t i = 0; i < m; ++i)
-            for (int64_t e = 0; e < nU; ++e)
-                P.Aw[(size_t)(i * P.ld + e)] = (float)(P.wt[(size_t)e] * A->val[(size_t)i * nU + e]);
+            for (int64_t e = 0; e < nU; ++e) {
+                const int64_t ie = inv[(size_t)e];
+                P.Aw[(size_t)(i * P.ld + ie)] = (float)(P.wt[(size_t)ie] * A->val[(size_t)i * nU + e]);
+            }
     } else {
         std::vector<double> row((size_t)nU);
         for (int32_t i = 0; i < m; ++i) {
             std::fill(row.begin(), row.end(), 0.0);
-            for (int64_t q = A->ptr[i]; q < A->ptr[i + 1]; ++q) row[(size_t)A->idx[q]] += A->val[q];
+            for (int64_t q = A->ptr[i]; q < A->ptr[i + 1]; ++q) row[(size_t)inv[(size_t)A->idx[q]]] += A->val[q];
             for (int64_t e = 0; e < nU; ++e) P.Aw[(size_t)(i * P.ld + e)] = (float)(P.wt[(size_t)e] * row[(size_t)e]);
         }
     }
@@ -301,8 +328,8 @@ void inverse_map(const std::vector<int32_t> &gather, const std::vector<int32_t> 
 cdcs_status upload_common(cdcs_handle *h, const std::vector<int32_t> &size, const std::vector<int32_t> &gather,
                           const std::vector<int32_t> &cnt, const std::vector<double> &wt,
                           const std::vector<double> &invD, const std::vector<double> &s2,
-                          const std::vector<double> &c, const std::vector<double> &b, int heavy_above,
-                          hipStream_t s) {
+                          const std::vector<double> &c, const std::vector<double> &b,
+                          const std::vector<int32_t> &perm, int heavy_above, hipStream_t s) {
     Dev &d = h->d;
     const int32_t p = d.p;
     std::vector<int32_t> inv_ptr, inv_slot, heavy;
@@ -324,6 +351,11 @@ cdcs_status upload_common(cdcs_handle *h, const std::vector<int32_t> &size, cons
     CK(upload(h, &d.clq_size, size, s));
     CK(upload(h, &d.clq_off, h->off_host, s));
     CK(upload(h, &d.gather, gather, s));
+    CK(upload(h, &d.perm, perm, s));
+    CK(h->alloc(&d.xi, d.ldU));
+    CK(h->alloc(&d.xtmp, d.ldU));
+    HIP_OK(hipMemsetAsync(d.xi, 0, (size_t)d.ldU * sizeof(double), s));
+    HIP_OK(hipMemsetAsync(d.xtmp, 0, (size_t)d.ldU * sizeof(double), s));
     CK(upload(h, &d.inv_ptr, inv_ptr, s));
     CK(upload(h, &d.inv_slot, inv_slot, s));
     CK(upload(h, &d.heavy, heavy, s));
@@ -440,7 +472,7 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
     pad_invD.resize((size_t)d.ldU, 0.0);
     pad_s2.resize((size_t)d.ldU, 0.0);
     pad_wt.resize((size_t)d.ldU, 0.0);
-    CK(upload_common(h, P.size, P.gather, P.cnt, pad_wt, pad_invD, pad_s2, P.c, P.b, heavy_threshold(), s));
+    CK(upload_common(h, P.size, P.gather, P.cnt, pad_wt, pad_invD, pad_s2, P.c, P.b, P.perm, heavy_threshold(), s));
     CK(h->alloc(&d.spart, 2 * (int64_t)scatter_blocks(d)));
     CK(h->alloc(&d.u, d.ldU));
     HIP_OK(hipMemsetAsync(d.u, 0, (size_t)d.ldU * sizeof(double), s));
@@ -532,7 +564,7 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
     B.nprob = nprob;
     std::vector<int64_t> U_off(1, 0), A_off, F_off;
     std::vector<int32_t> m_off(1, 0), k_off(1, 0), A_ld, einst, rinst, kinst;
-    std::vector<int32_t> size, gather, cnt;
+    std::vector<int32_t> size, gather, cnt, perm;
     std::vector<double> wt, invD, s2, c, b;
     std::vector<float> Aw;
     std::vector<int32_t> sblk, sblk_off(1, 0), syrk_jobs, trtri_jobs, rjobs, ejobs;
@@ -554,6 +586,7 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
             kinst.push_back(q);
         }
         for (int32_t g : P.gather) gather.push_back((int32_t)(u0 + g));
+        for (int32_t e : P.perm) perm.push_back((int32_t)(u0 + e));
         cnt.insert(cnt.end(), P.cnt.begin(), P.cnt.end());
         wt.insert(wt.end(), P.wt.begin(), P.wt.end());
         invD.insert(invD.end(), P.invD.begin(), P.invD.end());
@@ -611,7 +644,7 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
     if (d.nU >= (int64_t)1 << 31 || d.nslots >= (int64_t)1 << 31) return fail(CDCS_E_ARG, "batch too large");
     d.ldU = d.nU;
     d.ldM = round_up(d.m, 4);
-    CK(upload_common(h, size, gather, cnt, wt, invD, s2, c, b, 1 << 30, s));
+    CK(upload_common(h, size, gather, cnt, wt, invD, s2, c, b, perm, 1 << 30, s));
     CK(h->alloc(&d.u, d.nU));
     CK(upload(h, &d.Aw, Aw, s));
     CK(upload(h, &B.U_off, U_off, s));
@@ -1036,14 +1069,16 @@ cdcs_status cdcs_psd_project_vjp(int32_t nb, int32_t smax, const int32_t *sizes,
 
 cdcs_status cdcs_gather(const cdcs_handle *h, const double *x, double *packed, hipStream_t stream) {
     if (!h || !x || !packed) return fail(CDCS_E_ARG, "NULL argument");
-    launch_gather_f64(h->d, x, packed, stream);
+    launch_perm_in(h->d, x, h->d.xtmp, stream);
+    launch_gather_f64(h->d, h->d.xtmp, packed, stream);
     HIP_OK(hipGetLastError());
     return CDCS_OK;
 }
 
 cdcs_status cdcs_scatter(const cdcs_handle *h, const double *packed, double *out, hipStream_t stream) {
     if (!h || !packed || !out) return fail(CDCS_E_ARG, "NULL argument");
-    launch_scatter_f64(h->d, packed, out, stream);
+    launch_scatter_f64(h->d, packed, h->d.xtmp, stream);
+    launch_perm_out(h->d, h->d.xtmp, out, stream);
     HIP_OK(hipGetLastError());
     return CDCS_OK;
 }
@@ -1052,17 +1087,23 @@ cdcs_status cdcs_affine_project(const cdcs_handle *h, const double *r1, const do
                                 hipStream_t stream) {
     if (!h || !r1 || !r2 || !x || !y) return fail(CDCS_E_ARG, "NULL argument");
     const Dev &d = h->d;
-    launch_scale_u(d, r1, x, stream);
-    if (d.batch) launch_baffine(d, r2, 1.0, x, y, nullptr, nullptr, stream);
-    else launch_affine(d, r2, 1.0, x, y, nullptr, stream);
+    launch_perm_in(d, r1, d.xtmp, stream);
+    launch_scale_u(d, d.xtmp, d.xi, stream);
+    if (d.batch) launch_baffine(d, r2, 1.0, d.xi, y, nullptr, nullptr, stream);
+    else launch_affine(d, r2, 1.0, d.xi, y, nullptr, stream);
+    launch_perm_out(d, d.xi, x, stream);
     HIP_OK(hipGetLastError());
     return CDCS_OK;
 }
 
-cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st, const cdcs_options *opts, cdcs_info *info,
+cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st_user, const cdcs_options *opts, cdcs_info *info,
                             hipStream_t stream) {
-    if (!h || !st || !opts) return fail(CDCS_E_ARG, "NULL argument");
-    if (!st->x || !st->y || !st->blk || !st->lam) return fail(CDCS_E_ARG, "state has NULL buffers");
+    if (!h || !st_user || !opts) return fail(CDCS_E_ARG, "NULL argument");
+    if (!st_user->x || !st_user->y || !st_user->blk || !st_user->lam) return fail(CDCS_E_ARG, "state has NULL buffers");
+    // the iteration runs on x in internal entry order
+    cdcs_state st_int = *st_user;
+    st_int.x = h->d.xi;
+    const cdcs_state *st = &st_int;
     const int form = opts->form;
     if (form != CDCS_PRIMAL && form != CDCS_DUAL) return fail(CDCS_E_ARG, "bad form");
     if (form == CDCS_DUAL && !st->v) return fail(CDCS_E_ARG, "dual form needs state.v");
@@ -1090,6 +1131,7 @@ cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st, const cdcs_opt
     // the eigenvector warm start restarts at each solve: a solve is a function
     // of (problem, state, options) only
     launch_identity_blocks(d.clq_size, d.vwoff, d.p, d.vwarm, stream);
+    launch_perm_in(d, st_user->x, d.xi, stream);
     HIP_OK(hipGetLastError());
     auto t0 = std::chrono::steady_clock::now();
     const int K = opts->check_every;
@@ -1124,6 +1166,7 @@ cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st, const cdcs_opt
         launch_check_primal(d, rho, stream);
     }
     launch_objectives(d, st->x, st->y, stream);
+    launch_perm_out(d, d.xi, st_user->x, stream);
     HIP_OK(hipGetLastError());
     HIP_OK(hipMemcpyAsync(d.ctl_host, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
     double obj[2] = {0.0, 0.0};
@@ -1173,13 +1216,19 @@ cdcs_status cdcs_admm_step(cdcs_handle *h, const cdcs_state *st, int32_t form, d
     return cdcs_admm_solve(h, st, &o, nullptr, stream);
 }
 
-cdcs_status cdcs_profile_kernel(cdcs_handle *h, const cdcs_state *st, int32_t form, double rho, int32_t kernel,
-                                int32_t reps, hipStream_t stream) {
-    if (!h || !st || !st->x || !st->y || !st->blk || !st->lam) return fail(CDCS_E_ARG, "NULL argument");
+cdcs_status cdcs_profile_kernel(cdcs_handle *h, const cdcs_state *st_user, int32_t form, double rho,
+                                int32_t kernel, int32_t reps, hipStream_t stream) {
+    if (!h || !st_user || !st_user->x || !st_user->y || !st_user->blk || !st_user->lam)
+        return fail(CDCS_E_ARG, "NULL argument");
     if (form != CDCS_PRIMAL && form != CDCS_DUAL) return fail(CDCS_E_ARG, "bad form");
-    if (form == CDCS_DUAL && !st->v) return fail(CDCS_E_ARG, "dual form needs state.v");
+    if (form == CDCS_DUAL && !st_user->v) return fail(CDCS_E_ARG, "dual form needs state.v");
     if (reps < 1 || !(rho > 0.0)) return fail(CDCS_E_ARG, "need reps >= 1, rho > 0");
     Dev &d = h->d;
+    // x is the handle's copy of the iterate (internal entry order), so that
+    // only the named kernel runs between the caller's events
+    cdcs_state st_int = *st_user;
+    st_int.x = d.xi;
+    const cdcs_state *st = &st_int;
     launch_reset_ctl(d, 1 << 30, 0.0, stream);
     if (d.batch) {
         launch_breset(d, stream);

@@ -136,7 +136,8 @@ struct Dev {
     int64_t ldM = 0;               // row stride of AwT (m rounded up to 4)
     int32_t *clq_size = nullptr;   // [p]
     int64_t *clq_off = nullptr;    // [p+1]
-    int32_t *gather = nullptr;     // [nslots]
+    int32_t *gather = nullptr;     // [nslots] internal entry of each packed slot
+    int32_t *perm = nullptr;       // [nU] pattern position of each internal entry
     int32_t *inv_ptr = nullptr;    // [nU+1]
     int32_t *inv_slot = nullptr;   // [nslots]
     int32_t *heavy = nullptr;      // [nheavy] entries with long inverse lists
@@ -174,6 +175,8 @@ struct Dev {
     float *vwarm = nullptr;        // [sum s_k^2] eigenvectors of the last projection
     // work
     double *u = nullptr;           // [ldU] r1 / D, zero padded
+    double *xi = nullptr;          // [ldU] x in internal entry order (the solver's iterate)
+    double *xtmp = nullptr;        // [ldU] entry-space scratch of the interface calls
     double *t = nullptr;           // [m]
     double *tpart = nullptr;       // [8 * m] split-K partials of A u
     double *y1 = nullptr;          // [m]
@@ -223,6 +226,8 @@ void launch_affine_part(const Dev &d, int part, const double *r2, double r2scale
                         const Ctl *ctl, hipStream_t s);
 // FP64 gather (entries -> packed slots) and scatter-add (packed -> entries).
 void launch_gather_f64(const Dev &d, const double *x, double *packed, hipStream_t s);
+void launch_perm_in(const Dev &d, const double *x_pattern, double *x_internal, hipStream_t s);
+void launch_perm_out(const Dev &d, const double *x_internal, double *x_pattern, hipStream_t s);
 void launch_scatter_f64(const Dev &d, const double *packed, double *out, hipStream_t s);
 void launch_objectives(const Dev &d, const double *x, const double *y, hipStream_t s);
 int objective_partials();

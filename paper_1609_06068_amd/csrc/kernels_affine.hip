@@ -565,6 +565,20 @@ __global__ __launch_bounds__(kNT) void k_objectives_finish(const double *__restr
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kNT - 1) / kNT); }
 
+// Entry-space vectors cross the interface in pattern order; inside they are
+// kept in the internal order (perm[e]: pattern position of internal entry e).
+__global__ __launch_bounds__(kNT) void k_perm_in(const double *__restrict__ xp, const int32_t *__restrict__ perm,
+                                                 double *__restrict__ xi, int64_t nU) {
+    const int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (e < nU) xi[e] = xp[perm[e]];
+}
+
+__global__ __launch_bounds__(kNT) void k_perm_out(const double *__restrict__ xi, const int32_t *__restrict__ perm,
+                                                  double *__restrict__ xp, int64_t nU) {
+    const int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (e < nU) xp[perm[e]] = xi[e];
+}
+
 }  // namespace
 
 int scatter_light_blocks(const Dev &d) { return (int)blocks_for(d.nU); }
@@ -674,6 +688,16 @@ void launch_affine(const Dev &d, const double *r2, double r2scale, double *x, do
     launch_affine_part(d, 3, r2, r2scale, x, y, ctl, s);
     launch_affine_part(d, 1, r2, r2scale, x, y, ctl, s);
     launch_affine_part(d, 2, r2, r2scale, x, y, ctl, s);
+}
+
+void launch_perm_in(const Dev &d, const double *x_pattern, double *x_internal, hipStream_t s) {
+    hipLaunchKernelGGL(k_perm_in, dim3(blocks_for(d.nU)), dim3(kNT), 0, s, x_pattern, (const int32_t *)d.perm,
+                       x_internal, d.nU);
+}
+
+void launch_perm_out(const Dev &d, const double *x_internal, double *x_pattern, hipStream_t s) {
+    hipLaunchKernelGGL(k_perm_out, dim3(blocks_for(d.nU)), dim3(kNT), 0, s, x_internal, (const int32_t *)d.perm,
+                       x_pattern, d.nU);
 }
 
 void launch_gather_f64(const Dev &d, const double *x, double *packed, hipStream_t s) {
