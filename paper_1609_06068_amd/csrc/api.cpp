@@ -567,7 +567,9 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
     std::vector<int32_t> size, gather, cnt, perm;
     std::vector<double> wt, invD, s2, c, b;
     std::vector<float> Aw;
-    std::vector<int32_t> sblk, sblk_off(1, 0), syrk_jobs, trtri_jobs, rjobs, ejobs;
+    std::vector<int32_t> sblk, sblk_off(1, 0), syrk_jobs, trtri_jobs, rjobs, ejobs, nch;
+    std::vector<int64_t> p_off;
+    int64_t ptot = 0;
     h->off_host.assign(1, 0);
     int64_t Atot = 0, Ftot = 0;
     d.smax = 0;
@@ -621,12 +623,17 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
             trtri_jobs.push_back(q);
             trtri_jobs.push_back(j);
         }
-        for (int32_t r = 0; r < P.m; r += 4) {
-            rjobs.push_back(q);
-            rjobs.push_back(m_off.back() + r);
-            rjobs.push_back(std::min<int32_t>(4, P.m - r));
-            rjobs.push_back(0);
-        }
+        const int32_t nc = (int32_t)((P.nU + kBatchAuChunk - 1) / kBatchAuChunk);
+        nch.push_back(nc);
+        p_off.push_back(ptot);
+        if (nc > 1) ptot += (int64_t)P.m * nc;
+        for (int32_t r = 0; r < P.m; r += 4)
+            for (int32_t c = 0; c < nc; ++c) {
+                rjobs.push_back(q);
+                rjobs.push_back(m_off.back() + r);
+                rjobs.push_back(std::min<int32_t>(4, P.m - r));
+                rjobs.push_back(c);
+            }
         for (int64_t e0 = 0; e0 < P.nU; e0 += 1024) {
             ejobs.push_back(q);
             ejobs.push_back((int32_t)e0);
@@ -667,7 +674,9 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
         for (size_t t = 0; t < order.size(); ++t) order[t] = (int32_t)t;
         auto rwork = [&](int32_t t) {
             const int32_t q = rjobs[(size_t)t * 4];
-            return (U_off[(size_t)q + 1] - U_off[(size_t)q]) * rjobs[(size_t)t * 4 + 2];
+            const int64_t nUq = U_off[(size_t)q + 1] - U_off[(size_t)q];
+            const int64_t c0 = (int64_t)rjobs[(size_t)t * 4 + 3] * kBatchAuChunk;
+            return std::min<int64_t>(kBatchAuChunk, nUq - c0) * rjobs[(size_t)t * 4 + 2];
         };
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return rwork(a) > rwork(b); });
         std::vector<int32_t> sorted;
@@ -688,6 +697,10 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
     }
     CK(upload(h, &B.rjobs, rjobs, s));
     CK(upload(h, &B.ejobs, ejobs, s));
+    CK(upload(h, &B.nch, nch, s));
+    CK(upload(h, &B.p_off, p_off, s));
+    B.split = ptot > 0;
+    CK(h->alloc(&B.tpart, std::max<int64_t>(ptot, 1)));
     B.nrjobs = (int32_t)(rjobs.size() / 4);
     B.nejobs = (int32_t)(ejobs.size() / 2);
     B.nsblk = (int32_t)(sblk.size() / 4);

@@ -96,6 +96,10 @@ void launch_tune_blocks(const int32_t *size, const int64_t *off, int p, float *W
 void launch_identity_blocks(const int32_t *size, const int64_t *voff, int p, float *V, hipStream_t s);
 
 // Many independent SDPs in one handle: index ranges and per-instance state.
+// Column chunk (entries) of one job of the batched A u product: long rows
+// are split so that jobs are of similar size.
+constexpr int kBatchAuChunk = 4096;
+
 struct Batch {
     int32_t nprob = 0;
     int64_t *U_off = nullptr;      // [nprob+1] entry ranges
@@ -113,7 +117,11 @@ struct Batch {
     int32_t *syrk_jobs = nullptr;  // [nsyrk * 4] (q, I, J, 0) tiles of M_q
     int32_t nsyrk = 0;
     int32_t *trtri_jobs = nullptr; // [m * 2] (q, j)
-    int32_t *rjobs = nullptr;      // [nrjobs * 4] (q, first row, rows <= 4, 0) of the A u product
+    int32_t *rjobs = nullptr;      // [nrjobs * 4] (q, first row, rows <= 4, column chunk) of the A u product
+    int32_t *nch = nullptr;        // [nprob] column chunks of kBatchAuChunk entries per row of A_q
+    int64_t *p_off = nullptr;      // [nprob] offset of instance q's per-chunk partial sums in tpart
+    double *tpart = nullptr;       // [sum over split instances of m_q * nch_q] partial sums of A u
+    int32_t split = 0;             // some instance has rows of more than one chunk
     int32_t nrjobs = 0;
     int32_t *ejobs = nullptr;      // [nejobs * 2] (q, first entry in q) of 1024-entry A^T y blocks
     int32_t nejobs = 0;

@@ -148,18 +148,22 @@ __global__ void k_bcheck_finish(const int32_t *nrunning, Ctl *ctl) {
     else ctl->iter = ctl->iter + 1;
 }
 
-// t_r = A_q(r) . (w u)_q - r2scale r2_r, one wave per global constraint row.
 // t = A_q (w u_q) - r2scale r2 for up to 8 consecutive rows of one instance
-// per wave (job (q, first row, rows)): each u element loaded once serves all
-// the wave's rows.  Lanes stride the row in float4 groups; FP64 accumulation.
+// and one column chunk of kBatchAuChunk entries per wave (job (q, first row,
+// rows, chunk)): each u element loaded once serves all the wave's rows.  Lanes
+// stride the chunk in float4 groups; FP64 accumulation.  An instance whose
+// rows span several chunks writes per-chunk partial sums, which
+// k_bAu_reduce adds in chunk order (deterministic).
 constexpr int kRowsPerWave = 8;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kMaxBatchRows = 256;  // constraints per instance (checked at setup)
+static_assert(kBatchAuChunk % 256 == 0, "chunks hold whole float4 groups of a wave");
 
 __global__ __launch_bounds__(kNT) void k_bgemv_Au(const float *__restrict__ A, const int64_t *__restrict__ A_off,
                                                   const int32_t *__restrict__ A_ld, const int4 *__restrict__ rjobs,
                                                   int njobs, const int32_t *__restrict__ m_off,
-                                                  const int64_t *__restrict__ U_off,
+                                                  const int64_t *__restrict__ U_off, const int32_t *__restrict__ nch,
+                                                  const int64_t *__restrict__ p_off, double *__restrict__ tpart,
                                                   const int32_t *__restrict__ istop, const double *__restrict__ u,
                                                   const double *__restrict__ r2, double r2scale,
                                                   double *__restrict__ t, const Ctl *ctl) {
@@ -167,18 +171,19 @@ __global__ __launch_bounds__(kNT) void k_bgemv_Au(const float *__restrict__ A, c
     const int lane = threadIdx.x & 63;
     const int jb = blockIdx.x * (kNT / 64) + (threadIdx.x >> 6);
     if (jb >= njobs) return;
-    const int4 job = rjobs[jb];  // (q, first row (global), rows, 0)
-    const int q = job.x, r0 = job.y, nr = job.z;
+    const int4 job = rjobs[jb];  // (q, first row (global), rows, chunk)
+    const int q = job.x, r0 = job.y, nr = job.z, ch = job.w;
     if (istop != nullptr && istop[q]) return;
     const int64_t u0 = U_off[q];
     const int nU = (int)(U_off[q + 1] - u0);
     const int ld = A_ld[q];
     const float *base = A + A_off[q] + (int64_t)(r0 - m_off[q]) * ld;
     const double *uq = u + u0;
+    const int jhi = min(nU, (ch + 1) * kBatchAuChunk);
     double acc[kRowsPerWave];
 #pragma unroll
     for (int v = 0; v < kRowsPerWave; ++v) acc[v] = 0.0;
-    for (int j = lane * 4; j < nU; j += 256) {
+    for (int j = ch * kBatchAuChunk + lane * 4; j < jhi; j += 256) {
         double uj[4];  // (u_q may start at an odd entry: scalar loads)
 #pragma unroll
         for (int v = 0; v < 4; ++v) uj[v] = (j + v < nU) ? uq[j + v] : 0.0;
@@ -191,11 +196,36 @@ __global__ __launch_bounds__(kNT) void k_bgemv_Au(const float *__restrict__ A, c
             }
         }
     }
+    const int nc = nch[q];
 #pragma unroll
     for (int v = 0; v < kRowsPerWave; ++v) {
         const double sv = wave_sum_d(acc[v]);
-        if (lane == 0 && v < nr) t[r0 + v] = sv - r2scale * r2[r0 + v];
+        if (lane == 0 && v < nr) {
+            if (nc == 1) t[r0 + v] = sv - r2scale * r2[r0 + v];
+            else tpart[p_off[q] + (int64_t)(r0 + v - m_off[q]) * nc + ch] = sv;
+        }
     }
+}
+
+// t_r = sum of row r's chunk partial sums (in chunk order) - r2scale r2_r, for
+// the rows of instances split into several chunks.
+__global__ __launch_bounds__(kNT) void k_bAu_reduce(const int32_t *__restrict__ rinst,
+                                                    const int32_t *__restrict__ m_off,
+                                                    const int32_t *__restrict__ nch,
+                                                    const int64_t *__restrict__ p_off,
+                                                    const double *__restrict__ tpart,
+                                                    const int32_t *__restrict__ istop, const double *__restrict__ r2,
+                                                    double r2scale, double *__restrict__ t, int mtot, const Ctl *ctl) {
+    if (ctl != nullptr && ctl->stop) return;
+    const int r = blockIdx.x * kNT + threadIdx.x;
+    if (r >= mtot) return;
+    const int q = rinst[r];
+    const int nc = nch[q];
+    if (nc == 1 || (istop != nullptr && istop[q])) return;
+    const double *pr = tpart + p_off[q] + (int64_t)(r - m_off[q]) * nc;
+    double sacc = 0.0;
+    for (int c = 0; c < nc; ++c) sacc += pr[c];
+    t[r] = sacc - r2scale * r2[r];
 }
 
 // One triangular product per instance: out_q = T_q in_q, T_q lower (upper = 0)
@@ -431,8 +461,12 @@ void launch_baffine(const Dev &d, const double *r2, double r2scale, double *x, d
     const Batch &B = *d.batch;
     hipLaunchKernelGGL(k_bgemv_Au, dim3(waves_blocks(B.nrjobs)), dim3(kNT), 0, s, (const float *)d.Aw,
                        (const int64_t *)B.A_off, (const int32_t *)B.A_ld, (const int4 *)B.rjobs, B.nrjobs,
-                       (const int32_t *)B.m_off, (const int64_t *)B.U_off, istop, (const double *)d.u, r2, r2scale,
-                       d.t, ctl);
+                       (const int32_t *)B.m_off, (const int64_t *)B.U_off, (const int32_t *)B.nch,
+                       (const int64_t *)B.p_off, B.tpart, istop, (const double *)d.u, r2, r2scale, d.t, ctl);
+    if (B.split)
+        hipLaunchKernelGGL(k_bAu_reduce, dim3((d.m + kNT - 1) / kNT), dim3(kNT), 0, s, (const int32_t *)B.rinst,
+                           (const int32_t *)B.m_off, (const int32_t *)B.nch, (const int64_t *)B.p_off,
+                           (const double *)B.tpart, istop, r2, r2scale, d.t, d.m, ctl);
     hipLaunchKernelGGL(k_btrmv, dim3(waves_blocks(d.m)), dim3(kNT), 0, s, (const double *)d.Linv,
                        (const int64_t *)B.F_off, (const int32_t *)B.rinst, (const int32_t *)B.m_off, istop, 0,
                        (const double *)d.t, d.y1, d.m, ctl);
