@@ -465,7 +465,7 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
     d.smax = P.smax;
     d.nslots = P.nslots;
     d.ldU = P.ld;
-    d.ldM = round_up(P.m, 4);
+    d.ldM = round_up(P.m, 32);  // rows of A^T start on 128-byte lines
     h->off_host = P.off;
     // u is padded to ldU (the A u kernel reads whole 4-wide groups)
     std::vector<double> pad_invD(P.invD), pad_s2(P.s2), pad_wt(P.wt);

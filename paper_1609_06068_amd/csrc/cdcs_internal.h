@@ -141,7 +141,7 @@ struct Dev {
     int32_t n = 0, m = 0, p = 0, smax = 0;
     int64_t nU = 0, nslots = 0;
     int64_t ldU = 0;               // row stride of Aw (nU rounded up to 64)
-    int64_t ldM = 0;               // row stride of AwT (m rounded up to 4)
+    int64_t ldM = 0;               // row stride of AwT (m rounded up to 32; 4 on batch handles)
     int32_t *clq_size = nullptr;   // [p]
     int64_t *clq_off = nullptr;    // [p+1]
     int32_t *gather = nullptr;     // [nslots] internal entry of each packed slot
