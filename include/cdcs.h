@@ -357,7 +357,7 @@ cdcs_status cdcs_get_tuning(const cdcs_handle *h, cdcs_tuning *out);
 /*
  * Override the tuned plan: persistent = 1 with threads 256 or 512, or
  * persistent = 0 with threads 64, 256 or 512 for every bucket that has that
- * size built (64: buckets 16 and 32; 512: buckets 48 and up; others keep 256), or 0
+ * size built (64: buckets 16 and 32 only, the others keep 256; 256 and 512: every bucket), or 0
  * to keep the tuned per-bucket sizes.
  * Synchronizes the device and drops captured graphs.  Errors: CDCS_E_ARG,
  * CDCS_E_DEVICE.

@@ -958,9 +958,8 @@ int proj_bucket(int smax) {
 }
 
 bool proj_threads_ok(int S, int nthreads) {
-    if (nthreads == 256) return true;
+    if (nthreads == 256 || nthreads == 512) return true;
     if (nthreads == 64) return S <= 32;
-    if (nthreads == 512) return S >= 48;
     return false;
 }
 
@@ -969,8 +968,8 @@ void launch_project(const ProjArgs &a, int smax, int nthreads, hipStream_t s) {
     const int S = proj_bucket(smax);
     const int nt = proj_threads_ok(S, nthreads) ? nthreads : 256;
     switch (S) {
-    case 16: nt == 64 ? launch_t<16, 64>(a, s) : launch_t<16, 256>(a, s); break;
-    case 32: nt == 64 ? launch_t<32, 64>(a, s) : launch_t<32, 256>(a, s); break;
+    case 16: nt == 64 ? launch_t<16, 64>(a, s) : nt == 512 ? launch_t<16, 512>(a, s) : launch_t<16, 256>(a, s); break;
+    case 32: nt == 64 ? launch_t<32, 64>(a, s) : nt == 512 ? launch_t<32, 512>(a, s) : launch_t<32, 256>(a, s); break;
     case 48: nt == 512 ? launch_t<48, 512>(a, s) : launch_t<48, 256>(a, s); break;
     case 64: nt == 512 ? launch_t<64, 512>(a, s) : launch_t<64, 256>(a, s); break;
     case 80: nt == 512 ? launch_t<80, 512>(a, s) : launch_t<80, 256>(a, s); break;
