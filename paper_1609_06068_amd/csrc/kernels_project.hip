@@ -6,14 +6,15 @@
 // One workgroup per clique.  Every clique of a size bucket is padded to the
 // bucket size S with zero rows and columns (a zero pair never rotates), so all
 // loops have compile-time trip counts.  The clique matrix (FP32) lives in LDS
-// and is diagonalised by two-sided Jacobi with the round-robin (circle)
-// ordering: the disjoint pairs of a step are rotated together.  During the
-// sweeps A is stored by position, as lower 2x2 pair blocks in four element
-// planes, so a thread reads its blocks with unit-stride LDS accesses and
-// writes the rotated elements straight to where the ring move takes them
-// (two buffers, swapped every step); V stays in registers.  A step is two
-// phases separated by barriers: one wave computes the rotations, then every
-// thread applies them to its fixed blocks of A and to its rows of V.  Sweeps
+// and is diagonalised by two-sided Jacobi in the odd-even ordering: the
+// disjoint pairs of a step are rotated together.  During the sweeps A is
+// stored by position, as lower 2x2 pair blocks in four element planes, so a
+// thread reads its blocks with unit-stride LDS accesses and writes the rotated
+// elements straight to where the step's exchange moves them (two buffers,
+// swapped every step); V stays in registers.  A step is two phases separated
+// by barriers: one wave computes the rotations (and writes the pairs' new
+// diagonal blocks), then every thread applies them to its fixed off-diagonal
+// blocks of A and to its rows of V.  Sweeps
 // stop when off(A) <= tau ||W||_F: the projection onto the PSD cone is
 // 1-Lipschitz in the Frobenius norm, so rebuilding from the diagonal of a
 // matrix whose off-diagonal part E remains moves P by at most ||E||_F.  Inside
@@ -321,7 +322,7 @@ struct ProjSmall {
     float4 cst[64];              // rotations of one step: (c, s, -, -) of pair t
     float lam[96], lp[96];       // eigenvalues, clamped eigenvalues
     float redf[8];
-    double redd[8];
+    double redd[24];             // three FP64 partial sums per wave
     int zero;                    // 0; read as volatile (see project_one)
 };
 
@@ -705,13 +706,29 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
         }
     }
     if (a.mode == PROJ_PRIMAL) {
-        p0 = block_sum<NT>(p0, sm.redd);
-        p1 = block_sum<NT>(p1, sm.redd);
-        p2 = block_sum<NT>(p2, sm.redd);
+        // the three residual partial sums in one workgroup reduction (waves
+        // added in order, as block_sum does); only thread 0 reads the result
+        p0 = wave_sum(p0);
+        p1 = wave_sum(p1);
+        p2 = wave_sum(p2);
+        if ((tid & 63) == 0) {
+            const int w = tid >> 6;
+            sm.redd[3 * w + 0] = p0;
+            sm.redd[3 * w + 1] = p1;
+            sm.redd[3 * w + 2] = p2;
+        }
+        __syncthreads();
         if (tid == 0) {
-            a.cpart[4 * (int64_t)id + 0] = p0;
-            a.cpart[4 * (int64_t)id + 1] = p1;
-            a.cpart[4 * (int64_t)id + 2] = p2;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int i = 0; i < NT / 64; ++i) {
+                s0 += sm.redd[3 * i + 0];
+                s1 += sm.redd[3 * i + 1];
+                s2 += sm.redd[3 * i + 2];
+            }
+            a.cpart[4 * (int64_t)id + 0] = s0;
+            a.cpart[4 * (int64_t)id + 1] = s1;
+            a.cpart[4 * (int64_t)id + 2] = s2;
         }
     }
     if (a.mode == PROJ_STANDALONE) {
