@@ -485,17 +485,27 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
             dgo[T][2] = move_to(T, t, t, 3);
         }
     }
-    // V in registers: lane i of a wave holds, for its rows (wave w: rows
-    // w, w + NW, ...), the columns at positions 2i ("top") and 2i+1.
+    // V in registers: the lane for pair i holds, for its rows (wave w: rows
+    // w, w + NW, ...), the columns at positions 2i ("top") and 2i+1.  Buckets
+    // up to 48 use at most 25 lanes per row, so a register carries two rows:
+    // lanes 0-31 and 32-63 (lane 31 is never a pair's lane, so nothing a lane
+    // shift carries across the halves reaches one; lane 32 is the ghost pair
+    // of its row, which ignores what it receives).
+    constexpr bool PACK = S <= 48;
+    static_assert(!PACK || HMAX + 1 < 32, "two rows per register need a spare lane between them");
+    constexpr int RV = PACK ? (RPW + 1) / 2 : RPW;  // V registers per wave
     const int lane = tid & 63, wv = uniform(tid >> 6);
-    const bool vlane = lane < HK;
-    float vt[RPW], vb[RPW];
+    const int pi = PACK ? (lane & 31) : lane;  // pair of this lane
+    const int half = PACK ? (lane >> 5) : 0;
+    auto vrow = [&](int j) { return wv + (PACK ? 2 * j + half : j) * NW; };
+    const bool vlane = pi < HK;
+    float vt[RV], vb[RV];
 #pragma unroll
-    for (int j = 0; j < RPW; ++j) {
-        const int row = wv + j * NW;
+    for (int j = 0; j < RV; ++j) {
+        const int row = vrow(j);
         const bool ok = vlane && row < K;
-        vt[j] = ok ? sV[row * LD + 2 * lane] : 0.0f;
-        vb[j] = ok ? sV[row * LD + 2 * lane + 1] : 0.0f;
+        vt[j] = ok ? sV[row * LD + 2 * pi] : 0.0f;
+        vb[j] = ok ? sV[row * LD + 2 * pi + 1] : 0.0f;
     }
     __syncthreads();  // sV is free: it becomes pair-block buffer 0
     char *const B0 = reinterpret_cast<char *>(sV);
@@ -571,11 +581,11 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
         // steps: lane i pairs position 2i-1 (bottom of lane i-1) with its top;
         // the new position 2i-1 goes back to lane i-1.  Lanes past the pairs
         // rotate by the identity and keep zeros.
-        const bool pl = lane < npair;
-        const float4 csl = sm.cst[pl ? lane : 0];
+        const bool pl = pi < npair;
+        const float4 csl = sm.cst[pl ? pi : 0];
         const float c = pl ? csl.x : 1.0f, sg = pl ? csl.y : 0.0f;
 #pragma unroll
-        for (int j = 0; j < RPW; ++j) {
+        for (int j = 0; j < RV; ++j) {
             if (T == 0) {
                 const float t0 = vt[j];
                 vt[j] = sg * t0 + c * vb[j];
@@ -643,10 +653,10 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
         if (i >= K || j >= K) sV[i * LD + j] = (i == j) ? 1.0f : 0.0f;
     }
 #pragma unroll
-    for (int j = 0; j < RPW; ++j) {
-        const int row = wv + j * NW;
+    for (int j = 0; j < RV; ++j) {
+        const int row = vrow(j);
         if (vlane && row < K) {
-            const int c0 = rev ? K - 1 - 2 * lane : 2 * lane, c1 = rev ? K - 2 - 2 * lane : 2 * lane + 1;
+            const int c0 = rev ? K - 1 - 2 * pi : 2 * pi, c1 = rev ? K - 2 - 2 * pi : 2 * pi + 1;
             sV[row * LD + c0] = vt[j];
             sV[row * LD + c1] = vb[j];
         }
