@@ -597,10 +597,17 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
         b.insert(b.end(), P.b.begin(), P.b.end());
         for (int64_t e = 0; e < P.nU; ++e) einst.push_back(q);
         for (int32_t i = 0; i < P.m; ++i) rinst.push_back(q);
+        // rows of A_q start on 128-byte lines (leading dimension a multiple of
+        // 32 floats), so the column blocks of the A^T y product touch no
+        // straddled line
+        const int64_t ldq = round_up(P.nU, 32);
         A_off.push_back(Atot);
-        A_ld.push_back((int32_t)P.ld);
-        Aw.insert(Aw.end(), P.Aw.begin(), P.Aw.end());
-        Atot += (int64_t)P.Aw.size();
+        A_ld.push_back((int32_t)ldq);
+        Aw.resize((size_t)(Atot + P.m * ldq), 0.0f);
+        for (int32_t i = 0; i < P.m; ++i)
+            std::copy(P.Aw.begin() + (size_t)i * P.ld, P.Aw.begin() + (size_t)i * P.ld + P.nU,
+                      Aw.begin() + (size_t)(Atot + i * ldq));
+        Atot += P.m * ldq;
         F_off.push_back(Ftot);
         Ftot += (int64_t)P.m * P.m;
         // scatter blocks of <= 256 entries inside the instance
@@ -627,8 +634,9 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
         nch.push_back(nc);
         p_off.push_back(ptot);
         if (nc > 1) ptot += (int64_t)P.m * nc;
-        for (int32_t r = 0; r < P.m; r += 4)
-            for (int32_t c = 0; c < nc; ++c) {
+        // chunk-major: the row groups that share one u chunk are consecutive
+        for (int32_t c = 0; c < nc; ++c)
+            for (int32_t r = 0; r < P.m; r += 4) {
                 rjobs.push_back(q);
                 rjobs.push_back(m_off.back() + r);
                 rjobs.push_back(std::min<int32_t>(4, P.m - r));
@@ -667,22 +675,40 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
     CK(upload(h, &B.sblk_off, sblk_off, s));
     CK(upload(h, &B.syrk_jobs, syrk_jobs, s));
     CK(upload(h, &B.trtri_jobs, trtri_jobs, s));
-    // largest jobs first (rows of the longest instances, blocks of the instances
-    // with the most constraints), so no long job starts last
+    // A u jobs by XCD: workgroups are handed to the 8 XCDs round robin
+    // (workgroup b to XCD b mod 8), each with its own L2.  The job list (in
+    // instance, chunk, row-group order) is cut into 8 contiguous segments of
+    // equal work and workgroup b takes the next 4 jobs of segment b mod 8, so
+    // the waves that share a u chunk run on one XCD, mostly on one CU.  Unused
+    // slots hold rows = 0.  The order only affects speed: every row's chunk
+    // partials are summed in chunk order.
     {
-        std::vector<int32_t> order((size_t)(rjobs.size() / 4));
-        for (size_t t = 0; t < order.size(); ++t) order[t] = (int32_t)t;
-        auto rwork = [&](int32_t t) {
-            const int32_t q = rjobs[(size_t)t * 4];
+        const size_t nj = rjobs.size() / 4;
+        std::vector<int64_t> wsum(nj + 1, 0);
+        for (size_t t = 0; t < nj; ++t) {
+            const int32_t q = rjobs[t * 4];
             const int64_t nUq = U_off[(size_t)q + 1] - U_off[(size_t)q];
-            const int64_t c0 = (int64_t)rjobs[(size_t)t * 4 + 3] * kBatchAuChunk;
-            return std::min<int64_t>(kBatchAuChunk, nUq - c0) * rjobs[(size_t)t * 4 + 2];
-        };
-        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return rwork(a) > rwork(b); });
-        std::vector<int32_t> sorted;
-        sorted.reserve(rjobs.size());
-        for (int32_t t : order) sorted.insert(sorted.end(), rjobs.begin() + (size_t)t * 4, rjobs.begin() + (size_t)t * 4 + 4);
-        rjobs.swap(sorted);
+            const int64_t c0 = (int64_t)rjobs[t * 4 + 3] * kBatchAuChunk;
+            wsum[t + 1] = wsum[t] + std::min<int64_t>(kBatchAuChunk, nUq - c0) * rjobs[t * 4 + 2];
+        }
+        size_t bnd[kXcds + 1];
+        for (int x = 0; x <= kXcds; ++x)
+            bnd[x] = (size_t)(std::lower_bound(wsum.begin(), wsum.end(), wsum[nj] * x / kXcds) - wsum.begin());
+        bnd[kXcds] = nj;
+        size_t wg = 0;
+        for (int x = 0; x < kXcds; ++x) wg = std::max(wg, (bnd[x + 1] - bnd[x] + 3) / 4);
+        std::vector<int32_t> slots(wg * kXcds * 4 * 4, 0);
+        for (int x = 0; x < kXcds; ++x)
+            for (size_t k = 0; k < bnd[x + 1] - bnd[x]; ++k) {
+                const size_t slot = ((k / 4) * kXcds + (size_t)x) * 4 + k % 4;
+                std::copy(rjobs.begin() + (bnd[x] + k) * 4, rjobs.begin() + (bnd[x] + k) * 4 + 4,
+                          slots.begin() + slot * 4);
+            }
+        rjobs.swap(slots);
+    }
+    // A^T y blocks of the instances with the most constraints first, so no long
+    // job starts last
+    {
         std::vector<int32_t> eorder((size_t)(ejobs.size() / 2));
         for (size_t t = 0; t < eorder.size(); ++t) eorder[t] = (int32_t)t;
         auto ework = [&](int32_t t) {

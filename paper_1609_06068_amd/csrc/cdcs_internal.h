@@ -99,6 +99,7 @@ void launch_identity_blocks(const int32_t *size, const int64_t *voff, int p, flo
 // Column chunk (entries) of one job of the batched A u product: long rows
 // are split so that jobs are of similar size.
 constexpr int kBatchAuChunk = 4096;
+constexpr int kXcds = 8;  // XCDs of the MI355X (workgroups are dispatched to them round robin)
 
 struct Batch {
     int32_t nprob = 0;
@@ -117,7 +118,7 @@ struct Batch {
     int32_t *syrk_jobs = nullptr;  // [nsyrk * 4] (q, I, J, 0) tiles of M_q
     int32_t nsyrk = 0;
     int32_t *trtri_jobs = nullptr; // [m * 2] (q, j)
-    int32_t *rjobs = nullptr;      // [nrjobs * 4] (q, first row, rows <= 4, column chunk) of the A u product
+    int32_t *rjobs = nullptr;      // [nrjobs * 4] (q, first row, rows <= 4, column chunk) of the A u product, by XCD; rows 0 = unused slot
     int32_t *nch = nullptr;        // [nprob] column chunks of kBatchAuChunk entries per row of A_q
     int64_t *p_off = nullptr;      // [nprob] offset of instance q's per-chunk partial sums in tpart
     double *tpart = nullptr;       // [sum over split instances of m_q * nch_q] partial sums of A u

@@ -153,7 +153,8 @@ __global__ void k_bcheck_finish(const int32_t *nrunning, Ctl *ctl) {
 // rows, chunk)): each u element loaded once serves all the wave's rows.  Lanes
 // stride the chunk in float4 groups; FP64 accumulation.  An instance whose
 // rows span several chunks writes per-chunk partial sums, which
-// k_bAu_reduce adds in chunk order (deterministic).
+// k_bAu_reduce adds in chunk order (deterministic).  A job with rows = 0 is an
+// unused slot of the per-XCD job layout.
 constexpr int kRowsPerWave = 8;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kMaxBatchRows = 256;  // constraints per instance (checked at setup)
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(kNT) void k_bgemv_Au(const float *__restrict__ A, c
     if (jb >= njobs) return;
     const int4 job = rjobs[jb];  // (q, first row (global), rows, chunk)
     const int q = job.x, r0 = job.y, nr = job.z, ch = job.w;
-    if (istop != nullptr && istop[q]) return;
+    if (nr == 0 || (istop != nullptr && istop[q])) return;
     const int64_t u0 = U_off[q];
     const int nU = (int)(U_off[q + 1] - u0);
     const int ld = A_ld[q];
