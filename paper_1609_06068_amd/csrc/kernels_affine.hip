@@ -447,27 +447,27 @@ __global__ __launch_bounds__(kNT) void k_reduce_t(const double *__restrict__ tpa
 }
 
 // Triangular product out = T vin over the row range [lo, hi) of each row:
-// lower (T = L^-1): [0, i]; upper (T = L^-T): [i, m).  One wave per row.
+// lower (T = L^-1): [0, i]; upper (T = L^-T): [i, m).  One workgroup per row,
+// its elements spread over all kNT threads (coalesced), so every wave waits on
+// only a few loads and enough of them are in flight to keep HBM busy; rows are
+// dispatched longest first.  Fixed-order block sum.
 __global__ __launch_bounds__(kNT) void k_trmv(const double *__restrict__ T, int m, int upper,
                                               const double *__restrict__ vin, double *__restrict__ vout,
                                               const Ctl *ctl) {
+    __shared__ double red[kNT / 64];
     if (ctl != nullptr && ctl->stop) return;
-    const int lane = threadIdx.x & 63;
-    const int row = blockIdx.x * (kNT / 64) + (threadIdx.x >> 6);
-    if (row >= m) return;
+    const int row = upper ? (int)blockIdx.x : m - 1 - (int)blockIdx.x;
     const int lo = upper ? row : 0, hi = upper ? m : row + 1;
     const double *tr = T + (int64_t)row * m;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int j = lo + lane;
-    for (; j + 192 < hi; j += 256) {
+    double a0 = 0.0, a1 = 0.0;
+    int j = lo + (int)threadIdx.x;
+    for (; j + kNT < hi; j += 2 * kNT) {
         a0 += tr[j] * vin[j];
-        a1 += tr[j + 64] * vin[j + 64];
-        a2 += tr[j + 128] * vin[j + 128];
-        a3 += tr[j + 192] * vin[j + 192];
+        a1 += tr[j + kNT] * vin[j + kNT];
     }
-    for (; j < hi; j += 64) a0 += tr[j] * vin[j];
-    const double acc = wave_sum_d((a0 + a1) + (a2 + a3));
-    if (lane == 0) vout[row] = acc;
+    if (j < hi) a0 += tr[j] * vin[j];
+    const double acc = block_sum_d(a0 + a1, red);
+    if (threadIdx.x == 0) vout[row] = acc;
 }
 
 // Sparse triangular product out = T vin with T in CSR (sparse inverse
@@ -670,10 +670,9 @@ void launch_affine_part(const Dev &d, int part, const double *r2, double r2scale
         hipLaunchKernelGGL(k_csr_mv, dim3(tb), dim3(kNT), 0, s, (const int32_t *)d.lt_ptr, (const int32_t *)d.lt_col,
                            (const double *)d.lt_val, (const double *)d.y1, y, d.m, ctl);
     } else if (part == 1) {
-        const unsigned tb = (unsigned)((d.m + kNT / 64 - 1) / (kNT / 64));
-        hipLaunchKernelGGL(k_trmv, dim3(tb), dim3(kNT), 0, s, (const double *)d.Linv, d.m, 0, (const double *)d.t,
+        hipLaunchKernelGGL(k_trmv, dim3(d.m), dim3(kNT), 0, s, (const double *)d.Linv, d.m, 0, (const double *)d.t,
                            d.y1, ctl);
-        hipLaunchKernelGGL(k_trmv, dim3(tb), dim3(kNT), 0, s, (const double *)d.LinvT, d.m, 1, (const double *)d.y1,
+        hipLaunchKernelGGL(k_trmv, dim3(d.m), dim3(kNT), 0, s, (const double *)d.LinvT, d.m, 1, (const double *)d.y1,
                            y, ctl);
     } else {
         const unsigned gb = (unsigned)((d.nU + kAtyRows - 1) / kAtyRows);
