@@ -12,7 +12,10 @@ projection with multiplier epilogue -> residuals), replayed from captured
 HIP graphs of 50 iterations.  The timed region runs exactly --steps
 iterations with the early exit disabled, on inputs already resident in HBM.
 A separate cold-start solve reports the iterations needed for
-max(eps_p, eps_d) <= 1e-4.
+max(eps_p, eps_d) <= 1e-4.  Per-kernel durations (and the roofline figure)
+are averages over the timed iterations themselves: they are run again from a
+copy of their starting state with eager launches and HIP events around every
+kernel, and the replay must end on the timed run's iterate bit for bit.
 
 Other workloads (each prints its own JSON line; not part of the default run):
   c3  uneven cliques: clique tree of 3000 cliques of 4..96 vertices with
@@ -101,22 +104,22 @@ def projection_model_flops(sizes):
     return float(np.sum(10.0 * k ** 3))
 
 
-def kernel_times(torch, sol, state, form, rho, reps):
-    """Average duration (ms) of each kernel of the iteration: `reps` launches
-    captured in one graph (the solve's launch mode), replayed between events."""
-    from paper_1609_06068_amd import cdcs
-    names = {cdcs.K_GEMV_AU: "gemv_Au", cdcs.K_GEMV_ATY: "gemv_ATy", cdcs.K_TRMV: "trmv",
-             cdcs.K_PROJECT: "project", cdcs.K_SCATTER: "scatter"}
-    out = {}
-    for kid, name in names.items():
-        sol.profile_kernel(state, kid, reps=2, form=form, rho=rho)  # warm
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            sol.profile_kernel(state, kid, reps=reps, form=form, rho=rho)
-        g.replay()
-        out[name] = time_events(torch, g.replay, reps_outer=3) / reps
-        del g
-    return out
+def snapshot(state):
+    return {k: (v.clone() if v is not None else None) for k, v in state.items()}
+
+
+def replay_kernel_ms(torch, sol, start, final, form, rho, K):
+    """Average duration (ms) of each kernel over the timed iterations.  A solve
+    is a function of (problem, state, options), so the K timed iterations are
+    run again from a copy of their starting state with eager launches and HIP
+    events around every kernel (cdcs_admm_solve_timed); the replay has to end
+    on the timed run's iterate, bit for bit."""
+    st = snapshot(start)
+    info, times = sol.solve_timed(st, form=form, rho=rho, tol=0.0, max_iter=K)
+    assert info.iters == K, info
+    for key in ("x", "y", "blk", "lam"):
+        assert torch.equal(st[key], final[key]), f"the replay left the timed run's trajectory ({key})"
+    return {n: ms / cnt for n, (ms, cnt) in times.items() if cnt > 0}
 
 
 def batched_vs_plain(torch, sol, state, rho):
@@ -210,6 +213,7 @@ def run_single(args, torch, workload):
     stt = sol.new_state(form)
     if W > 0:
         sol.solve(stt, form=form, rho=rho, tol=0.0, max_iter=W, check_every=min(GRAPH_CHUNK, W))
+    start = snapshot(stt)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     info = sol.solve(stt, form=form, rho=rho, tol=0.0, max_iter=K, check_every=GRAPH_CHUNK)
@@ -220,7 +224,7 @@ def run_single(args, torch, workload):
     ips = K / elapsed
     _log(f"timed: {K} iterations in {elapsed:.4f}s -> {ips:.1f} it/s, {sweeps_per_solve:.2f} sweeps/eigensolve")
 
-    kern_ms = kernel_times(torch, sol, stt, form, rho, args.kernel_reps)
+    kern_ms = replay_kernel_ms(torch, sol, start, stt, form, rho, K)
     abytes = algorithmic_bytes(sol, prob)
     kern = {n: {"us": kern_ms[n] * 1e3, "GB_s": abytes[n] / (kern_ms[n] * 1e-3) / 1e9} for n in kern_ms}
     _log("kernels: " + ", ".join(f"{n} {v['us']:.1f}us {v['GB_s']:.0f}GB/s" for n, v in kern.items()))
@@ -314,6 +318,7 @@ def run_many(args, torch):
     stt = sol.new_state("primal")
     if W > 0:
         sol.solve(stt, form="primal", rho=rho, tol=0.0, max_iter=W, check_every=min(GRAPH_CHUNK, W))
+    start = snapshot(stt)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     info = sol.solve(stt, form="primal", rho=rho, tol=0.0, max_iter=K, check_every=GRAPH_CHUNK)
@@ -337,17 +342,11 @@ def run_many(args, torch):
         "batched_vs_plain": None if args.profile else batched_vs_plain(torch, sol, st, rho),
         "projection_plan": tuning,
     })
-    # per-kernel averages: projection, scatter, whole affine step
-    R = args.kernel_reps
-    kern = {}
-    for kid, name in ((cdcs.K_PROJECT, "project"), (cdcs.K_SCATTER, "scatter"), (cdcs.K_GEMV_AU, "affine")):
-        sol.profile_kernel(stt, kid, reps=2)
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            sol.profile_kernel(stt, kid, reps=R)
-        g.replay()
-        kern[name] = {"us": time_events(torch, g.replay, reps_outer=3) / R * 1e3}
-        del g
+    # per-kernel averages over the timed iterations: projection, scatter, whole
+    # affine step (the gemv_Au kind of a batch handle)
+    kms = replay_kernel_ms(torch, sol, start, stt, "primal", rho, K)
+    kern = {"project": {"us": kms["project"] * 1e3}, "scatter": {"us": kms["scatter"] * 1e3},
+            "affine": {"us": kms["gemv_Au"] * 1e3}}
     # algorithmic bytes of the affine step: A_q read twice (FP32, rows of ld_q),
     # the triangular factors (FP64 triangles) and the vectors u, x, t, y
     a_bytes = 0
@@ -458,7 +457,6 @@ def main():
     ap.add_argument("--form", default="primal", choices=["primal", "dual"])
     ap.add_argument("--cpu-iters", type=int, default=None, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
-    ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB elementwise kernel (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--print-hash", action="store_true", help="print the kernel source hash and exit")

@@ -315,6 +315,24 @@ typedef enum {
 } cdcs_kernel;
 
 /*
+ * Instrumentation: cdcs_admm_solve with eager launches (opts->check_every is
+ * not used) that brackets each kernel kind of every iteration with HIP events
+ * on `stream`.  The launches, their order and so the iterates are those of
+ * cdcs_admm_solve with the same state and options, so replaying a timed
+ * cdcs_admm_solve from a copy of its starting state gives its per-kernel
+ * durations.  On return kernel_ms[k] holds the summed milliseconds and
+ * launches[k] the number of bracketed launches of kind k (arrays of 5,
+ * indexed by cdcs_kernel, owned by the caller; CDCS_K_GEMV_AU without the
+ * small reduction that follows it).  Batch handles: CDCS_K_GEMV_AU covers the
+ * whole affine step, CDCS_K_TRMV and CDCS_K_GEMV_ATY stay 0.  The residual
+ * checks run unbracketed.  Synchronises on stream.
+ * Errors: those of cdcs_admm_solve; CDCS_E_ARG for NULL kernel_ms or launches.
+ */
+cdcs_status cdcs_admm_solve_timed(cdcs_handle *h, const cdcs_state *st, const cdcs_options *opts,
+                                  cdcs_info *info, double *kernel_ms, int64_t *launches,
+                                  hipStream_t stream);
+
+/*
  * Instrumentation: enqueue `reps` back-to-back launches of one kernel of an
  * iteration of the given form, with the arguments it has inside
  * cdcs_admm_solve on this state (y, blk, lam, v are updated as by those

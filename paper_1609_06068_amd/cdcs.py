@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "CDCS_OK", 1: "CDCS_E_ARG", 2: "CDCS_E_PATTERN", 3: "CDCS_E_R
 # Every symbol include/cdcs.h declares.
 EXPORTS = ["cdcs_setup", "cdcs_setup_batch", "cdcs_batch_info", "cdcs_get_sizes", "cdcs_clique_offsets", "cdcs_psd_project_batched",
            "cdcs_psd_project_vjp", "cdcs_gather", "cdcs_scatter", "cdcs_affine_project", "cdcs_admm_solve",
-           "cdcs_admm_step", "cdcs_profile_kernel", "cdcs_get_tuning", "cdcs_set_projection_plan",
+           "cdcs_admm_step", "cdcs_admm_solve_timed", "cdcs_profile_kernel", "cdcs_get_tuning", "cdcs_set_projection_plan",
            "cdcs_residual_history", "cdcs_destroy", "cdcs_last_error"]
 
 
@@ -121,6 +121,7 @@ def load_library(path: str = LIB_PATH):
     L.cdcs_affine_project.argtypes = [vp, vp, vp, vp, vp, vp]
     L.cdcs_admm_solve.argtypes = [vp, P(_State), P(_Options), P(_Info), vp]
     L.cdcs_admm_step.argtypes = [vp, P(_State), i32, dbl, vp]
+    L.cdcs_admm_solve_timed.argtypes = [vp, P(_State), P(_Options), P(_Info), vp, vp, vp]
     L.cdcs_profile_kernel.argtypes = [vp, P(_State), i32, dbl, i32, i32, vp]
     L.cdcs_residual_history.argtypes = [vp, vp, i32]
     L.cdcs_destroy.argtypes = [vp]
@@ -266,6 +267,26 @@ class Solver:
             _check(st, "cdcs_admm_solve")
         return SolveInfo(info.iters, info.status, bool(info.converged), info.jacobi_cap_hits, info.eps_p,
                          info.eps_d, info.obj_primal, info.obj_dual, info.loop_s, info.jacobi_sweeps)
+
+    def solve_timed(self, state: dict, form: str = "primal", rho: float = 1.0, tol: float = 0.0,
+                    max_iter: int = 500, stream=None):
+        """cdcs_admm_solve with eager launches and events around every kernel:
+        returns (SolveInfo, {kernel name: (total ms, launches)})."""
+        L = load_library()
+        f = PRIMAL if form == "primal" else DUAL
+        opts = _Options(float(rho), float(tol), int(max_iter), f, 0)
+        info = _Info()
+        cs = self._cstate(state)
+        ms = np.zeros(5, dtype=np.float64)
+        n = np.zeros(5, dtype=np.int64)
+        st = L.cdcs_admm_solve_timed(self._h, ctypes.byref(cs), ctypes.byref(opts), ctypes.byref(info),
+                                     ms.ctypes.data, n.ctypes.data, _stream(self._torch, stream))
+        if st not in (OK, E_NOT_CONVERGED):
+            _check(st, "cdcs_admm_solve_timed")
+        names = ("project", "gemv_Au", "trmv", "gemv_ATy", "scatter")
+        times = {names[k]: (float(ms[k]), int(n[k])) for k in range(5)}
+        return SolveInfo(info.iters, info.status, bool(info.converged), info.jacobi_cap_hits, info.eps_p,
+                         info.eps_d, info.obj_primal, info.obj_dual, info.loop_s, info.jacobi_sweeps), times
 
     def step(self, state: dict, form: str = "primal", rho: float = 1.0, stream=None):
         L = load_library()

@@ -910,24 +910,84 @@ cdcs_status tune_projection(cdcs_handle *h, hipStream_t s) {
     return CDCS_OK;
 }
 
-void enqueue_iteration(cdcs_handle *h, const cdcs_state *st, int form, double rho, hipStream_t s) {
+// HIP events around the kernels of eager iterations (cdcs_admm_solve_timed):
+// a pool for kGroup iterations, read back and summed per cdcs_kernel kind
+// after each group's stream synchronisation.
+struct IterTimer {
+    static constexpr int kGroup = 64;
+    static constexpr int kPerIter = 5;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;  // of each recorded pair
+    double ms[kPerIter] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    int64_t n[kPerIter] = {0, 0, 0, 0, 0};
+    hipError_t init() {
+        ev.assign((size_t)2 * kGroup * kPerIter, nullptr);
+        for (hipEvent_t &e : ev) {
+            // no system-scope fence at the events: they only time device work
+            const hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
+    }
+    ~IterTimer() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    // launch `fn` on stream s between two events of the pool
+    template <class F>
+    void around(int k, hipStream_t s, F &&fn) {
+        const size_t i = 2 * kind.size();
+        (void)hipEventRecord(ev[i], s);
+        fn();
+        (void)hipEventRecord(ev[i + 1], s);
+        kind.push_back(k);
+    }
+    // after a synchronisation of the stream: add up the recorded pairs
+    hipError_t collect() {
+        for (size_t p = 0; p < kind.size(); ++p) {
+            float t = 0.0f;
+            const hipError_t r = hipEventElapsedTime(&t, ev[2 * p], ev[2 * p + 1]);
+            if (r != hipSuccess) return r;
+            ms[kind[p]] += (double)t;
+            n[kind[p]] += 1;
+        }
+        kind.clear();
+        return hipSuccess;
+    }
+};
+
+// One ADMM iteration.  With a timer (eager launches only) each kernel kind is
+// bracketed by events; the launches are the same either way.
+void enqueue_iteration(cdcs_handle *h, const cdcs_state *st, int form, double rho, hipStream_t s,
+                       IterTimer *tm = nullptr) {
     Dev &d = h->d;
+    auto timed = [&](int k, auto &&fn) {
+        if (tm) tm->around(k, s, fn);
+        else fn();
+    };
     if (d.batch) {  // Algorithm 1, per-instance stopping
-        launch_bscatter_primal(d, st->blk, st->lam, rho, s);
+        timed(CDCS_K_SCATTER, [&] { launch_bscatter_primal(d, st->blk, st->lam, rho, s); });
         launch_bcheck_primal(d, rho, s);
-        launch_baffine(d, d.b, 1.0, st->x, st->y, d.ctl, d.batch->istop, s);
-        launch_projection(h, PROJ_PRIMAL, st, rho, s);
+        timed(CDCS_K_GEMV_AU, [&] { launch_baffine(d, d.b, 1.0, st->x, st->y, d.ctl, d.batch->istop, s); });
+        timed(CDCS_K_PROJECT, [&] { launch_projection(h, PROJ_PRIMAL, st, rho, s); });
         return;
     }
+    // the affine step (t, then y = L^-T L^-1 t, then x) part by part
+    auto affine = [&](double r2scale) {
+        timed(CDCS_K_GEMV_AU, [&] { launch_affine_part(d, 0, d.b, r2scale, st->x, st->y, d.ctl, s); });
+        launch_affine_part(d, 3, d.b, r2scale, st->x, st->y, d.ctl, s);
+        timed(CDCS_K_TRMV, [&] { launch_affine_part(d, 1, d.b, r2scale, st->x, st->y, d.ctl, s); });
+        timed(CDCS_K_GEMV_ATY, [&] { launch_affine_part(d, 2, d.b, r2scale, st->x, st->y, d.ctl, s); });
+    };
     if (form == CDCS_PRIMAL) {
-        launch_scatter_primal(d, st->blk, st->lam, rho, st->x, s);
+        timed(CDCS_K_SCATTER, [&] { launch_scatter_primal(d, st->blk, st->lam, rho, st->x, s); });
         launch_check_primal(d, rho, s);
-        launch_affine(d, d.b, 1.0, st->x, st->y, d.ctl, s);
-        launch_projection(h, PROJ_PRIMAL, st, rho, s);
+        affine(1.0);
+        timed(CDCS_K_PROJECT, [&] { launch_projection(h, PROJ_PRIMAL, st, rho, s); });
     } else {
-        launch_projection(h, PROJ_DUAL, st, rho, s);
-        launch_scatter_dual(d, st->blk, st->lam, rho, st->x, s);
-        launch_affine(d, d.b, -1.0 / rho, st->x, st->y, d.ctl, s);
+        timed(CDCS_K_PROJECT, [&] { launch_projection(h, PROJ_DUAL, st, rho, s); });
+        timed(CDCS_K_SCATTER, [&] { launch_scatter_dual(d, st->blk, st->lam, rho, st->x, s); });
+        affine(-1.0 / rho);
         launch_vupdate(d, st->x, st->blk, st->lam, st->v, rho, s);
         launch_check_dual(d, rho, s);
     }
@@ -1135,8 +1195,9 @@ cdcs_status cdcs_affine_project(const cdcs_handle *h, const double *r1, const do
     return CDCS_OK;
 }
 
-cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st_user, const cdcs_options *opts, cdcs_info *info,
-                            hipStream_t stream) {
+namespace {
+cdcs_status solve_impl(cdcs_handle *h, const cdcs_state *st_user, const cdcs_options *opts, cdcs_info *info,
+                       hipStream_t stream, IterTimer *tm) {
     if (!h || !st_user || !opts) return fail(CDCS_E_ARG, "NULL argument");
     if (!st_user->x || !st_user->y || !st_user->blk || !st_user->lam) return fail(CDCS_E_ARG, "state has NULL buffers");
     // the iteration runs on x in internal entry order
@@ -1173,7 +1234,7 @@ cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st_user, const cdc
     launch_perm_in(d, st_user->x, d.xi, stream);
     HIP_OK(hipGetLastError());
     auto t0 = std::chrono::steady_clock::now();
-    const int K = opts->check_every;
+    const int K = tm ? 0 : opts->check_every;
     if (K > 0) {
         hipGraphExec_t ex = nullptr;
         CK(get_graph(h, st, form, K, rho, &ex));
@@ -1184,12 +1245,14 @@ cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st_user, const cdc
             if (d.ctl_host->stop) break;
         }
     } else {
+        const int group = tm ? IterTimer::kGroup : 16;
         for (int it = 0; it < opts->max_iter; ++it) {
-            enqueue_iteration(h, st, form, rho, stream);
+            enqueue_iteration(h, st, form, rho, stream, tm);
             HIP_OK(hipGetLastError());
-            if ((it + 1) % 16 == 0) {
+            if ((it + 1) % group == 0 || (tm && it + 1 == opts->max_iter)) {
                 HIP_OK(hipMemcpyAsync(d.ctl_host, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
                 HIP_OK(hipStreamSynchronize(stream));
+                if (tm) HIP_OK(tm->collect());
                 if (d.ctl_host->stop) break;
             }
         }
@@ -1243,6 +1306,25 @@ cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st_user, const cdc
     if (status != CDCS_OK)
         g_err = status == CDCS_E_NUMERIC ? "an eigensolve hit its sweep cap" : "iteration cap reached";
     return status;
+}
+}  // namespace
+
+cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st, const cdcs_options *opts, cdcs_info *info,
+                            hipStream_t stream) {
+    return solve_impl(h, st, opts, info, stream, nullptr);
+}
+
+cdcs_status cdcs_admm_solve_timed(cdcs_handle *h, const cdcs_state *st, const cdcs_options *opts, cdcs_info *info,
+                                  double *kernel_ms, int64_t *launches, hipStream_t stream) {
+    if (!kernel_ms || !launches) return fail(CDCS_E_ARG, "NULL kernel_ms or launches");
+    IterTimer tm;
+    HIP_OK(tm.init());
+    const cdcs_status r = solve_impl(h, st, opts, info, stream, &tm);
+    for (int k = 0; k < IterTimer::kPerIter; ++k) {
+        kernel_ms[k] = tm.ms[k];
+        launches[k] = tm.n[k];
+    }
+    return r;
 }
 
 cdcs_status cdcs_admm_step(cdcs_handle *h, const cdcs_state *st, int32_t form, double rho, hipStream_t stream) {
