@@ -39,18 +39,25 @@ __device__ __forceinline__ double block_sum_d(double v, double *red) {
 
 // The residual checks reduce the partial sums of the scatter and projection
 // launches in one workgroup of CNT threads (1024 when there are tens of
-// thousands of partials, 256 otherwise), fixed order (bitwise reproducible).
+// thousands of partials, 256 otherwise), fixed order (bitwise reproducible):
+// five sums at once, each a wave sum and then the waves in order, with one
+// barrier (every sum has its own row of `red`).
 template <int CNT>
-__device__ __forceinline__ double check_sum_d(double v, double *red) {
+__device__ __forceinline__ void check_sum5_d(double (&v)[5], double (*red)[CNT / 64]) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    v = wave_sum_d(v);
-    __syncthreads();
-    if (lane == 0) red[w] = v;
-    __syncthreads();
-    double r = 0.0;
 #pragma unroll
-    for (int i = 0; i < CNT / 64; ++i) r += red[i];
-    return r;
+    for (int i = 0; i < 5; ++i) v[i] = wave_sum_d(v[i]);
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) red[i][w] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        double r = 0.0;
+#pragma unroll
+        for (int j = 0; j < CNT / 64; ++j) r += red[i][j];
+        v[i] = r;
+    }
 }
 
 __global__ __launch_bounds__(kNT) void k_reset_ctl(Ctl *ctl, int max_iter, double tol) {
@@ -100,6 +107,9 @@ __global__ __launch_bounds__(kNT) void k_scatter_primal(const int32_t *__restric
             const int32_t q0 = inv_ptr[e], q1 = inv_ptr[e + 1];
             if (q1 - q0 <= kHeavy) {
                 owner = true;
+                // unrolled so that the loads of several slots are in flight
+                // together (the sum keeps its order)
+#pragma unroll 4
                 for (int32_t q = q0; q < q1; ++q) {
                     const int32_t sl = inv_slot[q];
                     s_x += (double)blk[sl];
@@ -144,38 +154,42 @@ __global__ __launch_bounds__(kNT) void k_scatter_primal(const int32_t *__restric
 }
 
 // Alg. 1 residual check of iteration n = ctl->iter (if any), then start the next one.
+// The partial sums' loads are issued before the control block is waited for
+// (the buffers always hold p and nsblk entries; before the first iteration
+// their values are not used).  Every thread reads the control block before a
+// barrier that precedes any write to it, so all waves take the same branches.
 template <int CNT>
 __global__ __launch_bounds__(CNT) void k_check_primal(const double *__restrict__ cpart, int p,
                                                       const double *__restrict__ spart, int nsblk, double rho,
                                                       double *__restrict__ hist, int hist_cap, Ctl *ctl) {
-    __shared__ double red[CNT / 64];
-    if (ctl->stop) return;
-    const int n = ctl->iter;
+    __shared__ double red[5][CNT / 64];
     const int tid = threadIdx.x;
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |x_k - H_k x|^2, |H_k x|^2, |x_k|^2, |dS|^2, |S_lam|^2
+#pragma unroll 4
+    for (int k = tid; k < p; k += CNT) {
+        const double4 c4 = *reinterpret_cast<const double4 *>(cpart + 4 * (int64_t)k);
+        v[0] += c4.x;
+        v[1] += c4.y;
+        v[2] += c4.z;
+    }
+#pragma unroll 8
+    for (int b = tid; b < nsblk; b += CNT) {
+        const double2 s2v = *reinterpret_cast<const double2 *>(spart + 2 * (int64_t)b);
+        v[3] += s2v.x;
+        v[4] += s2v.y;
+    }
+    const int stop = ctl->stop, n = ctl->iter, max_iter = ctl->max_iter;
+    const double tol = ctl->tol;
+    __syncthreads();
+    if (stop) return;
     if (n >= 1) {
-        double r2 = 0.0, h2 = 0.0, x2 = 0.0, d2 = 0.0, l2 = 0.0;
-        for (int k = tid; k < p; k += CNT) {
-            const double4 c4 = *reinterpret_cast<const double4 *>(cpart + 4 * (int64_t)k);
-            r2 += c4.x;
-            h2 += c4.y;
-            x2 += c4.z;
-        }
-        for (int b = tid; b < nsblk; b += CNT) {
-            const double2 s2v = *reinterpret_cast<const double2 *>(spart + 2 * (int64_t)b);
-            d2 += s2v.x;
-            l2 += s2v.y;
-        }
-        r2 = check_sum_d<CNT>(r2, red);
-        h2 = check_sum_d<CNT>(h2, red);
-        x2 = check_sum_d<CNT>(x2, red);
-        d2 = check_sum_d<CNT>(d2, red);
-        l2 = check_sum_d<CNT>(l2, red);
+        check_sum5_d<CNT>(v, red);
         if (tid == 0) {
-            const double den_p = fmax(sqrt(h2), sqrt(x2));
-            const double num_p = sqrt(r2);
+            const double den_p = fmax(sqrt(v[1]), sqrt(v[2]));
+            const double num_p = sqrt(v[0]);
             const double eps_p = den_p > 0.0 ? num_p / den_p : num_p;
-            const double num_d = rho * sqrt(d2);
-            const double den_d = sqrt(l2);
+            const double num_d = rho * sqrt(v[3]);
+            const double den_d = sqrt(v[4]);
             const double eps_d = den_d > 0.0 ? num_d / den_d : num_d;
             ctl->eps_p = eps_p;
             ctl->eps_d = eps_d;
@@ -183,17 +197,15 @@ __global__ __launch_bounds__(CNT) void k_check_primal(const double *__restrict__
                 hist[2 * (int64_t)(n - 1) + 0] = eps_p;
                 hist[2 * (int64_t)(n - 1) + 1] = eps_d;
             }
-            if (fmax(eps_p, eps_d) <= ctl->tol) {
+            if (fmax(eps_p, eps_d) <= tol) {
                 ctl->stop = 1;
                 return;
             }
         }
     }
     if (tid == 0) {
-        if (ctl->stop == 0) {
-            if (n >= ctl->max_iter) ctl->stop = 2;
-            else ctl->iter = n + 1;
-        }
+        if (n >= max_iter) ctl->stop = 2;
+        else ctl->iter = n + 1;
     }
 }
 
@@ -215,6 +227,7 @@ __global__ __launch_bounds__(kNT) void k_scatter_dual(const int32_t *__restrict_
         const int32_t q0 = inv_ptr[e], q1 = inv_ptr[e + 1];
         if (q1 - q0 > kHeavy) return;
         double s = 0.0;
+#pragma unroll 4
         for (int32_t q = q0; q < q1; ++q) {
             const int32_t sl = inv_slot[q];
             s += (double)blk[sl] + (double)lam[sl] / rho;
@@ -280,33 +293,30 @@ __global__ __launch_bounds__(kNT) void k_vupdate(const int32_t *__restrict__ gat
     }
 }
 
-// Alg. 2 residual check of the iteration just completed.
+// Alg. 2 residual check of the iteration just completed (loads issued before
+// the control block is waited for; its only writer is thread 0, after the
+// reduction's barrier).
 template <int CNT>
 __global__ __launch_bounds__(CNT) void k_check_dual(const double *__restrict__ vpart, int nvblk, double rho,
                                                     double *__restrict__ hist, int hist_cap, Ctl *ctl) {
-    __shared__ double red[CNT / 64];
-    if (ctl->stop) return;
+    __shared__ double red[5][CNT / 64];
     const int tid = threadIdx.x;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0;
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
     for (int b = tid; b < nvblk; b += CNT) {
         const double *o = vpart + 5 * (int64_t)b;
-        a0 += o[0];
-        a1 += o[1];
-        a2 += o[2];
-        a3 += o[3];
-        a4 += o[4];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) v[i] += o[i];
     }
-    a0 = check_sum_d<CNT>(a0, red);
-    a1 = check_sum_d<CNT>(a1, red);
-    a2 = check_sum_d<CNT>(a2, red);
-    a3 = check_sum_d<CNT>(a3, red);
-    a4 = check_sum_d<CNT>(a4, red);
+    const int stop = ctl->stop, n = ctl->iter + 1, max_iter = ctl->max_iter;
+    const double tol = ctl->tol;
+    if (stop) return;
+    check_sum5_d<CNT>(v, red);
     if (tid == 0) {
-        const int n = ctl->iter + 1;
-        const double den_p = fmax(sqrt(a1), sqrt(a2));
-        const double eps_p = den_p > 0.0 ? sqrt(a0) / den_p : sqrt(a0);
-        const double den_d = sqrt(a4);
-        const double eps_d = den_d > 0.0 ? rho * sqrt(a3) / den_d : rho * sqrt(a3);
+        const double den_p = fmax(sqrt(v[1]), sqrt(v[2]));
+        const double eps_p = den_p > 0.0 ? sqrt(v[0]) / den_p : sqrt(v[0]);
+        const double den_d = sqrt(v[4]);
+        const double eps_d = den_d > 0.0 ? rho * sqrt(v[3]) / den_d : rho * sqrt(v[3]);
         ctl->eps_p = eps_p;
         ctl->eps_d = eps_d;
         ctl->iter = n;
@@ -314,8 +324,8 @@ __global__ __launch_bounds__(CNT) void k_check_dual(const double *__restrict__ v
             hist[2 * (int64_t)(n - 1) + 0] = eps_p;
             hist[2 * (int64_t)(n - 1) + 1] = eps_d;
         }
-        if (fmax(eps_p, eps_d) <= ctl->tol) ctl->stop = 1;
-        else if (n >= ctl->max_iter) ctl->stop = 2;
+        if (fmax(eps_p, eps_d) <= tol) ctl->stop = 1;
+        else if (n >= max_iter) ctl->stop = 2;
     }
 }
 
@@ -340,6 +350,7 @@ __global__ __launch_bounds__(kNT) void k_scatter_f64(const int32_t *__restrict__
         const int32_t q0 = inv_ptr[e], q1 = inv_ptr[e + 1];
         if (q1 - q0 > kHeavy) return;
         double acc = 0.0;
+#pragma unroll 4
         for (int32_t q = q0; q < q1; ++q) acc += packed[inv_slot[q]];
         out[e] = acc;
     } else {
@@ -438,12 +449,15 @@ __global__ __launch_bounds__(kNT) void k_gemv_Au(const float *__restrict__ Aw, i
 __global__ __launch_bounds__(kNT) void k_reduce_t(const double *__restrict__ tpart, int nslice,
                                                   const double *__restrict__ r2, double r2scale,
                                                   double *__restrict__ t, int m, const Ctl *ctl) {
-    if (ctl != nullptr && ctl->stop) return;
     const int i = blockIdx.x * kNT + threadIdx.x;
     if (i >= m) return;
-    double sum = 0.0;
-    for (int q = 0; q < nslice; ++q) sum += tpart[(int64_t)q * m + i];
-    t[i] = sum - r2scale * r2[i];
+    double sum = 0.0;  // nslice <= kGemvSlices; the loads issue together, before the stop flag is waited for
+#pragma unroll
+    for (int q = 0; q < kGemvSlices; ++q)
+        if (q < nslice) sum += tpart[(int64_t)q * m + i];
+    const double r2i = r2[i];
+    if (ctl != nullptr && ctl->stop) return;
+    t[i] = sum - r2scale * r2i;
 }
 
 // Triangular product out = T vin over the row range [lo, hi) of each row:

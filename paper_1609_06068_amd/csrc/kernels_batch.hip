@@ -103,11 +103,13 @@ __global__ __launch_bounds__(kNT) void k_bcheck_primal(const double *__restrict_
     const int n = ctl->iter;
     if (n >= 1) {
         double r2 = 0.0, h2 = 0.0, x2 = 0.0, d2 = 0.0, l2 = 0.0;
+#pragma unroll 4
         for (int k = k_off[q] + lane; k < k_off[q + 1]; k += 64) {
             r2 += cpart[4 * (int64_t)k + 0];
             h2 += cpart[4 * (int64_t)k + 1];
             x2 += cpart[4 * (int64_t)k + 2];
         }
+#pragma unroll 4
         for (int b = sblk_off[q] + lane; b < sblk_off[q + 1]; b += 64) {
             d2 += spart[2 * (int64_t)b + 0];
             l2 += spart[2 * (int64_t)b + 1];
@@ -225,6 +227,7 @@ __global__ __launch_bounds__(kNT) void k_bAu_reduce(const int32_t *__restrict__ 
     if (nc == 1 || (istop != nullptr && istop[q])) return;
     const double *pr = tpart + p_off[q] + (int64_t)(r - m_off[q]) * nc;
     double sacc = 0.0;
+#pragma unroll 8
     for (int c = 0; c < nc; ++c) sacc += pr[c];
     t[r] = sacc - r2scale * r2[r];
 }
