@@ -135,13 +135,25 @@ typedef struct {
  *   y   [m]      FP64  KKT multiplier y (Alg. 1: y_sdp = -rho y; Alg. 2: y_sdp = y)
  *   blk [nslots] FP32  x_k (Alg. 1) or z_k (Alg. 2), packed
  *   lam [nslots] FP32  lambda_k, packed
- *   v   [nslots] FP32  v_k (Alg. 2 only; NULL allowed for Alg. 1) */
+ *   v   [nslots] FP32  v_k (Alg. 2 only; NULL allowed for Alg. 1)
+ *   vw  [nwarm]  FP32  eigenvectors of each clique's last projection (k x k
+ *                      blocks, row-major, clique order, offsets the prefix
+ *                      sums of s_k^2): the starting basis of the clique's
+ *                      next Jacobi eigensolve (Sec. III-B.2: one small
+ *                      eigendecomposition per cone and iteration).  Must hold
+ *                      orthogonal blocks; cdcs_warm_reset writes identities.
+ *                      With vw the warm start carries over from one solve
+ *                      call to the next, so splitting a solve into several
+ *                      calls does not change its iterates.  NULL: the handle
+ *                      keeps its own copy and restarts it at identity in
+ *                      every solve. */
 typedef struct {
     double *x;
     double *y;
     float *blk;
     float *lam;
     float *v;
+    float *vw;
 } cdcs_state;
 
 /* Sizes of a handle.  sparse_a = 1 if A is kept sparse (nnz_a coefficients),
@@ -154,6 +166,7 @@ typedef struct {
     int32_t sparse_a, sparse_factor;
     int64_t nnz_a;
     int64_t nnz_factor;
+    int64_t nwarm;        /* sum of s_k^2: length of cdcs_state.vw */
 } cdcs_sizes;
 
 /*
@@ -298,6 +311,11 @@ cdcs_status cdcs_affine_project(const cdcs_handle *h, const double *r1, const do
  */
 cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st, const cdcs_options *opts,
                             cdcs_info *info, hipStream_t stream);
+
+/* Write identity blocks into a caller's warm-start buffer (cdcs_state.vw,
+ * nwarm floats, device memory) on `stream`: the basis a new state starts
+ * from.  Errors: CDCS_E_ARG (NULL handle or buffer). */
+cdcs_status cdcs_warm_reset(const cdcs_handle *h, float *vw, hipStream_t stream);
 
 /* One iteration (eager launches) continuing from the state; equivalent to
  * cdcs_admm_solve with max_iter = 1, tol = 0, check_every = 0. */

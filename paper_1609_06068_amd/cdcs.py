@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "CDCS_OK", 1: "CDCS_E_ARG", 2: "CDCS_E_PATTERN", 3: "CDCS_E_R
 EXPORTS = ["cdcs_setup", "cdcs_setup_batch", "cdcs_batch_info", "cdcs_get_sizes", "cdcs_clique_offsets", "cdcs_psd_project_batched",
            "cdcs_psd_project_vjp", "cdcs_gather", "cdcs_scatter", "cdcs_affine_project", "cdcs_admm_solve",
            "cdcs_admm_step", "cdcs_admm_solve_timed", "cdcs_profile_kernel", "cdcs_get_tuning", "cdcs_set_projection_plan",
-           "cdcs_residual_history", "cdcs_destroy", "cdcs_last_error"]
+           "cdcs_residual_history", "cdcs_warm_reset", "cdcs_destroy", "cdcs_last_error"]
 
 
 class CdcsLibraryMissing(ImportError):
@@ -67,7 +67,7 @@ class _Info(ctypes.Structure):
 
 class _State(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("blk", ctypes.c_void_p),
-                ("lam", ctypes.c_void_p), ("v", ctypes.c_void_p)]
+                ("lam", ctypes.c_void_p), ("v", ctypes.c_void_p), ("vw", ctypes.c_void_p)]
 
 
 class _Problem(ctypes.Structure):
@@ -91,7 +91,8 @@ class _Tuning(ctypes.Structure):
 class _Sizes(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("p", ctypes.c_int32), ("smax", ctypes.c_int32),
                 ("nnz", ctypes.c_int64), ("nslots", ctypes.c_int64), ("sparse_a", ctypes.c_int32),
-                ("sparse_factor", ctypes.c_int32), ("nnz_a", ctypes.c_int64), ("nnz_factor", ctypes.c_int64)]
+                ("sparse_factor", ctypes.c_int32), ("nnz_a", ctypes.c_int64), ("nnz_factor", ctypes.c_int64),
+                ("nwarm", ctypes.c_int64)]
 
 
 _lib = None
@@ -121,6 +122,7 @@ def load_library(path: str = LIB_PATH):
     L.cdcs_affine_project.argtypes = [vp, vp, vp, vp, vp, vp]
     L.cdcs_admm_solve.argtypes = [vp, P(_State), P(_Options), P(_Info), vp]
     L.cdcs_admm_step.argtypes = [vp, P(_State), i32, dbl, vp]
+    L.cdcs_warm_reset.argtypes = [vp, vp, vp]
     L.cdcs_admm_solve_timed.argtypes = [vp, P(_State), P(_Options), P(_Info), vp, vp, vp]
     L.cdcs_profile_kernel.argtypes = [vp, P(_State), i32, dbl, i32, i32, vp]
     L.cdcs_residual_history.argtypes = [vp, vp, i32]
@@ -220,6 +222,7 @@ class Solver:
         self.nnz, self.nslots = sz.nnz, sz.nslots
         self.sparse_a, self.nnz_a = bool(sz.sparse_a), sz.nnz_a
         self.sparse_factor, self.nnz_factor = bool(sz.sparse_factor), sz.nnz_factor
+        self.nwarm = sz.nwarm
         off = np.empty(self.p + 1, dtype=np.int64)
         _check(L.cdcs_clique_offsets(h, _np_ptr(off)), "cdcs_clique_offsets")
         self.offsets = off
@@ -247,12 +250,16 @@ class Solver:
             "blk": torch.zeros(self.nslots, dtype=torch.float32, device=dev),
             "lam": torch.zeros(self.nslots, dtype=torch.float32, device=dev),
             "v": torch.zeros(self.nslots, dtype=torch.float32, device=dev) if form == "dual" else None,
+            # eigenvector warm start carried from one solve call to the next
+            "vw": torch.empty(self.nwarm, dtype=torch.float32, device=dev),
         }
+        _check(load_library().cdcs_warm_reset(self._h, _ptr(st["vw"]), _stream(torch, None)), "cdcs_warm_reset")
         return st
 
     @staticmethod
     def _cstate(st: dict) -> _State:
-        return _State(_ptr(st["x"]), _ptr(st["y"]), _ptr(st["blk"]), _ptr(st["lam"]), _ptr(st.get("v")))
+        return _State(_ptr(st["x"]), _ptr(st["y"]), _ptr(st["blk"]), _ptr(st["lam"]), _ptr(st.get("v")),
+                      _ptr(st.get("vw")))
 
     def solve(self, state: dict, form: str = "primal", rho: float = 1.0, tol: float = 1e-4,
               max_iter: int = 500, check_every: int = 50, stream=None, raise_on_cap: bool = False) -> SolveInfo:

@@ -40,9 +40,10 @@ struct GraphKey {
     int form;
     int K;
     double rho;
-    const void *x, *y, *blk, *lam, *v;
+    const void *x, *y, *blk, *lam, *v, *vw;
     bool operator<(const GraphKey &o) const {
-        return std::tie(form, K, rho, x, y, blk, lam, v) < std::tie(o.form, o.K, o.rho, o.x, o.y, o.blk, o.lam, o.v);
+        return std::tie(form, K, rho, x, y, blk, lam, v, vw) <
+               std::tie(o.form, o.K, o.rho, o.x, o.y, o.blk, o.lam, o.v, o.vw);
     }
 };
 
@@ -370,6 +371,7 @@ cdcs_status upload_common(cdcs_handle *h, const std::vector<int32_t> &size, cons
         vwoff[(size_t)k + 1] = vwoff[(size_t)k] + (int64_t)size[(size_t)k] * size[(size_t)k];
     CK(upload(h, &d.vwoff, vwoff, s));
     CK(h->alloc(&d.vwarm, vwoff[(size_t)p]));
+    d.nwarm = vwoff[(size_t)p];
     launch_identity_blocks(d.clq_size, d.vwoff, p, d.vwarm, s);
     for (int q = 0; q < NBK; ++q) {
         if (bl[(size_t)q].empty()) continue;
@@ -780,7 +782,7 @@ ProjArgs proj_args(const cdcs_handle *h, int mode, const cdcs_state *st, double 
     a.rho = rho;
     a.kinst = d.batch ? d.batch->kinst : nullptr;
     a.istop = d.batch ? d.batch->istop : nullptr;
-    a.vwarm = d.vwarm;
+    a.vwarm = (st && st->vw) ? st->vw : d.vwarm;
     a.vwoff = d.vwoff;
     a.warm_store = 1;
     a.cpart = d.cpart;
@@ -994,7 +996,7 @@ void enqueue_iteration(cdcs_handle *h, const cdcs_state *st, int form, double rh
 }
 
 cdcs_status get_graph(cdcs_handle *h, const cdcs_state *st, int form, int K, double rho, hipGraphExec_t *out) {
-    GraphKey key{form, K, rho, st->x, st->y, st->blk, st->lam, st->v};
+    GraphKey key{form, K, rho, st->x, st->y, st->blk, st->lam, st->v, st->vw};
     auto it = h->graphs.find(key);
     if (it != h->graphs.end()) {
         *out = it->second;
@@ -1112,6 +1114,15 @@ cdcs_status cdcs_get_sizes(const cdcs_handle *h, cdcs_sizes *out) {
     out->sparse_factor = h->d.sparse_linv;
     out->nnz_a = h->d.sparse ? h->d.nnzA : (int64_t)h->d.m * h->d.nU;
     out->nnz_factor = h->d.sparse_linv ? h->d.nnz_linv : (int64_t)h->d.m * (h->d.m + 1) / 2;
+    out->nwarm = h->d.nwarm;
+    return CDCS_OK;
+}
+
+cdcs_status cdcs_warm_reset(const cdcs_handle *h, float *vw, hipStream_t stream) {
+    if (!h || !vw) return fail(CDCS_E_ARG, "NULL argument");
+    const Dev &d = h->d;
+    launch_identity_blocks(d.clq_size, d.vwoff, d.p, vw, stream);
+    HIP_OK(hipGetLastError());
     return CDCS_OK;
 }
 
@@ -1228,9 +1239,9 @@ cdcs_status solve_impl(cdcs_handle *h, const cdcs_state *st_user, const cdcs_opt
     }
     launch_reset_ctl(d, opts->max_iter, opts->tol, stream);
     if (d.batch) launch_breset(d, stream);
-    // the eigenvector warm start restarts at each solve: a solve is a function
-    // of (problem, state, options) only
-    launch_identity_blocks(d.clq_size, d.vwoff, d.p, d.vwarm, stream);
+    // a solve is a function of (problem, state, options) only: without a
+    // warm-start buffer in the state the handle's copy restarts at identity
+    if (!st_user->vw) launch_identity_blocks(d.clq_size, d.vwoff, d.p, d.vwarm, stream);
     launch_perm_in(d, st_user->x, d.xi, stream);
     HIP_OK(hipGetLastError());
     auto t0 = std::chrono::steady_clock::now();

@@ -182,6 +182,7 @@ struct Dev {
     int32_t *order = nullptr;      // [p] cliques by decreasing size
     int64_t *vwoff = nullptr;      // [p+1] offsets of k x k blocks (prefix sums of s_k^2)
     float *vwarm = nullptr;        // [sum s_k^2] eigenvectors of the last projection
+    int64_t nwarm = 0;             // sum s_k^2
     // work
     double *u = nullptr;           // [ldU] r1 / D, zero padded
     double *xi = nullptr;          // [ldU] x in internal entry order (the solver's iterate)

@@ -171,21 +171,52 @@ def test_graph_and_eager_give_identical_bits(torch):
 
 
 @pytest.mark.parametrize("form", ["primal", "dual"])
-def test_warm_start_continues_the_iteration(torch, form):
-    """18 + 12 iterations from the saved state equal 30 in one solve.  Not
-    bitwise: each solve restarts the eigensolver's eigenvector warm start from
-    the identity, so iteration 19 takes a cold Jacobi run (same projection to
-    FP32 accuracy)."""
+def test_split_solve_equals_one_solve(torch, form):
+    """18 + 12 iterations from the saved state equal 30 in one solve, bit for
+    bit: the state carries the eigensolver's eigenvector warm start (vw) from
+    one call to the next."""
+    prob = synth.c1()
+    sol = cdcs.Solver(prob)
+    assert sol.nwarm == int(np.sum(np.asarray(sol.sizes, dtype=np.int64) ** 2))
+    a = sol.new_state(form)
+    sol.solve(a, form=form, tol=0.0, max_iter=30, check_every=0)
+    b = sol.new_state(form)
+    sol.solve(b, form=form, tol=0.0, max_iter=18, check_every=6)
+    sol.solve(b, form=form, tol=0.0, max_iter=12, check_every=0)
+    keys = ("x", "y", "blk", "lam", "vw") + (("v",) if form == "dual" else ())
+    for k in keys:
+        assert torch.equal(a[k], b[k]), k
+    sol.close()
+
+
+@pytest.mark.parametrize("form", ["primal", "dual"])
+def test_split_solve_without_warm_buffer(torch, form):
+    """Without vw in the state the handle restarts the eigenvector warm start
+    from the identity in every solve, so iteration 19 takes a cold Jacobi run:
+    the same projection to FP32 accuracy, not the same bits."""
     prob = synth.c1()
     sol = cdcs.Solver(prob)
     a = sol.new_state(form)
     sol.solve(a, form=form, tol=0.0, max_iter=30, check_every=0)
     b = sol.new_state(form)
+    b["vw"] = None
     sol.solve(b, form=form, tol=0.0, max_iter=18, check_every=0)
     sol.solve(b, form=form, tol=0.0, max_iter=12, check_every=0)
     keys = ("x", "blk", "lam", "v") if form == "dual" else ("x", "blk", "lam")
     for k in keys:
         assert _rel(b[k].cpu().numpy().astype(np.float64), a[k].cpu().numpy().astype(np.float64)) <= 1e-5
+    # a solve without vw is a function of the rest of the state
+    c = sol.new_state(form)
+    c["vw"] = None
+    sol.solve(c, form=form, tol=0.0, max_iter=18, check_every=0)
+    d = {k: (v.clone() if v is not None else None) for k, v in c.items()}
+    sol.solve(c, form=form, tol=0.0, max_iter=12, check_every=0)
+    sol.solve(d, form=form, tol=0.0, max_iter=12, check_every=4)
+    for k in keys:
+        assert torch.equal(c[k], d[k]), k
+    with pytest.raises(cdcs.CdcsError) as e:
+        cdcs._check(cdcs.load_library().cdcs_warm_reset(sol._h, None, None), "cdcs_warm_reset")
+    assert e.value.status == cdcs.E_ARG
     sol.close()
 
 
