@@ -982,13 +982,13 @@ void enqueue_iteration(cdcs_handle *h, const cdcs_state *st, int form, double rh
         timed(CDCS_K_GEMV_ATY, [&] { launch_affine_part(d, 2, d.b, r2scale, st->x, st->y, d.ctl, s); });
     };
     if (form == CDCS_PRIMAL) {
-        timed(CDCS_K_SCATTER, [&] { launch_scatter_primal(d, st->blk, st->lam, rho, st->x, s); });
+        timed(CDCS_K_SCATTER, [&] { launch_scatter_primal(d, st->blk, st->lam, rho, s); });
         launch_check_primal(d, rho, s);
         affine(1.0);
         timed(CDCS_K_PROJECT, [&] { launch_projection(h, PROJ_PRIMAL, st, rho, s); });
     } else {
         timed(CDCS_K_PROJECT, [&] { launch_projection(h, PROJ_DUAL, st, rho, s); });
-        timed(CDCS_K_SCATTER, [&] { launch_scatter_dual(d, st->blk, st->lam, rho, st->x, s); });
+        timed(CDCS_K_SCATTER, [&] { launch_scatter_dual(d, st->blk, st->lam, rho, s); });
         affine(-1.0 / rho);
         launch_vupdate(d, st->x, st->blk, st->lam, st->v, rho, s);
         launch_check_dual(d, rho, s);
@@ -1198,7 +1198,7 @@ cdcs_status cdcs_affine_project(const cdcs_handle *h, const double *r1, const do
     if (!h || !r1 || !r2 || !x || !y) return fail(CDCS_E_ARG, "NULL argument");
     const Dev &d = h->d;
     launch_perm_in(d, r1, d.xtmp, stream);
-    launch_scale_u(d, d.xtmp, d.xi, stream);
+    launch_scale_u(d, d.xtmp, stream);
     if (d.batch) launch_baffine(d, r2, 1.0, d.xi, y, nullptr, nullptr, stream);
     else launch_affine(d, r2, 1.0, d.xi, y, nullptr, stream);
     launch_perm_out(d, d.xi, x, stream);
@@ -1274,8 +1274,8 @@ cdcs_status solve_impl(cdcs_handle *h, const cdcs_state *st_user, const cdcs_opt
         launch_bobjectives(d, st->x, st->y, d.batch->iobj, stream);
     } else if (form == CDCS_PRIMAL) {
         // residuals of the last iteration need the next right-hand side's scatter
-        // (x keeps the last iterate: no copy of u into it)
-        launch_scatter_primal(d, st->blk, st->lam, rho, nullptr, stream);
+        // (it writes u only; x keeps the last iterate)
+        launch_scatter_primal(d, st->blk, st->lam, rho, stream);
         launch_check_primal(d, rho, stream);
     }
     launch_objectives(d, st->x, st->y, stream);
@@ -1388,8 +1388,8 @@ cdcs_status cdcs_profile_kernel(cdcs_handle *h, const cdcs_state *st_user, int32
             launch_affine_part(d, 2, d.b, 1.0, st->x, st->y, d.ctl, stream);
             break;
         case CDCS_K_SCATTER:
-            if (form == CDCS_PRIMAL) launch_scatter_primal(d, st->blk, st->lam, rho, st->x, stream);
-            else launch_scatter_dual(d, st->blk, st->lam, rho, st->x, stream);
+            if (form == CDCS_PRIMAL) launch_scatter_primal(d, st->blk, st->lam, rho, stream);
+            else launch_scatter_dual(d, st->blk, st->lam, rho, stream);
             break;
         default:
             return fail(CDCS_E_ARG, "unknown kernel id");

@@ -218,16 +218,13 @@ int scatter_blocks(const Dev &d);
 int heavy_threshold();
 int vupdate_blocks(const Dev &d);
 void launch_reset_ctl(const Dev &d, int max_iter, double tol, hipStream_t s);
-// xcopy: sparse-A handles also write x = u (entries without coefficients keep it)
-void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, double rho, double *xcopy,
-                           hipStream_t s);
+void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s);
 void launch_check_primal(const Dev &d, double rho, hipStream_t s);
-void launch_scatter_dual(const Dev &d, const float *blk, const float *lam, double rho, double *xcopy,
-                        hipStream_t s);
+void launch_scatter_dual(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s);
 void launch_vupdate(const Dev &d, const double *x, const float *blk, float *lam, float *v, double rho,
                     hipStream_t s);
 void launch_check_dual(const Dev &d, double rho, hipStream_t s);
-void launch_scale_u(const Dev &d, const double *r1, double *xcopy, hipStream_t s);
+void launch_scale_u(const Dev &d, const double *r1, hipStream_t s);
 void launch_affine(const Dev &d, const double *r2, double r2scale, double *x, double *y, const Ctl *ctl,
                    hipStream_t s);
 // One part of the affine step: 0 split-K A u partials, 3 their reduction to t,

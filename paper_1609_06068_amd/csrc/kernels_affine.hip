@@ -91,7 +91,6 @@ __global__ __launch_bounds__(kNT) void k_scatter_primal(const int32_t *__restric
                                                         const double *__restrict__ c,
                                                         const double *__restrict__ invD,
                                                         const double *__restrict__ wt, double *__restrict__ u,
-                                                        double *__restrict__ xcopy,
                                                         double *__restrict__ sx, double *__restrict__ spart,
                                                         int64_t nU, double rho, const Ctl *ctl) {
     __shared__ double red[kNT / 64];
@@ -136,7 +135,6 @@ __global__ __launch_bounds__(kNT) void k_scatter_primal(const int32_t *__restric
     if (owner) {
         const double r1 = s_x + s_l / rho - c[e] / rho;
         u[e] = r1 * invD[e];
-        if (xcopy) xcopy[e] = r1 * invD[e];
         double *cur = sx + (int64_t)(n & 1) * nU;
         const double *prev = sx + (int64_t)((n + 1) & 1) * nU;
         const double d = s_x - prev[e];
@@ -217,7 +215,7 @@ __global__ __launch_bounds__(kNT) void k_scatter_dual(const int32_t *__restrict_
                                                       const float *__restrict__ lam,
                                                       const double *__restrict__ c,
                                                       const double *__restrict__ invD, double *__restrict__ u,
-                                                      double *__restrict__ xcopy, int64_t nU, double rho,
+                                                      int64_t nU, double rho,
                                                       const Ctl *ctl) {
     if (ctl->stop) return;
     const int lane = threadIdx.x & 63;
@@ -233,7 +231,6 @@ __global__ __launch_bounds__(kNT) void k_scatter_dual(const int32_t *__restrict_
             s += (double)blk[sl] + (double)lam[sl] / rho;
         }
         u[e] = (c[e] - s) * invD[e];
-        if (xcopy) xcopy[e] = (c[e] - s) * invD[e];
     } else {
         const int hw = ((int)blockIdx.x - nlight_blocks) * (kNT / 64) + (threadIdx.x >> 6);
         if (hw >= nheavy) return;
@@ -247,8 +244,7 @@ __global__ __launch_bounds__(kNT) void k_scatter_dual(const int32_t *__restrict_
         s = wave_sum_d(s);
         if (lane == 0) {
             u[e] = (c[e] - s) * invD[e];
-            if (xcopy) xcopy[e] = (c[e] - s) * invD[e];
-        }
+            }
     }
 }
 
@@ -366,11 +362,10 @@ __global__ __launch_bounds__(kNT) void k_scatter_f64(const int32_t *__restrict__
 }
 
 __global__ __launch_bounds__(kNT) void k_scale_u(const double *__restrict__ r1, const double *__restrict__ invD,
-                                                 double *__restrict__ u, double *__restrict__ xcopy, int64_t nU) {
+                                                 double *__restrict__ u, int64_t nU) {
     const int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x;
     if (e >= nU) return;
     u[e] = r1[e] * invD[e];
-    if (xcopy) xcopy[e] = r1[e] * invD[e];
 }
 
 // Sparse A: t_i = sum over the coefficients of row i of Aw_ie u_e - r2scale r2_i.
@@ -390,8 +385,22 @@ __global__ __launch_bounds__(kNT) void k_spmv_Au(const int32_t *__restrict__ sp_
     if (lane == 0) t[row] = acc - r2scale * r2[row];
 }
 
-// Sparse A: x_e = u_e - s2_e (Aw^T y)_e on the entries that carry coefficients
-// (x = u elsewhere was written with u).  One thread per touched entry.
+// Sparse A, second half of the x-update: x = u (k_copy_u), then x_e = u_e -
+// s2_e (Aw^T y)_e on the entries that carry coefficients (k_sp_xcorr, one
+// thread per touched entry).  Both are gated by the stop flag like the rest
+// of the affine step, so a solve that stops inside an iteration (after its
+// scatter and check) keeps the last completed iterate in x.
+__global__ __launch_bounds__(kNT) void k_copy_u(const double *__restrict__ u, double *__restrict__ x, int64_t n,
+                                                const Ctl *ctl) {
+    if (ctl != nullptr && ctl->stop) return;
+    const int64_t e = 2 * ((int64_t)blockIdx.x * kNT + threadIdx.x);
+    if (e + 1 < n) {
+        *reinterpret_cast<double2 *>(x + e) = *reinterpret_cast<const double2 *>(u + e);
+    } else if (e < n) {
+        x[e] = u[e];
+    }
+}
+
 __global__ __launch_bounds__(kNT) void k_sp_xcorr(const int32_t *__restrict__ tc_e,
                                                   const int32_t *__restrict__ tc_ptr,
                                                   const int32_t *__restrict__ tc_row,
@@ -604,11 +613,11 @@ void launch_reset_ctl(const Dev &d, int max_iter, double tol, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(kNT), 0, s, d.ctl, max_iter, tol);
 }
 
-void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, double rho, double *xcopy,
+void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, double rho,
                            hipStream_t s) {
     hipLaunchKernelGGL(k_scatter_primal, dim3(scatter_blocks(d)), dim3(kNT), 0, s, d.inv_ptr, d.inv_slot,
                        (const int32_t *)d.heavy, d.nheavy, scatter_light_blocks(d), blk, lam, d.c, d.invD, d.wt, d.u,
-                       d.sparse ? xcopy : nullptr, d.sx, d.spart, d.nU, rho, (const Ctl *)d.ctl);
+                       d.sx, d.spart, d.nU, rho, (const Ctl *)d.ctl);
 }
 
 void launch_check_primal(const Dev &d, double rho, hipStream_t s) {
@@ -620,11 +629,11 @@ void launch_check_primal(const Dev &d, double rho, hipStream_t s) {
                            (const double *)d.spart, scatter_blocks(d), rho, d.hist, d.hist_cap, d.ctl);
 }
 
-void launch_scatter_dual(const Dev &d, const float *blk, const float *lam, double rho, double *xcopy,
+void launch_scatter_dual(const Dev &d, const float *blk, const float *lam, double rho,
                         hipStream_t s) {
     hipLaunchKernelGGL(k_scatter_dual, dim3(scatter_blocks(d)), dim3(kNT), 0, s, d.inv_ptr, d.inv_slot,
                        (const int32_t *)d.heavy, d.nheavy, scatter_light_blocks(d), blk, lam, d.c, d.invD, d.u,
-                       d.sparse ? xcopy : nullptr, d.nU, rho, (const Ctl *)d.ctl);
+                       d.nU, rho, (const Ctl *)d.ctl);
 }
 
 void launch_vupdate(const Dev &d, const double *x, const float *blk, float *lam, float *v, double rho,
@@ -642,9 +651,8 @@ void launch_check_dual(const Dev &d, double rho, hipStream_t s) {
                            rho, d.hist, d.hist_cap, d.ctl);
 }
 
-void launch_scale_u(const Dev &d, const double *r1, double *xcopy, hipStream_t s) {
-    hipLaunchKernelGGL(k_scale_u, dim3(blocks_for(d.nU)), dim3(kNT), 0, s, r1, (const double *)d.invD, d.u,
-                       d.sparse ? xcopy : nullptr, d.nU);
+void launch_scale_u(const Dev &d, const double *r1, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_u, dim3(blocks_for(d.nU)), dim3(kNT), 0, s, r1, (const double *)d.invD, d.u, d.nU);
 }
 
 // Affine projection from u = r1 / D: t = A (w u) - r2scale r2, y = L^-T L^-1 t,
@@ -663,6 +671,8 @@ void launch_affine_part(const Dev &d, int part, const double *r2, double r2scale
     } else if (d.sparse && part == 3) {
         // A u already carries - r2scale r2
     } else if (d.sparse && part == 2) {
+        hipLaunchKernelGGL(k_copy_u, dim3(blocks_for((d.nU + 1) / 2)), dim3(kNT), 0, s, (const double *)d.u, x, d.nU,
+                           ctl);
         if (d.ntc > 0)
             hipLaunchKernelGGL(k_sp_xcorr, dim3(blocks_for(d.ntc)), dim3(kNT), 0, s, (const int32_t *)d.tc_e,
                                (const int32_t *)d.tc_ptr, (const int32_t *)d.tc_row, (const double *)d.tc_val,
