@@ -88,8 +88,8 @@ def algorithmic_bytes(sol, prob):
         nnz = sol.nnz_a
         ntc = int(np.unique(prob.A_idx).shape[0])
         out["gemv_Au"] = nnz * (4 + 8 + 8) + 2 * m * 8         # coefficients, u gathers, b, t
-        out["gemv_ATy"] = nnz * (4 + 8 + 8) + ntc * (4 + 8 * 3)  # coefficients, y gathers; u, s2 in, x out
-        out["scatter"] += nU * 8                               # x = u on entries without coefficients
+        # coefficients, y gathers; x = u on every entry, then u, s2 in and x out on the touched ones
+        out["gemv_ATy"] = nnz * (4 + 8 + 8) + nU * 16 + ntc * (4 + 8 * 3)
     else:
         out["gemv_Au"] = m * nU * 4 + nU * 8 + 2 * m * 8        # A (FP32), u, b, t
         out["gemv_ATy"] = nU * m * 4 + m * 8 + 3 * nU * 8       # A^T, y, u, 1/(wD), x
@@ -144,20 +144,22 @@ def batched_vs_plain(torch, sol, state, rho):
 
 
 def roofline_for(kern_ms, abytes, sizes, traffic_file):
-    """Roofline of the kernel that takes the most time per iteration."""
+    """Roofline of the kernel that takes the most time per iteration; `traffic`
+    is its counter-measured HBM bytes per launch while the counters were taken
+    on the current kernel sources."""
     dom = max(kern_ms, key=lambda n: kern_ms[n])
-    if dom == "project":
-        fl = projection_model_flops(sizes)
-        ach = fl / (kern_ms[dom] * 1e-3) / 1e12
-        return {"bound": "alu", "kernel": dom, "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / FP32_VALU_PEAK_TFLOPS, "traffic": None, "algorithmic_flops": fl,
-                "avg_us": kern_ms[dom] * 1e3}
     traffic = None
     if traffic_file and os.path.exists(traffic_file):
         with open(traffic_file) as fh:
             tj = json.load(fh)
         if tj.get("source_hash") == kernel_source_hash() and dom in tj.get("kernels", {}):
             traffic = tj["kernels"][dom]["bytes_per_launch"]
+    if dom == "project":
+        fl = projection_model_flops(sizes)
+        ach = fl / (kern_ms[dom] * 1e-3) / 1e12
+        return {"bound": "alu", "kernel": dom, "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP32_VALU_PEAK_TFLOPS, "traffic": traffic, "algorithmic_flops": fl,
+                "avg_us": kern_ms[dom] * 1e3}
     gbs = abytes[dom] / (kern_ms[dom] * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": dom, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes": abytes[dom],
