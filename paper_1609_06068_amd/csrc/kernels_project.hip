@@ -319,7 +319,8 @@ __device__ __forceinline__ void product_store(const float *X, const float *Y, co
 
 // Small per-workgroup LDS of the projection (sized for the largest bucket).
 struct ProjSmall {
-    float4 cst[64];              // rotations of one step: (c, s, -, -) of pair t
+    float2 cst[64];              // rotations of one step: (c, s) of pair t (8-byte stride: the reads of
+                                 // consecutive pairs fall in distinct bank pairs)
     float lam[96], lp[96];       // eigenvalues, clamped eigenvalues
     float redf[8];
     double redd[24];             // three FP64 partial sums per wave
@@ -553,7 +554,7 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
                 SF(nxt, dgo[T][1]) = 0.0f;
                 SF(nxt, dgo[T][2]) = aqq + ta;
             }
-            sm.cst[tid] = make_float4(c, s, 0.0f, 0.0f);
+            sm.cst[tid] = make_float2(c, s);
         }
         __syncthreads();
         // A <- J^T A J on this thread's off-diagonal blocks (and the ghost
@@ -567,8 +568,8 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
             const int b4 = (tid + q * NT) * 4;
             const float a00 = LF(cur, b4), a01 = LF(cur, PL + b4);
             const float a10 = LF(cur, 2 * PL + b4), a11 = LF(cur, 3 * PL + b4);
-            const float2 cs1 = *reinterpret_cast<const float2 *>(&sm.cst[I]);
-            const float2 cs2 = *reinterpret_cast<const float2 *>(&sm.cst[J]);
+            const float2 cs1 = sm.cst[I];
+            const float2 cs2 = sm.cst[J];
             const float c1 = cs1.x, s1 = cs1.y, c2 = cs2.x, s2 = cs2.y;
             const float b00 = c1 * a00 - s1 * a10, b01 = c1 * a01 - s1 * a11;
             const float b10 = s1 * a00 + c1 * a10, b11 = s1 * a01 + c1 * a11;
@@ -582,7 +583,7 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
         // the new position 2i-1 goes back to lane i-1.  Lanes past the pairs
         // rotate by the identity and keep zeros.
         const bool pl = pi < npair;
-        const float4 csl = sm.cst[pl ? pi : 0];
+        const float2 csl = sm.cst[pl ? pi : 0];
         const float c = pl ? csl.x : 1.0f, sg = pl ? csl.y : 0.0f;
 #pragma unroll
         for (int j = 0; j < RV; ++j) {
