@@ -381,7 +381,7 @@ def run_many(args, torch):
         from threadpoolctl import threadpool_limits
 
         from oracle import oracle as orc
-        sample = list(range(0, len(probs), len(probs) // 24))[:24]  # about 10 s of oracle work
+        sample = list(range(0, len(probs), len(probs) // 40))[:40]  # about 10 s of oracle work
         n_cpu = 50
         _log(f"oracle leg ({len(sample)} instances x {n_cpu} iterations)")
         cpu_s = 0.0
