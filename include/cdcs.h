@@ -353,7 +353,7 @@ cdcs_status cdcs_admm_solve_timed(cdcs_handle *h, const cdcs_state *st, const cd
 /*
  * Instrumentation: enqueue `reps` back-to-back launches of one kernel of an
  * iteration of the given form, with the arguments it has inside
- * cdcs_admm_solve on this state (y, blk, lam, v are updated as by those
+ * cdcs_admm_solve on this state (y, blk, lam, v, vw are updated as by those
  * launches).  The x these launches read and write is the handle's own copy of
  * the iterate, which equals st->x after a cdcs_admm_solve or cdcs_admm_step
  * on this state; st->x itself is neither read nor written, so nothing but the
