@@ -543,9 +543,12 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
                 const float app = LF(cur, bd), apq = LF(cur, 2 * PL + bd), aqq = LF(cur, 3 * PL + bd);
                 float ta = 0.0f;
                 if (fabsf(apq) > 1e-30f) {  // entries are scaled to max |a| ~ 1
+                    // hardware rcp / sqrt / rsq (about 1 ulp): the step needs
+                    // c^2 + s^2 = 1 to rounding, which c = rsq(1 + t^2) and
+                    // s = t c give for any t, not a correctly rounded t
                     const float tau = 0.5f * (aqq - app) * __builtin_amdgcn_rcpf(apq);
-                    const float t =
-                        copysignf(__builtin_amdgcn_rcpf(fabsf(tau) + __builtin_sqrtf(1.0f + tau * tau)), tau);
+                    const float t = copysignf(
+                        __builtin_amdgcn_rcpf(fabsf(tau) + __builtin_amdgcn_sqrtf(1.0f + tau * tau)), tau);
                     c = __builtin_amdgcn_rsqf(1.0f + t * t);
                     s = t * c;
                     ta = t * apq;
