@@ -780,6 +780,7 @@ ProjArgs proj_args(const cdcs_handle *h, int mode, const cdcs_state *st, double 
         a.v = st->v;
     }
     a.rho = rho;
+    a.inv_rho = 1.0 / rho;
     a.kinst = d.batch ? d.batch->kinst : nullptr;
     a.istop = d.batch ? d.batch->istop : nullptr;
     a.vwarm = (st && st->vw) ? st->vw : d.vwarm;

@@ -54,6 +54,7 @@ struct ProjArgs {
     float *lam;                // [nslots]
     const float *v;            // [nslots]
     double rho;
+    double inv_rho;            // 1 / rho (computed on the host: one FP64 multiply per slot, not a divide)
     const int32_t *kinst;      // [*] instance of each block (many-SDP handles), or NULL
     const int32_t *istop;      // [nprob] per-instance stop flags, or NULL
     float *vwarm;              // eigenvector warm start, NULL: cold

@@ -97,7 +97,7 @@ __device__ __forceinline__ float block_max(float v, float *red) {
 
 // Row a of the packed lower-triangular slot s = a(a+1)/2 + b.
 __device__ __forceinline__ int tri_row(int s) {
-    int a = (int)((sqrtf(8.0f * (float)s + 1.0f) - 1.0f) * 0.5f);
+    int a = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)s + 1.0f) - 1.0f) * 0.5f);  // the loops below make it exact
     while ((a + 1) * (a + 2) / 2 <= s) ++a;
     while (a * (a + 1) / 2 > s) --a;
     return a;
@@ -387,9 +387,9 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
                 w[u] = a.Win[g];
             } else if (a.mode == PROJ_PRIMAL) {
                 const double hx = a.x[a.gather[g]];
-                w[u] = (float)(hx - (double)a.lam[g] / a.rho);
+                w[u] = (float)(hx - (double)a.lam[g] * a.inv_rho);
             } else {
-                w[u] = (float)((double)a.v[g] - (double)a.lam[g] / a.rho);
+                w[u] = (float)((double)a.v[g] - (double)a.lam[g] * a.inv_rho);
             }
         }
 #pragma unroll
