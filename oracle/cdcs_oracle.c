@@ -17,6 +17,10 @@
  *     the KKT systems (E:OptCondMinYPrimal) and (E:OptCondMinYDual)).
  *
  * All matrices are dense, row-major, double precision.
+ * Threads (OpenMP): the batch entry points project independent cliques
+ * concurrently and the Cholesky factorisation computes the rows below each
+ * pivot concurrently; every output element is still computed by one thread
+ * in the sequential order, so the results do not depend on the thread count.
  * Status codes: 0 ok, 1 bad argument, 3 non-positive pivot (rank),
  *               7 sweep cap reached without convergence.
  */
@@ -150,10 +154,14 @@ int oracle_psd_project_batch(int nb, const int64_t *sizes, const int64_t *offset
                              const double *W, double *P, int *status)
 {
     int first = OR_OK;
+    #pragma omp parallel for schedule(dynamic, 1)
     for (int t = 0; t < nb; ++t) {
         int st = oracle_psd_project((int)sizes[t], W + offsets[t], P + offsets[t], NULL, NULL);
         if (status) status[t] = st;
-        if (st != OR_OK && first == OR_OK) first = st;
+        if (st != OR_OK) {
+            #pragma omp critical
+            if (first == OR_OK) first = st;
+        }
     }
     return first;
 }
@@ -165,10 +173,14 @@ int oracle_psd_project_batch_eig(int nb, const int64_t *sizes, const int64_t *of
                                  double *evals, double *V)
 {
     int first = OR_OK;
+    #pragma omp parallel for schedule(dynamic, 1)
     for (int t = 0; t < nb; ++t) {
         int st = oracle_psd_project((int)sizes[t], W + offsets[t], P + offsets[t],
                                     evals + eoffsets[t], V + offsets[t]);
-        if (st != OR_OK && first == OR_OK) first = st;
+        if (st != OR_OK) {
+            #pragma omp critical
+            if (first == OR_OK) first = st;
+        }
     }
     return first;
 }
@@ -191,6 +203,7 @@ int oracle_cholesky(int m, const double *M, double *L)
         if (!(s > ldexp(M[(size_t)j * m + j], -40))) return OR_E_RANK;
         double ljj = sqrt(s);
         L[(size_t)j * m + j] = ljj;
+        #pragma omp parallel for schedule(static)
         for (int i = j + 1; i < m; ++i) {
             const double *Li = L + (size_t)i * m;
             double t = M[(size_t)i * m + j];
