@@ -9,8 +9,11 @@ standing in for the paper's block-arrow benchmark), rho = 1, Algorithm 1.
 
 A step is one ADMM iteration (scatter -> affine projection -> batched PSD
 projection with multiplier epilogue -> residuals), replayed from captured
-HIP graphs of 50 iterations.  The timed region runs exactly --steps
-iterations with the early exit disabled, on inputs already resident in HBM.
+HIP graphs of 50 iterations (the last graph holds the remaining steps mod 50).
+The --warmup iterations run first through graphs of the same size on the same
+state; the graphs of the timed solve are captured before the timer starts
+(cdcs_admm_prepare), so the timed region holds exactly --steps launched
+iterations, with the early exit disabled, on inputs already resident in HBM.
 A separate cold-start solve reports the iterations needed for
 max(eps_p, eps_d) <= 1e-4.  Per-kernel durations (and the roofline figure)
 are averages over the timed iterations themselves: they are run again from a
@@ -18,13 +21,25 @@ copy of their starting state with eager launches and HIP events around every
 kernel; the JSON line reports whether the replay ended on the timed run's iterate
 bit for bit (kernels_replay_bitwise).
 
-Other workloads (each prints its own JSON line; not part of the default run):
+cpu_baseline is the oracle (FP64, test infrastructure) on the host cores:
+one thread and all threads of the process's CPU share (OpenMP over cliques,
+threaded BLAS), with the CPU model and os.cpu_count() recorded; its parity
+record compares the GPU iterates with the oracle's after 50 and after the
+sampled number of iterations.
+
+The default line (C2 headline) also carries two sub-objects measured in the
+same run, with the same --steps/--warmup:
   c3  uneven cliques: clique tree of 3000 cliques of 4..96 vertices with
-      separators of 1..8, m = 8000 sparse constraints (20 coefficients each);
-  c4  512 independent block-arrow SDPs in one handle, per-instance stopping,
-      p50/p99 of the per-instance time to tolerance;
-  c5  gradient of <C, X_K> through K = 100 unrolled iterations (l = 100,
-      d = 16, h = 8, m = 800) with per-iteration checkpointing.
+      separators of 1..8, m = 8000 sparse constraints (20 coefficients each):
+      iterations/s, scatter GB/s against the method's bytes, batched vs plain
+      projection, and 50-iteration parity against the oracle-written golden
+      (tests/golden/c3_iter50.json);
+  c4  512 independent block-arrow SDPs in one handle: iterations/s,
+      per-instance p50/p99 time to tolerance, batched vs plain, and
+      50-iteration parity against the oracle on sampled instances.
+--only-headline skips them.  --workload c3|c4|c5 prints a full line for one
+workload (c5: gradient of <C, X_K> through K = 100 unrolled iterations,
+l = 100, d = 16, h = 8, m = 800, with per-iteration checkpointing).
 
 --gpus N with N > 1 exits: this build runs on one GPU.
 """
@@ -126,24 +141,32 @@ def replay_kernel_ms(torch, sol, start, final, form, rho, K):
 
 
 def batched_vs_plain(torch, sol, state, rho):
-    """The batched projection (one launch per size bucket) against the
-    clique-per-launch form on the same clique matrices W_k = x_k - lam_k / rho."""
+    """Clique projections/s of the batched form against the clique-per-launch
+    form, both on the same clique matrices W_k = x_k - lam_k / rho and both
+    from a cold start (Jacobi from the identity).  Batched: the handle's tuned
+    plan (one persistent work-queue launch, or one launch per size bucket),
+    cdcs_psd_project_cliques.  Plain: the same projection kernel launched
+    once per clique with a one-workgroup grid of that clique's own size
+    bucket, no graph."""
     import numpy as np
     from paper_1609_06068_amd import cdcs
-    sizes_h = sol.sizes
+    sizes_h = np.asarray(sol.sizes, dtype=np.int64)
     sizes_d = torch.as_tensor(sizes_h.astype(np.int32), device="cuda")
     off_d = torch.as_tensor(sol.offsets, device="cuda")
     Wp = (state["blk"] - state["lam"] / rho).contiguous()
-    smax = int(sizes_h.max())
-    P1 = cdcs.psd_project_batched(Wp, sizes_d, off_d, smax=smax)
-    t_batched = time_events(torch, lambda: cdcs.psd_project_batched(Wp, sizes_d, off_d, smax=smax), reps_outer=10)
-    P2 = cdcs.psd_project_plain(Wp, sizes_d, off_d, smax)
-    t_plain = time_events(torch, lambda: cdcs.psd_project_plain(Wp, sizes_d, off_d, smax, P=P2), reps_outer=3)
-    assert torch.equal(P1, P2), "plain and batched projections differ"
-    _log(f"projection batched {t_batched:.3f}ms vs plain {t_plain:.3f}ms ({t_plain / t_batched:.1f}x)")
+    P1 = sol.project_cliques(Wp)
+    t_batched = time_events(torch, lambda: sol.project_cliques(Wp, P=P1), reps_outer=10)
+    P2 = cdcs.psd_project_plain(Wp, sizes_d, off_d, sizes_h)
+    t_plain = time_events(torch, lambda: cdcs.psd_project_plain(Wp, sizes_d, off_d, sizes_h, P=P2), reps_outer=3)
+    diff = float(torch.linalg.norm((P1 - P2).double()) / torch.linalg.norm(Wp.double()))
+    _log(f"projection batched {t_batched:.3f}ms vs plain {t_plain:.3f}ms ({t_plain / t_batched:.1f}x), "
+         f"|P_batched - P_plain| / |W| = {diff:.2e}")
     return {"batched_clique_proj_per_s": sol.p / (t_batched * 1e-3),
             "plain_clique_proj_per_s": sol.p / (t_plain * 1e-3),
-            "batched_ms": t_batched, "plain_ms": t_plain, "speedup": t_plain / t_batched}
+            "batched_ms": t_batched, "plain_ms": t_plain, "speedup": t_plain / t_batched,
+            "batched_form": "tuned plan (cdcs_psd_project_cliques), cold start",
+            "plain_form": "one launch per clique at its own size bucket, cold start",
+            "rel_diff_batched_plain": diff}
 
 
 def roofline_for(kern_ms, abytes, sizes, traffic_file):
@@ -151,12 +174,7 @@ def roofline_for(kern_ms, abytes, sizes, traffic_file):
     is its counter-measured HBM bytes per launch while the counters were taken
     on the current kernel sources."""
     dom = max(kern_ms, key=lambda n: kern_ms[n])
-    traffic = None
-    if traffic_file and os.path.exists(traffic_file):
-        with open(traffic_file) as fh:
-            tj = json.load(fh)
-        if tj.get("source_hash") == kernel_source_hash() and dom in tj.get("kernels", {}):
-            traffic = tj["kernels"][dom]["bytes_per_launch"]
+    traffic = counter_bytes(traffic_file, dom)
     if dom == "project":
         fl = projection_model_flops(sizes)
         ach = fl / (kern_ms[dom] * 1e-3) / 1e12
@@ -169,12 +187,134 @@ def roofline_for(kern_ms, abytes, sizes, traffic_file):
             "avg_us": kern_ms[dom] * 1e3}
 
 
+def counter_bytes(traffic_file, kernel):
+    """HBM bytes per launch of `kernel` from the counter summary, or None when
+    the summary was taken on other kernel sources."""
+    if not traffic_file or not os.path.exists(traffic_file):
+        return None
+    with open(traffic_file) as fh:
+        tj = json.load(fh)
+    if tj.get("source_hash") == kernel_source_hash() and kernel in tj.get("kernels", {}):
+        return tj["kernels"][kernel]["bytes_per_launch"]
+    return None
+
+
 def base_result(value, unit, K, W, ms_per_step, workload, extra_config=None):
     cfg = {"workload": workload}
     cfg.update(extra_config or {})
     return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": K, "warmup": W,
             "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f32 eig + f64 affine", "data": "synthetic", "config": cfg}
+
+
+# --------------------------------------------------------------------------
+# The oracle on the host cores (cpu_baseline)
+# --------------------------------------------------------------------------
+
+def host_cpu():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model
+
+
+def all_threads():
+    """Threads of this process's CPU share: OMP_NUM_THREADS when it is set
+    (the GPU hosts set it to their share), else os.cpu_count()."""
+    n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return n
+
+
+def oracle_timed(fn, threads):
+    """Run fn() with `threads` BLAS and OpenMP threads; return (result, seconds)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import oracle as orc
+    orc.lib()  # loaded first, so that its OpenMP runtime is under the limit
+    with threadpool_limits(limits=threads):
+        t0 = time.perf_counter()
+        out = fn()
+        return out, time.perf_counter() - t0
+
+
+def cpu_legs(fn, units, unit, sample, fn_all=None, how="OpenMP over cliques, threaded BLAS"):
+    """cpu_baseline from one run of fn() on one thread and one on all threads
+    of the share (fn_all(threads) when given, else fn under a thread limit);
+    the all-threads run's result is returned for parity checks."""
+    _, s1 = oracle_timed(fn, 1)
+    nall = all_threads()
+    if fn_all is None:
+        res, sn = oracle_timed(fn, nall)
+    else:
+        t0 = time.perf_counter()
+        res = fn_all(nall)
+        sn = time.perf_counter() - t0
+    _log(f"oracle: {units / s1:.3f} {unit} on 1 thread, {units / sn:.3f} on {nall} threads")
+    rec = {"value": units / sn, "unit": unit, "cores": nall, "kind": "oracle",
+           "sample": f"{sample}, FP64, {nall} threads ({how}; {sn:.1f}s; one thread: {s1:.1f}s)",
+           "single_thread": {"value": units / s1, "cores": 1, "seconds": s1},
+           "cpu_model": host_cpu(), "os_cpu_count": os.cpu_count()}
+    return rec, res
+
+
+_POOL = {}
+
+
+def _pool_solve(i):
+    """Worker of the many-SDP oracle leg: one instance on one thread."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        _POOL["oracles"][i].solve("primal", rho=_POOL["rho"], max_iter=_POOL["iters"])
+    return i
+
+
+def oracle_pool_child(spec):
+    """The all-threads leg of the many-SDP oracle baseline, in a child process
+    that never touches the GPU (started by bench.py itself): the sampled
+    instances on `workers` forked processes, one thread each, the oracles
+    built before the fork so that the timed region holds the solves only.
+    Prints {"seconds": ...}."""
+    from multiprocessing import get_context
+
+    from oracle import oracle as orc
+    from paper_1609_06068_amd import synth
+    qs = [int(v) for v in spec["instances"].split(",")]
+    _POOL["oracles"] = [orc.Oracle(synth.c4(count=1, first=q)[0]) for q in qs]
+    _POOL["rho"], _POOL["iters"] = spec["rho"], spec["iters"]
+    orc.lib()
+    with get_context("fork").Pool(spec["workers"]) as pool:
+        t0 = time.perf_counter()
+        pool.map(_pool_solve, range(len(qs)), chunksize=1)
+        sec = time.perf_counter() - t0
+    print(json.dumps({"seconds": sec, "workers": spec["workers"]}), flush=True)
+
+
+def pool_leg(sample, rho, n_it, workers):
+    """Seconds of the all-threads many-SDP oracle leg (a child process)."""
+    import subprocess
+    spec = json.dumps({"instances": ",".join(str(q) for q in sample), "rho": rho, "iters": n_it,
+                       "workers": workers})
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--oracle-pool", spec],
+                       capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        raise RuntimeError(f"oracle pool leg failed: {r.stderr[-2000:]}")
+    return json.loads(r.stdout.strip().splitlines()[-1])["seconds"]
+
+
+def rel(a, b):
+    import numpy as np
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 # --------------------------------------------------------------------------
@@ -190,7 +330,62 @@ SINGLE = {
 }
 
 
-def run_single(args, torch, workload):
+def timed_solve(torch, sol, form, rho, K, W):
+    """W warm-up iterations, then exactly K timed iterations (graphs of
+    GRAPH_CHUNK iterations plus one of K mod GRAPH_CHUNK, captured before the
+    timer starts).  Returns (info, seconds, start state, end state)."""
+    stt = sol.new_state(form)
+    if W > 0:
+        sol.solve(stt, form=form, rho=rho, tol=0.0, max_iter=W, check_every=GRAPH_CHUNK)
+    sol.prepare(stt, form=form, rho=rho, tol=0.0, max_iter=K, check_every=GRAPH_CHUNK)
+    start = snapshot(stt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = sol.solve(stt, form=form, rho=rho, tol=0.0, max_iter=K, check_every=GRAPH_CHUNK)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    assert info.iters == K, info
+    return info, elapsed, start, stt
+
+
+def packed_at(sol, packed, ks, a, b):
+    """Values of packed clique blocks at (clique, row a >= column b)."""
+    import numpy as np
+    ks, a, b = (np.asarray(v, dtype=np.int64) for v in (ks, a, b))
+    return packed[sol.offsets[ks] + a * (a + 1) // 2 + b]
+
+
+def golden_parity(torch, sol, rho):
+    """50 iterations of Algorithms 1 and 2 from a cold state against the
+    oracle-written golden (sampled x entries and clique-block slots),
+    element by element: |gpu - oracle| <= 1e-4 RMS(oracle vector)."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "c3_iter50.json")
+    with open(path) as fh:
+        g = json.load(fh)
+    out = {"iterations": g["iterations"], "tol": 1e-4, "samples": len(g["entries"])}
+    ok = True
+    for form in ("primal", "dual"):
+        st = sol.new_state(form)
+        sol.solve(st, form=form, rho=rho, tol=0.0, max_iter=g["iterations"], check_every=GRAPH_CHUNK)
+        ref = g[form]
+        got = {"x": st["x"].cpu().numpy()[np.asarray(g["entries"])]}
+        for name in ("blk", "lam") + (("v",) if form == "dual" else ()):
+            got[name] = packed_at(sol, st[name].cpu().numpy().astype(np.float64), g["slots"]["clique"],
+                                  g["slots"]["a"], g["slots"]["b"])
+        rec = {}
+        for name, val in got.items():
+            r = np.asarray(ref[name])
+            worst = float(np.max(np.abs(val - r)) / (1e-4 * ref[name + "_rms"]))
+            rec[name] = {"max_err_over_tol": worst, "sampled_rel": rel(val, r)}
+            ok = ok and worst <= 1.0
+        out[form] = rec
+    out["pass"] = ok
+    _log(f"c3 golden parity at 50 iterations: {out}")
+    return out
+
+
+def run_single(args, torch, workload, nested=False):
     import numpy as np
     from paper_1609_06068_amd import cdcs, synth
     spec = SINGLE[workload]
@@ -215,16 +410,7 @@ def run_single(args, torch, workload):
 
     # Timed region: warmup, then exactly K iterations (no early exit).
     K, W = args.steps, args.warmup
-    stt = sol.new_state(form)
-    if W > 0:
-        sol.solve(stt, form=form, rho=rho, tol=0.0, max_iter=W, check_every=min(GRAPH_CHUNK, W))
-    start = snapshot(stt)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    info = sol.solve(stt, form=form, rho=rho, tol=0.0, max_iter=K, check_every=GRAPH_CHUNK)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    assert info.iters == K, info
+    info, elapsed, start, stt = timed_solve(torch, sol, form, rho, K, W)
     sweeps_per_solve = info.jacobi_sweeps / (K * sol.p)
     ips = K / elapsed
     _log(f"timed: {K} iterations in {elapsed:.4f}s -> {ips:.1f} it/s, {sweeps_per_solve:.2f} sweeps/eigensolve")
@@ -240,6 +426,18 @@ def run_single(args, torch, workload):
                          spec["desc"] + (", Alg. 1 (primal)" if form == "primal" else ", Alg. 2 (dual)") + ", rho=1",
                          {"graph_chunk": GRAPH_CHUNK, "setup_s": setup_s, "n": sol.n, "nnz": sol.nnz,
                           "p": sol.p, "m": sol.m})
+    # gather/scatter against the method's bytes: the scatter reads one 4-byte
+    # contribution per clique slot and writes one 8-byte right-hand side entry
+    # per pattern entry; the gather is fused into the projection kernel
+    if "scatter" in kern_ms:
+        sb = 4 * sol.nslots + 8 * sol.nnz
+        sgbs = sb / (kern_ms["scatter"] * 1e-3) / 1e9
+        gs = {"scatter_us": kern_ms["scatter"] * 1e3, "scatter_method_bytes": sb, "scatter_GB_s": sgbs,
+              "scatter_frac": sgbs / HBM_PEAK_GBS, "scatter_impl_bytes": abytes["scatter"],
+              "scatter_counter_bytes": counter_bytes(tfile, "scatter"),
+              "gather": "fused into the projection kernel (not timed apart)"}
+    else:
+        gs = None
     result.update({
         "clique_projections_per_s": ips * sol.p,
         "jacobi_sweeps_per_eigensolve": sweeps_per_solve,
@@ -250,41 +448,52 @@ def run_single(args, torch, workload):
         "projection_plan": tuning,
         "kernels": kern,
         "kernels_replay_bitwise": replay_same,
+        "gather_scatter": gs,
         "roofline": roofline,
     })
     if workload == "c3":
         result["projection_model_tflops"] = projection_model_flops(sol.sizes) / (kern_ms["project"] * 1e-3) / 1e12
+        if not args.profile:
+            result["parity"] = golden_parity(torch, sol, rho)
 
-    if not (args.no_cpu or args.profile):
-        from threadpoolctl import threadpool_limits
-
+    if workload == "c2" and not (args.no_cpu or args.profile):
         from oracle import oracle as orc
         n_cpu = args.cpu_iters if args.cpu_iters is not None else spec["cpu_iters"]
-        _log(f"oracle leg ({n_cpu} iterations)")
-        with threadpool_limits(limits=1):
-            t0 = time.perf_counter()
-            o = orc.Oracle(prob)
-            cpu_setup = time.perf_counter() - t0
-            t0 = time.perf_counter()
-            ref = o.solve(form, rho=rho, max_iter=n_cpu)
-            cpu_s = time.perf_counter() - t0
-        result["cpu_baseline"] = {"value": n_cpu / cpu_s, "unit": "ADMM iterations/s", "cores": 1,
-                                  "kind": "oracle",
-                                  "sample": f"first {n_cpu} iterations of the same solve, FP64, one thread "
-                                            f"({cpu_s:.1f}s; oracle setup {cpu_setup:.1f}s excluded)"}
-        # parity at the same iteration count (cold start)
+        o = orc.Oracle(prob)
+        snap = {}
+
+        def keep50(it, x, y, blocks, lam):
+            if it == 50:
+                snap.update(x=x.copy(), blocks=[B.copy() for B in blocks], lam=[B.copy() for B in lam])
+
+        _log(f"oracle legs ({n_cpu} iterations)")
+        cpu, ref = cpu_legs(lambda: o.solve(form, rho=rho, max_iter=n_cpu, callback=keep50), n_cpu,
+                            "ADMM iterations/s", f"first {n_cpu} iterations of the same solve (setup excluded)")
+        result["cpu_baseline"] = cpu
+        # parity: a cold solve of 50 iterations, continued to n_cpu (the state
+        # carries the eigenvector warm start, so this equals one solve)
+        par = {"tol": 1e-4}
         sp = sol.new_state(form)
-        sol.solve(sp, form=form, rho=rho, tol=0.0, max_iter=n_cpu, check_every=min(GRAPH_CHUNK, n_cpu))
-        xg = sp["x"].cpu().numpy()
-        lam_g = np.concatenate([B.ravel() for B in cdcs.unpack_blocks(sp["lam"].cpu().numpy().astype(np.float64),
-                                                                       sol.sizes, sol.offsets)])
-        lam_r = np.concatenate([B.ravel() for B in ref.lam])
-        result["parity"] = {"iterations": n_cpu,
-                            "x_rel": float(np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x)),
-                            "lam_rel": float(np.linalg.norm(lam_g - lam_r) / np.linalg.norm(lam_r)),
-                            "tol": 1e-4}
-        _log(f"oracle {n_cpu / cpu_s:.3f} it/s; parity {result['parity']}")
+        for n_it, r in ((50, snap), (n_cpu, {"x": ref.x, "blocks": ref.blocks, "lam": ref.lam})):
+            done = 0 if n_it == 50 else 50
+            if not r or n_it <= done:
+                continue
+            sol.solve(sp, form=form, rho=rho, tol=0.0, max_iter=n_it - done, check_every=GRAPH_CHUNK)
+            xg = sp["x"].cpu().numpy()
+            blk = sp["blk"].cpu().numpy().astype(np.float64)
+            lam = sp["lam"].cpu().numpy().astype(np.float64)
+            par[f"iter{n_it}"] = {"x_rel": rel(xg, r["x"]), "blk_rel": rel(blk, cdcs.pack_blocks(r["blocks"])),
+                                  "lam_rel": rel(lam, cdcs.pack_blocks(r["lam"]))}
+        result["parity"] = par
+        _log(f"parity {par}")
     sol.close()
+    if nested:
+        keep = ("value", "unit", "ms_per_step", "clique_projections_per_s", "jacobi_sweeps_per_eigensolve",
+                "accuracy", "batched_vs_plain", "projection_plan", "kernels", "kernels_replay_bitwise",
+                "gather_scatter", "roofline", "projection_model_tflops", "parity")
+        out = {k: result[k] for k in keep if k in result}
+        out["config"] = result["config"]
+        return out
     return result
 
 
@@ -292,7 +501,7 @@ def run_single(args, torch, workload):
 # Many SDPs in one handle (c4)
 # --------------------------------------------------------------------------
 
-def run_many(args, torch):
+def run_many(args, torch, nested=False):
     import numpy as np
     from paper_1609_06068_amd import cdcs, synth
     rho = 1.0
@@ -306,8 +515,7 @@ def run_many(args, torch):
     # cold solves to 1e-4, every instance stopping on its own
     cap = 1 if args.profile else 3000
     st = sol.new_state("primal")
-    sol.solve(st, form="primal", rho=rho, tol=1e-4, max_iter=cap, check_every=GRAPH_CHUNK)  # warm graphs
-    st = sol.new_state("primal")
+    sol.prepare(st, form="primal", rho=rho, tol=1e-4, max_iter=cap, check_every=GRAPH_CHUNK)
     acc = sol.solve(st, form="primal", rho=rho, tol=1e-4, max_iter=cap, check_every=GRAPH_CHUNK)
     torch.cuda.synchronize()
     inst = sol.instance_info()
@@ -321,16 +529,7 @@ def run_many(args, torch):
     _log(f"projection plan: {tuning}")
     # Timed region: exactly K whole-batch iterations (no early exit).
     K, W = args.steps, args.warmup
-    stt = sol.new_state("primal")
-    if W > 0:
-        sol.solve(stt, form="primal", rho=rho, tol=0.0, max_iter=W, check_every=min(GRAPH_CHUNK, W))
-    start = snapshot(stt)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    info = sol.solve(stt, form="primal", rho=rho, tol=0.0, max_iter=K, check_every=GRAPH_CHUNK)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    assert info.iters == K
+    info, elapsed, start, stt = timed_solve(torch, sol, "primal", rho, K, W)
     ips = K / elapsed
     _log(f"timed: {K} batch iterations in {elapsed:.4f}s -> {ips:.1f} it/s")
     result = base_result(ips, "ADMM iterations/s (all 512 instances)", K, W, 1e3 * elapsed / K,
@@ -358,13 +557,19 @@ def run_many(args, torch):
     a_bytes = 0
     f_bytes = 0
     for pr in probs:
-        ld = (pr.nU + 3) // 4 * 4
+        ld = (pr.nU + 31) // 32 * 32
         a_bytes += 2 * pr.m * ld * 4
         f_bytes += 2 * (pr.m * (pr.m + 1) // 2) * 8
     aff_bytes = a_bytes + f_bytes + sol.nnz * 8 * 4 + sol.m * 8 * 4
     kern["affine"]["GB_s"] = aff_bytes / (kern["affine"]["us"] * 1e-6) / 1e9
+    sb = 4 * sol.nslots + 8 * sol.nnz
+    kern["scatter"]["GB_s"] = sb / (kern["scatter"]["us"] * 1e-6) / 1e9
     result["kernels"] = kern
     result["kernels_replay_bitwise"] = replay_same
+    result["gather_scatter"] = {"scatter_us": kern["scatter"]["us"], "scatter_method_bytes": sb,
+                                "scatter_GB_s": kern["scatter"]["GB_s"],
+                                "scatter_frac": kern["scatter"]["GB_s"] / HBM_PEAK_GBS,
+                                "gather": "fused into the projection kernel (not timed apart)"}
     _log("kernels: " + ", ".join(f"{n} {v['us']:.1f}us" for n, v in kern.items()))
     if kern["affine"]["us"] >= kern["project"]["us"]:
         gbs = kern["affine"]["GB_s"]
@@ -378,25 +583,60 @@ def run_many(args, torch):
                               "unit": "TFLOP/s", "frac": ach / FP32_VALU_PEAK_TFLOPS, "traffic": None,
                               "algorithmic_flops": fl, "avg_us": kern["project"]["us"]}
     if not (args.no_cpu or args.profile):
-        from threadpoolctl import threadpool_limits
-
         from oracle import oracle as orc
-        sample = list(range(0, len(probs), len(probs) // 40))[:40]  # about 10 s of oracle work
+        sample = list(range(0, len(probs), len(probs) // 40))[:40]  # about 10 s of oracle work on one thread
         n_cpu = 50
-        _log(f"oracle leg ({len(sample)} instances x {n_cpu} iterations)")
-        cpu_s = 0.0
-        with threadpool_limits(limits=1):
-            for q in sample:
-                o = orc.Oracle(probs[q])
-                t0 = time.perf_counter()
-                o.solve("primal", rho=rho, max_iter=n_cpu)
-                cpu_s += time.perf_counter() - t0
-        per_batch_iter = cpu_s / n_cpu * len(probs) / len(sample)
-        result["cpu_baseline"] = {"value": 1.0 / per_batch_iter, "unit": "ADMM iterations/s (all 512 instances)",
-                                  "cores": 1, "kind": "oracle",
-                                  "sample": f"{n_cpu} iterations of instances {sample} ({cpu_s:.1f}s), scaled to "
-                                            f"all 512 instances, FP64, one thread"}
+        _log(f"oracle legs ({len(sample)} instances x {n_cpu} iterations)")
+        oracles = [orc.Oracle(probs[q]) for q in sample]
+        # n_cpu iterations of the sampled instances stand for n_cpu |sample| / 512
+        # iterations of the whole batch
+        units = n_cpu * len(sample) / len(probs)
+        refs, s1 = oracle_timed(lambda: [o.solve("primal", rho=rho, max_iter=n_cpu) for o in oracles], 1)
+        nall = all_threads()
+        try:
+            sn = pool_leg(sample, rho, n_cpu, nall)
+        except Exception as exc:  # the single-thread figure still stands
+            _log(f"oracle all-threads leg failed: {exc}")
+            sn = None
+        smp = f"{n_cpu} iterations of instances {sample}, scaled to all 512 instances (setup excluded), FP64"
+        if sn is not None:
+            _log(f"oracle: {units / s1:.3f} batch it/s on 1 thread, {units / sn:.3f} on {nall} processes")
+            result["cpu_baseline"] = {
+                "value": units / sn, "unit": "ADMM iterations/s (all 512 instances)", "cores": nall,
+                "kind": "oracle",
+                "sample": f"{smp}, {nall} processes of one thread each ({sn:.1f}s; one thread: {s1:.1f}s)",
+                "single_thread": {"value": units / s1, "cores": 1, "seconds": s1},
+                "cpu_model": host_cpu(), "os_cpu_count": os.cpu_count()}
+        else:
+            result["cpu_baseline"] = {
+                "value": units / s1, "unit": "ADMM iterations/s (all 512 instances)", "cores": 1,
+                "kind": "oracle", "sample": f"{smp}, one thread ({s1:.1f}s)",
+                "cpu_model": host_cpu(), "os_cpu_count": os.cpu_count()}
+        # parity: the batch after 50 iterations from a cold state, per sampled instance
+        sp = sol.new_state("primal")
+        sol.solve(sp, form="primal", rho=rho, tol=0.0, max_iter=n_cpu, check_every=GRAPH_CHUNK)
+        xg = sp["x"].cpu().numpy()
+        blk = sp["blk"].cpu().numpy().astype(np.float64)
+        lam = sp["lam"].cpu().numpy().astype(np.float64)
+        worst = {"x_rel": 0.0, "blk_rel": 0.0, "lam_rel": 0.0}
+        for q, r in zip(sample, refs):
+            e0, e1 = sol.entry_off[q], sol.entry_off[q + 1]
+            k0, k1 = sol.clique_off[q], sol.clique_off[q + 1]
+            o0, o1 = sol.offsets[k0], sol.offsets[k1]
+            worst["x_rel"] = max(worst["x_rel"], rel(xg[e0:e1], r.x))
+            worst["blk_rel"] = max(worst["blk_rel"], rel(blk[o0:o1], cdcs.pack_blocks(r.blocks)))
+            worst["lam_rel"] = max(worst["lam_rel"], rel(lam[o0:o1], cdcs.pack_blocks(r.lam)))
+        result["parity"] = {"iterations": n_cpu, "instances": sample, "worst": worst, "tol": 1e-4,
+                            "pass": max(worst.values()) <= 1e-4}
+        _log(f"c4 parity at {n_cpu} iterations: {result['parity']['worst']}")
     sol.close()
+    if nested:
+        keep = ("value", "unit", "ms_per_step", "clique_projections_per_s", "instance_iterations_per_s",
+                "accuracy", "batched_vs_plain", "projection_plan", "kernels", "kernels_replay_bitwise",
+                "gather_scatter", "roofline", "cpu_baseline", "parity")
+        out = {k: result[k] for k in keep if k in result}
+        out["config"] = result["config"]
+        return out
     return result
 
 
@@ -415,7 +655,7 @@ def run_grad(args, torch):
     def fwd_bwd():
         c = torch.as_tensor(prob.c, device="cuda").requires_grad_(True)
         b = torch.as_tensor(prob.b, device="cuda").requires_grad_(True)
-        x = ag.unrolled_x(sol, prob, c, b, K=Kun, rho=1.0, use_checkpoint=True)
+        x = ag.unrolled_x(sol, c, b, K=Kun, rho=1.0)
         L = (w * c * x).sum()
         L.backward()
         return c.grad, b.grad
@@ -473,7 +713,13 @@ def main():
     ap.add_argument("--print-hash", action="store_true", help="print the kernel source hash and exit")
     ap.add_argument("--profile", action="store_true",
                     help="profiler runs: skip the accuracy solve, the plain-form comparison and the oracle")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="default workload without the c3 and c4 sub-objects")
+    ap.add_argument("--oracle-pool", default=None, help=argparse.SUPPRESS)  # internal: the c4 oracle child
     args = ap.parse_args()
+    if args.oracle_pool is not None:
+        oracle_pool_child(json.loads(args.oracle_pool))
+        return
     if args.print_hash:
         print(kernel_source_hash())
         return
@@ -496,6 +742,9 @@ def main():
         del xp, yp
     if args.workload in SINGLE:
         result = run_single(args, torch, args.workload)
+        if args.workload == "c2" and not (args.only_headline or args.profile):
+            result["c3"] = run_single(args, torch, "c3", nested=True)
+            result["c4"] = run_many(args, torch, nested=True)
     elif args.workload == "c4":
         result = run_many(args, torch)
     else:

@@ -26,7 +26,9 @@
  * Cliques.  p cliques as a CSR (ptr[p+1], vert[]), vertices strictly
  * increasing inside a clique (the natural order of Sec. II-B).  The pattern
  * must equal the union of C_k x C_k (lower triangles).  Clique sizes are
- * limited to 1..CDCS_MAX_CLIQUE.
+ * limited to 1..CDCS_MAX_CLIQUE.  cdcs_setup without cliques computes a
+ * chordal extension of the pattern and its maximal cliques itself
+ * (cdcs_chordal_extension).
  *
  * Packed clique blocks.  Per-clique matrices (x_k, z_k, v_k, lambda_k, W_k,
  * P(W_k)) are stored as packed lower triangles, row-major: element (a, b),
@@ -69,7 +71,7 @@ typedef enum {
     CDCS_E_DEVICE = 4,         /* HIP runtime failure */
     CDCS_E_NOMEM = 5,          /* device allocation failed */
     CDCS_E_NOT_CONVERGED = 6,  /* iteration cap reached; results are written */
-    CDCS_E_NUMERIC = 7         /* an eigensolve hit its sweep cap, or NaN/Inf */
+    CDCS_E_NUMERIC = 7         /* an eigensolve hit its sweep cap, or NaN/Inf in the iterate */
 } cdcs_status;
 
 typedef enum { CDCS_PRIMAL = 0, /* Algorithm 1 */ CDCS_DUAL = 1 /* Algorithm 2 */ } cdcs_form;
@@ -170,8 +172,32 @@ typedef struct {
 } cdcs_sizes;
 
 /*
- * Setup (Algorithms 1/2, "Setup: Chordal decomposition, KKT factorization").
- * Validates the pattern and cliques, builds the entry selectors H_k and the
+ * Chordal extension of an arbitrary aggregate pattern and its maximal cliques
+ * (Sec. II-A, Definition 1; finding a minimum-fill extension is NP-complete,
+ * so a heuristic is used): the graph of the pattern (vertices that occur in
+ * an entry, edges the off-diagonal entries) is tested for chordality by
+ * maximum cardinality search; a chordal graph is kept as it is, any other is
+ * filled by minimum-degree elimination (smallest label on ties).  The maximal
+ * cliques come from the resulting perfect elimination ordering, in that
+ * order, each with its vertices sorted.  Deterministic.
+ *   pattern: as for cdcs_setup.  Outputs (host): nfill added entries
+ *   (fill_i[e] >= fill_j[e], not in the pattern), p cliques with nvert
+ *   vertices in all (clique_ptr [p+1], clique_vert [nvert]).  Call once with
+ *   NULL arrays for the sizes, then with arrays of those sizes (any NULL
+ *   array is skipped).
+ * cdcs_setup with cliques = NULL runs this and appends the fill entries to
+ * the caller's entries, with zero values of C and of every A_i on them: the
+ * handle's global vectors then have nnz + nfill entries, the caller's first
+ * (so x[0 .. nnz) is X on the caller's pattern and x beyond it is the
+ * positive semidefinite completion's value on the fill).
+ * Errors: CDCS_E_ARG, CDCS_E_PATTERN (entry out of range, duplicate).
+ */
+cdcs_status cdcs_chordal_extension(const cdcs_pattern *pattern, int64_t *nfill, int32_t *p, int64_t *nvert,
+                                   int32_t *fill_i, int32_t *fill_j, int64_t *clique_ptr, int32_t *clique_vert);
+
+/*
+ * Setup step of Algorithms 1 and 2: the chordal decomposition data and the
+ * cached factor of the KKT system (Sec. III-B.1).  Validates the pattern and cliques, builds the entry selectors H_k and the
  * overlap counts D = sum_k H_k^T H_k (Sec. III-B.1), uploads the data, forms
  * M = A diag(w/D) A^T on the device in FP64 and factors it (Cholesky), caching
  * the inverse triangular factor for the affine projection (as CSR when L^-1
@@ -179,6 +205,10 @@ typedef struct {
  * launch forms of the batched projection (cdcs_get_tuning).
  *   b [m] host FP64, c [nnz] host FP64 (values of C on the entries).
  *   opts may be NULL (rho = 1).  The cached factor does not depend on rho.
+ *   cliques may be NULL: the pattern is then extended to a chordal one and
+ *   its maximal cliques found (cdcs_chordal_extension); the fill entries
+ *   follow the caller's (dense A is read as m x nnz for the caller's nnz).
+ *   A clique above CDCS_MAX_CLIQUE is rejected with CDCS_E_ARG.
  * Errors: CDCS_E_ARG, CDCS_E_PATTERN (unsorted/duplicate clique vertex, clique
  * pair missing from the pattern, entry in no clique, index out of range),
  * CDCS_E_RANK (A not of full row rank), CDCS_E_NOMEM, CDCS_E_DEVICE.
@@ -259,6 +289,17 @@ cdcs_status cdcs_psd_project_batched(int32_t nb, int32_t smax, const int32_t *si
                                      float *evecs, const int64_t *voff, hipStream_t stream);
 
 /*
+ * The same projection for the cliques of a handle, launched with the handle's
+ * tuned plan (cdcs_get_tuning: one persistent work-queue launch or one launch
+ * per size bucket), as inside cdcs_admm_solve but on given blocks and from a
+ * cold start (Jacobi from the identity, no eigenvector warm start).
+ *   W, P [nslots] device FP32 packed clique blocks (cdcs_clique_offsets), no
+ *        aliasing.  Accuracy as cdcs_psd_project_batched without eigenpairs.
+ * Errors: CDCS_E_ARG (NULL argument), CDCS_E_DEVICE.
+ */
+cdcs_status cdcs_psd_project_cliques(cdcs_handle *h, const float *W, float *P, hipStream_t stream);
+
+/*
  * Adjoint of the batched projection, for differentiating through
  * (E:XkUpdate) / (E:zkUpdate): given the eigenpairs written by
  * cdcs_psd_project_batched (evals, evecs with the same eoff/voff) and the
@@ -304,13 +345,29 @@ cdcs_status cdcs_affine_project(const cdcs_handle *h, const double *r1, const do
  *   Alg. 2: eps_p = ||z_k - v_k|| / max(||z_k||, ||v_k||),
  *           eps_d = rho ||v_k - v_k_prev|| / ||lambda_k||.
  * With check_every > 0, check_every iterations are captured in one HIP graph
- * and replayed; every kernel of an iteration after convergence returns at
- * once.  Synchronises on stream.  Returns CDCS_OK when converged (or when
- * tol = 0 and max_iter iterations ran), CDCS_E_NOT_CONVERGED at the cap,
- * CDCS_E_NUMERIC if an eigensolve hit its sweep cap.  info may be NULL.
+ * and replayed (a last graph holds the max_iter % check_every remaining
+ * iterations, so exactly max_iter iterations are launched); every kernel of
+ * an iteration after convergence returns at once.  Synchronises on stream.
+ * Returns CDCS_OK when converged (or when tol = 0 and max_iter iterations
+ * ran), CDCS_E_NOT_CONVERGED at the cap, CDCS_E_NUMERIC if an eigensolve hit
+ * its sweep cap or a residual is not finite (a NaN or Inf in the state or
+ * the data reaches the residual sums within one iteration; the solve stops
+ * there, on a batch handle the instance stops).  info may be NULL.
  */
 cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st, const cdcs_options *opts,
                             cdcs_info *info, hipStream_t stream);
+
+/*
+ * Capture and instantiate, without running any iteration, the HIP graphs that
+ * cdcs_admm_solve with the same handle, state buffers and options launches
+ * (max_iter / check_every graphs of check_every iterations, then one graph of
+ * the remaining max_iter % check_every iterations), so that the solve itself
+ * spends no time on capture.  Nothing is enqueued on `stream`; the state is
+ * not read.  check_every = 0 (eager launches) is a no-op.
+ * Errors: as cdcs_admm_solve's argument checks; CDCS_E_DEVICE.
+ */
+cdcs_status cdcs_admm_prepare(cdcs_handle *h, const cdcs_state *st, const cdcs_options *opts,
+                              hipStream_t stream);
 
 /* Write identity blocks into a caller's warm-start buffer (cdcs_state.vw,
  * nwarm floats, device memory) on `stream`: the basis a new state starts
@@ -321,6 +378,52 @@ cdcs_status cdcs_warm_reset(const cdcs_handle *h, float *vw, hipStream_t stream)
  * cdcs_admm_solve with max_iter = 1, tol = 0, check_every = 0. */
 cdcs_status cdcs_admm_step(cdcs_handle *h, const cdcs_state *st, int32_t form, double rho,
                            hipStream_t stream);
+
+/*
+ * Differentiation through unrolled iterations (not in the paper: the
+ * adjoint of the map (c, b) -> x after K iterations of Algorithm 1).
+ *
+ * cdcs_unrolled_step: one iteration of Algorithm 1 on the caller's state,
+ * exactly as cdcs_admm_step (primal form) runs it, but with the cost c
+ * [nnz, pattern order] and right-hand side b [m] taken from the caller's
+ * device buffers (FP64) instead of the handle's data, and writing the
+ * eigenpairs of every clique's projection (E:XkUpdate): evals [sum_k s_k]
+ * (clique k at the prefix sum of s_j, j < k) and evecs [nwarm] (k x k
+ * row-major, eigenvectors in columns, offsets the prefix sums of s_k^2), FP32
+ * device buffers, each may be NULL.  With c and b equal to the handle's data
+ * the new state equals cdcs_admm_step's bit for bit.  The eigenvectors are
+ * those the state's warm start (vw) keeps; give the state a vw buffer, or
+ * every step restarts Jacobi from the identity.
+ *
+ * cdcs_unrolled_step_vjp: its adjoint.  Inputs: the step's saved evals and
+ * evecs; the cotangents of the step's outputs: xbar [nnz, pattern order] of
+ * its x (NULL: zero), blkbar and lambar [nslots] FP64 of its x_k and
+ * lambda_k (packed coordinates: the derivative with respect to each packed
+ * value; an off-diagonal value stands for both mirrored entries).  Outputs:
+ * blkbar and lambar are overwritten with the cotangents of the step's input
+ * x_k and lambda_k; cbar [nnz, pattern order] and bbar [m] accumulate the
+ * cotangents of c and b.  The projection's adjoint is the Daleckii-Krein
+ * form of cdcs_psd_project_vjp (FP32); the affine adjoint is the cached
+ * KKT solve applied to the cotangent (FP64): for x = F(r1, b),
+ * rbar1 = w F(xbar / w, 0) and bbar is that solve's y.
+ *
+ * cdcs_affine_project_adjoint: the affine part alone, for
+ * x = cdcs_affine_project(r1, r2): r1bar [nnz] = w F(xbar / w, 0) and
+ * r2bar [m] = that solve's y (both overwritten; pattern order).
+ *
+ * All buffers are device memory; no aliasing between outputs and inputs
+ * except as stated.  The handle allocates its work buffers at the first call.
+ * Errors: CDCS_E_ARG (NULL argument, rho <= 0, a batch handle for the
+ * unrolled step), CDCS_E_NOMEM, CDCS_E_DEVICE; cdcs_unrolled_step returns
+ * cdcs_admm_step's status.
+ */
+cdcs_status cdcs_unrolled_step(cdcs_handle *h, const cdcs_state *st, const double *c, const double *b, double rho,
+                               float *evals, float *evecs, hipStream_t stream);
+cdcs_status cdcs_unrolled_step_vjp(cdcs_handle *h, double rho, const float *evals, const float *evecs,
+                                   const double *xbar, double *blkbar, double *lambar, double *cbar, double *bbar,
+                                   hipStream_t stream);
+cdcs_status cdcs_affine_project_adjoint(cdcs_handle *h, const double *xbar, double *r1bar, double *r2bar,
+                                        hipStream_t stream);
 
 /* Kernels of one iteration, for cdcs_profile_kernel. */
 typedef enum {
@@ -391,14 +494,16 @@ typedef struct {
 cdcs_status cdcs_get_tuning(const cdcs_handle *h, cdcs_tuning *out);
 
 /*
- * Override the tuned plan: persistent = 1 with threads 256 or 512, or
- * persistent = 0 with threads 64, 256 or 512 for every bucket that has that
- * size built (64: buckets 16 and 32 only, the others keep 256; 256 and 512: every bucket), or 0
- * to keep the tuned per-bucket sizes.
- * Synchronizes the device and drops captured graphs.  Errors: CDCS_E_ARG,
- * CDCS_E_DEVICE.
+ * Override the tuned plan: persistent = 1 with threads 256 or 512 and `grid`
+ * workgroups (0: as many as stay resident, at most one per clique; a smaller
+ * grid makes every workgroup project several cliques), or persistent = 0 with
+ * threads 64, 256 or 512 for every bucket that has that size built (64:
+ * buckets 16 and 32 only, the others keep 256; 256 and 512: every bucket),
+ * or 0 to keep the tuned per-bucket sizes (grid is ignored).
+ * Synchronizes the device and drops captured graphs.  Errors: CDCS_E_ARG
+ * (also for a grid above the resident workgroups), CDCS_E_DEVICE.
  */
-cdcs_status cdcs_set_projection_plan(cdcs_handle *h, int32_t persistent, int32_t threads);
+cdcs_status cdcs_set_projection_plan(cdcs_handle *h, int32_t persistent, int32_t threads, int32_t grid);
 
 /* Residual history of the last solve: n_host pairs (eps_p, eps_d), host. */
 cdcs_status cdcs_residual_history(const cdcs_handle *h, double *hist_host, int32_t n_host);

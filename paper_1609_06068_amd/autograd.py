@@ -1,25 +1,68 @@
-"""Differentiable building blocks over the gfx950 library (torch.autograd).
+"""Differentiable entry points over the gfx950 library (torch.autograd).
 
-Each Function's forward and backward call library kernels: the batched PSD
-projection and its Daleckii-Krein adjoint, the entry selectors H_k (gather)
-and sum_k H_k^T (scatter), which are each other's transposes, and the affine
-projection.  The affine map x = F(r1, b) of the KKT system
-(E:OptCondMinYPrimal) satisfies (dF/dr1)^T = W (dF/dr1) W^-1 with W = diag(w)
-(w = 1 on diagonal entries, 2 off-diagonal), and (dF/db)^T xbar is the y of
-that same solve, so its adjoint is the cached-factor solve applied to the
-cotangent.
+Every forward and backward is a library call; PyTorch only supplies device
+memory, the stream and the autograd bookkeeping.
 
-`unrolled_x` runs K iterations of Algorithm 1 from zero state as a function of
-(c, b) with per-iteration checkpointing (only the state entering each
-iteration is kept; the backward recomputes one iteration at a time).
+* `UnrolledADMM` / `unrolled_x`: x after K iterations of Algorithm 1 from
+  zero state as a function of (c, b).  The forward runs the library's own
+  iteration (cdcs_unrolled_step: the kernels of cdcs_admm_step, with the
+  caller's c and b) and keeps, per iteration, the eigenpairs of every
+  clique's projection (the per-iteration checkpoint: the adjoint of an
+  iteration needs nothing else, since the rest of the iteration is linear).
+  The backward runs the library's adjoint of one iteration
+  (cdcs_unrolled_step_vjp: Daleckii-Krein adjoint of the projection, the
+  gather/scatter transposes and the cached KKT solve) from the last
+  iteration to the first.
+* `PSDProject`: P(W_k) for packed FP32 clique blocks, backward by
+  cdcs_psd_project_vjp.
+* `Gather` / `Scatter`: the entry selectors H_k and sum_k H_k^T, each other's
+  transposes.
+* `Affine`: x = F(r1, b) of the KKT system (E:OptCondMinYPrimal), backward by
+  cdcs_affine_project_adjoint.
 """
 from __future__ import annotations
 
 import numpy as np
 import torch
-from torch.utils.checkpoint import checkpoint
 
 from . import cdcs
+
+
+class UnrolledADMM(torch.autograd.Function):
+    """x_K(c, b) of K Algorithm-1 iterations from zero state."""
+
+    @staticmethod
+    def forward(ctx, c, b, sol, K, rho):
+        st = sol.new_state("primal")
+        c = c.detach().contiguous()
+        b = b.detach().contiguous()
+        evals = torch.empty((K, sol.nevals), dtype=torch.float32, device=c.device)
+        evecs = torch.empty((K, sol.nwarm), dtype=torch.float32, device=c.device)
+        for n in range(K):
+            sol.unrolled_step(st, c, b, rho, evals[n], evecs[n])
+        ctx.save_for_backward(evals, evecs)
+        ctx.sol, ctx.K, ctx.rho = sol, K, rho
+        return st["x"]
+
+    @staticmethod
+    def backward(ctx, xbar):
+        evals, evecs = ctx.saved_tensors
+        sol, K, rho = ctx.sol, ctx.K, ctx.rho
+        dev = xbar.device
+        cbar = torch.zeros(sol.nnz, dtype=torch.float64, device=dev)
+        bbar = torch.zeros(sol.m, dtype=torch.float64, device=dev)
+        blkbar = torch.zeros(sol.nslots, dtype=torch.float64, device=dev)
+        lambar = torch.zeros(sol.nslots, dtype=torch.float64, device=dev)
+        xbar = xbar.contiguous().to(torch.float64)
+        for n in range(K - 1, -1, -1):
+            sol.unrolled_step_vjp(evals[n], evecs[n], xbar if n == K - 1 else None, blkbar, lambar, cbar, bbar,
+                                  rho=rho)
+        return cbar, bbar, None, None, None
+
+
+def unrolled_x(sol, c, b, K: int, rho: float = 1.0):
+    """x after K iterations of Algorithm 1 from zero state, differentiable in (c, b)."""
+    return UnrolledADMM.apply(c, b, sol, K, rho)
 
 
 class PSDProject(torch.autograd.Function):
@@ -36,7 +79,7 @@ class PSDProject(torch.autograd.Function):
     def backward(ctx, gP):
         ev, V, eoff, voff = ctx.saved_tensors
         g = ctx.geo
-        gW = cdcs.psd_project_vjp(gP.float(), ev, V, eoff, voff, g["sizes_d"], g["off_d"], g["smax"])
+        gW = cdcs.psd_project_vjp(gP.contiguous(), ev, V, eoff, voff, g["sizes_d"], g["off_d"], g["smax"])
         return gW, None
 
 
@@ -50,7 +93,7 @@ class Gather(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        return ctx.sol.scatter(g.double()), None
+        return ctx.sol.scatter(g), None
 
 
 class Scatter(torch.autograd.Function):
@@ -63,24 +106,22 @@ class Scatter(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        return ctx.sol.gather(g.double()), None
+        return ctx.sol.gather(g), None
 
 
 class Affine(torch.autograd.Function):
     """x = F(r1, b): the x part of the KKT solve with right-hand side (r1, b)."""
 
     @staticmethod
-    def forward(ctx, r1, b, sol, w):
-        ctx.sol, ctx.w = sol, w
+    def forward(ctx, r1, b, sol):
+        ctx.sol = sol
         x, _ = sol.affine_project(r1, b)
         return x
 
     @staticmethod
     def backward(ctx, gx):
-        w = ctx.w
-        xo, yo = ctx.sol.affine_project(gx.double() / w, torch.zeros(ctx.sol.m, dtype=torch.float64,
-                                                                        device=gx.device))
-        return w * xo, yo, None, None
+        r1bar, bbar = ctx.sol.affine_project_adjoint(gx)
+        return r1bar, bbar, None
 
 
 def geometry(sol):
@@ -91,28 +132,5 @@ def geometry(sol):
 
 
 def entry_weights(prob, device="cuda"):
+    """w_e = 1 on diagonal pattern entries, 2 off the diagonal (vec inner products)."""
     return torch.as_tensor(np.where(prob.ei == prob.ej, 1.0, 2.0), dtype=torch.float64, device=device)
-
-
-def unrolled_x(sol, prob, c, b, K: int, rho: float = 1.0, use_checkpoint: bool = True):
-    """x after K iterations of Algorithm 1 from zero state, differentiable in (c, b)."""
-    geo = geometry(sol)
-    w = entry_weights(prob, c.device)
-    xk = torch.zeros(sol.nslots, dtype=torch.float64, device=c.device)
-    lam = torch.zeros_like(xk)
-
-    def step(xk, lam, c, b):
-        r1 = Scatter.apply(xk + lam / rho, sol) - c / rho           # (E:OptCondMinYPrimal) rhs
-        x = Affine.apply(r1, b, sol, w)
-        h = Gather.apply(x, sol)
-        P = PSDProject.apply((h - lam / rho).float(), geo).double()  # (E:XkUpdate)
-        lam_new = lam + rho * (P - h)                                # (E:LambdakUpdate)
-        return x, P, lam_new
-
-    x = None
-    for _ in range(K):
-        if use_checkpoint:
-            x, xk, lam = checkpoint(step, xk, lam, c, b, use_reentrant=False)
-        else:
-            x, xk, lam = step(xk, lam, c, b)
-    return x

@@ -27,7 +27,9 @@ STATUS_NAMES = {0: "CDCS_OK", 1: "CDCS_E_ARG", 2: "CDCS_E_PATTERN", 3: "CDCS_E_R
 EXPORTS = ["cdcs_setup", "cdcs_setup_batch", "cdcs_batch_info", "cdcs_get_sizes", "cdcs_clique_offsets", "cdcs_psd_project_batched",
            "cdcs_psd_project_vjp", "cdcs_gather", "cdcs_scatter", "cdcs_affine_project", "cdcs_admm_solve",
            "cdcs_admm_step", "cdcs_admm_solve_timed", "cdcs_profile_kernel", "cdcs_get_tuning", "cdcs_set_projection_plan",
-           "cdcs_residual_history", "cdcs_warm_reset", "cdcs_destroy", "cdcs_last_error"]
+           "cdcs_residual_history", "cdcs_warm_reset", "cdcs_destroy", "cdcs_last_error", "cdcs_admm_prepare",
+           "cdcs_psd_project_cliques", "cdcs_unrolled_step", "cdcs_unrolled_step_vjp",
+           "cdcs_affine_project_adjoint", "cdcs_chordal_extension"]
 
 
 class CdcsLibraryMissing(ImportError):
@@ -113,7 +115,13 @@ def load_library(path: str = LIB_PATH):
     L.cdcs_batch_info.argtypes = [vp, i32, P(_InstanceInfo)]
     L.cdcs_get_sizes.argtypes = [vp, P(_Sizes)]
     L.cdcs_get_tuning.argtypes = [vp, P(_Tuning)]
-    L.cdcs_set_projection_plan.argtypes = [vp, i32, i32]
+    L.cdcs_set_projection_plan.argtypes = [vp, i32, i32, i32]
+    L.cdcs_admm_prepare.argtypes = [vp, P(_State), P(_Options), vp]
+    L.cdcs_psd_project_cliques.argtypes = [vp, vp, vp, vp]
+    L.cdcs_unrolled_step.argtypes = [vp, P(_State), vp, vp, dbl, vp, vp, vp]
+    L.cdcs_unrolled_step_vjp.argtypes = [vp, dbl, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.cdcs_affine_project_adjoint.argtypes = [vp, vp, vp, vp, vp]
+    L.cdcs_chordal_extension.argtypes = [P(_Pattern), P(i64), P(i32), P(i64), vp, vp, vp, vp]
     L.cdcs_clique_offsets.argtypes = [vp, vp]
     L.cdcs_psd_project_batched.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.cdcs_psd_project_vjp.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -180,12 +188,16 @@ def _marshal(prob):
     """C structs describing one problem (host arrays kept alive in the tuple)."""
     ei = np.ascontiguousarray(prob.ei, dtype=np.int32)
     ej = np.ascontiguousarray(prob.ej, dtype=np.int32)
-    cptr = np.ascontiguousarray(prob.clique_ptr, dtype=np.int64)
-    cvert = np.ascontiguousarray(prob.clique_vert, dtype=np.int32)
     b = np.ascontiguousarray(prob.b, dtype=np.float64)
     c = np.ascontiguousarray(prob.c, dtype=np.float64)
     pat = _Pattern(int(prob.n), int(ei.shape[0]), _np_ptr(ei), _np_ptr(ej))
-    cl = _Cliques(int(cptr.shape[0] - 1), _np_ptr(cptr), _np_ptr(cvert))
+    if prob.clique_ptr is None:
+        # no cliques given: setup computes a chordal extension and its cliques
+        cptr = cvert = cl = None
+    else:
+        cptr = np.ascontiguousarray(prob.clique_ptr, dtype=np.int64)
+        cvert = np.ascontiguousarray(prob.clique_vert, dtype=np.int32)
+        cl = _Cliques(int(cptr.shape[0] - 1), _np_ptr(cptr), _np_ptr(cvert))
     if prob.A is not None:
         aval = np.ascontiguousarray(prob.A, dtype=np.float64)
         cons = _Constraints(int(b.shape[0]), 1, None, None, _np_ptr(aval))
@@ -209,8 +221,8 @@ class Solver:
         if _handle is None:
             pat, cons, b, c, cl, keep = _marshal(prob)
             h = ctypes.c_void_p()
-            st = L.cdcs_setup(ctypes.byref(pat), ctypes.byref(cons), _np_ptr(b), _np_ptr(c), ctypes.byref(cl),
-                              None, _stream(torch), ctypes.byref(h))
+            st = L.cdcs_setup(ctypes.byref(pat), ctypes.byref(cons), _np_ptr(b), _np_ptr(c),
+                              ctypes.byref(cl) if cl is not None else None, None, _stream(torch), ctypes.byref(h))
             del keep
             _check(st, "cdcs_setup")
         else:
@@ -262,7 +274,11 @@ class Solver:
                       _ptr(st.get("vw")))
 
     def solve(self, state: dict, form: str = "primal", rho: float = 1.0, tol: float = 1e-4,
-              max_iter: int = 500, check_every: int = 50, stream=None, raise_on_cap: bool = False) -> SolveInfo:
+              max_iter: int = 500, check_every: int = 50, stream=None, raise_on_cap: bool = False,
+              raise_on_numeric: bool = True) -> SolveInfo:
+        """cdcs_admm_solve.  Raises CdcsError on failure; CDCS_E_NOT_CONVERGED
+        only with raise_on_cap, CDCS_E_NUMERIC unless raise_on_numeric is
+        False (then SolveInfo.status carries it)."""
         L = load_library()
         f = PRIMAL if form == "primal" else DUAL
         opts = _Options(float(rho), float(tol), int(max_iter), f, int(check_every))
@@ -270,7 +286,8 @@ class Solver:
         cs = self._cstate(state)
         st = L.cdcs_admm_solve(self._h, ctypes.byref(cs), ctypes.byref(opts), ctypes.byref(info),
                                _stream(self._torch, stream))
-        if st not in (OK, E_NOT_CONVERGED) or (raise_on_cap and st == E_NOT_CONVERGED):
+        allowed = (OK, E_NOT_CONVERGED) if raise_on_numeric else (OK, E_NOT_CONVERGED, E_NUMERIC)
+        if st not in allowed or (raise_on_cap and st == E_NOT_CONVERGED):
             _check(st, "cdcs_admm_solve")
         return SolveInfo(info.iters, info.status, bool(info.converged), info.jacobi_cap_hits, info.eps_p,
                          info.eps_d, info.obj_primal, info.obj_dual, info.loop_s, info.jacobi_sweeps)
@@ -319,10 +336,29 @@ class Solver:
                              "us": t.bucket_us[q]} for q in range(nb)],
                 "queue_us": t.queue_us, "buckets_us": t.buckets_us}
 
-    def set_projection_plan(self, persistent: bool, threads: int = 0):
+    def set_projection_plan(self, persistent: bool, threads: int = 0, grid: int = 0):
         """Override the tuned plan (cdcs_set_projection_plan)."""
-        _check(load_library().cdcs_set_projection_plan(self._h, int(bool(persistent)), int(threads)),
+        _check(load_library().cdcs_set_projection_plan(self._h, int(bool(persistent)), int(threads), int(grid)),
                "cdcs_set_projection_plan")
+
+    def prepare(self, state: dict, form: str = "primal", rho: float = 1.0, tol: float = 1e-4,
+                max_iter: int = 500, check_every: int = 50, stream=None):
+        """Capture the graphs solve() with these arguments launches (cdcs_admm_prepare)."""
+        opts = _Options(float(rho), float(tol), int(max_iter), PRIMAL if form == "primal" else DUAL,
+                        int(check_every))
+        cs = self._cstate(state)
+        _check(load_library().cdcs_admm_prepare(self._h, ctypes.byref(cs), ctypes.byref(opts),
+                                                _stream(self._torch, stream)), "cdcs_admm_prepare")
+
+    def project_cliques(self, W, P=None, stream=None):
+        """P(W_k) for this handle's cliques with the tuned launch plan, cold start
+        (cdcs_psd_project_cliques).  W: packed FP32 device tensor of nslots."""
+        torch = self._torch
+        W = W.contiguous()
+        P = torch.empty_like(W) if P is None else P
+        _check(load_library().cdcs_psd_project_cliques(self._h, _ptr(W), _ptr(P), _stream(torch, stream)),
+               "cdcs_psd_project_cliques")
+        return P
 
     def history(self, n: int) -> np.ndarray:
         out = np.zeros((n, 2))
@@ -345,6 +381,40 @@ class Solver:
         _check(load_library().cdcs_scatter(self._h, _ptr(packed), _ptr(out), _stream(torch, stream)),
                "cdcs_scatter")
         return out
+
+    @property
+    def nevals(self) -> int:
+        return int(np.sum(self.sizes))
+
+    def unrolled_step(self, state: dict, c, b, rho: float = 1.0, evals=None, evecs=None, stream=None):
+        """One Algorithm-1 iteration with the given c and b (device FP64),
+        saving the projections' eigenpairs (cdcs_unrolled_step)."""
+        cs = self._cstate(state)
+        c = c.contiguous()
+        b = b.contiguous()
+        st = load_library().cdcs_unrolled_step(self._h, ctypes.byref(cs), _ptr(c), _ptr(b), float(rho),
+                                               _ptr(evals), _ptr(evecs), _stream(self._torch, stream))
+        if st not in (OK, E_NOT_CONVERGED):
+            _check(st, "cdcs_unrolled_step")
+
+    def unrolled_step_vjp(self, evals, evecs, xbar, blkbar, lambar, cbar, bbar, rho: float = 1.0, stream=None):
+        """Adjoint of unrolled_step (cdcs_unrolled_step_vjp): blkbar, lambar
+        (FP64 packed) are updated in place, cbar and bbar accumulate."""
+        _check(load_library().cdcs_unrolled_step_vjp(self._h, float(rho), _ptr(evals), _ptr(evecs),
+                                                     _ptr(xbar.contiguous() if xbar is not None else None),
+                                                     _ptr(blkbar), _ptr(lambar), _ptr(cbar), _ptr(bbar),
+                                                     _stream(self._torch, stream)), "cdcs_unrolled_step_vjp")
+
+    def affine_project_adjoint(self, xbar, stream=None):
+        """Cotangents (r1bar, r2bar) of cdcs_affine_project's inputs from the
+        cotangent of its x (cdcs_affine_project_adjoint)."""
+        torch = self._torch
+        xbar = xbar.contiguous()
+        r1bar = torch.empty(self.nnz, dtype=torch.float64, device=xbar.device)
+        r2bar = torch.empty(self.m, dtype=torch.float64, device=xbar.device)
+        _check(load_library().cdcs_affine_project_adjoint(self._h, _ptr(xbar), _ptr(r1bar), _ptr(r2bar),
+                                                          _stream(torch, stream)), "cdcs_affine_project_adjoint")
+        return r1bar, r2bar
 
     def affine_project(self, r1, r2, stream=None):
         torch = self._torch
@@ -395,6 +465,27 @@ class BatchSolver(Solver):
         _check(load_library().cdcs_batch_info(self._h, self.nprob, out), "cdcs_batch_info")
         return [InstanceInfo(o.iters, o.status, o.eps_p, o.eps_d, o.obj_primal, o.obj_dual, o.time_to_tol_s)
                 for o in out]
+
+
+def chordal_extension(n: int, ei, ej):
+    """Chordal extension of the pattern (ei, ej) of an n x n matrix and its
+    maximal cliques (cdcs_chordal_extension, host code: no device needed).
+    Returns (fill_i, fill_j, clique_ptr, clique_vert)."""
+    L = load_library()
+    ei = np.ascontiguousarray(ei, dtype=np.int32)
+    ej = np.ascontiguousarray(ej, dtype=np.int32)
+    pat = _Pattern(int(n), int(ei.shape[0]), _np_ptr(ei), _np_ptr(ej))
+    nfill, p, nvert = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+    _check(L.cdcs_chordal_extension(ctypes.byref(pat), ctypes.byref(nfill), ctypes.byref(p), ctypes.byref(nvert),
+                                    None, None, None, None), "cdcs_chordal_extension")
+    fi = np.empty(nfill.value, dtype=np.int32)
+    fj = np.empty(nfill.value, dtype=np.int32)
+    cptr = np.empty(p.value + 1, dtype=np.int64)
+    cvert = np.empty(nvert.value, dtype=np.int32)
+    _check(L.cdcs_chordal_extension(ctypes.byref(pat), ctypes.byref(nfill), ctypes.byref(p), ctypes.byref(nvert),
+                                    _np_ptr(fi), _np_ptr(fj), _np_ptr(cptr), _np_ptr(cvert)),
+           "cdcs_chordal_extension")
+    return fi, fj, cptr, cvert
 
 
 def packed_offsets(sizes) -> np.ndarray:
@@ -461,18 +552,20 @@ def psd_project_vjp(gP, evals, evecs, eoff, voff, sizes_d, offsets_d, smax: int,
     return gW
 
 
-def psd_project_plain(W, sizes_d, offsets_d, smax: int, P=None, stream=None):
+def psd_project_plain(W, sizes_d, offsets_d, sizes_h, P=None, stream=None):
     """The clique-per-launch form: the same projection kernel launched once per
-    block with a one-workgroup grid (no graph).  Baseline for the batched form."""
+    block with a one-workgroup grid of the block's own size bucket (no
+    graph).  Baseline for the batched form."""
     torch = _torch()
     L = load_library()
     P = torch.empty_like(W) if P is None else P
     s = _stream(torch, stream)
+    sizes_h = np.asarray(sizes_h, dtype=np.int64)
     nb = int(sizes_d.shape[0])
     sp, op, wp, pp = sizes_d.data_ptr(), offsets_d.data_ptr(), W.data_ptr(), P.data_ptr()
     fn = L.cdcs_psd_project_batched
     for t in range(nb):
-        st = fn(1, int(smax), ctypes.c_void_p(sp + 4 * t), ctypes.c_void_p(op + 8 * t), ctypes.c_void_p(wp),
+        st = fn(1, int(sizes_h[t]), ctypes.c_void_p(sp + 4 * t), ctypes.c_void_p(op + 8 * t), ctypes.c_void_p(wp),
                 ctypes.c_void_p(pp), None, None, None, None, s)
         if st != OK:
             _check(st, "cdcs_psd_project_batched")

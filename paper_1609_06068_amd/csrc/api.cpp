@@ -81,6 +81,17 @@ struct cdcs_handle {
     std::unique_ptr<Batch> batch_host;
     int last_iters = 0;
     double last_rho = 1.0;
+    // differentiation (allocated at the first call that needs them)
+    struct Diff {
+        double *c = nullptr;       // [ldU] caller's c in internal entry order
+        int64_t *eoff = nullptr;   // [p+1] offsets of each clique's eigenvalues (prefix sums of s_k)
+        float *gP = nullptr, *gW = nullptr;  // [nslots] projection adjoint in/out
+        double *hbar = nullptr;    // [nslots]
+        double *x = nullptr;       // [ldU] solve output, then r1bar
+        double *y = nullptr;       // [ldM]
+    } diff;
+    float *save_evals = nullptr;  // set while an unrolled step runs: the projection
+    float *save_evecs = nullptr;  // writes its eigenpairs here
 
     template <typename T>
     cdcs_status alloc(T **p, int64_t count) {
@@ -788,7 +799,34 @@ ProjArgs proj_args(const cdcs_handle *h, int mode, const cdcs_state *st, double 
     a.warm_store = 1;
     a.cpart = d.cpart;
     a.ctl = d.ctl;
+    if (h->save_evals || h->save_evecs) {
+        a.evals = h->save_evals;
+        a.eoff = h->diff.eoff;
+        a.evecs = h->save_evecs;
+        a.voff = d.vwoff;
+    }
     return a;
+}
+
+// Buffers of the differentiation entry points, allocated once per handle.
+cdcs_status diff_buffers(cdcs_handle *h) {
+    cdcs_handle::Diff &f = h->diff;
+    if (f.c) return CDCS_OK;
+    const Dev &d = h->d;
+    std::vector<int64_t> eoff((size_t)d.p + 1, 0);
+    for (int32_t k = 0; k < d.p; ++k) {
+        const int64_t pk = h->off_host[(size_t)k + 1] - h->off_host[(size_t)k];  // s (s + 1) / 2
+        const int64_t sk = (int64_t)((std::sqrt(8.0 * (double)pk + 1.0) - 1.0) / 2.0 + 0.5);
+        eoff[(size_t)k + 1] = eoff[(size_t)k] + sk;
+    }
+    CK(upload(h, &f.eoff, eoff, nullptr));
+    CK(h->alloc(&f.gP, d.nslots));
+    CK(h->alloc(&f.gW, d.nslots));
+    CK(h->alloc(&f.hbar, d.nslots));
+    CK(h->alloc(&f.x, d.ldU));
+    CK(h->alloc(&f.y, d.ldM));
+    CK(h->alloc(&f.c, d.ldU));  // last: marks the set as complete
+    return CDCS_OK;
 }
 
 // The projection of every clique with the handle's plan.
@@ -1025,6 +1063,25 @@ extern "C" {
 
 const char *cdcs_last_error(void) { return g_err.c_str(); }
 
+cdcs_status cdcs_chordal_extension(const cdcs_pattern *pattern, int64_t *nfill, int32_t *p, int64_t *nvert,
+                                   int32_t *fill_i, int32_t *fill_j, int64_t *clique_ptr, int32_t *clique_vert) {
+    if (!pattern || !nfill || !p || !nvert) return fail(CDCS_E_ARG, "NULL argument");
+    ChordalExt ext;
+    std::string err;
+    const cdcs_status st = chordal_extension(pattern->n, pattern->nnz, pattern->i, pattern->j, ext, err);
+    if (st != CDCS_OK) return fail(st, err);
+    *nfill = (int64_t)ext.fill_i.size();
+    *p = (int32_t)(ext.ptr.size() - 1);
+    *nvert = ext.ptr.back();
+    if (fill_i && fill_j) {
+        std::copy(ext.fill_i.begin(), ext.fill_i.end(), fill_i);
+        std::copy(ext.fill_j.begin(), ext.fill_j.end(), fill_j);
+    }
+    if (clique_ptr) std::copy(ext.ptr.begin(), ext.ptr.end(), clique_ptr);
+    if (clique_vert) std::copy(ext.vert.begin(), ext.vert.end(), clique_vert);
+    return CDCS_OK;
+}
+
 cdcs_status cdcs_setup(const cdcs_pattern *pattern, const cdcs_constraints *A, const double *b, const double *c,
                        const cdcs_cliques *cliques, const cdcs_options *opts, hipStream_t stream,
                        cdcs_handle **out) {
@@ -1032,6 +1089,33 @@ cdcs_status cdcs_setup(const cdcs_pattern *pattern, const cdcs_constraints *A, c
     if (!out) return fail(CDCS_E_ARG, "out is NULL");
     *out = nullptr;
     g_err.clear();
+    if (!cliques) {
+        // chordal decomposition of an arbitrary pattern: the extension's fill
+        // entries follow the caller's entries, with zero data (C and every A_i
+        // vanish on them)
+        if (!pattern || !A || !b || !c || !A->val) return fail(CDCS_E_ARG, "NULL argument");
+        ChordalExt ext;
+        std::string err;
+        const cdcs_status st = chordal_extension(pattern->n, pattern->nnz, pattern->i, pattern->j, ext, err);
+        if (st != CDCS_OK) return fail(st, err);
+        const int64_t nu = pattern->nnz, nf = (int64_t)ext.fill_i.size(), ne = nu + nf;
+        std::vector<int32_t> pi(pattern->i, pattern->i + nu), pj(pattern->j, pattern->j + nu);
+        pi.insert(pi.end(), ext.fill_i.begin(), ext.fill_i.end());
+        pj.insert(pj.end(), ext.fill_j.begin(), ext.fill_j.end());
+        std::vector<double> cx(c, c + nu);
+        cx.resize((size_t)ne, 0.0);
+        std::vector<double> ax;
+        cdcs_constraints Ax = *A;
+        if (A->dense && nf > 0) {
+            ax.assign((size_t)(A->m * ne), 0.0);
+            for (int32_t r = 0; r < A->m; ++r)
+                std::copy(A->val + (size_t)r * nu, A->val + (size_t)(r + 1) * nu, ax.begin() + (size_t)r * ne);
+            Ax.val = ax.data();
+        }
+        const cdcs_pattern px{pattern->n, ne, pi.data(), pj.data()};
+        const cdcs_cliques cx_cl{(int32_t)(ext.ptr.size() - 1), ext.ptr.data(), ext.vert.data()};
+        return cdcs_setup(&px, &Ax, b, cx.data(), &cx_cl, opts, stream, out);
+    }
     cdcs_handle *h = new (std::nothrow) cdcs_handle();
     if (!h) return fail(CDCS_E_NOMEM, "host allocation");
     hipError_t e = hipGetDevice(&h->device);
@@ -1093,7 +1177,7 @@ cdcs_status cdcs_batch_info(const cdcs_handle *h, int32_t nprob, cdcs_instance_i
     for (int32_t q = 0; q < nprob; ++q) {
         cdcs_instance_info &o = out_host[q];
         o.iters = stp[(size_t)q] ? its[(size_t)q] : h->last_iters;
-        o.status = stp[(size_t)q] == 1 ? CDCS_OK : CDCS_E_NOT_CONVERGED;
+        o.status = stp[(size_t)q] == 1 ? CDCS_OK : stp[(size_t)q] == 3 ? CDCS_E_NUMERIC : CDCS_E_NOT_CONVERGED;
         o.eps_p = eps[(size_t)(2 * q)];
         o.eps_d = eps[(size_t)(2 * q + 1)];
         o.obj_primal = obj[(size_t)(2 * q)];
@@ -1156,6 +1240,21 @@ cdcs_status cdcs_psd_project_batched(int32_t nb, int32_t smax, const int32_t *si
     return CDCS_OK;
 }
 
+cdcs_status cdcs_psd_project_cliques(cdcs_handle *h, const float *W, float *P, hipStream_t stream) {
+    if (!h || !W || !P) return fail(CDCS_E_ARG, "NULL argument");
+    ProjArgs a = proj_args(h, PROJ_STANDALONE, nullptr, 1.0);
+    a.Win = W;
+    a.Pout = P;
+    a.vwarm = nullptr;  // cold start: Jacobi from the identity
+    a.warm_store = 0;
+    a.kinst = nullptr;
+    a.istop = nullptr;
+    a.ctl = nullptr;
+    launch_plan(h, a, stream);
+    HIP_OK(hipGetLastError());
+    return CDCS_OK;
+}
+
 cdcs_status cdcs_psd_project_vjp(int32_t nb, int32_t smax, const int32_t *sizes, const int64_t *off,
                                  const float *evals, const int64_t *eoff, const float *evecs, const int64_t *voff,
                                  const float *gP, float *gW, hipStream_t stream) {
@@ -1208,23 +1307,19 @@ cdcs_status cdcs_affine_project(const cdcs_handle *h, const double *r1, const do
 }
 
 namespace {
-cdcs_status solve_impl(cdcs_handle *h, const cdcs_state *st_user, const cdcs_options *opts, cdcs_info *info,
-                       hipStream_t stream, IterTimer *tm) {
+// Validation shared by the solve entry points, and the residual history
+// buffer sized for max_iter (allocating it drops the captured graphs, which
+// hold the old pointer).
+cdcs_status solve_check(cdcs_handle *h, const cdcs_state *st_user, const cdcs_options *opts, hipStream_t stream) {
     if (!h || !st_user || !opts) return fail(CDCS_E_ARG, "NULL argument");
     if (!st_user->x || !st_user->y || !st_user->blk || !st_user->lam) return fail(CDCS_E_ARG, "state has NULL buffers");
-    // the iteration runs on x in internal entry order
-    cdcs_state st_int = *st_user;
-    st_int.x = h->d.xi;
-    const cdcs_state *st = &st_int;
     const int form = opts->form;
     if (form != CDCS_PRIMAL && form != CDCS_DUAL) return fail(CDCS_E_ARG, "bad form");
-    if (form == CDCS_DUAL && !st->v) return fail(CDCS_E_ARG, "dual form needs state.v");
-    if (!(opts->rho > 0.0) || !(opts->tol >= 0.0) || opts->max_iter < 1)
-        return fail(CDCS_E_ARG, "need rho > 0, tol >= 0, max_iter >= 1");
+    if (form == CDCS_DUAL && !st_user->v) return fail(CDCS_E_ARG, "dual form needs state.v");
+    if (!(opts->rho > 0.0) || !(opts->tol >= 0.0) || opts->max_iter < 1 || opts->check_every < 0)
+        return fail(CDCS_E_ARG, "need rho > 0, tol >= 0, max_iter >= 1, check_every >= 0");
     Dev &d = h->d;
-    const double rho = opts->rho;
     if (d.batch && form != CDCS_PRIMAL) return fail(CDCS_E_ARG, "batch handles run Algorithm 1 only");
-    h->last_rho = rho;
     if (d.hist_cap < opts->max_iter) {
         if (d.hist) {
             HIP_OK(hipStreamSynchronize(stream));
@@ -1238,6 +1333,32 @@ cdcs_status solve_impl(cdcs_handle *h, const cdcs_state *st_user, const cdcs_opt
         for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
         h->graphs.clear();
     }
+    return CDCS_OK;
+}
+
+// The graphs a solve launches: max_iter / check_every launches of a graph of
+// check_every iterations, then one of the remaining max_iter % check_every.
+cdcs_status solve_graphs(cdcs_handle *h, const cdcs_state *st, const cdcs_options *opts, hipGraphExec_t *full,
+                         hipGraphExec_t *tail) {
+    const int K = opts->check_every;
+    *full = nullptr;
+    *tail = nullptr;
+    if (opts->max_iter >= K) CK(get_graph(h, st, opts->form, K, opts->rho, full));
+    if (opts->max_iter % K) CK(get_graph(h, st, opts->form, opts->max_iter % K, opts->rho, tail));
+    return CDCS_OK;
+}
+
+cdcs_status solve_impl(cdcs_handle *h, const cdcs_state *st_user, const cdcs_options *opts, cdcs_info *info,
+                       hipStream_t stream, IterTimer *tm) {
+    CK(solve_check(h, st_user, opts, stream));
+    // the iteration runs on x in internal entry order
+    cdcs_state st_int = *st_user;
+    st_int.x = h->d.xi;
+    const cdcs_state *st = &st_int;
+    const int form = opts->form;
+    Dev &d = h->d;
+    const double rho = opts->rho;
+    h->last_rho = rho;
     launch_reset_ctl(d, opts->max_iter, opts->tol, stream);
     if (d.batch) launch_breset(d, stream);
     // a solve is a function of (problem, state, options) only: without a
@@ -1248,10 +1369,12 @@ cdcs_status solve_impl(cdcs_handle *h, const cdcs_state *st_user, const cdcs_opt
     auto t0 = std::chrono::steady_clock::now();
     const int K = tm ? 0 : opts->check_every;
     if (K > 0) {
-        hipGraphExec_t ex = nullptr;
-        CK(get_graph(h, st, form, K, rho, &ex));
-        for (int done = 0; done < opts->max_iter; done += K) {
-            HIP_OK(hipGraphLaunch(ex, stream));
+        hipGraphExec_t full = nullptr, tail = nullptr;
+        CK(solve_graphs(h, st, opts, &full, &tail));
+        for (int done = 0; done < opts->max_iter;) {
+            const int n = std::min(K, opts->max_iter - done);
+            HIP_OK(hipGraphLaunch(n == K ? full : tail, stream));
+            done += n;
             HIP_OK(hipMemcpyAsync(d.ctl_host, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
             HIP_OK(hipStreamSynchronize(stream));
             if (d.ctl_host->stop) break;
@@ -1296,7 +1419,13 @@ cdcs_status solve_impl(cdcs_handle *h, const cdcs_state *st_user, const cdcs_opt
         HIP_OK(hipMemcpy(stp.data(), d.batch->istop, stp.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
         converged = std::all_of(stp.begin(), stp.end(), [](int32_t v) { return v == 1; });
     }
-    if (c.jacobi_cap > 0) status = CDCS_E_NUMERIC;
+    bool nonfinite = c.stop == 3;
+    if (d.batch) {
+        std::vector<int32_t> stp((size_t)d.batch->nprob);
+        HIP_OK(hipMemcpy(stp.data(), d.batch->istop, stp.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        nonfinite = std::any_of(stp.begin(), stp.end(), [](int32_t v) { return v == 3; });
+    }
+    if (c.jacobi_cap > 0 || nonfinite) status = CDCS_E_NUMERIC;
     else if (!converged && opts->tol > 0.0) status = CDCS_E_NOT_CONVERGED;
     if (info) {
         info->iters = c.iter;
@@ -1316,7 +1445,9 @@ cdcs_status solve_impl(cdcs_handle *h, const cdcs_state *st_user, const cdcs_opt
         info->jacobi_sweeps = c.sweeps;
     }
     if (status != CDCS_OK)
-        g_err = status == CDCS_E_NUMERIC ? "an eigensolve hit its sweep cap" : "iteration cap reached";
+        g_err = nonfinite                     ? "NaN or Inf in the iterate (residuals not finite)"
+                : status == CDCS_E_NUMERIC ? "an eigensolve hit its sweep cap"
+                                           : "iteration cap reached";
     return status;
 }
 }  // namespace
@@ -1324,6 +1455,89 @@ cdcs_status solve_impl(cdcs_handle *h, const cdcs_state *st_user, const cdcs_opt
 cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st, const cdcs_options *opts, cdcs_info *info,
                             hipStream_t stream) {
     return solve_impl(h, st, opts, info, stream, nullptr);
+}
+
+cdcs_status cdcs_admm_prepare(cdcs_handle *h, const cdcs_state *st_user, const cdcs_options *opts,
+                              hipStream_t stream) {
+    CK(solve_check(h, st_user, opts, stream));
+    if (opts->check_every == 0) return CDCS_OK;
+    cdcs_state st_int = *st_user;
+    st_int.x = h->d.xi;
+    hipGraphExec_t full = nullptr, tail = nullptr;
+    CK(solve_graphs(h, &st_int, opts, &full, &tail));
+    return CDCS_OK;
+}
+
+cdcs_status cdcs_unrolled_step(cdcs_handle *h, const cdcs_state *st, const double *c, const double *b, double rho,
+                               float *evals, float *evecs, hipStream_t stream) {
+    if (!h || !st || !c || !b) return fail(CDCS_E_ARG, "NULL argument");
+    if (h->d.batch) return fail(CDCS_E_ARG, "unrolled steps run on single-SDP handles");
+    CK(diff_buffers(h));
+    Dev &d = h->d;
+    launch_perm_in(d, c, h->diff.c, stream);
+    double *c0 = d.c, *b0 = d.b;
+    d.c = h->diff.c;
+    d.b = const_cast<double *>(b);
+    h->save_evals = evals;
+    h->save_evecs = evecs;
+    cdcs_options o{};
+    o.rho = rho;
+    o.tol = 0.0;
+    o.max_iter = 1;
+    o.form = CDCS_PRIMAL;
+    o.check_every = 0;
+    const cdcs_status r = cdcs_admm_solve(h, st, &o, nullptr, stream);
+    d.c = c0;
+    d.b = b0;
+    h->save_evals = nullptr;
+    h->save_evecs = nullptr;
+    return r;
+}
+
+cdcs_status cdcs_unrolled_step_vjp(cdcs_handle *h, double rho, const float *evals, const float *evecs,
+                                   const double *xbar, double *blkbar, double *lambar, double *cbar, double *bbar,
+                                   hipStream_t stream) {
+    if (!h || !evals || !evecs || !blkbar || !lambar || !cbar || !bbar) return fail(CDCS_E_ARG, "NULL argument");
+    if (!(rho > 0.0)) return fail(CDCS_E_ARG, "need rho > 0");
+    if (h->d.batch) return fail(CDCS_E_ARG, "unrolled steps run on single-SDP handles");
+    CK(diff_buffers(h));
+    Dev &d = h->d;
+    cdcs_handle::Diff &f = h->diff;
+    launch_adjoint_in(d, blkbar, lambar, rho, f.gP, stream);
+    VjpArgs a{};
+    a.nblk = d.p;
+    a.size = d.clq_size;
+    a.off = d.clq_off;
+    a.evals = evals;
+    a.eoff = f.eoff;
+    a.evecs = evecs;
+    a.voff = d.vwoff;
+    a.gP = f.gP;
+    a.gW = f.gW;
+    launch_project_vjp(a, d.smax, stream);
+    launch_adjoint_mid(d, f.gW, lambar, rho, f.hbar, stream);
+    launch_adjoint_scatter(d, f.hbar, xbar, stream);
+    launch_affine(d, d.b, 0.0, f.x, f.y, nullptr, stream);
+    launch_adjoint_post(d, f.x, cbar, -1.0 / rho, 1, stream);
+    launch_adjoint_slots(d, f.x, blkbar, lambar, rho, stream);
+    launch_add_to(f.y, bbar, d.m, 1, stream);
+    HIP_OK(hipGetLastError());
+    return CDCS_OK;
+}
+
+cdcs_status cdcs_affine_project_adjoint(cdcs_handle *h, const double *xbar, double *r1bar, double *bbar,
+                                        hipStream_t stream) {
+    if (!h || !xbar || !r1bar || !bbar) return fail(CDCS_E_ARG, "NULL argument");
+    CK(diff_buffers(h));
+    Dev &d = h->d;
+    cdcs_handle::Diff &f = h->diff;
+    launch_adjoint_scatter(d, nullptr, xbar, stream);
+    if (d.batch) launch_baffine(d, d.b, 0.0, f.x, f.y, nullptr, nullptr, stream);
+    else launch_affine(d, d.b, 0.0, f.x, f.y, nullptr, stream);
+    launch_adjoint_post(d, f.x, r1bar, 1.0, 0, stream);
+    launch_add_to(f.y, bbar, d.m, 0, stream);
+    HIP_OK(hipGetLastError());
+    return CDCS_OK;
 }
 
 cdcs_status cdcs_admm_solve_timed(cdcs_handle *h, const cdcs_state *st, const cdcs_options *opts, cdcs_info *info,
@@ -1418,13 +1632,16 @@ cdcs_status cdcs_get_tuning(const cdcs_handle *h, cdcs_tuning *out) {
     return CDCS_OK;
 }
 
-cdcs_status cdcs_set_projection_plan(cdcs_handle *h, int32_t persistent, int32_t threads) {
+cdcs_status cdcs_set_projection_plan(cdcs_handle *h, int32_t persistent, int32_t threads, int32_t grid_req) {
     if (!h) return fail(CDCS_E_ARG, "NULL handle");
     if (persistent != 0 && persistent != 1) return fail(CDCS_E_ARG, "persistent must be 0 or 1");
     if (persistent) {
         if (threads != 256 && threads != 512) return fail(CDCS_E_ARG, "queue launches use 256 or 512 threads");
-        const int grid = queue_grid(h, threads);
-        if (grid < 1) return fail(CDCS_E_DEVICE, "queue kernel does not fit on a CU");
+        const int grid_max = queue_grid(h, threads);
+        if (grid_max < 1) return fail(CDCS_E_DEVICE, "queue kernel does not fit on a CU");
+        if (grid_req < 0 || grid_req > grid_max)
+            return fail(CDCS_E_ARG, "grid outside 0.." + std::to_string(grid_max) + " (resident workgroups)");
+        const int grid = grid_req > 0 ? grid_req : grid_max;
         HIP_OK(hipDeviceSynchronize());
         HIP_OK(hipMemset(h->ticket, 0, sizeof(unsigned long long)));
         h->plan.queue = true;

@@ -18,7 +18,7 @@ namespace cdcs {
 // several iterations becomes a no-op after convergence.
 struct Ctl {
     int32_t iter;       // completed iterations
-    int32_t stop;       // 0 running, 1 converged, 2 iteration cap
+    int32_t stop;       // 0 running, 1 converged, 2 iteration cap, 3 NaN/Inf in the residuals
     int32_t max_iter;
     int32_t jacobi_cap; // eigensolves that hit the sweep cap
     int32_t sweeps;     // Jacobi sweeps summed over all eigensolves
@@ -127,7 +127,7 @@ struct Batch {
     int32_t nrjobs = 0;
     int32_t *ejobs = nullptr;      // [nejobs * 2] (q, first entry in q) of 1024-entry A^T y blocks
     int32_t nejobs = 0;
-    int32_t *istop = nullptr;      // [nprob] 0 running, 1 converged, 2 iteration cap
+    int32_t *istop = nullptr;      // [nprob] 0 running, 1 converged, 2 iteration cap, 3 NaN/Inf
     int32_t *iiters = nullptr;     // [nprob] iterations at stop
     uint64_t *itime = nullptr;     // [nprob] device wall clock at stop
     uint64_t *t0 = nullptr;        // [1] device wall clock at solve start
@@ -239,6 +239,29 @@ void launch_perm_out(const Dev &d, const double *x_internal, double *x_pattern, 
 void launch_scatter_f64(const Dev &d, const double *packed, double *out, hipStream_t s);
 void launch_objectives(const Dev &d, const double *x, const double *y, hipStream_t s);
 int objective_partials();
+// Adjoint of one unrolled Algorithm-1 iteration (packed coordinates):
+// gP = blkbar + rho lambar; hbar = gW - rho lambar, lambar -= gW / rho;
+// d.u = s2 (sum_k H_k^T hbar + xbar) (hbar, xbar_pat nullable; xbar in pattern
+// order); r1bar = w x kept in x, out_pat[perm] (+)= scale r1bar;
+// blkbar = H_k r1bar, lambar += H_k r1bar / rho; out (+)= v.
+void launch_adjoint_in(const Dev &d, const double *blkbar, const double *lambar, double rho, float *gP,
+                       hipStream_t s);
+void launch_adjoint_mid(const Dev &d, const float *gW, double *lambar, double rho, double *hbar, hipStream_t s);
+void launch_adjoint_scatter(const Dev &d, const double *hbar, const double *xbar_pat, hipStream_t s);
+void launch_adjoint_post(const Dev &d, double *x, double *out_pat, double scale, int accumulate, hipStream_t s);
+void launch_adjoint_slots(const Dev &d, const double *r1bar, double *blkbar, double *lambar, double rho,
+                          hipStream_t s);
+void launch_add_to(const double *v, double *out, int n, int accumulate, hipStream_t s);
+
+// Chordal extension of a pattern and its maximal cliques (chordal.cpp, host).
+struct ChordalExt {
+    bool chordal_input = false;           // the pattern was chordal already (no fill)
+    std::vector<int32_t> fill_i, fill_j;  // added lower-triangular entries, in clique order
+    std::vector<int64_t> ptr;             // maximal cliques, CSR, vertices sorted
+    std::vector<int32_t> vert;
+};
+cdcs_status chordal_extension(int32_t n, int64_t nnz, const int32_t *ei, const int32_t *ej, ChordalExt &out,
+                              std::string &err);
 
 // setup kernels (kernels_setup.hip)
 void launch_syrk(const float *Aw, int64_t ld, const double *s2, int m, double *M, hipStream_t s);

@@ -195,6 +195,11 @@ __global__ __launch_bounds__(CNT) void k_check_primal(const double *__restrict__
                 hist[2 * (int64_t)(n - 1) + 0] = eps_p;
                 hist[2 * (int64_t)(n - 1) + 1] = eps_d;
             }
+            // a NaN or Inf anywhere in the iterate reaches these sums
+            if (!(isfinite(eps_p) && isfinite(eps_d))) {
+                ctl->stop = 3;
+                return;
+            }
             if (fmax(eps_p, eps_d) <= tol) {
                 ctl->stop = 1;
                 return;
@@ -320,7 +325,8 @@ __global__ __launch_bounds__(CNT) void k_check_dual(const double *__restrict__ v
             hist[2 * (int64_t)(n - 1) + 0] = eps_p;
             hist[2 * (int64_t)(n - 1) + 1] = eps_d;
         }
-        if (fmax(eps_p, eps_d) <= tol) ctl->stop = 1;
+        if (!(isfinite(eps_p) && isfinite(eps_d))) ctl->stop = 3;  // NaN or Inf in the iterate
+        else if (fmax(eps_p, eps_d) <= tol) ctl->stop = 1;
         else if (n >= max_iter) ctl->stop = 2;
     }
 }
@@ -602,6 +608,101 @@ __global__ __launch_bounds__(kNT) void k_perm_out(const double *__restrict__ xi,
     if (e < nU) xp[perm[e]] = xi[e];
 }
 
+// ---- Adjoint of one unrolled iteration of Algorithm 1 ----------------------
+// Packed coordinates: a cotangent of a packed slot is the derivative with
+// respect to the slot's value (an off-diagonal slot stands for both mirrored
+// entries of the clique matrix).  Forward: r1 = sum_k H_k^T (x_k + lam_k / rho)
+// - c / rho, x = F(r1, b), h = H_k x, P = P_+(h - lam / rho),
+// lam' = lam + rho (P - h), x_k' = P.
+
+// gP = xbar_k' + rho lambar'  (cotangent of P, FP32 for the projection adjoint)
+__global__ __launch_bounds__(kNT) void k_adj_in(const double *__restrict__ blkbar, const double *__restrict__ lambar,
+                                                double rho, float *__restrict__ gP, int64_t nslots) {
+    const int64_t s = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (s < nslots) gP[s] = (float)(blkbar[s] + rho * lambar[s]);
+}
+
+// hbar = gW - rho lambar' (cotangent of h), lambar <- lambar' - gW / rho
+__global__ __launch_bounds__(kNT) void k_adj_mid(const float *__restrict__ gW, double *__restrict__ lambar,
+                                                 double rho, double inv_rho, double *__restrict__ hbar,
+                                                 int64_t nslots) {
+    const int64_t s = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (s >= nslots) return;
+    const double g = (double)gW[s], l = lambar[s];
+    hbar[s] = g - rho * l;
+    lambar[s] = l - g * inv_rho;
+}
+
+// xbar_e = sum over the slots of e of hbar (the gather's transpose) plus the
+// caller's cotangent of x (pattern order), then u = xbar / (w D): the input
+// of the affine solve F(xbar / w, 0), whose x times w is the cotangent of r1
+// (F's Jacobian in r1 is diag(w)^-1 J^T diag(w)) and whose y is the cotangent
+// of b.  hbar and xbar_pat may be NULL.  Owner-computes, fixed order.
+__global__ __launch_bounds__(kNT) void k_adj_scatter(const int32_t *__restrict__ inv_ptr,
+                                                     const int32_t *__restrict__ inv_slot,
+                                                     const int32_t *__restrict__ heavy, int nheavy, int nlight_blocks,
+                                                     const double *__restrict__ hbar,
+                                                     const double *__restrict__ xbar_pat,
+                                                     const int32_t *__restrict__ perm,
+                                                     const double *__restrict__ s2, double *__restrict__ u,
+                                                     int64_t nU) {
+    const int lane = threadIdx.x & 63;
+    int64_t e = -1;
+    double acc = 0.0;
+    bool owner = false;
+    if ((int)blockIdx.x < nlight_blocks) {
+        e = (int64_t)blockIdx.x * kNT + threadIdx.x;
+        if (e >= nU) return;
+        const int32_t q0 = inv_ptr[e], q1 = inv_ptr[e + 1];
+        if (hbar != nullptr && q1 - q0 > kHeavy) return;
+        if (hbar != nullptr)
+            for (int32_t q = q0; q < q1; ++q) acc += hbar[inv_slot[q]];
+        owner = true;
+    } else {
+        if (hbar == nullptr) return;
+        const int hw = ((int)blockIdx.x - nlight_blocks) * (kNT / 64) + (threadIdx.x >> 6);
+        if (hw >= nheavy) return;
+        e = heavy[hw];
+        const int32_t q0 = inv_ptr[e], q1 = inv_ptr[e + 1];
+        for (int32_t q = q0 + lane; q < q1; q += 64) acc += hbar[inv_slot[q]];
+        acc = wave_sum_d(acc);
+        owner = lane == 0;
+    }
+    if (!owner) return;
+    if (xbar_pat != nullptr) acc += xbar_pat[perm[e]];
+    u[e] = s2[e] * acc;
+}
+
+// r1bar = w x (x of the solve F(xbar / w, 0)); out[perm[e]] = scale r1bar_e
+// (accumulate: +=).  r1bar is kept in x.
+__global__ __launch_bounds__(kNT) void k_adj_post(const double *__restrict__ wt, double *__restrict__ x,
+                                                  const int32_t *__restrict__ perm, double *__restrict__ out,
+                                                  double scale, int accumulate, int64_t nU) {
+    const int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (e >= nU) return;
+    const double r = wt[e] * x[e];
+    x[e] = r;
+    const int32_t pe = perm[e];
+    out[pe] = accumulate ? out[pe] + scale * r : scale * r;
+}
+
+// Cotangents of the iteration's inputs: xbar_k = H_k r1bar, lambar += H_k r1bar / rho.
+__global__ __launch_bounds__(kNT) void k_adj_slots(const int32_t *__restrict__ gather,
+                                                   const double *__restrict__ r1bar, double *__restrict__ blkbar,
+                                                   double *__restrict__ lambar, double inv_rho, int64_t nslots) {
+    const int64_t s = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (s >= nslots) return;
+    const double r = r1bar[gather[s]];
+    blkbar[s] = r;
+    lambar[s] += r * inv_rho;
+}
+
+__global__ __launch_bounds__(kNT) void k_add_to(const double *__restrict__ v, double *__restrict__ out, int n,
+                                                int accumulate) {
+    const int i = blockIdx.x * kNT + threadIdx.x;
+    if (i < n) out[i] = accumulate ? out[i] + v[i] : v[i];
+}
+
 }  // namespace
 
 int scatter_light_blocks(const Dev &d) { return (int)blocks_for(d.nU); }
@@ -735,6 +836,37 @@ void launch_scatter_f64(const Dev &d, const double *packed, double *out, hipStre
 }
 
 int objective_partials() { return 2 * kObjBlocks; }
+
+void launch_adjoint_in(const Dev &d, const double *blkbar, const double *lambar, double rho, float *gP,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_in, dim3(blocks_for(d.nslots)), dim3(kNT), 0, s, blkbar, lambar, rho, gP, d.nslots);
+}
+
+void launch_adjoint_mid(const Dev &d, const float *gW, double *lambar, double rho, double *hbar, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_mid, dim3(blocks_for(d.nslots)), dim3(kNT), 0, s, gW, lambar, rho, 1.0 / rho, hbar,
+                       d.nslots);
+}
+
+void launch_adjoint_scatter(const Dev &d, const double *hbar, const double *xbar_pat, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_scatter, dim3(scatter_blocks(d)), dim3(kNT), 0, s, (const int32_t *)d.inv_ptr,
+                       (const int32_t *)d.inv_slot, (const int32_t *)d.heavy, d.nheavy, scatter_light_blocks(d), hbar,
+                       xbar_pat, (const int32_t *)d.perm, (const double *)d.s2, d.u, d.nU);
+}
+
+void launch_adjoint_post(const Dev &d, double *x, double *out_pat, double scale, int accumulate, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_post, dim3(blocks_for(d.nU)), dim3(kNT), 0, s, (const double *)d.wt, x,
+                       (const int32_t *)d.perm, out_pat, scale, accumulate, d.nU);
+}
+
+void launch_adjoint_slots(const Dev &d, const double *r1bar, double *blkbar, double *lambar, double rho,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_slots, dim3(blocks_for(d.nslots)), dim3(kNT), 0, s, (const int32_t *)d.gather, r1bar,
+                       blkbar, lambar, 1.0 / rho, d.nslots);
+}
+
+void launch_add_to(const double *v, double *out, int n, int accumulate, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_add_to, dim3(blocks_for(n)), dim3(kNT), 0, s, v, out, n, accumulate);
+}
 
 void launch_objectives(const Dev &d, const double *x, const double *y, hipStream_t s) {
     hipLaunchKernelGGL(k_objectives, dim3(kObjBlocks), dim3(kNT), 0, s, (const double *)d.c, (const double *)d.wt, x,

@@ -126,8 +126,9 @@ __global__ __launch_bounds__(kNT) void k_bcheck_primal(const double *__restrict_
             const double eps_d = den_d > 0.0 ? rho * sqrt(d2) / den_d : rho * sqrt(d2);
             ieps[2 * q + 0] = eps_p;
             ieps[2 * q + 1] = eps_d;
-            if (fmax(eps_p, eps_d) <= ctl->tol) {
-                istop[q] = 1;
+            const bool finite = isfinite(eps_p) && isfinite(eps_d);  // NaN or Inf in the instance's iterate: 3
+            if (!finite || fmax(eps_p, eps_d) <= ctl->tol) {
+                istop[q] = finite ? 1 : 3;
                 iiters[q] = n;
                 itime[q] = wall_clock64();
                 atomicSub(nrunning, 1);

@@ -417,7 +417,10 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
         fro += (i == j ? 1.0f : 2.0f) * w * w;
     }
     const float fro2 = block_sum<NT>(fro, sm.redf);
-    const float tau = (a.evals != nullptr || a.evecs != nullptr) ? kTauEig : kTauProj;
+    // standalone calls that return eigenpairs converge them to 2^-23; the
+    // ADMM modes keep the loop's rule also when they save eigenpairs (for the
+    // adjoint of an unrolled iteration), so that iteration is the loop's own
+    const float tau = (a.mode == PROJ_STANDALONE && (a.evals != nullptr || a.evecs != nullptr)) ? kTauEig : kTauProj;
     const float thr = tau * tau * fro2;
 
     const int Kw = k + (k & 1);  // products run over the active size
@@ -745,16 +748,14 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
             a.cpart[4 * (int64_t)id + 2] = s2;
         }
     }
-    if (a.mode == PROJ_STANDALONE) {
-        // eigenpairs of the k x k block: Lambda and the re-orthonormalised V
-        if (a.evals != nullptr)
-            for (int t = tid; t < k; t += NT) a.evals[a.eoff[id] + t] = sm.lam[t];
-        if (a.evecs != nullptr)
-            for (int idx = tid; idx < k * k; idx += NT) {
-                const int i = idx / k, j = idx - i * k;
-                a.evecs[a.voff[id] + idx] = sV[i * LD + j];
-            }
-    }
+    // eigenpairs of the k x k block: Lambda and the re-orthonormalised V
+    if (a.evals != nullptr)
+        for (int t = tid; t < k; t += NT) a.evals[a.eoff[id] + t] = sm.lam[t];
+    if (a.evecs != nullptr)
+        for (int idx = tid; idx < k * k; idx += NT) {
+            const int i = idx / k, j = idx - i * k;
+            a.evecs[a.voff[id] + idx] = sV[i * LD + j];
+        }
     __syncthreads();  // LDS is reused by the next clique of a queue launch
 }
 

@@ -381,6 +381,37 @@ def small_chordal(n: int, p: int, smax: int, m: int, seed: int) -> Problem:
     return _finish(nv, cliques, ei, ej, A, rng, m, meta={"kind": "small_chordal", "seed": seed})
 
 
+def random_sparse(n: int, extra: int, m: int, seed: int) -> Problem:
+    """SDP on a pattern that is not chordal and comes without cliques: the
+    cycle 0-1-...-(n-1)-0 (chordless for n >= 4) plus `extra` random chords,
+    diagonal included.  Dense symmetrised N(0,1) constraints on the pattern,
+    b = A(X0) with X0 = G G^T / n + I, C = A*(y0) + Z0 with Z0 diagonally
+    dominant on the pattern (so positive definite): strictly feasible.
+    clique_ptr is None (the setup computes a chordal extension)."""
+    rng = _rng(seed)
+    edges = {(max(i, (i + 1) % n), min(i, (i + 1) % n)) for i in range(n)}
+    while len(edges) < n + extra:
+        i, j = (int(v) for v in rng.integers(0, n, size=2))
+        if i != j:
+            edges.add((max(i, j), min(i, j)))
+    ent = sorted(edges) + [(i, i) for i in range(n)]
+    ei = np.array([e[0] for e in ent], dtype=np.int32)
+    ej = np.array([e[1] for e in ent], dtype=np.int32)
+    nU = ei.shape[0]
+    w = np.where(ei == ej, 1.0, 2.0)
+    A = _symmetrised_normal(rng, m, ei, ej)
+    G = rng.standard_normal((n, n))
+    x0 = np.einsum("ij,ij->i", G[ei], G[ej]) / n + (ei == ej)
+    z0 = np.where(ei == ej, 0.0, 0.5 * rng.standard_normal(nU))
+    rowsum = np.zeros(n)
+    np.add.at(rowsum, ei, np.abs(z0))
+    np.add.at(rowsum, ej, np.abs(z0))
+    z0[ei == ej] = 1.0 + rowsum[ei[ei == ej]]
+    y0 = rng.standard_normal(m)
+    return Problem(n=n, ei=ei, ej=ej, clique_ptr=None, clique_vert=None, b=A @ (w * x0), c=A.T @ y0 + z0, A=A,
+                   meta={"kind": "random_sparse", "seed": seed, "x0": x0, "y0": y0, "z0": z0})
+
+
 def _peo_cliques(p: int, smin: int, smax: int, omax: int, rng):
     """Clique tree grown in perfect-elimination order: clique 0 has s_0 fresh
     vertices; clique k > 0 draws s_k, a uniform parent j < k and a separator of

@@ -145,3 +145,58 @@ def test_queue_with_many_cliques_per_workgroup(torch):
     assert _rel(xq, xb) <= 1e-5
     assert _rel(lq, lb) <= 1e-5
     assert swq <= 1.25 * swb + 0.05
+
+
+@pytest.mark.parametrize("threads,grid", [(256, 4), (512, 3), (256, 1)])
+def test_queue_with_several_cliques_per_workgroup_vs_oracle(torch, small, threads, grid):
+    """A queue launch with a grid far below the clique count: each workgroup
+    draws cliques of several size buckets in turn (largest first), carrying
+    LDS and the warm-start state from clique to clique, through 30 ADMM
+    iterations; the iterates must match the oracle."""
+    prob, ref = small
+    sol = cdcs.Solver(prob)
+    sol.set_projection_plan(True, threads, grid)
+    t = sol.tuning()
+    assert t["persistent"] and t["grid"] == grid and t["threads"] == threads
+    st = sol.new_state("primal")
+    info = sol.solve(st, form="primal", tol=0.0, max_iter=30, check_every=10)
+    assert info.iters == 30 and info.jacobi_cap_hits == 0
+    assert _rel(st["x"].cpu().numpy(), ref.x) <= 1e-4
+    assert _rel(st["blk"].cpu().numpy().astype(np.float64), cdcs.pack_blocks(ref.blocks)) <= 1e-4
+    assert _rel(_lam(sol, st), np.concatenate([B.ravel() for B in ref.lam])) <= 1e-4
+    sol.close()
+
+
+def test_queue_grid_limits(torch, small):
+    prob, _ = small
+    sol = cdcs.Solver(prob)
+    sol.set_projection_plan(True, 256)
+    gmax = sol.tuning()["grid"]
+    with pytest.raises(cdcs.CdcsError) as e:
+        sol.set_projection_plan(True, 256, gmax + 1)
+    assert e.value.status == cdcs.E_ARG
+    with pytest.raises(cdcs.CdcsError):
+        sol.set_projection_plan(True, 256, -1)
+    sol.close()
+
+
+@pytest.mark.parametrize("plan", [(True, 256, 5), (True, 512, 0), (False, 256, 0), (False, 64, 0)])
+def test_project_cliques_with_the_plan_vs_oracle(torch, small, plan):
+    """cdcs_psd_project_cliques: the handle's launch plan on given blocks
+    (cold start), per clique within 1e-5 ||W||_F of the oracle's projection."""
+    prob, _ = small
+    sol = cdcs.Solver(prob)
+    sol.set_projection_plan(*plan)
+    sizes = np.asarray(sol.sizes)
+    blocks = [synth.random_symmetric(int(s), seed=300 + k) for k, s in enumerate(sizes)]
+    W32 = [np.asarray(B, dtype=np.float32) for B in blocks]
+    Wp = torch.as_tensor(cdcs.pack_blocks(W32), device="cuda")
+    P = cdcs.unpack_blocks(sol.project_cliques(Wp).cpu().numpy(), sizes, sol.offsets)
+    for B, G in zip(W32, P):
+        ref = O.psd_project(B.astype(np.float64))
+        assert np.linalg.norm(G - ref) <= 1e-5 * np.linalg.norm(B.astype(np.float64))
+    # the plan's repeated launches give the same bits (the queue's tickets stay aligned)
+    P2 = sol.project_cliques(Wp).cpu().numpy()
+    P3 = sol.project_cliques(Wp).cpu().numpy()
+    assert np.array_equal(P2, P3)
+    sol.close()
