@@ -425,6 +425,24 @@ cdcs_status cdcs_unrolled_step_vjp(cdcs_handle *h, double rho, const float *eval
 cdcs_status cdcs_affine_project_adjoint(cdcs_handle *h, const double *xbar, double *r1bar, double *r2bar,
                                         hipStream_t stream);
 
+/*
+ * cdcs_affine_project_adjoint without any device allocation, for callers
+ * that cannot allocate (code under HIP graph capture, serving loops, hosts
+ * that forbid hipMalloc after initialisation).  Same inputs, outputs and
+ * results as cdcs_affine_project_adjoint (the same kernels); its staging
+ * buffers (the KKT solve's x and y) are a fixed array in device memory,
+ * 8,454,144 bytes per device, held until the process ends, instead of the
+ * buffers cdcs_affine_project_adjoint allocates at its first call.  Limits:
+ * the handle's pattern entries at most 2^20 and its constraints at most 8192,
+ * each counted as the handle pads them (single-SDP handles: entries to a
+ * multiple of 64, constraints to a multiple of 32).
+ * Calls that overlap on one device race on that array (serialise them, e.g.
+ * one stream).  Errors: CDCS_E_ARG (NULL argument, handle above the limits),
+ * CDCS_E_DEVICE.
+ */
+cdcs_status cdcs_affine_project_adjoint_noalloc(cdcs_handle *h, const double *xbar, double *r1bar, double *r2bar,
+                                                hipStream_t stream);
+
 /* Kernels of one iteration, for cdcs_profile_kernel. */
 typedef enum {
     CDCS_K_PROJECT = 0,   /* fused gather + Jacobi projection + epilogue, all size buckets */

@@ -29,7 +29,7 @@ EXPORTS = ["cdcs_setup", "cdcs_setup_batch", "cdcs_batch_info", "cdcs_get_sizes"
            "cdcs_admm_step", "cdcs_admm_solve_timed", "cdcs_profile_kernel", "cdcs_get_tuning", "cdcs_set_projection_plan",
            "cdcs_residual_history", "cdcs_warm_reset", "cdcs_destroy", "cdcs_last_error", "cdcs_admm_prepare",
            "cdcs_psd_project_cliques", "cdcs_unrolled_step", "cdcs_unrolled_step_vjp",
-           "cdcs_affine_project_adjoint", "cdcs_chordal_extension"]
+           "cdcs_affine_project_adjoint", "cdcs_chordal_extension", "cdcs_affine_project_adjoint_noalloc"]
 
 
 class CdcsLibraryMissing(ImportError):
@@ -122,6 +122,7 @@ def load_library(path: str = LIB_PATH):
     L.cdcs_unrolled_step_vjp.argtypes = [vp, dbl, vp, vp, vp, vp, vp, vp, vp, vp]
     L.cdcs_affine_project_adjoint.argtypes = [vp, vp, vp, vp, vp]
     L.cdcs_chordal_extension.argtypes = [P(_Pattern), P(i64), P(i32), P(i64), vp, vp, vp, vp]
+    L.cdcs_affine_project_adjoint_noalloc.argtypes = [vp, vp, vp, vp, vp]
     L.cdcs_clique_offsets.argtypes = [vp, vp]
     L.cdcs_psd_project_batched.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.cdcs_psd_project_vjp.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]

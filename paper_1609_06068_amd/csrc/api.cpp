@@ -1059,6 +1059,32 @@ cdcs_status get_graph(cdcs_handle *h, const cdcs_state *st, int form, int K, dou
 
 }  // namespace
 
+namespace cdcs {
+
+cdcs_status set_error(cdcs_status st, const std::string &msg) { return fail(st, msg); }
+
+void handle_dims(const cdcs_handle *h, int64_t *ldU, int64_t *ldM) {
+    *ldU = h->d.ldU;
+    *ldM = h->d.ldM;
+}
+
+// The affine adjoint with the solve's x and y staged in xs [ldU] and ys [ldM]
+// (device): r1bar = w F(xbar / w, 0), r2bar = that solve's y.  Every element
+// of xs and ys is written before it is read.
+cdcs_status affine_adjoint_into(cdcs_handle *h, const double *xbar, double *r1bar, double *r2bar, double *xs,
+                                double *ys, hipStream_t stream) {
+    Dev &d = h->d;
+    launch_adjoint_scatter(d, nullptr, xbar, stream);
+    if (d.batch) launch_baffine(d, d.b, 0.0, xs, ys, nullptr, nullptr, stream);
+    else launch_affine(d, d.b, 0.0, xs, ys, nullptr, stream);
+    launch_adjoint_post(d, xs, r1bar, 1.0, 0, stream);
+    launch_add_to(ys, r2bar, d.m, 0, stream);
+    HIP_OK(hipGetLastError());
+    return CDCS_OK;
+}
+
+}  // namespace cdcs
+
 extern "C" {
 
 const char *cdcs_last_error(void) { return g_err.c_str(); }
@@ -1529,15 +1555,7 @@ cdcs_status cdcs_affine_project_adjoint(cdcs_handle *h, const double *xbar, doub
                                         hipStream_t stream) {
     if (!h || !xbar || !r1bar || !bbar) return fail(CDCS_E_ARG, "NULL argument");
     CK(diff_buffers(h));
-    Dev &d = h->d;
-    cdcs_handle::Diff &f = h->diff;
-    launch_adjoint_scatter(d, nullptr, xbar, stream);
-    if (d.batch) launch_baffine(d, d.b, 0.0, f.x, f.y, nullptr, nullptr, stream);
-    else launch_affine(d, d.b, 0.0, f.x, f.y, nullptr, stream);
-    launch_adjoint_post(d, f.x, r1bar, 1.0, 0, stream);
-    launch_add_to(f.y, bbar, d.m, 0, stream);
-    HIP_OK(hipGetLastError());
-    return CDCS_OK;
+    return cdcs::affine_adjoint_into(h, xbar, r1bar, bbar, h->diff.x, h->diff.y, stream);
 }
 
 cdcs_status cdcs_admm_solve_timed(cdcs_handle *h, const cdcs_state *st, const cdcs_options *opts, cdcs_info *info,

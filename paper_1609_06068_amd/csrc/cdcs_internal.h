@@ -253,6 +253,12 @@ void launch_adjoint_slots(const Dev &d, const double *r1bar, double *blkbar, dou
                           hipStream_t s);
 void launch_add_to(const double *v, double *out, int n, int accumulate, hipStream_t s);
 
+// api.cpp helpers for the entry points of other translation units.
+cdcs_status set_error(cdcs_status st, const std::string &msg);   // message of cdcs_last_error
+void handle_dims(const cdcs_handle *h, int64_t *ldU, int64_t *ldM);
+cdcs_status affine_adjoint_into(cdcs_handle *h, const double *xbar, double *r1bar, double *r2bar, double *xs,
+                                double *ys, hipStream_t stream);
+
 // Chordal extension of a pattern and its maximal cliques (chordal.cpp, host).
 struct ChordalExt {
     bool chordal_input = false;           // the pattern was chordal already (no fill)
