@@ -61,7 +61,12 @@
 extern "C" {
 #endif
 
-#define CDCS_MAX_CLIQUE 96
+/* Largest clique of a handle.  Cliques of up to CDCS_MAX_BATCHED_CLIQUE
+ * vertices are projected by Jacobi eigensolves in one workgroup's LDS (the
+ * handle-free cdcs_psd_project_batched and the adjoint take only these);
+ * larger ones by the matrix sign function on the matrix cores. */
+#define CDCS_MAX_CLIQUE 1024
+#define CDCS_MAX_BATCHED_CLIQUE 126
 
 typedef enum {
     CDCS_OK = 0,
@@ -161,7 +166,10 @@ typedef struct {
 /* Sizes of a handle.  sparse_a = 1 if A is kept sparse (nnz_a coefficients),
  * 0 if it is stored densely (nnz_a = m * nnz).  sparse_factor = 1 if the
  * inverse Cholesky factor is kept as CSR (nnz_factor nonzeros in L^-1), 0 if
- * dense (nnz_factor = m (m + 1) / 2). */
+ * dense (nnz_factor = m (m + 1) / 2).  nnz_l > 0: the factor of
+ * A D^-1 A^T was computed sparse (symbolic elimination order, then the
+ * numeric factor on the device; no dense m x m matrix), with nnz_l nonzeros
+ * in L; 0: it was factored dense. */
 typedef struct {
     int32_t n, m, p, smax;
     int64_t nnz, nslots;
@@ -169,6 +177,7 @@ typedef struct {
     int64_t nnz_a;
     int64_t nnz_factor;
     int64_t nwarm;        /* sum of s_k^2: length of cdcs_state.vw */
+    int64_t nnz_l;        /* nonzeros of the sparse Cholesky factor (0: dense factor) */
 } cdcs_sizes;
 
 /*
@@ -197,12 +206,19 @@ cdcs_status cdcs_chordal_extension(const cdcs_pattern *pattern, int64_t *nfill, 
 
 /*
  * Setup step of Algorithms 1 and 2: the chordal decomposition data and the
- * cached factor of the KKT system (Sec. III-B.1).  Validates the pattern and cliques, builds the entry selectors H_k and the
- * overlap counts D = sum_k H_k^T H_k (Sec. III-B.1), uploads the data, forms
- * M = A diag(w/D) A^T on the device in FP64 and factors it (Cholesky), caching
- * the inverse triangular factor for the affine projection (as CSR when L^-1
- * has under an eighth of a triangle's entries, else dense), and times the
- * launch forms of the batched projection (cdcs_get_tuning).
+ * cached factor of the KKT system (Sec. III-B.1).  Validates the pattern and
+ * cliques, builds the entry selectors H_k and the overlap counts
+ * D = sum_k H_k^T H_k (Sec. III-B.1), uploads the data, factors
+ * M = A diag(w/D) A^T (Cholesky, FP64, on the device) and caches the inverse
+ * triangular factor for the affine projection, and times the launch forms of
+ * the batched projection (cdcs_get_tuning).  The factor is sparse when A is
+ * kept sparse and the inverse factor stays sparse: a symbolic step on the
+ * host orders M's rows (constraints sharing a pattern entry are adjacent;
+ * perfect elimination order when that graph is chordal, else minimum degree)
+ * and the device computes L column by column, level by level of the
+ * elimination tree, then L^-1 along the tree paths (CSR, no m x m matrix).
+ * Otherwise M is formed and factored dense (m <= 8192) and L^-1 kept as CSR
+ * when it has under an eighth of a triangle's entries.
  *   b [m] host FP64, c [nnz] host FP64 (values of C on the entries).
  *   opts may be NULL (rho = 1).  The cached factor does not depend on rho.
  *   cliques may be NULL: the pattern is then extended to a chordal one and
@@ -236,7 +252,7 @@ typedef struct {
  * packed offsets from cdcs_clique_offsets; instance boundaries are the
  * prefix sums of the per-instance nnz, slots and m).  One projection launch
  * covers every instance's cliques; the affine step uses one cached factor per
- * instance (block-diagonal A).  cdcs_admm_solve (Algorithm 1 only) stops each
+ * instance (block-diagonal A).  cdcs_admm_solve (Algorithm 1 or 2) stops each
  * instance on its own residuals: once max(eps_p, eps_d) <= tol, that
  * instance's state is frozen and its time to tolerance is recorded
  * (cdcs_batch_info).  Each instance needs m <= 256.  Errors as cdcs_setup
@@ -266,7 +282,7 @@ cdcs_status cdcs_clique_offsets(const cdcs_handle *h, int64_t *off_host);
  * and (E:zkUpdate): P(W) = Q max(Lambda, 0) Q^T for each of nb independent
  * symmetric blocks, FP32 (round-robin parallel Jacobi, one workgroup per
  * block).  Handle-free.
- *   sizes [nb] device int32, each in 1..CDCS_MAX_CLIQUE
+ *   sizes [nb] device int32, each in 1..CDCS_MAX_BATCHED_CLIQUE
  *   off   [nb+1] device int64, packed offsets (prefix sums of s(s+1)/2)
  *   W, P  [off[nb]] device FP32 packed lower triangles (may not alias)
  *   evals [sum s] device FP32 or NULL: eigenvalues, block t at eoff[t]
@@ -280,7 +296,7 @@ cdcs_status cdcs_clique_offsets(const cdcs_handle *h, int64_t *off_host);
  * rounding) of P(W).  When evals or evecs are requested the sweeps run to
  * 2^-23 ||W||_F, so the eigenpairs themselves are converged.
  * A block whose size lies outside 1..smax is skipped (its P is not written);
- * nb <= 0 is a no-op.  Errors: CDCS_E_ARG (smax outside 1..CDCS_MAX_CLIQUE,
+ * nb <= 0 is a no-op.  Errors: CDCS_E_ARG (smax outside 1..CDCS_MAX_BATCHED_CLIQUE,
  * NULL W/P/sizes/off), CDCS_E_DEVICE.
  */
 cdcs_status cdcs_psd_project_batched(int32_t nb, int32_t smax, const int32_t *sizes,
@@ -488,7 +504,7 @@ cdcs_status cdcs_profile_kernel(cdcs_handle *h, const cdcs_state *st, int32_t fo
 /*
  * Launch plan of the batched projection inside the ADMM loop ("thousands of
  * cliques of uneven sizes" in one step, Sec. III-B.2): cliques are padded to
- * size buckets S in {16, 32, 48, 64, 80, 96}.  Either one persistent launch
+ * size buckets S in {16, 32, 48, 64, 80, 96, 112, 128}.  Either one persistent launch
  * draws every clique, largest first, from a device work queue
  * (persistent = 1, `threads` per workgroup, `grid` workgroups), or each
  * bucket gets its own launch with its own workgroup size (persistent = 0).
@@ -512,7 +528,8 @@ typedef struct {
 cdcs_status cdcs_get_tuning(const cdcs_handle *h, cdcs_tuning *out);
 
 /*
- * Override the tuned plan: persistent = 1 with threads 256 or 512 and `grid`
+ * Override the tuned plan: persistent = 1 with threads 256 or 512 (512 only
+ * when a clique has more than 96 vertices) and `grid`
  * workgroups (0: as many as stay resident, at most one per clique; a smaller
  * grid makes every workgroup project several cliques), or persistent = 0 with
  * threads 64, 256 or 512 for every bucket that has that size built (64:

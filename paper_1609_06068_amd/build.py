@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcdcs.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["kernels_project.hip", "kernels_affine.hip", "kernels_setup.hip", "kernels_batch.hip", "api.cpp",
-           "chordal.cpp", "noalloc.hip"]
+           "chordal.cpp", "noalloc.hip", "kernels_big.hip"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]

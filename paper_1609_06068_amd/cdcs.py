@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libcdcs.so")
 OK, E_ARG, E_PATTERN, E_RANK, E_DEVICE, E_NOMEM, E_NOT_CONVERGED, E_NUMERIC = range(8)
 K_PROJECT, K_GEMV_AU, K_TRMV, K_GEMV_ATY, K_SCATTER = range(5)
 PRIMAL, DUAL = 0, 1
-MAX_CLIQUE = 96
+MAX_CLIQUE = 1024
+MAX_BATCHED_CLIQUE = 126
 STATUS_NAMES = {0: "CDCS_OK", 1: "CDCS_E_ARG", 2: "CDCS_E_PATTERN", 3: "CDCS_E_RANK", 4: "CDCS_E_DEVICE",
                 5: "CDCS_E_NOMEM", 6: "CDCS_E_NOT_CONVERGED", 7: "CDCS_E_NUMERIC"}
 
@@ -94,7 +95,7 @@ class _Sizes(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("p", ctypes.c_int32), ("smax", ctypes.c_int32),
                 ("nnz", ctypes.c_int64), ("nslots", ctypes.c_int64), ("sparse_a", ctypes.c_int32),
                 ("sparse_factor", ctypes.c_int32), ("nnz_a", ctypes.c_int64), ("nnz_factor", ctypes.c_int64),
-                ("nwarm", ctypes.c_int64)]
+                ("nwarm", ctypes.c_int64), ("nnz_l", ctypes.c_int64)]
 
 
 _lib = None
@@ -236,6 +237,7 @@ class Solver:
         self.sparse_a, self.nnz_a = bool(sz.sparse_a), sz.nnz_a
         self.sparse_factor, self.nnz_factor = bool(sz.sparse_factor), sz.nnz_factor
         self.nwarm = sz.nwarm
+        self.nnz_l = sz.nnz_l  # > 0: sparse Cholesky factor of A D^-1 A^T
         off = np.empty(self.p + 1, dtype=np.int64)
         _check(L.cdcs_clique_offsets(h, _np_ptr(off)), "cdcs_clique_offsets")
         self.offsets = off
@@ -515,8 +517,8 @@ def psd_project_batched(W, sizes, offsets=None, smax=None, eig: bool = False, st
         nb = int(sizes_h.shape[0])
         if smax is None:
             smax = int(sizes_h.max()) if nb else 1
-        if nb and (sizes_h.min() < 1 or sizes_h.max() > MAX_CLIQUE):
-            raise CdcsError(E_ARG, "block sizes must lie in 1..96")
+        if nb and (sizes_h.min() < 1 or sizes_h.max() > MAX_BATCHED_CLIQUE):
+            raise CdcsError(E_ARG, f"block sizes must lie in 1..{MAX_BATCHED_CLIQUE}")
         sizes_d = torch.as_tensor(sizes_h.astype(np.int32), device=dev)
         if offsets is None:
             offsets = torch.as_tensor(packed_offsets(sizes_h), device=dev)

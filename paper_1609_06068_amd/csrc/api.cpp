@@ -81,6 +81,7 @@ struct cdcs_handle {
     std::unique_ptr<Batch> batch_host;
     int last_iters = 0;
     double last_rho = 1.0;
+    int last_form = CDCS_PRIMAL;
     // differentiation (allocated at the first call that needs them)
     struct Diff {
         double *c = nullptr;       // [ldU] caller's c in internal entry order
@@ -347,18 +348,52 @@ cdcs_status upload_common(cdcs_handle *h, const std::vector<int32_t> &size, cons
     std::vector<int32_t> inv_ptr, inv_slot, heavy;
     inverse_map(gather, cnt, heavy_above, inv_ptr, inv_slot, heavy);
     d.nheavy = (int32_t)heavy.size();
-    // Cliques by decreasing size, split into LDS size buckets.
-    std::vector<int32_t> order((size_t)p);
-    for (int32_t k = 0; k < p; ++k) order[(size_t)k] = k;
+    // Cliques by decreasing size: those that fit a workgroup's LDS split into
+    // size buckets, the larger ones projected by the Newton-Schulz path.
+    std::vector<int32_t> order, big;
+    for (int32_t k = 0; k < p; ++k) (size[(size_t)k] > kMaxLdsClique ? big : order).push_back(k);
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t bq) { return size[(size_t)a] > size[(size_t)bq]; });
-    constexpr int NBK = 6;
-    const int bmax[NBK] = {16, 32, 48, 64, 80, 96};
+    d.p_lds = (int32_t)order.size();
+    d.smax_lds = order.empty() ? 1 : size[(size_t)order.front()];
+    constexpr int NBK = 8;
+    const int bmax[NBK] = {16, 32, 48, 64, 80, 96, 112, 128};
     std::vector<std::vector<int32_t>> bl(NBK);
     for (int32_t k : order) {
         const int S = proj_bucket(size[(size_t)k]);
         for (int q = 0; q < NBK; ++q)
             if (bmax[q] == S) bl[(size_t)q].push_back(k);
+    }
+    if (!big.empty()) {
+        BigCliques &B = d.big;
+        std::vector<int32_t> bn, bN;
+        std::vector<int64_t> boff(1, 0);
+        int32_t tmax = 0;
+        for (int32_t k : big) {
+            const int32_t sk = size[(size_t)k], Nk = (sk + 63) / 64 * 64;
+            bn.push_back(sk);
+            bN.push_back(Nk);
+            boff.push_back(boff.back() + (int64_t)Nk * Nk);
+            tmax = std::max(tmax, Nk / 64);
+        }
+        B.nbig = (int32_t)big.size();
+        B.tmax2 = tmax * tmax;
+        int32_t *ids_d = nullptr, *n_d = nullptr, *N_d = nullptr;
+        int64_t *boff_d = nullptr;
+        CK(upload(h, &ids_d, big, s));
+        CK(upload(h, &n_d, bn, s));
+        CK(upload(h, &N_d, bN, s));
+        CK(upload(h, &boff_d, boff, s));
+        B.ids = ids_d;
+        B.n = n_d;
+        B.N = N_d;
+        B.boff = boff_d;
+        CK(h->alloc(&B.W, boff.back()));
+        CK(h->alloc(&B.X0, boff.back()));
+        CK(h->alloc(&B.X1, boff.back()));
+        CK(h->alloc(&B.Y, boff.back()));
+        CK(h->alloc(&B.part, (int64_t)B.nbig * B.tmax2));
+        CK(h->alloc(&B.inv_norm, B.nbig));
     }
     CK(upload(h, &d.clq_size, size, s));
     CK(upload(h, &d.clq_off, h->off_host, s));
@@ -465,12 +500,193 @@ cdcs_status compress_factors(cdcs_handle *h, hipStream_t s) {
     return CDCS_OK;
 }
 
+// Symbolic sparse Cholesky of M = A D^-1 A^T (host, integer work).  The graph
+// of M joins two constraints that share a pattern entry; its elimination
+// order (perfect when the graph is chordal, else minimum degree) gives the
+// structure of every column of L (factor order), the elimination tree
+// (parent = first row below the diagonal), its levels (a column's
+// descendants are in lower levels), the row lists (columns k < j with
+// L_jk != 0 and where row j sits in column k) and the structure of
+// X = L^-1: column j is nonzero on the tree path from j to its root.
+// Returns false when a path is longer than max_path or X would hold more
+// than max_x entries (then the dense factor is used).
+struct SpSym {
+    std::vector<int32_t> order, pinv, cp, ri, rk_ptr, rk_col, rk_pos, level_cols, level_off, xr;
+    std::vector<int64_t> xp;
+};
+
+bool sp_symbolic(int32_t m, const std::vector<int32_t> &tcp, const std::vector<int32_t> &tcr, int max_path,
+                 int64_t max_x, SpSym &S) {
+    std::vector<std::vector<int32_t>> adj((size_t)m);
+    for (size_t t = 0; t + 1 < tcp.size(); ++t)
+        for (int32_t a = tcp[t]; a < tcp[t + 1]; ++a)
+            for (int32_t b2 = tcp[t]; b2 < a; ++b2) {
+                adj[(size_t)tcr[(size_t)a]].push_back(tcr[(size_t)b2]);
+                adj[(size_t)tcr[(size_t)b2]].push_back(tcr[(size_t)a]);
+            }
+    for (auto &l : adj) {
+        std::sort(l.begin(), l.end());
+        l.erase(std::unique(l.begin(), l.end()), l.end());
+    }
+    std::vector<char> used((size_t)m, 1);
+    std::vector<std::vector<int32_t>> later;
+    elimination_order(m, adj, used, S.order, later);
+    if ((int32_t)S.order.size() != m) return false;
+    S.pinv.assign((size_t)m, 0);
+    for (int32_t j = 0; j < m; ++j) S.pinv[(size_t)S.order[(size_t)j]] = j;
+    S.cp.assign(1, 0);
+    std::vector<int32_t> parent((size_t)m, -1), col;
+    for (int32_t j = 0; j < m; ++j) {
+        col.assign(1, j);
+        for (int32_t u : later[(size_t)S.order[(size_t)j]]) col.push_back(S.pinv[(size_t)u]);
+        std::sort(col.begin() + 1, col.end());
+        if (col.size() > 1) parent[(size_t)j] = col[1];
+        S.ri.insert(S.ri.end(), col.begin(), col.end());
+        S.cp.push_back((int32_t)S.ri.size());
+    }
+    // levels: a column after all of its descendants
+    std::vector<int32_t> lev((size_t)m, 0);
+    int32_t nlev = 0;
+    for (int32_t j = 0; j < m; ++j) {
+        nlev = std::max(nlev, lev[(size_t)j] + 1);
+        if (parent[(size_t)j] >= 0)
+            lev[(size_t)parent[(size_t)j]] = std::max(lev[(size_t)parent[(size_t)j]], lev[(size_t)j] + 1);
+    }
+    S.level_off.assign((size_t)nlev + 1, 0);
+    for (int32_t j = 0; j < m; ++j) ++S.level_off[(size_t)lev[(size_t)j] + 1];
+    for (int32_t l = 0; l < nlev; ++l) S.level_off[(size_t)l + 1] += S.level_off[(size_t)l];
+    S.level_cols.assign((size_t)m, 0);
+    {
+        std::vector<int32_t> fp(S.level_off.begin(), S.level_off.end() - 1);
+        for (int32_t j = 0; j < m; ++j) S.level_cols[(size_t)fp[(size_t)lev[(size_t)j]]++] = j;
+    }
+    // row lists (k increasing)
+    std::vector<int32_t> rcount((size_t)m, 0);
+    for (int32_t k = 0; k < m; ++k)
+        for (int32_t q = S.cp[(size_t)k] + 1; q < S.cp[(size_t)k + 1]; ++q) ++rcount[(size_t)S.ri[(size_t)q]];
+    S.rk_ptr.assign((size_t)m + 1, 0);
+    for (int32_t j = 0; j < m; ++j) S.rk_ptr[(size_t)j + 1] = S.rk_ptr[(size_t)j] + rcount[(size_t)j];
+    S.rk_col.resize((size_t)S.rk_ptr[(size_t)m]);
+    S.rk_pos.resize((size_t)S.rk_ptr[(size_t)m]);
+    {
+        std::vector<int32_t> fp(S.rk_ptr.begin(), S.rk_ptr.end() - 1);
+        for (int32_t k = 0; k < m; ++k)
+            for (int32_t q = S.cp[(size_t)k] + 1; q < S.cp[(size_t)k + 1]; ++q) {
+                const int32_t i = S.ri[(size_t)q];
+                S.rk_col[(size_t)fp[(size_t)i]] = k;
+                S.rk_pos[(size_t)fp[(size_t)i]++] = q - S.cp[(size_t)k];
+            }
+    }
+    // X = L^-1 by columns: the tree paths
+    std::vector<int32_t> plen((size_t)m, 1);
+    int64_t nx = 0;
+    for (int32_t j = m - 1; j >= 0; --j) {
+        if (parent[(size_t)j] >= 0) plen[(size_t)j] = 1 + plen[(size_t)parent[(size_t)j]];
+        if (plen[(size_t)j] > max_path) return false;
+        nx += plen[(size_t)j];
+    }
+    if (nx > max_x) return false;
+    S.xp.assign(1, 0);
+    S.xr.reserve((size_t)nx);
+    for (int32_t j = 0; j < m; ++j) {
+        for (int32_t v = j; v >= 0; v = parent[(size_t)v]) S.xr.push_back(v);
+        S.xp.push_back((int64_t)S.xr.size());
+    }
+    return true;
+}
+
+// Numeric sparse factor on the device from the symbolic step, then the CSR
+// copies the affine step multiplies by: y1 = L^-1 (P t) with the columns
+// labelled by the original rows, and y = P^T L^-T y1 with the rows labelled
+// by the original rows (P M P^T = L L^T, so M^-1 = P^T L^-T L^-1 P).
+cdcs_status sparse_factor(cdcs_handle *h, const SpSym &S, const int32_t *tid_d, hipStream_t s) {
+    Dev &d = h->d;
+    const int32_t m = d.m;
+    SpFactor f;
+    int32_t *order_d, *pinv_d, *cp_d, *ri_d, *rkp_d, *rkc_d, *rkq_d, *lc_d, *xr_d;
+    int64_t *xp_d;
+    CK(upload(h, &order_d, S.order, s));
+    CK(upload(h, &pinv_d, S.pinv, s));
+    CK(upload(h, &cp_d, S.cp, s));
+    CK(upload(h, &ri_d, S.ri, s));
+    CK(upload(h, &rkp_d, S.rk_ptr, s));
+    CK(upload(h, &rkc_d, S.rk_col, s));
+    CK(upload(h, &rkq_d, S.rk_pos, s));
+    CK(upload(h, &lc_d, S.level_cols, s));
+    CK(upload(h, &xp_d, S.xp, s));
+    CK(upload(h, &xr_d, S.xr, s));
+    f.order = order_d;
+    f.pinv = pinv_d;
+    f.cp = cp_d;
+    f.ri = ri_d;
+    f.rk_ptr = rkp_d;
+    f.rk_col = rkc_d;
+    f.rk_pos = rkq_d;
+    f.level_cols = lc_d;
+    f.xp = xp_d;
+    f.xr = xr_d;
+    const int64_t nnzL = (int64_t)S.ri.size(), nnzX = (int64_t)S.xr.size();
+    CK(h->alloc(&f.Lv, nnzL));
+    CK(h->alloc(&f.diag0, m));
+    CK(h->alloc(&f.xv, nnzX));
+    launch_spchol_fill(d, f, tid_d, s);
+    launch_spchol(d, f, S.level_off, d.info, s);
+    // CSR copies: rows of X (columns relabelled to original rows) and rows of
+    // P^T X^T (= columns of X, in original row order)
+    std::vector<int32_t> li_ptr((size_t)m + 1, 0), li_col((size_t)nnzX), lt_ptr((size_t)m + 1, 0),
+        lt_col((size_t)nnzX);
+    std::vector<int64_t> li_idx((size_t)nnzX), lt_idx((size_t)nnzX);
+    for (int64_t q = 0; q < nnzX; ++q) ++li_ptr[(size_t)S.xr[(size_t)q] + 1];
+    for (int32_t r = 0; r < m; ++r) li_ptr[(size_t)r + 1] += li_ptr[(size_t)r];
+    {
+        std::vector<int32_t> fp(li_ptr.begin(), li_ptr.end() - 1);
+        for (int32_t cidx = 0; cidx < m; ++cidx)  // columns increasing: each row's columns increase
+            for (int64_t q = S.xp[(size_t)cidx]; q < S.xp[(size_t)cidx + 1]; ++q) {
+                const int32_t r = S.xr[(size_t)q];
+                li_col[(size_t)fp[(size_t)r]] = S.order[(size_t)cidx];
+                li_idx[(size_t)fp[(size_t)r]++] = q;
+            }
+    }
+    for (int32_t i = 0; i < m; ++i) {
+        const int32_t cidx = S.pinv[(size_t)i];
+        lt_ptr[(size_t)i + 1] = lt_ptr[(size_t)i] + (int32_t)(S.xp[(size_t)cidx + 1] - S.xp[(size_t)cidx]);
+        int64_t o = lt_ptr[(size_t)i];
+        for (int64_t q = S.xp[(size_t)cidx]; q < S.xp[(size_t)cidx + 1]; ++q, ++o) {
+            lt_col[(size_t)o] = S.xr[(size_t)q];
+            lt_idx[(size_t)o] = q;
+        }
+    }
+    int64_t *li_idx_d = nullptr, *lt_idx_d = nullptr;
+    CK(upload(h, &d.li_ptr, li_ptr, s));
+    CK(upload(h, &d.li_col, li_col, s));
+    CK(upload(h, &d.lt_ptr, lt_ptr, s));
+    CK(upload(h, &d.lt_col, lt_col, s));
+    CK(upload(h, &li_idx_d, li_idx, s));
+    CK(upload(h, &lt_idx_d, lt_idx, s));
+    CK(h->alloc(&d.li_val, nnzX));
+    CK(h->alloc(&d.lt_val, nnzX));
+    launch_gather_vals(f.xv, li_idx_d, d.li_val, nnzX, s);
+    launch_gather_vals(f.xv, lt_idx_d, d.lt_val, nnzX, s);
+    int32_t info_h[4] = {0, 0, 0, 0};
+    HIP_OK(hipMemcpyAsync(info_h, d.info, sizeof(info_h), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (info_h[0] != 0)
+        return fail(CDCS_E_RANK,
+                    "A D^-1 A^T is not positive definite (pivot " + std::to_string(info_h[1]) + "): A is rank deficient");
+    d.sparse_linv = 1;
+    d.spchol = 1;
+    d.nnz_linv = nnzX;
+    d.nnz_l = nnzL;
+    CK(tune_projection(h, s));
+    HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    return CDCS_OK;
+}
+
 cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraints *A, const double *b,
                   const double *c, const cdcs_cliques *cl, hipStream_t s) {
     Dev &d = h->d;
     HostProblem P;
     CK(host_problem(pat, A, b, c, cl, 64, true, P));
-    if (P.m > 8192) return fail(CDCS_E_ARG, "m > 8192 is not supported by the dense factor");
     d.n = P.n;
     d.m = P.m;
     d.p = P.p;
@@ -491,6 +707,7 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
     HIP_OK(hipMemsetAsync(d.u, 0, (size_t)d.ldU * sizeof(double), s));
     const int64_t nU = P.nU, m = P.m;
     std::vector<int32_t> tid;  // touched-entry index of each coefficient (sparse setup only)
+    std::vector<int32_t> tcp_h, tcr_h;  // the touched entries' constraint rows (sparse setup only)
     if (P.sparse) {
         // Coefficients by touched entry (the columns of A that are not zero).
         d.sparse = 1;
@@ -523,6 +740,8 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
         CK(upload(h, &d.tc_ptr, tc_ptr, s));
         CK(upload(h, &d.tc_row, tc_row, s));
         CK(upload(h, &d.tc_val, tc_val, s));
+        tcp_h.swap(tc_ptr);
+        tcr_h.swap(tc_row);
     } else {
         // A (w-scaled, FP32) row-major and transposed.
         std::vector<float> AwT((size_t)(nU * d.ldM), 0.0f);
@@ -532,7 +751,18 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
         CK(upload(h, &d.AwT, AwT, s));
     }
 
-    // KKT factor: M = Aw diag(s2) Aw^T, Cholesky, inverse factors.
+    // KKT factor: sparse when A is kept sparse and the factor's inverse stays
+    // sparse (the symbolic step decides); otherwise M = Aw diag(s2) Aw^T
+    // dense, Cholesky, inverse factors.
+    if (d.sparse) {
+        SpSym S;
+        if (sp_symbolic((int32_t)m, tcp_h, tcr_h, spinv_max_path(), (int64_t)m * (m + 1) / 2 / 8, S)) {
+            int32_t *tid_d = nullptr;
+            CK(upload(h, &tid_d, tid, s));
+            return sparse_factor(h, S, tid_d, s);
+        }
+    }
+    if (m > 8192) return fail(CDCS_E_ARG, "m > 8192 is not supported by the dense factor");
     double *M = nullptr, *diag0 = nullptr;
     HIP_OK(hipMalloc(&M, (size_t)m * m * sizeof(double)));
     hipError_t e1 = hipMalloc(&diag0, (size_t)m * sizeof(double));
@@ -580,7 +810,7 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
     std::vector<int32_t> size, gather, cnt, perm;
     std::vector<double> wt, invD, s2, c, b;
     std::vector<float> Aw;
-    std::vector<int32_t> sblk, sblk_off(1, 0), syrk_jobs, trtri_jobs, rjobs, ejobs, nch;
+    std::vector<int32_t> sblk, sblk_off(1, 0), vblk, vblk_off(1, 0), syrk_jobs, trtri_jobs, rjobs, ejobs, nch;
     std::vector<int64_t> p_off;
     int64_t ptot = 0;
     h->off_host.assign(1, 0);
@@ -593,6 +823,9 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
         cdcs_status st = host_problem(pr.pattern, pr.A, pr.b, pr.c, pr.cliques, 4, false, P);
         if (st != CDCS_OK) return fail(st, "problem " + std::to_string(q) + ": " + g_err);
         if (P.m > 256) return fail(CDCS_E_ARG, "problem " + std::to_string(q) + ": batched factors need m <= 256");
+        if (P.smax > kMaxLdsClique)
+            return fail(CDCS_E_ARG, "problem " + std::to_string(q) + ": batch handles take cliques of at most " +
+                                        std::to_string(kMaxLdsClique) + " vertices");
         const int64_t u0 = U_off.back();
         const int64_t slot0 = h->off_host.back();
         for (int32_t k = 0; k < P.p; ++k) {
@@ -631,6 +864,14 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
             sblk.push_back(0);
         }
         sblk_off.push_back((int32_t)(sblk.size() / 4));
+        // Alg. 2 epilogue blocks of <= 256 slots inside the instance
+        for (int64_t s0 = 0; s0 < P.nslots; s0 += 256) {
+            vblk.push_back(q);
+            vblk.push_back((int32_t)(slot0 + s0));
+            vblk.push_back((int32_t)(slot0 + std::min<int64_t>(P.nslots, s0 + 256)));
+            vblk.push_back(0);
+        }
+        vblk_off.push_back((int32_t)(vblk.size() / 4));
         const int T = (P.m + 31) / 32;
         for (int I = 0; I < T; ++I)
             for (int J = 0; J <= I; ++J) {
@@ -745,6 +986,10 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
     B.nsblk = (int32_t)(sblk.size() / 4);
     B.nsyrk = (int32_t)(syrk_jobs.size() / 4);
     CK(h->alloc(&d.spart, 2 * (int64_t)B.nsblk));
+    CK(upload(h, &B.vblk, vblk, s));
+    CK(upload(h, &B.vblk_off, vblk_off, s));
+    B.nvblk = (int32_t)(vblk.size() / 4);
+    CK(h->alloc(&d.vpart, 5 * (int64_t)B.nvblk));  // per slot block (the single-SDP layout is per 256 slots)
     CK(h->alloc(&B.istop, nprob));
     HIP_OK(hipMemsetAsync(B.istop, 0, (size_t)nprob * sizeof(int32_t), s));
     CK(h->alloc(&B.iiters, nprob));
@@ -832,10 +1077,11 @@ cdcs_status diff_buffers(cdcs_handle *h) {
 // The projection of every clique with the handle's plan.
 void launch_plan(cdcs_handle *h, ProjArgs a, hipStream_t s) {
     const Dev &d = h->d;
+    launch_big_projection(a, d.big, s);  // cliques above the LDS limit, if any
     if (h->plan.queue) {
-        a.nblk = d.p;
+        a.nblk = d.p_lds;
         a.ids = d.order;
-        launch_project_queue(a, d.smax, h->plan.nt, h->plan.grid, h->ticket, s);
+        launch_project_queue(a, d.smax_lds, h->plan.nt, h->plan.grid, h->ticket, s);
         return;
     }
     for (const Bucket &bk : h->buckets) {
@@ -857,8 +1103,9 @@ int device_cus(cdcs_handle *h) {
 }
 
 int queue_grid(cdcs_handle *h, int nt) {
-    const int occ = project_queue_occupancy(h->d.smax, nt);
-    return occ < 1 ? 0 : std::min(h->d.p, occ * device_cus(h));
+    if (h->d.p_lds < 1) return 0;
+    const int occ = project_queue_occupancy(h->d.smax_lds, nt);
+    return occ < 1 ? 0 : std::min(h->d.p_lds, occ * device_cus(h));
 }
 
 // Autotuner: time every candidate launch form of the projection on this
@@ -933,9 +1180,9 @@ cdcs_status tune_projection(cdcs_handle *h, hipStream_t s) {
         if (grid < 1) continue;
         HIP_OK(hipMemsetAsync(h->ticket, 0, sizeof(unsigned long long), s));
         ProjArgs b = a;
-        b.nblk = d.p;
+        b.nblk = d.p_lds;
         b.ids = d.order;
-        const float us = time_us([&]() { launch_project_queue(b, d.smax, nt, grid, h->ticket, s); });
+        const float us = time_us([&]() { launch_project_queue(b, d.smax_lds, nt, grid, h->ticket, s); });
         if (us < qbest) {
             qbest = us;
             h->plan.nt = nt;
@@ -1006,11 +1253,20 @@ void enqueue_iteration(cdcs_handle *h, const cdcs_state *st, int form, double rh
         if (tm) tm->around(k, s, fn);
         else fn();
     };
-    if (d.batch) {  // Algorithm 1, per-instance stopping
+    if (d.batch && form == CDCS_PRIMAL) {  // Algorithm 1, per-instance stopping
         timed(CDCS_K_SCATTER, [&] { launch_bscatter_primal(d, st->blk, st->lam, rho, s); });
         launch_bcheck_primal(d, rho, s);
         timed(CDCS_K_GEMV_AU, [&] { launch_baffine(d, d.b, 1.0, st->x, st->y, d.ctl, d.batch->istop, s); });
         timed(CDCS_K_PROJECT, [&] { launch_projection(h, PROJ_PRIMAL, st, rho, s); });
+        return;
+    }
+    if (d.batch) {  // Algorithm 2, per-instance stopping
+        timed(CDCS_K_PROJECT, [&] { launch_projection(h, PROJ_DUAL, st, rho, s); });
+        timed(CDCS_K_SCATTER, [&] { launch_bscatter_dual(d, st->blk, st->lam, rho, s); });
+        timed(CDCS_K_GEMV_AU,
+              [&] { launch_baffine(d, d.b, -1.0 / rho, st->x, st->y, d.ctl, d.batch->istop, s); });
+        launch_bvupdate(d, st->x, st->blk, st->lam, st->v, rho, s);
+        launch_bcheck_dual(d, rho, s);
         return;
     }
     // the affine step (t, then y = L^-T L^-1 t, then x) part by part
@@ -1206,8 +1462,13 @@ cdcs_status cdcs_batch_info(const cdcs_handle *h, int32_t nprob, cdcs_instance_i
         o.status = stp[(size_t)q] == 1 ? CDCS_OK : stp[(size_t)q] == 3 ? CDCS_E_NUMERIC : CDCS_E_NOT_CONVERGED;
         o.eps_p = eps[(size_t)(2 * q)];
         o.eps_d = eps[(size_t)(2 * q + 1)];
-        o.obj_primal = obj[(size_t)(2 * q)];
-        o.obj_dual = -rho * obj[(size_t)(2 * q + 1)];
+        if (h->last_form == CDCS_PRIMAL) {
+            o.obj_primal = obj[(size_t)(2 * q)];
+            o.obj_dual = -rho * obj[(size_t)(2 * q + 1)];
+        } else {  // Algorithm 2: X_sdp = -rho x, y_sdp = y
+            o.obj_primal = -rho * obj[(size_t)(2 * q)];
+            o.obj_dual = obj[(size_t)(2 * q + 1)];
+        }
         o.time_to_tol_s = (stp[(size_t)q] && rate_khz > 0) ? (double)(tim[(size_t)q] - t0) / (1e3 * rate_khz) : -1.0;
     }
     return CDCS_OK;
@@ -1226,6 +1487,7 @@ cdcs_status cdcs_get_sizes(const cdcs_handle *h, cdcs_sizes *out) {
     out->nnz_a = h->d.sparse ? h->d.nnzA : (int64_t)h->d.m * h->d.nU;
     out->nnz_factor = h->d.sparse_linv ? h->d.nnz_linv : (int64_t)h->d.m * (h->d.m + 1) / 2;
     out->nwarm = h->d.nwarm;
+    out->nnz_l = h->d.spchol ? h->d.nnz_l : 0;
     return CDCS_OK;
 }
 
@@ -1247,7 +1509,7 @@ cdcs_status cdcs_psd_project_batched(int32_t nb, int32_t smax, const int32_t *si
                                      const float *W, float *P, float *evals, const int64_t *eoff, float *evecs,
                                      const int64_t *voff, hipStream_t stream) {
     if (nb <= 0) return CDCS_OK;
-    if (smax < 1 || smax > CDCS_MAX_CLIQUE) return fail(CDCS_E_ARG, "smax outside 1..CDCS_MAX_CLIQUE");
+    if (smax < 1 || smax > CDCS_MAX_BATCHED_CLIQUE) return fail(CDCS_E_ARG, "smax outside 1..CDCS_MAX_BATCHED_CLIQUE");
     if (!sizes || !off || !W || !P) return fail(CDCS_E_ARG, "NULL device pointer");
     if ((evals && !eoff) || (evecs && !voff)) return fail(CDCS_E_ARG, "evals/evecs need eoff/voff");
     ProjArgs a{};
@@ -1285,7 +1547,7 @@ cdcs_status cdcs_psd_project_vjp(int32_t nb, int32_t smax, const int32_t *sizes,
                                  const float *evals, const int64_t *eoff, const float *evecs, const int64_t *voff,
                                  const float *gP, float *gW, hipStream_t stream) {
     if (nb <= 0) return CDCS_OK;
-    if (smax < 1 || smax > CDCS_MAX_CLIQUE) return fail(CDCS_E_ARG, "smax outside 1..CDCS_MAX_CLIQUE");
+    if (smax < 1 || smax > CDCS_MAX_BATCHED_CLIQUE) return fail(CDCS_E_ARG, "smax outside 1..CDCS_MAX_BATCHED_CLIQUE");
     if (!sizes || !off || !evals || !eoff || !evecs || !voff || !gP || !gW)
         return fail(CDCS_E_ARG, "NULL device pointer");
     VjpArgs a{};
@@ -1345,7 +1607,6 @@ cdcs_status solve_check(cdcs_handle *h, const cdcs_state *st_user, const cdcs_op
     if (!(opts->rho > 0.0) || !(opts->tol >= 0.0) || opts->max_iter < 1 || opts->check_every < 0)
         return fail(CDCS_E_ARG, "need rho > 0, tol >= 0, max_iter >= 1, check_every >= 0");
     Dev &d = h->d;
-    if (d.batch && form != CDCS_PRIMAL) return fail(CDCS_E_ARG, "batch handles run Algorithm 1 only");
     if (d.hist_cap < opts->max_iter) {
         if (d.hist) {
             HIP_OK(hipStreamSynchronize(stream));
@@ -1385,6 +1646,7 @@ cdcs_status solve_impl(cdcs_handle *h, const cdcs_state *st_user, const cdcs_opt
     Dev &d = h->d;
     const double rho = opts->rho;
     h->last_rho = rho;
+    h->last_form = form;
     launch_reset_ctl(d, opts->max_iter, opts->tol, stream);
     if (d.batch) launch_breset(d, stream);
     // a solve is a function of (problem, state, options) only: without a
@@ -1419,8 +1681,10 @@ cdcs_status solve_impl(cdcs_handle *h, const cdcs_state *st_user, const cdcs_opt
         }
     }
     if (d.batch) {
-        launch_bscatter_primal(d, st->blk, st->lam, rho, stream);
-        launch_bcheck_primal(d, rho, stream);
+        if (form == CDCS_PRIMAL) {
+            launch_bscatter_primal(d, st->blk, st->lam, rho, stream);
+            launch_bcheck_primal(d, rho, stream);
+        }
         launch_bobjectives(d, st->x, st->y, d.batch->iobj, stream);
     } else if (form == CDCS_PRIMAL) {
         // residuals of the last iteration need the next right-hand side's scatter
@@ -1498,6 +1762,9 @@ cdcs_status cdcs_unrolled_step(cdcs_handle *h, const cdcs_state *st, const doubl
                                float *evals, float *evecs, hipStream_t stream) {
     if (!h || !st || !c || !b) return fail(CDCS_E_ARG, "NULL argument");
     if (h->d.batch) return fail(CDCS_E_ARG, "unrolled steps run on single-SDP handles");
+    if (h->d.big.nbig > 0)
+        return fail(CDCS_E_ARG, "unrolled steps need eigenpairs: cliques of at most " +
+                                    std::to_string(kMaxLdsClique) + " vertices");
     CK(diff_buffers(h));
     Dev &d = h->d;
     launch_perm_in(d, c, h->diff.c, stream);
@@ -1526,6 +1793,9 @@ cdcs_status cdcs_unrolled_step_vjp(cdcs_handle *h, double rho, const float *eval
     if (!h || !evals || !evecs || !blkbar || !lambar || !cbar || !bbar) return fail(CDCS_E_ARG, "NULL argument");
     if (!(rho > 0.0)) return fail(CDCS_E_ARG, "need rho > 0");
     if (h->d.batch) return fail(CDCS_E_ARG, "unrolled steps run on single-SDP handles");
+    if (h->d.big.nbig > 0)
+        return fail(CDCS_E_ARG, "unrolled steps need eigenpairs: cliques of at most " +
+                                    std::to_string(kMaxLdsClique) + " vertices");
     CK(diff_buffers(h));
     Dev &d = h->d;
     cdcs_handle::Diff &f = h->diff;
@@ -1597,10 +1867,14 @@ cdcs_status cdcs_profile_kernel(cdcs_handle *h, const cdcs_state *st_user, int32
     launch_reset_ctl(d, 1 << 30, 0.0, stream);
     if (d.batch) {
         launch_breset(d, stream);
+        const bool primal = form == CDCS_PRIMAL;
         for (int r = 0; r < reps; ++r) {
-            if (kernel == CDCS_K_PROJECT) launch_projection(h, PROJ_PRIMAL, st, rho, stream);
-            else if (kernel == CDCS_K_SCATTER) launch_bscatter_primal(d, st->blk, st->lam, rho, stream);
-            else if (kernel == CDCS_K_GEMV_AU) launch_baffine(d, d.b, 1.0, st->x, st->y, d.ctl, nullptr, stream);
+            if (kernel == CDCS_K_PROJECT) launch_projection(h, primal ? PROJ_PRIMAL : PROJ_DUAL, st, rho, stream);
+            else if (kernel == CDCS_K_SCATTER)
+                primal ? launch_bscatter_primal(d, st->blk, st->lam, rho, stream)
+                       : launch_bscatter_dual(d, st->blk, st->lam, rho, stream);
+            else if (kernel == CDCS_K_GEMV_AU)
+                launch_baffine(d, d.b, primal ? 1.0 : -1.0 / rho, st->x, st->y, d.ctl, nullptr, stream);
             else return fail(CDCS_E_ARG, "batch handles profile CDCS_K_PROJECT, CDCS_K_SCATTER, CDCS_K_GEMV_AU");
         }
         HIP_OK(hipGetLastError());
@@ -1656,7 +1930,9 @@ cdcs_status cdcs_set_projection_plan(cdcs_handle *h, int32_t persistent, int32_t
     if (persistent) {
         if (threads != 256 && threads != 512) return fail(CDCS_E_ARG, "queue launches use 256 or 512 threads");
         const int grid_max = queue_grid(h, threads);
-        if (grid_max < 1) return fail(CDCS_E_DEVICE, "queue kernel does not fit on a CU");
+        if (grid_max < 1)
+            return fail(CDCS_E_ARG, h->d.p_lds < 1 ? "no cliques for the queue launch"
+                                                    : "queue launches over cliques above 96 vertices use 512 threads");
         if (grid_req < 0 || grid_req > grid_max)
             return fail(CDCS_E_ARG, "grid outside 0.." + std::to_string(grid_max) + " (resident workgroups)");
         const int grid = grid_req > 0 ? grid_req : grid_max;

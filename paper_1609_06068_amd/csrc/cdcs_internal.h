@@ -65,7 +65,7 @@ struct ProjArgs {
 };
 
 // Size bucket (padded clique size) of the projection kernel for cliques <= smax:
-// 16, 32, 48, 64, 80 or 96.
+// 16, 32, 48, 64, 80, 96, 112 or 128 (cliques of at most 126 vertices).
 int proj_bucket(int smax);
 // Workgroup sizes built for a bucket: 64 (S <= 32), 256, 512 (S >= 48).
 bool proj_threads_ok(int S, int nthreads);
@@ -77,6 +77,25 @@ void launch_project_queue(const ProjArgs &a, int smax, int nthreads, int grid, u
                           hipStream_t s);
 // Resident workgroups per CU of the persistent launch.
 int project_queue_occupancy(int smax, int nthreads);
+
+// Cliques above the LDS-resident limit (kMaxLdsClique vertices): projection
+// through the Newton-Schulz sign iteration on N x N blocks (kernels_big.hip).
+constexpr int kMaxLdsClique = 126;
+constexpr int kNsSteps = 48;
+struct BigCliques {
+    int32_t nbig = 0;              // large cliques
+    int32_t tmax2 = 0;             // largest (N / 64)^2: 64 x 64 tiles of one block
+    const int32_t *ids = nullptr;  // [nbig] clique ids
+    const int32_t *n = nullptr;    // [nbig] sizes
+    const int32_t *N = nullptr;    // [nbig] sizes rounded up to 64
+    const int64_t *boff = nullptr; // [nbig + 1] offsets of the N x N blocks
+    float *W = nullptr;            // [boff[nbig]] W, zero padded
+    float *X0 = nullptr, *X1 = nullptr;  // Newton-Schulz iterates
+    float *Y = nullptr;            // products; P at the end
+    double *part = nullptr;        // [nbig * tmax2] per-tile partial sums
+    double *inv_norm = nullptr;    // [nbig] 1 / ||W||_F
+};
+void launch_big_projection(const ProjArgs &a, const BigCliques &b, hipStream_t s);
 
 // Arguments of the projection adjoint (Daleckii-Krein) kernel.
 struct VjpArgs {
@@ -127,6 +146,9 @@ struct Batch {
     int32_t nrjobs = 0;
     int32_t *ejobs = nullptr;      // [nejobs * 2] (q, first entry in q) of 1024-entry A^T y blocks
     int32_t nejobs = 0;
+    int32_t *vblk = nullptr;       // [nvblk * 4] slot blocks (q, s0, s1, 0) of the Alg. 2 epilogue
+    int32_t *vblk_off = nullptr;   // [nprob+1] slot-block ranges
+    int32_t nvblk = 0;
     int32_t *istop = nullptr;      // [nprob] 0 running, 1 converged, 2 iteration cap, 3 NaN/Inf
     int32_t *iiters = nullptr;     // [nprob] iterations at stop
     uint64_t *itime = nullptr;     // [nprob] device wall clock at stop
@@ -174,13 +196,18 @@ struct Dev {
     // L^-1 (lower) and of L^-T (upper), FP64
     int32_t sparse_linv = 0;
     int64_t nnz_linv = 0;
+    int32_t spchol = 0;            // L computed sparse (symbolic + numeric), no dense M ever formed
+    int64_t nnz_l = 0;             // its nonzeros
     int32_t *li_ptr = nullptr, *li_col = nullptr;
     double *li_val = nullptr;
     int32_t *lt_ptr = nullptr, *lt_col = nullptr;
     double *lt_val = nullptr;
     double *Linv = nullptr;        // [m * m] row-major, L^-1 (lower)
     double *LinvT = nullptr;       // [m * m] row-major, L^-T (upper)
-    int32_t *order = nullptr;      // [p] cliques by decreasing size
+    int32_t *order = nullptr;      // [p_lds] cliques of at most kMaxLdsClique vertices, by decreasing size
+    int32_t p_lds = 0;             // cliques projected in LDS (the others: big)
+    int32_t smax_lds = 0;          // largest of them
+    BigCliques big;
     int64_t *vwoff = nullptr;      // [p+1] offsets of k x k blocks (prefix sums of s_k^2)
     float *vwarm = nullptr;        // [sum s_k^2] eigenvectors of the last projection
     int64_t nwarm = 0;             // sum s_k^2
@@ -209,6 +236,10 @@ struct Dev {
 void launch_breset(const Dev &d, hipStream_t s);
 void launch_bscatter_primal(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s);
 void launch_bcheck_primal(const Dev &d, double rho, hipStream_t s);
+void launch_bscatter_dual(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s);
+void launch_bvupdate(const Dev &d, const double *x, const float *blk, float *lam, float *v, double rho,
+                     hipStream_t s);
+void launch_bcheck_dual(const Dev &d, double rho, hipStream_t s);
 void launch_baffine(const Dev &d, const double *r2, double r2scale, double *x, double *y, const Ctl *ctl,
                     const int32_t *istop, hipStream_t s);
 void launch_bsetup(const Dev &d, double *M, hipStream_t s);
@@ -268,6 +299,35 @@ struct ChordalExt {
 };
 cdcs_status chordal_extension(int32_t n, int64_t nnz, const int32_t *ei, const int32_t *ej, ChordalExt &out,
                               std::string &err);
+// Elimination order of the graph adj (vertices with used[v]): the maximum
+// cardinality search order when it is perfect (returns true: no fill), else
+// minimum degree; later[v] = the neighbours of v eliminated after it in the
+// filled graph (the structure of column v of the Cholesky factor).
+bool elimination_order(int32_t n, const std::vector<std::vector<int32_t>> &adj, const std::vector<char> &used,
+                       std::vector<int32_t> &order, std::vector<std::vector<int32_t>> &later);
+
+// Sparse Cholesky factor of M (sparse A): structure from the host's symbolic
+// step, values on the device (kernels_setup.hip).  All device arrays.
+struct SpFactor {
+    const int32_t *cp = nullptr;        // [m+1] column pointers of L (factor order)
+    const int32_t *ri = nullptr;        // [nnzL] rows, increasing per column, diagonal first
+    const int32_t *order = nullptr;     // [m] original row of factor index j
+    const int32_t *pinv = nullptr;      // [m] factor index of original row r
+    const int32_t *rk_ptr = nullptr;    // [m+1] per row j: the columns k < j with L_jk != 0
+    const int32_t *rk_col = nullptr;    // [nnzL - m] k, increasing
+    const int32_t *rk_pos = nullptr;    // [nnzL - m] position of row j within column k
+    const int32_t *level_cols = nullptr;  // columns by elimination-tree level (leaves first)
+    const int64_t *xp = nullptr;        // [m+1] column pointers of X = L^-1 (paths to the root)
+    const int32_t *xr = nullptr;        // [nnzX] rows of X
+    double *Lv = nullptr;               // [nnzL] values of L
+    double *diag0 = nullptr;            // [m] diagonal of M (factor order)
+    double *xv = nullptr;               // [nnzX] values of X
+};
+void launch_spchol_fill(const Dev &d, const SpFactor &f, const int32_t *tid, hipStream_t s);
+void launch_spchol(const Dev &d, const SpFactor &f, const std::vector<int32_t> &level_off, int32_t *info,
+                   hipStream_t s);
+int spinv_max_path();
+void launch_gather_vals(const double *in, const int64_t *idx, double *out, int64_t n, hipStream_t s);
 
 // setup kernels (kernels_setup.hip)
 void launch_syrk(const float *Aw, int64_t ld, const double *s2, int m, double *M, hipStream_t s);

@@ -102,6 +102,53 @@ bool mcs_peo(int32_t n, const std::vector<std::vector<int32_t>> &adj, const std:
 
 }  // namespace
 
+bool elimination_order(int32_t n, const std::vector<std::vector<int32_t>> &adj, const std::vector<char> &used,
+                       std::vector<int32_t> &order, std::vector<std::vector<int32_t>> &later) {
+    later.assign((size_t)n, {});
+    const bool chordal = mcs_peo(n, adj, used, order);
+    if (chordal) {
+        std::vector<int32_t> pos((size_t)n, -1);
+        for (size_t t = 0; t < order.size(); ++t) pos[(size_t)order[t]] = (int32_t)t;
+        for (int32_t v : order)
+            for (int32_t u : adj[(size_t)v])
+                if (pos[(size_t)u] > pos[(size_t)v]) later[(size_t)v].push_back(u);
+        return true;
+    }
+    // minimum degree on the elimination graph (sorted adjacency vectors)
+    std::vector<std::vector<int32_t>> g((size_t)n);
+    for (int32_t v = 0; v < n; ++v) {
+        g[(size_t)v] = adj[(size_t)v];
+        std::sort(g[(size_t)v].begin(), g[(size_t)v].end());
+    }
+    // (degree, vertex) pairs of the vertices not yet eliminated, ordered
+    std::set<std::pair<int32_t, int32_t>> queue;
+    for (int32_t v = 0; v < n; ++v)
+        if (used[(size_t)v]) queue.insert({(int32_t)g[(size_t)v].size(), v});
+    order.clear();
+    order.reserve(queue.size());
+    std::vector<int32_t> merged;
+    while (!queue.empty()) {
+        const int32_t v = queue.begin()->second;
+        queue.erase(queue.begin());
+        order.push_back(v);
+        const std::vector<int32_t> nb = g[(size_t)v];
+        later[(size_t)v] = nb;
+        // join the neighbours into a clique, drop v from their lists
+        for (int32_t a : nb) {
+            std::vector<int32_t> &ga = g[(size_t)a];
+            queue.erase({(int32_t)ga.size(), a});
+            merged.clear();
+            std::set_union(ga.begin(), ga.end(), nb.begin(), nb.end(), std::back_inserter(merged));
+            ga.clear();
+            for (int32_t u : merged)
+                if (u != a && u != v) ga.push_back(u);
+            queue.insert({(int32_t)ga.size(), a});
+        }
+        g[(size_t)v].clear();
+    }
+    return false;
+}
+
 cdcs_status chordal_extension(int32_t n, int64_t nnz, const int32_t *ei, const int32_t *ej, ChordalExt &out,
                               std::string &err) {
     out = ChordalExt();
@@ -130,48 +177,8 @@ cdcs_status chordal_extension(int32_t n, int64_t nnz, const int32_t *ei, const i
         }
     }
     std::vector<int32_t> order;
-    std::vector<std::vector<int32_t>> later((size_t)n);  // N+(v) in the filled graph
-    out.chordal_input = mcs_peo(n, adj, used, order);
-    if (out.chordal_input) {
-        std::vector<int32_t> pos((size_t)n, -1);
-        for (size_t t = 0; t < order.size(); ++t) pos[(size_t)order[t]] = (int32_t)t;
-        for (int32_t v : order)
-            for (int32_t u : adj[(size_t)v])
-                if (pos[(size_t)u] > pos[(size_t)v]) later[(size_t)v].push_back(u);
-    } else {
-        // minimum degree on the elimination graph (sorted adjacency vectors)
-        std::vector<std::vector<int32_t>> g((size_t)n);
-        for (int32_t v = 0; v < n; ++v) {
-            g[(size_t)v] = adj[(size_t)v];
-            std::sort(g[(size_t)v].begin(), g[(size_t)v].end());
-        }
-        // (degree, vertex) pairs of the vertices not yet eliminated, ordered
-        std::set<std::pair<int32_t, int32_t>> queue;
-        for (int32_t v = 0; v < n; ++v)
-            if (used[(size_t)v]) queue.insert({(int32_t)g[(size_t)v].size(), v});
-        order.clear();
-        order.reserve(queue.size());
-        std::vector<int32_t> merged;
-        while (!queue.empty()) {
-            const int32_t v = queue.begin()->second;
-            queue.erase(queue.begin());
-            order.push_back(v);
-            const std::vector<int32_t> nb = g[(size_t)v];
-            later[(size_t)v] = nb;
-            // join the neighbours into a clique, drop v from their lists
-            for (int32_t a : nb) {
-                std::vector<int32_t> &ga = g[(size_t)a];
-                queue.erase({(int32_t)ga.size(), a});
-                merged.clear();
-                std::set_union(ga.begin(), ga.end(), nb.begin(), nb.end(), std::back_inserter(merged));
-                ga.clear();
-                for (int32_t u : merged)
-                    if (u != a && u != v) ga.push_back(u);
-                queue.insert({(int32_t)ga.size(), a});
-            }
-            g[(size_t)v].clear();
-        }
-    }
+    std::vector<std::vector<int32_t>> later;  // N+(v) in the filled graph
+    out.chordal_input = elimination_order(n, adj, used, order, later);
     // maximal cliques from the elimination order
     const size_t nv = order.size();
     std::vector<int32_t> pos((size_t)n, -1);

@@ -88,6 +88,117 @@ __global__ __launch_bounds__(kNT) void k_bscatter_primal(const int4 *__restrict_
     }
 }
 
+// Alg. 2 right-hand side per scatter block: u = (c - sum_k H_k^T (z_k + lam_k / rho)) / D.
+__global__ __launch_bounds__(kNT) void k_bscatter_dual(const int4 *__restrict__ sblk,
+                                                       const int32_t *__restrict__ istop,
+                                                       const int32_t *__restrict__ inv_ptr,
+                                                       const int32_t *__restrict__ inv_slot,
+                                                       const float *__restrict__ blk, const float *__restrict__ lam,
+                                                       const double *__restrict__ c, const double *__restrict__ invD,
+                                                       double *__restrict__ u, double rho, const Ctl *ctl) {
+    if (ctl->stop) return;
+    const int4 bk = sblk[blockIdx.x];
+    if (istop[bk.x]) return;
+    const int64_t e = (int64_t)bk.y + threadIdx.x;
+    if (e >= bk.z) return;
+    double acc = 0.0;
+    const int32_t q1 = inv_ptr[e + 1];
+    for (int32_t q = inv_ptr[e]; q < q1; ++q) {
+        const int32_t sl = inv_slot[q];
+        acc += (double)blk[sl] + (double)lam[sl] / rho;
+    }
+    u[e] = (c[e] - acc) * invD[e];
+}
+
+// Alg. 2 epilogue per slot block (q, s0, s1) of one instance: v_k = z_k +
+// lam_k / rho + H_k x (E:vkEqn), lam_k += rho (z_k - v_k) (E:MultUpdateDualSDP),
+// and the block's residual partial sums.
+__global__ __launch_bounds__(kNT) void k_bvupdate(const int4 *__restrict__ vblk, const int32_t *__restrict__ istop,
+                                                  const int32_t *__restrict__ gather, const double *__restrict__ x,
+                                                  const double *__restrict__ wt, const float *__restrict__ blk,
+                                                  float *__restrict__ lam, float *__restrict__ v,
+                                                  double *__restrict__ vpart, double rho, const Ctl *ctl) {
+    __shared__ double red[kNT / 64];
+    if (ctl->stop) return;
+    const int4 bk = vblk[blockIdx.x];
+    if (istop[bk.x]) return;
+    const int64_t s = (int64_t)bk.y + threadIdx.x;
+    double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0, q4 = 0.0;
+    if (s < bk.z) {
+        const int32_t e = gather[s];
+        const double hx = x[e];
+        const double z = blk[s], l = lam[s], vo = v[s];
+        const double vn = z + l / rho + hx;
+        const double ln = l + rho * (z - vn);
+        v[s] = (float)vn;
+        lam[s] = (float)ln;
+        const double w = wt[e];
+        q0 = w * (z - vn) * (z - vn);
+        q1 = w * z * z;
+        q2 = w * vn * vn;
+        q3 = w * (vn - vo) * (vn - vo);
+        q4 = w * ln * ln;
+    }
+    q0 = block_sum_d(q0, red);
+    q1 = block_sum_d(q1, red);
+    q2 = block_sum_d(q2, red);
+    q3 = block_sum_d(q3, red);
+    q4 = block_sum_d(q4, red);
+    if (threadIdx.x == 0) {
+        double *o = vpart + 5 * (int64_t)blockIdx.x;
+        o[0] = q0;
+        o[1] = q1;
+        o[2] = q2;
+        o[3] = q3;
+        o[4] = q4;
+    }
+}
+
+// Alg. 2 per-instance residual check of the iteration just completed
+// (n = ctl->iter + 1): one wave per instance over its slot blocks.
+__global__ __launch_bounds__(kNT) void k_bcheck_dual(const double *__restrict__ vpart,
+                                                     const int32_t *__restrict__ vblk_off, int nprob, double rho,
+                                                     int32_t *__restrict__ istop, int32_t *__restrict__ iiters,
+                                                     uint64_t *__restrict__ itime, double *__restrict__ ieps,
+                                                     int32_t *nrunning, const Ctl *ctl) {
+    if (ctl->stop) return;
+    const int lane = threadIdx.x & 63;
+    const int q = blockIdx.x * (kNT / 64) + (threadIdx.x >> 6);
+    if (q >= nprob || istop[q]) return;
+    const int n = ctl->iter + 1;
+    double r[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = vblk_off[q] + lane; b < vblk_off[q + 1]; b += 64)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) r[i] += vpart[5 * (int64_t)b + i];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) r[i] = wave_sum_d(r[i]);
+    if (lane != 0) return;
+    const double den_p = fmax(sqrt(r[1]), sqrt(r[2]));
+    const double eps_p = den_p > 0.0 ? sqrt(r[0]) / den_p : sqrt(r[0]);
+    const double den_d = sqrt(r[4]);
+    const double eps_d = den_d > 0.0 ? rho * sqrt(r[3]) / den_d : rho * sqrt(r[3]);
+    ieps[2 * q + 0] = eps_p;
+    ieps[2 * q + 1] = eps_d;
+    const bool finite = isfinite(eps_p) && isfinite(eps_d);  // NaN or Inf in the instance's iterate: 3
+    int st = 0;
+    if (!finite) st = 3;
+    else if (fmax(eps_p, eps_d) <= ctl->tol) st = 1;
+    else if (n >= ctl->max_iter) st = 2;
+    if (st) {
+        istop[q] = st;
+        iiters[q] = n;
+        itime[q] = wall_clock64();
+        atomicSub(nrunning, 1);
+    }
+}
+
+// Global bookkeeping after the per-instance Alg. 2 checks.
+__global__ void k_bcheck_dual_finish(const int32_t *nrunning, Ctl *ctl) {
+    if (threadIdx.x != 0 || ctl->stop) return;
+    ctl->iter = ctl->iter + 1;
+    if (*nrunning <= 0) ctl->stop = 1;
+}
+
 // Per-instance residual check of iteration n = ctl->iter: one wave per instance.
 __global__ __launch_bounds__(kNT) void k_bcheck_primal(const double *__restrict__ cpart,
                                                        const int32_t *__restrict__ k_off,
@@ -459,6 +570,29 @@ void launch_bcheck_primal(const Dev &d, double rho, hipStream_t s) {
                        (const int32_t *)B.k_off, (const double *)d.spart, (const int32_t *)B.sblk_off, B.nprob, rho,
                        B.istop, B.iiters, B.itime, B.ieps, B.nrunning, (const Ctl *)d.ctl);
     hipLaunchKernelGGL(k_bcheck_finish, dim3(1), dim3(64), 0, s, (const int32_t *)B.nrunning, d.ctl);
+}
+
+void launch_bscatter_dual(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s) {
+    const Batch &B = *d.batch;
+    hipLaunchKernelGGL(k_bscatter_dual, dim3(B.nsblk), dim3(kNT), 0, s, (const int4 *)B.sblk, (const int32_t *)B.istop,
+                       (const int32_t *)d.inv_ptr, (const int32_t *)d.inv_slot, blk, lam, (const double *)d.c,
+                       (const double *)d.invD, d.u, rho, (const Ctl *)d.ctl);
+}
+
+void launch_bvupdate(const Dev &d, const double *x, const float *blk, float *lam, float *v, double rho,
+                     hipStream_t s) {
+    const Batch &B = *d.batch;
+    hipLaunchKernelGGL(k_bvupdate, dim3(B.nvblk), dim3(kNT), 0, s, (const int4 *)B.vblk, (const int32_t *)B.istop,
+                       (const int32_t *)d.gather, x, (const double *)d.wt, blk, lam, v, d.vpart, rho,
+                       (const Ctl *)d.ctl);
+}
+
+void launch_bcheck_dual(const Dev &d, double rho, hipStream_t s) {
+    const Batch &B = *d.batch;
+    hipLaunchKernelGGL(k_bcheck_dual, dim3(waves_blocks(B.nprob)), dim3(kNT), 0, s, (const double *)d.vpart,
+                       (const int32_t *)B.vblk_off, B.nprob, rho, B.istop, B.iiters, B.itime, B.ieps, B.nrunning,
+                       (const Ctl *)d.ctl);
+    hipLaunchKernelGGL(k_bcheck_dual_finish, dim3(1), dim3(64), 0, s, (const int32_t *)B.nrunning, d.ctl);
 }
 
 void launch_baffine(const Dev &d, const double *r2, double r2scale, double *x, double *y, const Ctl *ctl,

@@ -1,0 +1,251 @@
+// Projection onto the PSD cone for cliques too large for one workgroup's LDS
+// (more than 126 vertices; the paper's Table I has cliques of 322 and 323).
+//
+// P_+(W) = W (I + sign(W)) / 2 (Higham, "Functions of Matrices", ch. 5), so
+// the projection needs the matrix sign function, not an eigendecomposition.
+// sign(W) comes from the Newton-Schulz iteration
+//     X_0 = W / ||W||_F,   X_{t+1} = X_t (3 I - X_t^2) / 2,
+// which converges to sign(W) for ||X_0||_2 < sqrt(3) (every step maps an
+// eigenvalue s to s (3 - s^2) / 2: quadratically near +-1, by a factor 3/2
+// per step while |s| is small).  Every step is two products of k x k FP32
+// matrices on the matrix cores, tiled over many workgroups, so a large clique
+// is spread across the GPU.  A fixed number of steps, kNsSteps = 48, takes
+// every eigenvalue with |lambda| >= 2e-7 ||W||_F to within rounding of +-1;
+// a smaller eigenvalue contributes at most |lambda| / 2 to the error of P.
+// (The product's FP32 rounding leaves X a few ulps off sign(W); each step
+// squares the previous deviation, so it does not accumulate.)  A NaN or Inf
+// in W reaches the residual sums, which report it.
+//
+// Layout: each large clique c has an N x N row-major FP32 block (N = its size
+// rounded up to 64, zero padded) in four buffers: W, two iterates and one
+// product; launches cover every large clique at once (grid: 64 x 64 output
+// tiles x cliques), and all reductions are fixed-order (no atomics).
+#include "cdcs_internal.h"
+
+namespace cdcs {
+namespace {
+
+constexpr int kNT = 256;
+constexpr int kTile = 64;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Workgroup sum in fixed order; the result is valid in thread 0.
+__device__ __forceinline__ double block_sum0(double v, double *red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    v = wave_sum_d(v);
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kNT / 64; ++i) r += red[i];
+    return r;
+}
+
+__device__ __forceinline__ bool big_skip(const ProjArgs &a, int id) {
+    if (a.ctl != nullptr && a.ctl->stop) return true;
+    return a.istop != nullptr && a.istop[a.kinst[id]];
+}
+
+// W of clique c into its N x N block (both triangles, zero padding) from the
+// projection's source, and per-tile partial sums of ||W||_F^2.
+__global__ __launch_bounds__(kNT) void k_big_gather(ProjArgs a, BigCliques b) {
+    __shared__ double red[kNT / 64];
+    const int c = blockIdx.y;
+    const int id = b.ids[c];
+    if (big_skip(a, id)) return;
+    const int n = b.n[c], N = b.N[c], T = N / kTile;
+    const int t = blockIdx.x;
+    if (t >= T * T) return;
+    const int ti = t / T, tj = t - ti * T;
+    const int64_t off = a.off[id];
+    float *W = b.W + b.boff[c];
+    double s2 = 0.0;
+    for (int e = threadIdx.x; e < kTile * kTile; e += kNT) {
+        const int i = ti * kTile + e / kTile, j = tj * kTile + e % kTile;
+        float w = 0.0f;
+        if (i < n && j < n) {
+            const int r = max(i, j), q = min(i, j);
+            const int64_t g = off + (int64_t)r * (r + 1) / 2 + q;
+            if (a.mode == PROJ_STANDALONE) w = a.Win[g];
+            else if (a.mode == PROJ_PRIMAL) w = (float)(a.x[a.gather[g]] - (double)a.lam[g] * a.inv_rho);
+            else w = (float)((double)a.v[g] - (double)a.lam[g] * a.inv_rho);
+        }
+        W[(int64_t)i * N + j] = w;
+        s2 += (double)w * (double)w;
+    }
+    s2 = block_sum0(s2, red);
+    if (threadIdx.x == 0) b.part[(int64_t)c * b.tmax2 + t] = s2;
+}
+
+// ||W||_F from the tile partials (in tile order); 1 / ||W||_F for the scaling.
+__global__ __launch_bounds__(64) void k_big_norm(ProjArgs a, BigCliques b) {
+    const int c = blockIdx.x;
+    if (big_skip(a, b.ids[c])) return;
+    const int T = b.N[c] / kTile;
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int t = 0; t < T * T; ++t) s += b.part[(int64_t)c * b.tmax2 + t];
+        const double fro = sqrt(s);
+        b.inv_norm[c] = fro > 0.0 ? 1.0 / fro : 0.0;
+    }
+}
+
+// X_0 = W / ||W||_F
+__global__ __launch_bounds__(kNT) void k_big_scale(ProjArgs a, BigCliques b) {
+    const int c = blockIdx.y;
+    if (big_skip(a, b.ids[c])) return;
+    const int N = b.N[c];
+    const int64_t NN = (int64_t)N * N;
+    const float sc = (float)b.inv_norm[c];
+    const float *W = b.W + b.boff[c];
+    float *X = b.X0 + b.boff[c];
+    for (int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x; e < NN; e += (int64_t)gridDim.x * kNT) X[e] = W[e] * sc;
+}
+
+// One 64 x 64 tile of C = A B for every large clique (N x N blocks, N a
+// multiple of 64), on v_mfma_f32_16x16x4_f32: wave w computes the 32 x 32
+// quadrant (w / 2, w % 2) as 2 x 2 instruction tiles, with 16-deep slices of
+// A and B staged in LDS.  Epilogue EPI: 0: C = A B; 1 (a Newton-Schulz step,
+// A = X, B = X^2): C = 1.5 A - 0.5 A B; 2 (the projection, A = W, B =
+// sign(W)): C = (A + A B) / 2.  Operand layout of the instruction (lane l):
+// A[l % 16][l / 16], B[l / 16][l % 16]; result element r at
+// D[(l / 16) * 4 + r][l % 16].
+template <int EPI>
+__global__ __launch_bounds__(kNT) void k_big_gemm(ProjArgs a, BigCliques b, const float *__restrict__ Ab,
+                                                  const float *__restrict__ Bb, float *__restrict__ Cb) {
+    __shared__ float As[kTile][17];
+    __shared__ float Bs[16][kTile + 1];
+    const int c = blockIdx.y;
+    if (big_skip(a, b.ids[c])) return;
+    const int N = b.N[c], T = N / kTile;
+    const int t = blockIdx.x;
+    if (t >= T * T) return;
+    const int ti = t / T, tj = t - ti * T;
+    const int64_t o = b.boff[c];
+    const float *A = Ab + o, *B = Bb + o;
+    float *C = Cb + o;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int qr = w >> 1, qc = w & 1;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int ar = tid >> 2, ac = (tid & 3) * 4;   // A slice: 64 rows x 16 columns, 4 per thread
+    const int br = tid >> 4, bc = (tid & 15) * 4;  // B slice: 16 rows x 64 columns, 4 per thread
+    for (int k0 = 0; k0 < N; k0 += 16) {
+        const f32x4 av = *reinterpret_cast<const f32x4 *>(A + (int64_t)(ti * kTile + ar) * N + k0 + ac);
+        const f32x4 bv = *reinterpret_cast<const f32x4 *>(B + (int64_t)(k0 + br) * N + tj * kTile + bc);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            As[ar][ac + q] = av[q];
+            Bs[br][bc + q] = bv[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            float am[2], bm[2];
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi) am[mi] = As[qr * 32 + mi * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni) bm[ni] = Bs[kk + (lane >> 4)][qc * 32 + ni * 16 + (lane & 15)];
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[mi], bm[ni], acc[mi][ni], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = ti * kTile + qr * 32 + mi * 16 + (lane >> 4) * 4 + r;
+                const int col = tj * kTile + qc * 32 + ni * 16 + (lane & 15);
+                const int64_t e = (int64_t)row * N + col;
+                const float v = acc[mi][ni][r];
+                if (EPI == 0) C[e] = v;
+                else if (EPI == 1) C[e] = 1.5f * A[e] - 0.5f * v;
+                else C[e] = 0.5f * (A[e] + v);
+            }
+}
+
+// The projection's epilogue for large cliques, as for the LDS-resident ones:
+// P (symmetrised) to the packed outputs, the multiplier update of Algorithm 1
+// and the residual partial sums (fixed order), one workgroup per clique.
+__global__ __launch_bounds__(kNT) void k_big_epilogue(ProjArgs a, BigCliques b, const float *__restrict__ Pb) {
+    __shared__ double red[kNT / 64];
+    const int c = blockIdx.x;
+    const int id = b.ids[c];
+    if (big_skip(a, id)) return;
+    const int n = b.n[c], N = b.N[c];
+    const float *P = Pb + b.boff[c];
+    const int64_t off = a.off[id];
+    const int nslot = n * (n + 1) / 2;
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+    for (int s = threadIdx.x; s < nslot; s += kNT) {
+        int i = (int)((sqrt(8.0 * (double)s + 1.0) - 1.0) * 0.5);
+        while ((i + 1) * (i + 2) / 2 <= s) ++i;
+        while (i * (i + 1) / 2 > s) --i;
+        const int j = s - i * (i + 1) / 2;
+        const float pv32 = 0.5f * (P[(int64_t)i * N + j] + P[(int64_t)j * N + i]);
+        const int64_t g = off + s;
+        if (a.mode == PROJ_STANDALONE) {
+            a.Pout[g] = pv32;
+        } else if (a.mode == PROJ_PRIMAL) {
+            const double hx = a.x[a.gather[g]];
+            const double pv = (double)pv32;
+            a.lam[g] = (float)((double)a.lam[g] + a.rho * (pv - hx));
+            a.blk[g] = pv32;
+            const double wgt = (i == j) ? 1.0 : 2.0;
+            const double d = pv - hx;
+            p0 += wgt * d * d;
+            p1 += wgt * hx * hx;
+            p2 += wgt * pv * pv;
+        } else {
+            a.blk[g] = pv32;
+        }
+    }
+    if (a.mode == PROJ_PRIMAL) {
+        p0 = block_sum0(p0, red);
+        p1 = block_sum0(p1, red);
+        p2 = block_sum0(p2, red);
+        if (threadIdx.x == 0) {
+            a.cpart[4 * (int64_t)id + 0] = p0;
+            a.cpart[4 * (int64_t)id + 1] = p1;
+            a.cpart[4 * (int64_t)id + 2] = p2;
+        }
+    }
+}
+
+}  // namespace
+
+void launch_big_projection(const ProjArgs &a, const BigCliques &b, hipStream_t s) {
+    if (b.nbig <= 0) return;
+    const dim3 tiles((unsigned)b.tmax2, (unsigned)b.nbig);
+    hipLaunchKernelGGL(k_big_gather, tiles, dim3(kNT), 0, s, a, b);
+    hipLaunchKernelGGL(k_big_norm, dim3((unsigned)b.nbig), dim3(64), 0, s, a, b);
+    hipLaunchKernelGGL(k_big_scale, dim3(64, (unsigned)b.nbig), dim3(kNT), 0, s, a, b);
+    float *X[2] = {b.X0, b.X1};
+    for (int t = 0; t < kNsSteps; ++t) {
+        hipLaunchKernelGGL(k_big_gemm<0>, tiles, dim3(kNT), 0, s, a, b, (const float *)X[t & 1],
+                           (const float *)X[t & 1], b.Y);
+        hipLaunchKernelGGL(k_big_gemm<1>, tiles, dim3(kNT), 0, s, a, b, (const float *)X[t & 1],
+                           (const float *)b.Y, X[(t + 1) & 1]);
+    }
+    hipLaunchKernelGGL(k_big_gemm<2>, tiles, dim3(kNT), 0, s, a, b, (const float *)b.W,
+                       (const float *)X[kNsSteps & 1], b.Y);
+    hipLaunchKernelGGL(k_big_epilogue, dim3((unsigned)b.nbig), dim3(kNT), 0, s, a, b, (const float *)b.Y);
+}
+
+}  // namespace cdcs

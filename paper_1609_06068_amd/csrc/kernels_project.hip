@@ -4,8 +4,11 @@
 // and the per-clique residual partial sums.
 //
 // One workgroup per clique.  Every clique of a size bucket is padded to the
-// bucket size S with zero rows and columns (a zero pair never rotates), so all
-// loops have compile-time trip counts.  The clique matrix (FP32) lives in LDS
+// bucket size S (16, 32, ..., 128) with zero rows and columns (a zero pair
+// never rotates), so all loops have compile-time trip counts.  Cliques of up
+// to kMaxK = 126 vertices fit: the Jacobi runs on K = k rounded up to even
+// positions, a wave lane holds two of them, and the odd steps' end pair needs
+// one lane more than the K/2 pairs, so K/2 <= 63.  The clique matrix (FP32) lives in LDS
 // and is diagonalised by two-sided Jacobi in the odd-even ordering: the
 // disjoint pairs of a step are rotated together.  During the sweeps A is
 // stored by position, as lower 2x2 pair blocks in four element planes, so a
@@ -38,6 +41,7 @@ namespace cdcs {
 namespace {
 
 constexpr int kMaxSweeps = 30;
+constexpr int kMaxK = 126;  // largest clique: K / 2 + 1 pairs in one 64-lane wave
 constexpr float kTauEig = 1.1920928955078125e-07f;   // 2^-23: eigenpairs returned
 constexpr float kTauProj = 9.5367431640625e-07f;     // 2^-20: projection only
 
@@ -321,7 +325,7 @@ __device__ __forceinline__ void product_store(const float *X, const float *Y, co
 struct ProjSmall {
     float2 cst[64];              // rotations of one step: (c, s) of pair t (8-byte stride: the reads of
                                  // consecutive pairs fall in distinct bank pairs)
-    float lam[96], lp[96];       // eigenvalues, clamped eigenvalues
+    float lam[128], lp[128];     // eigenvalues, clamped eigenvalues
     float redf[8];
     double redd[24];             // three FP64 partial sums per wave
     int zero;                    // 0; read as volatile (see project_one)
@@ -332,7 +336,7 @@ struct ProjSmall {
 template <int S, int NT>
 __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__restrict__ sA,
                                             float *__restrict__ sV, ProjSmall &sm) {
-    static_assert(S % 16 == 0 && S <= 96, "bucket size");
+    static_assert(S % 16 == 0 && S <= 128, "bucket size");
     static_assert(NT == 64 || NT == 256 || NT == 512, "workgroup size");
     constexpr int LD = S + 1;                    // odd row stride
     constexpr int HMAX = S / 2;                  // pairs per step, at most
@@ -343,7 +347,7 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
 
     if (a.istop != nullptr && a.istop[a.kinst[id]]) return;  // instance already stopped
     const int k = uniform(a.size[id]);
-    if (k < 1 || k > S) return;
+    if (k < 1 || k > S || k > kMaxK) return;
     const int64_t off = a.off[id];
     const int nslot = k * (k + 1) / 2;
     // The thread index goes through a volatile LDS zero so that the compiler
@@ -785,7 +789,7 @@ void k_project(ProjArgs a) {
 }
 
 __device__ __forceinline__ int bucket_of(int k) {
-    return k <= 16 ? 16 : k <= 32 ? 32 : k <= 48 ? 48 : k <= 64 ? 64 : k <= 80 ? 80 : 96;
+    return k <= 16 ? 16 : k <= 32 ? 32 : k <= 48 ? 48 : k <= 64 ? 64 : k <= 80 ? 80 : k <= 96 ? 96 : k <= 112 ? 112 : 128;
 }
 
 // Draw the next queue ticket for the workgroup (two barriers).
@@ -830,6 +834,8 @@ void k_project_queue(ProjArgs a, unsigned long long *ticket,
     if (a.ctl != nullptr && a.ctl->stop) return;
     if (threadIdx.x == 0) sm.zero = 0;  // published by draw_item's barriers
     int item = draw_item(ticket, period, &s_item);
+    if constexpr (SB >= 128) item = drain_bucket<128, NT>(a, item, sbuf, sm, ticket, period, &s_item);
+    if constexpr (SB >= 112) item = drain_bucket<112, NT>(a, item, sbuf, sm, ticket, period, &s_item);
     if constexpr (SB >= 96) item = drain_bucket<96, NT>(a, item, sbuf, sm, ticket, period, &s_item);
     if constexpr (SB >= 80) item = drain_bucket<80, NT>(a, item, sbuf, sm, ticket, period, &s_item);
     if constexpr (SB >= 64) item = drain_bucket<64, NT>(a, item, sbuf, sm, ticket, period, &s_item);
@@ -847,14 +853,11 @@ void k_project_queue(ProjArgs a, unsigned long long *ticket,
 // triangles, so G gets half of it on each side and Wbar's two triangles add up.
 template <int S, int NT>
 __global__ __launch_bounds__(NT) void k_project_vjp(VjpArgs a) {
-    static_assert(S % 16 == 0 && S <= 96, "bucket size");
+    static_assert(S % 16 == 0 && S <= 128, "bucket size");
     constexpr int LD = S + 1;
-    constexpr int GC = Tiles<S, NT>::GC, T = Tiles<S, NT>::TR;
-    static_assert(Tiles<S, NT>::TR == Tiles<S, NT>::TC, "square tiles");
     __shared__ float sA[S * LD];
     __shared__ float sV[S * LD];
-    __shared__ float sX[S * LD];
-    __shared__ float sLam[S];
+    __shared__ float sLam[S], sOne[S];
     const int bi = blockIdx.x;
     if (bi >= a.nblk) return;
     const int k = a.size[bi];
@@ -862,13 +865,17 @@ __global__ __launch_bounds__(NT) void k_project_vjp(VjpArgs a) {
     const int64_t off = a.off[bi], eo = a.eoff[bi], vo = a.voff[bi];
     const int nslot = k * (k + 1) / 2;
     const int tid = threadIdx.x;
-    const int ti = tid / GC, tj = tid % GC;
+    // V (identity past k: harmless, every product pairs it with zeros) and
+    // G (zero past k)
     for (int idx = tid; idx < S * S; idx += NT) {
         const int i = idx / S, j = idx % S;
         sA[i * LD + j] = 0.0f;
         sV[i * LD + j] = (i < k && j < k) ? a.evecs[vo + i * k + j] : (i == j ? 1.0f : 0.0f);
     }
-    if (tid < S) sLam[tid] = tid < k ? a.evals[eo + tid] : 0.0f;
+    if (tid < S) {
+        sLam[tid] = tid < k ? a.evals[eo + tid] : 0.0f;
+        sOne[tid] = 1.0f;
+    }
     __syncthreads();
     for (int s = tid; s < nslot; s += NT) {
         const int i = tri_row(s), j = s - i * (i + 1) / 2;
@@ -881,48 +888,28 @@ __global__ __launch_bounds__(NT) void k_project_vjp(VjpArgs a) {
         }
     }
     __syncthreads();
-    float acc[T][T];
-    tile_product<S, NT, 1>(sA, sV, acc, ti, tj);  // G V
-#pragma unroll
-    for (int u = 0; u < T; ++u)
-#pragma unroll
-        for (int v = 0; v < T; ++v) sX[(ti * T + u) * LD + tj * T + v] = acc[u][v];
+    // Each product keeps its result in registers until every thread has read
+    // its operands, so it may overwrite one (matrix cores for S >= 32).
+    auto to_sA = [&](int i, int j, float v) { sA[i * LD + j] = v; };
+    product_store<S, NT, 1>(sA, sV, nullptr, k, tid, to_sA);  // G V
     __syncthreads();
-    tile_product<S, NT, 0>(sV, sX, acc, ti, tj);  // V^T G V
-#pragma unroll
-    for (int u = 0; u < T; ++u)
-#pragma unroll
-        for (int v = 0; v < T; ++v) {
-            const int i = ti * T + u, j = tj * T + v;
-            const float li = sLam[i], lj = sLam[j];
-            float gam;
-            if (li > 0.0f && lj > 0.0f) gam = 1.0f;
-            else if (li <= 0.0f && lj <= 0.0f) gam = 0.0f;
-            else gam = (fmaxf(li, 0.0f) - fmaxf(lj, 0.0f)) / (li - lj);
-            acc[u][v] *= gam;
-        }
+    product_store<S, NT, 0>(sV, sA, nullptr, k, tid, [&](int i, int j, float v) {  // Gamma o (V^T G V)
+        const float li = sLam[i], lj = sLam[j];
+        float gam;
+        if (li > 0.0f && lj > 0.0f) gam = 1.0f;
+        else if (li <= 0.0f && lj <= 0.0f) gam = 0.0f;
+        else gam = (fmaxf(li, 0.0f) - fmaxf(lj, 0.0f)) / (li - lj);
+        sA[i * LD + j] = gam * v;
+    });
     __syncthreads();
-#pragma unroll
-    for (int u = 0; u < T; ++u)
-#pragma unroll
-        for (int v = 0; v < T; ++v) sA[(ti * T + u) * LD + tj * T + v] = acc[u][v];
+    product_store<S, NT, 1>(sV, sA, nullptr, k, tid, to_sA);  // V (Gamma o B)
     __syncthreads();
-    tile_product<S, NT, 1>(sV, sA, acc, ti, tj);  // V (Gamma o B)
-#pragma unroll
-    for (int u = 0; u < T; ++u)
-#pragma unroll
-        for (int v = 0; v < T; ++v) sX[(ti * T + u) * LD + tj * T + v] = acc[u][v];
-    __syncthreads();
-    tile_product<S, NT, 2>(sX, sV, acc, ti, tj);  // (V (Gamma o B)) V^T
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < T; ++u)
-#pragma unroll
-        for (int v = 0; v < T; ++v) sA[(ti * T + u) * LD + tj * T + v] = acc[u][v];
+    // (V (Gamma o B)) V^T is symmetric: its lower triangle suffices
+    product_store<S, NT, 2, true>(sA, sV, sOne, k, tid, to_sA);
     __syncthreads();
     for (int s = tid; s < nslot; s += NT) {
         const int i = tri_row(s), j = s - i * (i + 1) / 2;
-        a.gW[off + s] = (i == j) ? sA[i * LD + i] : sA[i * LD + j] + sA[j * LD + i];
+        a.gW[off + s] = (i == j) ? sA[i * LD + i] : 2.0f * sA[i * LD + j];
     }
 }
 
@@ -986,7 +973,9 @@ int proj_bucket(int smax) {
     if (smax <= 48) return 48;
     if (smax <= 64) return 64;
     if (smax <= 80) return 80;
-    return 96;
+    if (smax <= 96) return 96;
+    if (smax <= 112) return 112;
+    return 128;
 }
 
 bool proj_threads_ok(int S, int nthreads) {
@@ -1005,19 +994,24 @@ void launch_project(const ProjArgs &a, int smax, int nthreads, hipStream_t s) {
     case 48: nt == 512 ? launch_t<48, 512>(a, s) : launch_t<48, 256>(a, s); break;
     case 64: nt == 512 ? launch_t<64, 512>(a, s) : launch_t<64, 256>(a, s); break;
     case 80: nt == 512 ? launch_t<80, 512>(a, s) : launch_t<80, 256>(a, s); break;
-    default: nt == 512 ? launch_t<96, 512>(a, s) : launch_t<96, 256>(a, s); break;
+    case 96: nt == 512 ? launch_t<96, 512>(a, s) : launch_t<96, 256>(a, s); break;
+    case 112: nt == 512 ? launch_t<112, 512>(a, s) : launch_t<112, 256>(a, s); break;
+    default: nt == 512 ? launch_t<128, 512>(a, s) : launch_t<128, 256>(a, s); break;
     }
 }
 
 int project_queue_occupancy(int smax, int nthreads) {
     const bool w = nthreads == 512;
+    if (!w && proj_bucket(smax) > 96) return 0;  // queue launches over buckets 112 and 128 use 512 threads
     switch (proj_bucket(smax)) {
     case 16: return w ? queue_occ_t<16, 512>() : queue_occ_t<16, 256>();
     case 32: return w ? queue_occ_t<32, 512>() : queue_occ_t<32, 256>();
     case 48: return w ? queue_occ_t<48, 512>() : queue_occ_t<48, 256>();
     case 64: return w ? queue_occ_t<64, 512>() : queue_occ_t<64, 256>();
     case 80: return w ? queue_occ_t<80, 512>() : queue_occ_t<80, 256>();
-    default: return w ? queue_occ_t<96, 512>() : queue_occ_t<96, 256>();
+    case 96: return w ? queue_occ_t<96, 512>() : queue_occ_t<96, 256>();
+    case 112: return queue_occ_t<112, 512>();
+    default: return queue_occ_t<128, 512>();
     }
 }
 
@@ -1025,13 +1019,20 @@ void launch_project_queue(const ProjArgs &a, int smax, int nthreads, int grid, u
                           hipStream_t s) {
     if (a.nblk <= 0 || grid <= 0) return;
     const bool w = nthreads == 512;
+    // Buckets 112 and 128 are drained by 512-thread workgroups only: with 256
+    // threads every thread holds twice the eigenvector rows, and the kernel
+    // that drains all eight buckets exceeds the architected registers (the
+    // 256-thread build gave wrong results in its bucket-96 loop).
+    if (!w && proj_bucket(smax) > 96) return;
     switch (proj_bucket(smax)) {
     case 16: w ? launch_queue_t<16, 512>(a, grid, ticket, s) : launch_queue_t<16, 256>(a, grid, ticket, s); break;
     case 32: w ? launch_queue_t<32, 512>(a, grid, ticket, s) : launch_queue_t<32, 256>(a, grid, ticket, s); break;
     case 48: w ? launch_queue_t<48, 512>(a, grid, ticket, s) : launch_queue_t<48, 256>(a, grid, ticket, s); break;
     case 64: w ? launch_queue_t<64, 512>(a, grid, ticket, s) : launch_queue_t<64, 256>(a, grid, ticket, s); break;
     case 80: w ? launch_queue_t<80, 512>(a, grid, ticket, s) : launch_queue_t<80, 256>(a, grid, ticket, s); break;
-    default: w ? launch_queue_t<96, 512>(a, grid, ticket, s) : launch_queue_t<96, 256>(a, grid, ticket, s); break;
+    case 96: w ? launch_queue_t<96, 512>(a, grid, ticket, s) : launch_queue_t<96, 256>(a, grid, ticket, s); break;
+    case 112: launch_queue_t<112, 512>(a, grid, ticket, s); break;
+    default: launch_queue_t<128, 512>(a, grid, ticket, s); break;
     }
 }
 
@@ -1043,7 +1044,9 @@ void launch_project_vjp(const VjpArgs &a, int smax, hipStream_t s) {
     case 48: launch_vjp_t<48, 256>(a, s); break;
     case 64: launch_vjp_t<64, 256>(a, s); break;
     case 80: launch_vjp_t<80, 256>(a, s); break;
-    default: launch_vjp_t<96, 256>(a, s); break;
+    case 96: launch_vjp_t<96, 256>(a, s); break;
+    case 112: launch_vjp_t<112, 256>(a, s); break;
+    default: launch_vjp_t<128, 256>(a, s); break;
     }
 }
 

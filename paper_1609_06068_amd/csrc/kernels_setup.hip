@@ -382,4 +382,175 @@ void launch_trtri(const double *L, int m, double *LinvT, double *Linv, hipStream
                        LinvT);
 }
 
+namespace {
+
+// ---- Sparse factor of M = A D^-1 A^T (sparse A) ----------------------------
+// The rows and columns of M are taken in an elimination order (a perfect one
+// when M's graph is chordal, else minimum degree; host symbolic step): column
+// j of the factor L holds the rows cp[j] .. cp[j+1] of ri[] (increasing, the
+// diagonal first).  Numeric work on the device, deterministic order.
+
+// Column j of L <- the entries of M in column j's structure (rows >= j of
+// M's row order[j], in the factor's order): one thread per column, adding the
+// products of the coefficients that share each pattern entry, as k_sp_syrk.
+__global__ __launch_bounds__(256) void k_spchol_fill(const int32_t *__restrict__ cp, const int32_t *__restrict__ ri,
+                                                     const int32_t *__restrict__ order,
+                                                     const int32_t *__restrict__ pinv,
+                                                     const int32_t *__restrict__ sp_ptr,
+                                                     const int32_t *__restrict__ sp_col,
+                                                     const double *__restrict__ sp_val,
+                                                     const int32_t *__restrict__ tid,
+                                                     const int32_t *__restrict__ tc_ptr,
+                                                     const int32_t *__restrict__ tc_row,
+                                                     const double *__restrict__ tc_val,
+                                                     const double *__restrict__ s2, int m, double *__restrict__ Lv,
+                                                     double *__restrict__ diag0) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= m) return;
+    const int32_t c0 = cp[j], c1 = cp[j + 1];
+    for (int32_t p = c0; p < c1; ++p) Lv[p] = 0.0;
+    const int32_t r = order[j];
+    for (int32_t q = sp_ptr[r]; q < sp_ptr[r + 1]; ++q) {
+        const double a = sp_val[q] * s2[sp_col[q]];
+        const int32_t t = tid[q];
+        for (int32_t u = tc_ptr[t]; u < tc_ptr[t + 1]; ++u) {
+            const int32_t i = pinv[tc_row[u]];
+            if (i < j) continue;
+            int32_t lo = c0, hi = c1 - 1;  // i is in the column's structure
+            while (lo < hi) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (ri[mid] < i) lo = mid + 1;
+                else hi = mid;
+            }
+            Lv[lo] += a * tc_val[u];
+        }
+    }
+    diag0[j] = Lv[c0];
+}
+
+// Left-looking Cholesky of the columns of one elimination-tree level (their
+// descendants are done): column j -= L_jk L(rows >= j, k) over the columns k
+// with L_jk != 0 (rk lists: k increasing, with the position of row j in
+// column k), then scaled by 1 / sqrt of its diagonal.  One workgroup per
+// column; threads over the rows of column k.  A pivot <= 2^-40 times M_jj
+// flags rank deficiency (info[0] = 1, info[1] = the original row) and is
+// replaced by 1.
+__global__ __launch_bounds__(256) void k_spchol_level(const int32_t *__restrict__ cols, const int32_t *__restrict__ cp,
+                                                      const int32_t *__restrict__ ri,
+                                                      const int32_t *__restrict__ rk_ptr,
+                                                      const int32_t *__restrict__ rk_col,
+                                                      const int32_t *__restrict__ rk_pos,
+                                                      const int32_t *__restrict__ order,
+                                                      const double *__restrict__ diag0, double *__restrict__ Lv,
+                                                      int32_t *info) {
+    __shared__ double s_ljj;
+    const int j = cols[blockIdx.x];
+    const int32_t c0 = cp[j], c1 = cp[j + 1];
+    for (int32_t q = rk_ptr[j]; q < rk_ptr[j + 1]; ++q) {
+        const int32_t k = rk_col[q];
+        const int32_t k0 = cp[k] + rk_pos[q], k1 = cp[k + 1];
+        const double ljk = Lv[k0];
+        for (int32_t p = k0 + threadIdx.x; p < k1; p += 256) {
+            const int32_t i = ri[p];
+            int32_t lo = c0, hi = c1 - 1;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (ri[mid] < i) lo = mid + 1;
+                else hi = mid;
+            }
+            Lv[lo] -= Lv[p] * ljk;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double piv = Lv[c0];
+        if (!(piv > ldexp(diag0[j], -40))) {
+            if (atomicCAS(&info[0], 0, 1) == 0) info[1] = order[j];
+            piv = 1.0;
+        }
+        s_ljj = sqrt(piv);
+        Lv[c0] = s_ljj;
+    }
+    __syncthreads();
+    const double inv = 1.0 / s_ljj;
+    for (int32_t p = c0 + 1 + threadIdx.x; p < c1; p += 256) Lv[p] *= inv;
+}
+
+// Column j of X = L^-1: nonzero on the elimination-tree path from j to its
+// root (xr[xp[j] .. xp[j+1]), increasing); X_jj = 1 / L_jj and, along the
+// path, X_ij = -(sum over path rows k < i with L_ik != 0 of L_ik X_kj) / L_ii.
+// One wave per column; the path and its values in LDS (at most 256).
+constexpr int kMaxPath = 256;
+__global__ __launch_bounds__(64) void k_spinv_col(const int32_t *__restrict__ cp, const int32_t *__restrict__ ri,
+                                                  const int32_t *__restrict__ rk_ptr,
+                                                  const int32_t *__restrict__ rk_col,
+                                                  const int32_t *__restrict__ rk_pos,
+                                                  const double *__restrict__ Lv, const int64_t *__restrict__ xp,
+                                                  const int32_t *__restrict__ xr, double *__restrict__ xv, int m) {
+    __shared__ int32_t path[kMaxPath];
+    __shared__ double val[kMaxPath];
+    const int j = blockIdx.x;
+    if (j >= m) return;
+    const int lane = threadIdx.x;
+    const int64_t p0 = xp[j];
+    const int P = (int)(xp[j + 1] - p0);
+    for (int t = lane; t < P; t += 64) path[t] = xr[p0 + t];
+    if (lane == 0) val[0] = 1.0 / Lv[cp[j]];
+    __syncthreads();
+    for (int t = 1; t < P; ++t) {
+        const int i = path[t];
+        double acc = 0.0;
+        for (int32_t q = rk_ptr[i] + lane; q < rk_ptr[i + 1]; q += 64) {
+            const int32_t k = rk_col[q];
+            if (k < j) continue;
+            int lo = 0, hi = t - 1;  // is k on the path below i?
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (path[mid] < k) lo = mid + 1;
+                else hi = mid;
+            }
+            if (path[lo] == k) acc += Lv[cp[k] + rk_pos[q]] * val[lo];
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (lane == 0) val[t] = -acc / Lv[cp[i]];
+        __syncthreads();
+    }
+    for (int t = lane; t < P; t += 64) xv[p0 + t] = val[t];
+}
+
+// out[q] = in[idx[q]] (value layouts of the CSR copies)
+__global__ __launch_bounds__(256) void k_gather_vals(const double *__restrict__ in, const int64_t *__restrict__ idx,
+                                                     double *__restrict__ out, int64_t n) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q < n) out[q] = in[idx[q]];
+}
+
+}  // namespace
+
+void launch_spchol_fill(const Dev &d, const SpFactor &f, const int32_t *tid, hipStream_t s) {
+    hipLaunchKernelGGL(k_spchol_fill, dim3((d.m + 255) / 256), dim3(256), 0, s, f.cp, f.ri, f.order, f.pinv,
+                       (const int32_t *)d.sp_ptr, (const int32_t *)d.sp_col, (const double *)d.sp_val, tid,
+                       (const int32_t *)d.tc_ptr, (const int32_t *)d.tc_row, (const double *)d.tc_val,
+                       (const double *)d.s2, d.m, f.Lv, f.diag0);
+}
+
+void launch_spchol(const Dev &d, const SpFactor &f, const std::vector<int32_t> &level_off, int32_t *info,
+                   hipStream_t s) {
+    for (size_t l = 0; l + 1 < level_off.size(); ++l) {
+        const int ncol = level_off[l + 1] - level_off[l];
+        if (ncol > 0)
+            hipLaunchKernelGGL(k_spchol_level, dim3(ncol), dim3(256), 0, s, f.level_cols + level_off[l], f.cp, f.ri,
+                               f.rk_ptr, f.rk_col, f.rk_pos, f.order, (const double *)f.diag0, f.Lv, info);
+    }
+    hipLaunchKernelGGL(k_spinv_col, dim3(d.m), dim3(64), 0, s, f.cp, f.ri, f.rk_ptr, f.rk_col, f.rk_pos,
+                       (const double *)f.Lv, f.xp, f.xr, f.xv, d.m);
+}
+
+int spinv_max_path() { return kMaxPath; }
+
+void launch_gather_vals(const double *in, const int64_t *idx, double *out, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_gather_vals, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, idx, out, n);
+}
+
 }  // namespace cdcs

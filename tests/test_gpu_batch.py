@@ -111,7 +111,7 @@ def test_batch_affine_projection(torch):
 def test_batch_errors(torch):
     probs = _small_batch()[:2]
     sol = cdcs.BatchSolver(probs)
-    st = sol.new_state("dual")
+    st = sol.new_state("primal")  # no v buffer
     with pytest.raises(cdcs.CdcsError) as e:
         sol.solve(st, form="dual", tol=0.0, max_iter=2)
     assert e.value.status == cdcs.E_ARG
@@ -137,4 +137,60 @@ def test_many_sdp_workload_subset(torch):
     for q in (0, 17, 63):
         ref = O.Oracle(probs[q]).admm_primal(max_iter=2000, tol=1e-4)
         assert abs(inst[q].obj_primal - ref.obj_primal) <= 1e-4 * max(1.0, abs(ref.obj_primal))
+    sol.close()
+
+
+def _split_v(sol, st, q):
+    k0, k1 = sol.clique_off[q], sol.clique_off[q + 1]
+    off = sol.offsets
+    return st["v"].cpu().numpy()[off[k0]:off[k1]].astype(np.float64)
+
+
+def test_batch_dual_iterates_after_50_iterations(torch):
+    """Algorithm 2 on a batch handle: per-instance parity with the oracle."""
+    probs = _small_batch()
+    sol = cdcs.BatchSolver(probs)
+    st = sol.new_state("dual")
+    info = sol.solve(st, form="dual", tol=0.0, max_iter=50, check_every=10)
+    assert info.iters == 50 and info.jacobi_cap_hits == 0
+    for q, prob in enumerate(probs):
+        ref = O.Oracle(prob).admm_dual(max_iter=50)
+        x, blk, lam = _split(sol, st, q, probs)
+        assert _rel(x, ref.x) <= 1e-4, q
+        assert _rel(blk, cdcs.pack_blocks(ref.blocks)) <= 1e-4, q
+        assert _rel(lam, cdcs.pack_blocks(ref.lam)) <= 1e-4, q
+        assert _rel(_split_v(sol, st, q), cdcs.pack_blocks(ref.v)) <= 1e-4, q
+    sol.close()
+
+
+def test_batch_dual_per_instance_stopping(torch):
+    probs = _small_batch()
+    sol = cdcs.BatchSolver(probs)
+    st = sol.new_state("dual")
+    info = sol.solve(st, form="dual", tol=1e-4, max_iter=3000, check_every=25)
+    assert info.converged
+    inst = sol.instance_info()
+    for q, prob in enumerate(probs):
+        ref = O.Oracle(prob).admm_dual(max_iter=3000, tol=1e-4)
+        assert ref.converged and inst[q].status == cdcs.OK
+        assert abs(inst[q].iters - ref.iters) <= max(3, ref.iters // 50), (q, inst[q].iters, ref.iters)
+        assert abs(inst[q].obj_primal - ref.obj_primal) <= 1e-4 * max(1.0, abs(ref.obj_primal))
+        assert abs(inst[q].obj_dual - ref.obj_dual) <= 1e-4 * max(1.0, abs(ref.obj_dual))
+        assert max(inst[q].eps_p, inst[q].eps_d) <= 1e-4
+    sol.close()
+
+
+def test_batch_dual_matches_single_handles(torch):
+    probs = _small_batch()[:3]
+    sol = cdcs.BatchSolver(probs)
+    st = sol.new_state("dual")
+    sol.solve(st, form="dual", tol=0.0, max_iter=30, check_every=0)
+    for q, prob in enumerate(probs):
+        one = cdcs.Solver(prob)
+        s1 = one.new_state("dual")
+        one.solve(s1, form="dual", tol=0.0, max_iter=30, check_every=0)
+        x, blk, lam = _split(sol, st, q, probs)
+        assert _rel(x, s1["x"].cpu().numpy()) <= 1e-5
+        assert _rel(lam, s1["lam"].cpu().numpy().astype(np.float64)) <= 1e-5
+        one.close()
     sol.close()

@@ -42,7 +42,7 @@ def _full_to_packed_grad(Wbar, k):
 
 
 def test_projection_vjp_matches_oracle(torch):
-    sizes = np.array([1, 3, 8, 17, 24, 30, 33, 48, 64, 80, 96])
+    sizes = np.array([1, 3, 8, 17, 24, 30, 33, 48, 64, 80, 96, 100, 126])
     rng = np.random.default_rng(4)
     W32 = [np.asarray(synth.random_symmetric(int(s), seed=300 + int(s)), dtype=np.float32) for s in sizes]
     gps = [rng.standard_normal(int(s) * (int(s) + 1) // 2).astype(np.float32) for s in sizes]

@@ -42,10 +42,11 @@ def _proj_err(torch, blocks):
     return np.array(errs), Pb
 
 
-SWEEP = [1, 2, 3, 4, 5, 7, 8, 15, 16, 17, 24, 30, 31, 32, 33, 40, 44, 63, 64, 65, 80, 95, 96]
+SWEEP = [1, 2, 3, 4, 5, 7, 8, 15, 16, 17, 24, 30, 31, 32, 33, 40, 44, 63, 64, 65, 80, 95, 96, 97, 111, 112, 113,
+         120, 125, 126]
 
 
-@pytest.mark.parametrize("bucket", [(1, 32), (33, 64), (65, 96)])
+@pytest.mark.parametrize("bucket", [(1, 32), (33, 64), (65, 96), (97, 126)])
 def test_projection_parity_size_sweep(torch, bucket):
     lo, hi = bucket
     sizes = [s for s in SWEEP if lo <= s <= hi] * 2

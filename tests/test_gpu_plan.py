@@ -92,7 +92,7 @@ def test_tuning_report_and_plan_errors(torch, small):
     assert t["persistent"] == (t["queue_us"] < t["buckets_us"])
     assert sum(b["count"] for b in t["buckets"]) == prob.p
     assert [b["size"] for b in t["buckets"]] == sorted(b["size"] for b in t["buckets"])
-    assert all(b["size"] in (16, 32, 48, 64, 80, 96) for b in t["buckets"])
+    assert all(b["size"] in (16, 32, 48, 64, 80, 96, 112, 128) for b in t["buckets"])
     if t["persistent"]:
         assert t["threads"] in (256, 512) and 0 < t["grid"] <= prob.p
     with pytest.raises(cdcs.CdcsError) as e:
@@ -199,4 +199,27 @@ def test_project_cliques_with_the_plan_vs_oracle(torch, small, plan):
     P2 = sol.project_cliques(Wp).cpu().numpy()
     P3 = sol.project_cliques(Wp).cpu().numpy()
     assert np.array_equal(P2, P3)
+    sol.close()
+
+
+@pytest.mark.parametrize("plan", [(True, 512), (False, 256), (False, 512), (False, 0)],
+                         ids=["queue512", "buckets256", "buckets512", "tuned"])
+def test_cliques_up_to_126_vs_oracle(torch, plan):
+    """A clique tree with cliques of 60..126 vertices (buckets 64 to 128):
+    every launch plan through 20 ADMM iterations against the oracle (the
+    queue launch over buckets above 96 takes 512 threads only)."""
+    prob = synth.peo_chordal(p=8, smin=60, smax=126, omax=8, m=60, nnz_row=20, seed=4343)
+    assert prob.clique_sizes().max() > 112
+    ref = O.Oracle(prob).solve("primal", rho=1.0, max_iter=20)
+    sol = cdcs.Solver(prob)
+    with pytest.raises(cdcs.CdcsError) as e:
+        sol.set_projection_plan(True, 256)
+    assert e.value.status == cdcs.E_ARG
+    if plan != (False, 0):
+        sol.set_projection_plan(*plan)
+    st = sol.new_state("primal")
+    info = sol.solve(st, form="primal", tol=0.0, max_iter=20, check_every=10)
+    assert info.iters == 20 and info.jacobi_cap_hits == 0
+    assert _rel(st["x"].cpu().numpy(), ref.x) <= 1e-4
+    assert _rel(_lam(sol, st), np.concatenate([B.ravel() for B in ref.lam])) <= 1e-4
     sol.close()
