@@ -97,8 +97,11 @@ def algorithmic_bytes(sol, prob):
     out = {
         # L^-1 and L^-T (dense triangles, or CSR: 4 B column + 8 B value + 8 B gathered element), vectors
         "trmv": (2 * sol.nnz_factor * (4 + 8 + 8) if sol.sparse_factor else 2 * (m * (m + 1) // 2) * 8) + 4 * m * 8,
-        "project": nU * 8 + ns * (4 + 4 + 4) + p * 24,        # x, lam in/out, x_k out, partials
-        "scatter": ns * 8 + nU * (8 * 3 + 8 * 2),             # x_k, lam; c, 1/D, w; S_prev in, u and S out
+        # x, lam in/out, x_k in/out, the per-slot x_k difference out, partials
+        "project": nU * 8 + ns * (4 + 4 + 4 + 4 + 4) + p * 24,
+        # per slot: its index, x_k, lam and x_k difference; per entry: the inverse-map
+        # pointer, c, u out and a bit of w
+        "scatter": ns * (4 + 4 + 4 + 4) + nU * (4 + 8 + 8) + nU // 8,
     }
     if sol.sparse_a:
         nnz = sol.nnz_a

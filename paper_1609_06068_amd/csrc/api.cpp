@@ -428,8 +428,14 @@ cdcs_status upload_common(cdcs_handle *h, const std::vector<int32_t> &size, cons
     CK(h->alloc(&d.t, d.ldM));
     CK(h->alloc(&d.tpart, 8 * d.ldM));
     CK(h->alloc(&d.y1, d.ldM));
-    CK(h->alloc(&d.sx, 2 * d.nU));
-    HIP_OK(hipMemsetAsync(d.sx, 0, (size_t)(2 * d.nU) * sizeof(double), s));
+    CK(h->alloc(&d.dslot, d.nslots));
+    HIP_OK(hipMemsetAsync(d.dslot, 0, (size_t)d.nslots * sizeof(float), s));
+    {
+        std::vector<uint32_t> bits((size_t)((d.nU + 31) / 32), 0u);
+        for (int64_t e = 0; e < d.nU; ++e)
+            if (wt[(size_t)e] == 2.0) bits[(size_t)(e >> 5)] |= 1u << (e & 31);
+        CK(upload(h, &d.wbits, bits, s));
+    }
     CK(h->alloc(&d.cpart, 4 * (int64_t)p));
     HIP_OK(hipMemsetAsync(d.cpart, 0, (size_t)(4 * p) * sizeof(double), s));
     CK(h->alloc(&d.vpart, 5 * (int64_t)vupdate_blocks(d)));
@@ -1044,6 +1050,7 @@ ProjArgs proj_args(const cdcs_handle *h, int mode, const cdcs_state *st, double 
     a.warm_store = 1;
     a.cpart = d.cpart;
     a.ctl = d.ctl;
+    a.dslot = mode == PROJ_PRIMAL ? d.dslot : nullptr;
     if (h->save_evals || h->save_evecs) {
         a.evals = h->save_evals;
         a.eoff = h->diff.eoff;

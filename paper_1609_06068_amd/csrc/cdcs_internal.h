@@ -61,6 +61,7 @@ struct ProjArgs {
     const int64_t *vwoff;      // [*] offsets of the k x k blocks in vwarm
     int32_t warm_store;        // write the new eigenvectors back to vwarm
     double *cpart;             // [p][4] per-block partial sums
+    float *dslot;              // [nslots] Alg. 1: x_k(new) - x_k(old) per slot (the dual residual's terms), or NULL
     Ctl *ctl;                  // may be NULL (standalone)
 };
 
@@ -218,7 +219,8 @@ struct Dev {
     double *t = nullptr;           // [m]
     double *tpart = nullptr;       // [8 * m] split-K partials of A u
     double *y1 = nullptr;          // [m]
-    double *sx = nullptr;          // [2 * nU] sum_k H_k^T x_k, two generations
+    float *dslot = nullptr;        // [nslots] x_k(new) - x_k(old) of the last Alg. 1 projection, per slot
+    uint32_t *wbits = nullptr;     // [(nU + 31) / 32] bit e: entry e is off the diagonal (w_e = 2)
     double *cpart = nullptr;       // [p * 4]
     double *spart = nullptr;       // [nsblk * 2]
     double *vpart = nullptr;       // [nvblk * 5]

@@ -79,40 +79,48 @@ __global__ __launch_bounds__(kNT) void k_reset_ctl(Ctl *ctl, int max_iter, doubl
 // reproducible.
 constexpr int kHeavy = 32;
 
-// Alg. 1 right-hand side r1 = sum_k H_k^T (x_k + lam_k / rho) - c / rho, u = r1 / D,
-// plus the dual-residual terms: S^n = sum_k H_k^T x_k is kept in two generations
-// (indexed by the parity of the completed-iteration count, so a repeated launch
-// for the same n rewrites the same values), and sum_k H_k^T lam_k.
+// w_e from the packed flags: 2 off the diagonal, 1 on it.
+__device__ __forceinline__ double entry_weight(const uint32_t *__restrict__ wbits, int64_t e) {
+    return ((wbits[e >> 5] >> (e & 31)) & 1u) ? 2.0 : 1.0;
+}
+
+// Alg. 1 right-hand side r1 = sum_k H_k^T (x_k + lam_k / rho) - c / rho,
+// u = r1 / D (D_e = the number of slots of e, read from the inverse map), plus
+// the dual-residual terms ||sum_k H_k^T (x_k - x_k_prev)||_w^2 (from the
+// projection's per-slot differences) and ||sum_k H_k^T lam_k||_w^2 as
+// per-block partial sums.
 __global__ __launch_bounds__(kNT) void k_scatter_primal(const int32_t *__restrict__ inv_ptr,
                                                         const int32_t *__restrict__ inv_slot,
                                                         const int32_t *__restrict__ heavy, int nheavy,
                                                         int nlight_blocks, const float *__restrict__ blk,
                                                         const float *__restrict__ lam,
+                                                        const float *__restrict__ dslot,
                                                         const double *__restrict__ c,
-                                                        const double *__restrict__ invD,
-                                                        const double *__restrict__ wt, double *__restrict__ u,
-                                                        double *__restrict__ sx, double *__restrict__ spart,
-                                                        int64_t nU, double rho, const Ctl *ctl) {
+                                                        const uint32_t *__restrict__ wbits, double *__restrict__ u,
+                                                        double *__restrict__ spart, int64_t nU, double rho,
+                                                        const Ctl *ctl) {
     __shared__ double red[kNT / 64];
     if (ctl->stop) return;
-    const int n = ctl->iter;
     const int lane = threadIdx.x & 63;
     int64_t e = -1;
-    double s_x = 0.0, s_l = 0.0;
+    double s_x = 0.0, s_l = 0.0, s_d = 0.0;
+    int32_t D = 1;
     bool owner = false;
     if ((int)blockIdx.x < nlight_blocks) {
         e = (int64_t)blockIdx.x * kNT + threadIdx.x;
         if (e < nU) {
             const int32_t q0 = inv_ptr[e], q1 = inv_ptr[e + 1];
-            if (q1 - q0 <= kHeavy) {
+            D = q1 - q0;
+            if (D <= kHeavy) {
                 owner = true;
                 // unrolled so that the loads of several slots are in flight
-                // together (the sum keeps its order)
+                // together (the sums keep their order)
 #pragma unroll 4
                 for (int32_t q = q0; q < q1; ++q) {
                     const int32_t sl = inv_slot[q];
                     s_x += (double)blk[sl];
                     s_l += (double)lam[sl];
+                    s_d += (double)dslot[sl];
                 }
             }
         }
@@ -121,26 +129,25 @@ __global__ __launch_bounds__(kNT) void k_scatter_primal(const int32_t *__restric
         if (hw < nheavy) {
             e = heavy[hw];
             const int32_t q0 = inv_ptr[e], q1 = inv_ptr[e + 1];
+            D = q1 - q0;
             for (int32_t q = q0 + lane; q < q1; q += 64) {
                 const int32_t sl = inv_slot[q];
                 s_x += (double)blk[sl];
                 s_l += (double)lam[sl];
+                s_d += (double)dslot[sl];
             }
             s_x = wave_sum_d(s_x);
             s_l = wave_sum_d(s_l);
+            s_d = wave_sum_d(s_d);
             owner = (lane == 0);
         }
     }
     double ds2 = 0.0, sl2 = 0.0;
     if (owner) {
         const double r1 = s_x + s_l / rho - c[e] / rho;
-        u[e] = r1 * invD[e];
-        double *cur = sx + (int64_t)(n & 1) * nU;
-        const double *prev = sx + (int64_t)((n + 1) & 1) * nU;
-        const double d = s_x - prev[e];
-        cur[e] = s_x;
-        const double w = wt[e];
-        ds2 = w * d * d;
+        u[e] = r1 / (double)D;
+        const double w = entry_weight(wbits, e);
+        ds2 = w * s_d * s_d;
         sl2 = w * s_l * s_l;
     }
     ds2 = block_sum_d(ds2, red);
@@ -218,8 +225,7 @@ __global__ __launch_bounds__(kNT) void k_scatter_dual(const int32_t *__restrict_
                                                       const int32_t *__restrict__ heavy, int nheavy,
                                                       int nlight_blocks, const float *__restrict__ blk,
                                                       const float *__restrict__ lam,
-                                                      const double *__restrict__ c,
-                                                      const double *__restrict__ invD, double *__restrict__ u,
+                                                      const double *__restrict__ c, double *__restrict__ u,
                                                       int64_t nU, double rho,
                                                       const Ctl *ctl) {
     if (ctl->stop) return;
@@ -235,7 +241,7 @@ __global__ __launch_bounds__(kNT) void k_scatter_dual(const int32_t *__restrict_
             const int32_t sl = inv_slot[q];
             s += (double)blk[sl] + (double)lam[sl] / rho;
         }
-        u[e] = (c[e] - s) * invD[e];
+        u[e] = (c[e] - s) / (double)(q1 - q0);
     } else {
         const int hw = ((int)blockIdx.x - nlight_blocks) * (kNT / 64) + (threadIdx.x >> 6);
         if (hw >= nheavy) return;
@@ -247,9 +253,7 @@ __global__ __launch_bounds__(kNT) void k_scatter_dual(const int32_t *__restrict_
             s += (double)blk[sl] + (double)lam[sl] / rho;
         }
         s = wave_sum_d(s);
-        if (lane == 0) {
-            u[e] = (c[e] - s) * invD[e];
-            }
+        if (lane == 0) u[e] = (c[e] - s) / (double)(q1 - q0);
     }
 }
 
@@ -717,8 +721,9 @@ void launch_reset_ctl(const Dev &d, int max_iter, double tol, hipStream_t s) {
 void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, double rho,
                            hipStream_t s) {
     hipLaunchKernelGGL(k_scatter_primal, dim3(scatter_blocks(d)), dim3(kNT), 0, s, d.inv_ptr, d.inv_slot,
-                       (const int32_t *)d.heavy, d.nheavy, scatter_light_blocks(d), blk, lam, d.c, d.invD, d.wt, d.u,
-                       d.sx, d.spart, d.nU, rho, (const Ctl *)d.ctl);
+                       (const int32_t *)d.heavy, d.nheavy, scatter_light_blocks(d), blk, lam,
+                       (const float *)d.dslot, (const double *)d.c, (const uint32_t *)d.wbits, d.u, d.spart, d.nU,
+                       rho, (const Ctl *)d.ctl);
 }
 
 void launch_check_primal(const Dev &d, double rho, hipStream_t s) {
@@ -733,7 +738,7 @@ void launch_check_primal(const Dev &d, double rho, hipStream_t s) {
 void launch_scatter_dual(const Dev &d, const float *blk, const float *lam, double rho,
                         hipStream_t s) {
     hipLaunchKernelGGL(k_scatter_dual, dim3(scatter_blocks(d)), dim3(kNT), 0, s, d.inv_ptr, d.inv_slot,
-                       (const int32_t *)d.heavy, d.nheavy, scatter_light_blocks(d), blk, lam, d.c, d.invD, d.u,
+                       (const int32_t *)d.heavy, d.nheavy, scatter_light_blocks(d), blk, lam, d.c, d.u,
                        d.nU, rho, (const Ctl *)d.ctl);
 }
 

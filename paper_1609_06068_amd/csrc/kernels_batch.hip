@@ -52,32 +52,28 @@ __global__ __launch_bounds__(kNT) void k_bscatter_primal(const int4 *__restrict_
                                                          const int32_t *__restrict__ inv_ptr,
                                                          const int32_t *__restrict__ inv_slot,
                                                          const float *__restrict__ blk, const float *__restrict__ lam,
-                                                         const double *__restrict__ c, const double *__restrict__ invD,
-                                                         const double *__restrict__ wt, double *__restrict__ u,
-                                                         double *__restrict__ sx, double *__restrict__ spart,
-                                                         int64_t nU, double rho, const Ctl *ctl) {
+                                                         const float *__restrict__ dslot,
+                                                         const double *__restrict__ c,
+                                                         const uint32_t *__restrict__ wbits, double *__restrict__ u,
+                                                         double *__restrict__ spart, double rho, const Ctl *ctl) {
     __shared__ double red[kNT / 64];
     if (ctl->stop) return;
     const int4 bk = sblk[blockIdx.x];
     if (istop[bk.x]) return;
-    const int n = ctl->iter;
     const int64_t e = (int64_t)bk.y + threadIdx.x;
     double ds2 = 0.0, sl2 = 0.0;
     if (e < bk.z) {
-        double s_x = 0.0, s_l = 0.0;
-        const int32_t q1 = inv_ptr[e + 1];
-        for (int32_t q = inv_ptr[e]; q < q1; ++q) {
+        double s_x = 0.0, s_l = 0.0, s_d = 0.0;
+        const int32_t q0 = inv_ptr[e], q1 = inv_ptr[e + 1];
+        for (int32_t q = q0; q < q1; ++q) {
             const int32_t sl = inv_slot[q];
             s_x += (double)blk[sl];
             s_l += (double)lam[sl];
+            s_d += (double)dslot[sl];
         }
-        u[e] = (s_x + s_l / rho - c[e] / rho) * invD[e];
-        double *cur = sx + (int64_t)(n & 1) * nU;
-        const double *prev = sx + (int64_t)((n + 1) & 1) * nU;
-        const double d = s_x - prev[e];
-        cur[e] = s_x;
-        const double w = wt[e];
-        ds2 = w * d * d;
+        u[e] = (s_x + s_l / rho - c[e] / rho) / (double)(q1 - q0);
+        const double w = ((wbits[e >> 5] >> (e & 31)) & 1u) ? 2.0 : 1.0;
+        ds2 = w * s_d * s_d;
         sl2 = w * s_l * s_l;
     }
     ds2 = block_sum_d(ds2, red);
@@ -94,7 +90,7 @@ __global__ __launch_bounds__(kNT) void k_bscatter_dual(const int4 *__restrict__ 
                                                        const int32_t *__restrict__ inv_ptr,
                                                        const int32_t *__restrict__ inv_slot,
                                                        const float *__restrict__ blk, const float *__restrict__ lam,
-                                                       const double *__restrict__ c, const double *__restrict__ invD,
+                                                       const double *__restrict__ c,
                                                        double *__restrict__ u, double rho, const Ctl *ctl) {
     if (ctl->stop) return;
     const int4 bk = sblk[blockIdx.x];
@@ -102,12 +98,12 @@ __global__ __launch_bounds__(kNT) void k_bscatter_dual(const int4 *__restrict__ 
     const int64_t e = (int64_t)bk.y + threadIdx.x;
     if (e >= bk.z) return;
     double acc = 0.0;
-    const int32_t q1 = inv_ptr[e + 1];
-    for (int32_t q = inv_ptr[e]; q < q1; ++q) {
+    const int32_t q0 = inv_ptr[e], q1 = inv_ptr[e + 1];
+    for (int32_t q = q0; q < q1; ++q) {
         const int32_t sl = inv_slot[q];
         acc += (double)blk[sl] + (double)lam[sl] / rho;
     }
-    u[e] = (c[e] - acc) * invD[e];
+    u[e] = (c[e] - acc) / (double)(q1 - q0);
 }
 
 // Alg. 2 epilogue per slot block (q, s0, s1) of one instance: v_k = z_k +
@@ -560,7 +556,7 @@ void launch_bscatter_primal(const Dev &d, const float *blk, const float *lam, do
     const Batch &B = *d.batch;
     hipLaunchKernelGGL(k_bscatter_primal, dim3(B.nsblk), dim3(kNT), 0, s, (const int4 *)B.sblk,
                        (const int32_t *)B.istop, (const int32_t *)d.inv_ptr, (const int32_t *)d.inv_slot, blk, lam,
-                       (const double *)d.c, (const double *)d.invD, (const double *)d.wt, d.u, d.sx, d.spart, d.nU, rho,
+                       (const float *)d.dslot, (const double *)d.c, (const uint32_t *)d.wbits, d.u, d.spart, rho,
                        (const Ctl *)d.ctl);
 }
 
@@ -576,7 +572,7 @@ void launch_bscatter_dual(const Dev &d, const float *blk, const float *lam, doub
     const Batch &B = *d.batch;
     hipLaunchKernelGGL(k_bscatter_dual, dim3(B.nsblk), dim3(kNT), 0, s, (const int4 *)B.sblk, (const int32_t *)B.istop,
                        (const int32_t *)d.inv_ptr, (const int32_t *)d.inv_slot, blk, lam, (const double *)d.c,
-                       (const double *)d.invD, d.u, rho, (const Ctl *)d.ctl);
+                       d.u, rho, (const Ctl *)d.ctl);
 }
 
 void launch_bvupdate(const Dev &d, const double *x, const float *blk, float *lam, float *v, double rho,

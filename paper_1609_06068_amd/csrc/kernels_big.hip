@@ -206,6 +206,7 @@ __global__ __launch_bounds__(kNT) void k_big_epilogue(ProjArgs a, BigCliques b, 
             const double hx = a.x[a.gather[g]];
             const double pv = (double)pv32;
             a.lam[g] = (float)((double)a.lam[g] + a.rho * (pv - hx));
+            if (a.dslot != nullptr) a.dslot[g] = (float)(pv - (double)a.blk[g]);
             a.blk[g] = pv32;
             const double wgt = (i == j) ? 1.0 : 2.0;
             const double d = pv - hx;

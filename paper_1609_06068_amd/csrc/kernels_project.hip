@@ -694,13 +694,14 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
     double p0 = 0.0, p1 = 0.0, p2 = 0.0;
     for (int s0 = tid; s0 < nslot; s0 += GU * NT) {
         double hx[GU];
-        float lm[GU];
+        float lm[GU], bo[GU];
         if (a.mode == PROJ_PRIMAL) {
 #pragma unroll
             for (int u = 0; u < GU; ++u) {
                 const int64_t g = off + min(s0 + u * NT, nslot - 1);
                 hx[u] = a.x[a.gather[g]];
                 lm[u] = a.lam[g];
+                bo[u] = a.dslot != nullptr ? a.blk[g] : 0.0f;
             }
         }
 #pragma unroll
@@ -716,6 +717,7 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
                 const double pv = (double)pv32;
                 a.lam[g] = (float)((double)lm[u] + a.rho * (pv - hx[u]));
                 a.blk[g] = pv32;
+                if (a.dslot != nullptr) a.dslot[g] = (float)(pv - (double)bo[u]);
                 const double wgt = (i == j) ? 1.0 : 2.0;
                 const double d = pv - hx[u];
                 p0 += wgt * d * d;
