@@ -33,6 +33,14 @@ Readings of the paper taken here (each is also listed in the design notes):
   * Alg. 2 uses the unsubstituted multiplier update lam += rho (z - v); the
     printed shortcut lam = rho H_k x has the wrong sign (it is -rho H_k x,
     checked by a test).
+
+Vector cones (CDCS's other cone types, Sec. IV: free, nonnegative orthant,
+second-order cone) sit on the diagonal entries of vertices that lie in no
+clique; each is one more block of the decomposition with H_k selecting its
+entries (D_e = 1 on them).  Algorithm 1 projects onto the cones, Algorithm 2
+onto their dual cones (the free cone's dual cone is {0}).  The homogeneous
+self-dual embedding (the variant the paper names as future work, Sec. VI) is
+the class Hsde below; its readings are in its docstring.
 """
 from __future__ import annotations
 
@@ -169,6 +177,33 @@ def psd_project_batch_eig(blocks: list[np.ndarray]):
     return Ps, evs, Vs
 
 
+def soc_project(v: np.ndarray) -> np.ndarray:
+    """Euclidean projection onto the second-order cone {(t, z): ||z|| <= t}:
+    v itself inside the cone, 0 inside its polar (||z|| <= -t), otherwise
+    ((t + ||z||) / 2) (1, z / ||z||) (Boyd and Vandenberghe, Convex
+    Optimization, Exercise 8.3(c))."""
+    v = np.asarray(v, dtype=np.float64)
+    t, z = v[0], v[1:]
+    nz = float(np.sqrt(np.sum(z * z)))
+    if nz <= t:
+        return v.copy()
+    if nz <= -t:
+        return np.zeros_like(v)
+    a = 0.5 * (t + nz)
+    return np.concatenate([[a], (a / nz) * z])
+
+
+def vector_cone_project(kind: int, v: np.ndarray) -> np.ndarray:
+    """Projection onto a vector cone: free (R^n: identity), nonnegative
+    orthant (entrywise max(., 0)) or second-order cone (CDCS's cone types
+    besides PSD, Sec. IV)."""
+    if kind == 0:
+        return np.asarray(v, dtype=np.float64).copy()
+    if kind == 1:
+        return np.maximum(v, 0.0)
+    return soc_project(v)
+
+
 def cholesky(M: np.ndarray) -> np.ndarray:
     """M = L L^T (lower L).  Raises OracleError(E_RANK) if M is not PD."""
     M = np.ascontiguousarray(M, dtype=np.float64)
@@ -234,20 +269,69 @@ class Decomposition:
             ia, ib = np.tril_indices(s)
             self.tril.append((ia, ib))
             np.add.at(D, tab[ia, ib], 1.0)
+        # vector cones: each covers the diagonal entries of its vertices, which
+        # lie in no clique and in no other cone and have no off-diagonal entry
+        self.p = prob.p
+        self.vidx, self.vkind = [], []
+        in_clique = np.zeros(n, dtype=bool)
+        if prob.p > 0:
+            in_clique[np.asarray(prob.clique_vert, dtype=np.int64)] = True
+        offdiag_v = np.zeros(n, dtype=bool)
+        offdiag_v[ei[ei != ej]] = True
+        offdiag_v[ej[ei != ej]] = True
+        for q in range(prob.ncones):
+            vs = np.asarray(prob.cone(q), dtype=np.int64)
+            kind = int(prob.cone_kind[q])
+            if vs.shape[0] == 0 or kind not in (0, 1, 2) or (kind == 2 and vs.shape[0] < 2):
+                raise OracleError(2, f"vector cone {q}: empty, unknown kind or a one-vertex second-order cone")
+            if np.any(vs < 0) or np.any(vs >= n) or np.any(in_clique[vs]) or np.any(offdiag_v[vs]):
+                raise OracleError(2, f"vector cone {q}: vertex out of range, in a clique or with off-diagonal entries")
+            pos = np.minimum(np.searchsorted(skey, vs * n + vs), self.nU - 1)
+            if np.any(skey[pos] != vs * n + vs):
+                raise OracleError(2, f"vector cone {q}: diagonal entry missing from the pattern")
+            ent = order[pos]
+            if np.any(D[ent] != 0):
+                raise OracleError(2, f"vector cone {q}: entry already covered")
+            D[ent] = 1.0
+            self.vidx.append(ent)
+            self.vkind.append(kind)
+        self.ncones = self.p + len(self.vidx)
         if np.any(D == 0):
-            raise OracleError(2, "pattern entry covered by no clique")
+            raise OracleError(2, "pattern entry covered by no clique or cone")
         self.D = D
 
     def gather(self, x: np.ndarray, k: int) -> np.ndarray:
-        """H_k x as the clique submatrix E_k X E_k^T."""
+        """H_k x: the clique submatrix E_k X E_k^T (k < p), or the vector of a
+        vector cone's entries (k >= p)."""
+        if k >= self.p:
+            return x[self.vidx[k - self.p]]
         return x[self.idx[k]]
 
     def scatter(self, blocks) -> np.ndarray:
-        """sum_k H_k^T vec(B_k) in entry coordinates."""
+        """sum_k H_k^T vec(B_k) in entry coordinates (cliques, then vector cones)."""
         out = np.zeros(self.nU)
         for k, B in enumerate(blocks):
+            if k >= self.p:
+                np.add.at(out, self.vidx[k - self.p], B)
+                continue
             ia, ib = self.tril[k]
             np.add.at(out, self.idx[k][ia, ib], B[ia, ib])
+        return out
+
+    def zero_blocks(self):
+        return ([np.zeros(t.shape) for t in self.idx] + [np.zeros(v.shape[0]) for v in self.vidx])
+
+    def project(self, W: list, dual: bool = False) -> list:
+        """Projection of every cone block onto its cone (dual=False) or onto
+        its dual cone (dual=True): the PSD projection for cliques (self-dual),
+        the vector cones' own projections after them (the free cone's dual
+        cone is {0}; the orthant and the second-order cone are self-dual)."""
+        out = psd_project_batch(W[:self.p]) if self.p > 0 else []
+        for q, kind in enumerate(self.vkind):
+            if dual and kind == 0:
+                out.append(np.zeros_like(W[self.p + q]))
+            else:
+                out.append(vector_cone_project(kind, W[self.p + q]))
         return out
 
     def wdot(self, u, v) -> float:
@@ -334,7 +418,7 @@ class Oracle:
         self.sizes = [int(s) for s in prob.clique_sizes()]
 
     def zero_blocks(self):
-        return [np.zeros((s, s)) for s in self.sizes]
+        return self.dec.zero_blocks()
 
     # ---- Algorithm 1: decomposed primal form ------------------------------
     def admm_primal(self, rho=1.0, max_iter=200, tol=0.0, xk=None, lam=None, callback=None) -> Result:
@@ -343,20 +427,22 @@ class Oracle:
         xk = self.zero_blocks() if xk is None else [B.copy() for B in xk]
         lam = self.zero_blocks() if lam is None else [B.copy() for B in lam]
         res = Result("primal", 0, False, None, None, xk, lam, None)
+        nc = dec.ncones
         for it in range(1, max_iter + 1):
             # X-block: (E:OptCondMinYPrimal)
-            r1 = dec.scatter([xk[k] + lam[k] / rho for k in range(prob.p)]) - c / rho
+            r1 = dec.scatter([xk[k] + lam[k] / rho for k in range(nc)]) - c / rho
             x, y = kkt.solve(r1, b)
-            # Y-block: (E:XkUpdate), one PSD projection per clique
-            Hx = [dec.gather(x, k) for k in range(prob.p)]
-            W = [Hx[k] - lam[k] / rho for k in range(prob.p)]
-            xk_new = psd_project_batch(W)
+            # Y-block: (E:XkUpdate), one PSD projection per clique (and one
+            # projection per vector cone)
+            Hx = [dec.gather(x, k) for k in range(nc)]
+            W = [Hx[k] - lam[k] / rho for k in range(nc)]
+            xk_new = dec.project(W)
             # Z-block: (E:LambdakUpdate)
-            lam = [lam[k] + rho * (xk_new[k] - Hx[k]) for k in range(prob.p)]
+            lam = [lam[k] + rho * (xk_new[k] - Hx[k]) for k in range(nc)]
             # relative residuals
-            rp = _stack_norm([xk_new[k] - Hx[k] for k in range(prob.p)])
+            rp = _stack_norm([xk_new[k] - Hx[k] for k in range(nc)])
             eps_p = _rel(rp, max(_stack_norm(Hx), _stack_norm(xk_new)))
-            s = rho * dec.scatter([xk_new[k] - xk[k] for k in range(prob.p)])
+            s = rho * dec.scatter([xk_new[k] - xk[k] for k in range(nc)])
             eps_d = _rel(dec.wnorm(s), dec.wnorm(dec.scatter(lam)))
             xk = xk_new
             res.eps_p.append(eps_p)
@@ -383,18 +469,19 @@ class Oracle:
         v = self.zero_blocks() if v is None else [B.copy() for B in v]
         lam = self.zero_blocks() if lam is None else [B.copy() for B in lam]
         res = Result("dual", 0, False, None, None, z, lam, v)
+        nc = dec.ncones
         for it in range(1, max_iter + 1):
             # Y-block first: (E:zkUpdate)
-            z = psd_project_batch([v[k] - lam[k] / rho for k in range(prob.p)])
+            z = dec.project([v[k] - lam[k] / rho for k in range(nc)], dual=True)
             # X-block: (E:OptCondMinYDual), then (E:vkEqn)
-            r1 = c - dec.scatter([z[k] + lam[k] / rho for k in range(prob.p)])
+            r1 = c - dec.scatter([z[k] + lam[k] / rho for k in range(nc)])
             x, y = kkt.solve(r1, -b / rho)
-            v_new = [z[k] + lam[k] / rho + dec.gather(x, k) for k in range(prob.p)]
+            v_new = [z[k] + lam[k] / rho + dec.gather(x, k) for k in range(nc)]
             # Z-block: (E:MultUpdateDualSDP)
-            lam = [lam[k] + rho * (z[k] - v_new[k]) for k in range(prob.p)]
-            rp = _stack_norm([z[k] - v_new[k] for k in range(prob.p)])
+            lam = [lam[k] + rho * (z[k] - v_new[k]) for k in range(nc)]
+            rp = _stack_norm([z[k] - v_new[k] for k in range(nc)])
             eps_p = _rel(rp, max(_stack_norm(z), _stack_norm(v_new)))
-            eps_d = _rel(rho * _stack_norm([v_new[k] - v[k] for k in range(prob.p)]), _stack_norm(lam))
+            eps_d = _rel(rho * _stack_norm([v_new[k] - v[k] for k in range(nc)]), _stack_norm(lam))
             v = v_new
             res.eps_p.append(eps_p)
             res.eps_d.append(eps_d)
@@ -430,10 +517,223 @@ class Oracle:
         pobj = dec.wdot(prob.c, X)
         dobj = float(np.dot(prob.b, y))
         gap = abs(pobj - dobj) / (1.0 + abs(pobj) + abs(dobj))
-        xmin = min(float(np.linalg.eigvalsh(dec.gather(X, k)).min()) for k in range(prob.p))
         zblocks = res.lam if res.form == "primal" else res.blocks
-        zmin = min(float(np.linalg.eigvalsh(B).min()) for B in zblocks)
+        xmin = min(cone_margin(dec, k, dec.gather(X, k)) for k in range(dec.ncones))
+        zmin = min(cone_margin(dec, k, zblocks[k], dual=True) for k in range(dec.ncones))
         return dict(pinf=pinf, dinf=dinf, gap=gap, pobj=pobj, dobj=dobj, xmin=xmin, zmin=zmin)
+
+
+def cone_margin(dec: Decomposition, k: int, B, dual: bool = False) -> float:
+    """How far B lies inside cone k (negative: outside): the smallest
+    eigenvalue (PSD), the smallest entry (orthant), t - ||z|| (second-order
+    cone); the free cone always holds (+inf) and its dual cone {0} holds to
+    -max |B|."""
+    if k < dec.p:
+        return float(np.linalg.eigvalsh(B).min())
+    kind = dec.vkind[k - dec.p]
+    B = np.asarray(B, dtype=np.float64)
+    if kind == 0:
+        return -float(np.abs(B).max()) if dual else float("inf")
+    if kind == 1:
+        return float(B.min())
+    return float(B[0] - np.linalg.norm(B[1:]))
+
+
+# --------------------------------------------------------------------------
+# Homogeneous self-dual embedding of the decomposed problem (the HSDE variant
+# the paper names as future work, Sec. VI, following O'Donoghue, Chu, Parikh
+# and Boyd 2016, "Conic optimization via operator splitting and homogeneous
+# self-dual embedding")
+# --------------------------------------------------------------------------
+
+HSDE_SOLVED, HSDE_MAXIT, HSDE_NUMERIC, HSDE_INFEASIBLE, HSDE_UNBOUNDED = 1, 2, 3, 4, 5
+
+
+@dataclass
+class HsdeResult:
+    iters: int
+    status: int              # 0 running (max_iter not reached), 1 solved, 2 cap, 4 primal infeasible, 5 dual infeasible
+    x: np.ndarray            # u_x (entries)
+    y: np.ndarray            # u_y on the equality rows
+    z: list                  # u_y on the cone rows (one block per cone)
+    s: list                  # v_s on the cone rows
+    tau: float
+    kappa: float
+    res_pri: list = field(default_factory=list)
+    res_dual: list = field(default_factory=list)
+    gap: list = field(default_factory=list)
+    X_sdp: np.ndarray | None = None
+    y_sdp: np.ndarray | None = None
+    Z_sdp: np.ndarray | None = None
+    obj_primal: float = 0.0
+    obj_dual: float = 0.0
+    cert_y: np.ndarray | None = None   # primal infeasible: A*(y) in -K*, b^T y = 1
+    cert_x: np.ndarray | None = None   # dual infeasible: A(x) = 0, x in K, <c, x> = -1
+
+
+class Hsde:
+    """The decomposed primal problem min <c, x>_w s.t. A(x) = b, H_k x = x_k in
+    K_k, written as the conic program min <c, x> s.t. Ahat x + s = bhat,
+    s in {0}^m x K_1 x ... x K_p with Ahat = [A; -H_1; ...; -H_p] and
+    bhat = (b, 0, ..., 0), and embedded homogeneously:
+        Q = [[0, Ahat^T, c], [-Ahat, 0, bhat], [-c^T, -bhat^T, 0]],
+        u = (x, y, z, tau) in R^nU x (R^m x K*) x R_+,  v = Q u = (0, 0, s, kappa).
+    The iteration (no over-relaxation) is
+        ut = (I + Q)^-1 (u + v),  u = Pi(ut - v),  v = v - ut + u.
+    All inner products on the entries are w-weighted (vec coordinates), so
+    the adjoint of A is (A^T y)_e = sum_i A_ie y_i and H_k^T H_k sums to D.
+
+    The linear system: with M = [[I, Ahat^T], [-Ahat, I]] and h = (c, bhat),
+    (I + Q) ut = w splits into M zeta = w_xy, M g = h (g cached) and
+    ut_tau = (w_tau + h^T zeta) / (1 + h^T g), ut_xy = zeta - ut_tau g.
+    M (a, b) = (r_x, r_y) is solved by eliminating b = r_y + Ahat a:
+    (I + D + A^T A) a = r_x - Ahat^T r_y, and with E = 1 + D that system is
+    solved through the m x m matrix M' = I + A diag(w / E) A^T (cached
+    Cholesky factor): p = r_x + sum_k H_k^T r_k, t = A(w p / E) + r_0,
+    y' = M'^-1 t, a = (p - A^T y') / E, b_0 = y', b_k = r_k - H_k a.
+
+    Termination (readings: the paper gives none for this variant; these are
+    the scaled residuals of the reference above, relative to 1 + ||b|| and
+    1 + ||c||), at an iterate with tau > 0:
+        res_pri  = ||(A(x) - tau b, s_k - H_k x)|| / (tau (1 + ||b||)),
+        res_dual = ||A^T y - sum_k H_k^T z_k + tau c||_w / (tau (1 + ||c||_w)),
+        gap      = |<c, x>_w + b^T y| / (tau + |<c, x>_w| + |b^T y|),
+    solved when all three are <= tol; primal infeasible (certificate
+    -y / (-b^T y)) when b^T y < 0 and ||A^T y - sum_k H_k^T z_k||_w ||b|| <=
+    tol (-b^T y); dual infeasible (certificate x / (-<c, x>_w)) when
+    <c, x>_w < 0 and ||(A(x), s_k - H_k x)|| ||c||_w <= tol (-<c, x>_w).
+    Checked in that order after every iteration.
+    """
+
+    def __init__(self, prob):
+        self.prob = prob
+        self.dec = dec = Decomposition(prob)
+        if prob.A is not None:
+            self.A = np.asarray(prob.A, dtype=np.float64)
+        else:
+            import scipy.sparse as sp
+            self.A = sp.csr_matrix((prob.A_val, prob.A_idx.astype(np.int64), prob.A_ptr), shape=(prob.m, dec.nU))
+        self.E = 1.0 + dec.D
+        sc = dec.w / self.E
+        if isinstance(self.A, np.ndarray):
+            Mp = (self.A * sc[None, :]) @ self.A.T
+        else:
+            import scipy.sparse as sp
+            Mp = (self.A @ sp.diags(sc) @ self.A.T).toarray()
+        Mp = 0.5 * (Mp + Mp.T) + np.eye(prob.m)
+        self.L = cholesky(Mp)
+        self.gx, self.gy, self.gz = self.solve_m(prob.c, prob.b, dec.zero_blocks())
+        self.hg = dec.wdot(prob.c, self.gx) + float(np.dot(prob.b, self.gy))
+        self.nb = float(np.linalg.norm(prob.b))
+        self.nc = dec.wnorm(prob.c)
+
+    def A_op(self, x):
+        """A(x) = [<A_i, X>] = sum_e w_e A_ie x_e."""
+        return self.A @ (self.dec.w * x)
+
+    def AT_op(self, y):
+        """The adjoint: (A^T y)_e = sum_i A_ie y_i."""
+        return self.A.T @ y
+
+    def solve_m(self, rx, ry, rz):
+        """(a, b_0, b_k) with M (a, b) = (rx, (ry, rz))."""
+        dec = self.dec
+        p = rx + dec.scatter(rz)
+        t = self.A_op(p / self.E) + ry
+        y1 = chol_solve(self.L, t)
+        a = (p - self.AT_op(y1)) / self.E
+        bz = [rz[k] - dec.gather(a, k) for k in range(dec.ncones)]
+        return a, y1, bz
+
+    def solve_iq(self, wx, wy, wz, wt):
+        """ut = (I + Q)^-1 w for w = (wx, wy, wz, wt)."""
+        dec, prob = self.dec, self.prob
+        za, zy, zz = self.solve_m(wx, wy, wz)
+        ut = (wt + dec.wdot(prob.c, za) + float(np.dot(prob.b, zy))) / (1.0 + self.hg)
+        return (za - ut * self.gx, zy - ut * self.gy, [zz[k] - ut * self.gz[k] for k in range(dec.ncones)], ut)
+
+    def step(self, x, y, z, s, tau, kappa):
+        """One iteration; returns the new (x, y, z, s, tau, kappa) and ut_tau."""
+        dec = self.dec
+        nc = dec.ncones
+        # ut = (I + Q)^-1 (u + v); v is zero on the x and y rows
+        ux, uy, uz, ut = self.solve_iq(x, y, [z[k] + s[k] for k in range(nc)], tau + kappa)
+        # u = Pi_C(ut - v): x and y free, z onto the dual cones, tau >= 0
+        z_new = dec.project([uz[k] - s[k] for k in range(nc)], dual=True)
+        tau_new = max(ut - kappa, 0.0)
+        # v = v - ut + u
+        s_new = [s[k] - uz[k] + z_new[k] for k in range(nc)]
+        kappa_new = kappa - ut + tau_new
+        return ux, uy, z_new, s_new, tau_new, kappa_new, ut
+
+    def initial(self):
+        """u = (0, 0, 0, 1), v = (0, 0, 0, 1)."""
+        dec = self.dec
+        return (np.zeros(dec.nU), np.zeros(self.prob.m), dec.zero_blocks(), dec.zero_blocks(), 1.0, 1.0)
+
+    def residuals(self, x, y, z, s, tau):
+        dec, prob = self.dec, self.prob
+        nc = dec.ncones
+        Ax = self.A_op(x)
+        cons = [s[k] - dec.gather(x, k) for k in range(nc)]
+        r_cone = _stack_norm(cons)
+        pri_nt = float(np.sqrt(np.sum((Ax - tau * prob.b) ** 2) + r_cone ** 2))
+        ray_nt = float(np.sqrt(np.sum(Ax ** 2) + r_cone ** 2))
+        aty = self.AT_op(y) - dec.scatter(z)
+        dual_nt = dec.wnorm(aty + tau * prob.c)
+        aty_n = dec.wnorm(aty)
+        cx = dec.wdot(prob.c, x)
+        by = float(np.dot(prob.b, y))
+        return pri_nt, dual_nt, ray_nt, aty_n, cx, by
+
+    def solve(self, max_iter=2000, tol=1e-6, state=None, callback=None) -> HsdeResult:
+        dec, prob = self.dec, self.prob
+        nc = dec.ncones
+        x, y, z, s, tau, kappa = self.initial() if state is None else state
+        z = [B.copy() for B in z]
+        s = [B.copy() for B in s]
+        res = HsdeResult(0, 0, x, y, z, s, tau, kappa)
+        for it in range(1, max_iter + 1):
+            x, y, z, s, tau, kappa, _ = self.step(x, y, z, s, tau, kappa)
+            pri_nt, dual_nt, ray_nt, aty_n, cx, by = self.residuals(x, y, z, s, tau)
+            if tau > 0:
+                rp = pri_nt / (tau * (1.0 + self.nb))
+                rd = dual_nt / (tau * (1.0 + self.nc))
+            else:
+                rp = rd = float("inf")
+            gp = abs(cx + by) / (tau + abs(cx) + abs(by)) if tau + abs(cx) + abs(by) > 0 else 0.0
+            res.res_pri.append(rp)
+            res.res_dual.append(rd)
+            res.gap.append(gp)
+            res.iters = it
+            if callback is not None:
+                callback(it, x, y, z, s, tau, kappa)
+            if not all(np.isfinite(v) for v in (pri_nt, dual_nt, cx, by, tau, kappa)):
+                res.status = HSDE_NUMERIC
+                break
+            if tau > 0 and max(rp, rd, gp) <= tol:
+                res.status = HSDE_SOLVED
+                break
+            if by < 0 and aty_n * self.nb <= tol * (-by):
+                res.status = HSDE_INFEASIBLE
+                break
+            if cx < 0 and ray_nt * self.nc <= tol * (-cx):
+                res.status = HSDE_UNBOUNDED
+                break
+        else:
+            res.status = HSDE_MAXIT
+        res.x, res.y, res.z, res.s, res.tau, res.kappa = x, y, z, s, tau, kappa
+        if res.status == HSDE_INFEASIBLE:
+            res.cert_y = y / float(np.dot(prob.b, y))
+        elif res.status == HSDE_UNBOUNDED:
+            res.cert_x = x / (-dec.wdot(prob.c, x))
+        elif tau > 0:
+            res.X_sdp = x / tau
+            res.y_sdp = -y / tau
+            res.Z_sdp = dec.scatter(z) / tau
+            res.obj_primal = dec.wdot(prob.c, res.X_sdp)
+            res.obj_dual = float(np.dot(prob.b, res.y_sdp))
+        return res
 
 
 # --------------------------------------------------------------------------

@@ -28,6 +28,9 @@ from dataclasses import dataclass, field
 import numpy as np
 
 
+CONE_FREE, CONE_ORTHANT, CONE_SOC = 0, 1, 2
+
+
 @dataclass
 class Problem:
     n: int
@@ -42,6 +45,19 @@ class Problem:
     A_idx: np.ndarray | None = None  # int32 [nnzA]  entry indices
     A_val: np.ndarray | None = None  # float64 [nnzA]
     meta: dict = field(default_factory=dict)
+    # vector cones (CDCS's cone types besides PSD): cone q covers the diagonal
+    # entries of vertices cone_vert[cone_ptr[q]:cone_ptr[q+1]]; cone_kind[q] is
+    # CONE_FREE, CONE_ORTHANT or CONE_SOC (second-order cone, first vertex t)
+    cone_kind: np.ndarray | None = None  # int32 [ncones]
+    cone_ptr: np.ndarray | None = None   # int64 [ncones+1]
+    cone_vert: np.ndarray | None = None  # int32 [sum of cone sizes]
+
+    @property
+    def ncones(self) -> int:
+        return 0 if self.cone_kind is None else int(self.cone_kind.shape[0])
+
+    def cone(self, q: int) -> np.ndarray:
+        return self.cone_vert[self.cone_ptr[q]:self.cone_ptr[q + 1]]
 
     @property
     def nU(self) -> int:
@@ -498,3 +514,174 @@ def c4(count: int = 512, first: int = 0):
     params = c4_params(first + count)
     return [block_arrow(l, d, h, m, seed=config_seed(4, first + i))
             for i, (l, d, h, m) in enumerate(params[first:first + count])]
+
+
+# --------------------------------------------------------------------------
+# Vector cones (free, nonnegative orthant, second-order) beside the PSD
+# cliques, and instances with a known status (infeasible / unbounded)
+# --------------------------------------------------------------------------
+
+def _append_vector_vertices(ei, ej, n0, kinds_sizes):
+    """Diagonal entries of fresh vertices n0, n0+1, ... for each vector cone
+    (kind, size); returns the new entry arrays, vertex count and the cone CSR."""
+    kinds, ptr, vert = [], [0], []
+    v = n0
+    for kind, size in kinds_sizes:
+        kinds.append(kind)
+        vert.extend(range(v, v + size))
+        v += size
+        ptr.append(len(vert))
+    nv = v - n0
+    newv = np.arange(n0, v, dtype=np.int32)
+    ei = np.concatenate([ei, newv]).astype(np.int32)
+    ej = np.concatenate([ej, newv]).astype(np.int32)
+    return (ei, ej, v, np.asarray(kinds, dtype=np.int32), np.asarray(ptr, dtype=np.int64),
+            np.asarray(vert, dtype=np.int32), nv)
+
+
+def _interior_vector_point(rng, kind, size, dual=False):
+    """A point in the interior of a vector cone (or of its dual cone; the free
+    cone's dual is {0})."""
+    if kind == CONE_FREE:
+        return np.zeros(size) if dual else rng.standard_normal(size)
+    if kind == CONE_ORTHANT:
+        return rng.uniform(0.5, 1.5, size)
+    z = rng.standard_normal(size - 1)
+    return np.concatenate([[np.linalg.norm(z) + rng.uniform(0.5, 1.5)], z])
+
+
+def mixed_cones(l: int, d: int, h: int, m: int, cones, seed: int) -> Problem:
+    """Block-arrow SDP part (as block_arrow) plus vector cones `cones`, a list
+    of (kind, size), on fresh vertices (their diagonal entries).  Dense N(0,1)
+    constraints over every entry (symmetrised on the PSD part); b = A(x0) and
+    c = A*(y0) + z0 with x0 and z0 interior to the cone and its dual cone, so
+    the instance is strictly feasible (and a free variable's dual slack is 0).
+    l = 0 gives a problem with vector cones only (no cliques)."""
+    rng = _rng(seed)
+    if l > 0:
+        n0, cliques, ei, ej = _block_arrow_pattern(l, d, h)
+    else:
+        n0, cliques, ei, ej = 0, [], np.empty(0, np.int32), np.empty(0, np.int32)
+    npsd = ei.shape[0]
+    ei, ej, n, kinds, cptr, cvert, nv = _append_vector_vertices(ei, ej, n0, cones)
+    nU = ei.shape[0]
+    w = np.where(ei == ej, 1.0, 2.0)
+    A = _symmetrised_normal(rng, m, ei, ej)
+    x0 = np.zeros(nU)
+    z0 = np.zeros(nU)
+    if l > 0:
+        G = rng.standard_normal((n0, n0))
+        x0[:npsd] = np.einsum("ij,ij->i", G[ei[:npsd]], G[ej[:npsd]]) / n0
+        lookup = _entry_lookup(n, ei, ej)
+        for cl in cliques:
+            s = cl.shape[0]
+            R = rng.standard_normal((s, s))
+            Zk = R @ R.T / s
+            ia, ib = np.tril_indices(s)
+            np.add.at(z0, _find_entries(n, lookup, cl[ia], cl[ib]), Zk[ia, ib])
+    # vector-cone vertices own the entries npsd + (vertex - n0)
+    for q, kind in enumerate(kinds):
+        ent = npsd + (cvert[cptr[q]:cptr[q + 1]] - n0)
+        x0[ent] = _interior_vector_point(rng, int(kind), ent.shape[0])
+        z0[ent] = _interior_vector_point(rng, int(kind), ent.shape[0], dual=True)
+    y0 = rng.standard_normal(m)
+    clique_ptr = np.zeros(len(cliques) + 1, dtype=np.int64)
+    clique_ptr[1:] = np.cumsum([cl.shape[0] for cl in cliques])
+    clique_vert = np.concatenate(cliques).astype(np.int32) if cliques else np.empty(0, np.int32)
+    return Problem(n=n, ei=ei, ej=ej, clique_ptr=clique_ptr, clique_vert=clique_vert, b=A @ (w * x0),
+                   c=A.T @ y0 + z0, A=A, cone_kind=kinds, cone_ptr=cptr, cone_vert=cvert,
+                   meta={"kind": "mixed_cones", "l": l, "d": d, "h": h, "seed": seed, "x0": x0, "y0": y0,
+                         "z0": z0})
+
+
+def mixed_small(seed: int = 7001) -> Problem:
+    """Small mixed-cone instance: block-arrow l=6, d=6, h=3 and a free cone
+    of 5, an orthant of 12 and second-order cones of 6 and 9, m = 40."""
+    return mixed_cones(6, 6, 3, 40, [(CONE_FREE, 5), (CONE_ORTHANT, 12), (CONE_SOC, 6), (CONE_SOC, 9)], seed)
+
+
+def lp(nvar: int, m: int, seed: int, status: str = "feasible") -> Problem:
+    """Linear program min c^T x, A x = b, x >= 0 (one orthant cone, no
+    cliques).  status "feasible": strictly feasible primal and dual;
+    "infeasible": A^T y1 <= -0.1 componentwise and b^T y1 > 0 for a drawn y1
+    (Farkas: no x >= 0 has A x = b); "unbounded": a drawn ray r > 0 with
+    A r = 0 and c^T r = -1, and a feasible x0 > 0 (the objective is unbounded
+    below)."""
+    rng = _rng(seed)
+    A = rng.standard_normal((m, nvar))
+    x0 = rng.uniform(0.5, 1.5, nvar)
+    y0 = rng.standard_normal(m)
+    z0 = rng.uniform(0.5, 1.5, nvar)
+    meta = {"kind": "lp", "status": status, "seed": seed}
+    if status == "infeasible":
+        y1 = rng.standard_normal(m)
+        v = np.maximum(A.T @ y1, 0.0) + 0.1
+        A = A - np.outer(y1, v) / (y1 @ y1)
+        A = _f32(A)
+        b = rng.standard_normal(m)
+        b = b + y1 * (1.0 + abs(b @ y1)) / (y1 @ y1)
+        c = A.T @ y0 + z0
+        meta["y1"] = y1
+    elif status == "unbounded":
+        r = rng.uniform(0.5, 1.5, nvar)
+        A = A - np.outer(A @ r, r) / (r @ r)
+        A = _f32(A)
+        b = A @ x0
+        c = rng.standard_normal(nvar)
+        c = c - r * (c @ r + 1.0) / (r @ r)
+        meta["ray"] = r
+    else:
+        A = _f32(A)
+        b = A @ x0
+        c = A.T @ y0 + z0
+    v = np.arange(nvar, dtype=np.int32)
+    return Problem(n=nvar, ei=v.copy(), ej=v.copy(), clique_ptr=np.zeros(1, np.int64),
+                   clique_vert=np.empty(0, np.int32), b=b, c=c, A=A,
+                   cone_kind=np.array([CONE_ORTHANT], np.int32), cone_ptr=np.array([0, nvar], np.int64),
+                   cone_vert=v.copy(), meta={**meta, "x0": x0, "y0": y0, "z0": z0})
+
+
+def socp_norm(a: np.ndarray) -> Problem:
+    """min t s.t. z = a, (t, z) in the second-order cone: the optimum is
+    ||a|| (primal t = ||a||, z = a; dual y = a / ||a||)."""
+    q = a.shape[0]
+    v = np.arange(q + 1, dtype=np.int32)
+    A = np.zeros((q, q + 1))
+    A[np.arange(q), np.arange(1, q + 1)] = 1.0
+    c = np.zeros(q + 1)
+    c[0] = 1.0
+    return Problem(n=q + 1, ei=v.copy(), ej=v.copy(), clique_ptr=np.zeros(1, np.int64),
+                   clique_vert=np.empty(0, np.int32), b=np.asarray(a, dtype=np.float64), c=c, A=A,
+                   cone_kind=np.array([CONE_SOC], np.int32), cone_ptr=np.array([0, q + 1], np.int64),
+                   cone_vert=v.copy(), meta={"kind": "socp_norm"})
+
+
+def sdp_infeasible(seed: int = 7101) -> Problem:
+    """The C1-shaped block-arrow SDP (l=10, d=10, h=5, m=50) with one more
+    constraint trace(X) = -1, which no PSD X meets (primal infeasible)."""
+    p = block_arrow(10, 10, 5, 50, seed)
+    tr = np.where(p.ei == p.ej, 1.0, 0.0)
+    A = np.vstack([p.A, tr[None, :]])
+    b = np.concatenate([p.b, [-1.0]])
+    out = Problem(**{**p.__dict__})
+    out.A, out.b = A, b
+    out.meta = {**p.meta, "kind": "sdp_infeasible"}
+    return out
+
+
+def sdp_unbounded(seed: int = 7102) -> Problem:
+    """The C1-shaped block-arrow SDP with every constraint's coefficient on
+    the diagonal entry of vertex 0 set to zero and C_00 = -1: X0 + t e_0 e_0^T
+    stays feasible for every t >= 0 while <C, X> decreases without bound
+    (dual infeasible)."""
+    p = block_arrow(10, 10, 5, 50, seed)
+    e00 = int(np.nonzero((p.ei == 0) & (p.ej == 0))[0][0])
+    A = p.A.copy()
+    A[:, e00] = 0.0
+    w = np.where(p.ei == p.ej, 1.0, 2.0)
+    c = p.c.copy()
+    c[e00] = -1.0
+    out = Problem(**{**p.__dict__})
+    out.A, out.b, out.c = A, A @ (w * p.meta["x0"]), c
+    out.meta = {**p.meta, "kind": "sdp_unbounded", "ray_entry": e00}
+    return out
