@@ -76,7 +76,9 @@ typedef enum {
     CDCS_E_DEVICE = 4,         /* HIP runtime failure */
     CDCS_E_NOMEM = 5,          /* device allocation failed */
     CDCS_E_NOT_CONVERGED = 6,  /* iteration cap reached; results are written */
-    CDCS_E_NUMERIC = 7         /* an eigensolve hit its sweep cap, or NaN/Inf in the iterate */
+    CDCS_E_NUMERIC = 7,        /* an eigensolve hit its sweep cap, or NaN/Inf in the iterate */
+    CDCS_PRIMAL_INFEASIBLE = 8, /* HSDE solve: certificate of primal infeasibility found */
+    CDCS_DUAL_INFEASIBLE = 9   /* HSDE solve: certificate of dual infeasibility (unbounded primal) found */
 } cdcs_status;
 
 typedef enum { CDCS_PRIMAL = 0, /* Algorithm 1 */ CDCS_DUAL = 1 /* Algorithm 2 */ } cdcs_form;
@@ -178,6 +180,9 @@ typedef struct {
     int64_t nnz_factor;
     int64_t nwarm;        /* sum of s_k^2: length of cdcs_state.vw */
     int64_t nnz_l;        /* nonzeros of the sparse Cholesky factor (0: dense factor) */
+    int32_t nvcones;      /* vector cones (cdcs_setup_cones) */
+    int32_t pad_;
+    int64_t nslots_psd;   /* packed slots of the cliques; the cones' slots follow them */
 } cdcs_sizes;
 
 /*
@@ -233,6 +238,44 @@ cdcs_status cdcs_chordal_extension(const cdcs_pattern *pattern, int64_t *nfill, 
 cdcs_status cdcs_setup(const cdcs_pattern *pattern, const cdcs_constraints *A,
                        const double *b, const double *c, const cdcs_cliques *cliques,
                        const cdcs_options *opts, hipStream_t stream, cdcs_handle **out);
+
+/*
+ * Vector cones beside the PSD cliques (the cone types other than PSD that
+ * CDCS accepts, Sec. IV: the free cone R^q, the nonnegative orthant R^q_+ and
+ * the second-order cone {(t, z) : ||z|| <= t}).  Cone q covers the diagonal
+ * entries of vertices vert[ptr[q] .. ptr[q+1]) (host arrays), in that order;
+ * a second-order cone has at least 2 vertices, the first holding t.  A cone
+ * vertex lies in no clique and in no other cone, and the pattern holds its
+ * diagonal entry and no off-diagonal entry of it (so its variables are
+ * ordinary vector variables, w_e = 1).  Each cone is one more block of the
+ * decomposition: its selector H_k reads the cone's entries as a vector and
+ * D_e = 1 on them.  Its slots follow the clique blocks' slots in cone order
+ * (one slot per vertex), so state buffers hold nslots = nslots_psd + the cone
+ * sizes (cdcs_get_sizes).  Algorithm 1 (and the HSDE solver) projects a cone
+ * block onto its cone, Algorithm 2 onto the dual cone (the free cone's dual
+ * cone is {0}; the orthant and the second-order cone are self-dual).
+ */
+typedef enum { CDCS_CONE_FREE = 0, CDCS_CONE_ORTHANT = 1, CDCS_CONE_SOC = 2 } cdcs_cone_kind;
+
+typedef struct {
+    int32_t ncones;
+    const int32_t *kind;  /* host [ncones] cdcs_cone_kind */
+    const int64_t *ptr;   /* host [ncones+1], ptr[0] = 0 */
+    const int32_t *vert;  /* host [ptr[ncones]] */
+} cdcs_vcones;
+
+/*
+ * cdcs_setup with vector cones (cones NULL or empty: the same as cdcs_setup).
+ * With cones the clique list may be empty (p = 0: a linear or second-order
+ * cone program).  cliques = NULL: the chordal extension covers the pattern
+ * without the cone vertices.  Handles with cones run Algorithms 1 and 2 and
+ * the HSDE solver; the differentiation entry points reject them (CDCS_E_ARG).
+ * Errors: as for cdcs_setup; CDCS_E_PATTERN for a cone that breaks the rules
+ * above, CDCS_E_ARG for an unknown kind.
+ */
+cdcs_status cdcs_setup_cones(const cdcs_pattern *pattern, const cdcs_constraints *A, const double *b,
+                             const double *c, const cdcs_cliques *cliques, const cdcs_vcones *cones,
+                             const cdcs_options *opts, hipStream_t stream, cdcs_handle **out);
 
 /* One SDP of a batch (all pointers host, as for cdcs_setup). */
 typedef struct {
@@ -458,6 +501,99 @@ cdcs_status cdcs_affine_project_adjoint(cdcs_handle *h, const double *xbar, doub
  */
 cdcs_status cdcs_affine_project_adjoint_noalloc(cdcs_handle *h, const double *xbar, double *r1bar, double *r2bar,
                                                 hipStream_t stream);
+
+/*
+ * Homogeneous self-dual embedding (HSDE) of the decomposed problem: the
+ * variant the paper names as future work so that infeasibility can be
+ * detected (Sec. VI), solved by the operator-splitting iteration of
+ * O'Donoghue, Chu, Parikh and Boyd (2016) without over-relaxation.
+ *
+ * The decomposed primal problem min <c, x>_w s.t. A(x) = b, H_k x in K_k
+ * (cliques: PSD cones; vector cones) is the conic program
+ * min <c, x> s.t. Ahat x + s = bhat, s in {0}^m x K_1 x ... x K_p, with
+ * Ahat = [A; -H_1; ...; -H_p] and bhat = (b, 0).  Its embedding seeks
+ * u = (x, y, z, tau) in R^nnz x R^m x K* x R_+ and v = (0, 0, s, kappa) in
+ * {0} x {0} x K x R_+ with v = Q u,
+ *   Q = [[0, Ahat^T, c], [-Ahat, 0, bhat], [-c^T, -bhat^T, 0]].
+ * An iteration is ut = (I + Q)^-1 (u + v), u = Pi(ut - v), v = v - ut + u:
+ * the linear step eliminates down to the m x m matrix
+ * M' = I + A diag(w / (1 + D)) A^T, whose factor is cached like Algorithm 1's
+ * (dense, CSR inverse or sparse, built at the first HSDE call on a handle),
+ * and the cone step is the Algorithm-1 projection kernel with rho = 1
+ * (s_k = P(H_k x - z_k), z_k = s_k - (H_k x - z_k)).  After each iteration
+ * the residuals, from differences of successive iterates (no extra pass over
+ * A), decide the outcome, in this order (tau > 0 for the first):
+ *   solved:   ||(A(x) - tau b, s - Hx)|| <= tol tau (1 + ||b||),
+ *             ||A^T y - sum_k H_k^T z_k + tau c||_w <= tol tau (1 + ||c||_w),
+ *             |<c, x>_w + b^T y| <= tol (tau + |<c, x>_w| + |b^T y|);
+ *   primal infeasible: b^T y < 0, ||A^T y - sum_k H_k^T z_k||_w ||b|| <= tol (-b^T y);
+ *   dual infeasible:   <c, x>_w < 0, ||(A(x), s - Hx)|| ||c||_w <= tol (-<c, x>_w).
+ * Solved: X = x / tau solves the primal SDP, y_sdp = -y / tau the dual one,
+ * Z = sum_k H_k^T z_k / tau.  Primal infeasible: y / (b^T y) is a Farkas
+ * certificate (b^T y_c = 1, A^T y_c in -K*).  Dual infeasible:
+ * x / (-<c, x>_w) is a ray (A(x_c) = 0, x_c in K, <c, x_c> = -1).
+ *
+ * State (device, caller-owned; sizes from cdcs_get_sizes):
+ *   x  [nnz]    FP64  u_x, pattern order
+ *   y  [m]      FP64  u_y on the equality rows
+ *   s  [nslots] FP32  the cone slacks s_k, packed as cdcs_state.blk
+ *   z  [nslots] FP32  the cone duals z_k, packed
+ *   tk [2]      FP64  tau, kappa
+ *   vw [nwarm]  FP32  eigenvector warm start as in cdcs_state (NULL: the
+ *                     handle's copy, restarted at identity by every solve)
+ */
+typedef struct {
+    double *x;
+    double *y;
+    float *s;
+    float *z;
+    double *tk;
+    float *vw;
+} cdcs_hsde_state;
+
+typedef struct {
+    int32_t iters;        /* completed iterations */
+    int32_t status;       /* CDCS_OK (solved), CDCS_PRIMAL_INFEASIBLE, CDCS_DUAL_INFEASIBLE,
+                             CDCS_E_NOT_CONVERGED or CDCS_E_NUMERIC */
+    int32_t jacobi_cap_hits;
+    int32_t pad_;
+    double res_pri, res_dual, gap;  /* the solved test's three ratios at the last iterate */
+    double obj_primal;    /* <C, X> with X = x / tau (NaN if tau = 0) */
+    double obj_dual;      /* b^T y_sdp with y_sdp = -y / tau (NaN if tau = 0) */
+    double tau, kappa;
+    double loop_s;
+    int64_t jacobi_sweeps;
+} cdcs_hsde_info;
+
+/* Starting point u = (0, 0, 0, 1), v = (0, 0, 0, 1) (every buffer of st
+ * written; vw set to identities when given).  Errors: CDCS_E_ARG. */
+cdcs_status cdcs_hsde_init(cdcs_handle *h, const cdcs_hsde_state *st, hipStream_t stream);
+
+/*
+ * Up to opts->max_iter HSDE iterations from st (opts->tol, max_iter,
+ * check_every as for cdcs_admm_solve; rho and form are not used).  Builds the
+ * HSDE factor on the first call (CDCS_E_RANK if M' is not positive definite,
+ * which needs A rank deficient beyond rounding).  The outcome is in
+ * info->status and the return value.  Synchronises on stream.
+ * Errors: CDCS_E_ARG (NULL buffers, batch handle), CDCS_E_NOMEM, CDCS_E_DEVICE.
+ */
+cdcs_status cdcs_hsde_solve(cdcs_handle *h, const cdcs_hsde_state *st, const cdcs_options *opts,
+                            cdcs_hsde_info *info, hipStream_t stream);
+
+/*
+ * The primal and dual points of the state cdcs_hsde_solve returned, by its
+ * outcome `which`: 0 (solved) X = x / tau [nnz] and y_sdp = -y / tau [m];
+ * 1 (primal infeasible) y / (b^T y) into y_out (X_out untouched);
+ * 2 (dual infeasible) x / (-<c, x>_w) into X_out (y_out untouched).
+ * X_out and y_out device FP64, pattern order; the scale factors are the ones
+ * the solve's last check computed.  Errors: CDCS_E_ARG.
+ */
+cdcs_status cdcs_hsde_solution(cdcs_handle *h, const cdcs_hsde_state *st, int32_t which, double *X_out,
+                               double *y_out, hipStream_t stream);
+
+/* Residual history of the last HSDE solve: n_host triples (res_pri,
+ * res_dual, gap) of the solved test, one per iteration, host. */
+cdcs_status cdcs_hsde_history(const cdcs_handle *h, double *hist_host, int32_t n_host);
 
 /* Kernels of one iteration, for cdcs_profile_kernel. */
 typedef enum {

@@ -11,7 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcdcs.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["kernels_project.hip", "kernels_affine.hip", "kernels_setup.hip", "kernels_batch.hip", "api.cpp",
-           "chordal.cpp", "noalloc.hip", "kernels_big.hip"]
+           "chordal.cpp", "noalloc.hip", "kernels_big.hip", "kernels_cones.hip",
+           "kernels_hsde.hip"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]

@@ -17,12 +17,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcdcs.so")
 
 OK, E_ARG, E_PATTERN, E_RANK, E_DEVICE, E_NOMEM, E_NOT_CONVERGED, E_NUMERIC = range(8)
+PRIMAL_INFEASIBLE, DUAL_INFEASIBLE = 8, 9
 K_PROJECT, K_GEMV_AU, K_TRMV, K_GEMV_ATY, K_SCATTER = range(5)
 PRIMAL, DUAL = 0, 1
 MAX_CLIQUE = 1024
 MAX_BATCHED_CLIQUE = 126
 STATUS_NAMES = {0: "CDCS_OK", 1: "CDCS_E_ARG", 2: "CDCS_E_PATTERN", 3: "CDCS_E_RANK", 4: "CDCS_E_DEVICE",
-                5: "CDCS_E_NOMEM", 6: "CDCS_E_NOT_CONVERGED", 7: "CDCS_E_NUMERIC"}
+                5: "CDCS_E_NOMEM", 6: "CDCS_E_NOT_CONVERGED", 7: "CDCS_E_NUMERIC", 8: "CDCS_PRIMAL_INFEASIBLE",
+                9: "CDCS_DUAL_INFEASIBLE"}
 
 # Every symbol include/cdcs.h declares.
 EXPORTS = ["cdcs_setup", "cdcs_setup_batch", "cdcs_batch_info", "cdcs_get_sizes", "cdcs_clique_offsets", "cdcs_psd_project_batched",
@@ -30,7 +32,8 @@ EXPORTS = ["cdcs_setup", "cdcs_setup_batch", "cdcs_batch_info", "cdcs_get_sizes"
            "cdcs_admm_step", "cdcs_admm_solve_timed", "cdcs_profile_kernel", "cdcs_get_tuning", "cdcs_set_projection_plan",
            "cdcs_residual_history", "cdcs_warm_reset", "cdcs_destroy", "cdcs_last_error", "cdcs_admm_prepare",
            "cdcs_psd_project_cliques", "cdcs_unrolled_step", "cdcs_unrolled_step_vjp",
-           "cdcs_affine_project_adjoint", "cdcs_chordal_extension", "cdcs_affine_project_adjoint_noalloc"]
+           "cdcs_affine_project_adjoint", "cdcs_chordal_extension", "cdcs_affine_project_adjoint_noalloc",
+           "cdcs_setup_cones", "cdcs_hsde_init", "cdcs_hsde_solve", "cdcs_hsde_solution", "cdcs_hsde_history"]
 
 
 class CdcsLibraryMissing(ImportError):
@@ -95,7 +98,26 @@ class _Sizes(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("p", ctypes.c_int32), ("smax", ctypes.c_int32),
                 ("nnz", ctypes.c_int64), ("nslots", ctypes.c_int64), ("sparse_a", ctypes.c_int32),
                 ("sparse_factor", ctypes.c_int32), ("nnz_a", ctypes.c_int64), ("nnz_factor", ctypes.c_int64),
-                ("nwarm", ctypes.c_int64), ("nnz_l", ctypes.c_int64)]
+                ("nwarm", ctypes.c_int64), ("nnz_l", ctypes.c_int64), ("nvcones", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("nslots_psd", ctypes.c_int64)]
+
+
+class _Vcones(ctypes.Structure):
+    _fields_ = [("ncones", ctypes.c_int32), ("kind", ctypes.c_void_p), ("ptr", ctypes.c_void_p),
+                ("vert", ctypes.c_void_p)]
+
+
+class _HsdeState(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("s", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("tk", ctypes.c_void_p), ("vw", ctypes.c_void_p)]
+
+
+class _HsdeInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("jacobi_cap_hits", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("res_pri", ctypes.c_double), ("res_dual", ctypes.c_double),
+                ("gap", ctypes.c_double), ("obj_primal", ctypes.c_double), ("obj_dual", ctypes.c_double),
+                ("tau", ctypes.c_double), ("kappa", ctypes.c_double), ("loop_s", ctypes.c_double),
+                ("jacobi_sweeps", ctypes.c_int64)]
 
 
 _lib = None
@@ -112,6 +134,11 @@ def load_library(path: str = LIB_PATH):
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     P = ctypes.POINTER
     L.cdcs_setup.argtypes = [P(_Pattern), P(_Constraints), vp, vp, P(_Cliques), vp, vp, P(vp)]
+    L.cdcs_setup_cones.argtypes = [P(_Pattern), P(_Constraints), vp, vp, P(_Cliques), P(_Vcones), vp, vp, P(vp)]
+    L.cdcs_hsde_init.argtypes = [vp, P(_HsdeState), vp]
+    L.cdcs_hsde_solve.argtypes = [vp, P(_HsdeState), P(_Options), P(_HsdeInfo), vp]
+    L.cdcs_hsde_solution.argtypes = [vp, P(_HsdeState), i32, vp, vp, vp]
+    L.cdcs_hsde_history.argtypes = [vp, vp, i32]
     L.cdcs_setup_batch.argtypes = [i32, P(_Problem), vp, vp, P(vp)]
     L.cdcs_batch_info.argtypes = [vp, i32, P(_InstanceInfo)]
     L.cdcs_get_sizes.argtypes = [vp, P(_Sizes)]
@@ -213,6 +240,32 @@ def _marshal(prob):
     return pat, cons, b, c, cl, (ei, ej, cptr, cvert, b, c) + keep
 
 
+def _marshal_cones(prob):
+    """The vector cones of a problem as a C struct (None without cones)."""
+    if getattr(prob, "cone_kind", None) is None or len(prob.cone_kind) == 0:
+        return None, ()
+    kind = np.ascontiguousarray(prob.cone_kind, dtype=np.int32)
+    ptr = np.ascontiguousarray(prob.cone_ptr, dtype=np.int64)
+    vert = np.ascontiguousarray(prob.cone_vert, dtype=np.int32)
+    return _Vcones(int(kind.shape[0]), _np_ptr(kind), _np_ptr(ptr), _np_ptr(vert)), (kind, ptr, vert)
+
+
+@dataclass
+class HsdeInfo:
+    iters: int
+    status: int
+    jacobi_cap_hits: int
+    res_pri: float
+    res_dual: float
+    gap: float
+    obj_primal: float
+    obj_dual: float
+    tau: float
+    kappa: float
+    loop_s: float
+    jacobi_sweeps: int
+
+
 class Solver:
     """One SDP set up on the device (cdcs_setup) and its ADMM entry points."""
 
@@ -222,10 +275,16 @@ class Solver:
         self._torch = torch
         if _handle is None:
             pat, cons, b, c, cl, keep = _marshal(prob)
+            vc, keep_vc = _marshal_cones(prob)
             h = ctypes.c_void_p()
-            st = L.cdcs_setup(ctypes.byref(pat), ctypes.byref(cons), _np_ptr(b), _np_ptr(c),
-                              ctypes.byref(cl) if cl is not None else None, None, _stream(torch), ctypes.byref(h))
-            del keep
+            if vc is None:
+                st = L.cdcs_setup(ctypes.byref(pat), ctypes.byref(cons), _np_ptr(b), _np_ptr(c),
+                                  ctypes.byref(cl) if cl is not None else None, None, _stream(torch), ctypes.byref(h))
+            else:
+                st = L.cdcs_setup_cones(ctypes.byref(pat), ctypes.byref(cons), _np_ptr(b), _np_ptr(c),
+                                        ctypes.byref(cl) if cl is not None else None, ctypes.byref(vc), None,
+                                        _stream(torch), ctypes.byref(h))
+            del keep, keep_vc
             _check(st, "cdcs_setup")
         else:
             h = _handle
@@ -238,6 +297,7 @@ class Solver:
         self.sparse_factor, self.nnz_factor = bool(sz.sparse_factor), sz.nnz_factor
         self.nwarm = sz.nwarm
         self.nnz_l = sz.nnz_l  # > 0: sparse Cholesky factor of A D^-1 A^T
+        self.nvcones, self.nslots_psd = sz.nvcones, sz.nslots_psd
         off = np.empty(self.p + 1, dtype=np.int64)
         _check(L.cdcs_clique_offsets(h, _np_ptr(off)), "cdcs_clique_offsets")
         self.offsets = off
@@ -266,7 +326,7 @@ class Solver:
             "lam": torch.zeros(self.nslots, dtype=torch.float32, device=dev),
             "v": torch.zeros(self.nslots, dtype=torch.float32, device=dev) if form == "dual" else None,
             # eigenvector warm start carried from one solve call to the next
-            "vw": torch.empty(self.nwarm, dtype=torch.float32, device=dev),
+            "vw": torch.empty(max(self.nwarm, 1), dtype=torch.float32, device=dev),
         }
         _check(load_library().cdcs_warm_reset(self._h, _ptr(st["vw"]), _stream(torch, None)), "cdcs_warm_reset")
         return st
@@ -320,6 +380,63 @@ class Solver:
         cs = self._cstate(state)
         _check(L.cdcs_admm_step(self._h, ctypes.byref(cs), PRIMAL if form == "primal" else DUAL, float(rho),
                                 _stream(self._torch, stream)), "cdcs_admm_step")
+
+    # ---- homogeneous self-dual embedding ----------------------------------
+    def new_hsde_state(self) -> dict:
+        """HSDE state buffers at the starting point (cdcs_hsde_init)."""
+        torch = self._torch
+        dev = torch.device("cuda")
+        st = {
+            "x": torch.empty(self.nnz, dtype=torch.float64, device=dev),
+            "y": torch.empty(self.m, dtype=torch.float64, device=dev),
+            "s": torch.empty(self.nslots, dtype=torch.float32, device=dev),
+            "z": torch.empty(self.nslots, dtype=torch.float32, device=dev),
+            "tk": torch.empty(2, dtype=torch.float64, device=dev),
+            "vw": torch.empty(max(self.nwarm, 1), dtype=torch.float32, device=dev),
+        }
+        self.hsde_init(st)
+        return st
+
+    @staticmethod
+    def _hstate(st: dict) -> _HsdeState:
+        return _HsdeState(_ptr(st["x"]), _ptr(st["y"]), _ptr(st["s"]), _ptr(st["z"]), _ptr(st["tk"]),
+                          _ptr(st.get("vw")))
+
+    def hsde_init(self, st: dict, stream=None):
+        hs = self._hstate(st)
+        _check(load_library().cdcs_hsde_init(self._h, ctypes.byref(hs), _stream(self._torch, stream)),
+               "cdcs_hsde_init")
+
+    def hsde_solve(self, st: dict, tol: float = 1e-4, max_iter: int = 2000, check_every: int = 50,
+                   stream=None) -> HsdeInfo:
+        """cdcs_hsde_solve.  The outcome (solved, infeasible, unbounded, cap,
+        numeric) is HsdeInfo.status; other failures raise CdcsError."""
+        opts = _Options(1.0, float(tol), int(max_iter), 0, int(check_every))
+        info = _HsdeInfo()
+        hs = self._hstate(st)
+        r = load_library().cdcs_hsde_solve(self._h, ctypes.byref(hs), ctypes.byref(opts), ctypes.byref(info),
+                                           _stream(self._torch, stream))
+        if r not in (OK, E_NOT_CONVERGED, E_NUMERIC, PRIMAL_INFEASIBLE, DUAL_INFEASIBLE):
+            _check(r, "cdcs_hsde_solve")
+        return HsdeInfo(info.iters, info.status, info.jacobi_cap_hits, info.res_pri, info.res_dual, info.gap,
+                        info.obj_primal, info.obj_dual, info.tau, info.kappa, info.loop_s, info.jacobi_sweeps)
+
+    def hsde_solution(self, st: dict, which: int = 0, stream=None):
+        """(X, y_sdp) for which=0, the Farkas y for which=1, the ray X for which=2
+        (cdcs_hsde_solution; X in pattern order)."""
+        torch = self._torch
+        X = torch.empty(self.nnz, dtype=torch.float64, device="cuda") if which != 1 else None
+        y = torch.empty(self.m, dtype=torch.float64, device="cuda") if which != 2 else None
+        hs = self._hstate(st)
+        _check(load_library().cdcs_hsde_solution(self._h, ctypes.byref(hs), int(which), _ptr(X), _ptr(y),
+                                                  _stream(torch, stream)), "cdcs_hsde_solution")
+        return X, y
+
+    def hsde_history(self, n: int) -> np.ndarray:
+        """(res_pri, res_dual, gap) of the last HSDE solve's first n iterations."""
+        out = np.zeros((n, 3))
+        _check(load_library().cdcs_hsde_history(self._h, _np_ptr(out), int(n)), "cdcs_hsde_history")
+        return out
 
     def profile_kernel(self, state: dict, kernel: int, reps: int = 1, form: str = "primal", rho: float = 1.0,
                        stream=None):

@@ -36,16 +36,60 @@ cdcs_status fail(cdcs_status st, const std::string &msg) {
 int64_t round_up(int64_t v, int64_t q) { return (v + q - 1) / q * q; }
 
 
+// Internal form of the HSDE iteration (graphs and enqueue), beside CDCS_PRIMAL / CDCS_DUAL.
+constexpr int kFormHsde = 2;
+
 struct GraphKey {
     int form;
     int K;
     double rho;
-    const void *x, *y, *blk, *lam, *v, *vw;
+    const void *x, *y, *blk, *lam, *v, *vw, *tk;
     bool operator<(const GraphKey &o) const {
-        return std::tie(form, K, rho, x, y, blk, lam, v, vw) <
-               std::tie(o.form, o.K, o.rho, o.x, o.y, o.blk, o.lam, o.v, o.vw);
+        return std::tie(form, K, rho, x, y, blk, lam, v, vw, tk) <
+               std::tie(o.form, o.K, o.rho, o.x, o.y, o.blk, o.lam, o.v, o.vw, o.tk);
     }
 };
+
+// The inverse-factor fields of Dev (Algorithm 1/2's factor or the HSDE one).
+struct FactorFields {
+    double *Linv = nullptr, *LinvT = nullptr;
+    int32_t sparse_linv = 0, spchol = 0;
+    int64_t nnz_linv = 0, nnz_l = 0;
+    int32_t *li_ptr = nullptr, *li_col = nullptr, *lt_ptr = nullptr, *lt_col = nullptr;
+    double *li_val = nullptr, *lt_val = nullptr;
+};
+
+FactorFields get_factor(const Dev &d) {
+    FactorFields f;
+    f.Linv = d.Linv;
+    f.LinvT = d.LinvT;
+    f.sparse_linv = d.sparse_linv;
+    f.spchol = d.spchol;
+    f.nnz_linv = d.nnz_linv;
+    f.nnz_l = d.nnz_l;
+    f.li_ptr = d.li_ptr;
+    f.li_col = d.li_col;
+    f.li_val = d.li_val;
+    f.lt_ptr = d.lt_ptr;
+    f.lt_col = d.lt_col;
+    f.lt_val = d.lt_val;
+    return f;
+}
+
+void set_factor(Dev &d, const FactorFields &f) {
+    d.Linv = f.Linv;
+    d.LinvT = f.LinvT;
+    d.sparse_linv = f.sparse_linv;
+    d.spchol = f.spchol;
+    d.nnz_linv = f.nnz_linv;
+    d.nnz_l = f.nnz_l;
+    d.li_ptr = f.li_ptr;
+    d.li_col = f.li_col;
+    d.li_val = f.li_val;
+    d.lt_ptr = f.lt_ptr;
+    d.lt_col = f.lt_col;
+    d.lt_val = f.lt_val;
+}
 
 struct Bucket {
     int smax;
@@ -93,6 +137,15 @@ struct cdcs_handle {
     } diff;
     float *save_evals = nullptr;  // set while an unrolled step runs: the projection
     float *save_evecs = nullptr;  // writes its eigenpairs here
+    // sparse A: the symbolic input of the factor (touched entries' rows, host;
+    // touched-entry index of each coefficient, device), kept for the HSDE factor
+    std::vector<int32_t> sym_tcp, sym_tcr;
+    int32_t *sym_tid = nullptr;
+    // homogeneous self-dual embedding (built at the first HSDE call)
+    HsdeDev hs;
+    FactorFields hs_fac;
+    bool hs_ready = false;
+    double *hs_tk = nullptr;      // tau, kappa of the state the HSDE graphs were captured for
 
     template <typename T>
     cdcs_status alloc(T **p, int64_t count) {
@@ -150,6 +203,9 @@ struct HostProblem {
     bool sparse = false;             // CSR path: rows sorted by entry, duplicates summed
     std::vector<int32_t> sp_ptr, sp_col;
     std::vector<double> sp_val;      // w_e * A_ie
+    int64_t nslots_psd = 0;          // clique slots; the vector cones' slots follow
+    int32_t nvc = 0;                 // vector cones
+    std::vector<int32_t> vblk;       // [nvb * 4] (kind, s0, s1, cone) work blocks of the vector cones
 };
 
 // A CSR input is kept sparse when a dense FP32 copy would be read at more
@@ -157,11 +213,16 @@ struct HostProblem {
 bool keep_sparse(int64_t nnz, int64_t m, int64_t nU) { return nnz * 5 < m * nU; }
 
 cdcs_status host_problem(const cdcs_pattern *pat, const cdcs_constraints *A, const double *b, const double *c,
-                         const cdcs_cliques *cl, int64_t align, bool allow_sparse, HostProblem &P) {
+                         const cdcs_cliques *cl, const cdcs_vcones *cones, int64_t align, bool allow_sparse,
+                         HostProblem &P) {
     if (!pat || !A || !b || !c || !cl) return fail(CDCS_E_ARG, "NULL argument");
     if (pat->n < 1 || pat->nnz < 1 || !pat->i || !pat->j) return fail(CDCS_E_ARG, "empty or NULL pattern");
     if (A->m < 1 || !A->val) return fail(CDCS_E_ARG, "no constraints");
-    if (cl->p < 1 || !cl->ptr || !cl->vert) return fail(CDCS_E_ARG, "no cliques");
+    const int32_t nvc = cones ? cones->ncones : 0;
+    if (nvc < 0 || (nvc > 0 && (!cones->kind || !cones->ptr || !cones->vert)))
+        return fail(CDCS_E_ARG, "bad vector cone arrays");
+    if (cl->p < 0 || (cl->p == 0 && nvc == 0) || (cl->p > 0 && (!cl->ptr || !cl->vert)))
+        return fail(CDCS_E_ARG, "no cliques");
     const int32_t n = pat->n;
     const int64_t nU = pat->nnz;
     const int32_t m = A->m;
@@ -187,7 +248,7 @@ cdcs_status host_problem(const cdcs_pattern *pat, const cdcs_constraints *A, con
     };
 
     // Cliques: E_k with vertices in increasing order (Sec. II-B); gather map H_k.
-    if (cl->ptr[0] != 0) return fail(CDCS_E_PATTERN, "clique ptr[0] != 0");
+    if (p > 0 && cl->ptr[0] != 0) return fail(CDCS_E_PATTERN, "clique ptr[0] != 0");
     P.n = n;
     P.m = m;
     P.p = p;
@@ -212,7 +273,23 @@ cdcs_status host_problem(const cdcs_pattern *pat, const cdcs_constraints *A, con
         P.smax = std::max<int32_t>(P.smax, (int32_t)sk);
         P.off[(size_t)k + 1] = P.off[(size_t)k] + sk * (sk + 1) / 2;
     }
-    P.nslots = P.off[(size_t)p];
+    P.nslots_psd = P.off[(size_t)p];
+    // vector cones: one slot per vertex (its diagonal entry), after the cliques
+    int64_t nvs = 0;
+    if (nvc > 0) {
+        if (cones->ptr[0] != 0) return fail(CDCS_E_PATTERN, "cone ptr[0] != 0");
+        for (int32_t q = 0; q < nvc; ++q) {
+            const int64_t sz = cones->ptr[q + 1] - cones->ptr[q];
+            const int32_t kind = cones->kind[q];
+            if (kind != CDCS_CONE_FREE && kind != CDCS_CONE_ORTHANT && kind != CDCS_CONE_SOC)
+                return fail(CDCS_E_ARG, "vector cone " + std::to_string(q) + ": unknown kind");
+            if (sz < (kind == CDCS_CONE_SOC ? 2 : 1))
+                return fail(CDCS_E_PATTERN, "vector cone " + std::to_string(q) + " too small");
+            nvs += sz;
+        }
+    }
+    P.nvc = nvc;
+    P.nslots = P.nslots_psd + nvs;
     if (P.nslots >= (int64_t)1 << 31) return fail(CDCS_E_ARG, "too many clique slots");
     P.gather.resize((size_t)P.nslots);
     P.cnt.assign((size_t)nU, 0);
@@ -228,8 +305,43 @@ cdcs_status host_problem(const cdcs_pattern *pat, const cdcs_constraints *A, con
                 ++P.cnt[(size_t)e];
             }
     }
+    if (nvc > 0) {
+        // a cone vertex: in no clique and no other cone, only its diagonal entry
+        std::vector<char> taken((size_t)n, 0);
+        for (int32_t k = 0; k < p; ++k)
+            for (int64_t q = cl->ptr[k]; q < cl->ptr[k + 1]; ++q) taken[(size_t)cl->vert[q]] = 1;
+        std::vector<char> offd((size_t)n, 0);
+        for (int64_t e = 0; e < nU; ++e)
+            if (pat->i[e] != pat->j[e]) offd[(size_t)pat->i[e]] = offd[(size_t)pat->j[e]] = 1;
+        int64_t g = P.nslots_psd;
+        for (int32_t q = 0; q < nvc; ++q) {
+            const int32_t kind = cones->kind[q];
+            const int64_t s0 = g;
+            for (int64_t t = cones->ptr[q]; t < cones->ptr[q + 1]; ++t, ++g) {
+                const int32_t v = cones->vert[t];
+                if (v < 0 || v >= n) return fail(CDCS_E_PATTERN, "cone vertex out of range");
+                if (taken[(size_t)v] || offd[(size_t)v])
+                    return fail(CDCS_E_PATTERN, "cone vertex " + std::to_string(v) +
+                                                    " in a clique, in another cone or with off-diagonal entries");
+                taken[(size_t)v] = 1;
+                const int32_t e = find(v, v);
+                if (e < 0) return fail(CDCS_E_PATTERN, "cone vertex " + std::to_string(v) + " without diagonal entry");
+                P.gather[(size_t)g] = e;
+                ++P.cnt[(size_t)e];
+            }
+            // work blocks: a second-order cone whole, the others in chunks
+            const int64_t step = kind == CDCS_CONE_SOC ? g - s0 : kVecChunk;
+            for (int64_t a = s0; a < g; a += step) {
+                P.vblk.push_back(kind);
+                P.vblk.push_back((int32_t)a);
+                P.vblk.push_back((int32_t)std::min(g, a + step));
+                P.vblk.push_back(q);
+            }
+        }
+    }
     for (int64_t e = 0; e < nU; ++e)
-        if (P.cnt[(size_t)e] == 0) return fail(CDCS_E_PATTERN, "pattern entry " + std::to_string(e) + " lies in no clique");
+        if (P.cnt[(size_t)e] == 0)
+            return fail(CDCS_E_PATTERN, "pattern entry " + std::to_string(e) + " lies in no clique or cone");
     // Internal entry order: first appearance in the packed slots, clique by
     // clique.  An entry's value then sits where its (first) clique's slots
     // sit, so the gather of x into the blocks and the scatter back read
@@ -436,8 +548,8 @@ cdcs_status upload_common(cdcs_handle *h, const std::vector<int32_t> &size, cons
             if (wt[(size_t)e] == 2.0) bits[(size_t)(e >> 5)] |= 1u << (e & 31);
         CK(upload(h, &d.wbits, bits, s));
     }
-    CK(h->alloc(&d.cpart, 4 * (int64_t)p));
-    HIP_OK(hipMemsetAsync(d.cpart, 0, (size_t)(4 * p) * sizeof(double), s));
+    CK(h->alloc(&d.cpart, 4 * (int64_t)(p + d.nvb)));
+    HIP_OK(hipMemsetAsync(d.cpart, 0, (size_t)(4 * (p + d.nvb)) * sizeof(double), s));
     CK(h->alloc(&d.vpart, 5 * (int64_t)vupdate_blocks(d)));
     CK(h->alloc(&d.obj, 2));
     CK(h->alloc(&d.opart, objective_partials()));
@@ -605,7 +717,7 @@ bool sp_symbolic(int32_t m, const std::vector<int32_t> &tcp, const std::vector<i
 // copies the affine step multiplies by: y1 = L^-1 (P t) with the columns
 // labelled by the original rows, and y = P^T L^-T y1 with the rows labelled
 // by the original rows (P M P^T = L L^T, so M^-1 = P^T L^-T L^-1 P).
-cdcs_status sparse_factor(cdcs_handle *h, const SpSym &S, const int32_t *tid_d, hipStream_t s) {
+cdcs_status sparse_factor(cdcs_handle *h, const SpSym &S, const int32_t *tid_d, double shift, hipStream_t s) {
     Dev &d = h->d;
     const int32_t m = d.m;
     SpFactor f;
@@ -635,7 +747,7 @@ cdcs_status sparse_factor(cdcs_handle *h, const SpSym &S, const int32_t *tid_d, 
     CK(h->alloc(&f.Lv, nnzL));
     CK(h->alloc(&f.diag0, m));
     CK(h->alloc(&f.xv, nnzX));
-    launch_spchol_fill(d, f, tid_d, s);
+    launch_spchol_fill(d, f, tid_d, shift, s);
     launch_spchol(d, f, S.level_off, d.info, s);
     // CSR copies: rows of X (columns relabelled to original rows) and rows of
     // P^T X^T (= columns of X, in original row order)
@@ -683,22 +795,64 @@ cdcs_status sparse_factor(cdcs_handle *h, const SpSym &S, const int32_t *tid_d, 
     d.spchol = 1;
     d.nnz_linv = nnzX;
     d.nnz_l = nnzL;
-    CK(tune_projection(h, s));
-    HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     return CDCS_OK;
 }
 
+// KKT factor of M = Aw diag(s2) Aw^T + shift I with s2 = d.s2, into d's
+// factor fields: sparse when A is kept sparse and the factor's inverse stays
+// sparse (the symbolic step decides); otherwise M dense, Cholesky, inverse
+// factors (kept as CSR when sparse enough).
+cdcs_status factor_into(cdcs_handle *h, double shift, hipStream_t s) {
+    Dev &d = h->d;
+    const int64_t m = d.m;
+    if (d.sparse) {
+        SpSym S;
+        if (sp_symbolic((int32_t)m, h->sym_tcp, h->sym_tcr, spinv_max_path(), (int64_t)m * (m + 1) / 2 / 8, S))
+            return sparse_factor(h, S, h->sym_tid, shift, s);
+    }
+    if (m > 8192) return fail(CDCS_E_ARG, "m > 8192 is not supported by the dense factor");
+    double *M = nullptr, *diag0 = nullptr;
+    HIP_OK(hipMalloc(&M, (size_t)m * m * sizeof(double)));
+    hipError_t e1 = hipMalloc(&diag0, (size_t)m * sizeof(double));
+    if (e1 != hipSuccess) {
+        (void)hipFree(M);
+        return fail(CDCS_E_NOMEM, "hipMalloc diag");
+    }
+    CK(h->alloc(&d.Linv, m * m));
+    CK(h->alloc(&d.LinvT, m * m));
+    if (d.sparse) launch_sp_syrk(d, h->sym_tid, M, s);
+    else launch_syrk(d.Aw, d.ldU, d.s2, (int)m, M, s);
+    if (shift != 0.0) launch_add_diag(M, (int)m, shift, s);
+    launch_potrf(M, (int)m, diag0, d.info, s);
+    launch_trtri(M, (int)m, d.LinvT, d.Linv, s);
+    int32_t info_h[4] = {0, 0, 0, 0};
+    hipError_t e2 = hipMemcpyAsync(info_h, d.info, sizeof(info_h), hipMemcpyDeviceToHost, s);
+    hipError_t e3 = hipStreamSynchronize(s);
+    (void)hipFree(M);
+    (void)hipFree(diag0);
+    if (e2 != hipSuccess || e3 != hipSuccess)
+        return fail(CDCS_E_DEVICE, std::string("setup kernels: ") + hipGetErrorString(e2 != hipSuccess ? e2 : e3));
+    if (info_h[0] != 0)
+        return fail(CDCS_E_RANK,
+                    "A D^-1 A^T is not positive definite (pivot " + std::to_string(info_h[1]) + "): A is rank deficient");
+    return compress_factors(h, s);
+}
+
 cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraints *A, const double *b,
-                  const double *c, const cdcs_cliques *cl, hipStream_t s) {
+                  const double *c, const cdcs_cliques *cl, const cdcs_vcones *cones, hipStream_t s) {
     Dev &d = h->d;
     HostProblem P;
-    CK(host_problem(pat, A, b, c, cl, 64, true, P));
+    CK(host_problem(pat, A, b, c, cl, cones, 64, true, P));
     d.n = P.n;
     d.m = P.m;
     d.p = P.p;
     d.nU = P.nU;
     d.smax = P.smax;
     d.nslots = P.nslots;
+    d.nslots_psd = P.nslots_psd;
+    d.nvc = P.nvc;
+    d.nvb = (int32_t)(P.vblk.size() / 4);
+    if (d.nvb > 0) CK(upload(h, &d.vblk, P.vblk, s));
     d.ldU = P.ld;
     d.ldM = round_up(P.m, 32);  // rows of A^T start on 128-byte lines
     h->off_host = P.off;
@@ -757,47 +911,12 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
         CK(upload(h, &d.AwT, AwT, s));
     }
 
-    // KKT factor: sparse when A is kept sparse and the factor's inverse stays
-    // sparse (the symbolic step decides); otherwise M = Aw diag(s2) Aw^T
-    // dense, Cholesky, inverse factors.
     if (d.sparse) {
-        SpSym S;
-        if (sp_symbolic((int32_t)m, tcp_h, tcr_h, spinv_max_path(), (int64_t)m * (m + 1) / 2 / 8, S)) {
-            int32_t *tid_d = nullptr;
-            CK(upload(h, &tid_d, tid, s));
-            return sparse_factor(h, S, tid_d, s);
-        }
+        h->sym_tcp.swap(tcp_h);
+        h->sym_tcr.swap(tcr_h);
+        CK(upload(h, &h->sym_tid, tid, s));
     }
-    if (m > 8192) return fail(CDCS_E_ARG, "m > 8192 is not supported by the dense factor");
-    double *M = nullptr, *diag0 = nullptr;
-    HIP_OK(hipMalloc(&M, (size_t)m * m * sizeof(double)));
-    hipError_t e1 = hipMalloc(&diag0, (size_t)m * sizeof(double));
-    if (e1 != hipSuccess) {
-        (void)hipFree(M);
-        return fail(CDCS_E_NOMEM, "hipMalloc diag");
-    }
-    CK(h->alloc(&d.Linv, m * m));
-    CK(h->alloc(&d.LinvT, m * m));
-    int32_t *tid_d = nullptr;
-    if (d.sparse) {
-        CK(upload(h, &tid_d, tid, s));
-        launch_sp_syrk(d, tid_d, M, s);
-    } else {
-        launch_syrk(d.Aw, d.ldU, d.s2, (int)m, M, s);
-    }
-    launch_potrf(M, (int)m, diag0, d.info, s);
-    launch_trtri(M, (int)m, d.LinvT, d.Linv, s);
-    int32_t info_h[4] = {0, 0, 0, 0};
-    hipError_t e2 = hipMemcpyAsync(info_h, d.info, sizeof(info_h), hipMemcpyDeviceToHost, s);
-    hipError_t e3 = hipStreamSynchronize(s);
-    (void)hipFree(M);
-    (void)hipFree(diag0);
-    if (e2 != hipSuccess || e3 != hipSuccess)
-        return fail(CDCS_E_DEVICE, std::string("setup kernels: ") + hipGetErrorString(e2 != hipSuccess ? e2 : e3));
-    if (info_h[0] != 0)
-        return fail(CDCS_E_RANK,
-                    "A D^-1 A^T is not positive definite (pivot " + std::to_string(info_h[1]) + "): A is rank deficient");
-    CK(compress_factors(h, s));
+    CK(factor_into(h, 0.0, s));
     CK(tune_projection(h, s));
     HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     return CDCS_OK;
@@ -826,7 +945,7 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
     for (int32_t q = 0; q < nprob; ++q) {
         HostProblem P;
         const cdcs_problem &pr = probs[q];
-        cdcs_status st = host_problem(pr.pattern, pr.A, pr.b, pr.c, pr.cliques, 4, false, P);
+        cdcs_status st = host_problem(pr.pattern, pr.A, pr.b, pr.c, pr.cliques, nullptr, 4, false, P);
         if (st != CDCS_OK) return fail(st, "problem " + std::to_string(q) + ": " + g_err);
         if (P.m > 256) return fail(CDCS_E_ARG, "problem " + std::to_string(q) + ": batched factors need m <= 256");
         if (P.smax > kMaxLdsClique)
@@ -916,6 +1035,7 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
     d.m = m_off.back();
     d.p = k_off.back();
     d.nslots = h->off_host.back();
+    d.nslots_psd = d.nslots;
     if (d.nU >= (int64_t)1 << 31 || d.nslots >= (int64_t)1 << 31) return fail(CDCS_E_ARG, "batch too large");
     d.ldU = d.nU;
     d.ldM = round_up(d.m, 4);
@@ -1099,7 +1219,9 @@ void launch_plan(cdcs_handle *h, ProjArgs a, hipStream_t s) {
 }
 
 void launch_projection(cdcs_handle *h, int mode, const cdcs_state *st, double rho, hipStream_t s) {
-    launch_plan(h, proj_args(h, mode, st, rho), s);
+    const ProjArgs a = proj_args(h, mode, st, rho);
+    launch_plan(h, a, s);
+    launch_project_vec(a, h->d.vblk, h->d.nvb, h->d.p, s);  // vector cones, if any
 }
 
 int device_cus(cdcs_handle *h) {
@@ -1253,6 +1375,16 @@ struct IterTimer {
 
 // One ADMM iteration.  With a timer (eager launches only) each kernel kind is
 // bracketed by events; the launches are the same either way.
+// Dev as the HSDE linear step sees it: 1 / E, 1 / (w E) and the factor of
+// I + A diag(w / E) A^T in place of Algorithm 1's.
+Dev hsde_dev(const cdcs_handle *h) {
+    Dev dh = h->d;
+    dh.invD = h->hs.invE;
+    dh.s2 = h->hs.s2E;
+    set_factor(dh, h->hs_fac);
+    return dh;
+}
+
 void enqueue_iteration(cdcs_handle *h, const cdcs_state *st, int form, double rho, hipStream_t s,
                        IterTimer *tm = nullptr) {
     Dev &d = h->d;
@@ -1260,6 +1392,21 @@ void enqueue_iteration(cdcs_handle *h, const cdcs_state *st, int form, double rh
         if (tm) tm->around(k, s, fn);
         else fn();
     };
+    if (form == kFormHsde) {  // st: x = u_x (internal order), y = u_y, blk = s, lam = z
+        const Dev dh = hsde_dev(h);
+        HsdeDev &hs = h->hs;
+        double *tk = h->hs_tk;
+        timed(CDCS_K_SCATTER, [&] { launch_hsde_scatter(d, hs, st->blk, st->lam, tk, s); });
+        launch_hsde_check(d, hs, tk, s);
+        timed(CDCS_K_GEMV_AU, [&] { launch_affine_part(dh, 0, st->y, -1.0, hs.a, hs.yh, d.ctl, s); });
+        launch_affine_part(dh, 3, st->y, -1.0, hs.a, hs.yh, d.ctl, s);
+        timed(CDCS_K_TRMV, [&] { launch_affine_part(dh, 1, st->y, -1.0, hs.a, hs.yh, d.ctl, s); });
+        timed(CDCS_K_GEMV_ATY, [&] { launch_affine_part(dh, 2, st->y, -1.0, hs.a, hs.yh, d.ctl, s); });
+        launch_hsde_tau(d, hs, st->y, tk, s);
+        launch_hsde_axpy(d, hs, s);
+        timed(CDCS_K_PROJECT, [&] { launch_projection(h, PROJ_PRIMAL, st, 1.0, s); });
+        return;
+    }
     if (d.batch && form == CDCS_PRIMAL) {  // Algorithm 1, per-instance stopping
         timed(CDCS_K_SCATTER, [&] { launch_bscatter_primal(d, st->blk, st->lam, rho, s); });
         launch_bcheck_primal(d, rho, s);
@@ -1298,7 +1445,8 @@ void enqueue_iteration(cdcs_handle *h, const cdcs_state *st, int form, double rh
 }
 
 cdcs_status get_graph(cdcs_handle *h, const cdcs_state *st, int form, int K, double rho, hipGraphExec_t *out) {
-    GraphKey key{form, K, rho, st->x, st->y, st->blk, st->lam, st->v, st->vw};
+    GraphKey key{form, K, rho, st->x, st->y, st->blk, st->lam, st->v, st->vw,
+                 form == kFormHsde ? (const void *)h->hs_tk : nullptr};
     auto it = h->graphs.find(key);
     if (it != h->graphs.end()) {
         *out = it->second;
@@ -1371,22 +1519,52 @@ cdcs_status cdcs_chordal_extension(const cdcs_pattern *pattern, int64_t *nfill, 
     return CDCS_OK;
 }
 
-cdcs_status cdcs_setup(const cdcs_pattern *pattern, const cdcs_constraints *A, const double *b, const double *c,
-                       const cdcs_cliques *cliques, const cdcs_options *opts, hipStream_t stream,
-                       cdcs_handle **out) {
+cdcs_status cdcs_setup_cones(const cdcs_pattern *pattern, const cdcs_constraints *A, const double *b,
+                             const double *c, const cdcs_cliques *cliques, const cdcs_vcones *cones,
+                             const cdcs_options *opts, hipStream_t stream, cdcs_handle **out) {
     (void)opts;
     if (!out) return fail(CDCS_E_ARG, "out is NULL");
     *out = nullptr;
     g_err.clear();
+    if (cones && cones->ncones == 0) cones = nullptr;
     if (!cliques) {
         // chordal decomposition of an arbitrary pattern: the extension's fill
         // entries follow the caller's entries, with zero data (C and every A_i
-        // vanish on them)
+        // vanish on them); the vector cones' vertices stay out of it
         if (!pattern || !A || !b || !c || !A->val) return fail(CDCS_E_ARG, "NULL argument");
+        if (pattern->n < 1 || pattern->nnz < 1 || !pattern->i || !pattern->j)
+            return fail(CDCS_E_ARG, "empty or NULL pattern");
+        const int32_t *ei = pattern->i, *ej = pattern->j;
+        int64_t next = pattern->nnz;
+        std::vector<int32_t> fi, fj;
+        if (cones) {
+            if (cones->ncones < 0 || !cones->ptr || !cones->vert || cones->ptr[0] != 0)
+                return fail(CDCS_E_ARG, "bad vector cone arrays");
+            std::vector<char> isc((size_t)pattern->n, 0);
+            for (int64_t t = 0; t < cones->ptr[cones->ncones]; ++t) {
+                const int32_t v = cones->vert[t];
+                if (v < 0 || v >= pattern->n) return fail(CDCS_E_PATTERN, "cone vertex out of range");
+                isc[(size_t)v] = 1;
+            }
+            for (int64_t e = 0; e < pattern->nnz; ++e) {
+                const int32_t i = pattern->i[e], j = pattern->j[e];
+                if (i < 0 || j < 0 || i >= pattern->n || j >= pattern->n)
+                    return fail(CDCS_E_PATTERN, "pattern entry " + std::to_string(e) + " out of range");
+                if (isc[(size_t)i] || isc[(size_t)j]) continue;
+                fi.push_back(i);
+                fj.push_back(j);
+            }
+            ei = fi.data();
+            ej = fj.data();
+            next = (int64_t)fi.size();
+        }
         ChordalExt ext;
-        std::string err;
-        const cdcs_status st = chordal_extension(pattern->n, pattern->nnz, pattern->i, pattern->j, ext, err);
-        if (st != CDCS_OK) return fail(st, err);
+        ext.ptr.assign(1, 0);
+        if (next > 0) {
+            std::string err;
+            const cdcs_status st = chordal_extension(pattern->n, next, ei, ej, ext, err);
+            if (st != CDCS_OK) return fail(st, err);
+        }
         const int64_t nu = pattern->nnz, nf = (int64_t)ext.fill_i.size(), ne = nu + nf;
         std::vector<int32_t> pi(pattern->i, pattern->i + nu), pj(pattern->j, pattern->j + nu);
         pi.insert(pi.end(), ext.fill_i.begin(), ext.fill_i.end());
@@ -1403,7 +1581,7 @@ cdcs_status cdcs_setup(const cdcs_pattern *pattern, const cdcs_constraints *A, c
         }
         const cdcs_pattern px{pattern->n, ne, pi.data(), pj.data()};
         const cdcs_cliques cx_cl{(int32_t)(ext.ptr.size() - 1), ext.ptr.data(), ext.vert.data()};
-        return cdcs_setup(&px, &Ax, b, cx.data(), &cx_cl, opts, stream, out);
+        return cdcs_setup_cones(&px, &Ax, b, cx.data(), &cx_cl, cones, opts, stream, out);
     }
     cdcs_handle *h = new (std::nothrow) cdcs_handle();
     if (!h) return fail(CDCS_E_NOMEM, "host allocation");
@@ -1412,7 +1590,7 @@ cdcs_status cdcs_setup(const cdcs_pattern *pattern, const cdcs_constraints *A, c
         delete h;
         return fail(CDCS_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
     }
-    cdcs_status st = build(h, pattern, A, b, c, cliques, stream);
+    cdcs_status st = build(h, pattern, A, b, c, cliques, cones, stream);
     if (st != CDCS_OK) {
         (void)hipStreamSynchronize(stream);
         delete h;
@@ -1420,6 +1598,12 @@ cdcs_status cdcs_setup(const cdcs_pattern *pattern, const cdcs_constraints *A, c
     }
     *out = h;
     return CDCS_OK;
+}
+
+cdcs_status cdcs_setup(const cdcs_pattern *pattern, const cdcs_constraints *A, const double *b, const double *c,
+                       const cdcs_cliques *cliques, const cdcs_options *opts, hipStream_t stream,
+                       cdcs_handle **out) {
+    return cdcs_setup_cones(pattern, A, b, c, cliques, nullptr, opts, stream, out);
 }
 
 cdcs_status cdcs_setup_batch(int32_t nprob, const cdcs_problem *probs, const cdcs_options *opts, hipStream_t stream,
@@ -1495,6 +1679,9 @@ cdcs_status cdcs_get_sizes(const cdcs_handle *h, cdcs_sizes *out) {
     out->nnz_factor = h->d.sparse_linv ? h->d.nnz_linv : (int64_t)h->d.m * (h->d.m + 1) / 2;
     out->nwarm = h->d.nwarm;
     out->nnz_l = h->d.spchol ? h->d.nnz_l : 0;
+    out->nvcones = h->d.nvc;
+    out->pad_ = 0;
+    out->nslots_psd = h->d.nvc > 0 ? h->d.nslots_psd : h->d.nslots;
     return CDCS_OK;
 }
 
@@ -1749,6 +1936,178 @@ cdcs_status solve_impl(cdcs_handle *h, const cdcs_state *st_user, const cdcs_opt
 }
 }  // namespace
 
+namespace {
+// HSDE data of a handle: 1 / E and 1 / (w E), the factor of
+// I + A diag(w / E) A^T (the Algorithm-1 factor code with those scales and a
+// unit diagonal shift), g = M^-1 (c, bhat) and the constants.
+cdcs_status hsde_prepare(cdcs_handle *h, hipStream_t s) {
+    if (h->hs_ready) return CDCS_OK;
+    Dev &d = h->d;
+    HsdeDev &hs = h->hs;
+    if (!hs.invE) {
+        CK(h->alloc(&hs.invE, d.ldU));
+        CK(h->alloc(&hs.s2E, d.ldU));
+        CK(h->alloc(&hs.gx, d.ldU));
+        CK(h->alloc(&hs.gy, d.ldM));
+        CK(h->alloc(&hs.a, d.ldU));
+        CK(h->alloc(&hs.yh, d.ldM));
+        CK(h->alloc(&hs.dx, d.ldU));
+        CK(h->alloc(&hs.sc, 16));
+        CK(h->alloc(&hs.hpart, 2 * (int64_t)scatter_blocks(d)));
+        CK(h->alloc(&hs.dpart, hsde_dot_blocks(d)));
+        for (double *q : {hs.a, hs.dx, hs.gx})
+            HIP_OK(hipMemsetAsync(q, 0, (size_t)d.ldU * sizeof(double), s));
+        HIP_OK(hipMemsetAsync(hs.sc, 0, 16 * sizeof(double), s));
+    }
+    launch_hsde_scales(d, hs, s);
+    HIP_OK(hipGetLastError());
+    const FactorFields keep = get_factor(d);
+    double *s2keep = d.s2;
+    set_factor(d, FactorFields());
+    d.s2 = hs.s2E;
+    const cdcs_status st = factor_into(h, 1.0, s);
+    h->hs_fac = get_factor(d);
+    set_factor(d, keep);
+    d.s2 = s2keep;
+    CK(st);
+    // g: u = c / E, t = A(w u) + b, g_y = M'^-1 t, g_x = u - (A^T g_y) / E
+    const Dev dh = hsde_dev(h);
+    launch_hsde_cu(d, hs, s);
+    launch_affine(dh, d.b, -1.0, hs.gx, hs.gy, nullptr, s);
+    launch_hsde_consts(d, hs, s);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(s));
+    h->hs_ready = true;
+    return CDCS_OK;
+}
+
+cdcs_status hsde_check_state(const cdcs_handle *h, const cdcs_hsde_state *st) {
+    if (!h || !st) return fail(CDCS_E_ARG, "NULL argument");
+    if (!st->x || !st->y || !st->s || !st->z || !st->tk) return fail(CDCS_E_ARG, "HSDE state has NULL buffers");
+    if (h->d.batch) return fail(CDCS_E_ARG, "the HSDE solver runs on single-SDP handles");
+    return CDCS_OK;
+}
+}  // namespace
+
+cdcs_status cdcs_hsde_init(cdcs_handle *h, const cdcs_hsde_state *st, hipStream_t stream) {
+    CK(hsde_check_state(h, st));
+    const Dev &d = h->d;
+    launch_hsde_init(d, st->x, st->y, st->s, st->z, st->tk, stream);
+    if (st->vw) launch_identity_blocks(d.clq_size, d.vwoff, d.p, st->vw, stream);
+    HIP_OK(hipGetLastError());
+    return CDCS_OK;
+}
+
+cdcs_status cdcs_hsde_solve(cdcs_handle *h, const cdcs_hsde_state *st, const cdcs_options *opts, cdcs_hsde_info *info,
+                            hipStream_t stream) {
+    CK(hsde_check_state(h, st));
+    if (!opts) return fail(CDCS_E_ARG, "NULL argument");
+    if (!(opts->tol >= 0.0) || opts->max_iter < 1 || opts->check_every < 0)
+        return fail(CDCS_E_ARG, "need tol >= 0, max_iter >= 1, check_every >= 0");
+    CK(hsde_prepare(h, stream));
+    Dev &d = h->d;
+    HsdeDev &hs = h->hs;
+    if (hs.hist_cap < opts->max_iter) {
+        if (hs.hist) {
+            HIP_OK(hipStreamSynchronize(stream));
+            (void)hipFree(hs.hist);
+            h->allocs.erase(std::remove(h->allocs.begin(), h->allocs.end(), (void *)hs.hist), h->allocs.end());
+            hs.hist = nullptr;
+        }
+        CK(h->alloc(&hs.hist, 3 * (int64_t)opts->max_iter));
+        hs.hist_cap = opts->max_iter;
+        for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+        h->graphs.clear();
+    }
+    // the iteration runs on x in internal entry order; s and z take the
+    // places of x_k and lambda_k
+    cdcs_state sti{d.xi, st->y, st->s, st->z, nullptr, st->vw};
+    h->hs_tk = st->tk;
+    launch_reset_ctl(d, opts->max_iter, opts->tol, stream);
+    if (!st->vw) launch_identity_blocks(d.clq_size, d.vwoff, d.p, d.vwarm, stream);
+    launch_perm_in(d, st->x, d.xi, stream);
+    HIP_OK(hipGetLastError());
+    const auto t0 = std::chrono::steady_clock::now();
+    const int K = opts->check_every;
+    if (K > 0) {
+        hipGraphExec_t full = nullptr, tail = nullptr;
+        if (opts->max_iter >= K) CK(get_graph(h, &sti, kFormHsde, K, 1.0, &full));
+        if (opts->max_iter % K) CK(get_graph(h, &sti, kFormHsde, opts->max_iter % K, 1.0, &tail));
+        for (int done = 0; done < opts->max_iter;) {
+            const int n = std::min(K, opts->max_iter - done);
+            HIP_OK(hipGraphLaunch(n == K ? full : tail, stream));
+            done += n;
+            HIP_OK(hipMemcpyAsync(d.ctl_host, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+            HIP_OK(hipStreamSynchronize(stream));
+            if (d.ctl_host->stop) break;
+        }
+    } else {
+        for (int it = 0; it < opts->max_iter; ++it) {
+            enqueue_iteration(h, &sti, kFormHsde, 1.0, stream);
+            HIP_OK(hipGetLastError());
+            if ((it + 1) % 16 == 0) {
+                HIP_OK(hipMemcpyAsync(d.ctl_host, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+                HIP_OK(hipStreamSynchronize(stream));
+                if (d.ctl_host->stop) break;
+            }
+        }
+    }
+    // the last iterate's check needs the next iteration's scatter
+    launch_hsde_scatter(d, hs, sti.blk, sti.lam, st->tk, stream);
+    launch_hsde_check(d, hs, st->tk, stream);
+    launch_perm_out(d, d.xi, st->x, stream);
+    HIP_OK(hipGetLastError());
+    double sc[16], tk[2];
+    HIP_OK(hipMemcpyAsync(d.ctl_host, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipMemcpyAsync(sc, hs.sc, sizeof(sc), hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipMemcpyAsync(tk, st->tk, sizeof(tk), hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    const auto t1 = std::chrono::steady_clock::now();
+    const Ctl c = *d.ctl_host;
+    h->last_iters = c.iter;
+    cdcs_status status = CDCS_OK;
+    if (c.stop == 3 || c.jacobi_cap > 0) status = CDCS_E_NUMERIC;
+    else if (c.stop == 4) status = CDCS_PRIMAL_INFEASIBLE;
+    else if (c.stop == 5) status = CDCS_DUAL_INFEASIBLE;
+    else if (c.stop != 1 && opts->tol > 0.0) status = CDCS_E_NOT_CONVERGED;
+    if (info) {
+        info->iters = c.iter;
+        info->status = status;
+        info->jacobi_cap_hits = c.jacobi_cap;
+        info->pad_ = 0;
+        info->res_pri = sc[10];
+        info->res_dual = sc[11];
+        info->gap = sc[12];
+        const double nan = std::nan("");
+        info->obj_primal = tk[0] > 0.0 ? sc[9] / tk[0] : nan;
+        info->obj_dual = tk[0] > 0.0 ? -sc[8] / tk[0] : nan;
+        info->tau = tk[0];
+        info->kappa = tk[1];
+        info->loop_s = std::chrono::duration<double>(t1 - t0).count();
+        info->jacobi_sweeps = c.sweeps;
+    }
+    if (status == CDCS_E_NUMERIC)
+        g_err = c.stop == 3 ? "NaN or Inf in the iterate (residuals not finite)" : "an eigensolve hit its sweep cap";
+    else if (status == CDCS_E_NOT_CONVERGED)
+        g_err = "iteration cap reached";
+    else if (status == CDCS_PRIMAL_INFEASIBLE)
+        g_err = "primal infeasible (certificate in y)";
+    else if (status == CDCS_DUAL_INFEASIBLE)
+        g_err = "dual infeasible (certificate in x)";
+    return status;
+}
+
+cdcs_status cdcs_hsde_solution(cdcs_handle *h, const cdcs_hsde_state *st, int32_t which, double *X_out,
+                               double *y_out, hipStream_t stream) {
+    CK(hsde_check_state(h, st));
+    if (which < 0 || which > 2) return fail(CDCS_E_ARG, "which must be 0, 1 or 2");
+    if ((which != 1 && !X_out) || (which != 2 && !y_out)) return fail(CDCS_E_ARG, "NULL output");
+    if (!h->hs_ready) return fail(CDCS_E_ARG, "no HSDE solve on this handle yet");
+    launch_hsde_solution(h->d, h->hs, which, st->x, st->y, st->tk, X_out, y_out, stream);
+    HIP_OK(hipGetLastError());
+    return CDCS_OK;
+}
+
 cdcs_status cdcs_admm_solve(cdcs_handle *h, const cdcs_state *st, const cdcs_options *opts, cdcs_info *info,
                             hipStream_t stream) {
     return solve_impl(h, st, opts, info, stream, nullptr);
@@ -1769,6 +2128,7 @@ cdcs_status cdcs_unrolled_step(cdcs_handle *h, const cdcs_state *st, const doubl
                                float *evals, float *evecs, hipStream_t stream) {
     if (!h || !st || !c || !b) return fail(CDCS_E_ARG, "NULL argument");
     if (h->d.batch) return fail(CDCS_E_ARG, "unrolled steps run on single-SDP handles");
+    if (h->d.nvc > 0) return fail(CDCS_E_ARG, "unrolled steps run on handles without vector cones");
     if (h->d.big.nbig > 0)
         return fail(CDCS_E_ARG, "unrolled steps need eigenpairs: cliques of at most " +
                                     std::to_string(kMaxLdsClique) + " vertices");
@@ -1800,6 +2160,7 @@ cdcs_status cdcs_unrolled_step_vjp(cdcs_handle *h, double rho, const float *eval
     if (!h || !evals || !evecs || !blkbar || !lambar || !cbar || !bbar) return fail(CDCS_E_ARG, "NULL argument");
     if (!(rho > 0.0)) return fail(CDCS_E_ARG, "need rho > 0");
     if (h->d.batch) return fail(CDCS_E_ARG, "unrolled steps run on single-SDP handles");
+    if (h->d.nvc > 0) return fail(CDCS_E_ARG, "unrolled steps run on handles without vector cones");
     if (h->d.big.nbig > 0)
         return fail(CDCS_E_ARG, "unrolled steps need eigenpairs: cliques of at most " +
                                     std::to_string(kMaxLdsClique) + " vertices");
@@ -1959,6 +2320,14 @@ cdcs_status cdcs_set_projection_plan(cdcs_handle *h, int32_t persistent, int32_t
     HIP_OK(hipDeviceSynchronize());
     for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     h->graphs.clear();
+    return CDCS_OK;
+}
+
+cdcs_status cdcs_hsde_history(const cdcs_handle *h, double *hist_host, int32_t n_host) {
+    if (!h || (!hist_host && n_host > 0)) return fail(CDCS_E_ARG, "NULL argument");
+    const int n = std::min<int>(n_host, std::min(h->last_iters, h->hs.hist_cap));
+    if (n <= 0) return CDCS_OK;
+    HIP_OK(hipMemcpy(hist_host, h->hs.hist, (size_t)n * 3 * sizeof(double), hipMemcpyDeviceToHost));
     return CDCS_OK;
 }
 

@@ -18,7 +18,8 @@ namespace cdcs {
 // several iterations becomes a no-op after convergence.
 struct Ctl {
     int32_t iter;       // completed iterations
-    int32_t stop;       // 0 running, 1 converged, 2 iteration cap, 3 NaN/Inf in the residuals
+    int32_t stop;       // 0 running, 1 converged, 2 iteration cap, 3 NaN/Inf in the residuals,
+                        // 4 / 5 primal / dual infeasibility certificate (HSDE)
     int32_t max_iter;
     int32_t jacobi_cap; // eigensolves that hit the sweep cap
     int32_t sweeps;     // Jacobi sweeps summed over all eigensolves
@@ -78,6 +79,13 @@ void launch_project_queue(const ProjArgs &a, int smax, int nthreads, int grid, u
                           hipStream_t s);
 // Resident workgroups per CU of the persistent launch.
 int project_queue_occupancy(int smax, int nthreads);
+
+// Vector cones: blocks of at most kVecChunk slots of a free or orthant cone,
+// or one whole second-order cone, one workgroup each (kernels_cones.hip).
+// vblk rows are (kind, first slot, end slot, cone); the blocks' residual
+// partial sums go to cpart rows cbase + b.
+constexpr int kVecChunk = 4096;
+void launch_project_vec(const ProjArgs &a, const int32_t *vblk, int nvb, int cbase, hipStream_t s);
 
 // Cliques above the LDS-resident limit (kMaxLdsClique vertices): projection
 // through the Newton-Schulz sign iteration on N x N blocks (kernels_big.hip).
@@ -165,6 +173,9 @@ struct Dev {
     // problem
     int32_t n = 0, m = 0, p = 0, smax = 0;
     int64_t nU = 0, nslots = 0;
+    int64_t nslots_psd = 0;        // slots of the cliques; the vector cones' slots follow
+    int32_t nvc = 0, nvb = 0;      // vector cones and their work blocks
+    int32_t *vblk = nullptr;       // [nvb * 4] (kind, s0, s1, cone)
     int64_t ldU = 0;               // row stride of Aw (nU rounded up to 64)
     int64_t ldM = 0;               // row stride of AwT (m rounded up to 32; 4 on batch handles)
     int32_t *clq_size = nullptr;   // [p]
@@ -221,7 +232,7 @@ struct Dev {
     double *y1 = nullptr;          // [m]
     float *dslot = nullptr;        // [nslots] x_k(new) - x_k(old) of the last Alg. 1 projection, per slot
     uint32_t *wbits = nullptr;     // [(nU + 31) / 32] bit e: entry e is off the diagonal (w_e = 2)
-    double *cpart = nullptr;       // [p * 4]
+    double *cpart = nullptr;       // [(p + nvb) * 4]
     double *spart = nullptr;       // [nsblk * 2]
     double *vpart = nullptr;       // [nvblk * 5]
     double *hist = nullptr;        // [hist_cap * 2]
@@ -247,8 +258,40 @@ void launch_baffine(const Dev &d, const double *r2, double r2scale, double *x, d
 void launch_bsetup(const Dev &d, double *M, hipStream_t s);
 void launch_bobjectives(const Dev &d, const double *x, const double *y, double *out, hipStream_t s);
 
+// Homogeneous self-dual embedding (kernels_hsde.hip): per-handle data, built
+// at the first HSDE call.  sc: [0] h^T g, [1] <c, g_x>_w, [2] ||b||,
+// [3] ||c||_w, [4] ut (tau row of the last linear step), [5] tau - ut,
+// [6] ||A(x) - tau b||^2, [7] ||A(x)||^2, [8] b^T y, [9] <c, x>_w,
+// [10..12] the solved test's ratios of the last check.
+struct HsdeDev {
+    double *invE = nullptr, *s2E = nullptr;  // [ldU] 1 / E, 1 / (w E), E = 1 + D
+    double *gx = nullptr;                     // [ldU] g_x (internal entry order)
+    double *gy = nullptr;                     // [ldM] g_y
+    double *a = nullptr;                      // [ldU] x rows of the linear step
+    double *yh = nullptr;                     // [ldM] y rows of the linear step
+    double *dx = nullptr;                     // [ldU] x(previous) - x
+    double *sc = nullptr;                     // [16]
+    double *hpart = nullptr;                  // [scatter_blocks * 2]
+    double *dpart = nullptr;                  // [hsde_dot_blocks]
+    double *hist = nullptr;                   // [3 * hist_cap] res_pri, res_dual, gap per iteration
+    int32_t hist_cap = 0;
+};
+int hsde_dot_blocks(const Dev &d);
+void launch_hsde_scales(const Dev &d, const HsdeDev &hs, hipStream_t s);
+void launch_hsde_cu(const Dev &d, const HsdeDev &hs, hipStream_t s);
+void launch_hsde_consts(const Dev &d, const HsdeDev &hs, hipStream_t s);
+void launch_hsde_init(const Dev &d, double *x, double *y, float *sl, float *z, double *tk, hipStream_t s);
+void launch_hsde_scatter(const Dev &d, const HsdeDev &hs, const float *sl, const float *z, const double *tk,
+                         hipStream_t s);
+void launch_hsde_check(const Dev &d, const HsdeDev &hs, const double *tk, hipStream_t s);
+void launch_hsde_tau(const Dev &d, const HsdeDev &hs, double *y, double *tk, hipStream_t s);
+void launch_hsde_axpy(const Dev &d, const HsdeDev &hs, hipStream_t s);
+void launch_hsde_solution(const Dev &d, const HsdeDev &hs, int which, const double *x, const double *y,
+                          const double *tk, double *X, double *Y, hipStream_t s);
+
 // scatter / residual / affine kernels
 int scatter_blocks(const Dev &d);
+int scatter_light_blocks(const Dev &d);
 int heavy_threshold();
 int vupdate_blocks(const Dev &d);
 void launch_reset_ctl(const Dev &d, int max_iter, double tol, hipStream_t s);
@@ -325,7 +368,8 @@ struct SpFactor {
     double *diag0 = nullptr;            // [m] diagonal of M (factor order)
     double *xv = nullptr;               // [nnzX] values of X
 };
-void launch_spchol_fill(const Dev &d, const SpFactor &f, const int32_t *tid, hipStream_t s);
+// shift: added to the diagonal of M (0 for A D^-1 A^T, 1 for the HSDE matrix I + A E^-1 A^T)
+void launch_spchol_fill(const Dev &d, const SpFactor &f, const int32_t *tid, double shift, hipStream_t s);
 void launch_spchol(const Dev &d, const SpFactor &f, const std::vector<int32_t> &level_off, int32_t *info,
                    hipStream_t s);
 int spinv_max_path();
@@ -336,6 +380,7 @@ void launch_syrk(const float *Aw, int64_t ld, const double *s2, int m, double *M
 // M (zeroed, m x m) = sum over coefficients of a sparse A; tid[q] = touched-entry index of sp_col[q]
 void launch_sp_syrk(const Dev &d, const int32_t *tid, double *M, hipStream_t s);
 void launch_potrf(double *M, int m, double *diag0, int32_t *info, hipStream_t s);
+void launch_add_diag(double *M, int m, double shift, hipStream_t s);
 void launch_trtri(const double *L, int m, double *LinvT, double *Linv, hipStream_t s);
 // Nonzeros of each row of a dense m x m triangle (lower: columns <= row,
 // upper: columns >= row) -> cnt[m]; then the CSR copy given ptr[m+1].

@@ -727,11 +727,13 @@ void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, dou
 }
 
 void launch_check_primal(const Dev &d, double rho, hipStream_t s) {
-    if (d.p + scatter_blocks(d) > 8192)
-        hipLaunchKernelGGL(k_check_primal<1024>, dim3(1), dim3(1024), 0, s, (const double *)d.cpart, d.p,
+    // partial sums of the cliques, then of the vector cones' blocks
+    const int ncp = d.p + d.nvb;
+    if (ncp + scatter_blocks(d) > 8192)
+        hipLaunchKernelGGL(k_check_primal<1024>, dim3(1), dim3(1024), 0, s, (const double *)d.cpart, ncp,
                            (const double *)d.spart, scatter_blocks(d), rho, d.hist, d.hist_cap, d.ctl);
     else
-        hipLaunchKernelGGL(k_check_primal<kNT>, dim3(1), dim3(kNT), 0, s, (const double *)d.cpart, d.p,
+        hipLaunchKernelGGL(k_check_primal<kNT>, dim3(1), dim3(kNT), 0, s, (const double *)d.cpart, ncp,
                            (const double *)d.spart, scatter_blocks(d), rho, d.hist, d.hist_cap, d.ctl);
 }
 

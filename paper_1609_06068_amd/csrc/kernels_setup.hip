@@ -77,6 +77,11 @@ __global__ void k_copy_diag(const double *__restrict__ M, int m, double *__restr
     if (i < m) d[i] = M[(int64_t)i * m + i];
 }
 
+__global__ void k_add_diag(double *__restrict__ M, int m, double shift) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) M[(int64_t)i * m + i] += shift;
+}
+
 // Unblocked Cholesky of the diagonal block [kb, kb+nb)^2 (lower) in LDS.
 // A pivot <= 2^-40 times the original diagonal flags rank deficiency
 // (info[0] = 1, info[1] = row) and is replaced by 1 to keep the rest finite.
@@ -342,6 +347,10 @@ void launch_syrk(const float *Aw, int64_t ld, const double *s2, int m, double *M
     hipLaunchKernelGGL(k_syrk, dim3(T * (T + 1) / 2), dim3(256), 0, s, Aw, ld, s2, m, M);
 }
 
+void launch_add_diag(double *M, int m, double shift, hipStream_t s) {
+    hipLaunchKernelGGL(k_add_diag, dim3((m + 255) / 256), dim3(256), 0, s, M, m, shift);
+}
+
 void launch_potrf(double *M, int m, double *diag0, int32_t *info, hipStream_t s) {
     hipLaunchKernelGGL(k_copy_diag, dim3((m + 255) / 256), dim3(256), 0, s, (const double *)M, m, diag0);
     for (int kb = 0; kb < m; kb += NB) {
@@ -403,8 +412,8 @@ __global__ __launch_bounds__(256) void k_spchol_fill(const int32_t *__restrict__
                                                      const int32_t *__restrict__ tc_ptr,
                                                      const int32_t *__restrict__ tc_row,
                                                      const double *__restrict__ tc_val,
-                                                     const double *__restrict__ s2, int m, double *__restrict__ Lv,
-                                                     double *__restrict__ diag0) {
+                                                     const double *__restrict__ s2, double shift, int m,
+                                                     double *__restrict__ Lv, double *__restrict__ diag0) {
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= m) return;
     const int32_t c0 = cp[j], c1 = cp[j + 1];
@@ -425,6 +434,7 @@ __global__ __launch_bounds__(256) void k_spchol_fill(const int32_t *__restrict__
             Lv[lo] += a * tc_val[u];
         }
     }
+    Lv[c0] += shift;  // the diagonal leads the column
     diag0[j] = Lv[c0];
 }
 
@@ -528,11 +538,11 @@ __global__ __launch_bounds__(256) void k_gather_vals(const double *__restrict__ 
 
 }  // namespace
 
-void launch_spchol_fill(const Dev &d, const SpFactor &f, const int32_t *tid, hipStream_t s) {
+void launch_spchol_fill(const Dev &d, const SpFactor &f, const int32_t *tid, double shift, hipStream_t s) {
     hipLaunchKernelGGL(k_spchol_fill, dim3((d.m + 255) / 256), dim3(256), 0, s, f.cp, f.ri, f.order, f.pinv,
                        (const int32_t *)d.sp_ptr, (const int32_t *)d.sp_col, (const double *)d.sp_val, tid,
                        (const int32_t *)d.tc_ptr, (const int32_t *)d.tc_row, (const double *)d.tc_val,
-                       (const double *)d.s2, d.m, f.Lv, f.diag0);
+                       (const double *)d.s2, shift, d.m, f.Lv, f.diag0);
 }
 
 void launch_spchol(const Dev &d, const SpFactor &f, const std::vector<int32_t> &level_off, int32_t *info,

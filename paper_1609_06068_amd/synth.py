@@ -670,18 +670,20 @@ def sdp_infeasible(seed: int = 7101) -> Problem:
 
 
 def sdp_unbounded(seed: int = 7102) -> Problem:
-    """The C1-shaped block-arrow SDP with every constraint's coefficient on
-    the diagonal entry of vertex 0 set to zero and C_00 = -1: X0 + t e_0 e_0^T
-    stays feasible for every t >= 0 while <C, X> decreases without bound
-    (dual infeasible)."""
+    """The C1-shaped block-arrow SDP with every constraint's coefficients on
+    the diagonal entries of block 0's vertices (0..9) set to zero, C = -1 on
+    those entries and C = A*(y0 / 20) + Z0 elsewhere: X0 + t D with D the
+    identity on block 0's vertices stays feasible for every t >= 0 while
+    <C, X> decreases without bound (dual infeasible).  The smaller y0 keeps
+    the ray's cost (-10 for ||D||_F = sqrt(10)) a sizeable part of ||C||."""
     p = block_arrow(10, 10, 5, 50, seed)
-    e00 = int(np.nonzero((p.ei == 0) & (p.ej == 0))[0][0])
+    ray = np.nonzero((p.ei == p.ej) & (p.ei < 10))[0]
     A = p.A.copy()
-    A[:, e00] = 0.0
+    A[:, ray] = 0.0
     w = np.where(p.ei == p.ej, 1.0, 2.0)
-    c = p.c.copy()
-    c[e00] = -1.0
+    c = A.T @ (p.meta["y0"] / 20.0) + p.meta["z0"]
+    c[ray] = -1.0
     out = Problem(**{**p.__dict__})
     out.A, out.b, out.c = A, A @ (w * p.meta["x0"]), c
-    out.meta = {**p.meta, "kind": "sdp_unbounded", "ray_entry": e00}
+    out.meta = {**p.meta, "kind": "sdp_unbounded", "ray_entries": ray}
     return out

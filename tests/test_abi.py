@@ -60,7 +60,8 @@ _STRUCTS = {
     "cdcs_pattern": cdcs._Pattern, "cdcs_cliques": cdcs._Cliques, "cdcs_constraints": cdcs._Constraints,
     "cdcs_options": cdcs._Options, "cdcs_info": cdcs._Info, "cdcs_state": cdcs._State,
     "cdcs_problem": cdcs._Problem, "cdcs_instance_info": cdcs._InstanceInfo, "cdcs_tuning": cdcs._Tuning,
-    "cdcs_sizes": cdcs._Sizes,
+    "cdcs_sizes": cdcs._Sizes, "cdcs_vcones": cdcs._Vcones, "cdcs_hsde_state": cdcs._HsdeState,
+    "cdcs_hsde_info": cdcs._HsdeInfo,
 }
 
 
