@@ -276,7 +276,7 @@ def _pool_solve(i):
     """Worker of the many-SDP oracle leg: one instance on one thread."""
     from threadpoolctl import threadpool_limits
     with threadpool_limits(limits=1):
-        _POOL["oracles"][i].solve("primal", rho=_POOL["rho"], max_iter=_POOL["iters"])
+        _POOL["oracles"][i].solve(_POOL["form"], rho=_POOL["rho"], max_iter=_POOL["iters"])
     return i
 
 
@@ -292,7 +292,7 @@ def oracle_pool_child(spec):
     from paper_1609_06068_amd import synth
     qs = [int(v) for v in spec["instances"].split(",")]
     _POOL["oracles"] = [orc.Oracle(synth.c4(count=1, first=q)[0]) for q in qs]
-    _POOL["rho"], _POOL["iters"] = spec["rho"], spec["iters"]
+    _POOL["rho"], _POOL["iters"], _POOL["form"] = spec["rho"], spec["iters"], spec.get("form", "primal")
     orc.lib()
     with get_context("fork").Pool(spec["workers"]) as pool:
         t0 = time.perf_counter()
@@ -301,11 +301,11 @@ def oracle_pool_child(spec):
     print(json.dumps({"seconds": sec, "workers": spec["workers"]}), flush=True)
 
 
-def pool_leg(sample, rho, n_it, workers):
+def pool_leg(sample, rho, n_it, workers, form="primal"):
     """Seconds of the all-threads many-SDP oracle leg (a child process)."""
     import subprocess
     spec = json.dumps({"instances": ",".join(str(q) for q in sample), "rho": rho, "iters": n_it,
-                       "workers": workers})
+                       "workers": workers, "form": form})
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--oracle-pool", spec],
                        capture_output=True, text=True, timeout=600)
     if r.returncode != 0:
@@ -500,6 +500,110 @@ def run_single(args, torch, workload, nested=False):
     return result
 
 
+def run_hsde(args, torch, workload):
+    """The homogeneous self-dual embedding solver on a single-SDP workload:
+    HSDE iterations/s over exactly K timed iterations (graphs captured before
+    the timer), a cold solve to 1e-4 (outcome, iterations, objectives beside
+    Algorithm 1's), per-kernel averages from an instrumented replay of the
+    timed iterations, the oracle's HSDE on the host and parity after 50
+    iterations."""
+    import numpy as np
+    from paper_1609_06068_amd import cdcs, synth
+    spec = SINGLE[workload]
+    _log(f"generating workload {workload}")
+    prob = synth.c2() if workload == "c2" else synth.c3()
+    t0 = time.perf_counter()
+    sol = cdcs.Solver(prob)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    cap = 1 if args.profile else 4 * spec["acc_cap"]
+    st = sol.new_hsde_state()
+    acc = sol.hsde_solve(st, tol=1e-4, max_iter=cap, check_every=GRAPH_CHUNK)
+    torch.cuda.synchronize()
+    _log(f"HSDE to 1e-4: status {acc.status}, {acc.iters} iterations, {acc.loop_s:.4f}s, "
+         f"objectives {acc.obj_primal:.6f} / {acc.obj_dual:.6f}")
+    ref1 = None
+    if not args.profile:
+        s1 = sol.new_state("primal")
+        ref1 = sol.solve(s1, form="primal", tol=1e-4, max_iter=spec["acc_cap"], check_every=GRAPH_CHUNK)
+    # timed region: W warm-up iterations, graphs for K captured on the state
+    # (then the state is restored), exactly K iterations timed
+    K, W = args.steps, args.warmup
+    stt = sol.new_hsde_state()
+    if W > 0:
+        sol.hsde_solve(stt, tol=0.0, max_iter=W, check_every=GRAPH_CHUNK)
+    start = snapshot(stt)
+    sol.hsde_solve(stt, tol=0.0, max_iter=K, check_every=GRAPH_CHUNK)
+    for k in stt:
+        stt[k].copy_(start[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    info = sol.hsde_solve(stt, tol=0.0, max_iter=K, check_every=GRAPH_CHUNK)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    assert info.iters == K, info
+    ips = K / elapsed
+    _log(f"timed: {K} HSDE iterations in {elapsed:.4f}s -> {ips:.1f} it/s")
+    rep = snapshot(start)
+    _, times = sol.hsde_solve_timed(rep, tol=0.0, max_iter=K)
+    same = all(torch.equal(rep[k], stt[k]) for k in ("x", "y", "s", "z", "tk"))
+    kern_ms = {n: ms / cnt for n, (ms, cnt) in times.items() if cnt > 0}
+    abytes = algorithmic_bytes(sol, prob)
+    kern = {n: {"us": kern_ms[n] * 1e3, "GB_s": abytes[n] / (kern_ms[n] * 1e-3) / 1e9} for n in kern_ms}
+    _log("kernels: " + ", ".join(f"{n} {v['us']:.1f}us {v['GB_s']:.0f}GB/s" for n, v in kern.items()))
+    roofline = roofline_for(kern_ms, abytes, sol.sizes, None)
+    result = base_result(ips, "HSDE iterations/s", K, W, 1e3 * elapsed / K,
+                         spec["desc"] + ", homogeneous self-dual embedding (no over-relaxation)",
+                         {"graph_chunk": GRAPH_CHUNK, "setup_s": setup_s, "n": sol.n, "nnz": sol.nnz,
+                          "p": sol.p, "m": sol.m})
+    result.update({
+        "accuracy": {"tol": 1e-4, "cap": cap, "status": cdcs.STATUS_NAMES.get(acc.status, acc.status),
+                     "iters_to_tol": acc.iters, "time_to_tol_s": acc.loop_s, "res_pri": acc.res_pri,
+                     "res_dual": acc.res_dual, "gap": acc.gap, "obj_primal": acc.obj_primal,
+                     "obj_dual": acc.obj_dual,
+                     "algorithm_1": None if ref1 is None else {"iters_to_tol": ref1.iters,
+                                                               "obj_primal": ref1.obj_primal,
+                                                               "obj_dual": ref1.obj_dual}},
+        "kernels": kern,
+        "kernels_replay_bitwise": same,
+        "roofline": roofline,
+    })
+    if not (args.no_cpu or args.profile):
+        from oracle import oracle as orc
+        n_cpu = args.cpu_iters if args.cpu_iters is not None else spec["cpu_iters"]
+        h = orc.Hsde(prob)
+        keep = {}
+
+        def at50(it, x, y, z, s_, tau, kappa):
+            if it == 50:
+                keep.update(x=x.copy(), y=y.copy(), z=[B.copy() for B in z], s=[B.copy() for B in s_], tau=tau,
+                            kappa=kappa)
+
+        _log(f"oracle HSDE ({n_cpu} iterations)")
+        cpu, _ = cpu_legs(lambda: h.solve(max_iter=n_cpu, tol=0.0, callback=at50), n_cpu, "HSDE iterations/s",
+                          f"first {n_cpu} HSDE iterations of the same solve (setup excluded)")
+        result["cpu_baseline"] = cpu
+        if keep:
+            sp = sol.new_hsde_state()
+            sol.hsde_solve(sp, tol=0.0, max_iter=50, check_every=GRAPH_CHUNK)
+
+            def packed(blocks):
+                return np.concatenate([B[np.tril_indices(B.shape[0])] if B.ndim == 2 else B for B in blocks])
+
+            sw = np.sqrt(h.dec.w)
+            par = {"iterations": 50, "tol": 1e-4,
+                   "x_rel": rel(sp["x"].cpu().numpy() * sw, keep["x"] * sw),
+                   "y_rel": rel(sp["y"].cpu().numpy(), keep["y"]),
+                   "s_rel": rel(sp["s"].cpu().numpy(), packed(keep["s"])),
+                   "z_rel": rel(sp["z"].cpu().numpy(), packed(keep["z"])),
+                   "tau_rel": rel([sp["tk"][0].item()], [keep["tau"]])}
+            par["pass"] = max(v for k, v in par.items() if k.endswith("_rel")) <= 1e-4
+            result["parity"] = par
+            _log(f"HSDE parity at 50 iterations: {par}")
+    sol.close()
+    return result
+
+
 # --------------------------------------------------------------------------
 # Many SDPs in one handle (c4)
 # --------------------------------------------------------------------------
@@ -508,6 +612,8 @@ def run_many(args, torch, nested=False):
     import numpy as np
     from paper_1609_06068_amd import cdcs, synth
     rho = 1.0
+    form = args.form
+    alg = "Alg. 1" if form == "primal" else "Alg. 2"
     _log("generating 512 block-arrow instances")
     probs = synth.c4()
     t0 = time.perf_counter()
@@ -517,9 +623,9 @@ def run_many(args, torch, nested=False):
     _log(f"setup {setup_s:.2f}s  nnz={sol.nnz} m={sol.m} p={sol.p}")
     # cold solves to 1e-4, every instance stopping on its own
     cap = 1 if args.profile else 3000
-    st = sol.new_state("primal")
-    sol.prepare(st, form="primal", rho=rho, tol=1e-4, max_iter=cap, check_every=GRAPH_CHUNK)
-    acc = sol.solve(st, form="primal", rho=rho, tol=1e-4, max_iter=cap, check_every=GRAPH_CHUNK)
+    st = sol.new_state(form)
+    sol.prepare(st, form=form, rho=rho, tol=1e-4, max_iter=cap, check_every=GRAPH_CHUNK)
+    acc = sol.solve(st, form=form, rho=rho, tol=1e-4, max_iter=cap, check_every=GRAPH_CHUNK)
     torch.cuda.synchronize()
     inst = sol.instance_info()
     t2t = np.array([i.time_to_tol_s for i in inst])
@@ -532,12 +638,12 @@ def run_many(args, torch, nested=False):
     _log(f"projection plan: {tuning}")
     # Timed region: exactly K whole-batch iterations (no early exit).
     K, W = args.steps, args.warmup
-    info, elapsed, start, stt = timed_solve(torch, sol, "primal", rho, K, W)
+    info, elapsed, start, stt = timed_solve(torch, sol, form, rho, K, W)
     ips = K / elapsed
     _log(f"timed: {K} batch iterations in {elapsed:.4f}s -> {ips:.1f} it/s")
     result = base_result(ips, "ADMM iterations/s (all 512 instances)", K, W, 1e3 * elapsed / K,
                          "512 independent block-arrow SDPs, l in 5..40, d in 8..32, h in 2..12, m = 5 l, "
-                         "one handle, Alg. 1, rho=1",
+                         f"one handle, {alg}, rho=1",
                          {"graph_chunk": GRAPH_CHUNK, "setup_s": setup_s, "p": sol.p, "m": sol.m, "nnz": sol.nnz})
     result.update({
         "clique_projections_per_s": ips * sol.p,
@@ -552,7 +658,7 @@ def run_many(args, torch, nested=False):
     })
     # per-kernel averages over the timed iterations: projection, scatter, whole
     # affine step (the gemv_Au kind of a batch handle)
-    kms, replay_same = replay_kernel_ms(torch, sol, start, stt, "primal", rho, K)
+    kms, replay_same = replay_kernel_ms(torch, sol, start, stt, form, rho, K)
     kern = {"project": {"us": kms["project"] * 1e3}, "scatter": {"us": kms["scatter"] * 1e3},
             "affine": {"us": kms["gemv_Au"] * 1e3}}
     # algorithmic bytes of the affine step: A_q read twice (FP32, rows of ld_q),
@@ -594,10 +700,10 @@ def run_many(args, torch, nested=False):
         # n_cpu iterations of the sampled instances stand for n_cpu |sample| / 512
         # iterations of the whole batch
         units = n_cpu * len(sample) / len(probs)
-        refs, s1 = oracle_timed(lambda: [o.solve("primal", rho=rho, max_iter=n_cpu) for o in oracles], 1)
+        refs, s1 = oracle_timed(lambda: [o.solve(form, rho=rho, max_iter=n_cpu) for o in oracles], 1)
         nall = all_threads()
         try:
-            sn = pool_leg(sample, rho, n_cpu, nall)
+            sn = pool_leg(sample, rho, n_cpu, nall, form)
         except Exception as exc:  # the single-thread figure still stands
             _log(f"oracle all-threads leg failed: {exc}")
             sn = None
@@ -616,8 +722,8 @@ def run_many(args, torch, nested=False):
                 "kind": "oracle", "sample": f"{smp}, one thread ({s1:.1f}s)",
                 "cpu_model": host_cpu(), "os_cpu_count": os.cpu_count()}
         # parity: the batch after 50 iterations from a cold state, per sampled instance
-        sp = sol.new_state("primal")
-        sol.solve(sp, form="primal", rho=rho, tol=0.0, max_iter=n_cpu, check_every=GRAPH_CHUNK)
+        sp = sol.new_state(form)
+        sol.solve(sp, form=form, rho=rho, tol=0.0, max_iter=n_cpu, check_every=GRAPH_CHUNK)
         xg = sp["x"].cpu().numpy()
         blk = sp["blk"].cpu().numpy().astype(np.float64)
         lam = sp["lam"].cpu().numpy().astype(np.float64)
@@ -708,7 +814,8 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
-    ap.add_argument("--form", default="primal", choices=["primal", "dual"])
+    ap.add_argument("--form", default="primal", choices=["primal", "dual", "hsde"],
+                    help="Algorithm 1, Algorithm 2, or the homogeneous self-dual embedding (c2, c3)")
     ap.add_argument("--cpu-iters", type=int, default=None, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -743,7 +850,12 @@ def main():
             torch.mul(xp, 2.0, out=yp)
         torch.cuda.synchronize()
         del xp, yp
-    if args.workload in SINGLE:
+    if args.form == "hsde":
+        if args.workload not in SINGLE:
+            print(json.dumps({"error": "--form hsde runs on the single-SDP workloads c2 and c3"}), flush=True)
+            sys.exit(2)
+        result = run_hsde(args, torch, args.workload)
+    elif args.workload in SINGLE:
         result = run_single(args, torch, args.workload)
         if args.workload == "c2" and not (args.only_headline or args.profile):
             result["c3"] = run_single(args, torch, "c3", nested=True)

@@ -591,6 +591,15 @@ cdcs_status cdcs_hsde_solve(cdcs_handle *h, const cdcs_hsde_state *st, const cdc
 cdcs_status cdcs_hsde_solution(cdcs_handle *h, const cdcs_hsde_state *st, int32_t which, double *X_out,
                                double *y_out, hipStream_t stream);
 
+/* cdcs_hsde_solve with eager launches and HIP events around each kernel kind
+ * of every iteration, as cdcs_admm_solve_timed does for Algorithms 1 and 2
+ * (kinds: the projection, the A u partials, the triangular products, A^T y,
+ * the scatter; the tau row, the update of x and the check run unbracketed).
+ * The iterates are those of cdcs_hsde_solve with the same state and options.
+ * Errors: those of cdcs_hsde_solve; CDCS_E_ARG for NULL kernel_ms or launches. */
+cdcs_status cdcs_hsde_solve_timed(cdcs_handle *h, const cdcs_hsde_state *st, const cdcs_options *opts,
+                                  cdcs_hsde_info *info, double *kernel_ms, int64_t *launches, hipStream_t stream);
+
 /* Residual history of the last HSDE solve: n_host triples (res_pri,
  * res_dual, gap) of the solved test, one per iteration, host. */
 cdcs_status cdcs_hsde_history(const cdcs_handle *h, double *hist_host, int32_t n_host);

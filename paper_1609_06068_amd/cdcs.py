@@ -33,7 +33,8 @@ EXPORTS = ["cdcs_setup", "cdcs_setup_batch", "cdcs_batch_info", "cdcs_get_sizes"
            "cdcs_residual_history", "cdcs_warm_reset", "cdcs_destroy", "cdcs_last_error", "cdcs_admm_prepare",
            "cdcs_psd_project_cliques", "cdcs_unrolled_step", "cdcs_unrolled_step_vjp",
            "cdcs_affine_project_adjoint", "cdcs_chordal_extension", "cdcs_affine_project_adjoint_noalloc",
-           "cdcs_setup_cones", "cdcs_hsde_init", "cdcs_hsde_solve", "cdcs_hsde_solution", "cdcs_hsde_history"]
+           "cdcs_setup_cones", "cdcs_hsde_init", "cdcs_hsde_solve", "cdcs_hsde_solution", "cdcs_hsde_history",
+           "cdcs_hsde_solve_timed"]
 
 
 class CdcsLibraryMissing(ImportError):
@@ -139,6 +140,7 @@ def load_library(path: str = LIB_PATH):
     L.cdcs_hsde_solve.argtypes = [vp, P(_HsdeState), P(_Options), P(_HsdeInfo), vp]
     L.cdcs_hsde_solution.argtypes = [vp, P(_HsdeState), i32, vp, vp, vp]
     L.cdcs_hsde_history.argtypes = [vp, vp, i32]
+    L.cdcs_hsde_solve_timed.argtypes = [vp, P(_HsdeState), P(_Options), P(_HsdeInfo), vp, vp, vp]
     L.cdcs_setup_batch.argtypes = [i32, P(_Problem), vp, vp, P(vp)]
     L.cdcs_batch_info.argtypes = [vp, i32, P(_InstanceInfo)]
     L.cdcs_get_sizes.argtypes = [vp, P(_Sizes)]
@@ -420,6 +422,22 @@ class Solver:
             _check(r, "cdcs_hsde_solve")
         return HsdeInfo(info.iters, info.status, info.jacobi_cap_hits, info.res_pri, info.res_dual, info.gap,
                         info.obj_primal, info.obj_dual, info.tau, info.kappa, info.loop_s, info.jacobi_sweeps)
+
+    def hsde_solve_timed(self, st: dict, tol: float = 0.0, max_iter: int = 500, stream=None):
+        """cdcs_hsde_solve_timed: (HsdeInfo, {kernel name: (total ms, launches)})."""
+        opts = _Options(1.0, float(tol), int(max_iter), 0, 0)
+        info = _HsdeInfo()
+        hs = self._hstate(st)
+        ms = np.zeros(5, dtype=np.float64)
+        n = np.zeros(5, dtype=np.int64)
+        r = load_library().cdcs_hsde_solve_timed(self._h, ctypes.byref(hs), ctypes.byref(opts), ctypes.byref(info),
+                                                 ms.ctypes.data, n.ctypes.data, _stream(self._torch, stream))
+        if r not in (OK, E_NOT_CONVERGED, E_NUMERIC, PRIMAL_INFEASIBLE, DUAL_INFEASIBLE):
+            _check(r, "cdcs_hsde_solve_timed")
+        names = ("project", "gemv_Au", "trmv", "gemv_ATy", "scatter")
+        return (HsdeInfo(info.iters, info.status, info.jacobi_cap_hits, info.res_pri, info.res_dual, info.gap,
+                         info.obj_primal, info.obj_dual, info.tau, info.kappa, info.loop_s, info.jacobi_sweeps),
+                {names[k]: (float(ms[k]), int(n[k])) for k in range(5)})
 
     def hsde_solution(self, st: dict, which: int = 0, stream=None):
         """(X, y_sdp) for which=0, the Farkas y for which=1, the ray X for which=2

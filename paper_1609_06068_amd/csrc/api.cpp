@@ -1998,8 +1998,9 @@ cdcs_status cdcs_hsde_init(cdcs_handle *h, const cdcs_hsde_state *st, hipStream_
     return CDCS_OK;
 }
 
-cdcs_status cdcs_hsde_solve(cdcs_handle *h, const cdcs_hsde_state *st, const cdcs_options *opts, cdcs_hsde_info *info,
-                            hipStream_t stream) {
+namespace {
+cdcs_status hsde_solve_impl(cdcs_handle *h, const cdcs_hsde_state *st, const cdcs_options *opts,
+                            cdcs_hsde_info *info, hipStream_t stream, IterTimer *tm) {
     CK(hsde_check_state(h, st));
     if (!opts) return fail(CDCS_E_ARG, "NULL argument");
     if (!(opts->tol >= 0.0) || opts->max_iter < 1 || opts->check_every < 0)
@@ -2028,7 +2029,7 @@ cdcs_status cdcs_hsde_solve(cdcs_handle *h, const cdcs_hsde_state *st, const cdc
     launch_perm_in(d, st->x, d.xi, stream);
     HIP_OK(hipGetLastError());
     const auto t0 = std::chrono::steady_clock::now();
-    const int K = opts->check_every;
+    const int K = tm ? 0 : opts->check_every;
     if (K > 0) {
         hipGraphExec_t full = nullptr, tail = nullptr;
         if (opts->max_iter >= K) CK(get_graph(h, &sti, kFormHsde, K, 1.0, &full));
@@ -2042,12 +2043,14 @@ cdcs_status cdcs_hsde_solve(cdcs_handle *h, const cdcs_hsde_state *st, const cdc
             if (d.ctl_host->stop) break;
         }
     } else {
+        const int group = tm ? IterTimer::kGroup : 16;
         for (int it = 0; it < opts->max_iter; ++it) {
-            enqueue_iteration(h, &sti, kFormHsde, 1.0, stream);
+            enqueue_iteration(h, &sti, kFormHsde, 1.0, stream, tm);
             HIP_OK(hipGetLastError());
-            if ((it + 1) % 16 == 0) {
+            if ((it + 1) % group == 0 || (tm && it + 1 == opts->max_iter)) {
                 HIP_OK(hipMemcpyAsync(d.ctl_host, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
                 HIP_OK(hipStreamSynchronize(stream));
+                if (tm) HIP_OK(tm->collect());
                 if (d.ctl_host->stop) break;
             }
         }
@@ -2095,6 +2098,25 @@ cdcs_status cdcs_hsde_solve(cdcs_handle *h, const cdcs_hsde_state *st, const cdc
     else if (status == CDCS_DUAL_INFEASIBLE)
         g_err = "dual infeasible (certificate in x)";
     return status;
+}
+}  // namespace
+
+cdcs_status cdcs_hsde_solve(cdcs_handle *h, const cdcs_hsde_state *st, const cdcs_options *opts, cdcs_hsde_info *info,
+                            hipStream_t stream) {
+    return hsde_solve_impl(h, st, opts, info, stream, nullptr);
+}
+
+cdcs_status cdcs_hsde_solve_timed(cdcs_handle *h, const cdcs_hsde_state *st, const cdcs_options *opts,
+                                  cdcs_hsde_info *info, double *kernel_ms, int64_t *launches, hipStream_t stream) {
+    if (!kernel_ms || !launches) return fail(CDCS_E_ARG, "NULL kernel_ms or launches");
+    IterTimer tm;
+    HIP_OK(tm.init());
+    const cdcs_status r = hsde_solve_impl(h, st, opts, info, stream, &tm);
+    for (int k = 0; k < IterTimer::kPerIter; ++k) {
+        kernel_ms[k] = tm.ms[k];
+        launches[k] = tm.n[k];
+    }
+    return r;
 }
 
 cdcs_status cdcs_hsde_solution(cdcs_handle *h, const cdcs_hsde_state *st, int32_t which, double *X_out,

@@ -200,3 +200,21 @@ def test_errors(torch):
         sol.hsde_solution(st, 3)
     assert e.value.status == cdcs.E_ARG
     sol.close()
+
+
+def test_timed_solve_same_iterates(torch):
+    """The instrumented HSDE solve launches the same kernels eagerly: it ends
+    on the graph-captured solve's iterates bit for bit and brackets every
+    kernel kind once per iteration."""
+    prob = synth.c3_small()
+    sol = cdcs.Solver(prob)
+    a = sol.new_hsde_state()
+    b = sol.new_hsde_state()
+    sol.hsde_solve(a, tol=0.0, max_iter=23, check_every=10)
+    info, times = sol.hsde_solve_timed(b, tol=0.0, max_iter=23)
+    assert info.iters == 23
+    for k in ("x", "y", "s", "z", "tk"):
+        assert torch.equal(a[k], b[k]), k
+    for name, (ms, n) in times.items():
+        assert n == 23 and ms > 0.0, name
+    sol.close()
