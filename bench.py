@@ -330,7 +330,23 @@ SINGLE = {
     "c3": dict(desc="clique-tree SDP, 3000 cliques of 4..96 (separators 1..8), m=8000 sparse A "
                     "(20 coefficients per constraint)",
                acc_cap=6000, cpu_iters=2, traffic="traffic_c3.json"),
+    "big": dict(desc="clique-tree SDP, 40 cliques of 127..330 (separators 1..8), m=2000 sparse A "
+                     "(20 coefficients per constraint), cliques projected by the matrix sign function",
+                acc_cap=3000, cpu_iters=1, traffic=None),
 }
+
+
+def make_single(workload):
+    from paper_1609_06068_amd import synth
+    return {"c2": synth.c2, "c3": synth.c3, "big": synth.c3_big}[workload]()
+
+
+def sign_function_flops(sizes):
+    """FP32 flops of the large-clique projection: kNs = 48 Newton-Schulz
+    steps of two k x k products (4 k^3) and the final product W (I + S) (2 k^3)."""
+    import numpy as np
+    k = np.asarray(sizes, dtype=np.float64)
+    return float(np.sum((4.0 * 48 + 2.0) * k ** 3))
 
 
 def timed_solve(torch, sol, form, rho, K, W):
@@ -394,7 +410,7 @@ def run_single(args, torch, workload, nested=False):
     spec = SINGLE[workload]
     form, rho = args.form, 1.0
     _log(f"generating workload {workload}")
-    prob = synth.c2() if workload == "c2" else synth.c3()
+    prob = make_single(workload)
     t0 = time.perf_counter()
     sol = cdcs.Solver(prob)
     torch.cuda.synchronize()
@@ -414,7 +430,7 @@ def run_single(args, torch, workload, nested=False):
     # Timed region: warmup, then exactly K iterations (no early exit).
     K, W = args.steps, args.warmup
     info, elapsed, start, stt = timed_solve(torch, sol, form, rho, K, W)
-    sweeps_per_solve = info.jacobi_sweeps / (K * sol.p)
+    sweeps_per_solve = info.jacobi_sweeps / (K * sol.p)  # 0 when every clique takes the sign function
     ips = K / elapsed
     _log(f"timed: {K} iterations in {elapsed:.4f}s -> {ips:.1f} it/s, {sweeps_per_solve:.2f} sweeps/eigensolve")
 
@@ -422,9 +438,17 @@ def run_single(args, torch, workload, nested=False):
     abytes = algorithmic_bytes(sol, prob)
     kern = {n: {"us": kern_ms[n] * 1e3, "GB_s": abytes[n] / (kern_ms[n] * 1e-3) / 1e9} for n in kern_ms}
     _log("kernels: " + ", ".join(f"{n} {v['us']:.1f}us {v['GB_s']:.0f}GB/s" for n, v in kern.items()))
-    batched = None if args.profile else batched_vs_plain(torch, sol, st, rho)
-    tfile = os.path.join(ROOT, "profiles", spec["traffic"])
+    # (the clique-per-launch form exists for cliques of the LDS path only)
+    batched = None if (args.profile or workload == "big") else batched_vs_plain(torch, sol, st, rho)
+    tfile = os.path.join(ROOT, "profiles", spec["traffic"]) if spec["traffic"] else None
     roofline = roofline_for(kern_ms, abytes, sol.sizes, tfile)
+    if workload == "big":
+        # every clique above the LDS limit: the projection is FP32 products on the matrix cores
+        fl = sign_function_flops(sol.sizes)
+        ach = fl / (kern_ms["project"] * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "kernel": "project (sign function)", "achieved": ach,
+                    "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP32_VALU_PEAK_TFLOPS,
+                    "traffic": None, "algorithmic_flops": fl, "avg_us": kern_ms["project"] * 1e3}
     result = base_result(ips, "ADMM iterations/s", K, W, 1e3 * elapsed / K,
                          spec["desc"] + (", Alg. 1 (primal)" if form == "primal" else ", Alg. 2 (dual)") + ", rho=1",
                          {"graph_chunk": GRAPH_CHUNK, "setup_s": setup_s, "n": sol.n, "nnz": sol.nnz,
@@ -459,7 +483,7 @@ def run_single(args, torch, workload, nested=False):
         if not args.profile:
             result["parity"] = golden_parity(torch, sol, rho)
 
-    if workload == "c2" and not (args.no_cpu or args.profile):
+    if workload in ("c2", "big") and not (args.no_cpu or args.profile):
         from oracle import oracle as orc
         n_cpu = args.cpu_iters if args.cpu_iters is not None else spec["cpu_iters"]
         o = orc.Oracle(prob)
@@ -477,11 +501,12 @@ def run_single(args, torch, workload, nested=False):
         # carries the eigenvector warm start, so this equals one solve)
         par = {"tol": 1e-4}
         sp = sol.new_state(form)
+        done = 0
         for n_it, r in ((50, snap), (n_cpu, {"x": ref.x, "blocks": ref.blocks, "lam": ref.lam})):
-            done = 0 if n_it == 50 else 50
             if not r or n_it <= done:
                 continue
             sol.solve(sp, form=form, rho=rho, tol=0.0, max_iter=n_it - done, check_every=GRAPH_CHUNK)
+            done = n_it
             xg = sp["x"].cpu().numpy()
             blk = sp["blk"].cpu().numpy().astype(np.float64)
             lam = sp["lam"].cpu().numpy().astype(np.float64)
@@ -511,7 +536,7 @@ def run_hsde(args, torch, workload):
     from paper_1609_06068_amd import cdcs, synth
     spec = SINGLE[workload]
     _log(f"generating workload {workload}")
-    prob = synth.c2() if workload == "c2" else synth.c3()
+    prob = make_single(workload)
     t0 = time.perf_counter()
     sol = cdcs.Solver(prob)
     torch.cuda.synchronize()
@@ -813,7 +838,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "big"])
     ap.add_argument("--form", default="primal", choices=["primal", "dual", "hsde"],
                     help="Algorithm 1, Algorithm 2, or the homogeneous self-dual embedding (c2, c3)")
     ap.add_argument("--cpu-iters", type=int, default=None, help="oracle iterations timed for cpu_baseline")

@@ -18,8 +18,15 @@
 //
 // Layout: each large clique c has an N x N row-major FP32 block (N = its size
 // rounded up to 64, zero padded) in four buffers: W, two iterates and one
-// product; launches cover every large clique at once (grid: 64 x 64 output
-// tiles x cliques), and all reductions are fixed-order (no atomics).
+// product; launches cover every large clique at once (grid: 64 x 64 tiles x
+// cliques), and all reductions are fixed-order (no atomics).  Every matrix of
+// the iteration is a polynomial in W, so all of them are symmetric and all
+// products commute: a launch computes only the tiles on and below the
+// diagonal, T (T + 1) / 2 of the T^2, and writes each off-diagonal tile to
+// its mirror position as well (the diagonal tiles keep their lower triangle
+// and mirror it), so every matrix of the iteration is exactly symmetric.
+#include <cmath>
+
 #include "cdcs_internal.h"
 
 namespace cdcs {
@@ -48,6 +55,15 @@ __device__ __forceinline__ double block_sum0(double v, double *red) {
     return r;
 }
 
+// Lower tile t (row-major over ti >= tj) -> (ti, tj).
+__device__ __forceinline__ void lower_tile(int t, int &ti, int &tj) {
+    int i = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    while (i * (i + 1) / 2 > t) --i;
+    ti = i;
+    tj = t - i * (i + 1) / 2;
+}
+
 __device__ __forceinline__ bool big_skip(const ProjArgs &a, int id) {
     if (a.ctl != nullptr && a.ctl->stop) return true;
     return a.istop != nullptr && a.istop[a.kinst[id]];
@@ -62,8 +78,9 @@ __global__ __launch_bounds__(kNT) void k_big_gather(ProjArgs a, BigCliques b) {
     if (big_skip(a, id)) return;
     const int n = b.n[c], N = b.N[c], T = N / kTile;
     const int t = blockIdx.x;
-    if (t >= T * T) return;
-    const int ti = t / T, tj = t - ti * T;
+    if (t >= T * (T + 1) / 2) return;
+    int ti, tj;
+    lower_tile(t, ti, tj);
     const int64_t off = a.off[id];
     float *W = b.W + b.boff[c];
     double s2 = 0.0;
@@ -78,10 +95,12 @@ __global__ __launch_bounds__(kNT) void k_big_gather(ProjArgs a, BigCliques b) {
             else w = (float)((double)a.v[g] - (double)a.lam[g] * a.inv_rho);
         }
         W[(int64_t)i * N + j] = w;
+        if (ti != tj) W[(int64_t)j * N + i] = w;
         s2 += (double)w * (double)w;
     }
     s2 = block_sum0(s2, red);
-    if (threadIdx.x == 0) b.part[(int64_t)c * b.tmax2 + t] = s2;
+    // an off-diagonal tile stands for its mirror too
+    if (threadIdx.x == 0) b.part[(int64_t)c * b.tmax2 + t] = (ti != tj) ? 2.0 * s2 : s2;
 }
 
 // ||W||_F from the tile partials (in tile order); 1 / ||W||_F for the scaling.
@@ -91,7 +110,7 @@ __global__ __launch_bounds__(64) void k_big_norm(ProjArgs a, BigCliques b) {
     const int T = b.N[c] / kTile;
     if (threadIdx.x == 0) {
         double s = 0.0;
-        for (int t = 0; t < T * T; ++t) s += b.part[(int64_t)c * b.tmax2 + t];
+        for (int t = 0; t < T * (T + 1) / 2; ++t) s += b.part[(int64_t)c * b.tmax2 + t];
         const double fro = sqrt(s);
         b.inv_norm[c] = fro > 0.0 ? 1.0 / fro : 0.0;
     }
@@ -109,25 +128,30 @@ __global__ __launch_bounds__(kNT) void k_big_scale(ProjArgs a, BigCliques b) {
     for (int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x; e < NN; e += (int64_t)gridDim.x * kNT) X[e] = W[e] * sc;
 }
 
-// One 64 x 64 tile of C = A B for every large clique (N x N blocks, N a
-// multiple of 64), on v_mfma_f32_16x16x4_f32: wave w computes the 32 x 32
-// quadrant (w / 2, w % 2) as 2 x 2 instruction tiles, with 16-deep slices of
-// A and B staged in LDS.  Epilogue EPI: 0: C = A B; 1 (a Newton-Schulz step,
-// A = X, B = X^2): C = 1.5 A - 0.5 A B; 2 (the projection, A = W, B =
-// sign(W)): C = (A + A B) / 2.  Operand layout of the instruction (lane l):
-// A[l % 16][l / 16], B[l / 16][l % 16]; result element r at
-// D[(l / 16) * 4 + r][l % 16].
+// One 64 x 64 tile (on or below the diagonal) of C = A B for every large
+// clique (N x N blocks, N a multiple of 64), on v_mfma_f32_16x16x4_f32: wave
+// w computes the 32 x 32 quadrant (w / 2, w % 2) as 2 x 2 instruction tiles.
+// 32-deep slices of A and B are staged in LDS; the next slice's global loads
+// are issued before the current slice's products, so they overlap.  An
+// off-diagonal tile is also written to its mirror position.  Epilogue EPI:
+// 0: C = A B; 1 (a Newton-Schulz step, A = X, B = X^2): C = 1.5 A - 0.5 A B;
+// 2 (the projection, A = W, B = sign(W)): C = (A + A B) / 2.  Operand layout
+// of the instruction (lane l): A[l % 16][l / 16], B[l / 16][l % 16]; result
+// element r at D[(l / 16) * 4 + r][l % 16].  The upper triangle is written
+// as the mirror of the lower one (also inside the diagonal tiles).
+constexpr int kK = 32;
 template <int EPI>
 __global__ __launch_bounds__(kNT) void k_big_gemm(ProjArgs a, BigCliques b, const float *__restrict__ Ab,
                                                   const float *__restrict__ Bb, float *__restrict__ Cb) {
-    __shared__ float As[kTile][17];
-    __shared__ float Bs[16][kTile + 1];
+    __shared__ float As[kTile][kK + 1];
+    __shared__ float Bs[kK][kTile + 1];
     const int c = blockIdx.y;
     if (big_skip(a, b.ids[c])) return;
     const int N = b.N[c], T = N / kTile;
     const int t = blockIdx.x;
-    if (t >= T * T) return;
-    const int ti = t / T, tj = t - ti * T;
+    if (t >= T * (T + 1) / 2) return;
+    int ti, tj;
+    lower_tile(t, ti, tj);
     const int64_t o = b.boff[c];
     const float *A = Ab + o, *B = Bb + o;
     float *C = Cb + o;
@@ -138,20 +162,31 @@ __global__ __launch_bounds__(kNT) void k_big_gemm(ProjArgs a, BigCliques b, cons
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    const int ar = tid >> 2, ac = (tid & 3) * 4;   // A slice: 64 rows x 16 columns, 4 per thread
-    const int br = tid >> 4, bc = (tid & 15) * 4;  // B slice: 16 rows x 64 columns, 4 per thread
-    for (int k0 = 0; k0 < N; k0 += 16) {
-        const f32x4 av = *reinterpret_cast<const f32x4 *>(A + (int64_t)(ti * kTile + ar) * N + k0 + ac);
-        const f32x4 bv = *reinterpret_cast<const f32x4 *>(B + (int64_t)(k0 + br) * N + tj * kTile + bc);
-        __syncthreads();
+    const int ar = tid >> 2, ac = (tid & 3) * 8;   // A slice: 64 rows x 32 columns, 8 per thread
+    const int br = tid >> 3, bc = (tid & 7) * 8;   // B slice: 32 rows x 64 columns, 8 per thread
+    const float *pa = A + (int64_t)(ti * kTile + ar) * N + ac;
+    const float *pb = B + (int64_t)br * N + tj * kTile + bc;
+    f32x4 av0 = *reinterpret_cast<const f32x4 *>(pa), av1 = *reinterpret_cast<const f32x4 *>(pa + 4);
+    f32x4 bv0 = *reinterpret_cast<const f32x4 *>(pb), bv1 = *reinterpret_cast<const f32x4 *>(pb + 4);
+    for (int k0 = 0; k0 < N; k0 += kK) {
+        __syncthreads();  // the previous slice's products are done with LDS
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            As[ar][ac + q] = av[q];
-            Bs[br][bc + q] = bv[q];
+            As[ar][ac + q] = av0[q];
+            As[ar][ac + 4 + q] = av1[q];
+            Bs[br][bc + q] = bv0[q];
+            Bs[br][bc + 4 + q] = bv1[q];
         }
         __syncthreads();
+        if (k0 + kK < N) {  // next slice in flight during this slice's products
+            const float *qa = pa + k0 + kK, *qb = pb + (int64_t)(k0 + kK) * N;
+            av0 = *reinterpret_cast<const f32x4 *>(qa);
+            av1 = *reinterpret_cast<const f32x4 *>(qa + 4);
+            bv0 = *reinterpret_cast<const f32x4 *>(qb);
+            bv1 = *reinterpret_cast<const f32x4 *>(qb + 4);
+        }
 #pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
+        for (int kk = 0; kk < kK; kk += 4) {
             float am[2], bm[2];
 #pragma unroll
             for (int mi = 0; mi < 2; ++mi) am[mi] = As[qr * 32 + mi * 16 + (lane & 15)][kk + (lane >> 4)];
@@ -164,6 +199,12 @@ __global__ __launch_bounds__(kNT) void k_big_gemm(ProjArgs a, BigCliques b, cons
                     acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[mi], bm[ni], acc[mi][ni], 0, 0, 0);
         }
     }
+    // Only the lower triangle is kept and mirrored, the diagonal tiles' too:
+    // the computed A B is symmetric only up to rounding, and a matrix whose
+    // diagonal tiles kept their own upper triangles next to mirrored
+    // off-diagonal tiles is not symmetric; the Newton-Schulz map does not damp
+    // an antisymmetric part (it grew to 2e-3 of X over 48 steps in a host
+    // emulation of that mix, against 3e-7 for the exactly symmetric one).
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -172,34 +213,40 @@ __global__ __launch_bounds__(kNT) void k_big_gemm(ProjArgs a, BigCliques b, cons
             for (int r = 0; r < 4; ++r) {
                 const int row = ti * kTile + qr * 32 + mi * 16 + (lane >> 4) * 4 + r;
                 const int col = tj * kTile + qc * 32 + ni * 16 + (lane & 15);
+                if (row < col) continue;
                 const int64_t e = (int64_t)row * N + col;
                 const float v = acc[mi][ni][r];
-                if (EPI == 0) C[e] = v;
-                else if (EPI == 1) C[e] = 1.5f * A[e] - 0.5f * v;
-                else C[e] = 0.5f * (A[e] + v);
+                float out;
+                if (EPI == 0) out = v;
+                else if (EPI == 1) out = 1.5f * A[e] - 0.5f * v;
+                else out = 0.5f * (A[e] + v);
+                C[e] = out;
+                if (row > col) C[(int64_t)col * N + row] = out;
             }
 }
 
 // The projection's epilogue for large cliques, as for the LDS-resident ones:
 // P (symmetrised) to the packed outputs, the multiplier update of Algorithm 1
-// and the residual partial sums (fixed order), one workgroup per clique.
+// and per-tile residual partial sums (grid: lower tiles x cliques; the slots
+// (i, j), j <= i, of a tile).
 __global__ __launch_bounds__(kNT) void k_big_epilogue(ProjArgs a, BigCliques b, const float *__restrict__ Pb) {
     __shared__ double red[kNT / 64];
-    const int c = blockIdx.x;
+    const int c = blockIdx.y;
     const int id = b.ids[c];
     if (big_skip(a, id)) return;
-    const int n = b.n[c], N = b.N[c];
+    const int n = b.n[c], N = b.N[c], T = N / kTile;
+    const int t = blockIdx.x;
+    if (t >= T * (T + 1) / 2) return;
+    int ti, tj;
+    lower_tile(t, ti, tj);
     const float *P = Pb + b.boff[c];
     const int64_t off = a.off[id];
-    const int nslot = n * (n + 1) / 2;
     double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-    for (int s = threadIdx.x; s < nslot; s += kNT) {
-        int i = (int)((sqrt(8.0 * (double)s + 1.0) - 1.0) * 0.5);
-        while ((i + 1) * (i + 2) / 2 <= s) ++i;
-        while (i * (i + 1) / 2 > s) --i;
-        const int j = s - i * (i + 1) / 2;
+    for (int e = threadIdx.x; e < kTile * kTile; e += kNT) {
+        const int i = ti * kTile + e / kTile, j = tj * kTile + e % kTile;
+        if (i >= n || j > i) continue;
         const float pv32 = 0.5f * (P[(int64_t)i * N + j] + P[(int64_t)j * N + i]);
-        const int64_t g = off + s;
+        const int64_t g = off + (int64_t)i * (i + 1) / 2 + j;
         if (a.mode == PROJ_STANDALONE) {
             a.Pout[g] = pv32;
         } else if (a.mode == PROJ_PRIMAL) {
@@ -222,10 +269,31 @@ __global__ __launch_bounds__(kNT) void k_big_epilogue(ProjArgs a, BigCliques b, 
         p1 = block_sum0(p1, red);
         p2 = block_sum0(p2, red);
         if (threadIdx.x == 0) {
-            a.cpart[4 * (int64_t)id + 0] = p0;
-            a.cpart[4 * (int64_t)id + 1] = p1;
-            a.cpart[4 * (int64_t)id + 2] = p2;
+            double *q = b.part + 3 * ((int64_t)c * b.tmax2 + t);
+            q[0] = p0;
+            q[1] = p1;
+            q[2] = p2;
         }
+    }
+}
+
+// The residual partial sums of each large clique from its tiles (tile order).
+__global__ __launch_bounds__(64) void k_big_epi_sum(ProjArgs a, BigCliques b) {
+    const int c = blockIdx.x;
+    const int id = b.ids[c];
+    if (big_skip(a, id) || a.mode != PROJ_PRIMAL) return;
+    const int T = b.N[c] / kTile;
+    if (threadIdx.x == 0) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int t = 0; t < T * (T + 1) / 2; ++t) {
+            const double *q = b.part + 3 * ((int64_t)c * b.tmax2 + t);
+            s0 += q[0];
+            s1 += q[1];
+            s2 += q[2];
+        }
+        a.cpart[4 * (int64_t)id + 0] = s0;
+        a.cpart[4 * (int64_t)id + 1] = s1;
+        a.cpart[4 * (int64_t)id + 2] = s2;
     }
 }
 
@@ -233,7 +301,8 @@ __global__ __launch_bounds__(kNT) void k_big_epilogue(ProjArgs a, BigCliques b, 
 
 void launch_big_projection(const ProjArgs &a, const BigCliques &b, hipStream_t s) {
     if (b.nbig <= 0) return;
-    const dim3 tiles((unsigned)b.tmax2, (unsigned)b.nbig);
+    const int tm = (int)std::lround(std::sqrt((double)b.tmax2));
+    const dim3 tiles((unsigned)(tm * (tm + 1) / 2), (unsigned)b.nbig);
     hipLaunchKernelGGL(k_big_gather, tiles, dim3(kNT), 0, s, a, b);
     hipLaunchKernelGGL(k_big_norm, dim3((unsigned)b.nbig), dim3(64), 0, s, a, b);
     hipLaunchKernelGGL(k_big_scale, dim3(64, (unsigned)b.nbig), dim3(kNT), 0, s, a, b);
@@ -246,7 +315,8 @@ void launch_big_projection(const ProjArgs &a, const BigCliques &b, hipStream_t s
     }
     hipLaunchKernelGGL(k_big_gemm<2>, tiles, dim3(kNT), 0, s, a, b, (const float *)b.W,
                        (const float *)X[kNsSteps & 1], b.Y);
-    hipLaunchKernelGGL(k_big_epilogue, dim3((unsigned)b.nbig), dim3(kNT), 0, s, a, b, (const float *)b.Y);
+    hipLaunchKernelGGL(k_big_epilogue, tiles, dim3(kNT), 0, s, a, b, (const float *)b.Y);
+    hipLaunchKernelGGL(k_big_epi_sum, dim3((unsigned)b.nbig), dim3(64), 0, s, a, b);
 }
 
 }  // namespace cdcs

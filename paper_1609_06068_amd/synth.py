@@ -266,6 +266,15 @@ def c3_small(instance: int = 0) -> Problem:
     return peo_chordal(seed=config_seed(3, 100 + instance), **C3_SMALL)
 
 
+# large cliques (the sizes of Table I's largest, 322/323): 40 cliques of
+# 127..330 vertices, projected by the matrix sign function
+C3_BIG = dict(p=40, smin=127, smax=330, omax=8, m=2000, nnz_row=20)
+
+
+def c3_big(instance: int = 0) -> Problem:
+    return peo_chordal(seed=config_seed(3, 200 + instance), **C3_BIG)
+
+
 def c5(instance: int = 0) -> Problem:
     return block_arrow(seed=config_seed(5, instance), **C5)
 
