@@ -134,7 +134,8 @@ typedef struct {
     double obj_primal;    /* <C, X> of the primal iterate */
     double obj_dual;      /* <b, y> of the dual iterate */
     double loop_s;        /* wall time of the iteration loop */
-    int64_t jacobi_sweeps; /* Jacobi sweeps summed over all eigensolves of the solve */
+    int64_t jacobi_sweeps; /* Jacobi sweeps summed over all eigensolves of the solve (and the
+                              Newton-Schulz steps of cliques above the LDS limit) */
 } cdcs_info;
 
 /* Caller-owned ADMM state (device memory).  Zero-filled state is the

@@ -504,8 +504,9 @@ cdcs_status upload_common(cdcs_handle *h, const std::vector<int32_t> &size, cons
         CK(h->alloc(&B.X0, boff.back()));
         CK(h->alloc(&B.X1, boff.back()));
         CK(h->alloc(&B.Y, boff.back()));
-        CK(h->alloc(&B.part, 3 * (int64_t)B.nbig * B.tmax2));
+        CK(h->alloc(&B.part, 4 * (int64_t)B.nbig * B.tmax2));
         CK(h->alloc(&B.inv_norm, B.nbig));
+        CK(h->alloc(&B.stop, B.nbig));
     }
     CK(upload(h, &d.clq_size, size, s));
     CK(upload(h, &d.clq_off, h->off_host, s));

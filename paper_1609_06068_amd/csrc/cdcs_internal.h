@@ -101,8 +101,9 @@ struct BigCliques {
     float *W = nullptr;            // [boff[nbig]] W, zero padded
     float *X0 = nullptr, *X1 = nullptr;  // Newton-Schulz iterates
     float *Y = nullptr;            // products; P at the end
-    double *part = nullptr;        // [3 * nbig * tmax2] per-tile partial sums
+    double *part = nullptr;        // [4 * nbig * tmax2] per-tile partial sums
     double *inv_norm = nullptr;    // [nbig] 1 / ||W||_F
+    int32_t *stop = nullptr;       // [nbig] Newton-Schulz step at which the clique stopped, -1 running
 };
 void launch_big_projection(const ProjArgs &a, const BigCliques &b, hipStream_t s);
 

@@ -9,9 +9,17 @@
 // eigenvalue s to s (3 - s^2) / 2: quadratically near +-1, by a factor 3/2
 // per step while |s| is small).  Every step is two products of k x k FP32
 // matrices on the matrix cores, tiled over many workgroups, so a large clique
-// is spread across the GPU.  A fixed number of steps, kNsSteps = 48, takes
-// every eigenvalue with |lambda| >= 2e-7 ||W||_F to within rounding of +-1;
-// a smaller eigenvalue contributes at most |lambda| / 2 to the error of P.
+// is spread across the GPU.  At most kNsSteps = 48 steps take every
+// eigenvalue with |lambda| >= 2e-7 ||W||_F to within rounding of +-1; a
+// smaller eigenvalue contributes at most |lambda| / 2 to the error of P.  A
+// clique stops earlier, after at least kNsMin = 20 steps, once a step changed
+// X by at most kNsTol = 3e-5 ||X||_F: then the next step's error is near FP32
+// rounding for the eigenvalues near +-1 (the convergence is quadratic there),
+// and an eigenvalue still in the linear phase (growing by 3/2 a step) has a
+// scaled size below 2 kNsTol sqrt(N) / 1.5^20 <= 3e-7, so it adds at most
+// that fraction of ||W||_F to the error of P, as the 48-step bound allows.
+// The step at which a clique stopped is recorded (stop[c]); its later
+// launches return at once and the final product reads X of that step.
 // (The product's FP32 rounding leaves X a few ulps off sign(W); each step
 // squares the previous deviation, so it does not accumulate.)  A NaN or Inf
 // in W reaches the residual sums, which report it.
@@ -55,6 +63,9 @@ __device__ __forceinline__ double block_sum0(double v, double *red) {
     return r;
 }
 
+constexpr int kNsMin = 20;
+constexpr double kNsTol2 = 9e-10;  // kNsTol^2
+
 // Lower tile t (row-major over ti >= tj) -> (ti, tj).
 __device__ __forceinline__ void lower_tile(int t, int &ti, int &tj) {
     int i = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
@@ -67,6 +78,22 @@ __device__ __forceinline__ void lower_tile(int t, int &ti, int &tj) {
 __device__ __forceinline__ bool big_skip(const ProjArgs &a, int id) {
     if (a.ctl != nullptr && a.ctl->stop) return true;
     return a.istop != nullptr && a.istop[a.kinst[id]];
+}
+
+// Whether clique c's Newton-Schulz iteration has stopped before step `step`:
+// at least kNsMin steps done and the last one moved X by at most kNsTol
+// ||X||_F (per-tile partial sums of that step, in tile order; the same
+// answer in every thread).  Partial sums alternate between two regions by
+// step parity, so a launch reads the previous step's while writing its own.
+__device__ __forceinline__ bool ns_stopped(const BigCliques &b, int c, int T, int step) {
+    if (step < kNsMin) return false;
+    const double *q = b.part + 4 * (int64_t)c * b.tmax2 + 2 * ((step - 1) & 1);
+    double d2 = 0.0, x2 = 0.0;
+    for (int t = 0; t < T * (T + 1) / 2; ++t) {
+        d2 += q[4 * t + 0];
+        x2 += q[4 * t + 1];
+    }
+    return d2 <= kNsTol2 * x2;
 }
 
 // W of clique c into its N x N block (both triangles, zero padding) from the
@@ -98,6 +125,7 @@ __global__ __launch_bounds__(kNT) void k_big_gather(ProjArgs a, BigCliques b) {
         if (ti != tj) W[(int64_t)j * N + i] = w;
         s2 += (double)w * (double)w;
     }
+    if (t == 0 && threadIdx.x == 0) b.stop[c] = -1;
     s2 = block_sum0(s2, red);
     // an off-diagonal tile stands for its mirror too
     if (threadIdx.x == 0) b.part[(int64_t)c * b.tmax2 + t] = (ti != tj) ? 2.0 * s2 : s2;
@@ -142,9 +170,11 @@ __global__ __launch_bounds__(kNT) void k_big_scale(ProjArgs a, BigCliques b) {
 constexpr int kK = 32;
 template <int EPI>
 __global__ __launch_bounds__(kNT) void k_big_gemm(ProjArgs a, BigCliques b, const float *__restrict__ Ab,
-                                                  const float *__restrict__ Bb, float *__restrict__ Cb) {
+                                                  const float *__restrict__ Bb, float *__restrict__ Cb, int step,
+                                                  const float *__restrict__ Xalt) {
     __shared__ float As[kTile][kK + 1];
     __shared__ float Bs[kK][kTile + 1];
+    __shared__ double red[kNT / 64];
     const int c = blockIdx.y;
     if (big_skip(a, b.ids[c])) return;
     const int N = b.N[c], T = N / kTile;
@@ -153,9 +183,18 @@ __global__ __launch_bounds__(kNT) void k_big_gemm(ProjArgs a, BigCliques b, cons
     int ti, tj;
     lower_tile(t, ti, tj);
     const int64_t o = b.boff[c];
-    const float *A = Ab + o, *B = Bb + o;
-    float *C = Cb + o;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int stopped = b.stop[c];  // step at which the clique stopped, or -1
+    if (EPI == 0 && stopped < 0 && ns_stopped(b, c, T, step)) {
+        if (t == 0 && tid == 0) b.stop[c] = step;  // X of this step (buffer step & 1) is the sign
+        return;
+    }
+    if (EPI != 2 && stopped >= 0) return;
+    // the final product reads X of the stopping step (the other buffer when
+    // that step had the other parity than kNsSteps)
+    const float *A = Ab + o, *B = ((EPI == 2 && stopped >= 0 && ((stopped ^ step) & 1)) ? Xalt : Bb) + o;
+    float *C = Cb + o;
+    double *np = b.part + 4 * ((int64_t)c * b.tmax2 + t) + 2 * (step & 1);  // this step's partial sums
     const int qr = w >> 1, qc = w & 1;
     f32x4 acc[2][2];
 #pragma unroll
@@ -199,6 +238,7 @@ __global__ __launch_bounds__(kNT) void k_big_gemm(ProjArgs a, BigCliques b, cons
                     acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[mi], bm[ni], acc[mi][ni], 0, 0, 0);
         }
     }
+    double d2 = 0.0, x2 = 0.0;  // EPI 1: ||X_new - X||^2 and ||X_new||^2 of the tile
     // Only the lower triangle is kept and mirrored, the diagonal tiles' too:
     // the computed A B is symmetric only up to rounding, and a matrix whose
     // diagonal tiles kept their own upper triangles next to mirrored
@@ -217,12 +257,30 @@ __global__ __launch_bounds__(kNT) void k_big_gemm(ProjArgs a, BigCliques b, cons
                 const int64_t e = (int64_t)row * N + col;
                 const float v = acc[mi][ni][r];
                 float out;
-                if (EPI == 0) out = v;
-                else if (EPI == 1) out = 1.5f * A[e] - 0.5f * v;
-                else out = 0.5f * (A[e] + v);
+                if (EPI == 0) {
+                    out = v;
+                } else if (EPI == 1) {
+                    const float x = A[e];
+                    out = 1.5f * x - 0.5f * v;
+                    const double wgt = row > col ? 2.0 : 1.0, dd = (double)out - (double)x;
+                    d2 += wgt * dd * dd;
+                    x2 += wgt * (double)out * (double)out;
+                } else {
+                    out = 0.5f * (A[e] + v);
+                }
                 C[e] = out;
                 if (row > col) C[(int64_t)col * N + row] = out;
             }
+    if (EPI == 1) {
+        d2 = block_sum0(d2, red);
+        x2 = block_sum0(x2, red);
+        if (tid == 0) {
+            np[0] = d2;
+            np[1] = x2;
+            // one Newton-Schulz step of this clique counted with the sweeps
+            if (t == 0 && a.ctl != nullptr) atomicAdd(&a.ctl->sweeps, 1);
+        }
+    }
 }
 
 // The projection's epilogue for large cliques, as for the LDS-resident ones:
@@ -309,12 +367,12 @@ void launch_big_projection(const ProjArgs &a, const BigCliques &b, hipStream_t s
     float *X[2] = {b.X0, b.X1};
     for (int t = 0; t < kNsSteps; ++t) {
         hipLaunchKernelGGL(k_big_gemm<0>, tiles, dim3(kNT), 0, s, a, b, (const float *)X[t & 1],
-                           (const float *)X[t & 1], b.Y);
+                           (const float *)X[t & 1], b.Y, t, (const float *)nullptr);
         hipLaunchKernelGGL(k_big_gemm<1>, tiles, dim3(kNT), 0, s, a, b, (const float *)X[t & 1],
-                           (const float *)b.Y, X[(t + 1) & 1]);
+                           (const float *)b.Y, X[(t + 1) & 1], t, (const float *)nullptr);
     }
     hipLaunchKernelGGL(k_big_gemm<2>, tiles, dim3(kNT), 0, s, a, b, (const float *)b.W,
-                       (const float *)X[kNsSteps & 1], b.Y);
+                       (const float *)X[kNsSteps & 1], b.Y, kNsSteps, (const float *)X[(kNsSteps + 1) & 1]);
     hipLaunchKernelGGL(k_big_epilogue, tiles, dim3(kNT), 0, s, a, b, (const float *)b.Y);
     hipLaunchKernelGGL(k_big_epi_sum, dim3((unsigned)b.nbig), dim3(64), 0, s, a, b);
 }
