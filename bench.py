@@ -330,6 +330,9 @@ SINGLE = {
     "c3": dict(desc="clique-tree SDP, 3000 cliques of 4..96 (separators 1..8), m=8000 sparse A "
                     "(20 coefficients per constraint)",
                acc_cap=6000, cpu_iters=2, traffic="traffic_c3.json"),
+    "lp": dict(desc="conic program with vector cones only: 4,000,000 orthant variables, a second-order cone of "
+                    "100,000, 10,000 free variables, m=8,000 sparse constraints (20 coefficients each)",
+               acc_cap=20000, cpu_iters=0, traffic=None),
     "big": dict(desc="clique-tree SDP, 40 cliques of 127..330 (separators 1..8), m=2000 sparse A "
                      "(20 coefficients per constraint), cliques projected by the matrix sign function",
                 acc_cap=3000, cpu_iters=1, traffic=None),
@@ -338,7 +341,7 @@ SINGLE = {
 
 def make_single(workload):
     from paper_1609_06068_amd import synth
-    return {"c2": synth.c2, "c3": synth.c3, "big": synth.c3_big}[workload]()
+    return {"c2": synth.c2, "c3": synth.c3, "big": synth.c3_big, "lp": synth.lp_big}[workload]()
 
 
 def sign_function_flops(sizes, steps_per_clique):
@@ -432,7 +435,8 @@ def run_single(args, torch, workload, nested=False):
     # Timed region: warmup, then exactly K iterations (no early exit).
     K, W = args.steps, args.warmup
     info, elapsed, start, stt = timed_solve(torch, sol, form, rho, K, W)
-    sweeps_per_solve = info.jacobi_sweeps / (K * sol.p)  # 0 when every clique takes the sign function
+    # 0 when every clique takes the sign function or there are no cliques
+    sweeps_per_solve = info.jacobi_sweeps / (K * sol.p) if sol.p > 0 else 0.0
     ips = K / elapsed
     _log(f"timed: {K} iterations in {elapsed:.4f}s -> {ips:.1f} it/s, {sweeps_per_solve:.2f} sweeps/eigensolve")
 
@@ -441,7 +445,7 @@ def run_single(args, torch, workload, nested=False):
     kern = {n: {"us": kern_ms[n] * 1e3, "GB_s": abytes[n] / (kern_ms[n] * 1e-3) / 1e9} for n in kern_ms}
     _log("kernels: " + ", ".join(f"{n} {v['us']:.1f}us {v['GB_s']:.0f}GB/s" for n, v in kern.items()))
     # (the clique-per-launch form exists for cliques of the LDS path only)
-    batched = None if (args.profile or workload == "big") else batched_vs_plain(torch, sol, st, rho)
+    batched = None if (args.profile or workload in ("big", "lp")) else batched_vs_plain(torch, sol, st, rho)
     tfile = os.path.join(ROOT, "profiles", spec["traffic"]) if spec["traffic"] else None
     roofline = roofline_for(kern_ms, abytes, sol.sizes, tfile)
     if workload == "big":
@@ -596,9 +600,9 @@ def run_hsde(args, torch, workload):
         "kernels_replay_bitwise": same,
         "roofline": roofline,
     })
-    if not (args.no_cpu or args.profile):
+    n_cpu = args.cpu_iters if args.cpu_iters is not None else spec["cpu_iters"]
+    if not (args.no_cpu or args.profile) and n_cpu > 0:
         from oracle import oracle as orc
-        n_cpu = args.cpu_iters if args.cpu_iters is not None else spec["cpu_iters"]
         h = orc.Hsde(prob)
         keep = {}
 
@@ -841,7 +845,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "big"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "big", "lp"])
     ap.add_argument("--form", default="primal", choices=["primal", "dual", "hsde"],
                     help="Algorithm 1, Algorithm 2, or the homogeneous self-dual embedding (c2, c3)")
     ap.add_argument("--cpu-iters", type=int, default=None, help="oracle iterations timed for cpu_baseline")

@@ -206,6 +206,7 @@ struct HostProblem {
     int64_t nslots_psd = 0;          // clique slots; the vector cones' slots follow
     int32_t nvc = 0;                 // vector cones
     std::vector<int32_t> vblk;       // [nvb * 4] (kind, s0, s1, cone) work blocks of the vector cones
+    std::vector<int32_t> soc;        // [nsoc * 3] (first slot, first block, end block) per second-order cone
 };
 
 // A CSR input is kept sparse when a dense FP32 copy would be read at more
@@ -329,13 +330,20 @@ cdcs_status host_problem(const cdcs_pattern *pat, const cdcs_constraints *A, con
                 P.gather[(size_t)g] = e;
                 ++P.cnt[(size_t)e];
             }
-            // work blocks: a second-order cone whole, the others in chunks
-            const int64_t step = kind == CDCS_CONE_SOC ? g - s0 : kVecChunk;
-            for (int64_t a = s0; a < g; a += step) {
+            // work blocks of at most kVecChunk slots; a second-order cone's
+            // blocks carry its index among the second-order cones
+            const int32_t b0 = (int32_t)(P.vblk.size() / 4);
+            const int32_t si = (int32_t)(P.soc.size() / 3);
+            for (int64_t a = s0; a < g; a += kVecChunk) {
                 P.vblk.push_back(kind);
                 P.vblk.push_back((int32_t)a);
-                P.vblk.push_back((int32_t)std::min(g, a + step));
-                P.vblk.push_back(q);
+                P.vblk.push_back((int32_t)std::min<int64_t>(g, a + kVecChunk));
+                P.vblk.push_back(kind == CDCS_CONE_SOC ? si : q);
+            }
+            if (kind == CDCS_CONE_SOC) {
+                P.soc.push_back((int32_t)s0);
+                P.soc.push_back(b0);
+                P.soc.push_back((int32_t)(P.vblk.size() / 4));
             }
         }
     }
@@ -854,6 +862,12 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
     d.nvc = P.nvc;
     d.nvb = (int32_t)(P.vblk.size() / 4);
     if (d.nvb > 0) CK(upload(h, &d.vblk, P.vblk, s));
+    d.nsoc = (int32_t)(P.soc.size() / 3);
+    if (d.nsoc > 0) {
+        CK(upload(h, &d.soc, P.soc, s));
+        CK(h->alloc(&d.soc_part, d.nvb));
+        CK(h->alloc(&d.soc_nt, 2 * (int64_t)d.nsoc));
+    }
     d.ldU = P.ld;
     d.ldM = round_up(P.m, 32);  // rows of A^T start on 128-byte lines
     h->off_host = P.off;
@@ -1222,7 +1236,7 @@ void launch_plan(cdcs_handle *h, ProjArgs a, hipStream_t s) {
 void launch_projection(cdcs_handle *h, int mode, const cdcs_state *st, double rho, hipStream_t s) {
     const ProjArgs a = proj_args(h, mode, st, rho);
     launch_plan(h, a, s);
-    launch_project_vec(a, h->d.vblk, h->d.nvb, h->d.p, s);  // vector cones, if any
+    launch_project_vec(a, h->d, s);  // vector cones, if any
 }
 
 int device_cus(cdcs_handle *h) {

@@ -80,12 +80,15 @@ void launch_project_queue(const ProjArgs &a, int smax, int nthreads, int grid, u
 // Resident workgroups per CU of the persistent launch.
 int project_queue_occupancy(int smax, int nthreads);
 
-// Vector cones: blocks of at most kVecChunk slots of a free or orthant cone,
-// or one whole second-order cone, one workgroup each (kernels_cones.hip).
-// vblk rows are (kind, first slot, end slot, cone); the blocks' residual
-// partial sums go to cpart rows cbase + b.
-constexpr int kVecChunk = 4096;
-void launch_project_vec(const ProjArgs &a, const int32_t *vblk, int nvb, int cbase, hipStream_t s);
+// Vector cones: blocks of at most kVecChunk slots, one workgroup each
+// (kernels_cones.hip).  vblk rows are (kind, first slot, end slot, cone; for
+// a second-order cone its index among those cones); the blocks' residual
+// partial sums go to cpart rows p + b.  A second-order cone's norm comes
+// first from per-block partial sums (soc_part), summed per cone in block
+// order (soc_nt: ||z||, t).
+constexpr int kVecChunk = 1024;
+struct Dev;
+void launch_project_vec(const ProjArgs &a, const Dev &d, hipStream_t s);
 
 // Cliques above the LDS-resident limit (kMaxLdsClique vertices): projection
 // through the Newton-Schulz sign iteration on N x N blocks (kernels_big.hip).
@@ -177,6 +180,10 @@ struct Dev {
     int64_t nslots_psd = 0;        // slots of the cliques; the vector cones' slots follow
     int32_t nvc = 0, nvb = 0;      // vector cones and their work blocks
     int32_t *vblk = nullptr;       // [nvb * 4] (kind, s0, s1, cone)
+    int32_t nsoc = 0;              // second-order cones
+    int32_t *soc = nullptr;        // [nsoc * 3] (first slot, first block, end block)
+    double *soc_part = nullptr;    // [nvb] per-block sums of z^2 (second-order cone blocks)
+    double *soc_nt = nullptr;      // [nsoc * 2] ||z||, t of each second-order cone
     int64_t ldU = 0;               // row stride of Aw (nU rounded up to 64)
     int64_t ldM = 0;               // row stride of AwT (m rounded up to 32; 4 on batch handles)
     int32_t *clq_size = nullptr;   // [p]

@@ -3,10 +3,11 @@
 // (the cone types other than PSD that CDCS accepts, Sec. IV), fused with the
 // same gather and multiplier epilogue as the clique projection kernel.
 //
-// Work units: a block of slots of one cone (orthant and free cones are cut
-// into chunks of at most kVecChunk slots, a second-order cone is one block:
-// its projection needs the norm of the whole z part).  One workgroup per
-// block.  Modes (ProjArgs.mode):
+// Work units: blocks of at most kVecChunk slots of one cone, one workgroup
+// each.  A second-order cone's projection needs the norm of its whole z part:
+// its blocks first write partial sums of z^2 (k_soc_partial), one thread per
+// cone adds them in block order and reads t (k_soc_finish), then every block
+// projects its slots.  Modes (ProjArgs.mode):
 //   PROJ_PRIMAL (Algorithm 1; the HSDE cone step with rho = 1):
 //     W = H_k x - lam / rho, x_k = P_K(W), lam += rho (x_k - H_k x), the slot
 //     difference x_k(new) - x_k(old), and the three residual partial sums
@@ -49,7 +50,40 @@ __device__ __forceinline__ double cone_input(const ProjArgs &a, int64_t g) {
     return (double)a.v[g] - l;
 }
 
-__global__ __launch_bounds__(kNT) void k_project_vec(ProjArgs a, const int32_t *__restrict__ vblk, int cbase) {
+// Partial sums of z^2 over a second-order cone's block (its first slot, t,
+// excluded).
+__global__ __launch_bounds__(kNT) void k_soc_partial(ProjArgs a, const int32_t *__restrict__ vblk,
+                                                     const int32_t *__restrict__ soc, double *__restrict__ part) {
+    __shared__ double red[kNT / 64];
+    if (a.ctl != nullptr && a.ctl->stop) return;
+    const int b = blockIdx.x;
+    if (vblk[4 * b + 0] != CDCS_CONE_SOC) return;
+    const int64_t first = soc[3 * vblk[4 * b + 3]];
+    const int64_t s0 = max<int64_t>(vblk[4 * b + 1], first + 1), s1 = vblk[4 * b + 2];
+    double z2 = 0.0;
+    for (int64_t g = s0 + threadIdx.x; g < s1; g += kNT) {
+        const double w = cone_input(a, g);
+        z2 += w * w;
+    }
+    z2 = block_sum(z2, red);
+    if (threadIdx.x == 0) part[b] = z2;
+}
+
+// ||z|| and t of every second-order cone (one thread per cone, blocks in order).
+__global__ __launch_bounds__(kNT) void k_soc_finish(ProjArgs a, const int32_t *__restrict__ soc, int nsoc,
+                                                    const double *__restrict__ part, double *__restrict__ nt) {
+    if (a.ctl != nullptr && a.ctl->stop) return;
+    const int q = blockIdx.x * kNT + threadIdx.x;
+    if (q >= nsoc) return;
+    double z2 = 0.0;
+    for (int b = soc[3 * q + 1]; b < soc[3 * q + 2]; ++b) z2 += part[b];
+    nt[2 * q + 0] = sqrt(z2);
+    nt[2 * q + 1] = cone_input(a, soc[3 * q]);
+}
+
+__global__ __launch_bounds__(kNT) void k_project_vec(ProjArgs a, const int32_t *__restrict__ vblk,
+                                                     const int32_t *__restrict__ soc, const double *__restrict__ nt,
+                                                     int cbase) {
     __shared__ double red[kNT / 64];
     if (a.ctl != nullptr && a.ctl->stop) return;
     const int b = blockIdx.x;
@@ -57,18 +91,14 @@ __global__ __launch_bounds__(kNT) void k_project_vec(ProjArgs a, const int32_t *
     const int64_t s0 = vblk[4 * b + 1], s1 = vblk[4 * b + 2];
     const int tid = threadIdx.x;
     const bool dual = (a.mode == PROJ_DUAL);
-    // second-order cone: t and ||z|| of the whole cone first
+    // second-order cone: ||z|| and t of the whole cone, and its first slot
     double t = 0.0, nz = 0.0;
+    int64_t first = -1;
     if (kind == CDCS_CONE_SOC) {
-        // every thread reads t before the reduction's barrier: the epilogue
-        // below overwrites the slot's multiplier
-        t = cone_input(a, s0);
-        double z2 = 0.0;
-        for (int64_t g = s0 + 1 + tid; g < s1; g += kNT) {
-            const double w = cone_input(a, g);
-            z2 += w * w;
-        }
-        nz = sqrt(block_sum(z2, red));
+        const int q = vblk[4 * b + 3];
+        nz = nt[2 * q + 0];
+        t = nt[2 * q + 1];
+        first = soc[3 * q];
     }
     double p0 = 0.0, p1 = 0.0, p2 = 0.0;
     for (int64_t g = s0 + tid; g < s1; g += kNT) {
@@ -84,7 +114,7 @@ __global__ __launch_bounds__(kNT) void k_project_vec(ProjArgs a, const int32_t *
             pv = 0.0;
         } else {
             const double h = 0.5 * (t + nz);
-            pv = (g == s0) ? h : (h / nz) * w;
+            pv = (g == first) ? h : (h / nz) * w;
         }
         const float pv32 = (float)pv;
         if (dual) {
@@ -116,9 +146,16 @@ __global__ __launch_bounds__(kNT) void k_project_vec(ProjArgs a, const int32_t *
 
 }  // namespace
 
-void launch_project_vec(const ProjArgs &a, const int32_t *vblk, int nvb, int cbase, hipStream_t s) {
-    if (nvb > 0 && a.mode != PROJ_STANDALONE)
-        hipLaunchKernelGGL(k_project_vec, dim3((unsigned)nvb), dim3(kNT), 0, s, a, vblk, cbase);
+void launch_project_vec(const ProjArgs &a, const Dev &d, hipStream_t s) {
+    if (d.nvb <= 0 || a.mode == PROJ_STANDALONE) return;
+    if (d.nsoc > 0) {
+        hipLaunchKernelGGL(k_soc_partial, dim3((unsigned)d.nvb), dim3(kNT), 0, s, a, (const int32_t *)d.vblk,
+                           (const int32_t *)d.soc, d.soc_part);
+        hipLaunchKernelGGL(k_soc_finish, dim3((unsigned)((d.nsoc + kNT - 1) / kNT)), dim3(kNT), 0, s, a,
+                           (const int32_t *)d.soc, d.nsoc, (const double *)d.soc_part, d.soc_nt);
+    }
+    hipLaunchKernelGGL(k_project_vec, dim3((unsigned)d.nvb), dim3(kNT), 0, s, a, (const int32_t *)d.vblk,
+                       (const int32_t *)d.soc, (const double *)d.soc_nt, d.p);
 }
 
 }  // namespace cdcs

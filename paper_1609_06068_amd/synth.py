@@ -696,3 +696,45 @@ def sdp_unbounded(seed: int = 7102) -> Problem:
     out.A, out.b, out.c = A, A @ (w * p.meta["x0"]), c
     out.meta = {**p.meta, "kind": "sdp_unbounded", "ray_entries": ray}
     return out
+
+
+def lp_sparse(nvar: int, m: int, nnz_row: int, seed: int, soc: int = 0, free: int = 0) -> Problem:
+    """Strictly feasible conic program with a sparse A: an orthant of nvar,
+    optionally a second-order cone of `soc` and a free cone of `free`
+    variables (no cliques).  Each constraint has nnz_row distinct uniform
+    variables with N(0,1) coefficients (FP32-representable, CSR); b = A x0,
+    c = A^T y0 + z0 with x0, z0 interior (z0 = 0 on the free variables)."""
+    rng = _rng(seed)
+    cones = [(CONE_ORTHANT, nvar)] + ([(CONE_SOC, soc)] if soc else []) + ([(CONE_FREE, free)] if free else [])
+    ei, ej, n, kinds, cptr, cvert, nv = _append_vector_vertices(np.empty(0, np.int32), np.empty(0, np.int32), 0,
+                                                                cones)
+    nU = ei.shape[0]
+    ptr = np.arange(m + 1, dtype=np.int64) * nnz_row
+    idx = np.empty(m * nnz_row, dtype=np.int32)
+    for i in range(m):
+        idx[i * nnz_row:(i + 1) * nnz_row] = np.sort(rng.choice(nU, size=nnz_row, replace=False))
+    val = _f32(rng.standard_normal(m * nnz_row))
+    x0 = np.empty(nU)
+    z0 = np.empty(nU)
+    for q, kind in enumerate(kinds):
+        ent = np.arange(cptr[q], cptr[q + 1])
+        x0[ent] = _interior_vector_point(rng, int(kind), ent.shape[0])
+        z0[ent] = _interior_vector_point(rng, int(kind), ent.shape[0], dual=True)
+    y0 = rng.standard_normal(m)
+    b = np.add.reduceat(val * x0[idx], ptr[:-1]) if m > 0 else np.empty(0)
+    c = z0.copy()
+    np.add.at(c, idx, val * np.repeat(y0, nnz_row))
+    return Problem(n=n, ei=ei, ej=ej, clique_ptr=np.zeros(1, np.int64), clique_vert=np.empty(0, np.int32), b=b,
+                   c=c, A=None, A_ptr=ptr, A_idx=idx, A_val=val, cone_kind=kinds, cone_ptr=cptr, cone_vert=cvert,
+                   meta={"kind": "lp_sparse", "seed": seed, "x0": x0, "y0": y0, "z0": z0})
+
+
+# a large conic program with vector cones only: 4 M orthant variables, a
+# second-order cone of 100,000 and 10,000 free variables, m = 8,000 sparse
+# constraints of 20 coefficients (few constraints share a variable, so the
+# factor stays sparse)
+LP_BIG = dict(nvar=4_000_000, m=8_000, nnz_row=20, soc=100_000, free=10_000)
+
+
+def lp_big(instance: int = 0) -> Problem:
+    return lp_sparse(seed=config_seed(6, instance), **LP_BIG)

@@ -107,8 +107,9 @@ def test_socp_closed_form(torch):
 
 
 def test_long_cones_several_blocks(torch):
-    """An orthant of 10,000 (three work blocks of at most 4096 slots), a
-    second-order cone of 3,000 (one block), a free cone of 20, no cliques."""
+    """An orthant of 10,000 and a second-order cone of 3,000 (several work
+    blocks of at most 1024 slots each; the cone's norm from per-block partial
+    sums), a free cone of 20, no cliques."""
     prob = synth.mixed_cones(0, 0, 0, 30, [(synth.CONE_ORTHANT, 10000), (synth.CONE_SOC, 3000),
                                             (synth.CONE_FREE, 20)], seed=7005)
     o = O.Oracle(prob)

@@ -4,7 +4,8 @@
   iterates x, x_k, lambda_k after 50 iterations of Algorithm 1 from zero
   (relative norm error <= 1e-4, and element by element within 1e-4 of the
   vector's RMS), and the converged objectives at max(eps_p, eps_d) <= 1e-4
-  (|obj_gpu - obj_ref| <= 1e-4 max(1, |obj_ref|)), the oracle running live.
+  (|obj_gpu - obj_ref| <= 1e-4 max(1, |obj_ref|)), the oracle running live;
+  the HSDE solver's iterates and residuals after 50 iterations, likewise.
 * Uneven-clique workload (3000 cliques of 4..96, m = 8000 sparse): the
   iterates after 50 iterations of Algorithms 1 and 2 against the golden the
   oracle wrote (tests/golden/c3_iter50.json, make_c3_iter50.py): sampled
@@ -70,6 +71,29 @@ def test_c2_iterates_after_50_iterations(torch, c2):
     hist = sol.history(50)
     assert np.allclose(hist[:, 0], ref.eps_p, rtol=1e-3, atol=0)
     assert np.allclose(hist[:, 1], ref.eps_d, rtol=1e-3, atol=0)
+
+
+def test_c2_hsde_iterates_after_50_iterations(torch, c2):
+    """The homogeneous self-dual embedding at the benchmark size: x, y, s, z,
+    tau, kappa after 50 iterations from the starting point and the
+    per-iteration residuals (library: from differences of iterates; oracle:
+    from their definitions) against the oracle run live."""
+    prob, _, sol = c2
+    h = O.Hsde(prob)
+    ref = h.solve(max_iter=50, tol=0.0)
+    st = sol.new_hsde_state()
+    info = sol.hsde_solve(st, tol=0.0, max_iter=50, check_every=50)
+    assert info.iters == 50 and info.jacobi_cap_hits == 0
+    sw = np.sqrt(h.dec.w)
+    assert _rel(st["x"].cpu().numpy() * sw, ref.x * sw) <= 1e-4
+    assert _rel(st["y"].cpu().numpy(), ref.y) <= 1e-4
+    assert _rel(st["s"].cpu().numpy().astype(np.float64), cdcs.pack_blocks(ref.s)) <= 1e-4
+    assert _rel(st["z"].cpu().numpy().astype(np.float64), cdcs.pack_blocks(ref.z)) <= 1e-4
+    tk = st["tk"].cpu().numpy()
+    assert abs(tk[0] - ref.tau) <= 1e-4 * max(ref.tau, 1e-3)
+    hist = sol.hsde_history(50)
+    for col, r in ((0, ref.res_pri), (1, ref.res_dual), (2, ref.gap)):
+        assert np.allclose(hist[:, col], r, rtol=1e-3, atol=1e-7), col
 
 
 def test_c2_converged_objective(torch, c2):
