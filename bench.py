@@ -175,10 +175,11 @@ def batched_vs_plain(torch, sol, state, rho):
 def roofline_for(kern_ms, abytes, sizes, traffic_file):
     """Roofline of the kernel that takes the most time per iteration; `traffic`
     is its counter-measured HBM bytes per launch while the counters were taken
-    on the current kernel sources."""
+    on the current kernel sources.  Without cliques the projection is the
+    vector cones' elementwise pass, bound by HBM."""
     dom = max(kern_ms, key=lambda n: kern_ms[n])
     traffic = counter_bytes(traffic_file, dom)
-    if dom == "project":
+    if dom == "project" and len(sizes) > 0:
         fl = projection_model_flops(sizes)
         ach = fl / (kern_ms[dom] * 1e-3) / 1e12
         return {"bound": "alu", "kernel": dom, "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
