@@ -490,6 +490,16 @@ def run_single(args, torch, workload, nested=False):
         result["projection_model_tflops"] = projection_model_flops(sol.sizes) / (kern_ms["project"] * 1e-3) / 1e12
         if not args.profile:
             result["parity"] = golden_parity(torch, sol, rho)
+            # the decomposition from the pattern alone (host): chordality test,
+            # maximal cliques; the generator's cliques are the exact answer
+            t0 = time.perf_counter()
+            fi, _, cptr, cvert = cdcs.chordal_extension(prob.n, prob.ei, prob.ej)
+            ext_s = time.perf_counter() - t0
+            same = (sorted(tuple(cvert[cptr[k]:cptr[k + 1]]) for k in range(len(cptr) - 1)) ==
+                    sorted(tuple(prob.clique(k)) for k in range(prob.p)))
+            result["chordal_extension"] = {"seconds": ext_s, "calls": 2, "fill": int(fi.shape[0]),
+                                           "cliques": int(len(cptr) - 1), "same_cliques_as_generator": bool(same)}
+            _log(f"chordal extension of the pattern: {result['chordal_extension']}")
 
     if workload in ("c2", "big") and not (args.no_cpu or args.profile):
         from oracle import oracle as orc
@@ -526,7 +536,7 @@ def run_single(args, torch, workload, nested=False):
     if nested:
         keep = ("value", "unit", "ms_per_step", "clique_projections_per_s", "jacobi_sweeps_per_eigensolve",
                 "accuracy", "batched_vs_plain", "projection_plan", "kernels", "kernels_replay_bitwise",
-                "gather_scatter", "roofline", "projection_model_tflops", "parity")
+                "gather_scatter", "roofline", "projection_model_tflops", "parity", "chordal_extension")
         out = {k: result[k] for k in keep if k in result}
         out["config"] = result["config"]
         return out
