@@ -164,3 +164,20 @@ def test_cone_validation_errors(torch):
                           1.0, ev, V)
     assert e.value.status == cdcs.E_ARG
     sol.close()
+
+
+@pytest.mark.parametrize("form", ["primal", "dual"])
+def test_sparse_a_with_cones_iterates_at_50(torch, form):
+    """Vector cones only, CSR constraints (the sparse-A kernels and the sparse
+    factor) and a second-order cone spread over several work blocks."""
+    prob = synth.lp_sparse(3000, 120, 10, seed=7007, soc=1500, free=40)
+    o = O.Oracle(prob)
+    ref = o.solve(form, rho=1.0, max_iter=50)
+    sol = cdcs.Solver(prob)
+    assert sol.sparse_a
+    st = sol.new_state(form)
+    sol.solve(st, form=form, tol=0.0, max_iter=50, check_every=10)
+    assert _wrel(st["x"].cpu().numpy(), ref.x, o.dec.w) <= 1e-4
+    assert _rel(st["blk"].cpu().numpy().astype(np.float64), _packed(o.dec, ref.blocks)) <= 1e-4
+    assert _rel(st["lam"].cpu().numpy().astype(np.float64), _packed(o.dec, ref.lam)) <= 1e-4
+    sol.close()

@@ -218,3 +218,27 @@ def test_timed_solve_same_iterates(torch):
     for name, (ms, n) in times.items():
         assert n == 23 and ms > 0.0, name
     sol.close()
+
+
+@pytest.mark.parametrize("which", ["sparse_cones", "large_cliques"])
+def test_iterates_at_20_other_paths(torch, which):
+    """HSDE iterates after 20 iterations on vector cones with CSR constraints,
+    and on a mix of cliques below and above the LDS limit (the latter through
+    the sign-function projection)."""
+    if which == "sparse_cones":
+        prob = synth.lp_sparse(3000, 120, 10, seed=7007, soc=1500, free=40)
+    else:
+        prob = synth.peo_chordal(p=10, smin=4, smax=200, omax=8, m=60, nnz_row=20, seed=5252)
+        assert prob.clique_sizes().max() > 126
+    h = O.Hsde(prob)
+    ref = h.solve(max_iter=20, tol=0.0)
+    sol = cdcs.Solver(prob)
+    st = sol.new_hsde_state()
+    info = sol.hsde_solve(st, tol=0.0, max_iter=20, check_every=10)
+    assert info.iters == 20 and info.status == cdcs.OK
+    sw = np.sqrt(h.dec.w)
+    assert _rel(_np(st["x"]) * sw, ref.x * sw) <= 1e-4
+    assert _rel(_np(st["y"]), ref.y) <= 1e-4
+    assert _rel(_np(st["s"]), _packed(h.dec, ref.s)) <= 1e-4
+    assert _rel(_np(st["z"]), _packed(h.dec, ref.z)) <= 1e-4
+    sol.close()
