@@ -207,6 +207,7 @@ struct HostProblem {
     int32_t nvc = 0;                 // vector cones
     std::vector<int32_t> vblk;       // [nvb * 4] (kind, s0, s1, cone) work blocks of the vector cones
     std::vector<int32_t> soc;        // [nsoc * 3] (first slot, first block, end block) per second-order cone
+    std::vector<int32_t> socb;       // indices of the second-order cones' work blocks
 };
 
 // A CSR input is kept sparse when a dense FP32 copy would be read at more
@@ -344,6 +345,7 @@ cdcs_status host_problem(const cdcs_pattern *pat, const cdcs_constraints *A, con
                 P.soc.push_back((int32_t)s0);
                 P.soc.push_back(b0);
                 P.soc.push_back((int32_t)(P.vblk.size() / 4));
+                for (int32_t b = b0; b < (int32_t)(P.vblk.size() / 4); ++b) P.socb.push_back(b);
             }
         }
     }
@@ -865,8 +867,9 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
     d.nsoc = (int32_t)(P.soc.size() / 3);
     if (d.nsoc > 0) {
         CK(upload(h, &d.soc, P.soc, s));
+        d.nsocb = (int32_t)P.socb.size();
+        CK(upload(h, &d.socb, P.socb, s));
         CK(h->alloc(&d.soc_part, d.nvb));
-        CK(h->alloc(&d.soc_nt, 2 * (int64_t)d.nsoc));
     }
     d.ldU = P.ld;
     d.ldM = round_up(P.m, 32);  // rows of A^T start on 128-byte lines

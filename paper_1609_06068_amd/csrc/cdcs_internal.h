@@ -84,8 +84,7 @@ int project_queue_occupancy(int smax, int nthreads);
 // (kernels_cones.hip).  vblk rows are (kind, first slot, end slot, cone; for
 // a second-order cone its index among those cones); the blocks' residual
 // partial sums go to cpart rows p + b.  A second-order cone's norm comes
-// first from per-block partial sums (soc_part), summed per cone in block
-// order (soc_nt: ||z||, t).
+// from per-block partial sums (soc_part) that each of its blocks adds up.
 constexpr int kVecChunk = 1024;
 struct Dev;
 void launch_project_vec(const ProjArgs &a, const Dev &d, hipStream_t s);
@@ -182,8 +181,9 @@ struct Dev {
     int32_t *vblk = nullptr;       // [nvb * 4] (kind, s0, s1, cone)
     int32_t nsoc = 0;              // second-order cones
     int32_t *soc = nullptr;        // [nsoc * 3] (first slot, first block, end block)
+    int32_t nsocb = 0;             // work blocks of the second-order cones
+    int32_t *socb = nullptr;       // [nsocb] their indices among the nvb blocks
     double *soc_part = nullptr;    // [nvb] per-block sums of z^2 (second-order cone blocks)
-    double *soc_nt = nullptr;      // [nsoc * 2] ||z||, t of each second-order cone
     int64_t ldU = 0;               // row stride of Aw (nU rounded up to 64)
     int64_t ldM = 0;               // row stride of AwT (m rounded up to 32; 4 on batch handles)
     int32_t *clq_size = nullptr;   // [p]

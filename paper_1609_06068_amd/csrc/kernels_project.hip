@@ -240,10 +240,13 @@ __device__ __forceinline__ void tile_rc(int t, int &ti, int &tj) {
 }
 
 // C = X^T Y (mode 0), X Y (mode 1) or X diag(lp) Y^T (mode 2) over q < n, on
-// this wave's tiles.
+// this wave's tiles.  With a column list qi (mode 2 only), term q of the sum
+// takes column qi[q] of X and Y (and lp[qi[q]]); qi must hold n rounded up to
+// 8 entries.
 template <int S, int NT, int MODE, bool LOWER>
 __device__ __forceinline__ void mfma_product(const float *X, const float *Y, const float *lp, int n, int lane,
-                                             int wv, f32x4 (&acc)[MfmaTiles<S, NT, LOWER>::PER]) {
+                                             int wv, f32x4 (&acc)[MfmaTiles<S, NT, LOWER>::PER],
+                                             const int *qi = nullptr) {
     using MT = MfmaTiles<S, NT, LOWER>;
     constexpr int LD = S + 1, PER = MT::PER;
     const int lr = lane & 15, lk = lane >> 4;
@@ -260,7 +263,7 @@ __device__ __forceinline__ void mfma_product(const float *X, const float *Y, con
     // are zero), so the second slice's loads overlap the first's products.
     const int n8 = (n + 7) & ~7;
     auto slice = [&](int q0) {
-        const int q = q0 + lk;
+        const int q = (MODE == 2 && qi != nullptr) ? qi[q0 + lk] : q0 + lk;
         const float l = MODE == 2 ? lp[q] : 1.0f;
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
@@ -286,12 +289,12 @@ __device__ __forceinline__ void mfma_product(const float *X, const float *Y, con
 // diagonal and may skip the others; MIRROR also hands over their transposes).
 template <int S, int NT, int MODE, bool LOWER = false, bool MIRROR = false, typename Store>
 __device__ __forceinline__ void product_store(const float *X, const float *Y, const float *lp, int n, int tid,
-                                              Store st) {
+                                              Store st, const int *qi = nullptr) {
     if constexpr (S >= 32) {
         using MT = MfmaTiles<S, NT, LOWER>;
         const int lane = tid & 63, wv = uniform(tid >> 6);
         f32x4 acc[MT::PER];
-        mfma_product<S, NT, MODE, LOWER>(X, Y, lp, n, lane, wv, acc);
+        mfma_product<S, NT, MODE, LOWER>(X, Y, lp, n, lane, wv, acc, qi);
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < MT::PER; ++r) {
@@ -323,8 +326,12 @@ __device__ __forceinline__ void product_store(const float *X, const float *Y, co
 
 // Small per-workgroup LDS of the projection (sized for the largest bucket).
 struct ProjSmall {
-    float2 cst[64];              // rotations of one step: (c, s) of pair t (8-byte stride: the reads of
+    union {
+        float2 cst[64];          // rotations of one step: (c, s) of pair t (8-byte stride: the reads of
                                  // consecutive pairs fall in distinct bank pairs)
+        int pidx[128];           // after the sweeps: indices of the positive eigenvalues, then the others
+    };
+    int npos[2];                 // positive eigenvalues counted by waves 0 and 1
     float lam[128], lp[128];     // eigenvalues, clamped eigenvalues
     float redf[8];
     double redd[24];             // three FP64 partial sums per wave
@@ -674,15 +681,45 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
     }
     __syncthreads();
 
-    // E = V^T V - I  -> sA (A's eigenvalues are in sm.lam)
-    product_store<S, NT, 0, true, true>(sV, sV, nullptr, K, tid,
-                                        [&](int i, int j, float v) { sA[i * LD + j] = v - (i == j ? 1.0f : 0.0f); });
-    __syncthreads();
-    // Vn = V - V E / 2  -> sV
-    product_store<S, NT, 1>(sV, sA, nullptr, K, tid, [&](int i, int j, float v) { sV[i * LD + j] -= 0.5f * v; });
-    __syncthreads();
-    // P = Vn diag(max(Lambda, 0)) Vn^T  -> sA (lower triangle; only it is read)
-    product_store<S, NT, 2, true>(sV, sV, sm.lp, K, tid, to_sA);
+    // Re-orthonormalisation, only after rotations: without a sweep V is the
+    // start matrix as it came in (the identity, or eigenvectors that were
+    // re-orthonormalised when they were made).
+    if (sweep > 0) {
+        // E = V^T V - I  -> sA (A's eigenvalues are in sm.lam)
+        product_store<S, NT, 0, true, true>(
+            sV, sV, nullptr, K, tid, [&](int i, int j, float v) { sA[i * LD + j] = v - (i == j ? 1.0f : 0.0f); });
+        __syncthreads();
+        // Vn = V - V E / 2  -> sV
+        product_store<S, NT, 1>(sV, sA, nullptr, K, tid,
+                                [&](int i, int j, float v) { sV[i * LD + j] -= 0.5f * v; });
+        __syncthreads();
+    }
+    // P = Vn diag(max(Lambda, 0)) Vn^T  -> sA (lower triangle; only it is
+    // read).  On the matrix cores the sum runs over the columns of the
+    // positive eigenvalues only: they are listed first in sm.pidx (the others
+    // follow, so the list is padded with columns whose clamped eigenvalue is
+    // zero), and the sum has their number rounded up to 8 terms instead of K.
+    if constexpr (S >= 32) {
+        static_assert(NT >= S, "one thread per column");
+        const int lane = tid & 63;
+        bool pos = false;
+        unsigned long long m = 0ull;
+        if (tid < S) {
+            pos = sm.lp[tid] > 0.0f;
+            m = __ballot(pos);
+            if (lane == 0) sm.npos[tid >> 6] = __popcll(m);
+        }
+        __syncthreads();
+        const int r = uniform(sm.npos[0] + (S > 64 ? sm.npos[1] : 0));
+        if (tid < S) {
+            const int before = (tid >= 64 ? sm.npos[0] : 0) + __popcll(m & ((1ull << lane) - 1ull));
+            sm.pidx[pos ? before : r + tid - before] = tid;
+        }
+        __syncthreads();
+        product_store<S, NT, 2, true>(sV, sV, sm.lp, r, tid, to_sA, sm.pidx);
+    } else {
+        product_store<S, NT, 2, true>(sV, sV, sm.lp, K, tid, to_sA);
+    }
     __syncthreads();
 
     if (warm && a.warm_store)
