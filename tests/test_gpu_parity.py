@@ -77,6 +77,27 @@ def test_projection_special_cases(torch):
     assert np.abs(Pb[2]).max() <= 1e-5 * np.linalg.norm(S)
 
 
+def test_projection_rank_extremes(torch):
+    """Every eigenvalue positive at full bucket sizes (the rebuild sums over
+    all columns), none positive, and a few positive eigenvalues (a sum
+    shorter than the block, padded with zero columns), across the buckets
+    that multiply on the matrix cores."""
+    rng = np.random.default_rng(11)
+    cases = []
+    for s, npos in ((32, 1), (48, 5), (64, 7), (80, 9), (95, 13), (96, 17)):
+        G = rng.standard_normal((s, s))
+        S = G @ G.T / s + 0.1 * np.eye(s)
+        cases += [S, -S]
+        Q, _ = np.linalg.qr(rng.standard_normal((s, s)))
+        ev = -rng.uniform(0.5, 2.0, s)
+        ev[:npos] *= -1.0
+        cases.append((Q * ev) @ Q.T)
+    errs, Pb = _proj_err(torch, cases)
+    assert errs.max() <= 1e-5, (errs.max(), int(errs.argmax()))
+    for t in range(1, len(cases), 3):  # negative definite: exactly zero
+        assert np.abs(Pb[t]).max() <= 1e-6 * np.linalg.norm(cases[t]), t
+
+
 def test_projection_eigen_outputs(torch):
     sizes = np.array([5, 30, 64])
     blocks = [np.asarray(synth.random_symmetric(s, seed=s), dtype=np.float32) for s in sizes]
