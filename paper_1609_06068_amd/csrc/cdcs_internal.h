@@ -300,6 +300,11 @@ void launch_hsde_solution(const Dev &d, const HsdeDev &hs, int which, const doub
 // scatter / residual / affine kernels
 int scatter_blocks(const Dev &d);
 int scatter_light_blocks(const Dev &d);
+// The Algorithm 1 and HSDE scatters give each thread of a light block
+// kScatterEPT entries: their block counts (light, and light + heavy).
+constexpr int kScatterEPT = 4;
+int pscatter_blocks(const Dev &d);
+int pscatter_light_blocks(const Dev &d);
 int heavy_threshold();
 int vupdate_blocks(const Dev &d);
 void launch_reset_ctl(const Dev &d, int max_iter, double tol, hipStream_t s);

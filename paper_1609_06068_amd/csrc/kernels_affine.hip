@@ -88,7 +88,12 @@ __device__ __forceinline__ double entry_weight(const uint32_t *__restrict__ wbit
 // u = r1 / D (D_e = the number of slots of e, read from the inverse map), plus
 // the dual-residual terms ||sum_k H_k^T (x_k - x_k_prev)||_w^2 (from the
 // projection's per-slot differences) and ||sum_k H_k^T lam_k||_w^2 as
-// per-block partial sums.
+// per-block partial sums.  Light blocks: kScatterEPT entries per thread
+// (entry e0 + u kNT for u < kScatterEPT), whose inverse-map pointers and
+// first slots are all loaded before their values, so that the loads of the
+// entries are in flight together (almost every entry has one slot); the
+// further slots of an entry follow in order.  Entries with more than kHeavy
+// slots are left to the heavy blocks, one wave each.
 __global__ __launch_bounds__(kNT) void k_scatter_primal(const int32_t *__restrict__ inv_ptr,
                                                         const int32_t *__restrict__ inv_slot,
                                                         const int32_t *__restrict__ heavy, int nheavy,
@@ -102,34 +107,55 @@ __global__ __launch_bounds__(kNT) void k_scatter_primal(const int32_t *__restric
     __shared__ double red[kNT / 64];
     if (ctl->stop) return;
     const int lane = threadIdx.x & 63;
-    int64_t e = -1;
-    double s_x = 0.0, s_l = 0.0, s_d = 0.0;
-    int32_t D = 1;
-    bool owner = false;
+    double ds2 = 0.0, sl2 = 0.0;
     if ((int)blockIdx.x < nlight_blocks) {
-        e = (int64_t)blockIdx.x * kNT + threadIdx.x;
-        if (e < nU) {
-            const int32_t q0 = inv_ptr[e], q1 = inv_ptr[e + 1];
-            D = q1 - q0;
-            if (D <= kHeavy) {
-                owner = true;
-                // unrolled so that the loads of several slots are in flight
-                // together (the sums keep their order)
-#pragma unroll 4
-                for (int32_t q = q0; q < q1; ++q) {
-                    const int32_t sl = inv_slot[q];
-                    s_x += (double)blk[sl];
-                    s_l += (double)lam[sl];
-                    s_d += (double)dslot[sl];
-                }
+        constexpr int U = kScatterEPT;
+        const int64_t e0 = (int64_t)blockIdx.x * (kNT * U) + threadIdx.x;
+        int32_t q0[U], q1[U], sl[U];
+#pragma unroll
+        for (int v = 0; v < U; ++v) {
+            const int64_t e = e0 + (int64_t)v * kNT;
+            q0[v] = e < nU ? inv_ptr[e] : 0;
+            q1[v] = e < nU ? inv_ptr[e + 1] : 0;
+        }
+#pragma unroll
+        for (int v = 0; v < U; ++v) sl[v] = q1[v] > q0[v] ? inv_slot[q0[v]] : 0;
+        float fx[U], fl[U], fd[U];
+#pragma unroll
+        for (int v = 0; v < U; ++v) {
+            fx[v] = blk[sl[v]];
+            fl[v] = lam[sl[v]];
+            fd[v] = dslot[sl[v]];
+        }
+#pragma unroll
+        for (int v = 0; v < U; ++v) {
+            const int64_t e = e0 + (int64_t)v * kNT;
+            const int32_t D = q1[v] - q0[v];
+            if (e >= nU || D > kHeavy) continue;
+            double s_x = 0.0, s_l = 0.0, s_d = 0.0;
+            if (D > 0) {
+                s_x = (double)fx[v];
+                s_l = (double)fl[v];
+                s_d = (double)fd[v];
             }
+            for (int32_t q = q0[v] + 1; q < q1[v]; ++q) {
+                const int32_t t = inv_slot[q];
+                s_x += (double)blk[t];
+                s_l += (double)lam[t];
+                s_d += (double)dslot[t];
+            }
+            const double r1 = s_x + s_l / rho - c[e] / rho;
+            u[e] = r1 / (double)D;
+            const double w = entry_weight(wbits, e);
+            ds2 += w * s_d * s_d;
+            sl2 += w * s_l * s_l;
         }
     } else {
         const int hw = ((int)blockIdx.x - nlight_blocks) * (kNT / 64) + (threadIdx.x >> 6);
         if (hw < nheavy) {
-            e = heavy[hw];
+            const int64_t e = heavy[hw];
             const int32_t q0 = inv_ptr[e], q1 = inv_ptr[e + 1];
-            D = q1 - q0;
+            double s_x = 0.0, s_l = 0.0, s_d = 0.0;
             for (int32_t q = q0 + lane; q < q1; q += 64) {
                 const int32_t sl = inv_slot[q];
                 s_x += (double)blk[sl];
@@ -139,16 +165,14 @@ __global__ __launch_bounds__(kNT) void k_scatter_primal(const int32_t *__restric
             s_x = wave_sum_d(s_x);
             s_l = wave_sum_d(s_l);
             s_d = wave_sum_d(s_d);
-            owner = (lane == 0);
+            if (lane == 0) {
+                const double r1 = s_x + s_l / rho - c[e] / rho;
+                u[e] = r1 / (double)(q1 - q0);
+                const double w = entry_weight(wbits, e);
+                ds2 = w * s_d * s_d;
+                sl2 = w * s_l * s_l;
+            }
         }
-    }
-    double ds2 = 0.0, sl2 = 0.0;
-    if (owner) {
-        const double r1 = s_x + s_l / rho - c[e] / rho;
-        u[e] = r1 / (double)D;
-        const double w = entry_weight(wbits, e);
-        ds2 = w * s_d * s_d;
-        sl2 = w * s_l * s_l;
     }
     ds2 = block_sum_d(ds2, red);
     sl2 = block_sum_d(sl2, red);
@@ -711,6 +735,8 @@ __global__ __launch_bounds__(kNT) void k_add_to(const double *__restrict__ v, do
 
 int scatter_light_blocks(const Dev &d) { return (int)blocks_for(d.nU); }
 int scatter_blocks(const Dev &d) { return scatter_light_blocks(d) + (d.nheavy + kNT / 64 - 1) / (kNT / 64); }
+int pscatter_light_blocks(const Dev &d) { return (int)((d.nU + kNT * kScatterEPT - 1) / (kNT * kScatterEPT)); }
+int pscatter_blocks(const Dev &d) { return pscatter_light_blocks(d) + (d.nheavy + kNT / 64 - 1) / (kNT / 64); }
 int heavy_threshold() { return kHeavy; }
 int vupdate_blocks(const Dev &d) { return (int)blocks_for(d.nslots); }
 
@@ -720,8 +746,8 @@ void launch_reset_ctl(const Dev &d, int max_iter, double tol, hipStream_t s) {
 
 void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, double rho,
                            hipStream_t s) {
-    hipLaunchKernelGGL(k_scatter_primal, dim3(scatter_blocks(d)), dim3(kNT), 0, s, d.inv_ptr, d.inv_slot,
-                       (const int32_t *)d.heavy, d.nheavy, scatter_light_blocks(d), blk, lam,
+    hipLaunchKernelGGL(k_scatter_primal, dim3(pscatter_blocks(d)), dim3(kNT), 0, s, d.inv_ptr, d.inv_slot,
+                       (const int32_t *)d.heavy, d.nheavy, pscatter_light_blocks(d), blk, lam,
                        (const float *)d.dslot, (const double *)d.c, (const uint32_t *)d.wbits, d.u, d.spart, d.nU,
                        rho, (const Ctl *)d.ctl);
 }
@@ -729,12 +755,12 @@ void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, dou
 void launch_check_primal(const Dev &d, double rho, hipStream_t s) {
     // partial sums of the cliques, then of the vector cones' blocks
     const int ncp = d.p + d.nvb;
-    if (ncp + scatter_blocks(d) > 8192)
+    if (ncp + pscatter_blocks(d) > 8192)
         hipLaunchKernelGGL(k_check_primal<1024>, dim3(1), dim3(1024), 0, s, (const double *)d.cpart, ncp,
-                           (const double *)d.spart, scatter_blocks(d), rho, d.hist, d.hist_cap, d.ctl);
+                           (const double *)d.spart, pscatter_blocks(d), rho, d.hist, d.hist_cap, d.ctl);
     else
         hipLaunchKernelGGL(k_check_primal<kNT>, dim3(1), dim3(kNT), 0, s, (const double *)d.cpart, ncp,
-                           (const double *)d.spart, scatter_blocks(d), rho, d.hist, d.hist_cap, d.ctl);
+                           (const double *)d.spart, pscatter_blocks(d), rho, d.hist, d.hist_cap, d.ctl);
 }
 
 void launch_scatter_dual(const Dev &d, const float *blk, const float *lam, double rho,

@@ -136,6 +136,10 @@ __global__ __launch_bounds__(kNT) void k_hsde_init(double *__restrict__ x, int64
 // ||A^T y - sum_k H_k^T z_k||_w^2 with
 //   r_d = (x_prev - x) - sum_k H_k^T (s_k - s_k_prev) + (tau - ut) c,
 //   A^T y - sum_k H_k^T z_k = r_d - tau c.
+// Light blocks give each thread kScatterEPT entries (entry e0 + v kNT), whose
+// inverse-map pointers and first slots are loaded before their values, so the
+// loads of the entries are in flight together; heavy entries (more than
+// kHeavy slots) get a wave each.
 __global__ __launch_bounds__(kNT) void k_hsde_scatter(const int32_t *__restrict__ inv_ptr,
                                                       const int32_t *__restrict__ inv_slot,
                                                       const int32_t *__restrict__ heavy, int nheavy,
@@ -150,29 +154,60 @@ __global__ __launch_bounds__(kNT) void k_hsde_scatter(const int32_t *__restrict_
     __shared__ double red[kNT / 64];
     if (ctl->stop) return;
     const int lane = threadIdx.x & 63;
-    int64_t e = -1;
-    double s_s = 0.0, s_z = 0.0, s_d = 0.0;
-    bool owner = false;
+    double rd2 = 0.0, at2 = 0.0;
+    auto finish = [&](int64_t e, double s_s, double s_z, double s_d) {
+        const double ce = c[e];
+        u[e] = (x[e] + s_s + s_z) * invE[e];
+        const double w = entry_weight(wbits, e);
+        const double rd = dx[e] - s_d + sc[5] * ce;
+        const double at = rd - tk[0] * ce;
+        rd2 += w * rd * rd;
+        at2 += w * at * at;
+    };
     if ((int)blockIdx.x < nlight_blocks) {
-        e = (int64_t)blockIdx.x * kNT + threadIdx.x;
-        if (e < nU) {
-            const int32_t q0 = inv_ptr[e], q1 = inv_ptr[e + 1];
-            if (q1 - q0 <= kHeavy) {
-                owner = true;
-#pragma unroll 4
-                for (int32_t q = q0; q < q1; ++q) {
-                    const int32_t sl = inv_slot[q];
-                    s_s += (double)s[sl];
-                    s_z += (double)z[sl];
-                    s_d += (double)dslot[sl];
-                }
+        constexpr int U = kScatterEPT;
+        const int64_t e0 = (int64_t)blockIdx.x * (kNT * U) + threadIdx.x;
+        int32_t q0[U], q1[U], sl[U];
+#pragma unroll
+        for (int v = 0; v < U; ++v) {
+            const int64_t e = e0 + (int64_t)v * kNT;
+            q0[v] = e < nU ? inv_ptr[e] : 0;
+            q1[v] = e < nU ? inv_ptr[e + 1] : 0;
+        }
+#pragma unroll
+        for (int v = 0; v < U; ++v) sl[v] = q1[v] > q0[v] ? inv_slot[q0[v]] : 0;
+        float fs[U], fz[U], fd[U];
+#pragma unroll
+        for (int v = 0; v < U; ++v) {
+            fs[v] = s[sl[v]];
+            fz[v] = z[sl[v]];
+            fd[v] = dslot[sl[v]];
+        }
+#pragma unroll
+        for (int v = 0; v < U; ++v) {
+            const int64_t e = e0 + (int64_t)v * kNT;
+            const int32_t D = q1[v] - q0[v];
+            if (e >= nU || D > kHeavy) continue;
+            double s_s = 0.0, s_z = 0.0, s_d = 0.0;
+            if (D > 0) {
+                s_s = (double)fs[v];
+                s_z = (double)fz[v];
+                s_d = (double)fd[v];
             }
+            for (int32_t q = q0[v] + 1; q < q1[v]; ++q) {
+                const int32_t t = inv_slot[q];
+                s_s += (double)s[t];
+                s_z += (double)z[t];
+                s_d += (double)dslot[t];
+            }
+            finish(e, s_s, s_z, s_d);
         }
     } else {
         const int hw = ((int)blockIdx.x - nlight_blocks) * (kNT / 64) + (threadIdx.x >> 6);
         if (hw < nheavy) {
-            e = heavy[hw];
+            const int64_t e = heavy[hw];
             const int32_t q0 = inv_ptr[e], q1 = inv_ptr[e + 1];
+            double s_s = 0.0, s_z = 0.0, s_d = 0.0;
             for (int32_t q = q0 + lane; q < q1; q += 64) {
                 const int32_t sl = inv_slot[q];
                 s_s += (double)s[sl];
@@ -182,18 +217,8 @@ __global__ __launch_bounds__(kNT) void k_hsde_scatter(const int32_t *__restrict_
             s_s = wave_sum_d(s_s);
             s_z = wave_sum_d(s_z);
             s_d = wave_sum_d(s_d);
-            owner = (lane == 0);
+            if (lane == 0) finish(e, s_s, s_z, s_d);
         }
-    }
-    double rd2 = 0.0, at2 = 0.0;
-    if (owner) {
-        const double ce = c[e];
-        u[e] = (x[e] + s_s + s_z) * invE[e];
-        const double w = entry_weight(wbits, e);
-        const double rd = dx[e] - s_d + sc[5] * ce;
-        const double at = rd - tk[0] * ce;
-        rd2 = w * rd * rd;
-        at2 = w * at * at;
     }
     rd2 = block_sum<kNT>(rd2, red);
     at2 = block_sum<kNT>(at2, red);
@@ -393,15 +418,15 @@ void launch_hsde_init(const Dev &d, double *x, double *y, float *sl, float *z, d
 
 void launch_hsde_scatter(const Dev &d, const HsdeDev &hs, const float *sl, const float *z, const double *tk,
                          hipStream_t s) {
-    hipLaunchKernelGGL(k_hsde_scatter, dim3(scatter_blocks(d)), dim3(kNT), 0, s, (const int32_t *)d.inv_ptr,
-                       (const int32_t *)d.inv_slot, (const int32_t *)d.heavy, d.nheavy, scatter_light_blocks(d), sl, z,
+    hipLaunchKernelGGL(k_hsde_scatter, dim3(pscatter_blocks(d)), dim3(kNT), 0, s, (const int32_t *)d.inv_ptr,
+                       (const int32_t *)d.inv_slot, (const int32_t *)d.heavy, d.nheavy, pscatter_light_blocks(d), sl, z,
                        (const float *)d.dslot, (const double *)d.xi, (const double *)hs.dx, (const double *)d.c,
                        (const double *)hs.invE, (const uint32_t *)d.wbits, (const double *)hs.sc, tk, d.u, hs.hpart,
                        d.nU, (const Ctl *)d.ctl);
 }
 
 void launch_hsde_check(const Dev &d, const HsdeDev &hs, const double *tk, hipStream_t s) {
-    const int ncp = d.p + d.nvb, nhb = scatter_blocks(d);
+    const int ncp = d.p + d.nvb, nhb = pscatter_blocks(d);
     if (ncp + nhb > 8192)
         hipLaunchKernelGGL(k_hsde_check<1024>, dim3(1), dim3(1024), 0, s, (const double *)d.cpart, ncp,
                            (const double *)hs.hpart, nhb, hs.sc, tk, hs.hist, hs.hist_cap, d.ctl);
