@@ -722,11 +722,10 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
     }
     __syncthreads();
 
+    // eigenvectors out row by row (a wave per row, lanes along it)
     if (warm && a.warm_store)
-        for (int idx = tid; idx < k * k; idx += NT) {
-            const int i = idx / k, j = idx - i * k;
-            vw[idx] = sV[i * LD + j];
-        }
+        for (int i = wv; i < k; i += NW)
+            for (int j = lane; j < k; j += 64) vw[i * k + j] = sV[i * LD + j];
 
     double p0 = 0.0, p1 = 0.0, p2 = 0.0;
     for (int s0 = tid; s0 < nslot; s0 += GU * NT) {
@@ -795,10 +794,8 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
     if (a.evals != nullptr)
         for (int t = tid; t < k; t += NT) a.evals[a.eoff[id] + t] = sm.lam[t];
     if (a.evecs != nullptr)
-        for (int idx = tid; idx < k * k; idx += NT) {
-            const int i = idx / k, j = idx - i * k;
-            a.evecs[a.voff[id] + idx] = sV[i * LD + j];
-        }
+        for (int i = wv; i < k; i += NW)
+            for (int j = lane; j < k; j += 64) a.evecs[a.voff[id] + i * k + j] = sV[i * LD + j];
     __syncthreads();  // LDS is reused by the next clique of a queue launch
 }
 
