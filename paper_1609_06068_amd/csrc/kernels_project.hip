@@ -113,27 +113,11 @@ __device__ __forceinline__ int tri_row(int s) {
 // (K-1, ghost) with a ghost position that holds zeros (tiling 1, K/2 + 1
 // pairs).  After every rotation the two positions of each pair exchange
 // their contents, so over K steps every two positions meet once and the
-// order is reversed.  Slot (t, h) is member h of pair t of a tiling; its
-// position, -1 for a ghost:
-__device__ __forceinline__ int slot_pos(int tiling, int t, int h, int HK) {
-    if (tiling == 0) return 2 * t + h;
-    if (t == 0) return h == 0 ? -1 : 0;
-    if (t == HK) return h == 0 ? 2 * HK - 1 : -1;
-    return 2 * t - 1 + h;
-}
-// ... and the slot of position p (not a ghost) in a tiling.
-__device__ __forceinline__ void pos_slot(int tiling, int p, int HK, int &t, int &h) {
-    if (tiling == 0) {
-        t = p >> 1;
-        h = p & 1;
-    } else if (p == 2 * HK - 1) {
-        t = HK;
-        h = 0;
-    } else {
-        t = (p + 1) >> 1;
-        h = (p + 1) & 1;
-    }
-}
+// order is reversed.  Slot (t, h) is member h of pair t of a tiling.  After
+// a step on tiling 0, the content of slot (t, h) sits in slot (t + 1 - h, h)
+// of tiling 1; after a step on tiling 1, in slot (t - h, h) of tiling 0,
+// except that what the rotation and swap move onto a ghost member, (0, 0) or
+// (K/2, 1) of tiling 1, is dropped.
 
 // Element offset (plane * nbs + block) of entry (slot (t1, g1), slot (t2, g2))
 // of a symmetric matrix stored as lower 2x2 pair blocks in four planes
@@ -466,11 +450,11 @@ __device__ __forceinline__ void project_one(const ProjArgs &a, int id, float *__
     // Byte offset in tiling 1-T of element e (= 2 h_row + h_col) of block
     // (I, J) of tiling T after the rotation and the swap.
     auto move_to = [&](int T, int I, int J, int e) {
-        const int p1 = slot_pos(T, I, 1 - (e >> 1), HK), p2 = slot_pos(T, J, 1 - (e & 1), HK);
-        int t1, g1, t2, g2;
-        pos_slot(1 - T, max(p1, 0), HK, t1, g1);
-        pos_slot(1 - T, max(p2, 0), HK, t2, g2);
-        return (p1 < 0 || p2 < 0) ? DUMMY : pair_slot(t1, g1, t2, g2, NBS) * 4;
+        const int h1 = e >> 1, h2 = e & 1;  // members of the row and the column
+        if (T == 0) return pair_slot(I + 1 - h1, h1, J + 1 - h2, h2, NBS) * 4;
+        // ghost members of the end pairs (their contents come from the ghost)
+        if ((I == 0 && h1 == 1) || (I == HK && h1 == 0) || (J == 0 && h2 == 1) || (J == HK && h2 == 0)) return DUMMY;
+        return pair_slot(I - h1, h1, J - h2, h2, NBS) * 4;
     };
     // Blocks of this thread (the same lower-triangle numbering in both
     // tilings): pair indices and, per tiling, where the four rotated
