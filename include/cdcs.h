@@ -653,10 +653,13 @@ cdcs_status cdcs_profile_kernel(cdcs_handle *h, const cdcs_state *st, int32_t fo
  * size buckets S in {16, 32, 48, 64, 80, 96, 112, 128}.  Either one persistent launch
  * draws every clique, largest first, from a device work queue
  * (persistent = 1, `threads` per workgroup, `grid` workgroups), or each
- * bucket gets its own launch with its own workgroup size (persistent = 0).
- * Setup picks the faster form by timing both on the handle's cliques
- * (queue_us, buckets_us = sum of bucket_us: microseconds per projection of
- * all cliques on generated nearly diagonal blocks).
+ * bucket gets its own launch with its own workgroup size, one after the other
+ * in the caller's stream (persistent = 0) or on parallel streams forked from
+ * it and joined back into it (persistent = 2: the launches' tails overlap;
+ * the same kernels, so the same bits as 0).  Setup picks the fastest form by
+ * timing all three on the handle's cliques (queue_us, buckets_us = sum of
+ * bucket_us, parallel_us: microseconds per projection of all cliques on
+ * generated nearly diagonal blocks; -1 where a form does not apply).
  */
 typedef struct {
     int32_t persistent;
@@ -669,6 +672,7 @@ typedef struct {
     float bucket_us[8];      /* best per-bucket launch time */
     float queue_us;
     float buckets_us;
+    float parallel_us;
 } cdcs_tuning;
 
 cdcs_status cdcs_get_tuning(const cdcs_handle *h, cdcs_tuning *out);
@@ -680,7 +684,8 @@ cdcs_status cdcs_get_tuning(const cdcs_handle *h, cdcs_tuning *out);
  * grid makes every workgroup project several cliques), or persistent = 0 with
  * threads 64, 256 or 512 for every bucket that has that size built (64:
  * buckets 16 and 32 only, the others keep 256; 256 and 512: every bucket),
- * or 0 to keep the tuned per-bucket sizes (grid is ignored).
+ * or 0 to keep the tuned per-bucket sizes (grid is ignored); persistent = 2
+ * is persistent = 0 with the buckets on parallel streams.
  * Synchronizes the device and drops captured graphs.  Errors: CDCS_E_ARG
  * (also for a grid above the resident workgroups), CDCS_E_DEVICE.
  */

@@ -92,7 +92,8 @@ class _Tuning(ctypes.Structure):
     _fields_ = [("persistent", ctypes.c_int32), ("threads", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("nbuckets", ctypes.c_int32), ("bucket_size", ctypes.c_int32 * 8),
                 ("bucket_threads", ctypes.c_int32 * 8), ("bucket_count", ctypes.c_int32 * 8),
-                ("bucket_us", ctypes.c_float * 8), ("queue_us", ctypes.c_float), ("buckets_us", ctypes.c_float)]
+                ("bucket_us", ctypes.c_float * 8), ("queue_us", ctypes.c_float), ("buckets_us", ctypes.c_float),
+                ("parallel_us", ctypes.c_float)]
 
 
 class _Sizes(ctypes.Structure):
@@ -469,14 +470,17 @@ class Solver:
         t = _Tuning()
         _check(load_library().cdcs_get_tuning(self._h, ctypes.byref(t)), "cdcs_get_tuning")
         nb = t.nbuckets
-        return {"persistent": bool(t.persistent), "threads": t.threads, "grid": t.grid,
+        return {"persistent": t.persistent == 1, "parallel_buckets": t.persistent == 2, "threads": t.threads,
+                "grid": t.grid,
                 "buckets": [{"size": t.bucket_size[q], "threads": t.bucket_threads[q], "count": t.bucket_count[q],
                              "us": t.bucket_us[q]} for q in range(nb)],
-                "queue_us": t.queue_us, "buckets_us": t.buckets_us}
+                "queue_us": t.queue_us, "buckets_us": t.buckets_us, "parallel_us": t.parallel_us}
 
-    def set_projection_plan(self, persistent: bool, threads: int = 0, grid: int = 0):
-        """Override the tuned plan (cdcs_set_projection_plan)."""
-        _check(load_library().cdcs_set_projection_plan(self._h, int(bool(persistent)), int(threads), int(grid)),
+    def set_projection_plan(self, persistent: bool, threads: int = 0, grid: int = 0, parallel: bool = False):
+        """Override the tuned plan (cdcs_set_projection_plan); parallel: the
+        per-bucket launches on parallel streams."""
+        mode = 1 if persistent else (2 if parallel else 0)
+        _check(load_library().cdcs_set_projection_plan(self._h, mode, int(threads), int(grid)),
                "cdcs_set_projection_plan")
 
     def prepare(self, state: dict, form: str = "primal", rho: float = 1.0, tol: float = 1e-4,

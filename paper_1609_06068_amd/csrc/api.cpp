@@ -104,10 +104,13 @@ struct Bucket {
 // the candidates on this handle's cliques.
 struct ProjPlan {
     bool queue = false;
+    bool parallel = false;  // per-bucket launches on parallel streams (not queue)
     int nt = 256;      // queue workgroup size
     int grid = 0;      // queue workgroups
-    float queue_us = -1.0f, buckets_us = -1.0f;
+    float queue_us = -1.0f, buckets_us = -1.0f, parallel_us = -1.0f;
 };
+
+constexpr int kSideStreams = 3;  // streams besides the caller's for the size buckets' launches
 
 }  // namespace
 
@@ -120,6 +123,10 @@ struct cdcs_handle {
     ProjPlan plan;
     unsigned long long *ticket = nullptr;  // device counter of the queue launch
     hipStream_t cap_stream = nullptr;
+    // the size buckets' launches of the parallel plan: forked from the
+    // caller's stream by fork_ev, joined back by join_ev (default priority)
+    hipStream_t side[kSideStreams] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[kSideStreams] = {};
     std::map<GraphKey, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_defs;
     std::unique_ptr<Batch> batch_host;
@@ -165,6 +172,11 @@ struct cdcs_handle {
         for (void *p : allocs) (void)hipFree(p);
         if (d.ctl_host) (void)hipHostFree(d.ctl_host);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        for (int i = 0; i < kSideStreams; ++i) {
+            if (side[i]) (void)hipStreamDestroy(side[i]);
+            if (join_ev[i]) (void)hipEventDestroy(join_ev[i]);
+        }
+        if (fork_ev) (void)hipEventDestroy(fork_ev);
     }
 };
 
@@ -849,6 +861,15 @@ cdcs_status factor_into(cdcs_handle *h, double shift, hipStream_t s) {
     return compress_factors(h, s);
 }
 
+cdcs_status create_side_streams(cdcs_handle *h) {
+    for (int i = 0; i < kSideStreams; ++i) {
+        HIP_OK(hipStreamCreateWithFlags(&h->side[i], hipStreamNonBlocking));
+        HIP_OK(hipEventCreateWithFlags(&h->join_ev[i], hipEventDisableTiming));
+    }
+    HIP_OK(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
+    return CDCS_OK;
+}
+
 cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraints *A, const double *b,
                   const double *c, const cdcs_cliques *cl, const cdcs_vcones *cones, hipStream_t s) {
     Dev &d = h->d;
@@ -935,6 +956,7 @@ cdcs_status build(cdcs_handle *h, const cdcs_pattern *pat, const cdcs_constraint
         CK(upload(h, &h->sym_tid, tid, s));
     }
     CK(factor_into(h, 0.0, s));
+    CK(create_side_streams(h));
     CK(tune_projection(h, s));
     HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     return CDCS_OK;
@@ -1161,6 +1183,7 @@ cdcs_status build_batch(cdcs_handle *h, int32_t nprob, const cdcs_problem *probs
         if (finfo[(size_t)q] != 0)
             return fail(CDCS_E_RANK, "problem " + std::to_string(q) + ": A D^-1 A^T is not positive definite (pivot " +
                                          std::to_string(finfo[(size_t)q] - 1) + ")");
+    CK(create_side_streams(h));
     CK(tune_projection(h, s));
     HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     return CDCS_OK;
@@ -1220,6 +1243,30 @@ cdcs_status diff_buffers(cdcs_handle *h) {
 }
 
 // The projection of every clique with the handle's plan.
+// One launch per size bucket, in stream order on s or (parallel) forked onto
+// the side streams and joined back into s: bucket 0 on s, bucket i >= 1 on
+// side stream (i - 1) mod kSideStreams.  Each clique is projected by the same
+// kernel either way, so both give the same bits.
+void launch_buckets(cdcs_handle *h, ProjArgs a, hipStream_t s, bool parallel) {
+    const int nb = (int)h->buckets.size();
+    const int ns = std::min(nb - 1, kSideStreams);
+    if (parallel && ns > 0) {
+        (void)hipEventRecord(h->fork_ev, s);
+        for (int j = 0; j < ns; ++j) (void)hipStreamWaitEvent(h->side[j], h->fork_ev, 0);
+    }
+    for (int i = 0; i < nb; ++i) {
+        const Bucket &bk = h->buckets[(size_t)i];
+        a.nblk = bk.count;
+        a.ids = bk.ids;
+        launch_project(a, bk.smax, bk.nt, (parallel && i > 0) ? h->side[(i - 1) % kSideStreams] : s);
+    }
+    if (parallel && ns > 0)
+        for (int j = 0; j < ns; ++j) {
+            (void)hipEventRecord(h->join_ev[j], h->side[j]);
+            (void)hipStreamWaitEvent(s, h->join_ev[j], 0);
+        }
+}
+
 void launch_plan(cdcs_handle *h, ProjArgs a, hipStream_t s) {
     const Dev &d = h->d;
     launch_big_projection(a, d.big, s);  // cliques above the LDS limit, if any
@@ -1229,11 +1276,7 @@ void launch_plan(cdcs_handle *h, ProjArgs a, hipStream_t s) {
         launch_project_queue(a, d.smax_lds, h->plan.nt, h->plan.grid, h->ticket, s);
         return;
     }
-    for (const Bucket &bk : h->buckets) {
-        a.nblk = bk.count;
-        a.ids = bk.ids;
-        launch_project(a, bk.smax, bk.nt, s);
-    }
+    launch_buckets(h, a, s, h->plan.parallel);
 }
 
 void launch_projection(cdcs_handle *h, int mode, const cdcs_state *st, double rho, hipStream_t s) {
@@ -1320,6 +1363,10 @@ cdcs_status tune_projection(cdcs_handle *h, hipStream_t s) {
         bsum += best;
     }
     h->plan.buckets_us = bsum;
+    // the same launches with the buckets on parallel streams
+    float psum = 1e30f;
+    if (h->buckets.size() > 1) psum = time_us([&]() { launch_buckets(h, a, s, true); });
+    h->plan.parallel_us = psum < 1e29f ? psum : -1.0f;
     // persistent queue launch
     float qbest = 1e30f;
     for (int nt : {256, 512}) {
@@ -1337,7 +1384,8 @@ cdcs_status tune_projection(cdcs_handle *h, hipStream_t s) {
         }
     }
     h->plan.queue_us = qbest < 1e29f ? qbest : -1.0f;
-    h->plan.queue = qbest < bsum;
+    h->plan.queue = qbest < std::min(bsum, psum);
+    h->plan.parallel = !h->plan.queue && psum < bsum;
     HIP_OK(hipMemsetAsync(h->ticket, 0, sizeof(unsigned long long), s));
     e = hipStreamSynchronize(s);
     cleanup();
@@ -2317,7 +2365,7 @@ cdcs_status cdcs_profile_kernel(cdcs_handle *h, const cdcs_state *st_user, int32
 cdcs_status cdcs_get_tuning(const cdcs_handle *h, cdcs_tuning *out) {
     if (!h || !out) return fail(CDCS_E_ARG, "NULL argument");
     std::memset(out, 0, sizeof(*out));
-    out->persistent = h->plan.queue ? 1 : 0;
+    out->persistent = h->plan.queue ? 1 : h->plan.parallel ? 2 : 0;
     out->threads = h->plan.nt;
     out->grid = h->plan.grid;
     out->nbuckets = (int32_t)std::min<size_t>(h->buckets.size(), 8);
@@ -2329,13 +2377,14 @@ cdcs_status cdcs_get_tuning(const cdcs_handle *h, cdcs_tuning *out) {
     }
     out->queue_us = h->plan.queue_us;
     out->buckets_us = h->plan.buckets_us;
+    out->parallel_us = h->plan.parallel_us;
     return CDCS_OK;
 }
 
 cdcs_status cdcs_set_projection_plan(cdcs_handle *h, int32_t persistent, int32_t threads, int32_t grid_req) {
     if (!h) return fail(CDCS_E_ARG, "NULL handle");
-    if (persistent != 0 && persistent != 1) return fail(CDCS_E_ARG, "persistent must be 0 or 1");
-    if (persistent) {
+    if (persistent < 0 || persistent > 2) return fail(CDCS_E_ARG, "persistent must be 0, 1 or 2");
+    if (persistent == 1) {
         if (threads != 256 && threads != 512) return fail(CDCS_E_ARG, "queue launches use 256 or 512 threads");
         const int grid_max = queue_grid(h, threads);
         if (grid_max < 1)
@@ -2347,12 +2396,14 @@ cdcs_status cdcs_set_projection_plan(cdcs_handle *h, int32_t persistent, int32_t
         HIP_OK(hipDeviceSynchronize());
         HIP_OK(hipMemset(h->ticket, 0, sizeof(unsigned long long)));
         h->plan.queue = true;
+        h->plan.parallel = false;
         h->plan.nt = threads;
         h->plan.grid = grid;
     } else {
         if (threads != 0 && threads != 64 && threads != 256 && threads != 512)
             return fail(CDCS_E_ARG, "threads must be 0, 64, 256 or 512");
         h->plan.queue = false;
+        h->plan.parallel = persistent == 2;
         if (threads != 0)
             for (Bucket &bk : h->buckets) bk.nt = proj_threads_ok(proj_bucket(bk.smax), threads) ? threads : 256;
     }

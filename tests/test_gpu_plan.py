@@ -71,6 +71,26 @@ def test_queue_tickets_stay_aligned_across_launch_kinds(torch, small):
     sol.close()
 
 
+def test_parallel_bucket_launches_give_the_same_bits(torch, small):
+    """The per-bucket launches on parallel streams run the same kernels on
+    the same cliques as in stream order: eager and graph-captured solves of
+    both plans agree bit for bit, and the plan is reported."""
+    prob, _ = small
+    sol = cdcs.Solver(prob)
+    out = {}
+    for parallel in (False, True):
+        sol.set_projection_plan(False, 256, parallel=parallel)
+        assert sol.tuning()["parallel_buckets"] == parallel and not sol.tuning()["persistent"]
+        for ce in (0, 10):
+            st = sol.new_state("primal")
+            sol.solve(st, form="primal", tol=0.0, max_iter=20, check_every=ce)
+            out[(parallel, ce)] = {k: st[k].clone() for k in ("x", "blk", "lam", "vw")}
+    for key in out:
+        for k in ("x", "blk", "lam", "vw"):
+            assert torch.equal(out[key][k], out[(False, 0)][k]), (key, k)
+    sol.close()
+
+
 def test_queue_and_bucket_launches_agree(torch, small):
     prob, _ = small
     out = []
@@ -88,8 +108,10 @@ def test_tuning_report_and_plan_errors(torch, small):
     prob, _ = small
     sol = cdcs.Solver(prob)
     t = sol.tuning()
-    assert t["queue_us"] > 0 and t["buckets_us"] > 0
-    assert t["persistent"] == (t["queue_us"] < t["buckets_us"])
+    assert t["queue_us"] > 0 and t["buckets_us"] > 0 and t["parallel_us"] > 0
+    # the fastest of the three forms
+    assert t["persistent"] == (t["queue_us"] < min(t["buckets_us"], t["parallel_us"]))
+    assert t["parallel_buckets"] == (not t["persistent"] and t["parallel_us"] < t["buckets_us"])
     assert sum(b["count"] for b in t["buckets"]) == prob.p
     assert [b["size"] for b in t["buckets"]] == sorted(b["size"] for b in t["buckets"])
     assert all(b["size"] in (16, 32, 48, 64, 80, 96, 112, 128) for b in t["buckets"])
