@@ -95,8 +95,9 @@ def algorithmic_bytes(sol, prob):
     import numpy as np
     m, nU, ns, p = sol.m, sol.nnz, sol.nslots, sol.p
     out = {
-        # L^-1 and L^-T (dense triangles, or CSR: 4 B column + 8 B value + 8 B gathered element), vectors
-        "trmv": (2 * sol.nnz_factor * (4 + 8 + 8) if sol.sparse_factor else 2 * (m * (m + 1) // 2) * 8) + 4 * m * 8,
+        # sparse: L^-1 and L^-T as CSR (4 B column + 8 B value + 8 B gathered element) and four vectors;
+        # dense: M^-1 as stored and read (m x m; its symmetry is not exploited), t in, y out
+        "trmv": (2 * sol.nnz_factor * (4 + 8 + 8) + 4 * m * 8 if sol.sparse_factor else m * m * 8 + 2 * m * 8),
         # x, lam in/out, x_k in/out, the per-slot x_k difference out, partials
         "project": nU * 8 + ns * (4 + 4 + 4 + 4 + 4) + p * 24,
         # per slot: its index, x_k, lam and x_k difference; per entry: the inverse-map

@@ -169,7 +169,8 @@ typedef struct {
 /* Sizes of a handle.  sparse_a = 1 if A is kept sparse (nnz_a coefficients),
  * 0 if it is stored densely (nnz_a = m * nnz).  sparse_factor = 1 if the
  * inverse Cholesky factor is kept as CSR (nnz_factor nonzeros in L^-1), 0 if
- * dense (nnz_factor = m (m + 1) / 2).  nnz_l > 0: the factor of
+ * it is dense (nnz_factor = m (m + 1) / 2, and the handle keeps the dense
+ * inverse M^-1 = L^-T L^-1 of A D^-1 A^T, m x m, in its place).  nnz_l > 0: the factor of
  * A D^-1 A^T was computed sparse (symbolic elimination order, then the
  * numeric factor on the device; no dense m x m matrix), with nnz_l nonzeros
  * in L; 0: it was factored dense. */
@@ -610,7 +611,8 @@ typedef enum {
     CDCS_K_PROJECT = 0,   /* fused gather + Jacobi projection + epilogue, all size buckets */
     CDCS_K_GEMV_AU = 1,   /* partials of A (w r1 / D)    (affine step, first half; without the
                              small reduction to t = A (w r1 / D) - r2 that follows it) */
-    CDCS_K_TRMV = 2,      /* y = L^-T (L^-1 t)           (two triangular products) */
+    CDCS_K_TRMV = 2,      /* y = M^-1 t                  (one product with the dense M^-1 = L^-T L^-1,
+                             or two with the sparse inverse factor L^-1 and its transpose) */
     CDCS_K_GEMV_ATY = 3,  /* x = (r1 - A^T y) / D        (affine step, second half) */
     CDCS_K_SCATTER = 4    /* r1 = sum_k H_k^T (...)      (right-hand side scatter) */
 } cdcs_kernel;

@@ -52,7 +52,7 @@ struct GraphKey {
 
 // The inverse-factor fields of Dev (Algorithm 1/2's factor or the HSDE one).
 struct FactorFields {
-    double *Linv = nullptr, *LinvT = nullptr;
+    double *Linv = nullptr, *LinvT = nullptr, *Minv = nullptr;
     int32_t sparse_linv = 0, spchol = 0;
     int64_t nnz_linv = 0, nnz_l = 0;
     int32_t *li_ptr = nullptr, *li_col = nullptr, *lt_ptr = nullptr, *lt_col = nullptr;
@@ -63,6 +63,7 @@ FactorFields get_factor(const Dev &d) {
     FactorFields f;
     f.Linv = d.Linv;
     f.LinvT = d.LinvT;
+    f.Minv = d.Minv;
     f.sparse_linv = d.sparse_linv;
     f.spchol = d.spchol;
     f.nnz_linv = d.nnz_linv;
@@ -79,6 +80,7 @@ FactorFields get_factor(const Dev &d) {
 void set_factor(Dev &d, const FactorFields &f) {
     d.Linv = f.Linv;
     d.LinvT = f.LinvT;
+    d.Minv = f.Minv;
     d.sparse_linv = f.sparse_linv;
     d.spchol = f.spchol;
     d.nnz_linv = f.nnz_linv;
@@ -858,7 +860,19 @@ cdcs_status factor_into(cdcs_handle *h, double shift, hipStream_t s) {
     if (info_h[0] != 0)
         return fail(CDCS_E_RANK,
                     "A D^-1 A^T is not positive definite (pivot " + std::to_string(info_h[1]) + "): A is rank deficient");
-    return compress_factors(h, s);
+    CK(compress_factors(h, s));
+    if (d.sparse_linv) return CDCS_OK;
+    // dense inverse factor: keep M^-1 = L^-T L^-1 instead, so each solve is one product
+    CK(h->alloc(&d.Minv, m * m));
+    launch_inv_product(d.LinvT, (int)m, d.Minv, s);
+    HIP_OK(hipStreamSynchronize(s));
+    for (double *p : {d.Linv, d.LinvT}) {
+        h->allocs.erase(std::remove(h->allocs.begin(), h->allocs.end(), (void *)p), h->allocs.end());
+        (void)hipFree(p);
+    }
+    d.Linv = nullptr;
+    d.LinvT = nullptr;
+    return CDCS_OK;
 }
 
 cdcs_status create_side_streams(cdcs_handle *h) {

@@ -222,8 +222,9 @@ struct Dev {
     double *li_val = nullptr;
     int32_t *lt_ptr = nullptr, *lt_col = nullptr;
     double *lt_val = nullptr;
-    double *Linv = nullptr;        // [m * m] row-major, L^-1 (lower)
-    double *LinvT = nullptr;       // [m * m] row-major, L^-T (upper)
+    double *Linv = nullptr;        // [m * m] row-major, L^-1 (lower); setup only (batch handles: per instance)
+    double *LinvT = nullptr;       // [m * m] row-major, L^-T (upper); setup only (batch handles: per instance)
+    double *Minv = nullptr;        // [m * m] row-major, M^-1 = L^-T L^-1 (dense factor of a single-SDP handle)
     int32_t *order = nullptr;      // [p_lds] cliques of at most kMaxLdsClique vertices, by decreasing size
     int32_t p_lds = 0;             // cliques projected in LDS (the others: big)
     int32_t smax_lds = 0;          // largest of them
@@ -395,6 +396,7 @@ void launch_sp_syrk(const Dev &d, const int32_t *tid, double *M, hipStream_t s);
 void launch_potrf(double *M, int m, double *diag0, int32_t *info, hipStream_t s);
 void launch_add_diag(double *M, int m, double shift, hipStream_t s);
 void launch_trtri(const double *L, int m, double *LinvT, double *Linv, hipStream_t s);
+void launch_inv_product(const double *LinvT, int m, double *Minv, hipStream_t s);
 // Nonzeros of each row of a dense m x m triangle (lower: columns <= row,
 // upper: columns >= row) -> cnt[m]; then the CSR copy given ptr[m+1].
 void launch_tri_count(const double *T, int m, int upper, int32_t *cnt, hipStream_t s);

@@ -503,18 +503,19 @@ __global__ __launch_bounds__(kNT) void k_reduce_t(const double *__restrict__ tpa
     t[i] = sum - r2scale * r2i;
 }
 
-// Triangular product out = T vin over the row range [lo, hi) of each row:
-// lower (T = L^-1): [0, i]; upper (T = L^-T): [i, m).  One workgroup per row,
-// its elements spread over all kNT threads (coalesced), so every wave waits on
-// only a few loads and enough of them are in flight to keep HBM busy; rows are
+// Product out = T vin of a row-major m x m matrix over the column range
+// [lo, hi) of each row: lower triangle (mode 0): [0, i]; upper (mode 1):
+// [i, m); full (mode 2, T = M^-1): [0, m).  One workgroup per row, its elements
+// spread over all kNT threads (coalesced), so every wave waits on only a few
+// loads and enough of them are in flight to keep HBM busy; triangle rows are
 // dispatched longest first.  Fixed-order block sum.
-__global__ __launch_bounds__(kNT) void k_trmv(const double *__restrict__ T, int m, int upper,
+__global__ __launch_bounds__(kNT) void k_trmv(const double *__restrict__ T, int m, int mode,
                                               const double *__restrict__ vin, double *__restrict__ vout,
                                               const Ctl *ctl) {
     __shared__ double red[kNT / 64];
     if (ctl != nullptr && ctl->stop) return;
-    const int row = upper ? (int)blockIdx.x : m - 1 - (int)blockIdx.x;
-    const int lo = upper ? row : 0, hi = upper ? m : row + 1;
+    const int row = mode != 0 ? (int)blockIdx.x : m - 1 - (int)blockIdx.x;
+    const int lo = mode == 1 ? row : 0, hi = mode == 0 ? row + 1 : m;
     const double *tr = T + (int64_t)row * m;
     double a0 = 0.0, a1 = 0.0;
     int j = lo + (int)threadIdx.x;
@@ -828,10 +829,8 @@ void launch_affine_part(const Dev &d, int part, const double *r2, double r2scale
         hipLaunchKernelGGL(k_csr_mv, dim3(tb), dim3(kNT), 0, s, (const int32_t *)d.lt_ptr, (const int32_t *)d.lt_col,
                            (const double *)d.lt_val, (const double *)d.y1, y, d.m, ctl);
     } else if (part == 1) {
-        hipLaunchKernelGGL(k_trmv, dim3(d.m), dim3(kNT), 0, s, (const double *)d.Linv, d.m, 0, (const double *)d.t,
-                           d.y1, ctl);
-        hipLaunchKernelGGL(k_trmv, dim3(d.m), dim3(kNT), 0, s, (const double *)d.LinvT, d.m, 1, (const double *)d.y1,
-                           y, ctl);
+        hipLaunchKernelGGL(k_trmv, dim3(d.m), dim3(kNT), 0, s, (const double *)d.Minv, d.m, 2, (const double *)d.t, y,
+                           ctl);
     } else {
         const unsigned gb = (unsigned)((d.nU + kAtyRows - 1) / kAtyRows);
         hipLaunchKernelGGL(k_gemv_ATy, dim3(gb), dim3(kNT), 0, s, (const float *)d.AwT, d.ldM, (const double *)y,

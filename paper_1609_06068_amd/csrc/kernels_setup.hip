@@ -5,10 +5,12 @@
 //   M = A diag(w / D) A^T = Aw diag(s2) Aw^T     (Aw = w A, s2 = 1 / (w D)), FP64
 //   M = L L^T                                    (blocked right-looking Cholesky)
 //   L^-1 and L^-T                                (blocked, 64-row block rows)
+//   M^-1 = L^-T L^-1                             (when L^-1 does not stay sparse)
 //
-// The solve y = M^-1 t of each iteration is then two triangular matrix-vector
-// products with the cached inverse factor, which spreads over the whole GPU
-// instead of a length-m chain of dependent substitution steps.
+// The solve y = M^-1 t of each iteration is then one matrix-vector product
+// with the cached inverse (or two sparse triangular ones with the inverse
+// factor), which spreads over the whole GPU instead of a length-m chain of
+// dependent substitution steps.
 #include "cdcs_internal.h"
 
 namespace cdcs {
@@ -69,6 +71,58 @@ __global__ __launch_bounds__(256) void k_syrk(const float *__restrict__ Aw, int6
         for (int b = 0; b < 4; ++b) {
             const int i = i0 + ty * 4 + a, j = j0 + tx * 4 + b;
             if (i < m && j < m) M[(int64_t)i * m + j] = acc[a][b];
+        }
+}
+
+// Minv[i][j] = Minv[j][i] = sum_k LinvT[i][k] LinvT[j][k] over i >= j tiles,
+// i.e. (L^-T L^-1)[i][j] = (L L^T)^-1[i][j].  L^-T is upper triangular, so the
+// sum starts at the row tile's first column; both triangles are written, from
+// the same sums, so Minv is exactly symmetric.
+__global__ __launch_bounds__(256) void k_inv_product(const double *__restrict__ LinvT, int m,
+                                                     double *__restrict__ Minv) {
+    __shared__ double As[TS][KC + 1];
+    __shared__ double Bs[TS][KC + 1];
+    const int tb = blockIdx.x;
+    const int I = tri_row_i(tb), J = tb - I * (I + 1) / 2;
+    const int i0 = I * TS, j0 = J * TS;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int e0 = i0; e0 < m; e0 += KC) {
+        for (int idx = threadIdx.x; idx < TS * KC; idx += 256) {
+            const int r = idx / KC, q = idx - r * KC;
+            const int e = e0 + q;
+            const int ri = i0 + r, rj = j0 + r;
+            As[r][q] = (ri < m && e < m) ? LinvT[(int64_t)ri * m + e] : 0.0;
+            Bs[r][q] = (rj < m && e < m) ? LinvT[(int64_t)rj * m + e] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int q = 0; q < KC; ++q) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = As[ty * 4 + a][q];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bv[b] = Bs[tx * 4 + b][q];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = i0 + ty * 4 + a, j = j0 + tx * 4 + b;
+            if (i < m && j < m) {
+                Minv[(int64_t)i * m + j] = acc[a][b];
+                Minv[(int64_t)j * m + i] = acc[a][b];
+            }
         }
 }
 
@@ -345,6 +399,11 @@ __global__ void k_transpose(const double *__restrict__ in, int m, double *__rest
 void launch_syrk(const float *Aw, int64_t ld, const double *s2, int m, double *M, hipStream_t s) {
     const int T = (m + TS - 1) / TS;
     hipLaunchKernelGGL(k_syrk, dim3(T * (T + 1) / 2), dim3(256), 0, s, Aw, ld, s2, m, M);
+}
+
+void launch_inv_product(const double *LinvT, int m, double *Minv, hipStream_t s) {
+    const int T = (m + TS - 1) / TS;
+    hipLaunchKernelGGL(k_inv_product, dim3(T * (T + 1) / 2), dim3(256), 0, s, LinvT, m, Minv);
 }
 
 void launch_add_diag(double *M, int m, double shift, hipStream_t s) {
