@@ -217,7 +217,8 @@ cdcs_status cdcs_chordal_extension(const cdcs_pattern *pattern, int64_t *nfill, 
  * cliques, builds the entry selectors H_k and the overlap counts
  * D = sum_k H_k^T H_k (Sec. III-B.1), uploads the data, factors
  * M = A diag(w/D) A^T (Cholesky, FP64, on the device) and caches the inverse
- * triangular factor for the affine projection, and times the launch forms of
+ * factor for the affine projection (as CSR when sparse, else the dense inverse
+ * M^-1 = L^-T L^-1 formed from it), and times the launch forms of
  * the batched projection (cdcs_get_tuning).  The factor is sparse when A is
  * kept sparse and the inverse factor stays sparse: a symbolic step on the
  * host orders M's rows (constraints sharing a pattern entry are adjacent;
@@ -595,7 +596,7 @@ cdcs_status cdcs_hsde_solution(cdcs_handle *h, const cdcs_hsde_state *st, int32_
 
 /* cdcs_hsde_solve with eager launches and HIP events around each kernel kind
  * of every iteration, as cdcs_admm_solve_timed does for Algorithms 1 and 2
- * (kinds: the projection, the A u partials, the triangular products, A^T y,
+ * (kinds: the projection, the A u partials, the solve with M^-1, A^T y,
  * the scatter; the tau row, the update of x and the check run unbracketed).
  * The iterates are those of cdcs_hsde_solve with the same state and options.
  * Errors: those of cdcs_hsde_solve; CDCS_E_ARG for NULL kernel_ms or launches. */
