@@ -629,7 +629,9 @@ typedef enum {
  * indexed by cdcs_kernel, owned by the caller; CDCS_K_GEMV_AU without the
  * small reduction that follows it).  Batch handles: CDCS_K_GEMV_AU covers the
  * whole affine step, CDCS_K_TRMV and CDCS_K_GEMV_ATY stay 0.  The residual
- * checks run unbracketed.  Synchronises on stream.
+ * checks run unbracketed, except Algorithm 1's on a dense single-SDP handle,
+ * which runs as the first workgroup of the A u launch (overlapping the
+ * product) and so falls inside CDCS_K_GEMV_AU.  Synchronises on stream.
  * Errors: those of cdcs_admm_solve; CDCS_E_ARG for NULL kernel_ms or launches.
  */
 cdcs_status cdcs_admm_solve_timed(cdcs_handle *h, const cdcs_state *st, const cdcs_options *opts,

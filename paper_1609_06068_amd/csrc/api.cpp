@@ -1503,22 +1503,25 @@ void enqueue_iteration(cdcs_handle *h, const cdcs_state *st, int form, double rh
         launch_bcheck_dual(d, rho, s);
         return;
     }
-    // the affine step (t, then y = L^-T L^-1 t, then x) part by part
-    auto affine = [&](double r2scale) {
-        timed(CDCS_K_GEMV_AU, [&] { launch_affine_part(d, 0, d.b, r2scale, st->x, st->y, d.ctl, s); });
+    // the affine step (t, then y = L^-T L^-1 t, then x) part by part; with
+    // check_au, Algorithm 1's residual check runs in the A u launch
+    auto affine = [&](double r2scale, bool check_au) {
+        if (check_au) timed(CDCS_K_GEMV_AU, [&] { launch_au_with_check(d, rho, d.ctl, s); });
+        else timed(CDCS_K_GEMV_AU, [&] { launch_affine_part(d, 0, d.b, r2scale, st->x, st->y, d.ctl, s); });
         launch_affine_part(d, 3, d.b, r2scale, st->x, st->y, d.ctl, s);
         timed(CDCS_K_TRMV, [&] { launch_affine_part(d, 1, d.b, r2scale, st->x, st->y, d.ctl, s); });
         timed(CDCS_K_GEMV_ATY, [&] { launch_affine_part(d, 2, d.b, r2scale, st->x, st->y, d.ctl, s); });
     };
     if (form == CDCS_PRIMAL) {
         timed(CDCS_K_SCATTER, [&] { launch_scatter_primal(d, st->blk, st->lam, rho, s); });
-        launch_check_primal(d, rho, s);
-        affine(1.0);
+        const bool check_au = check_in_au(d);
+        if (!check_au) launch_check_primal(d, rho, s);
+        affine(1.0, check_au);
         timed(CDCS_K_PROJECT, [&] { launch_projection(h, PROJ_PRIMAL, st, rho, s); });
     } else {
         timed(CDCS_K_PROJECT, [&] { launch_projection(h, PROJ_DUAL, st, rho, s); });
         timed(CDCS_K_SCATTER, [&] { launch_scatter_dual(d, st->blk, st->lam, rho, s); });
-        affine(-1.0 / rho);
+        affine(-1.0 / rho, false);
         launch_vupdate(d, st->x, st->blk, st->lam, st->v, rho, s);
         launch_check_dual(d, rho, s);
     }

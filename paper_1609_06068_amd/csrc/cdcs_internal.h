@@ -311,6 +311,10 @@ int vupdate_blocks(const Dev &d);
 void launch_reset_ctl(const Dev &d, int max_iter, double tol, hipStream_t s);
 void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s);
 void launch_check_primal(const Dev &d, double rho, hipStream_t s);
+// true when Algorithm 1's residual check can run as the first workgroup of
+// the dense A u launch (launch_au_with_check) instead of a launch of its own
+bool check_in_au(const Dev &d);
+void launch_au_with_check(const Dev &d, double rho, const Ctl *ctl, hipStream_t s);
 void launch_scatter_dual(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s);
 void launch_vupdate(const Dev &d, const double *x, const float *blk, float *lam, float *v, double rho,
                     hipStream_t s);

@@ -187,11 +187,11 @@ __global__ __launch_bounds__(kNT) void k_scatter_primal(const int32_t *__restric
 // (the buffers always hold p and nsblk entries; before the first iteration
 // their values are not used).  Every thread reads the control block before a
 // barrier that precedes any write to it, so all waves take the same branches.
+// Run by one workgroup of CNT threads.
 template <int CNT>
-__global__ __launch_bounds__(CNT) void k_check_primal(const double *__restrict__ cpart, int p,
-                                                      const double *__restrict__ spart, int nsblk, double rho,
-                                                      double *__restrict__ hist, int hist_cap, Ctl *ctl) {
-    __shared__ double red[5][CNT / 64];
+__device__ __forceinline__ void check_primal_block(const double *__restrict__ cpart, int p, const double *__restrict__ spart,
+                                   int nsblk, double rho, double *__restrict__ hist, int hist_cap, Ctl *ctl,
+                                   double (*red)[CNT / 64]) {
     const int tid = threadIdx.x;
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |x_k - H_k x|^2, |H_k x|^2, |x_k|^2, |dS|^2, |S_lam|^2
 #pragma unroll 4
@@ -241,6 +241,14 @@ __global__ __launch_bounds__(CNT) void k_check_primal(const double *__restrict__
         if (n >= max_iter) ctl->stop = 2;
         else ctl->iter = n + 1;
     }
+}
+
+template <int CNT>
+__global__ __launch_bounds__(CNT) void k_check_primal(const double *__restrict__ cpart, int p,
+                                                      const double *__restrict__ spart, int nsblk, double rho,
+                                                      double *__restrict__ hist, int hist_cap, Ctl *ctl) {
+    __shared__ double red[5][CNT / 64];
+    check_primal_block<CNT>(cpart, p, spart, nsblk, rho, hist, hist_cap, ctl, red);
 }
 
 // Alg. 2 right-hand side r1 = c - sum_k H_k^T (z_k + lam_k / rho), u = r1 / D.
@@ -450,17 +458,41 @@ __global__ __launch_bounds__(kNT) void k_sp_xcorr(const int32_t *__restrict__ tc
     x[e] = u[e] - s2[e] * acc;
 }
 
+// Algorithm 1's residual check, run by the first workgroup of the A u launch
+// that follows it (ck.ctl == nullptr: none).
+struct CheckArgs {
+    const double *cpart;
+    const double *spart;
+    double *hist;
+    Ctl *ctl;
+    double rho;
+    int p, nsblk, hist_cap;
+};
+
 // Split-K partial products of t = A (w u): tpart[slice][row] is the dot
 // product of row `row` of the FP32 matrix Aw (= w A, row-major, leading
 // dimension ld, zero padded) with u over the columns of one slice.  RG rows per
 // workgroup, so each u slice is read once per RG rows; FP64 accumulation.
+// With a check (ck.ctl set) the grid has one more column of workgroups in
+// front: workgroup (0, 0) runs the residual check of the iteration before
+// (dispatched first, so it overlaps the product), the rest of that column
+// returns.  The product only writes tpart, which the reduction that follows
+// reads only when the check did not stop the solve, so it does not matter
+// whether a product workgroup starts before or after the check's decision.
 template <int RG>
-__global__ __launch_bounds__(kNT) void k_gemv_Au(const float *__restrict__ Aw, int64_t ld,
-                                                 const double *__restrict__ u, double *__restrict__ tpart, int m,
-                                                 int64_t slice_cols, const Ctl *ctl) {
+__global__ __launch_bounds__(kNT, 5) void k_gemv_Au(const float *__restrict__ Aw, int64_t ld,
+                                                    const double *__restrict__ u, double *__restrict__ tpart, int m,
+                                                    int64_t slice_cols, const Ctl *ctl, CheckArgs ck) {
     __shared__ double red[kNT / 64];
+    __shared__ double ckred[5][kNT / 64];
+    const int lead = ck.ctl != nullptr ? 1 : 0;
+    if (lead && blockIdx.x == 0) {
+        if (blockIdx.y == 0)
+            check_primal_block<kNT>(ck.cpart, ck.p, ck.spart, ck.nsblk, ck.rho, ck.hist, ck.hist_cap, ck.ctl, ckred);
+        return;
+    }
     if (ctl != nullptr && ctl->stop) return;
-    const int row0 = blockIdx.x * RG;
+    const int row0 = ((int)blockIdx.x - lead) * RG;
     const int64_t c0 = (int64_t)blockIdx.y * slice_cols;
     const int64_t c1 = min(ld, c0 + slice_cols);
     double acc[RG];
@@ -753,6 +785,8 @@ void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, dou
                        rho, (const Ctl *)d.ctl);
 }
 
+bool check_in_au(const Dev &d) { return !d.sparse && d.p + d.nvb + pscatter_blocks(d) <= 8192; }
+
 void launch_check_primal(const Dev &d, double rho, hipStream_t s) {
     // partial sums of the cliques, then of the vector cones' blocks
     const int ncp = d.p + d.nvb;
@@ -797,6 +831,22 @@ int gemv_slices(const Dev &d) {
     return (int)std::min<int64_t>(kGemvSlices, ncb);
 }
 
+void launch_gemv_au(const Dev &d, const Ctl *ctl, const CheckArgs &ck, hipStream_t s) {
+    constexpr int RG = 8;
+    const int ns = gemv_slices(d);
+    const int64_t ncb = (d.ldU + 1023) / 1024;
+    const int64_t slice_cols = (ncb + ns - 1) / ns * 1024;
+    const int lead = ck.ctl != nullptr ? 1 : 0;
+    hipLaunchKernelGGL((k_gemv_Au<RG>), dim3((d.m + RG - 1) / RG + lead, ns), dim3(kNT), 0, s, (const float *)d.Aw,
+                       d.ldU, (const double *)d.u, d.tpart, d.m, slice_cols, ctl, ck);
+}
+
+void launch_au_with_check(const Dev &d, double rho, const Ctl *ctl, hipStream_t s) {
+    CheckArgs ck{(const double *)d.cpart, (const double *)d.spart, d.hist, d.ctl, rho, d.p + d.nvb,
+                 pscatter_blocks(d), d.hist_cap};
+    launch_gemv_au(d, ctl, ck, s);
+}
+
 void launch_affine_part(const Dev &d, int part, const double *r2, double r2scale, double *x, double *y,
                         const Ctl *ctl, hipStream_t s) {
     if (d.sparse && part == 0) {
@@ -813,12 +863,7 @@ void launch_affine_part(const Dev &d, int part, const double *r2, double r2scale
                                (const int32_t *)d.tc_ptr, (const int32_t *)d.tc_row, (const double *)d.tc_val,
                                (const double *)y, (const double *)d.u, (const double *)d.s2, x, d.ntc, ctl);
     } else if (part == 0) {
-        constexpr int RG = 8;
-        const int ns = gemv_slices(d);
-        const int64_t ncb = (d.ldU + 1023) / 1024;
-        const int64_t slice_cols = (ncb + ns - 1) / ns * 1024;
-        hipLaunchKernelGGL((k_gemv_Au<RG>), dim3((d.m + RG - 1) / RG, ns), dim3(kNT), 0, s, (const float *)d.Aw,
-                           d.ldU, (const double *)d.u, d.tpart, d.m, slice_cols, ctl);
+        launch_gemv_au(d, ctl, CheckArgs{}, s);
     } else if (part == 3) {
         hipLaunchKernelGGL(k_reduce_t, dim3((d.m + kNT - 1) / kNT), dim3(kNT), 0, s, (const double *)d.tpart,
                            gemv_slices(d), r2, r2scale, d.t, d.m, ctl);
