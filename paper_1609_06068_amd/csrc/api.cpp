@@ -1477,8 +1477,12 @@ void enqueue_iteration(cdcs_handle *h, const cdcs_state *st, int form, double rh
         HsdeDev &hs = h->hs;
         double *tk = h->hs_tk;
         timed(CDCS_K_SCATTER, [&] { launch_hsde_scatter(d, hs, st->blk, st->lam, tk, s); });
-        launch_hsde_check(d, hs, tk, s);
-        timed(CDCS_K_GEMV_AU, [&] { launch_affine_part(dh, 0, st->y, -1.0, hs.a, hs.yh, d.ctl, s); });
+        if (check_in_au(d)) {  // the check runs in the A u launch's first workgroup
+            timed(CDCS_K_GEMV_AU, [&] { launch_au_with_hsde_check(dh, d, hs, tk, d.ctl, s); });
+        } else {
+            launch_hsde_check(d, hs, tk, s);
+            timed(CDCS_K_GEMV_AU, [&] { launch_affine_part(dh, 0, st->y, -1.0, hs.a, hs.yh, d.ctl, s); });
+        }
         launch_affine_part(dh, 3, st->y, -1.0, hs.a, hs.yh, d.ctl, s);
         timed(CDCS_K_TRMV, [&] { launch_affine_part(dh, 1, st->y, -1.0, hs.a, hs.yh, d.ctl, s); });
         timed(CDCS_K_GEMV_ATY, [&] { launch_affine_part(dh, 2, st->y, -1.0, hs.a, hs.yh, d.ctl, s); });

@@ -293,6 +293,10 @@ void launch_hsde_init(const Dev &d, double *x, double *y, float *sl, float *z, d
 void launch_hsde_scatter(const Dev &d, const HsdeDev &hs, const float *sl, const float *z, const double *tk,
                          hipStream_t s);
 void launch_hsde_check(const Dev &d, const HsdeDev &hs, const double *tk, hipStream_t s);
+// the HSDE check in the first workgroup of the A u launch of its linear step
+// (dh: the HSDE's Dev, d: the handle's), when check_in_au(d)
+void launch_au_with_hsde_check(const Dev &dh, const Dev &d, const HsdeDev &hs, const double *tk, const Ctl *ctl,
+                               hipStream_t s);
 void launch_hsde_tau(const Dev &d, const HsdeDev &hs, double *y, double *tk, hipStream_t s);
 void launch_hsde_axpy(const Dev &d, const HsdeDev &hs, hipStream_t s);
 void launch_hsde_solution(const Dev &d, const HsdeDev &hs, int which, const double *x, const double *y,

@@ -189,9 +189,10 @@ __global__ __launch_bounds__(kNT) void k_scatter_primal(const int32_t *__restric
 // barrier that precedes any write to it, so all waves take the same branches.
 // Run by one workgroup of CNT threads.
 template <int CNT>
-__device__ __forceinline__ void check_primal_block(const double *__restrict__ cpart, int p, const double *__restrict__ spart,
-                                   int nsblk, double rho, double *__restrict__ hist, int hist_cap, Ctl *ctl,
-                                   double (*red)[CNT / 64]) {
+__device__ __forceinline__ void check_primal_block(const double *__restrict__ cpart, int p,
+                                                   const double *__restrict__ spart, int nsblk, double rho,
+                                                   double *__restrict__ hist, int hist_cap, Ctl *ctl,
+                                                   double (*red)[CNT / 64]) {
     const int tid = threadIdx.x;
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |x_k - H_k x|^2, |H_k x|^2, |x_k|^2, |dS|^2, |S_lam|^2
 #pragma unroll 4
@@ -249,6 +250,86 @@ __global__ __launch_bounds__(CNT) void k_check_primal(const double *__restrict__
                                                       double *__restrict__ hist, int hist_cap, Ctl *ctl) {
     __shared__ double red[5][CNT / 64];
     check_primal_block<CNT>(cpart, p, spart, nsblk, rho, hist, hist_cap, ctl, red);
+}
+
+// HSDE check of the iterate of iteration n = ctl->iter (n >= 1), then start
+// the next one.  sc[6] = ||(y' - y) + (ut - tau') b||^2, sc[7] = ||(y' - y) +
+// ut b||^2 (= ||A(x')||^2), sc[8] = b^T y', sc[9] = <c, x'>_w come from the tau
+// kernel; the projection's partial sums give ||s' - H x'||^2 and the HSDE
+// scatter's (hpart) the dual residual and ||A^T y'||^2.  Writes the three
+// ratios of the solved test to sc[10..12] and the history; stop 1 solved,
+// 2 iteration limit, 3 non-finite, 4 primal infeasible (certificate y'),
+// 5 dual infeasible (certificate x').  Run by one workgroup of CNT threads.
+template <int CNT>
+__device__ __forceinline__ void hsde_check_block(const double *__restrict__ cpart, int ncp,
+                                                 const double *__restrict__ hpart, int nhb, double *__restrict__ sc,
+                                                 const double *__restrict__ tk, double *__restrict__ hist,
+                                                 int hist_cap, Ctl *ctl, double (*red)[CNT / 64]) {
+    const int tid = threadIdx.x;
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // consensus, dual residual, |A^T y'|^2
+    for (int k = tid; k < ncp; k += CNT) v[0] += cpart[4 * (int64_t)k];
+    for (int b = tid; b < nhb; b += CNT) {
+        v[1] += hpart[2 * (int64_t)b + 0];
+        v[2] += hpart[2 * (int64_t)b + 1];
+    }
+    const int stop = ctl->stop, n = ctl->iter, max_iter = ctl->max_iter;
+    const double tol = ctl->tol;
+    __syncthreads();
+    if (stop) return;
+    if (n >= 1) {
+        check_sum5_d<CNT>(v, red);
+        const double cons = v[0], rd2 = v[1], at2 = v[2];
+        if (tid == 0) {
+            const double tau = tk[0];
+            const double nb = sc[2], nc = sc[3], by = sc[8], cx = sc[9];
+            const double pri = sqrt(sc[6] + cons), ray = sqrt(sc[7] + cons);
+            const double inf = __builtin_huge_val();
+            const double rp = tau > 0.0 ? pri / (tau * (1.0 + nb)) : inf;
+            const double rdv = tau > 0.0 ? sqrt(rd2) / (tau * (1.0 + nc)) : inf;
+            const double gden = tau + fabs(cx) + fabs(by);
+            const double gp = gden > 0.0 ? fabs(cx + by) / gden : 0.0;
+            sc[10] = rp;
+            sc[11] = rdv;
+            sc[12] = gp;
+            ctl->eps_p = rp;
+            ctl->eps_d = fmax(rdv, gp);
+            if (n - 1 < hist_cap) {
+                hist[3 * (int64_t)(n - 1) + 0] = rp;
+                hist[3 * (int64_t)(n - 1) + 1] = rdv;
+                hist[3 * (int64_t)(n - 1) + 2] = gp;
+            }
+            if (!(isfinite(pri) && isfinite(rd2) && isfinite(at2) && isfinite(by) && isfinite(cx) &&
+                  isfinite(tau) && isfinite(tk[1]))) {
+                ctl->stop = 3;
+                return;
+            }
+            if (tau > 0.0 && fmax(rp, fmax(rdv, gp)) <= tol) {
+                ctl->stop = 1;
+                return;
+            }
+            if (by < 0.0 && sqrt(at2) * nb <= tol * (-by)) {
+                ctl->stop = 4;
+                return;
+            }
+            if (cx < 0.0 && ray * nc <= tol * (-cx)) {
+                ctl->stop = 5;
+                return;
+            }
+        }
+    }
+    if (tid == 0) {
+        if (n >= max_iter) ctl->stop = 2;
+        else ctl->iter = n + 1;
+    }
+}
+
+template <int CNT>
+__global__ __launch_bounds__(CNT) void k_hsde_check(const double *__restrict__ cpart, int ncp,
+                                                    const double *__restrict__ hpart, int nhb, double *__restrict__ sc,
+                                                    const double *__restrict__ tk, double *__restrict__ hist,
+                                                    int hist_cap, Ctl *ctl) {
+    __shared__ double red[5][CNT / 64];
+    hsde_check_block<CNT>(cpart, ncp, hpart, nhb, sc, tk, hist, hist_cap, ctl, red);
 }
 
 // Alg. 2 right-hand side r1 = c - sum_k H_k^T (z_k + lam_k / rho), u = r1 / D.
@@ -458,15 +539,17 @@ __global__ __launch_bounds__(kNT) void k_sp_xcorr(const int32_t *__restrict__ tc
     x[e] = u[e] - s2[e] * acc;
 }
 
-// Algorithm 1's residual check, run by the first workgroup of the A u launch
-// that follows it (ck.ctl == nullptr: none).
+// The residual check (Algorithm 1's, or the HSDE's when sc is set) run by the
+// first workgroup of the A u launch that follows it (ctl == nullptr: none).
 struct CheckArgs {
     const double *cpart;
-    const double *spart;
+    const double *spart;  // the scatter's partial sums (HSDE: hpart)
     double *hist;
     Ctl *ctl;
     double rho;
     int p, nsblk, hist_cap;
+    double *sc;           // HSDE solved-test scalars, or nullptr
+    const double *tk;     // HSDE (tau, kappa)
 };
 
 // Split-K partial products of t = A (w u): tpart[slice][row] is the dot
@@ -487,8 +570,14 @@ __global__ __launch_bounds__(kNT, 5) void k_gemv_Au(const float *__restrict__ Aw
     __shared__ double ckred[5][kNT / 64];
     const int lead = ck.ctl != nullptr ? 1 : 0;
     if (lead && blockIdx.x == 0) {
-        if (blockIdx.y == 0)
-            check_primal_block<kNT>(ck.cpart, ck.p, ck.spart, ck.nsblk, ck.rho, ck.hist, ck.hist_cap, ck.ctl, ckred);
+        if (blockIdx.y == 0) {
+            if (ck.sc != nullptr)
+                hsde_check_block<kNT>(ck.cpart, ck.p, ck.spart, ck.nsblk, ck.sc, ck.tk, ck.hist, ck.hist_cap, ck.ctl,
+                                      ckred);
+            else
+                check_primal_block<kNT>(ck.cpart, ck.p, ck.spart, ck.nsblk, ck.rho, ck.hist, ck.hist_cap, ck.ctl,
+                                        ckred);
+        }
         return;
     }
     if (ctl != nullptr && ctl->stop) return;
@@ -843,8 +932,25 @@ void launch_gemv_au(const Dev &d, const Ctl *ctl, const CheckArgs &ck, hipStream
 
 void launch_au_with_check(const Dev &d, double rho, const Ctl *ctl, hipStream_t s) {
     CheckArgs ck{(const double *)d.cpart, (const double *)d.spart, d.hist, d.ctl, rho, d.p + d.nvb,
-                 pscatter_blocks(d), d.hist_cap};
+                 pscatter_blocks(d), d.hist_cap, nullptr, nullptr};
     launch_gemv_au(d, ctl, ck, s);
+}
+
+void launch_au_with_hsde_check(const Dev &dh, const Dev &d, const HsdeDev &hs, const double *tk, const Ctl *ctl,
+                               hipStream_t s) {
+    CheckArgs ck{(const double *)d.cpart, (const double *)hs.hpart, hs.hist, d.ctl, 0.0, d.p + d.nvb,
+                 pscatter_blocks(d), hs.hist_cap, hs.sc, tk};
+    launch_gemv_au(dh, ctl, ck, s);
+}
+
+void launch_hsde_check(const Dev &d, const HsdeDev &hs, const double *tk, hipStream_t s) {
+    const int ncp = d.p + d.nvb, nhb = pscatter_blocks(d);
+    if (ncp + nhb > 8192)
+        hipLaunchKernelGGL(k_hsde_check<1024>, dim3(1), dim3(1024), 0, s, (const double *)d.cpart, ncp,
+                           (const double *)hs.hpart, nhb, hs.sc, tk, hs.hist, hs.hist_cap, d.ctl);
+    else
+        hipLaunchKernelGGL(k_hsde_check<kNT>, dim3(1), dim3(kNT), 0, s, (const double *)d.cpart, ncp,
+                           (const double *)hs.hpart, nhb, hs.sc, tk, hs.hist, hs.hist_cap, d.ctl);
 }
 
 void launch_affine_part(const Dev &d, int part, const double *r2, double r2scale, double *x, double *y,

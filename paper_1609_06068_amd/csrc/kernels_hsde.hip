@@ -228,76 +228,6 @@ __global__ __launch_bounds__(kNT) void k_hsde_scatter(const int32_t *__restrict_
     }
 }
 
-// Check of the iterate of iteration n = ctl->iter (n >= 1), then start the
-// next one.  sc[6] = ||(y' - y) + (ut - tau') b||^2, sc[7] = ||(y' - y) + ut b||^2
-// (= ||A(x')||^2), sc[8] = b^T y', sc[9] = <c, x'>_w come from the tau
-// kernel; the projection's partial sums give ||s' - H x'||^2.  Writes the
-// three ratios of the solved test to sc[10..12] and the history.
-template <int CNT>
-__global__ __launch_bounds__(CNT) void k_hsde_check(const double *__restrict__ cpart, int ncp,
-                                                    const double *__restrict__ hpart, int nhb, double *__restrict__ sc,
-                                                    const double *__restrict__ tk, double *__restrict__ hist,
-                                                    int hist_cap, Ctl *ctl) {
-    __shared__ double red[CNT / 64];
-    const int tid = threadIdx.x;
-    double cons = 0.0, rd2 = 0.0, at2 = 0.0;
-    for (int k = tid; k < ncp; k += CNT) cons += cpart[4 * (int64_t)k];
-    for (int b = tid; b < nhb; b += CNT) {
-        rd2 += hpart[2 * (int64_t)b + 0];
-        at2 += hpart[2 * (int64_t)b + 1];
-    }
-    const int stop = ctl->stop, n = ctl->iter, max_iter = ctl->max_iter;
-    const double tol = ctl->tol;
-    __syncthreads();
-    if (stop) return;
-    if (n >= 1) {
-        cons = block_sum<CNT>(cons, red);
-        rd2 = block_sum<CNT>(rd2, red);
-        at2 = block_sum<CNT>(at2, red);
-        if (tid == 0) {
-            const double tau = tk[0];
-            const double nb = sc[2], nc = sc[3], by = sc[8], cx = sc[9];
-            const double pri = sqrt(sc[6] + cons), ray = sqrt(sc[7] + cons);
-            const double inf = __builtin_huge_val();
-            const double rp = tau > 0.0 ? pri / (tau * (1.0 + nb)) : inf;
-            const double rdv = tau > 0.0 ? sqrt(rd2) / (tau * (1.0 + nc)) : inf;
-            const double gden = tau + fabs(cx) + fabs(by);
-            const double gp = gden > 0.0 ? fabs(cx + by) / gden : 0.0;
-            sc[10] = rp;
-            sc[11] = rdv;
-            sc[12] = gp;
-            ctl->eps_p = rp;
-            ctl->eps_d = fmax(rdv, gp);
-            if (n - 1 < hist_cap) {
-                hist[3 * (int64_t)(n - 1) + 0] = rp;
-                hist[3 * (int64_t)(n - 1) + 1] = rdv;
-                hist[3 * (int64_t)(n - 1) + 2] = gp;
-            }
-            if (!(isfinite(pri) && isfinite(rd2) && isfinite(at2) && isfinite(by) && isfinite(cx) &&
-                  isfinite(tau) && isfinite(tk[1]))) {
-                ctl->stop = 3;
-                return;
-            }
-            if (tau > 0.0 && fmax(rp, fmax(rdv, gp)) <= tol) {
-                ctl->stop = 1;
-                return;
-            }
-            if (by < 0.0 && sqrt(at2) * nb <= tol * (-by)) {
-                ctl->stop = 4;
-                return;
-            }
-            if (cx < 0.0 && ray * nc <= tol * (-cx)) {
-                ctl->stop = 5;
-                return;
-            }
-        }
-    }
-    if (tid == 0) {
-        if (n >= max_iter) ctl->stop = 2;
-        else ctl->iter = n + 1;
-    }
-}
-
 // Partial sums of <c, a>_w, kDotPer * kNT entries per block.
 __global__ __launch_bounds__(kNT) void k_hsde_dot(const double *__restrict__ c, const double *__restrict__ a,
                                                   const uint32_t *__restrict__ wbits, double *__restrict__ dpart,
@@ -423,16 +353,6 @@ void launch_hsde_scatter(const Dev &d, const HsdeDev &hs, const float *sl, const
                        (const float *)d.dslot, (const double *)d.xi, (const double *)hs.dx, (const double *)d.c,
                        (const double *)hs.invE, (const uint32_t *)d.wbits, (const double *)hs.sc, tk, d.u, hs.hpart,
                        d.nU, (const Ctl *)d.ctl);
-}
-
-void launch_hsde_check(const Dev &d, const HsdeDev &hs, const double *tk, hipStream_t s) {
-    const int ncp = d.p + d.nvb, nhb = pscatter_blocks(d);
-    if (ncp + nhb > 8192)
-        hipLaunchKernelGGL(k_hsde_check<1024>, dim3(1), dim3(1024), 0, s, (const double *)d.cpart, ncp,
-                           (const double *)hs.hpart, nhb, hs.sc, tk, hs.hist, hs.hist_cap, d.ctl);
-    else
-        hipLaunchKernelGGL(k_hsde_check<kNT>, dim3(1), dim3(kNT), 0, s, (const double *)d.cpart, ncp,
-                           (const double *)hs.hpart, nhb, hs.sc, tk, hs.hist, hs.hist_cap, d.ctl);
 }
 
 void launch_hsde_tau(const Dev &d, const HsdeDev &hs, double *y, double *tk, hipStream_t s) {
