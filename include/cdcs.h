@@ -597,7 +597,8 @@ cdcs_status cdcs_hsde_solution(cdcs_handle *h, const cdcs_hsde_state *st, int32_
 /* cdcs_hsde_solve with eager launches and HIP events around each kernel kind
  * of every iteration, as cdcs_admm_solve_timed does for Algorithms 1 and 2
  * (kinds: the projection, the A u partials, the solve with M^-1, A^T y,
- * the scatter; the tau row, the update of x and the check run unbracketed).
+ * the scatter; the tau row and the update of x run unbracketed, the check
+ * inside the A u launch as for Algorithm 1).
  * The iterates are those of cdcs_hsde_solve with the same state and options.
  * Errors: those of cdcs_hsde_solve; CDCS_E_ARG for NULL kernel_ms or launches. */
 cdcs_status cdcs_hsde_solve_timed(cdcs_handle *h, const cdcs_hsde_state *st, const cdcs_options *opts,
@@ -629,9 +630,10 @@ typedef enum {
  * indexed by cdcs_kernel, owned by the caller; CDCS_K_GEMV_AU without the
  * small reduction that follows it).  Batch handles: CDCS_K_GEMV_AU covers the
  * whole affine step, CDCS_K_TRMV and CDCS_K_GEMV_ATY stay 0.  The residual
- * checks run unbracketed, except Algorithm 1's on a dense single-SDP handle,
- * which runs as the first workgroup of the A u launch (overlapping the
- * product) and so falls inside CDCS_K_GEMV_AU.  Synchronises on stream.
+ * checks run unbracketed, except Algorithm 1's on a single-SDP handle, which
+ * runs as the first workgroup of the A u launch (overlapping the product; a
+ * separate launch only when the partial sums number more than 8192) and so
+ * falls inside CDCS_K_GEMV_AU.  Synchronises on stream.
  * Errors: those of cdcs_admm_solve; CDCS_E_ARG for NULL kernel_ms or launches.
  */
 cdcs_status cdcs_admm_solve_timed(cdcs_handle *h, const cdcs_state *st, const cdcs_options *opts,

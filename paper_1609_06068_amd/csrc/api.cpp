@@ -1478,7 +1478,7 @@ void enqueue_iteration(cdcs_handle *h, const cdcs_state *st, int form, double rh
         double *tk = h->hs_tk;
         timed(CDCS_K_SCATTER, [&] { launch_hsde_scatter(d, hs, st->blk, st->lam, tk, s); });
         if (check_in_au(d)) {  // the check runs in the A u launch's first workgroup
-            timed(CDCS_K_GEMV_AU, [&] { launch_au_with_hsde_check(dh, d, hs, tk, d.ctl, s); });
+            timed(CDCS_K_GEMV_AU, [&] { launch_au_with_hsde_check(dh, d, hs, tk, st->y, -1.0, d.ctl, s); });
         } else {
             launch_hsde_check(d, hs, tk, s);
             timed(CDCS_K_GEMV_AU, [&] { launch_affine_part(dh, 0, st->y, -1.0, hs.a, hs.yh, d.ctl, s); });
@@ -1510,7 +1510,7 @@ void enqueue_iteration(cdcs_handle *h, const cdcs_state *st, int form, double rh
     // the affine step (t, then y = L^-T L^-1 t, then x) part by part; with
     // check_au, Algorithm 1's residual check runs in the A u launch
     auto affine = [&](double r2scale, bool check_au) {
-        if (check_au) timed(CDCS_K_GEMV_AU, [&] { launch_au_with_check(d, rho, d.ctl, s); });
+        if (check_au) timed(CDCS_K_GEMV_AU, [&] { launch_au_with_check(d, d.b, r2scale, rho, d.ctl, s); });
         else timed(CDCS_K_GEMV_AU, [&] { launch_affine_part(d, 0, d.b, r2scale, st->x, st->y, d.ctl, s); });
         launch_affine_part(d, 3, d.b, r2scale, st->x, st->y, d.ctl, s);
         timed(CDCS_K_TRMV, [&] { launch_affine_part(d, 1, d.b, r2scale, st->x, st->y, d.ctl, s); });

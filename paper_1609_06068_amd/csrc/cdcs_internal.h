@@ -294,9 +294,10 @@ void launch_hsde_scatter(const Dev &d, const HsdeDev &hs, const float *sl, const
                          hipStream_t s);
 void launch_hsde_check(const Dev &d, const HsdeDev &hs, const double *tk, hipStream_t s);
 // the HSDE check in the first workgroup of the A u launch of its linear step
-// (dh: the HSDE's Dev, d: the handle's), when check_in_au(d)
-void launch_au_with_hsde_check(const Dev &dh, const Dev &d, const HsdeDev &hs, const double *tk, const Ctl *ctl,
-                               hipStream_t s);
+// (dh: the HSDE's Dev, d: the handle's; r2, r2scale as for its part 0), when
+// check_in_au(d)
+void launch_au_with_hsde_check(const Dev &dh, const Dev &d, const HsdeDev &hs, const double *tk, const double *r2,
+                               double r2scale, const Ctl *ctl, hipStream_t s);
 void launch_hsde_tau(const Dev &d, const HsdeDev &hs, double *y, double *tk, hipStream_t s);
 void launch_hsde_axpy(const Dev &d, const HsdeDev &hs, hipStream_t s);
 void launch_hsde_solution(const Dev &d, const HsdeDev &hs, int which, const double *x, const double *y,
@@ -316,9 +317,11 @@ void launch_reset_ctl(const Dev &d, int max_iter, double tol, hipStream_t s);
 void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s);
 void launch_check_primal(const Dev &d, double rho, hipStream_t s);
 // true when Algorithm 1's residual check can run as the first workgroup of
-// the dense A u launch (launch_au_with_check) instead of a launch of its own
+// the A u launch (launch_au_with_check: part 0 of the affine step with the
+// same r2, r2scale) instead of a launch of its own
 bool check_in_au(const Dev &d);
-void launch_au_with_check(const Dev &d, double rho, const Ctl *ctl, hipStream_t s);
+void launch_au_with_check(const Dev &d, const double *r2, double r2scale, double rho, const Ctl *ctl,
+                          hipStream_t s);
 void launch_scatter_dual(const Dev &d, const float *blk, const float *lam, double rho, hipStream_t s);
 void launch_vupdate(const Dev &d, const double *x, const float *blk, float *lam, float *v, double rho,
                     hipStream_t s);

@@ -491,16 +491,46 @@ __global__ __launch_bounds__(kNT) void k_scale_u(const double *__restrict__ r1, 
     u[e] = r1[e] * invD[e];
 }
 
+// The residual check (Algorithm 1's, or the HSDE's when sc is set) run by the
+// first workgroup of the A u launch that follows it (ctl == nullptr: none).
+struct CheckArgs {
+    const double *cpart;
+    const double *spart;  // the scatter's partial sums (HSDE: hpart)
+    double *hist;
+    Ctl *ctl;
+    double rho;
+    int p, nsblk, hist_cap;
+    double *sc;           // HSDE solved-test scalars, or nullptr
+    const double *tk;     // HSDE (tau, kappa)
+};
+
+// The leading workgroup of an A u launch that carries a check runs it.
+__device__ __forceinline__ void run_check(const CheckArgs &ck, double (*red)[kNT / 64]) {
+    if (ck.sc != nullptr)
+        hsde_check_block<kNT>(ck.cpart, ck.p, ck.spart, ck.nsblk, ck.sc, ck.tk, ck.hist, ck.hist_cap, ck.ctl, red);
+    else
+        check_primal_block<kNT>(ck.cpart, ck.p, ck.spart, ck.nsblk, ck.rho, ck.hist, ck.hist_cap, ck.ctl, red);
+}
+
 // Sparse A: t_i = sum over the coefficients of row i of Aw_ie u_e - r2scale r2_i.
 // One wave per row, lanes over the coefficients.
+// With a check (ck.ctl set) the first workgroup runs it and the rows start at
+// the second: t is scratch, and the triangular products that read it test the
+// stop flag, so a stop decided while this launch runs changes nothing.
 __global__ __launch_bounds__(kNT) void k_spmv_Au(const int32_t *__restrict__ sp_ptr,
                                                  const int32_t *__restrict__ sp_col,
                                                  const double *__restrict__ sp_val, const double *__restrict__ u,
                                                  const double *__restrict__ r2, double r2scale,
-                                                 double *__restrict__ t, int m, const Ctl *ctl) {
+                                                 double *__restrict__ t, int m, const Ctl *ctl, CheckArgs ck) {
+    __shared__ double ckred[5][kNT / 64];
+    const int lead = ck.ctl != nullptr ? 1 : 0;
+    if (lead && blockIdx.x == 0) {
+        run_check(ck, ckred);
+        return;
+    }
     if (ctl != nullptr && ctl->stop) return;
     const int lane = threadIdx.x & 63;
-    const int row = blockIdx.x * (kNT / 64) + (threadIdx.x >> 6);
+    const int row = ((int)blockIdx.x - lead) * (kNT / 64) + (threadIdx.x >> 6);
     if (row >= m) return;
     double acc = 0.0;
     for (int32_t q = sp_ptr[row] + lane; q < sp_ptr[row + 1]; q += 64) acc += sp_val[q] * u[sp_col[q]];
@@ -539,19 +569,6 @@ __global__ __launch_bounds__(kNT) void k_sp_xcorr(const int32_t *__restrict__ tc
     x[e] = u[e] - s2[e] * acc;
 }
 
-// The residual check (Algorithm 1's, or the HSDE's when sc is set) run by the
-// first workgroup of the A u launch that follows it (ctl == nullptr: none).
-struct CheckArgs {
-    const double *cpart;
-    const double *spart;  // the scatter's partial sums (HSDE: hpart)
-    double *hist;
-    Ctl *ctl;
-    double rho;
-    int p, nsblk, hist_cap;
-    double *sc;           // HSDE solved-test scalars, or nullptr
-    const double *tk;     // HSDE (tau, kappa)
-};
-
 // Split-K partial products of t = A (w u): tpart[slice][row] is the dot
 // product of row `row` of the FP32 matrix Aw (= w A, row-major, leading
 // dimension ld, zero padded) with u over the columns of one slice.  RG rows per
@@ -570,14 +587,7 @@ __global__ __launch_bounds__(kNT, 5) void k_gemv_Au(const float *__restrict__ Aw
     __shared__ double ckred[5][kNT / 64];
     const int lead = ck.ctl != nullptr ? 1 : 0;
     if (lead && blockIdx.x == 0) {
-        if (blockIdx.y == 0) {
-            if (ck.sc != nullptr)
-                hsde_check_block<kNT>(ck.cpart, ck.p, ck.spart, ck.nsblk, ck.sc, ck.tk, ck.hist, ck.hist_cap, ck.ctl,
-                                      ckred);
-            else
-                check_primal_block<kNT>(ck.cpart, ck.p, ck.spart, ck.nsblk, ck.rho, ck.hist, ck.hist_cap, ck.ctl,
-                                        ckred);
-        }
+        if (blockIdx.y == 0) run_check(ck, ckred);
         return;
     }
     if (ctl != nullptr && ctl->stop) return;
@@ -874,7 +884,7 @@ void launch_scatter_primal(const Dev &d, const float *blk, const float *lam, dou
                        rho, (const Ctl *)d.ctl);
 }
 
-bool check_in_au(const Dev &d) { return !d.sparse && d.p + d.nvb + pscatter_blocks(d) <= 8192; }
+bool check_in_au(const Dev &d) { return d.p + d.nvb + pscatter_blocks(d) <= 8192; }
 
 void launch_check_primal(const Dev &d, double rho, hipStream_t s) {
     // partial sums of the cliques, then of the vector cones' blocks
@@ -930,17 +940,29 @@ void launch_gemv_au(const Dev &d, const Ctl *ctl, const CheckArgs &ck, hipStream
                        d.ldU, (const double *)d.u, d.tpart, d.m, slice_cols, ctl, ck);
 }
 
-void launch_au_with_check(const Dev &d, double rho, const Ctl *ctl, hipStream_t s) {
-    CheckArgs ck{(const double *)d.cpart, (const double *)d.spart, d.hist, d.ctl, rho, d.p + d.nvb,
-                 pscatter_blocks(d), d.hist_cap, nullptr, nullptr};
-    launch_gemv_au(d, ctl, ck, s);
+void launch_spmv_au(const Dev &d, const double *r2, double r2scale, const Ctl *ctl, const CheckArgs &ck,
+                    hipStream_t s) {
+    const int lead = ck.ctl != nullptr ? 1 : 0;
+    hipLaunchKernelGGL(k_spmv_Au, dim3((d.m + kNT / 64 - 1) / (kNT / 64) + lead), dim3(kNT), 0, s,
+                       (const int32_t *)d.sp_ptr, (const int32_t *)d.sp_col, (const double *)d.sp_val,
+                       (const double *)d.u, r2, r2scale, d.t, d.m, ctl, ck);
 }
 
-void launch_au_with_hsde_check(const Dev &dh, const Dev &d, const HsdeDev &hs, const double *tk, const Ctl *ctl,
-                               hipStream_t s) {
+// The A u part of the affine step (part 0) with the check in its first workgroup.
+void launch_au_with_check(const Dev &d, const double *r2, double r2scale, double rho, const Ctl *ctl,
+                          hipStream_t s) {
+    CheckArgs ck{(const double *)d.cpart, (const double *)d.spart, d.hist, d.ctl, rho, d.p + d.nvb,
+                 pscatter_blocks(d), d.hist_cap, nullptr, nullptr};
+    if (d.sparse) launch_spmv_au(d, r2, r2scale, ctl, ck, s);
+    else launch_gemv_au(d, ctl, ck, s);
+}
+
+void launch_au_with_hsde_check(const Dev &dh, const Dev &d, const HsdeDev &hs, const double *tk, const double *r2,
+                               double r2scale, const Ctl *ctl, hipStream_t s) {
     CheckArgs ck{(const double *)d.cpart, (const double *)hs.hpart, hs.hist, d.ctl, 0.0, d.p + d.nvb,
                  pscatter_blocks(d), hs.hist_cap, hs.sc, tk};
-    launch_gemv_au(dh, ctl, ck, s);
+    if (dh.sparse) launch_spmv_au(dh, r2, r2scale, ctl, ck, s);
+    else launch_gemv_au(dh, ctl, ck, s);
 }
 
 void launch_hsde_check(const Dev &d, const HsdeDev &hs, const double *tk, hipStream_t s) {
@@ -956,9 +978,7 @@ void launch_hsde_check(const Dev &d, const HsdeDev &hs, const double *tk, hipStr
 void launch_affine_part(const Dev &d, int part, const double *r2, double r2scale, double *x, double *y,
                         const Ctl *ctl, hipStream_t s) {
     if (d.sparse && part == 0) {
-        hipLaunchKernelGGL(k_spmv_Au, dim3((d.m + kNT / 64 - 1) / (kNT / 64)), dim3(kNT), 0, s,
-                           (const int32_t *)d.sp_ptr, (const int32_t *)d.sp_col, (const double *)d.sp_val,
-                           (const double *)d.u, r2, r2scale, d.t, d.m, ctl);
+        launch_spmv_au(d, r2, r2scale, ctl, CheckArgs{}, s);
     } else if (d.sparse && part == 3) {
         // A u already carries - r2scale r2
     } else if (d.sparse && part == 2) {
